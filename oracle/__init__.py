@@ -1,0 +1,219 @@
+"""Python side of the CPU oracle (test infrastructure only).
+
+The oracle is a plain FP64 C implementation of the SIDM scattering step
+(``sidm_oracle.c``), written from the paper and shared with nothing in the GPU
+library.  Only the tests, the package smoke check and the benchmark's
+CPU-baseline leg use it.  This module only marshals arguments, builds the C
+file with gcc, and -- for inputs too large for an all-pairs ranking -- gathers
+a *superset* of each target's candidate partners with scipy's k-d tree; the
+exact ranking by (r^2, ID) over that superset is still the C oracle's.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sidm_oracle.c")
+_LIB = os.path.join(_HERE, "libsidm_oracle.so")
+_lib = None
+
+CAND_ACCEPT0 = 1
+CAND_SCATTER = 2
+CAND_FLAGGED = 4
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle: no FMA contraction, no fast-math."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n_cand", ctypes.c_int64), ("n_accept0", ctypes.c_int64),
+                ("n_events", ctypes.c_int64), ("n_flagged", ctypes.c_int64),
+                ("n_p_ge_1", ctypes.c_int64), ("n_passes", ctypes.c_int32),
+                ("max_p", ctypes.c_double)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32, u32, u64, dbl = (ctypes.c_int64, ctypes.c_int, ctypes.c_uint32,
+                                   ctypes.c_uint64, ctypes.c_double)
+        L.oref_philox4x32_10.argtypes = [P, P, P]
+        L.oref_philox4x32_10.restype = None
+        L.oref_uniform_decision.argtypes = [u64, u32, u32, u32]
+        L.oref_uniform_decision.restype = dbl
+        L.oref_r2.argtypes = [dbl] * 6 + [i32, dbl]
+        L.oref_r2.restype = dbl
+        L.oref_kernel.argtypes = [dbl, dbl]
+        L.oref_kernel.restype = dbl
+        L.oref_sigma.argtypes = [dbl, i32, dbl, dbl]
+        L.oref_sigma.restype = dbl
+        L.oref_find_ngb.argtypes = [i64, P, P, P, P, i32, dbl, i64, P, i32, P, P, P, P]
+        L.oref_find_ngb.restype = i32
+        L.oref_scatter_step.argtypes = ([i64, P, P, P, P, P, P, P, dbl, P, P, i32, dbl,
+                                         i64, P, i32, P, P, P,
+                                         i32, dbl, dbl, i32, dbl, dbl, u64, u32, dbl,
+                                         P, ctypes.POINTER(_Stats)])
+        L.oref_scatter_step.restype = i32
+        L.oref_pair_timestep.argtypes = [i64, P, P, P, P, dbl, i64, P, i32, P, P,
+                                         i32, dbl, dbl, dbl, P]
+        L.oref_pair_timestep.restype = i32
+        L.oref_kick_pair.argtypes = [i32, i32, P, dbl, P, P, P, P, P, i32, dbl, dbl, u64, u32]
+        L.oref_kick_pair.restype = None
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ---------------------------------------------------------------------------
+def philox4x32_10(counter, key) -> np.ndarray:
+    c = _c(counter, np.uint32)
+    k = _c(key, np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().oref_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def uniform_decision(seed: int, step: int, id_i: int, id_j: int) -> float:
+    return lib().oref_uniform_decision(seed, step, id_i, id_j)
+
+
+def kernel(r: float, h: float) -> float:
+    return lib().oref_kernel(r, h)
+
+
+def sigma(w: float, xsec: int, s0: float, w0: float) -> float:
+    return lib().oref_sigma(w, xsec, s0, w0)
+
+
+def r2(pi, pj, periodic: bool, box: float) -> float:
+    return lib().oref_r2(*map(float, pi), *map(float, pj), int(periodic), float(box))
+
+
+# ---------------------------------------------------------------------------
+def candidate_superset(x, y, z, periodic, box, targets, k):
+    """CSR superset of every target's partners with r <= r_(k+1), from scipy's
+    k-d tree: the (k+2)-th closest point including the target itself bounds
+    r_(k+1); the ball query radius is padded far beyond rounding differences."""
+    from scipy.spatial import cKDTree
+    pts = np.stack([x, y, z], axis=1)
+    if periodic:
+        pts = np.where(pts >= box, pts - box, pts)
+        kd = cKDTree(pts, boxsize=box)
+    else:
+        kd = cKDTree(pts)
+    q = pts[targets]
+    d, _ = kd.query(q, k=k + 2, workers=-1)
+    rad = d[:, k + 1] * (1.0 + 1e-9) + 1e-300
+    lists = kd.query_ball_point(q, rad, workers=-1, return_sorted=False)
+    counts = np.fromiter((len(l) for l in lists), dtype=np.int64, count=len(lists))
+    ptr = np.zeros(len(lists) + 1, dtype=np.int64)
+    np.cumsum(counts, out=ptr[1:])
+    idx = np.fromiter((j for l in lists for j in l), dtype=np.int32, count=int(ptr[-1]))
+    return ptr, idx
+
+
+def find_ngb(w, targets=None, brute: Optional[bool] = None):
+    """Neighbour lists and smoothing lengths of ``targets`` (default: w.active).
+
+    Returns (ngb int32[n_t, k], h float64[n_t])."""
+    L = lib()
+    tg = _c(w.active if targets is None else targets, np.int32)
+    k = w.n_ngb
+    x, y, z = _c(w.x, np.float64), _c(w.y, np.float64), _c(w.z, np.float64)
+    ids = _c(w.id, np.uint32)
+    if brute is None:
+        brute = w.n <= 4096
+    ptr = idx = None
+    if not brute:
+        ptr, idx = candidate_superset(x, y, z, w.periodic, w.box, tg, k)
+    ngb = np.zeros((tg.size, k), dtype=np.int32)
+    h = np.zeros(tg.size, dtype=np.float64)
+    rc = L.oref_find_ngb(w.n, _p(x), _p(y), _p(z), _p(ids), int(w.periodic), float(w.box),
+                         tg.size, _p(tg), k, _p(ptr), _p(idx), _p(ngb), _p(h))
+    if rc != 0:
+        raise ValueError(f"oref_find_ngb failed ({rc})")
+    return ngb, h
+
+
+def scatter_step(w, ngb, h, band: float = 1e-9, want_info: bool = True):
+    """One scattering step on copies of w's velocities/states.
+
+    Returns (vx, vy, vz, state, cand_info uint32[n_active, k] | None, stats dict)."""
+    L = lib()
+    x, y, z = _c(w.x, np.float64), _c(w.y, np.float64), _c(w.z, np.float64)
+    vx, vy, vz = (np.array(w.vx, dtype=np.float64), np.array(w.vy, dtype=np.float64),
+                  np.array(w.vz, dtype=np.float64))
+    st = np.array(w.state, dtype=np.uint8)
+    ids = _c(w.id, np.uint32)
+    act = _c(w.active, np.int32)
+    ngb = _c(ngb, np.int32)
+    h = _c(h, np.float64)
+    dt = _c(w.dt, np.float64)
+    info = np.zeros((act.size, w.n_ngb), dtype=np.uint32) if want_info else None
+    stats = _Stats()
+    rc = L.oref_scatter_step(w.n, _p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), None,
+                             float(w.mass), _p(ids), _p(st), int(w.periodic), float(w.box),
+                             act.size, _p(act), w.n_ngb, _p(ngb), _p(h), _p(dt),
+                             int(w.xsec), float(w.sigma0), float(w.w0), int(w.model),
+                             float(w.eps), float(w.delta), int(w.seed), int(w.step),
+                             float(band), _p(info), ctypes.byref(stats))
+    if rc != 0:
+        raise ValueError(f"oref_scatter_step failed ({rc})")
+    sd = {f: getattr(stats, f) for f, _ in _Stats._fields_}
+    return vx, vy, vz, st, info, sd
+
+
+def pair_timestep(w, ngb, h, vx=None, vy=None, vz=None):
+    L = lib()
+    vx = _c(w.vx if vx is None else vx, np.float64)
+    vy = _c(w.vy if vy is None else vy, np.float64)
+    vz = _c(w.vz if vz is None else vz, np.float64)
+    act = _c(w.active, np.int32)
+    ngb = _c(ngb, np.int32)
+    h = _c(h, np.float64)
+    out = np.zeros(act.size, dtype=np.float64)
+    rc = L.oref_pair_timestep(w.n, _p(vx), _p(vy), _p(vz), None, float(w.mass), act.size,
+                              _p(act), w.n_ngb, _p(ngb), _p(h), int(w.xsec),
+                              float(w.sigma0), float(w.w0), float(w.c_sidm), _p(out))
+    if rc != 0:
+        raise ValueError(f"oref_pair_timestep failed ({rc})")
+    return out
+
+
+def kick_pair(i, j, vx, vy, vz, state, ids, mass, model, eps, delta, seed, step):
+    """Kick particles i and j in place (arrays are modified)."""
+    lib().oref_kick_pair(int(i), int(j), None, float(mass), _p(vx), _p(vy), _p(vz),
+                         _p(state), _p(ids), int(model), float(eps), float(delta),
+                         int(seed), int(step))
+
+
+def full_step(w, brute: Optional[bool] = None, band: float = 1e-9):
+    """Neighbours, scatter step and per-pair timestep of workload w."""
+    ngb, h = find_ngb(w, brute=brute)
+    vx, vy, vz, st, info, stats = scatter_step(w, ngb, h, band=band)
+    dt = pair_timestep(w, ngb, h, vx, vy, vz)
+    return dict(ngb=ngb, h=h, vx=vx, vy=vy, vz=vz, state=st, info=info, stats=stats,
+                dt_sidm=dt)

@@ -1,0 +1,477 @@
+/*
+ * sidm_oracle.c -- plain, slow, FP64 CPU reference of one SIDM scattering step
+ * (Zier et al., "A Novel Implementation of Self-Interacting Dark Matter in
+ * AREPO", arXiv 2607.05504).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle the GPU library is
+ * checked against.  Only the test-suite, the package smoke check and the
+ * CPU-baseline leg of the benchmark may load it; the GPU library neither
+ * includes, links nor calls anything here, and this file includes nothing of
+ * the GPU library.  Build:  gcc -O2 -ffp-contract=off -fno-fast-math -shared
+ * -fPIC (no FMA contraction, so every expression rounds exactly as written).
+ *
+ * What is computed, in the paper's order (section numbers are the paper's):
+ *   separation      minimum-image offset in a periodic box (sec. 5.2 uses a
+ *                   periodic box; the convention is this oracle's reading)
+ *   neighbours      the N_ngb nearest DM particles of each active target,
+ *                   inactive ones included (sec. 4.1, Fig. 3 caption);
+ *                   smoothing length h_i = distance of the (N_ngb+1)-th
+ *                   (reading of the "32 +- 5" bisection of sec. 4.2/4.5)
+ *   kernel          cubic spline W_CS(q, h) (sec. 4.2)
+ *   cross-section   sigma/m constant, or s0 / (1 + (w/w0)^2)^2 (sec. 5.2)
+ *   rate, P         Gamma(i|j) = m_j (sigma/m) |v_i - v_j| g_ij with the
+ *                   one-sided g_ij = W(x_j - x_i, h_i)   (Eqs. rate, oneSided)
+ *                   P(i|j) = Gamma(i|j) dt_i / 2        (Eq. probabilityScatter)
+ *   random numbers  Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11),
+ *                   keyed on the seed, counter = (lower ID, higher ID, step,
+ *                   purpose) -- the paper only says a random number is drawn
+ *   acceptance      every candidate (i|j) is evaluated once with the
+ *                   step-start velocities; accepted ones are then processed
+ *                   serially in increasing (priority, id_i, id_j) order, each
+ *                   re-evaluated with the current velocities and the same
+ *                   draw, so a particle's successive scatters build on each
+ *                   other (sec. 4.5, immediate update)
+ *   kick            centre-of-momentum kick with a direction uniform on the
+ *                   sphere and outgoing relative speed eps * w (sec. 4.1);
+ *                   eps = 1 elastic, constant eps, or a two-state model whose
+ *                   eps follows from the energy gap (sec. 4.1 relates eps to
+ *                   the energy released or absorbed)
+ *   timestep        dt_i = C_SIDM * 2 / (m_DM W(0, h_i) (v sigma/m)_max)
+ *                   (Eq. sidm_timestep)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OREF_PI 3.14159265358979323846
+#define OREF_OK 0
+#define OREF_E_INVAL -1
+#define OREF_E_NOMEM -2
+
+/* scatter models / cross-sections (integer values shared with the Python side) */
+#define OREF_XSEC_CONST 0
+#define OREF_XSEC_YUKAWA 1
+#define OREF_MODEL_ELASTIC 0
+#define OREF_MODEL_EPS 1
+#define OREF_MODEL_TWO_STATE 2
+
+/* per-candidate info word */
+#define OREF_CAND_ACCEPT0 1u   /* accepted by the step-start evaluation        */
+#define OREF_CAND_SCATTER 2u   /* produced a kick                              */
+#define OREF_CAND_FLAGGED 4u   /* some evaluation had |P - u| < band            */
+/* bits 8..31: index of the resolution pass that decided it (0: not accepted) */
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al. 2011): 10 rounds of the 4x32 S-box with the   */
+/* multipliers 0xD2511F53, 0xCD9E8D57 and Weyl key increments 0x9E3779B9,     */
+/* 0xBB67AE85.                                                                 */
+/* ------------------------------------------------------------------------ */
+void oref_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* purposes of a draw for one unordered pair in one step */
+#define PURPOSE_DECIDE 0u
+#define PURPOSE_DIR_LO_HI 1u
+#define PURPOSE_PRIORITY 2u
+#define PURPOSE_DIR_HI_LO 3u
+
+static void pair_draw(uint64_t seed, uint32_t step, uint32_t id_a, uint32_t id_b,
+                      uint32_t purpose, uint32_t out[4])
+{
+    uint32_t lo = id_a < id_b ? id_a : id_b;
+    uint32_t hi = id_a < id_b ? id_b : id_a;
+    uint32_t ctr[4] = {lo, hi, step, purpose};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    oref_philox4x32_10(ctr, key, out);
+}
+
+/* The 64-bit word serving the direction "target -> partner": words (x0,x1)
+ * serve the lower-ID target, (x2,x3) the higher-ID target. */
+static uint64_t direction_word(const uint32_t x[4], int target_is_lower)
+{
+    return target_is_lower ? ((uint64_t)x[1] << 32 | x[0]) : ((uint64_t)x[3] << 32 | x[2]);
+}
+
+static double unit_from_word(uint64_t w)
+{
+    return (double)(w >> 11) * 0x1.0p-53;   /* in [0, 1) */
+}
+
+double oref_uniform_decision(uint64_t seed, uint32_t step, uint32_t id_i, uint32_t id_j)
+{
+    uint32_t x[4];
+    pair_draw(seed, step, id_i, id_j, PURPOSE_DECIDE, x);
+    return unit_from_word(direction_word(x, id_i < id_j));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* one axis of the separation x_j - x_i, minimum image when periodic */
+static double axis_sep(double xi, double xj, int periodic, double box)
+{
+    double d = xj - xi;
+    if (periodic) {
+        if (d >= 0.5 * box) d = d - box;
+        else if (d < -0.5 * box) d = d + box;
+    }
+    return d;
+}
+
+double oref_r2(double xi, double yi, double zi, double xj, double yj, double zj,
+               int periodic, double box)
+{
+    double dx = axis_sep(xi, xj, periodic, box);
+    double dy = axis_sep(yi, yj, periodic, box);
+    double dz = axis_sep(zi, zj, periodic, box);
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+/* cubic spline kernel with compact support h (sec. 4.2) */
+double oref_kernel(double r, double h)
+{
+    double h3 = (h * h) * h;
+    double norm = 8.0 / (OREF_PI * h3);
+    double q = r / h;
+    if (q <= 0.5) {
+        double q2 = q * q;
+        double q3 = q2 * q;
+        return norm * ((1.0 - 6.0 * q2) + 6.0 * q3);
+    }
+    if (q <= 1.0) {
+        double t = 1.0 - q;
+        return norm * (2.0 * ((t * t) * t));
+    }
+    return 0.0;
+}
+
+double oref_sigma(double w, int xsec, double s0, double w0)
+{
+    if (xsec == OREF_XSEC_YUKAWA) {
+        double x = w / w0;
+        double d = 1.0 + x * x;
+        return s0 / (d * d);
+    }
+    return s0;
+}
+
+static double rel_speed(double ax, double ay, double az, double bx, double by, double bz)
+{
+    double dx = ax - bx, dy = ay - by, dz = az - bz;
+    return sqrt((dx * dx + dy * dy) + dz * dz);
+}
+
+/* P(i|j) = 1/2 m_j (sigma(w)/m) w W dt_i, multiplied left to right */
+static double pair_probability(double m_j, double sig, double w, double W, double dt)
+{
+    return (((0.5 * m_j) * sig) * w * W) * dt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbours: for each target i, all j != i ordered by (r2_ij, id_j); the    */
+/* first k are N(i) and h_i = sqrt(r2 of entry k+1).                          */
+/* ------------------------------------------------------------------------ */
+typedef struct { double r2; uint32_t id; int32_t j; } cand_t;
+
+static int cand_cmp(const void *pa, const void *pb)
+{
+    const cand_t *a = (const cand_t *)pa, *b = (const cand_t *)pb;
+    if (a->r2 < b->r2) return -1;
+    if (a->r2 > b->r2) return 1;
+    if (a->id < b->id) return -1;
+    if (a->id > b->id) return 1;
+    return 0;
+}
+
+/*
+ * n particles; targets[n_t] indices; k = N_ngb.
+ * cand_ptr/cand_idx: optional CSR superset of candidate partners per target
+ * (NULL: every particle).  A superset must contain every j with r2_ij <= the
+ * true (k+1)-th smallest value; the ranking below does not depend on it.
+ * Out: ngb[n_t*k] (row-major, sorted by (r2, id)), h[n_t].
+ */
+int oref_find_ngb(int64_t n, const double *x, const double *y, const double *z,
+                  const uint32_t *id, int periodic, double box,
+                  int64_t n_t, const int32_t *targets, int k,
+                  const int64_t *cand_ptr, const int32_t *cand_idx,
+                  int32_t *ngb, double *h)
+{
+    if (k < 1 || n < k + 2) return OREF_E_INVAL;
+    int64_t cap = n;
+    cand_t *buf = (cand_t *)malloc((size_t)cap * sizeof(cand_t));
+    if (!buf) return OREF_E_NOMEM;
+    int rc = OREF_OK;
+    for (int64_t t = 0; t < n_t; ++t) {
+        int32_t i = targets[t];
+        int64_t m = 0;
+        int64_t lo = cand_ptr ? cand_ptr[t] : 0;
+        int64_t hi = cand_ptr ? cand_ptr[t + 1] : n;
+        for (int64_t c = lo; c < hi; ++c) {
+            int32_t j = cand_ptr ? cand_idx[c] : (int32_t)c;
+            if (j == i) continue;
+            buf[m].r2 = oref_r2(x[i], y[i], z[i], x[j], y[j], z[j], periodic, box);
+            buf[m].id = id[j];
+            buf[m].j = j;
+            ++m;
+        }
+        if (m < k + 1) { rc = OREF_E_INVAL; break; }
+        qsort(buf, (size_t)m, sizeof(cand_t), cand_cmp);
+        for (int s = 0; s < k; ++s) ngb[t * k + s] = buf[s].j;
+        h[t] = sqrt(buf[k].r2);
+    }
+    free(buf);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kick (sec. 4.1): v' = v_com +- eps m_other |v_i - v_j| / (m_i + m_j) e     */
+/* ------------------------------------------------------------------------ */
+static void direction_from_draw(const uint32_t x[4], double e[3])
+{
+    uint64_t wa = (uint64_t)x[1] << 32 | x[0];
+    uint64_t wb = (uint64_t)x[3] << 32 | x[2];
+    double u1 = unit_from_word(wa), u2 = unit_from_word(wb);
+    double cth = 2.0 * u1 - 1.0;
+    double phi = 2.0 * OREF_PI * u2;
+    double s2 = 1.0 - cth * cth;
+    double sth = sqrt(s2 > 0.0 ? s2 : 0.0);
+    e[0] = sth * cos(phi);
+    e[1] = sth * sin(phi);
+    e[2] = cth;
+}
+
+typedef struct {
+    int xsec; double s0, w0;
+    int model; double eps, delta;
+    uint64_t seed; uint32_t step;
+} phys_t;
+
+/* Returns the outgoing/incoming relative-speed ratio and the state changes of
+ * the scatter of particles a (target) and b, for the chosen model. */
+static double scatter_eps(const phys_t *ph, double m_a, double m_b, double w,
+                          uint8_t s_a, uint8_t s_b, uint32_t id_a, uint32_t id_b,
+                          uint32_t channel_bit, uint8_t *ns_a, uint8_t *ns_b)
+{
+    *ns_a = s_a; *ns_b = s_b;
+    if (ph->model == OREF_MODEL_EPS) return ph->eps;
+    if (ph->model != OREF_MODEL_TWO_STATE) return 1.0;
+    /* two-state: energy gap delta per unit mass of the particle changing state.
+     * Centre-of-momentum kinetic energy (1/2) mu w^2 changes by -dE:
+     *   eps^2 = 1 - 2 dE / (mu w^2),  dE = +m_p delta (excite), -m_p delta (de-excite). */
+    double M = m_a + m_b;
+    double mu = (m_a * m_b) / M;
+    int a_is_lower = id_a < id_b;
+    if (s_a == 0 && s_b == 0) {
+        /* excite the lower-ID particle when the channel bit is 0, else the higher */
+        int excite_a = (channel_bit == 0) ? a_is_lower : !a_is_lower;
+        double m_p = excite_a ? m_a : m_b;
+        double e2 = 1.0 - (2.0 * m_p * ph->delta) / ((mu * w) * w);
+        if (!(e2 > 0.0)) return 1.0;               /* below threshold: elastic */
+        if (excite_a) *ns_a = 1; else *ns_b = 1;
+        return sqrt(e2);
+    }
+    int deexcite_a;
+    if (s_a && s_b) deexcite_a = (channel_bit == 0) ? a_is_lower : !a_is_lower;
+    else deexcite_a = s_a != 0;
+    double m_p = deexcite_a ? m_a : m_b;
+    double e2 = 1.0 + (2.0 * m_p * ph->delta) / ((mu * w) * w);
+    if (deexcite_a) *ns_a = 0; else *ns_b = 0;
+    return sqrt(e2);
+}
+
+static void do_kick(const phys_t *ph, int32_t i, int32_t j, const double *mass, double m_scalar,
+                    double *vx, double *vy, double *vz, uint8_t *state, const uint32_t *id)
+{
+    double mi = mass ? mass[i] : m_scalar;
+    double mj = mass ? mass[j] : m_scalar;
+    uint32_t x[4];
+    /* direction draw: purpose 1 serves the lower-ID target, 3 the higher-ID one */
+    pair_draw(ph->seed, ph->step, id[i], id[j],
+              id[i] < id[j] ? PURPOSE_DIR_LO_HI : PURPOSE_DIR_HI_LO, x);
+    double e[3];
+    direction_from_draw(x, e);
+    double w = rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
+    uint8_t si = state ? state[i] : 0, sj = state ? state[j] : 0, nsi, nsj;
+    double eps = scatter_eps(ph, mi, mj, w, si, sj, id[i], id[j], x[0] & 1u, &nsi, &nsj);
+    double M = mi + mj;
+    double vcx = (mi * vx[i] + mj * vx[j]) / M;
+    double vcy = (mi * vy[i] + mj * vy[j]) / M;
+    double vcz = (mi * vz[i] + mj * vz[j]) / M;
+    double c = (eps * w) / M;
+    double ci = mj * c, cj = mi * c;
+    vx[i] = vcx + ci * e[0]; vy[i] = vcy + ci * e[1]; vz[i] = vcz + ci * e[2];
+    vx[j] = vcx - cj * e[0]; vy[j] = vcy - cj * e[1]; vz[j] = vcz - cj * e[2];
+    if (state) { state[i] = nsi; state[j] = nsj; }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Scatter step                                                              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t c;          /* candidate index a*k + s */
+    int32_t i, j;       /* particle indices */
+    double u, W, m_j, dt;
+    uint64_t prio;
+    uint32_t id_i, id_j;
+} acc_t;
+
+static int acc_cmp(const void *pa, const void *pb)
+{
+    const acc_t *a = (const acc_t *)pa, *b = (const acc_t *)pb;
+    if (a->prio != b->prio) return a->prio < b->prio ? -1 : 1;
+    if (a->id_i != b->id_i) return a->id_i < b->id_i ? -1 : 1;
+    if (a->id_j != b->id_j) return a->id_j < b->id_j ? -1 : 1;
+    return 0;
+}
+
+typedef struct {
+    int64_t n_cand, n_accept0, n_events, n_flagged, n_p_ge_1;
+    int32_t n_passes; double max_p;
+} oref_stats;
+
+/*
+ * v and state are updated in place.  cand_info[n_active*k] (optional) gets the
+ * per-candidate flags/pass index.  band: |P - u| < band flags an evaluation.
+ */
+int oref_scatter_step(int64_t n, const double *x, const double *y, const double *z,
+                      double *vx, double *vy, double *vz, const double *mass, double m_scalar,
+                      const uint32_t *id, uint8_t *state, int periodic, double box,
+                      int64_t n_active, const int32_t *active, int k,
+                      const int32_t *ngb, const double *h, const double *dt,
+                      int xsec, double s0, double w0, int model, double eps, double delta,
+                      uint64_t seed, uint32_t step, double band,
+                      uint32_t *cand_info, oref_stats *stats)
+{
+    if (n < k + 2 || k < 1) return OREF_E_INVAL;
+    phys_t ph = {xsec, s0, w0, model, eps, delta, seed, step};
+    int64_t n_cand = n_active * (int64_t)k;
+    oref_stats st; memset(&st, 0, sizeof st);
+    st.n_cand = n_cand;
+    int64_t cap = 1024, n_acc = 0;
+    acc_t *acc = (acc_t *)malloc((size_t)cap * sizeof(acc_t));
+    if (!acc) return OREF_E_NOMEM;
+    if (cand_info) memset(cand_info, 0, (size_t)n_cand * sizeof(uint32_t));
+
+    /* evaluation 0: every candidate with the step-start velocities */
+    for (int64_t a = 0; a < n_active; ++a) {
+        int32_t i = active[a];
+        double mi_unused = 0; (void)mi_unused;
+        for (int s = 0; s < k; ++s) {
+            int32_t j = ngb[a * k + s];
+            double r = sqrt(oref_r2(x[i], y[i], z[i], x[j], y[j], z[j], periodic, box));
+            double W = oref_kernel(r, h[a]);
+            double w = rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
+            double sig = oref_sigma(w, xsec, s0, w0);
+            double mj = mass ? mass[j] : m_scalar;
+            double P = pair_probability(mj, sig, w, W, dt[a]);
+            double u = oref_uniform_decision(seed, step, id[i], id[j]);
+            if (P > st.max_p) st.max_p = P;
+            if (P >= 1.0) st.n_p_ge_1++;
+            if (fabs(P - u) < band) {
+                st.n_flagged++;
+                if (cand_info) cand_info[a * k + s] |= OREF_CAND_FLAGGED;
+            }
+            if (u < P) {
+                if (n_acc == cap) {
+                    cap *= 2;
+                    acc_t *nb = (acc_t *)realloc(acc, (size_t)cap * sizeof(acc_t));
+                    if (!nb) { free(acc); return OREF_E_NOMEM; }
+                    acc = nb;
+                }
+                uint32_t xr[4];
+                pair_draw(seed, step, id[i], id[j], PURPOSE_PRIORITY, xr);
+                acc_t e = {a * k + s, i, j, u, W, mj, dt[a],
+                           direction_word(xr, id[i] < id[j]), id[i], id[j]};
+                acc[n_acc++] = e;
+                if (cand_info) cand_info[a * k + s] |= OREF_CAND_ACCEPT0;
+            }
+        }
+    }
+    st.n_accept0 = n_acc;
+
+    /* serial processing in increasing (priority, id_i, id_j) */
+    qsort(acc, (size_t)n_acc, sizeof(acc_t), acc_cmp);
+    /* pass index of each accepted candidate = 1 + the largest pass index of an
+     * earlier (smaller-key) accepted candidate sharing a particle: the round in
+     * which a parallel matching of local minima would decide it. */
+    int32_t *last_pass = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+    if (!last_pass) { free(acc); return OREF_E_NOMEM; }
+    for (int64_t t = 0; t < n_acc; ++t) {
+        acc_t *c = &acc[t];
+        int32_t i = c->i, j = c->j;
+        int32_t pass = 1 + (last_pass[i] > last_pass[j] ? last_pass[i] : last_pass[j]);
+        last_pass[i] = last_pass[j] = pass;
+        if (pass > st.n_passes) st.n_passes = pass;
+        double w = rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
+        double sig = oref_sigma(w, xsec, s0, w0);
+        double P = pair_probability(c->m_j, sig, w, c->W, c->dt);
+        if (fabs(P - c->u) < band) {
+            st.n_flagged++;
+            if (cand_info) cand_info[c->c] |= OREF_CAND_FLAGGED;
+        }
+        if (cand_info) cand_info[c->c] |= (uint32_t)pass << 8;
+        if (c->u < P) {
+            do_kick(&ph, i, j, mass, m_scalar, vx, vy, vz, state, id);
+            st.n_events++;
+            if (cand_info) cand_info[c->c] |= OREF_CAND_SCATTER;
+        }
+    }
+    free(last_pass);
+    free(acc);
+    if (stats) *stats = st;
+    return OREF_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-pair timestep (Eq. sidm_timestep), with the current velocities:        */
+/* dt_i = C 2 / (m_DM W(0,h_i) max_j w_ij sigma(w_ij)/m); +inf if the max is 0 */
+/* ------------------------------------------------------------------------ */
+int oref_pair_timestep(int64_t n, const double *vx, const double *vy, const double *vz,
+                       const double *mass, double m_scalar,
+                       int64_t n_active, const int32_t *active, int k,
+                       const int32_t *ngb, const double *h,
+                       int xsec, double s0, double w0, double c_sidm, double *dt_out)
+{
+    if (n < k + 2 || k < 1) return OREF_E_INVAL;
+    for (int64_t a = 0; a < n_active; ++a) {
+        int32_t i = active[a];
+        double rmax = 0.0;
+        for (int s = 0; s < k; ++s) {
+            int32_t j = ngb[a * k + s];
+            double w = rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
+            double ws = w * oref_sigma(w, xsec, s0, w0);
+            if (ws > rmax) rmax = ws;
+        }
+        double mi = mass ? mass[i] : m_scalar;
+        double W0 = oref_kernel(0.0, h[a]);
+        dt_out[a] = rmax > 0.0 ? (2.0 * c_sidm) / ((mi * W0) * rmax) : INFINITY;
+    }
+    return OREF_OK;
+}
+
+/* pair kick exposed for the conservation tests */
+void oref_kick_pair(int32_t i, int32_t j, const double *mass, double m_scalar,
+                    double *vx, double *vy, double *vz, uint8_t *state, const uint32_t *id,
+                    int model, double eps, double delta, uint64_t seed, uint32_t step)
+{
+    phys_t ph = {0, 0.0, 1.0, model, eps, delta, seed, step};
+    do_kick(&ph, i, j, mass, m_scalar, vx, vy, vz, state, id);
+}

@@ -1,0 +1,368 @@
+"""Pins of the CPU oracle against things other than itself: closed forms the
+paper states, exact lattice geometry, an independent Philox implementation
+(rocRAND), scipy's k-d tree, conservation laws and statistical expectations.
+
+None of these tests needs a GPU.
+"""
+import json
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = json.load(open(os.path.join(HERE, "golden", "paper_values.json")))
+
+
+# ---------------------------------------------------------------------------
+# Philox4x32-10 against rocRAND's engine (host build of its header)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def rocrand_driver(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("rr") / "rocrand_philox")
+    subprocess.check_call([hipcc, "-O1", "-I/opt/rocm/include",
+                           os.path.join(HERE, "rocrand_philox_host.cpp"), "-o", exe])
+    return exe
+
+
+def test_philox_matches_rocrand(rocrand_driver):
+    rng = np.random.Generator(np.random.PCG64(5))
+    cases = [(0, 0, 0, 0, 0, 0), (2**32 - 1, 2**32 - 1, 2**30 - 1, 2**30 - 1, 2**32 - 1, 2**32 - 1)]
+    for _ in range(200):
+        kl, kh, c2, c3 = (int(v) for v in rng.integers(0, 2**32, 4))
+        c0 = int(rng.integers(0, 2**32))
+        c1 = int(rng.integers(0, 2**30))       # offset*4 must fit in 64 bits
+        cases.append((kl, kh, c0, c1, c2, c3))
+    inp = "\n".join(" ".join(str(v) for v in c) for c in cases) + "\n"
+    out = subprocess.run([rocrand_driver], input=inp, capture_output=True, text=True,
+                         check=True).stdout.split("\n")
+    for c, line in zip(cases, out):
+        ref = [int(v) for v in line.split()]
+        got = [int(v) for v in oracle.philox4x32_10([c[2], c[3], c[4], c[5]], [c[0], c[1]])]
+        assert got == ref, (c, got, ref)
+
+
+def test_decision_uniform_is_symmetric_pair_keyed():
+    # (i|j) and (j|i) use the two halves of one draw: different values, and
+    # both depend only on the unordered pair (swap IDs -> swap roles).
+    u_ij = oracle.uniform_decision(1, 7, 10, 20)
+    u_ji = oracle.uniform_decision(1, 7, 20, 10)
+    assert u_ij != u_ji
+    x = oracle.philox4x32_10([10, 20, 7, 0], [1, 0])
+    lo_word = (int(x[1]) << 32) | int(x[0])
+    hi_word = (int(x[3]) << 32) | int(x[2])
+    assert u_ij == (lo_word >> 11) * 2.0**-53
+    assert u_ji == (hi_word >> 11) * 2.0**-53
+
+
+# ---------------------------------------------------------------------------
+# Kernel and cross-section closed forms
+# ---------------------------------------------------------------------------
+def test_kernel_closed_forms():
+    from scipy.integrate import quad
+    c8pi = GOLD["cubic_spline_central_value_coeff"]["value"]
+    for h in (0.37, 1.0, 2.5):
+        assert oracle.kernel(0.0, h) == pytest.approx(c8pi / h**3, rel=1e-15)
+        half = GOLD["cubic_spline_branch_value_at_half"]["value"]
+        assert oracle.kernel(0.5 * h, h) == pytest.approx(half * c8pi / h**3, rel=1e-14)
+        # continuity across q = 1/2 and at the support edge
+        eps = 1e-9
+        assert oracle.kernel((0.5 - eps) * h, h) == pytest.approx(oracle.kernel((0.5 + eps) * h, h), rel=1e-7)
+        assert oracle.kernel(h, h) == 0.0
+        assert oracle.kernel(1.0001 * h, h) == 0.0
+        # normalisation: integral of W over the ball of radius h is 1
+        val, _ = quad(lambda r: 4 * math.pi * r * r * oracle.kernel(r, h), 0, h,
+                      points=[0.5 * h], epsabs=1e-14, epsrel=1e-13)
+        assert val == pytest.approx(1.0, abs=1e-12)
+        rs = np.linspace(0, h, 200)
+        ws = [oracle.kernel(r, h) for r in rs]
+        assert all(a >= b for a, b in zip(ws, ws[1:]))
+
+
+def test_sigma_models():
+    assert oracle.sigma(3.0, W.XSEC_CONST, 2.5, 1.0) == 2.5
+    s0, w0 = 268.3, 0.5
+    assert oracle.sigma(0.0, W.XSEC_YUKAWA, s0, w0) == s0
+    assert oracle.sigma(w0, W.XSEC_YUKAWA, s0, w0) == pytest.approx(s0 / 4, rel=1e-15)
+    assert oracle.sigma(3 * w0, W.XSEC_YUKAWA, s0, w0) == pytest.approx(s0 / 100, rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Neighbours
+# ---------------------------------------------------------------------------
+def test_knn_cubic_lattice_shells():
+    # simple cubic lattice, spacing s: shells of 6 (s), 12 (sqrt2 s), 8 (sqrt3 s),
+    # 6 (2s) fill exactly 32; the next shell is at sqrt5 s, so h = sqrt5 s.
+    w = W.uniform_box(512, lattice=True)
+    s = 1.0 / 8.0
+    ngb, h = oracle.find_ngb(w, brute=True)
+    assert np.all(h == math.sqrt(5.0 / 64.0))
+    pos = np.stack([w.x, w.y, w.z], 1)
+    for a in range(0, 512, 37):
+        d = pos[ngb[a]] - pos[a]
+        d = d - np.round(d)                    # lattice offsets are exact binary fractions
+        r2 = np.round((d * d).sum(1) / (s * s)).astype(int)
+        assert sorted(np.bincount(r2, minlength=5)[1:5]) == sorted([6, 12, 8, 6])
+        # ordering: r2 nondecreasing, IDs increasing within a shell
+        key = list(zip(r2, w.id[ngb[a]]))
+        assert key == sorted(key)
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_knn_against_scipy_kdtree(periodic):
+    from scipy.spatial import cKDTree
+    w = W.uniform_box(3000, ic_seed=11)
+    if not periodic:
+        w.periodic, w.box = False, 0.0
+    k = w.n_ngb
+    ngb, h = oracle.find_ngb(w, brute=True)
+    pts = np.stack([w.x, w.y, w.z], 1)
+    kd = cKDTree(pts, boxsize=1.0) if periodic else cKDTree(pts)
+    d, idx = kd.query(pts, k=k + 2)
+    # idx[:, 0] is the particle itself (no exact duplicates here)
+    assert np.all(idx[:, 0] == np.arange(w.n))
+    np.testing.assert_allclose(h, d[:, k + 1], rtol=1e-14)
+    for a in range(0, w.n, 97):
+        assert set(ngb[a]) == set(idx[a, 1:k + 1])
+
+
+def test_knn_superset_path_equals_all_pairs():
+    for periodic in (True, False):
+        w = W.uniform_box(2500, ic_seed=12)
+        if not periodic:
+            w.periodic, w.box = False, 0.0
+        n1, h1 = oracle.find_ngb(w, brute=True)
+        n2, h2 = oracle.find_ngb(w, brute=False)
+        assert np.array_equal(n1, n2) and np.array_equal(h1, h2)
+    # clustered (halo) inputs too
+    w = W.hernquist_halo(3000, ic_seed=13)
+    n1, h1 = oracle.find_ngb(w, brute=True)
+    n2, h2 = oracle.find_ngb(w, brute=False)
+    assert np.array_equal(n1, n2) and np.array_equal(h1, h2)
+
+
+def test_knn_rejects_too_few_particles():
+    w = W.uniform_box(33, ic_seed=1)
+    with pytest.raises(ValueError):
+        oracle.find_ngb(w, brute=True)
+
+
+def test_density_estimate_unbiased():
+    # One-sided estimate rho_i = sum_j m W(r_ij, h_i) over the k neighbours with
+    # h = r_(k+1): inner points are uniform in the ball given r_(k+1), so
+    # E[rho_i] = rho (1 - 1/N) in a uniform periodic box (rho = 1).
+    vals = []
+    for seed in range(4):
+        w = W.uniform_box(4000, ic_seed=200 + seed)
+        ngb, h = oracle.find_ngb(w, brute=False)
+        pos = np.stack([w.x, w.y, w.z], 1)
+        for a in range(0, w.n, 5):
+            d = pos[ngb[a]] - pos[a]
+            d = d - np.round(d)
+            r = np.sqrt((d * d).sum(1))
+            vals.append(w.mass * sum(oracle.kernel(ri, h[a]) for ri in r))
+    vals = np.array(vals)
+    expect = 1.0 - 1.0 / 4000
+    # per-target scatter ~ 1/sqrt(k); neighbouring targets are correlated, so be generous
+    err = vals.std() / math.sqrt(vals.size) * 3
+    assert abs(vals.mean() - expect) < 4 * err, (vals.mean(), expect, err)
+
+
+# ---------------------------------------------------------------------------
+# Kick: conservation and isotropy
+# ---------------------------------------------------------------------------
+def _pair_arrays(rng):
+    v = rng.normal(0, 1, (2, 3))
+    return (v[:, 0].copy(), v[:, 1].copy(), v[:, 2].copy())
+
+
+@pytest.mark.parametrize("model,eps", [(W.MODEL_ELASTIC, 1.0), (W.MODEL_EPS, 0.7)])
+def test_kick_conserves_momentum_and_scales_relative_speed(model, eps):
+    rng = np.random.Generator(np.random.PCG64(3))
+    ids = np.array([5, 9], dtype=np.uint32)
+    for trial in range(200):
+        vx, vy, vz = _pair_arrays(rng)
+        st = np.zeros(2, dtype=np.uint8)
+        p0 = np.array([vx.sum(), vy.sum(), vz.sum()])
+        e0 = 0.5 * (vx**2 + vy**2 + vz**2).sum()
+        w0 = math.sqrt((vx[0] - vx[1])**2 + (vy[0] - vy[1])**2 + (vz[0] - vz[1])**2)
+        oracle.kick_pair(0, 1, vx, vy, vz, st, ids, 1.0, model, eps, 0.0, 1, trial)
+        p1 = np.array([vx.sum(), vy.sum(), vz.sum()])
+        w1 = math.sqrt((vx[0] - vx[1])**2 + (vy[0] - vy[1])**2 + (vz[0] - vz[1])**2)
+        scale = np.abs(np.array([vx, vy, vz])).max() + 1
+        assert np.all(np.abs(p1 - p0) <= 8e-16 * scale)
+        assert w1 == pytest.approx(eps * w0, rel=1e-14)
+        e1 = 0.5 * (vx**2 + vy**2 + vz**2).sum()
+        # centre-of-momentum energy scales by eps^2
+        ecom = 0.25 * w0 * w0          # (1/2) mu w^2, mu = 1/2
+        assert e1 == pytest.approx(e0 - ecom * (1 - eps * eps), rel=1e-13, abs=1e-14)
+
+
+def test_two_state_energy_with_gap_conserved():
+    rng = np.random.Generator(np.random.PCG64(4))
+    ids = np.array([3, 8], dtype=np.uint32)
+    delta = 0.05
+    seen = set()
+    for trial in range(400):
+        vx, vy, vz = _pair_arrays(rng)
+        vx *= 0.3 if trial % 3 == 0 else 1.0     # some pairs below the up-threshold
+        st = rng.integers(0, 2, 2).astype(np.uint8)
+        m = 0.25
+        s_before = st.copy()
+        e0 = 0.5 * m * (vx**2 + vy**2 + vz**2).sum() + m * delta * st.sum()
+        w2 = (vx[0] - vx[1])**2 + (vy[0] - vy[1])**2 + (vz[0] - vz[1])**2
+        oracle.kick_pair(0, 1, vx, vy, vz, st, ids, m, W.MODEL_TWO_STATE, 1.0, delta, 9, trial)
+        e1 = 0.5 * m * (vx**2 + vy**2 + vz**2).sum() + m * delta * st.sum()
+        assert e1 == pytest.approx(e0, rel=1e-13)
+        if s_before.sum() == 0:
+            if w2 > 4 * delta:
+                assert st.sum() == 1
+                seen.add("up")
+            else:
+                assert st.sum() == 0
+                seen.add("below")
+        else:
+            assert st.sum() == s_before.sum() - 1
+            seen.add("down")
+    assert seen == {"up", "down", "below"}
+
+
+def test_scatter_direction_isotropic():
+    from scipy.stats import kstest
+    ids = np.array([1, 2], dtype=np.uint32)
+    cth, phi = [], []
+    for trial in range(20000):
+        vx = np.array([1.0, 0.0]); vy = np.zeros(2); vz = np.zeros(2)
+        oracle.kick_pair(0, 1, vx, vy, vz, np.zeros(2, np.uint8), ids, 1.0,
+                         W.MODEL_ELASTIC, 1.0, 0.0, 17, trial)
+        d = np.array([vx[0] - vx[1], vy[0] - vy[1], vz[0] - vz[1]])
+        d /= np.linalg.norm(d)
+        cth.append(d[0])        # angle to the incoming relative velocity (x axis)
+        phi.append(math.atan2(d[2], d[1]))
+    # f(theta) = sin(theta)/2  <=>  cos(theta) uniform on [-1, 1]
+    assert kstest(cth, "uniform", args=(-1, 2)).pvalue > 1e-3
+    assert kstest(phi, "uniform", args=(-math.pi, 2 * math.pi)).pvalue > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Whole step: rate, conservation, criterion, permutation invariance, passes
+# ---------------------------------------------------------------------------
+def test_scatter_rate_mono_speed_box():
+    # Mono-speed isotropic start (sec. 5.2): mean relative speed 4 v0 / 3.
+    # Expected events per step = (N/2) rho (sigma/m) <w> dt (1 - 1/N) to first order.
+    n, s = 4096, 0.01
+    mw = GOLD["mono_speed_mean_relative_speed_over_v0"]["value"]
+    tot, expect = 0, 0.0
+    for ic in range(12):
+        w = W.uniform_box(n, ic_seed=300 + ic, mono_speed=True, scatters_per_particle=s)
+        ngb, h = oracle.find_ngb(w, brute=False)
+        for ph in range(20):
+            w.seed = 1000 + ph
+            *_, stats = oracle.scatter_step(w, ngb, h, want_info=False)
+            tot += stats["n_events"]
+            expect += 0.5 * n * 1.0 * w.sigma0 * (mw * 1.0) * w.dt[0] * (1 - 1 / n)
+    # Poisson counting error; second-order loss (re-evaluation after a kick) ~ s
+    assert abs(tot - expect) < 4 * math.sqrt(expect) + 2 * s * expect, (tot, expect)
+
+
+def test_step_conserves_energy_momentum_many_scatters():
+    w = W.uniform_box(2048, ic_seed=21, scatters_per_particle=0.8)
+    ngb, h = oracle.find_ngb(w, brute=True)
+    vx, vy, vz, st, info, stats = oracle.scatter_step(w, ngb, h)
+    assert stats["n_events"] > 300 and stats["n_passes"] >= 3
+    p0 = np.array([w.vx.sum(), w.vy.sum(), w.vz.sum()])
+    p1 = np.array([vx.sum(), vy.sum(), vz.sum()])
+    assert np.all(np.abs(p1 - p0) < 1e-12)
+    e0 = (w.vx**2 + w.vy**2 + w.vz**2).sum()
+    e1 = (vx**2 + vy**2 + vz**2).sum()
+    assert e1 == pytest.approx(e0, rel=1e-13)
+    # each kick touches two particles: the moved set is consistent with events
+    moved = (vx != w.vx) | (vy != w.vy) | (vz != w.vz)
+    assert moved.sum() <= 2 * stats["n_events"]
+
+
+def test_two_state_step_conserves_energy_with_gap():
+    w = W.hernquist_halo(3000, ic_seed=22, two_state=True)
+    w.sigma0 *= 30.0
+    ngb, h = oracle.find_ngb(w, brute=True)
+    vx, vy, vz, st, info, stats = oracle.scatter_step(w, ngb, h)
+    assert stats["n_events"] > 50
+    e0 = 0.5 * w.mass * (w.vx**2 + w.vy**2 + w.vz**2).sum() + w.mass * w.delta * w.state.sum()
+    e1 = 0.5 * w.mass * (vx**2 + vy**2 + vz**2).sum() + w.mass * w.delta * st.astype(float).sum()
+    assert e1 == pytest.approx(e0, rel=1e-13)
+    assert (st != w.state).any()
+
+
+def test_criterion_bounds_pair_probability():
+    # With dt_i equal to the bound of Eq. sidm_timestep, every P(i|j) <= C_SIDM.
+    for mk in ("box", "halo"):
+        w = (W.uniform_box(3000, ic_seed=31) if mk == "box"
+             else W.hernquist_halo(3000, ic_seed=32))
+        ngb, h = oracle.find_ngb(w, brute=True)
+        dt = oracle.pair_timestep(w, ngb, h)
+        w.dt = dt
+        *_, stats = oracle.scatter_step(w, ngb, h, want_info=False)
+        assert stats["max_p"] <= w.c_sidm * (1 + 1e-12)
+        assert stats["max_p"] > 0.3 * w.c_sidm     # and the bound is not vacuous
+
+
+def test_permutation_invariance():
+    w = W.uniform_box(3000, ic_seed=41, scatters_per_particle=0.3)
+    w = w.subset_active(2000)
+    base = oracle.full_step(w, brute=True)
+    wp, perm = w.permuted(seed=7)
+    got = oracle.full_step(wp, brute=True)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(w.n)
+    order = wp.meta["active_order"]
+    # neighbour lists map through the permutation; same order (by r2, id)
+    assert np.array_equal(perm[got["ngb"]], base["ngb"][order])
+    assert np.array_equal(got["h"], base["h"][order])
+    for f in ("vx", "vy", "vz"):
+        assert np.array_equal(got[f], base[f][perm])
+    assert np.array_equal(got["dt_sidm"], base["dt_sidm"][order])
+    assert np.array_equal(got["info"], base["info"][order])
+
+
+def test_pass_indices_match_parallel_matching_rounds():
+    # The serial priority order equals repeated rounds in which every accepted
+    # candidate that holds the smallest key at both its particles is decided.
+    w = W.uniform_box(2048, ic_seed=51, scatters_per_particle=1.5)
+    ngb, h = oracle.find_ngb(w, brute=True)
+    *_, info, stats = oracle.scatter_step(w, ngb, h)
+    acc = np.argwhere(info & oracle.CAND_ACCEPT0)
+    assert len(acc) > 500
+    cands = []
+    for a, s in acc:
+        i, j = int(w.active[a]), int(ngb[a, s])
+        idi, idj = int(w.id[i]), int(w.id[j])
+        x = oracle.philox4x32_10([min(idi, idj), max(idi, idj), w.step, 2], [w.seed, 0])
+        word = ((int(x[1]) << 32) | int(x[0])) if idi < idj else ((int(x[3]) << 32) | int(x[2]))
+        cands.append(((word, idi, idj), i, j, int(info[a, s]) >> 8))
+    remaining = list(range(len(cands)))
+    rnd = 0
+    while remaining:
+        rnd += 1
+        best = {}
+        for c in remaining:
+            key, i, j, _ = cands[c]
+            for p in (i, j):
+                if p not in best or key < best[p]:
+                    best[p] = key
+        winners = [c for c in remaining
+                   if best[cands[c][1]] == cands[c][0] and best[cands[c][2]] == cands[c][0]]
+        assert winners
+        for c in winners:
+            assert cands[c][3] == rnd
+        ws = set(winners)
+        remaining = [c for c in remaining if c not in ws]
+    assert rnd == stats["n_passes"]

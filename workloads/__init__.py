@@ -1,0 +1,315 @@
+"""Seeded synthetic inputs for the SIDM scattering step.
+
+This module only *generates inputs*: particle positions, velocities, masses,
+IDs, internal states, the active set and each active particle's timestep, plus
+the scalar parameters of the step (box, cross-section model, scatter model).
+It contains none of the step's own arithmetic (no neighbour search, kernel,
+probability, random draw, kick or timestep criterion).  Both the CPU oracle and
+the GPU library are fed from here; neither is imported by this module.
+
+Workloads (the paper ships no initial conditions, so every one is a stand-in):
+
+* ``uniform_box``     -- periodic unit box, uniform positions, Maxwellian
+  velocities; the thermalisation box of the paper's section 5.2 with a
+  Maxwellian instead of a mono-speed start.
+* ``hernquist_halo``  -- isolated Hernquist (1990) halo, G=M=a=1, sampled from
+  its ergodic distribution function; stands in for the isolated-halo
+  core-collapse runs of section 5.3 (whose IC generator is not available).
+* ``hernquist_bins``  -- power-of-two timestep bins and the active subset for a
+  halo, from the collision-time scaling the paper gives in section 4.4.
+* ``clustered_box``   -- periodic box of NFW haloes plus a uniform background;
+  stands in for the 256^3 cosmological boxes of section 6.2.
+* ``serving_requests`` -- Poisson stream of independent halo requests.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+# Scatter models and cross-section models (mirrors of the library enums; the
+# integer values are part of the C ABI and of the oracle's interface).
+XSEC_CONST = 0
+XSEC_YUKAWA = 1
+MODEL_ELASTIC = 0
+MODEL_EPS = 1
+MODEL_TWO_STATE = 2
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    vx: np.ndarray
+    vy: np.ndarray
+    vz: np.ndarray
+    mass: float                 # equal-mass particles
+    id: np.ndarray              # uint32
+    state: np.ndarray           # uint8 (internal state bit, two-state model)
+    active: np.ndarray          # int32 indices into the particle arrays
+    dt: np.ndarray              # float64 [n_active]
+    periodic: bool = False
+    box: float = 0.0
+    n_ngb: int = 32
+    xsec: int = XSEC_CONST
+    sigma0: float = 0.0         # sigma/m (const) or s0 (Yukawa)
+    w0: float = 1.0
+    model: int = MODEL_ELASTIC
+    eps: float = 1.0
+    delta: float = 0.0
+    c_sidm: float = 0.1
+    seed: int = 1
+    step: int = 0
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    @property
+    def n_active(self) -> int:
+        return int(self.active.shape[0])
+
+    def copy(self) -> "Workload":
+        kw = {}
+        for f in dataclasses.fields(self):
+            v = getattr(self, f.name)
+            kw[f.name] = v.copy() if isinstance(v, (np.ndarray, dict)) else v
+        return Workload(**kw)
+
+    def subset_active(self, n_active: int) -> "Workload":
+        """Same particles, first ``n_active`` entries of the active list."""
+        w = self.copy()
+        w.active = w.active[:n_active].copy()
+        w.dt = w.dt[:n_active].copy()
+        return w
+
+    def permuted(self, seed: int) -> tuple["Workload", np.ndarray]:
+        """Storage-order permutation of the particles (IDs travel along).
+
+        Returns the permuted workload and ``perm`` with new[k] = old[perm[k]].
+        The active list is remapped and itself shuffled.
+        """
+        rng = np.random.Generator(np.random.PCG64(seed))
+        perm = rng.permutation(self.n)
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(self.n)
+        w = self.copy()
+        for f in ("x", "y", "z", "vx", "vy", "vz", "id", "state"):
+            setattr(w, f, getattr(self, f)[perm].copy())
+        order = rng.permutation(self.n_active)
+        w.active = inv[self.active[order]].astype(np.int32)
+        w.dt = self.dt[order].copy()
+        w.meta = dict(self.meta, active_order=order)
+        return w, perm
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ---------------------------------------------------------------------------
+# Uniform periodic box
+# ---------------------------------------------------------------------------
+
+def uniform_box(n: int = 32768, ic_seed: int = 101, philox_seed: int = 1,
+                sigma_1d: float = 1.0, scatters_per_particle: float = 0.01,
+                dt: float = 1.0, n_ngb: int = 32, step: int = 0,
+                lattice: bool = False, mono_speed: bool = False) -> Workload:
+    """Uniform periodic unit box, total mass 1 (rho = 1), Maxwellian velocities.
+
+    sigma/m is set so that the expected number of scatters a particle takes
+    part in during one step is ``scatters_per_particle``: with the rate
+    rho (sigma/m) <w> of the paper's section 5.2 and the Maxwellian mean
+    relative speed <w> = 4 sigma_1D / sqrt(pi), including the (1 - 1/N)
+    expectation of the one-sided kernel density estimate in a finite box.
+
+    ``lattice=True`` places the particles on a simple cubic lattice instead
+    (exact distance ties; n must be a cube).  ``mono_speed=True`` gives every
+    particle speed ``sigma_1d`` in an isotropic direction (the thermalisation
+    start of the paper's section 5.2, mean relative speed 4 v0 / 3).
+    """
+    rng = _rng(ic_seed)
+    if lattice:
+        side = round(n ** (1.0 / 3.0))
+        assert side ** 3 == n, "lattice needs a cube number of particles"
+        g = (np.arange(side, dtype=np.float64) + 0.5) / side
+        gx, gy, gz = np.meshgrid(g, g, g, indexing="ij")
+        x, y, z = gx.ravel().copy(), gy.ravel().copy(), gz.ravel().copy()
+    else:
+        x = rng.random(n)
+        y = rng.random(n)
+        z = rng.random(n)
+    if mono_speed:
+        ux, uy, uz = _isotropic(rng, n)
+        vx, vy, vz = sigma_1d * ux, sigma_1d * uy, sigma_1d * uz
+        mean_w = 4.0 * sigma_1d / 3.0
+    else:
+        vx = rng.normal(0.0, sigma_1d, n)
+        vy = rng.normal(0.0, sigma_1d, n)
+        vz = rng.normal(0.0, sigma_1d, n)
+        mean_w = 4.0 * sigma_1d / math.sqrt(math.pi)
+    sigma_m = scatters_per_particle / ((1.0 - 1.0 / n) * mean_w * dt)
+    return Workload(
+        name=f"uniform_box_n{n}", x=x, y=y, z=z, vx=vx, vy=vy, vz=vz,
+        mass=1.0 / n, id=np.arange(n, dtype=np.uint32),
+        state=np.zeros(n, dtype=np.uint8),
+        active=np.arange(n, dtype=np.int32), dt=np.full(n, dt),
+        periodic=True, box=1.0, n_ngb=n_ngb, xsec=XSEC_CONST, sigma0=sigma_m,
+        seed=philox_seed, step=step,
+        meta=dict(ic_seed=ic_seed, sigma_1d=sigma_1d, lattice=lattice,
+                  mono_speed=mono_speed))
+
+
+# ---------------------------------------------------------------------------
+# Hernquist halo (G = M = a = 1)
+# ---------------------------------------------------------------------------
+
+def hernquist_density(r):
+    """rho(r) = M a / (2 pi r (r + a)^3)  (Hernquist 1990, eq. 2)."""
+    r = np.asarray(r, dtype=np.float64)
+    return 1.0 / (2.0 * np.pi * r * (1.0 + r) ** 3)
+
+
+def hernquist_mass(r):
+    """M(<r) = M r^2 / (r + a)^2."""
+    r = np.asarray(r, dtype=np.float64)
+    return r * r / ((1.0 + r) ** 2)
+
+
+def hernquist_sigma_r(r):
+    """Isotropic Jeans radial velocity dispersion (Hernquist 1990, eq. 10)."""
+    r = np.asarray(r, dtype=np.float64)
+    t1 = 12.0 * r * (1.0 + r) ** 3 * np.log((1.0 + r) / r)
+    t2 = (r / (1.0 + r)) * (25.0 + 52.0 * r + 42.0 * r * r + 12.0 * r ** 3)
+    return np.sqrt(np.maximum(t1 - t2, 0.0) / 12.0)
+
+
+def hernquist_df(eps_rel):
+    """Ergodic DF f(E) of the Hernquist model (Hernquist 1990, eq. 17),
+    as a function of the relative energy eps_rel = -E a / (G M) in (0, 1)."""
+    q = np.sqrt(np.clip(eps_rel, 0.0, 1.0 - 1e-15))
+    q2 = q * q
+    pre = 1.0 / (8.0 * math.sqrt(2.0) * math.pi ** 3) * (1.0 - q2) ** (-2.5)
+    br = (3.0 * np.arcsin(q)
+          + q * np.sqrt(1.0 - q2) * (1.0 - 2.0 * q2) * (8.0 * q2 * q2 - 8.0 * q2 - 3.0))
+    return pre * br
+
+
+def _hernquist_speeds(rng, psi):
+    """Speeds v at relative potential psi from p(v) ~ v^2 f(psi - v^2/2)."""
+    n = psi.shape[0]
+    vesc = np.sqrt(2.0 * psi)
+    # envelope: max of g(x) = x^2 f(psi (1 - x^2)) on a grid, padded
+    xs = np.linspace(0.0, 1.0, 65)[1:-1]
+    gmax = np.zeros(n)
+    for xg in xs:
+        gmax = np.maximum(gmax, xg * xg * hernquist_df(psi * (1.0 - xg * xg)))
+    gmax *= 1.25
+    out = np.empty(n)
+    todo = np.arange(n)
+    while todo.size:
+        xx = rng.random(todo.size)
+        uu = rng.random(todo.size)
+        g = xx * xx * hernquist_df(psi[todo] * (1.0 - xx * xx))
+        ok = uu * gmax[todo] < g
+        out[todo[ok]] = xx[ok] * vesc[todo[ok]]
+        todo = todo[~ok]
+    return out
+
+
+def _isotropic(rng, n):
+    cth = 2.0 * rng.random(n) - 1.0
+    phi = 2.0 * np.pi * rng.random(n)
+    sth = np.sqrt(np.maximum(0.0, 1.0 - cth * cth))
+    return sth * np.cos(phi), sth * np.sin(phi), cth
+
+
+def yukawa_mean(sigma_1d: float, w0: float, n_quad: int = 4000) -> float:
+    """< w / (1 + (w/w0)^2)^2 > over Maxwellian relative speeds (1D dispersion
+    sqrt(2) sigma_1d), by quadrature.  Used only to normalise s0."""
+    s = math.sqrt(2.0) * sigma_1d
+    w = np.linspace(0.0, 12.0 * s, n_quad + 1)
+    pdf = np.sqrt(2.0 / np.pi) * w * w / s ** 3 * np.exp(-w * w / (2.0 * s * s))
+    f = w / (1.0 + (w / w0) ** 2) ** 2 * pdf
+    return float(np.trapezoid(f, w))
+
+
+def hernquist_s0(w0: float = 0.5) -> float:
+    """s0 giving ~1 scatter per particle per dynamical time at r = a:
+    s0 = 1 / (t_dyn(a) rho(a) < w / (1+(w/w0)^2)^2 >), t_dyn(a) = sqrt(a^3 / G M(<a))."""
+    t_dyn = math.sqrt(1.0 / float(hernquist_mass(1.0)))
+    rho_a = float(hernquist_density(1.0))
+    sig_a = float(hernquist_sigma_r(1.0))
+    return 1.0 / (t_dyn * rho_a * yukawa_mean(sig_a, w0))
+
+
+def hernquist_halo(n: int = 1_000_000, ic_seed: int = 102, philox_seed: int = 2,
+                   r_max: float = 100.0, w0: float = 0.5,
+                   s0: Optional[float] = None, n_ngb: int = 32,
+                   two_state: bool = False, delta_frac: float = 0.05,
+                   step: int = 0) -> Workload:
+    """Hernquist halo particles (all active, dt = 1 until binned)."""
+    rng = _rng(ic_seed)
+    m_trunc = float(hernquist_mass(r_max))
+    xq = rng.random(n) * m_trunc            # M(<r) uniform below the truncation
+    sq = np.sqrt(xq)
+    r = sq / (1.0 - sq)
+    ux, uy, uz = _isotropic(rng, n)
+    x, y, z = r * ux, r * uy, r * uz
+    psi = 1.0 / (1.0 + r)
+    v = _hernquist_speeds(rng, psi)
+    wx, wy, wz = _isotropic(rng, n)
+    state = np.zeros(n, dtype=np.uint8)
+    model, delta = MODEL_ELASTIC, 0.0
+    if two_state:
+        state = (rng.random(n) < 0.5).astype(np.uint8)
+        model = MODEL_TWO_STATE
+        delta = delta_frac * float(hernquist_sigma_r(1.0)) ** 2
+    if s0 is None:
+        s0 = hernquist_s0(w0)
+    return Workload(
+        name=f"hernquist_n{n}" + ("_2state" if two_state else ""),
+        x=x, y=y, z=z, vx=v * wx, vy=v * wy, vz=v * wz, mass=1.0 / n,
+        id=np.arange(n, dtype=np.uint32), state=state,
+        active=np.arange(n, dtype=np.int32), dt=np.ones(n),
+        periodic=False, box=0.0, n_ngb=n_ngb, xsec=XSEC_YUKAWA, sigma0=s0,
+        w0=w0, model=model, delta=delta, seed=philox_seed, step=step,
+        meta=dict(ic_seed=ic_seed, r_max=r_max, r=r))
+
+
+def hernquist_bins(w: Workload, active_frac: float = 0.125, dt_max: float = 2.0,
+                   n_ngb: int = 32, c_sidm: float = 0.1) -> Workload:
+    """Power-of-two timestep bins from the local collision time, and the
+    active set of one synchronisation point with at most ``active_frac`` of the
+    particles active.
+
+    Each particle's target step is the paper's collision-time scaling of the
+    per-pair criterion (section 4.4): dt ~ (3 N_ngb C / 16) / (rho sigma(v) v),
+    evaluated with the analytic density and the Maxwellian mean relative speed
+    4 sigma_1D / sqrt(pi) at the particle's radius.  Bin b holds steps
+    dt_max / 2^b; the active set is every particle in bins >= b*, b* being the
+    smallest bin for which at most ``active_frac`` of all particles are in bins
+    >= b*.
+    """
+    r = np.sqrt(w.x ** 2 + w.y ** 2 + w.z ** 2)
+    vbar = 4.0 * hernquist_sigma_r(r) / math.sqrt(math.pi)
+    sig = w.sigma0 / (1.0 + (vbar / w.w0) ** 2) ** 2
+    dt_t = (3.0 * n_ngb * c_sidm / 16.0) / (hernquist_density(r) * sig * vbar)
+    b = np.ceil(np.log2(dt_max / dt_t)).clip(0, 40).astype(np.int64)
+    counts = np.bincount(b, minlength=41)
+    tail = np.cumsum(counts[::-1])[::-1]          # particles in bins >= b
+    ok = np.nonzero(tail <= active_frac * w.n)[0]
+    b_star = int(ok[0])
+    act = np.nonzero(b >= b_star)[0].astype(np.int32)
+    out = w.copy()
+    out.active = act
+    out.dt = dt_max / (2.0 ** b[act].astype(np.float64))
+    out.name = w.name + "_bins"
+    out.meta = dict(w.meta, b_star=b_star, dt_max=dt_max,
+                    active_fraction=act.size / w.n)
+    return out
