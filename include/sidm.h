@@ -1,0 +1,182 @@
+/*
+ * sidm.h -- C ABI of the MI355X (gfx950) SIDM scattering step.
+ *
+ * The library performs the Monte-Carlo self-interacting dark matter
+ * scattering step of Zier et al., "A Novel Implementation of Self-Interacting
+ * Dark Matter in AREPO" (arXiv 2607.05504) on one GPU:
+ *
+ *   sidm_build_tree     spatial sort + bucket tree of the DM particles
+ *                       (the dedicated DM-only neighbour tree of sec. 4.3)
+ *   sidm_find_ngb       N_ngb nearest neighbours and smoothing length of every
+ *                       active particle (sec. 4.2, 4.5)
+ *   sidm_scatter_step   pair probabilities P(i|j) (Eqs. rate, oneSided,
+ *                       probabilityScatter), random draws, conflict resolution
+ *                       and momentum/energy-conserving kicks (sec. 4.1, 4.5)
+ *   sidm_pair_timestep  per-pair timestep bound (Eq. sidm_timestep, sec. 4.4)
+ *
+ * Conventions shared by every call:
+ *   - All array arguments are DEVICE pointers on the context's device, owned
+ *     by the caller (for example torch tensors' data_ptr()).  The library
+ *     owns only the scratch it allocates in sidm_create; no call after
+ *     sidm_create allocates device memory.
+ *   - Every call is asynchronous and ordered on the context's HIP stream.
+ *     Errors found on the host (bad sizes, NULL pointers, capacity) are
+ *     returned before anything is enqueued and leave every array untouched.
+ *     Errors found by a kernel (an index out of range, a duplicate active
+ *     entry, an overflowing accepted list) are latched in the context and
+ *     returned by sidm_sync (and by the next call that checks them).
+ *   - Indices in `active` and `ngb` are in the caller's particle order.
+ *   - A context is not thread-safe.  Distinct contexts are independent and
+ *     may run concurrently on different streams.
+ *
+ * Semantics fixed by this library where the paper leaves them open:
+ *   - N(i) is the set of the n_ngb particles j != i with the smallest
+ *     (r_ij^2, id_j), inactive particles included; h_i is the distance of the
+ *     (n_ngb+1)-th, so every neighbour lies inside the kernel support (the
+ *     paper iterates h to 32 +- 5 neighbours).  Distances use the minimum
+ *     image in a periodic box:  d = x_j - x_i;  d >= L/2 -> d - L;
+ *     d < -L/2 -> d + L;  r^2 = (dx*dx + dy*dy) + dz*dz.
+ *   - P(i|j) = ((((1/2 m_j) sigma(w)/m) w) W(r_ij, h_i)) dt_i with
+ *     w = |v_i - v_j|, the cubic-spline W of sec. 4.2.
+ *   - Random numbers: Philox4x32-10 keyed on `seed`, counter (min id,
+ *     max id, step, purpose); purpose 0 decides, 1/3 give the direction for
+ *     the lower/higher-ID target, 2 gives the priority.  Of a draw's words,
+ *     (x0, x1) serve the lower-ID target and (x2, x3) the higher-ID target;
+ *     u = (word >> 11) * 2^-53.
+ *   - Every candidate (i|j) is evaluated once with the step-start
+ *     velocities (accept iff u < P).  The accepted ones are then applied in
+ *     increasing (priority, id_i, id_j) order, each re-evaluated with the
+ *     current velocities and the same u.  The device runs this as passes: in
+ *     each pass every particle scatters with at most one partner.
+ */
+#ifndef SIDM_H
+#define SIDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SIDM_OK = 0,
+    SIDM_E_INVAL = -1,     /* invalid argument (host) or invalid index/duplicate (device) */
+    SIDM_E_NOMEM = -2,     /* device allocation failed in sidm_create                  */
+    SIDM_E_DEVICE = -3,    /* HIP runtime error                                        */
+    SIDM_E_CAPACITY = -4,  /* n or n_active above the context's capacity               */
+    SIDM_E_OVERFLOW = -5,  /* accepted-candidate list overflowed (results invalid)     */
+    SIDM_E_STATE = -6      /* call out of order (e.g. find_ngb before build_tree)      */
+} sidm_status;
+
+enum { SIDM_KERNEL_CUBIC_SPLINE = 0 };
+enum { SIDM_XSEC_CONST = 0, SIDM_XSEC_YUKAWA = 1 };
+enum { SIDM_MODEL_ELASTIC = 0, SIDM_MODEL_EPS = 1, SIDM_MODEL_TWO_STATE = 2 };
+enum { SIDM_FP64 = 0, SIDM_MIXED = 1 };
+
+/* per-candidate info word (optional output of sidm_scatter_step) */
+#define SIDM_CAND_ACCEPT0 1u   /* accepted by the step-start evaluation          */
+#define SIDM_CAND_SCATTER 2u   /* produced a kick                                */
+#define SIDM_CAND_FLAGGED 4u   /* an evaluation had |P - u| < flag_band          */
+/* bits 8..31: pass that decided the candidate (0 = not accepted at step start) */
+
+typedef struct {
+    int32_t n_ngb;        /* neighbours per target, 1..64 (paper: 32)                    */
+    int32_t kernel;       /* SIDM_KERNEL_CUBIC_SPLINE                                     */
+    int32_t periodic;     /* 1: periodic cube [0, box)^3 with minimum image; 0: open      */
+    int32_t xsec;         /* SIDM_XSEC_CONST: sigma/m = sigma0;
+                             SIDM_XSEC_YUKAWA: sigma0 / (1 + (w/w0)^2)^2                  */
+    int32_t model;        /* SIDM_MODEL_ELASTIC (eps = 1), SIDM_MODEL_EPS (constant eps),
+                             SIDM_MODEL_TWO_STATE (ground/excited, gap delta per unit mass) */
+    int32_t precision;    /* SIDM_FP64, or SIDM_MIXED (FP32 search/probability with an
+                             FP64 recheck inside the bands below; kicks stay FP64)        */
+    double box;           /* periodic box side L                                          */
+    double sigma0, w0;    /* cross-section parameters                                     */
+    double eps, delta;    /* constant eps; two-state energy gap per unit mass             */
+    double c_sidm;        /* timestep coefficient (paper: 0.1)                            */
+    double flag_band;     /* evaluations with |P - u| < flag_band are flagged (1e-9)      */
+    double band_r2;       /* mixed form: relative r^2 band rechecked in FP64              */
+    double band_p;        /* mixed form: relative |P - u| band rechecked in FP64          */
+} sidm_config;
+
+typedef struct {
+    const double *x, *y, *z;     /* positions [n]                                        */
+    double *vx, *vy, *vz;        /* velocities [n]; updated by sidm_scatter_step         */
+    const double *mass;          /* per-particle mass [n], or NULL to use m_scalar        */
+    double m_scalar;
+    const uint32_t *id;          /* unique particle IDs [n] (tie-break and RNG key)      */
+    uint8_t *state;              /* internal state bit [n] (two-state model), else NULL   */
+    int64_t n;
+} sidm_particles;
+
+typedef struct {
+    int64_t n_cand;       /* candidates evaluated at step start (n_active * n_ngb)       */
+    int64_t n_accept0;    /* accepted at step start                                      */
+    int64_t n_events;     /* kicks applied                                               */
+    int64_t n_flagged;    /* evaluations with |P - u| < flag_band                        */
+    int64_t n_p_ge_1;     /* step-start evaluations with P >= 1 (always accepted)        */
+    int64_t n_recheck;    /* mixed form: evaluations redone in FP64                      */
+    int32_t n_passes;     /* resolution passes used                                      */
+    int32_t error;        /* latched sidm_status of the device, 0 if none                */
+    double max_p;         /* largest step-start P                                        */
+} sidm_stats;
+
+typedef struct sidm_ctx sidm_ctx;
+
+/* Device bytes sidm_create would allocate for these capacities (the serving
+ * layer admits work against an HBM budget with it).  No device work. */
+sidm_status sidm_footprint(const sidm_config *cfg, int64_t cap_n, int64_t cap_active,
+                           size_t *bytes);
+
+/* Create a context on the current HIP device with capacity for cap_n
+ * particles and cap_active active particles; `hip_stream` (hipStream_t, may be
+ * NULL for the default stream) orders all its work.  *out receives the
+ * context, or NULL on error. */
+sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_active,
+                        void *hip_stream, sidm_ctx **out);
+sidm_status sidm_destroy(sidm_ctx *ctx);
+sidm_status sidm_set_stream(sidm_ctx *ctx, void *hip_stream);
+
+/* Last error message of the context (host-side text), "" if none. */
+const char *sidm_last_error(const sidm_ctx *ctx);
+const char *sidm_status_string(sidm_status s);
+
+/* Snapshot and spatially sort the particles (all of them, active or not:
+ * inactive particles are neighbours too).  The calls that follow read
+ * positions and velocities from this snapshot, and sidm_scatter_step keeps it
+ * in step with the velocity/state updates it writes back to the caller's
+ * arrays.  The caller must not change x, v or state between sidm_build_tree
+ * and the last call of the step.  Requires n_ngb + 2 <= n <= cap_n. */
+sidm_status sidm_build_tree(sidm_ctx *ctx, const sidm_particles *p);
+
+/* For every active particle a (0 <= a < n_active, active[a] a particle
+ * index, no duplicates): ngb[a*n_ngb + s] = its s-th nearest neighbour
+ * (ascending (r^2, id)), h[a] = distance of the (n_ngb+1)-th. */
+sidm_status sidm_find_ngb(sidm_ctx *ctx, const int32_t *active, int64_t n_active,
+                          int32_t *ngb, double *h);
+
+/* One scattering step of the active particles with neighbour lists ngb and
+ * smoothing lengths h (as produced by sidm_find_ngb), timesteps dt[n_active],
+ * Philox seed and step counter.  Velocities (and state) of every kicked
+ * particle are written to p's arrays, which must be the arrays given to
+ * sidm_build_tree.  cand_info (optional, [n_active*n_ngb]) receives the
+ * SIDM_CAND_* bits and pass index of every candidate. */
+sidm_status sidm_scatter_step(sidm_ctx *ctx, sidm_particles *p, const int32_t *active,
+                              int64_t n_active, const int32_t *ngb, const double *h,
+                              const double *dt, uint64_t seed, uint32_t step,
+                              uint32_t *cand_info);
+
+/* dt_sidm[a] = c_sidm * 2 / (m_i W(0, h_a) max_{j in N(i)} w_ij sigma(w_ij)/m) with
+ * the current (post-kick) velocities; +inf when the maximum is 0. */
+sidm_status sidm_pair_timestep(sidm_ctx *ctx, const int32_t *active, int64_t n_active,
+                               const int32_t *ngb, const double *h, double *dt_sidm);
+
+/* Wait for the context's stream, copy the statistics of the last
+ * sidm_scatter_step into *out (may be NULL) and return the latched device
+ * error (SIDM_OK if none).  Clears the latched error. */
+sidm_status sidm_sync(sidm_ctx *ctx, sidm_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIDM_H */

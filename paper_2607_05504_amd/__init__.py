@@ -1,0 +1,230 @@
+"""Thin Python binding of libsidm.so, the gfx950 SIDM scattering-step library.
+
+Only argument marshalling lives here: every step of the method runs in the HIP
+kernels behind the C ABI declared in ``include/sidm.h``.  PyTorch provides
+device memory and the HIP stream.  There is no CPU fallback: if the library
+is not built, importing :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsidm.so")
+
+SIDM_OK = 0
+SIDM_E_INVAL = -1
+SIDM_E_NOMEM = -2
+SIDM_E_DEVICE = -3
+SIDM_E_CAPACITY = -4
+SIDM_E_OVERFLOW = -5
+SIDM_E_STATE = -6
+
+KERNEL_CUBIC_SPLINE = 0
+XSEC_CONST, XSEC_YUKAWA = 0, 1
+MODEL_ELASTIC, MODEL_EPS, MODEL_TWO_STATE = 0, 1, 2
+FP64, MIXED = 0, 1
+
+CAND_ACCEPT0 = 1
+CAND_SCATTER = 2
+CAND_FLAGGED = 4
+
+
+class SidmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_ngb", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("periodic", ctypes.c_int32), ("xsec", ctypes.c_int32),
+                ("model", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("box", ctypes.c_double), ("sigma0", ctypes.c_double), ("w0", ctypes.c_double),
+                ("eps", ctypes.c_double), ("delta", ctypes.c_double),
+                ("c_sidm", ctypes.c_double), ("flag_band", ctypes.c_double),
+                ("band_r2", ctypes.c_double), ("band_p", ctypes.c_double)]
+
+
+class Particles(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("vx", ctypes.c_void_p), ("vy", ctypes.c_void_p), ("vz", ctypes.c_void_p),
+                ("mass", ctypes.c_void_p), ("m_scalar", ctypes.c_double),
+                ("id", ctypes.c_void_p), ("state", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_cand", ctypes.c_int64), ("n_accept0", ctypes.c_int64),
+                ("n_events", ctypes.c_int64), ("n_flagged", ctypes.c_int64),
+                ("n_p_ge_1", ctypes.c_int64), ("n_recheck", ctypes.c_int64),
+                ("n_passes", ctypes.c_int32), ("error", ctypes.c_int32),
+                ("max_p", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# Every symbol include/sidm.h declares (tests check the library exports them).
+EXPORTS = ["sidm_footprint", "sidm_create", "sidm_destroy", "sidm_set_stream",
+           "sidm_last_error", "sidm_status_string", "sidm_build_tree", "sidm_find_ngb",
+           "sidm_scatter_step", "sidm_pair_timestep", "sidm_sync"]
+
+_lib = None
+
+
+def lib():
+    """Load libsidm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i64, u64, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32
+        CP = ctypes.POINTER(Config)
+        L.sidm_footprint.argtypes = [CP, i64, i64, ctypes.POINTER(ctypes.c_size_t)]
+        L.sidm_create.argtypes = [CP, i64, i64, P, ctypes.POINTER(ctypes.c_void_p)]
+        L.sidm_destroy.argtypes = [P]
+        L.sidm_set_stream.argtypes = [P, P]
+        L.sidm_last_error.argtypes = [P]
+        L.sidm_last_error.restype = ctypes.c_char_p
+        L.sidm_status_string.argtypes = [ctypes.c_int]
+        L.sidm_status_string.restype = ctypes.c_char_p
+        L.sidm_build_tree.argtypes = [P, ctypes.POINTER(Particles)]
+        L.sidm_find_ngb.argtypes = [P, P, i64, P, P]
+        L.sidm_scatter_step.argtypes = [P, ctypes.POINTER(Particles), P, i64, P, P, P, u64, u32, P]
+        L.sidm_pair_timestep.argtypes = [P, P, i64, P, P, P]
+        L.sidm_sync.argtypes = [P, ctypes.POINTER(Stats)]
+        for name in EXPORTS:
+            if name not in ("sidm_last_error", "sidm_status_string"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def make_config(n_ngb=32, periodic=False, box=0.0, xsec=XSEC_CONST, sigma0=0.0, w0=1.0,
+                model=MODEL_ELASTIC, eps=1.0, delta=0.0, c_sidm=0.1, precision=FP64,
+                flag_band=1e-9, band_r2=1e-5, band_p=1e-5) -> Config:
+    return Config(int(n_ngb), KERNEL_CUBIC_SPLINE, int(bool(periodic)), int(xsec), int(model),
+                  int(precision), float(box), float(sigma0), float(w0), float(eps), float(delta),
+                  float(c_sidm), float(flag_band), float(band_r2), float(band_p))
+
+
+def footprint(cfg: Config, cap_n: int, cap_active: int) -> int:
+    out = ctypes.c_size_t(0)
+    st = lib().sidm_footprint(ctypes.byref(cfg), int(cap_n), int(cap_active), ctypes.byref(out))
+    if st != SIDM_OK:
+        raise SidmError(st, "sidm_footprint")
+    return int(out.value)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+class Context:
+    """One sidm_ctx: scratch for up to ``cap_n`` particles / ``cap_active`` targets,
+    bound to a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, cfg: Config, cap_n: int, cap_active: int, stream=None):
+        import torch
+        self.cfg = cfg
+        self._torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = lib().sidm_create(ctypes.byref(cfg), int(cap_n), int(cap_active),
+                               ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if st != SIDM_OK:
+            raise SidmError(st, "sidm_create")
+        self._h = h
+        self._particles = None
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, st: int, what: str):
+        if st != SIDM_OK:
+            msg = lib().sidm_last_error(self._h).decode()
+            raise SidmError(st, f"{what}: {msg}")
+
+    @staticmethod
+    def _dev(t, dtype, name):
+        if t is None:
+            return None
+        if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+            raise ValueError(f"{name}: need a contiguous {dtype} device tensor")
+        return t
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sidm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self.stream = stream
+        self._check(lib().sidm_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)),
+                    "sidm_set_stream")
+
+    # -- the four calls of the step ----------------------------------------------
+    def build_tree(self, x, y, z, vx, vy, vz, ids, state=None, mass=None, m_scalar=0.0):
+        torch = self._torch
+        f64 = torch.float64
+        arrs = dict(x=self._dev(x, f64, "x"), y=self._dev(y, f64, "y"), z=self._dev(z, f64, "z"),
+                    vx=self._dev(vx, f64, "vx"), vy=self._dev(vy, f64, "vy"),
+                    vz=self._dev(vz, f64, "vz"), id=self._dev(ids, torch.int32, "id"),
+                    state=self._dev(state, torch.uint8, "state"),
+                    mass=self._dev(mass, f64, "mass"))
+        p = Particles(_ptr(arrs["x"]), _ptr(arrs["y"]), _ptr(arrs["z"]), _ptr(arrs["vx"]),
+                      _ptr(arrs["vy"]), _ptr(arrs["vz"]), _ptr(arrs["mass"]), float(m_scalar),
+                      _ptr(arrs["id"]), _ptr(arrs["state"]), int(x.shape[0]))
+        self._particles = (p, arrs)      # keep tensors alive while the snapshot is in use
+        self._check(lib().sidm_build_tree(self._h, ctypes.byref(p)), "sidm_build_tree")
+
+    def find_ngb(self, active, ngb, h):
+        torch = self._torch
+        self._dev(active, torch.int32, "active")
+        self._dev(ngb, torch.int32, "ngb")
+        self._dev(h, torch.float64, "h")
+        self._check(lib().sidm_find_ngb(self._h, _ptr(active), int(active.shape[0]), _ptr(ngb),
+                                        _ptr(h)), "sidm_find_ngb")
+
+    def scatter_step(self, active, ngb, h, dt, seed: int, step: int, cand_info=None):
+        torch = self._torch
+        if self._particles is None:
+            raise SidmError(SIDM_E_STATE, "scatter_step before build_tree")
+        self._dev(active, torch.int32, "active")
+        self._dev(ngb, torch.int32, "ngb")
+        self._dev(h, torch.float64, "h")
+        self._dev(dt, torch.float64, "dt")
+        self._dev(cand_info, torch.int32, "cand_info")
+        p = self._particles[0]
+        self._check(lib().sidm_scatter_step(self._h, ctypes.byref(p), _ptr(active),
+                                            int(active.shape[0]), _ptr(ngb), _ptr(h), _ptr(dt),
+                                            int(seed) & (2**64 - 1), int(step) & (2**32 - 1),
+                                            _ptr(cand_info)), "sidm_scatter_step")
+
+    def pair_timestep(self, active, ngb, h, dt_sidm):
+        torch = self._torch
+        self._dev(active, torch.int32, "active")
+        self._dev(ngb, torch.int32, "ngb")
+        self._dev(h, torch.float64, "h")
+        self._dev(dt_sidm, torch.float64, "dt_sidm")
+        self._check(lib().sidm_pair_timestep(self._h, _ptr(active), int(active.shape[0]),
+                                             _ptr(ngb), _ptr(h), _ptr(dt_sidm)),
+                    "sidm_pair_timestep")
+
+    def sync(self) -> dict:
+        s = Stats()
+        st = lib().sidm_sync(self._h, ctypes.byref(s))
+        d = s.as_dict()
+        self._check(st, "sidm_sync")
+        return d

@@ -1,0 +1,380 @@
+// Host side of the C ABI (include/sidm.h): context lifetime, scratch
+// allocation sized once from the capacities, argument validation, and the
+// stream-ordered launch of each step's kernels.
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "sidm_internal.h"
+
+namespace {
+
+// Allocation plan: every buffer the context owns, sized from the capacities.
+struct Plan {
+    struct Item { void **dst; size_t bytes; };
+    Item items[64];
+    int n = 0;
+    size_t total = 0;
+    void add(void **dst, size_t bytes)
+    {
+        bytes = (bytes + 255) & ~(size_t)255;
+        items[n++] = Item{dst, bytes};
+        total += bytes;
+    }
+};
+
+int64_t acc_capacity(int64_t cap_active, int k)
+{
+    int64_t full = cap_active * (int64_t)k;
+    const int64_t floor_cap = (int64_t)1 << 20;
+    if (full <= floor_cap) return full > 0 ? full : 1;
+    int64_t quarter = full / 4;
+    return quarter > floor_cap ? quarter : floor_cap;
+}
+
+void make_plan(sidm_ctx *c, Plan &P)
+{
+    const int64_t N = c->cap_n, NA = c->cap_active;
+    const int k = c->cfg.n_ngb;
+    void **v;
+#define ADD(field, count, type) v = (void **)&c->field; P.add(v, (size_t)(count) * sizeof(type))
+    ADD(xs, N, double); ADD(ys, N, double); ADD(zs, N, double);
+    ADD(vxs, N, double); ADD(vys, N, double); ADD(vzs, N, double); ADD(ms, N, double);
+    ADD(ids, N, uint32_t); ADD(sts, N, uint8_t);
+    ADD(perm, N, int32_t); ADD(inv, N, int32_t);
+    ADD(key0, N, uint64_t); ADD(key1, N, uint64_t);
+    ADD(val0, N, int32_t); ADD(val1, N, int32_t);
+    const int64_t nsb = (N + SIDM_SORT_TILE - 1) / SIDM_SORT_TILE;
+    ADD(hist, 256 * nsb, uint32_t);
+    ADD(dtot, 256, uint32_t);
+    ADD(bounds, 6, unsigned long long);
+    int64_t nleaf = (N + SIDM_LEAF - 1) / SIDM_LEAF, p2 = 2;
+    while (p2 < nleaf) p2 <<= 1;
+    ADD(nodes, 2 * p2 * 6, double);
+    ADD(visit, p2, int32_t);
+    ADD(flag, N, int32_t);
+    ADD(tlist, NA, int32_t); ADD(slot, NA, int32_t);
+    ADD(blk, (N + SIDM_SCAN_TILE - 1) / SIDM_SCAN_TILE + 1, int32_t);
+    ADD(nt_dev, 1, int32_t);
+    const int64_t CA = acc_capacity(NA, k);
+    c->cap_acc = CA;
+    for (int b = 0; b < 2; ++b) {
+        ADD(acc[b].i, CA, int32_t); ADD(acc[b].j, CA, int32_t); ADD(acc[b].cand, CA, int32_t);
+        ADD(acc[b].u, CA, double); ADD(acc[b].W, CA, double); ADD(acc[b].dt, CA, double);
+        ADD(acc[b].prio, CA, uint64_t); ADD(acc[b].idpair, CA, uint64_t);
+        ADD(claim1[b], N, unsigned long long); ADD(claim2[b], N, unsigned long long);
+    }
+    ADD(acc_count, 8, int32_t);
+    ADD(dstats, 1, DevStats);
+    ADD(derr, 1, unsigned int);
+#undef ADD
+}
+
+void set_err(sidm_ctx *c, const char *fmt, ...)
+{
+    if (!c) return;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof c->err, fmt, ap);
+    va_end(ap);
+}
+
+sidm_status check_config(const sidm_config *cfg)
+{
+    if (!cfg) return SIDM_E_INVAL;
+    if (cfg->n_ngb < 1 || cfg->n_ngb > 64) return SIDM_E_INVAL;
+    if (cfg->kernel != SIDM_KERNEL_CUBIC_SPLINE) return SIDM_E_INVAL;
+    if (cfg->periodic && !(cfg->box > 0.0)) return SIDM_E_INVAL;
+    if (cfg->xsec != SIDM_XSEC_CONST && cfg->xsec != SIDM_XSEC_YUKAWA) return SIDM_E_INVAL;
+    if (cfg->xsec == SIDM_XSEC_YUKAWA && !(cfg->w0 > 0.0)) return SIDM_E_INVAL;
+    if (cfg->model < SIDM_MODEL_ELASTIC || cfg->model > SIDM_MODEL_TWO_STATE) return SIDM_E_INVAL;
+    if (cfg->precision != SIDM_FP64 && cfg->precision != SIDM_MIXED) return SIDM_E_INVAL;
+    if (!(cfg->c_sidm > 0.0)) return SIDM_E_INVAL;
+    if (!(cfg->flag_band >= 0.0)) return SIDM_E_INVAL;
+    return SIDM_OK;
+}
+
+sidm_status hip_fail(sidm_ctx *c, hipError_t e, const char *what)
+{
+    set_err(c, "%s: %s", what, hipGetErrorString(e));
+    return SIDM_E_DEVICE;
+}
+
+// Device errors latched by kernels, read without waiting (only when the host
+// already synchronised); here we only translate the bits.
+sidm_status status_from_bits(unsigned int bits)
+{
+    if (!bits) return SIDM_OK;
+    if (bits & DERR_OVERFLOW) return SIDM_E_OVERFLOW;
+    return SIDM_E_INVAL;
+}
+
+bool test_fail_alloc()
+{
+    const char *e = getenv("SIDM_TEST_FAIL_ALLOC");
+    return e && e[0] == '1';
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sidm_status_string(sidm_status s)
+{
+    switch (s) {
+    case SIDM_OK: return "ok";
+    case SIDM_E_INVAL: return "invalid argument";
+    case SIDM_E_NOMEM: return "out of device memory";
+    case SIDM_E_DEVICE: return "HIP runtime error";
+    case SIDM_E_CAPACITY: return "capacity exceeded";
+    case SIDM_E_OVERFLOW: return "accepted-candidate list overflow";
+    case SIDM_E_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+sidm_status sidm_footprint(const sidm_config *cfg, int64_t cap_n, int64_t cap_active, size_t *bytes)
+{
+    if (!bytes || check_config(cfg) != SIDM_OK) return SIDM_E_INVAL;
+    if (cap_n < cfg->n_ngb + 2 || cap_active < 0 || cap_active > cap_n) return SIDM_E_INVAL;
+    sidm_ctx tmp;
+    memset(&tmp, 0, sizeof tmp);
+    tmp.cfg = *cfg;
+    tmp.cap_n = cap_n;
+    tmp.cap_active = cap_active > 0 ? cap_active : 1;
+    Plan P;
+    make_plan(&tmp, P);
+    *bytes = P.total;
+    return SIDM_OK;
+}
+
+sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_active, void *hip_stream,
+                        sidm_ctx **out)
+{
+    if (!out) return SIDM_E_INVAL;
+    *out = nullptr;
+    if (check_config(cfg) != SIDM_OK) return SIDM_E_INVAL;
+    if (cap_n < cfg->n_ngb + 2 || cap_n > ((int64_t)1 << 31) - 1 || cap_active < 1 ||
+        cap_active > cap_n)
+        return SIDM_E_INVAL;
+    sidm_ctx *c = (sidm_ctx *)calloc(1, sizeof(sidm_ctx));
+    if (!c) return SIDM_E_NOMEM;
+    c->cfg = *cfg;
+    c->cap_n = cap_n;
+    c->cap_active = cap_active;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) { free(c); return SIDM_E_DEVICE; }
+    Plan P;
+    make_plan(c, P);
+    char *base = nullptr;
+    if (test_fail_alloc() || hipMalloc((void **)&base, P.total) != hipSuccess) {
+        (void)hipGetLastError();
+        free(c);
+        return SIDM_E_NOMEM;
+    }
+    c->dev_base = base;
+    size_t off = 0;
+    for (int t = 0; t < P.n; ++t) {
+        *P.items[t].dst = base + off;
+        off += P.items[t].bytes;
+    }
+    if (hipHostMalloc((void **)&c->hstats, sizeof(DevStats) + 64, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(base);
+        free(c);
+        return SIDM_E_NOMEM;
+    }
+    c->herr = (unsigned int *)((char *)c->hstats + sizeof(DevStats));
+    hipStream_t s = c->stream;
+    // claims start cleared; error word and counters zero
+    for (int b = 0; b < 2; ++b) {
+        launch_fill_u64(c->claim1[b], ~0ull, cap_n, s);
+        launch_fill_u64(c->claim2[b], ~0ull, cap_n, s);
+    }
+    launch_fill_i32((int32_t *)c->derr, 0, 1, s);
+    launch_fill_i32(c->acc_count, 0, 8, s);
+    launch_fill_i32((int32_t *)c->dstats, 0, (int64_t)(sizeof(DevStats) / 4), s);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(base);
+        (void)hipHostFree(c->hstats);
+        free(c);
+        return SIDM_E_DEVICE;
+    }
+    c->err[0] = 0;
+    *out = c;
+    return SIDM_OK;
+}
+
+sidm_status sidm_destroy(sidm_ctx *c)
+{
+    if (!c) return SIDM_E_INVAL;
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->dev_base);
+    (void)hipHostFree(c->hstats);
+    free(c);
+    return SIDM_OK;
+}
+
+sidm_status sidm_set_stream(sidm_ctx *c, void *hip_stream)
+{
+    if (!c) return SIDM_E_INVAL;
+    c->stream = (hipStream_t)hip_stream;
+    return SIDM_OK;
+}
+
+const char *sidm_last_error(const sidm_ctx *c)
+{
+    return c ? c->err : "null context";
+}
+
+sidm_status sidm_build_tree(sidm_ctx *c, const sidm_particles *p)
+{
+    if (!c) return SIDM_E_INVAL;
+    if (!p || !p->x || !p->y || !p->z || !p->vx || !p->vy || !p->vz || !p->id) {
+        set_err(c, "build_tree: NULL particle array");
+        return SIDM_E_INVAL;
+    }
+    if (p->n < c->cfg.n_ngb + 2) {
+        set_err(c, "build_tree: n=%lld < n_ngb+2", (long long)p->n);
+        return SIDM_E_INVAL;
+    }
+    if (p->n > c->cap_n) {
+        set_err(c, "build_tree: n=%lld above capacity %lld", (long long)p->n, (long long)c->cap_n);
+        return SIDM_E_CAPACITY;
+    }
+    if (!p->mass && !(p->m_scalar > 0.0)) {
+        set_err(c, "build_tree: no mass array and m_scalar <= 0");
+        return SIDM_E_INVAL;
+    }
+    if (c->cfg.model == SIDM_MODEL_TWO_STATE && !p->state) {
+        set_err(c, "build_tree: two-state model needs a state array");
+        return SIDM_E_INVAL;
+    }
+    c->n = p->n;
+    c->has_mass = p->mass != nullptr;
+    c->m_scalar = p->m_scalar;
+    hipError_t e = launch_build_tree(c, p);
+    if (e != hipSuccess) return hip_fail(c, e, "build_tree");
+    c->tree_ok = 1;
+    return SIDM_OK;
+}
+
+static sidm_status check_active(sidm_ctx *c, const int32_t *active, int64_t n_active, const char *who)
+{
+    if (!c->tree_ok) {
+        set_err(c, "%s: sidm_build_tree has not been called", who);
+        return SIDM_E_STATE;
+    }
+    if (n_active < 0 || (n_active > 0 && !active)) {
+        set_err(c, "%s: bad active list", who);
+        return SIDM_E_INVAL;
+    }
+    if (n_active > c->n) {
+        set_err(c, "%s: n_active=%lld > n=%lld", who, (long long)n_active, (long long)c->n);
+        return SIDM_E_INVAL;
+    }
+    if (n_active > c->cap_active) {
+        set_err(c, "%s: n_active=%lld above capacity %lld", who, (long long)n_active,
+                (long long)c->cap_active);
+        return SIDM_E_CAPACITY;
+    }
+    return SIDM_OK;
+}
+
+sidm_status sidm_find_ngb(sidm_ctx *c, const int32_t *active, int64_t n_active, int32_t *ngb, double *h)
+{
+    if (!c) return SIDM_E_INVAL;
+    sidm_status st = check_active(c, active, n_active, "find_ngb");
+    if (st != SIDM_OK) return st;
+    if (n_active > 0 && (!ngb || !h)) {
+        set_err(c, "find_ngb: NULL output");
+        return SIDM_E_INVAL;
+    }
+    if (n_active == 0) return SIDM_OK;
+    hipError_t e = launch_map_active(c, active, n_active);
+    if (e == hipSuccess) e = launch_knn(c, n_active, ngb, h);
+    if (e != hipSuccess) return hip_fail(c, e, "find_ngb");
+    return SIDM_OK;
+}
+
+sidm_status sidm_scatter_step(sidm_ctx *c, sidm_particles *p, const int32_t *active, int64_t n_active,
+                              const int32_t *ngb, const double *h, const double *dt, uint64_t seed,
+                              uint32_t step, uint32_t *cand_info)
+{
+    if (!c) return SIDM_E_INVAL;
+    sidm_status st = check_active(c, active, n_active, "scatter_step");
+    if (st != SIDM_OK) return st;
+    if (!p || p->n != c->n || !p->vx || !p->vy || !p->vz) {
+        set_err(c, "scatter_step: particles do not match the tree snapshot");
+        return SIDM_E_INVAL;
+    }
+    if (c->cfg.model == SIDM_MODEL_TWO_STATE && !p->state) {
+        set_err(c, "scatter_step: two-state model needs a state array");
+        return SIDM_E_INVAL;
+    }
+    if (n_active > 0 && (!ngb || !h || !dt)) {
+        set_err(c, "scatter_step: NULL ngb/h/dt");
+        return SIDM_E_INVAL;
+    }
+    hipError_t e = launch_map_active(c, active, n_active);
+    if (e == hipSuccess) e = launch_scatter(c, p, n_active, ngb, h, dt, seed, step, cand_info);
+    if (e != hipSuccess) return hip_fail(c, e, "scatter_step");
+    return SIDM_OK;
+}
+
+sidm_status sidm_pair_timestep(sidm_ctx *c, const int32_t *active, int64_t n_active, const int32_t *ngb,
+                               const double *h, double *dt_sidm)
+{
+    if (!c) return SIDM_E_INVAL;
+    sidm_status st = check_active(c, active, n_active, "pair_timestep");
+    if (st != SIDM_OK) return st;
+    if (n_active > 0 && (!ngb || !h || !dt_sidm)) {
+        set_err(c, "pair_timestep: NULL ngb/h/dt_sidm");
+        return SIDM_E_INVAL;
+    }
+    if (n_active == 0) return SIDM_OK;
+    hipError_t e = launch_map_active(c, active, n_active);
+    if (e == hipSuccess) e = launch_timestep(c, n_active, ngb, h, dt_sidm);
+    if (e != hipSuccess) return hip_fail(c, e, "pair_timestep");
+    return SIDM_OK;
+}
+
+sidm_status sidm_sync(sidm_ctx *c, sidm_stats *out)
+{
+    if (!c) return SIDM_E_INVAL;
+    hipError_t e = hipMemcpyAsync(c->hstats, c->dstats, sizeof(DevStats), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->herr, c->derr, sizeof(unsigned int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "sync");
+    unsigned int bits = *c->herr;
+    sidm_status st = status_from_bits(bits);
+    if (out) {
+        const DevStats &d = *c->hstats;
+        out->n_cand = (int64_t)d.n_cand;
+        out->n_accept0 = (int64_t)d.n_accept0;
+        out->n_events = (int64_t)d.n_events;
+        out->n_flagged = (int64_t)d.n_flagged;
+        out->n_p_ge_1 = (int64_t)d.n_p_ge_1;
+        out->n_recheck = (int64_t)d.n_recheck;
+        out->n_passes = (int32_t)d.n_passes;
+        out->error = (int32_t)st;
+        unsigned long long mb = d.max_p_bits;
+        double mp;
+        memcpy(&mp, &mb, sizeof mp);
+        out->max_p = mp;
+    }
+    if (bits) {
+        set_err(c, "device error bits 0x%x (%s%s%s%s%s)", bits, (bits & DERR_INDEX) ? "index " : "",
+                (bits & DERR_DUPLICATE) ? "duplicate-active " : "",
+                (bits & DERR_OVERFLOW) ? "accepted-overflow " : "",
+                (bits & DERR_COUNT) ? "too-few-neighbours " : "",
+                (bits & DERR_STALL) ? "stalled-resolution " : "");
+        launch_fill_i32((int32_t *)c->derr, 0, 1, c->stream);
+        (void)hipStreamSynchronize(c->stream);
+    }
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,503 @@
+// Scattering step of the active particles (paper sec. 4.1, 4.5) and the
+// per-pair timestep bound (sec. 4.4, Eq. sidm_timestep).
+//
+//  k_eval      one thread per candidate (i|j): P(i|j) = 1/2 m_j sigma(w)/m w
+//              W(r_ij, h_i) dt_i (Eqs. rate, oneSided, probabilityScatter),
+//              the Philox decision draw, and wave-aggregated compaction of
+//              the accepted candidates into a list.
+//  passes      the accepted candidates are applied in increasing
+//              (priority, id_i, id_j) order.  A pass lets every candidate that
+//              holds the smallest key at both of its particles re-evaluate P
+//              with the current velocities and kick (these winners form a
+//              matching, so each particle scatters at most once per pass);
+//              the others wait for the next pass.  Claims are 64-bit
+//              integer atomicMin (priority, then the ID pair): no
+//              floating-point atomics, so results do not depend on timing.
+//  finisher    one workgroup runs the remaining passes with barriers when the
+//              list is short, so the step needs no host round trip.
+//  k_timestep  dt_i = 2 C_SIDM / (m_i W(0, h_i) max_j w_ij sigma(w_ij)/m).
+#include "sidm_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMultiPasses = 4;        // passes run as grid-wide kernels
+constexpr int kFinisherMax = 4096;     // shorter lists go to the one-workgroup finisher
+
+// control block: [0..1] list counts, [2] completed passes, [3] hand-off flag
+enum { CTL_COUNT0 = 0, CTL_COUNT1 = 1, CTL_PASS = 2, CTL_HANDOFF = 3 };
+
+struct StepArgs {
+    // Morton-ordered snapshot
+    const double *xs, *ys, *zs, *ms;
+    double *vxs, *vys, *vzs;
+    const uint32_t *ids;
+    uint8_t *sts;
+    const int32_t *perm, *inv;
+    // caller arrays (write-back)
+    double *vx, *vy, *vz;
+    uint8_t *state;
+    // step inputs
+    const int32_t *tlist, *slot, *nt_dev;
+    const int32_t *ngb;
+    const double *h, *dt;
+    uint32_t *cand_info;
+    // resolution
+    AccList L0, L1;
+    int32_t *ctl;
+    unsigned long long *c1a, *c1b, *c2a, *c2b;
+    DevStats *st;
+    unsigned int *derr;
+    int64_t n, cap_acc;
+    double m_scalar, box, s0, w0, eps, delta, band;
+    uint64_t seed;
+    uint32_t step;
+    int k, periodic, xsec, model, has_mass;
+};
+
+__device__ __forceinline__ double mass_of(const StepArgs &A, int32_t s)
+{
+    return A.has_mass ? A.ms[s] : A.m_scalar;
+}
+
+__device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
+
+// wave-aggregated counter increment; returns this lane's slot (valid lanes only)
+__device__ __forceinline__ int64_t wave_append(int32_t *counter, bool on)
+{
+    uint64_t m = __ballot(on);
+    if (!m) return -1;
+    int leader = __ffsll((long long)m) - 1;
+    int lane = wave_lane();
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader);
+    uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    return on ? (int64_t)base + __popcll(m & lt) : -1;
+}
+
+__device__ __forceinline__ void wave_count(unsigned long long *ctr, bool on)
+{
+    uint64_t m = __ballot(on);
+    if (m && wave_lane() == __ffsll((long long)m) - 1) atomicAdd(ctr, (unsigned long long)__popcll(m));
+}
+
+// ----------------------------------------------------------------------------
+// Scatter models: outgoing/incoming relative-speed ratio eps and state changes
+// (sec. 4.1: the centre-of-momentum kinetic energy changes by eps^2).
+// ----------------------------------------------------------------------------
+__device__ double scatter_eps(const StepArgs &A, double ma, double mb, double w, uint8_t sa,
+                              uint8_t sb, uint32_t ida, uint32_t idb, uint32_t bit,
+                              uint8_t &nsa, uint8_t &nsb)
+{
+    nsa = sa;
+    nsb = sb;
+    if (A.model == SIDM_MODEL_EPS) return A.eps;
+    if (A.model != SIDM_MODEL_TWO_STATE) return 1.0;
+    double M = ma + mb;
+    double mu = (ma * mb) / M;
+    bool a_lower = ida < idb;
+    if (sa == 0 && sb == 0) {
+        bool excite_a = (bit == 0) ? a_lower : !a_lower;
+        double mp = excite_a ? ma : mb;
+        double e2 = 1.0 - (2.0 * mp * A.delta) / ((mu * w) * w);
+        if (!(e2 > 0.0)) return 1.0;
+        if (excite_a) nsa = 1; else nsb = 1;
+        return sqrt(e2);
+    }
+    bool deexcite_a = (sa && sb) ? ((bit == 0) ? a_lower : !a_lower) : (sa != 0);
+    double mp = deexcite_a ? ma : mb;
+    double e2 = 1.0 + (2.0 * mp * A.delta) / ((mu * w) * w);
+    if (deexcite_a) nsa = 0; else nsb = 0;
+    return sqrt(e2);
+}
+
+// Kick of the pair (i, j) in Morton order, centre-of-momentum frame, direction
+// uniform on the sphere from the pair's direction draw.
+__device__ void kick(const StepArgs &A, int32_t i, int32_t j)
+{
+    const uint32_t idi = A.ids[i], idj = A.ids[j];
+    Philox4 x = pair_draw(A.seed, A.step, idi, idj,
+                          idi < idj ? PURPOSE_DIR_LO_HI : PURPOSE_DIR_HI_LO);
+    double u1 = unit_from_word((uint64_t)x.x1 << 32 | x.x0);
+    double u2 = unit_from_word((uint64_t)x.x3 << 32 | x.x2);
+    double cth = 2.0 * u1 - 1.0;
+    double phi = 2.0 * SIDM_PI * u2;
+    double s2 = 1.0 - cth * cth;
+    double sth = sqrt(s2 > 0.0 ? s2 : 0.0);
+    double ex = sth * cos(phi), ey = sth * sin(phi), ez = cth;
+
+    const double mi = mass_of(A, i), mj = mass_of(A, j);
+    const double vix = A.vxs[i], viy = A.vys[i], viz = A.vzs[i];
+    const double vjx = A.vxs[j], vjy = A.vys[j], vjz = A.vzs[j];
+    const double w = rel_speed(vix, viy, viz, vjx, vjy, vjz);
+    uint8_t nsi, nsj;
+    double eps = scatter_eps(A, mi, mj, w, A.sts[i], A.sts[j], idi, idj, x.x0 & 1u, nsi, nsj);
+    double M = mi + mj;
+    double vcx = (mi * vix + mj * vjx) / M;
+    double vcy = (mi * viy + mj * vjy) / M;
+    double vcz = (mi * viz + mj * vjz) / M;
+    double c = (eps * w) / M;
+    double ci = mj * c, cj = mi * c;
+    double nix = vcx + ci * ex, niy = vcy + ci * ey, niz = vcz + ci * ez;
+    double njx = vcx - cj * ex, njy = vcy - cj * ey, njz = vcz - cj * ez;
+    A.vxs[i] = nix; A.vys[i] = niy; A.vzs[i] = niz;
+    A.vxs[j] = njx; A.vys[j] = njy; A.vzs[j] = njz;
+    const int32_t oi = A.perm[i], oj = A.perm[j];
+    A.vx[oi] = nix; A.vy[oi] = niy; A.vz[oi] = niz;
+    A.vx[oj] = njx; A.vy[oj] = njy; A.vz[oj] = njz;
+    if (A.model == SIDM_MODEL_TWO_STATE) {
+        A.sts[i] = nsi;
+        A.sts[j] = nsj;
+        if (A.state) { A.state[oi] = nsi; A.state[oj] = nsj; }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Evaluation 0: every candidate with the step-start velocities
+// ----------------------------------------------------------------------------
+template <bool PERIODIC>
+__global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
+{
+    const int64_t nt = *A.nt_dev;
+    const int64_t total = nt * A.k;
+    unsigned long long maxp = 0;
+    for (int64_t c0 = blockIdx.x * (int64_t)blockDim.x; c0 < total;
+         c0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = c0 + threadIdx.x;
+        const bool in = c < total;
+        bool acc = false, flagged = false, pge1 = false;
+        int32_t i = 0, j = 0, a = 0;
+        int s = 0;
+        double u = 0, W = 0, dta = 0;
+        uint32_t idi = 0, idj = 0;
+        if (in) {
+            const int64_t b = c / A.k;
+            s = (int)(c - b * A.k);
+            i = A.tlist[b];
+            a = A.slot[b];
+            const int32_t jc = A.ngb[(int64_t)a * A.k + s];
+            if (jc < 0 || jc >= A.n) {
+                atomicOr(A.derr, DERR_INDEX);
+            } else {
+                j = A.inv[jc];
+                const double r = sqrt(sep2<PERIODIC>(A.xs[i], A.ys[i], A.zs[i], A.xs[j], A.ys[j],
+                                                     A.zs[j], A.box));
+                W = cubic_spline(r, A.h[a]);
+                const double w = rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
+                const double sig = xsec_sigma(w, A.xsec, A.s0, A.w0);
+                dta = A.dt[a];
+                const double P = pair_prob(mass_of(A, j), sig, w, W, dta);
+                idi = A.ids[i];
+                idj = A.ids[j];
+                Philox4 x = pair_draw(A.seed, A.step, idi, idj, PURPOSE_DECIDE);
+                u = unit_from_word(direction_word(x, idi < idj));
+                acc = u < P;
+                flagged = fabs(P - u) < A.band;
+                pge1 = P >= 1.0;
+                unsigned long long pb = (unsigned long long)__double_as_longlong(P);
+                maxp = pb > maxp ? pb : maxp;
+                if (A.cand_info)
+                    A.cand_info[(int64_t)a * A.k + s] =
+                        (acc ? SIDM_CAND_ACCEPT0 : 0u) | (flagged ? SIDM_CAND_FLAGGED : 0u);
+            }
+        }
+        wave_count(&A.st->n_flagged, flagged);
+        wave_count(&A.st->n_p_ge_1, pge1);
+        wave_count(&A.st->n_accept0, acc);
+        int64_t pos = wave_append(&A.ctl[CTL_COUNT0], acc);
+        if (acc) {
+            if (pos >= A.cap_acc) {
+                atomicOr(A.derr, DERR_OVERFLOW);
+            } else {
+                Philox4 x = pair_draw(A.seed, A.step, idi, idj, PURPOSE_PRIORITY);
+                A.L0.i[pos] = i;
+                A.L0.j[pos] = j;
+                A.L0.cand[pos] = a * A.k + s;
+                A.L0.u[pos] = u;
+                A.L0.W[pos] = W;
+                A.L0.dt[pos] = dta;
+                A.L0.prio[pos] = direction_word(x, idi < idj);
+                A.L0.idpair[pos] = ((uint64_t)idi << 32) | idj;
+                A.c1a[i] = ~0ull; A.c1a[j] = ~0ull;
+                A.c2a[i] = ~0ull; A.c2a[j] = ~0ull;
+            }
+        }
+    }
+    // wave max of P, one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = (unsigned long long)__shfl_xor((long long)maxp, off);
+        maxp = o > maxp ? o : maxp;
+    }
+    if (wave_lane() == 0 && maxp) atomicMax(&A.st->max_p_bits, maxp);
+}
+
+// ----------------------------------------------------------------------------
+// Resolution passes: per-entry bodies shared by the grid kernels and the
+// one-workgroup finisher.  Pass t reads list t&1 and claim buffers t&1.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ const AccList &list_of(const StepArgs &A, int t) { return (t & 1) ? A.L1 : A.L0; }
+__device__ __forceinline__ unsigned long long *claim1_of(const StepArgs &A, int t) { return (t & 1) ? A.c1b : A.c1a; }
+__device__ __forceinline__ unsigned long long *claim2_of(const StepArgs &A, int t) { return (t & 1) ? A.c2b : A.c2a; }
+
+__device__ __forceinline__ unsigned long long load_claim(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int64_t list_count(const StepArgs &A, int t)
+{
+    int64_t c = A.ctl[(t & 1) ? CTL_COUNT1 : CTL_COUNT0];
+    return c < A.cap_acc ? c : A.cap_acc;
+}
+
+__device__ __forceinline__ void claim1_entry(const StepArgs &A, int t, int64_t e)
+{
+    const AccList &L = list_of(A, t);
+    unsigned long long *c1 = claim1_of(A, t);
+    unsigned long long pr = L.prio[e];
+    atomicMin(&c1[L.i[e]], pr);
+    atomicMin(&c1[L.j[e]], pr);
+}
+
+__device__ __forceinline__ void claim2_entry(const StepArgs &A, int t, int64_t e)
+{
+    const AccList &L = list_of(A, t);
+    const unsigned long long *c1 = claim1_of(A, t);
+    unsigned long long *c2 = claim2_of(A, t);
+    const unsigned long long pr = L.prio[e], ip = L.idpair[e];
+    const int32_t i = L.i[e], j = L.j[e];
+    if (load_claim(&c1[i]) == pr) atomicMin(&c2[i], ip);
+    if (load_claim(&c1[j]) == pr) atomicMin(&c2[j], ip);
+}
+
+// returns true if the entry was decided (winner) this pass
+template <bool PERIODIC>
+__device__ bool resolve_entry(const StepArgs &A, int t, int64_t e, int32_t *next_count)
+{
+    const AccList &L = list_of(A, t);
+    const unsigned long long *c1 = claim1_of(A, t), *c2 = claim2_of(A, t);
+    const int32_t i = L.i[e], j = L.j[e];
+    const unsigned long long pr = L.prio[e], ip = L.idpair[e];
+    const bool win = load_claim(&c1[i]) == pr && load_claim(&c1[j]) == pr &&
+                     load_claim(&c2[i]) == ip && load_claim(&c2[j]) == ip;
+    if (win) {
+        const double w = rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
+        const double sig = xsec_sigma(w, A.xsec, A.s0, A.w0);
+        const double P = pair_prob(mass_of(A, j), sig, w, L.W[e], L.dt[e]);
+        const double u = L.u[e];
+        const bool flagged = fabs(P - u) < A.band;
+        const bool hit = u < P;
+        if (flagged) atomicAdd(&A.st->n_flagged, 1ull);
+        if (hit) {
+            kick(A, i, j);
+            atomicAdd(&A.st->n_events, 1ull);
+        }
+        if (A.cand_info) {
+            const int32_t cand = L.cand[e];
+            A.cand_info[cand] |= ((uint32_t)(t + 1) << 8) | (hit ? SIDM_CAND_SCATTER : 0u) |
+                                 (flagged ? SIDM_CAND_FLAGGED : 0u);
+        }
+        return true;
+    }
+    // carry over to the next pass, and clear the claims it will use
+    const AccList &N = list_of(A, t + 1);
+    const int32_t pos = atomicAdd(next_count, 1);
+    N.i[pos] = i; N.j[pos] = j;
+    N.cand[pos] = L.cand[e];
+    N.u[pos] = L.u[e]; N.W[pos] = L.W[e]; N.dt[pos] = L.dt[e];
+    N.prio[pos] = pr; N.idpair[pos] = ip;
+    unsigned long long *n1 = claim1_of(A, t + 1), *n2 = claim2_of(A, t + 1);
+    n1[i] = ~0ull; n1[j] = ~0ull;
+    n2[i] = ~0ull; n2[j] = ~0ull;
+    return false;
+}
+
+// a grid pass runs only while no hand-off happened and the list is long
+__device__ __forceinline__ bool grid_pass_active(const StepArgs &A, int t)
+{
+    if (A.ctl[CTL_HANDOFF]) return false;
+    return list_count(A, t) > kFinisherMax;
+}
+
+__global__ __launch_bounds__(kBlock) void k_claim1(StepArgs A, int t)
+{
+    if (!grid_pass_active(A, t)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) A.ctl[CTL_HANDOFF] = 1;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) A.ctl[((t + 1) & 1) ? CTL_COUNT1 : CTL_COUNT0] = 0;
+    const int64_t cnt = list_count(A, t);
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+         e += (int64_t)gridDim.x * blockDim.x)
+        claim1_entry(A, t, e);
+}
+
+__global__ __launch_bounds__(kBlock) void k_claim2(StepArgs A, int t)
+{
+    if (A.ctl[CTL_HANDOFF]) return;
+    const int64_t cnt = list_count(A, t);
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+         e += (int64_t)gridDim.x * blockDim.x)
+        claim2_entry(A, t, e);
+}
+
+template <bool PERIODIC>
+__global__ __launch_bounds__(kBlock) void k_resolve(StepArgs A, int t)
+{
+    if (A.ctl[CTL_HANDOFF]) return;
+    const int64_t cnt = list_count(A, t);
+    int32_t *next = &A.ctl[((t + 1) & 1) ? CTL_COUNT1 : CTL_COUNT0];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+         e += (int64_t)gridDim.x * blockDim.x)
+        resolve_entry<PERIODIC>(A, t, e, next);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.ctl[CTL_PASS] = t + 1;
+        atomicMax(&A.st->n_passes, (unsigned)(t + 1));
+    }
+}
+
+// One workgroup finishes whatever passes remain.
+template <bool PERIODIC>
+__global__ __launch_bounds__(1024) void k_finish(StepArgs A)
+{
+    __shared__ int64_t s_cnt;
+    __shared__ int s_t;
+    if (threadIdx.x == 0) {
+        s_t = A.ctl[CTL_PASS];
+        s_cnt = list_count(A, s_t);
+    }
+    __syncthreads();
+    while (s_cnt > 0) {
+        const int t = s_t;
+        const int64_t cnt = s_cnt;
+        int32_t *next = &A.ctl[((t + 1) & 1) ? CTL_COUNT1 : CTL_COUNT0];
+        if (threadIdx.x == 0) *next = 0;
+        for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) claim1_entry(A, t, e);
+        __threadfence_block();
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) claim2_entry(A, t, e);
+        __threadfence_block();
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) resolve_entry<PERIODIC>(A, t, e, next);
+        __threadfence_block();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_t = t + 1;
+            int64_t nc = *next;
+            atomicMax(&A.st->n_passes, (unsigned)(t + 1));
+            if (nc >= cnt) {            // no winner: the global minimum always wins
+                atomicOr(A.derr, DERR_STALL);
+                nc = 0;
+            }
+            s_cnt = nc;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_step_reset(DevStats *st, int32_t *ctl)
+{
+    if (threadIdx.x == 0) {
+        DevStats z = {};
+        *st = z;
+        ctl[0] = ctl[1] = ctl[2] = ctl[3] = 0;
+    }
+}
+
+__global__ void k_count_cand(DevStats *st, const int32_t *nt_dev, int k)
+{
+    if (threadIdx.x == 0) st->n_cand = (unsigned long long)(*nt_dev) * (unsigned long long)k;
+}
+
+// ----------------------------------------------------------------------------
+// Per-pair timestep (Eq. sidm_timestep) with the current velocities
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_timestep(StepArgs A, double c_sidm, double *dt_out)
+{
+    const int64_t nt = *A.nt_dev;
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nt;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = A.tlist[b], a = A.slot[b];
+        const double vix = A.vxs[i], viy = A.vys[i], viz = A.vzs[i];
+        double rmax = 0.0;
+        for (int s = 0; s < A.k; ++s) {
+            const int32_t jc = A.ngb[(int64_t)a * A.k + s];
+            if (jc < 0 || jc >= A.n) { atomicOr(A.derr, DERR_INDEX); continue; }
+            const int32_t j = A.inv[jc];
+            const double w = rel_speed(vix, viy, viz, A.vxs[j], A.vys[j], A.vzs[j]);
+            const double ws = w * xsec_sigma(w, A.xsec, A.s0, A.w0);
+            rmax = ws > rmax ? ws : rmax;
+        }
+        const double W0 = cubic_spline(0.0, A.h[a]);
+        dt_out[a] = rmax > 0.0 ? (2.0 * c_sidm) / ((mass_of(A, i) * W0) * rmax) : INFINITY;
+    }
+}
+
+StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const double *h,
+                   const double *dt, uint64_t seed, uint32_t step, uint32_t *cand_info)
+{
+    StepArgs A;
+    A.xs = c->xs; A.ys = c->ys; A.zs = c->zs; A.ms = c->ms;
+    A.vxs = c->vxs; A.vys = c->vys; A.vzs = c->vzs;
+    A.ids = c->ids; A.sts = c->sts; A.perm = c->perm; A.inv = c->inv;
+    A.vx = p ? p->vx : nullptr; A.vy = p ? p->vy : nullptr; A.vz = p ? p->vz : nullptr;
+    A.state = p ? p->state : nullptr;
+    A.tlist = c->tlist; A.slot = c->slot; A.nt_dev = c->nt_dev;
+    A.ngb = ngb; A.h = h; A.dt = dt; A.cand_info = cand_info;
+    A.L0 = c->acc[0]; A.L1 = c->acc[1];
+    A.ctl = c->acc_count;
+    A.c1a = c->claim1[0]; A.c1b = c->claim1[1]; A.c2a = c->claim2[0]; A.c2b = c->claim2[1];
+    A.st = c->dstats; A.derr = c->derr;
+    A.n = c->n; A.cap_acc = c->cap_acc;
+    A.m_scalar = c->m_scalar;
+    A.box = c->cfg.box; A.s0 = c->cfg.sigma0; A.w0 = c->cfg.w0;
+    A.eps = c->cfg.eps; A.delta = c->cfg.delta; A.band = c->cfg.flag_band;
+    A.seed = seed; A.step = step;
+    A.k = c->cfg.n_ngb; A.periodic = c->cfg.periodic; A.xsec = c->cfg.xsec;
+    A.model = c->cfg.model; A.has_mass = c->has_mass;
+    return A;
+}
+
+int grid_for(int64_t n, int cap = 8192)
+{
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    return (int)(g > cap ? cap : g);
+}
+
+template <bool P>
+void run_scatter(const StepArgs &A, int64_t n_active, hipStream_t s)
+{
+    const int64_t total = n_active * A.k;
+    k_step_reset<<<1, 64, 0, s>>>(A.st, A.ctl);
+    k_count_cand<<<1, 64, 0, s>>>(A.st, A.nt_dev, A.k);
+    k_eval<P><<<grid_for(total), kBlock, 0, s>>>(A);
+    const int g = grid_for(A.cap_acc < total ? A.cap_acc : total, 2048);
+    for (int t = 0; t < kMultiPasses; ++t) {
+        k_claim1<<<g, kBlock, 0, s>>>(A, t);
+        k_claim2<<<g, kBlock, 0, s>>>(A, t);
+        k_resolve<P><<<g, kBlock, 0, s>>>(A, t);
+    }
+    k_finish<P><<<1, 1024, 0, s>>>(A);
+}
+
+}  // namespace
+
+hipError_t launch_scatter(sidm_ctx *c, sidm_particles *p, int64_t n_active, const int32_t *ngb,
+                          const double *h, const double *dt, uint64_t seed, uint32_t step,
+                          uint32_t *cand_info)
+{
+    StepArgs A = make_args(c, p, ngb, h, dt, seed, step, cand_info);
+    if (c->cfg.periodic) run_scatter<true>(A, n_active, c->stream);
+    else run_scatter<false>(A, n_active, c->stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, const double *h,
+                           double *dt_out)
+{
+    StepArgs A = make_args(c, nullptr, ngb, h, nullptr, 0, 0, nullptr);
+    k_timestep<<<grid_for(n_active), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm, dt_out);
+    return hipGetLastError();
+}

@@ -1,0 +1,219 @@
+// Internal declarations of the gfx950 SIDM library: context layout, device
+// helpers shared by the kernels, and the host-side launchers each .hip file
+// provides.  Not part of the public ABI (include/sidm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sidm.h"
+
+#define SIDM_PI 3.14159265358979323846
+#define SIDM_LEAF 32            // particles per tree leaf (consecutive in Morton order)
+#define SIDM_SORT_TILE 2048     // keys per radix-sort workgroup (256 threads x 8)
+#define SIDM_SCAN_TILE 1024     // elements per compaction workgroup
+
+// device-side error bits (latched, reported by sidm_sync)
+#define DERR_INDEX 1u           // an index outside [0, n)
+#define DERR_DUPLICATE 2u       // an active particle listed twice
+#define DERR_OVERFLOW 4u        // accepted-candidate list overflow
+#define DERR_COUNT 8u           // fewer than n_ngb + 1 candidates found
+#define DERR_STALL 16u          // a resolution pass decided nothing (cannot happen)
+
+struct DevStats {
+    unsigned long long n_cand, n_accept0, n_events, n_flagged, n_p_ge_1, n_recheck;
+    unsigned long long max_p_bits;      // positive doubles order like their bit patterns
+    unsigned int n_passes, pad;
+};
+
+// One accepted candidate (i|j), kept in structure-of-arrays form.
+struct AccList {
+    int32_t *i, *j;          // sorted-order particle indices (target, partner)
+    int32_t *cand;           // a * n_ngb + s  (caller's active slot and neighbour slot)
+    double *u;               // decision draw
+    double *W;               // kernel weight W(r_ij, h_i) (positions do not change)
+    double *dt;              // timestep of the target
+    uint64_t *prio;          // priority word
+    uint64_t *idpair;        // (id_i << 32) | id_j
+};
+
+struct sidm_ctx {
+    sidm_config cfg;
+    int64_t cap_n, cap_active, cap_acc;
+    int device;
+    hipStream_t stream;
+    char err[512];
+
+    // snapshot of the particles in Morton order
+    int64_t n;
+    int tree_ok;
+    int has_mass;
+    double m_scalar;         // particle mass when no per-particle array is given
+    double *xs, *ys, *zs, *vxs, *vys, *vzs, *ms;
+    uint32_t *ids;
+    uint8_t *sts;
+    int32_t *perm;           // sorted -> caller index
+    int32_t *inv;            // caller -> sorted index
+
+    // radix sort scratch
+    uint64_t *key0, *key1;
+    int32_t *val0, *val1;
+    uint32_t *hist;          // [256][n_sort_blocks]
+    uint32_t *dtot;          // [256]
+    unsigned long long *bounds;   // ordered-u64 encodings of min x,y,z / max x,y,z
+
+    // bucket tree: implicit binary tree over 2^p2log leaves, node 1 = root
+    int64_t nleaf, p2;
+    double *nodes;           // [2*p2][6]  lo x,y,z, hi x,y,z
+    int32_t *visit;          // [p2] bottom-up arrival counters
+
+    // active set in Morton order
+    int32_t *flag;           // [cap_n] caller slot of an active particle, or -1
+    int32_t *tlist;          // [cap_active] sorted index of the b-th active particle
+    int32_t *slot;           // [cap_active] its position in the caller's active list
+    int32_t *blk;            // compaction block counts / offsets
+    int32_t *nt_dev;         // number of compacted targets
+
+    // conflict resolution
+    AccList acc[2];
+    int32_t *acc_count;      // [4]: counts of list 0 / 1, pass counter
+    unsigned long long *claim1[2], *claim2[2];   // [cap_n] per-particle claims
+
+    DevStats *dstats;
+    unsigned int *derr;
+    void *dev_base;          // the one device allocation every buffer above lives in
+    DevStats *hstats;        // pinned host copy
+    unsigned int *herr;
+};
+
+// ---------------------------------------------------------------------------
+// Device helpers (shared by the kernels of this library)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long ordered_u64(double v)
+{
+    unsigned long long b = __double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double from_ordered_u64(unsigned long long b)
+{
+    return __longlong_as_double((b >> 63) ? (b & 0x7fffffffffffffffull) : ~b);
+}
+
+// Minimum-image separation of one axis: d = x_j - x_i, wrapped once.
+template <bool PERIODIC>
+__device__ __forceinline__ double axis_sep(double xi, double xj, double box)
+{
+    double d = xj - xi;
+    if (PERIODIC) {
+        if (d >= 0.5 * box) d = d - box;
+        else if (d < -0.5 * box) d = d + box;
+    }
+    return d;
+}
+
+template <bool PERIODIC>
+__device__ __forceinline__ double sep2(double xi, double yi, double zi, double xj, double yj,
+                                       double zj, double box)
+{
+    double dx = axis_sep<PERIODIC>(xi, xj, box);
+    double dy = axis_sep<PERIODIC>(yi, yj, box);
+    double dz = axis_sep<PERIODIC>(zi, zj, box);
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+// Cubic spline kernel W_CS(r, h) with support radius h.
+__device__ __forceinline__ double cubic_spline(double r, double h)
+{
+    double h3 = (h * h) * h;
+    double norm = 8.0 / (SIDM_PI * h3);
+    double q = r / h;
+    if (q <= 0.5) {
+        double q2 = q * q;
+        double q3 = q2 * q;
+        return norm * ((1.0 - 6.0 * q2) + 6.0 * q3);
+    }
+    if (q <= 1.0) {
+        double t = 1.0 - q;
+        return norm * (2.0 * ((t * t) * t));
+    }
+    return 0.0;
+}
+
+__device__ __forceinline__ double xsec_sigma(double w, int xsec, double s0, double w0)
+{
+    if (xsec == SIDM_XSEC_YUKAWA) {
+        double x = w / w0;
+        double d = 1.0 + x * x;
+        return s0 / (d * d);
+    }
+    return s0;
+}
+
+__device__ __forceinline__ double rel_speed(double ax, double ay, double az, double bx,
+                                            double by, double bz)
+{
+    double dx = ax - bx, dy = ay - by, dz = az - bz;
+    return sqrt((dx * dx + dy * dy) + dz * dz);
+}
+
+__device__ __forceinline__ double pair_prob(double m_j, double sig, double w, double W, double dt)
+{
+    return (((0.5 * m_j) * sig) * w * W) * dt;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
+struct Philox4 { uint32_t x0, x1, x2, x3; };
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    return Philox4{c0, c1, c2, c3};
+}
+
+#define PURPOSE_DECIDE 0u
+#define PURPOSE_DIR_LO_HI 1u
+#define PURPOSE_PRIORITY 2u
+#define PURPOSE_DIR_HI_LO 3u
+
+__device__ __forceinline__ Philox4 pair_draw(uint64_t seed, uint32_t step, uint32_t ida,
+                                             uint32_t idb, uint32_t purpose)
+{
+    uint32_t lo = ida < idb ? ida : idb, hi = ida < idb ? idb : ida;
+    return philox4x32_10(lo, hi, step, purpose, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+__device__ __forceinline__ uint64_t direction_word(const Philox4 &x, bool target_is_lower)
+{
+    return target_is_lower ? ((uint64_t)x.x1 << 32 | x.x0) : ((uint64_t)x.x3 << 32 | x.x2);
+}
+
+__device__ __forceinline__ double unit_from_word(uint64_t w)
+{
+    return (double)(w >> 11) * 0x1.0p-53;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (host side), one group per .hip file
+// ---------------------------------------------------------------------------
+// tree.hip
+hipError_t launch_build_tree(sidm_ctx *c, const sidm_particles *p);
+hipError_t launch_map_active(sidm_ctx *c, const int32_t *active, int64_t n_active);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+// knn.hip
+hipError_t launch_knn(sidm_ctx *c, int64_t n_active, int32_t *ngb, double *h);
+// scatter.hip
+hipError_t launch_scatter(sidm_ctx *c, sidm_particles *p, int64_t n_active, const int32_t *ngb,
+                          const double *h, const double *dt, uint64_t seed, uint32_t step,
+                          uint32_t *cand_info);
+hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, const double *h,
+                           double *dt_out);

@@ -1,0 +1,83 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/sidm.h declares, and its host-only calls behave."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2607_05504_amd as sidm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sidm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sidm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_lists_the_four_step_calls():
+    fns = declared_functions()
+    for name in ("sidm_build_tree", "sidm_find_ngb", "sidm_scatter_step", "sidm_pair_timestep"):
+        assert name in fns
+    assert sorted(sidm.EXPORTS) == fns
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", sidm.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    for name in declared_functions():
+        assert name in exported, name
+    L = sidm.lib()
+    for name in declared_functions():
+        assert hasattr(L, name)
+
+
+def test_status_strings():
+    L = sidm.lib()
+    assert L.sidm_status_string(0) == b"ok"
+    assert L.sidm_status_string(sidm.SIDM_E_OVERFLOW).startswith(b"accepted")
+
+
+def test_footprint_host_only():
+    cfg = sidm.make_config(n_ngb=32, periodic=True, box=1.0, sigma0=1.0)
+    small = sidm.footprint(cfg, 32768, 32768)
+    big = sidm.footprint(cfg, 1 << 24, 1 << 24)
+    assert 0 < small < big
+    # grows roughly linearly in N (per-particle state, sort and claim buffers)
+    assert 200 * (1 << 24) < big < 2000 * (1 << 24)
+
+
+def test_footprint_rejects_bad_config():
+    L = sidm.lib()
+    out = ctypes.c_size_t()
+    bad = sidm.make_config(n_ngb=0)
+    assert L.sidm_footprint(ctypes.byref(bad), 100, 10, ctypes.byref(out)) == sidm.SIDM_E_INVAL
+    bad = sidm.make_config(n_ngb=32, periodic=True, box=0.0)
+    assert L.sidm_footprint(ctypes.byref(bad), 100, 10, ctypes.byref(out)) == sidm.SIDM_E_INVAL
+    ok = sidm.make_config(n_ngb=32)
+    assert L.sidm_footprint(ctypes.byref(ok), 33, 10, ctypes.byref(out)) == sidm.SIDM_E_INVAL
+    assert L.sidm_footprint(ctypes.byref(ok), 100, 101, ctypes.byref(out)) == sidm.SIDM_E_INVAL
+    assert L.sidm_footprint(ctypes.byref(ok), 100, 50, None) == sidm.SIDM_E_INVAL
+
+
+def test_null_context_calls_are_rejected():
+    L = sidm.lib()
+    assert L.sidm_build_tree(None, None) == sidm.SIDM_E_INVAL
+    assert L.sidm_find_ngb(None, None, 0, None, None) == sidm.SIDM_E_INVAL
+    assert L.sidm_scatter_step(None, None, None, 0, None, None, None, 0, 0, None) == sidm.SIDM_E_INVAL
+    assert L.sidm_pair_timestep(None, None, 0, None, None, None) == sidm.SIDM_E_INVAL
+    assert L.sidm_sync(None, None) == sidm.SIDM_E_INVAL
+    assert L.sidm_destroy(None) == sidm.SIDM_E_INVAL
+    assert L.sidm_last_error(None) == b"null context"
+
+
+def test_library_does_not_reference_the_oracle():
+    # the GPU library shares nothing with the CPU oracle
+    out = subprocess.run(["nm", "-D", sidm.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    assert "oref_" not in out
