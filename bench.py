@@ -1,0 +1,179 @@
+"""Benchmark of the SIDM scattering step on one MI355X.
+
+A step is the whole hot path through the C ABI: sidm_build_tree ->
+sidm_find_ngb -> sidm_scatter_step -> sidm_pair_timestep, on inputs already
+resident in HBM.  The default workload is the isolated Hernquist halo
+(G = M = a = 1, N = 10^6, Eddington-sampled, radii < 100 a), velocity-dependent
+sigma/m = s0 / (1 + (w/0.5)^2)^2, power-of-two timestep bins with about 1/8 of
+the particles active, FP64.
+
+Prints ONE JSON line.  value = active particles per second of whole steps
+(K steps timed between two device synchronisations).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "active particles/s per SIDM step (ngb+scatter); p50/p99 step latency at fixed rate"
+HBM_PEAK_GBS = 8000.0
+
+
+def make_workload(name: str):
+    import workloads as W
+    if name == "hernquist1e6":
+        w = W.hernquist_bins(W.hernquist_halo(1_000_000))
+        desc = ("isolated Hernquist halo G=M=a=1, N=1e6 (Eddington DF, r<100a), "
+                "sigma/m=s0/(1+(w/0.5)^2)^2, power-of-two bins ~1/8 active, elastic, FP64")
+    elif name == "uniform32k":
+        w = W.uniform_box(32768)
+        desc = "uniform periodic box 32^3, Maxwellian sigma_1D=1, const sigma/m, all active, FP64"
+    elif name == "hernquist4e6_2state":
+        w = W.hernquist_bins(W.hernquist_halo(4_000_000, ic_seed=104, philox_seed=4,
+                                              two_state=True))
+        desc = "two-state Hernquist halo N=4e6, ~1/8 active, delta=0.05 sigma_1D(a)^2, FP64"
+    elif name == "hernquist4e6_2state_all":
+        w = W.hernquist_halo(4_000_000, ic_seed=104, philox_seed=4, two_state=True)
+        w.dt = np.full(w.n, 1e-3)
+        desc = "two-state Hernquist halo N=4e6, all active, dt=1e-3, FP64"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return w, desc
+
+
+def touched_count(ngb: np.ndarray, active: np.ndarray) -> int:
+    return int(np.unique(np.concatenate([ngb.ravel(), active])).size)
+
+
+def cpu_baseline(w, seconds_hint: float = 15.0) -> dict:
+    """The CPU oracle, as it stands, on a bounded sample of the same workload
+    (a prefix of the active list, same particles), single thread."""
+    import oracle
+    oracle.build(force=False)
+    # calibrate on a small prefix, then size the sample for ~seconds_hint
+    n0 = min(w.n_active, 2000)
+    t0 = time.perf_counter()
+    oracle.full_step(w.subset_active(n0), workers=1)
+    t_small = time.perf_counter() - t0
+    per = t_small / n0
+    n_s = int(min(w.n_active, max(n0, seconds_hint / max(per, 1e-9))))
+    ws = w.subset_active(n_s)
+    t0 = time.perf_counter()
+    oracle.full_step(ws, workers=1)
+    dt = time.perf_counter() - t0
+    return {"value": n_s / dt, "unit": "active particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_s} of {w.n_active} active particles of the same workload "
+                      f"(all {w.n} particles as neighbours), one full step "
+                      f"(neighbours + scatter + timestep), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="hernquist1e6")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
+                    help="per-kernel HBM traffic measured with rocprofv3 counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2607_05504_amd import Context, runner
+
+    torch.cuda.set_device(0)
+    w, desc = make_workload(args.workload)
+    ds = runner.upload(w, "cuda:0")
+    cfg = runner.config_for(w)
+    ctx = Context(cfg, w.n, w.n_active)
+    out = runner.alloc_out(ds, w.n_ngb)
+    print(f"[bench] workload {args.workload}: n={w.n} active={w.n_active}", file=sys.stderr,
+          flush=True)
+
+    for t in range(args.warmup):
+        runner.run_step(ctx, ds, out, w.seed, w.step + t)
+    ctx.sync()
+    torch.cuda.synchronize()
+
+    # timed region: K whole steps, per-step device time from events, per-kernel
+    # device time from the library's events on its stream
+    ctx.timing_enable(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.steps):
+        ev[t][0].record()
+        runner.run_step(ctx, ds, out, w.seed, w.step + args.warmup + t)
+        ev[t][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tim = ctx.timing_read()
+    stats = ctx.sync()
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+
+    na, k = w.n_active, w.n_ngb
+    ms_per_step = wall * 1e3 / args.steps
+    value = na / (wall / args.steps)
+    ngb_np = out.ngb.cpu().numpy()
+    n_t = touched_count(ngb_np, w.active)
+
+    # algorithmic bytes per launch (FP64 form)
+    knn_bytes = (4 + 4 * k + 8) * na + 24 * n_t
+    eval_bytes = (4 * k + 20) * na + 52 * n_t
+    ts_bytes = (4 * k + 20) * na + 24 * n_t
+    kern = {"knn": (tim["knn_ms"], knn_bytes), "eval": (tim["eval_ms"], eval_bytes),
+            "timestep": (tim["timestep_ms"], ts_bytes)}
+    dom = max(kern, key=lambda n: kern[n][0])
+    dom_ms, dom_bytes = kern[dom]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(args.traffic):
+        try:
+            tr = json.load(open(args.traffic))
+            ent = tr.get(args.workload, {}).get(dom)
+            if ent:
+                traffic = ent.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": dom_ms}
+
+    ngb_scatter_ms = tim["knn_ms"] + tim["eval_ms"] + tim["resolve_ms"] + 3 * tim["map_ms"]
+    res = {
+        "metric": METRIC, "value": value, "unit": "active particles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "n": w.n, "n_active": na,
+                   "n_ngb": k, "precision": "fp64", "touched": n_t},
+        "p50_step_ms": float(np.percentile(step_ms, 50)),
+        "p99_step_ms": float(np.percentile(step_ms, 99)),
+        "phase_ms": {kk: round(v, 5) for kk, v in tim.items() if kk.endswith("_ms")},
+        "ngb_scatter_device_ms": ngb_scatter_ms,
+        "ngb_scatter_rate": na / (ngb_scatter_ms * 1e-3) if ngb_scatter_ms > 0 else None,
+        "events_last_step": stats["n_events"], "passes_last_step": stats["n_passes"],
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

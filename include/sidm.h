@@ -176,6 +176,26 @@ sidm_status sidm_pair_timestep(sidm_ctx *ctx, const int32_t *active, int64_t n_a
  * error (SIDM_OK if none).  Clears the latched error. */
 sidm_status sidm_sync(sidm_ctx *ctx, sidm_stats *out);
 
+/* ---- Measurement (not part of the method) --------------------------------
+ * When enabled, the context brackets its main kernels with HIP events on its
+ * stream (up to 256 launches of each between two reads).  sidm_timing_read
+ * waits for the stream, reports the mean device time in milliseconds of the
+ * launches since the previous read (or enable) and starts a new window.
+ * Disabled by default. */
+typedef struct {
+    int32_t samples;      /* neighbour-search launches averaged                    */
+    int32_t pad;
+    double tree_ms;       /* sidm_build_tree: every kernel of the build            */
+    double map_ms;        /* active-list mapping of the most recent call           */
+    double knn_ms;        /* the neighbour-search kernel                           */
+    double eval_ms;       /* the candidate-evaluation kernel                       */
+    double resolve_ms;    /* all resolution passes (grid passes and finisher)      */
+    double timestep_ms;   /* the per-pair timestep kernel                          */
+} sidm_timing;
+
+sidm_status sidm_timing_enable(sidm_ctx *ctx, int on);
+sidm_status sidm_timing_read(sidm_ctx *ctx, sidm_timing *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -113,7 +113,7 @@ def r2(pi, pj, periodic: bool, box: float) -> float:
 
 
 # ---------------------------------------------------------------------------
-def candidate_superset(x, y, z, periodic, box, targets, k):
+def candidate_superset(x, y, z, periodic, box, targets, k, workers=-1):
     """CSR superset of every target's partners with r <= r_(k+1), from scipy's
     k-d tree: the (k+2)-th closest point including the target itself bounds
     r_(k+1); the ball query radius is padded far beyond rounding differences."""
@@ -125,9 +125,9 @@ def candidate_superset(x, y, z, periodic, box, targets, k):
     else:
         kd = cKDTree(pts)
     q = pts[targets]
-    d, _ = kd.query(q, k=k + 2, workers=-1)
+    d, _ = kd.query(q, k=k + 2, workers=workers)
     rad = d[:, k + 1] * (1.0 + 1e-9) + 1e-300
-    lists = kd.query_ball_point(q, rad, workers=-1, return_sorted=False)
+    lists = kd.query_ball_point(q, rad, workers=workers, return_sorted=False)
     counts = np.fromiter((len(l) for l in lists), dtype=np.int64, count=len(lists))
     ptr = np.zeros(len(lists) + 1, dtype=np.int64)
     np.cumsum(counts, out=ptr[1:])
@@ -135,7 +135,7 @@ def candidate_superset(x, y, z, periodic, box, targets, k):
     return ptr, idx
 
 
-def find_ngb(w, targets=None, brute: Optional[bool] = None):
+def find_ngb(w, targets=None, brute: Optional[bool] = None, workers: int = -1):
     """Neighbour lists and smoothing lengths of ``targets`` (default: w.active).
 
     Returns (ngb int32[n_t, k], h float64[n_t])."""
@@ -148,7 +148,7 @@ def find_ngb(w, targets=None, brute: Optional[bool] = None):
         brute = w.n <= 4096
     ptr = idx = None
     if not brute:
-        ptr, idx = candidate_superset(x, y, z, w.periodic, w.box, tg, k)
+        ptr, idx = candidate_superset(x, y, z, w.periodic, w.box, tg, k, workers)
     ngb = np.zeros((tg.size, k), dtype=np.int32)
     h = np.zeros(tg.size, dtype=np.float64)
     rc = L.oref_find_ngb(w.n, _p(x), _p(y), _p(z), _p(ids), int(w.periodic), float(w.box),
@@ -210,9 +210,9 @@ def kick_pair(i, j, vx, vy, vz, state, ids, mass, model, eps, delta, seed, step)
                          int(seed), int(step))
 
 
-def full_step(w, brute: Optional[bool] = None, band: float = 1e-9):
+def full_step(w, brute: Optional[bool] = None, band: float = 1e-9, workers: int = -1):
     """Neighbours, scatter step and per-pair timestep of workload w."""
-    ngb, h = find_ngb(w, brute=brute)
+    ngb, h = find_ngb(w, brute=brute, workers=workers)
     vx, vy, vz, st, info, stats = scatter_step(w, ngb, h, band=band)
     dt = pair_timestep(w, ngb, h, vx, vy, vz)
     return dict(ngb=ngb, h=h, vx=vx, vy=vy, vz=vz, state=st, info=info, stats=stats,

@@ -66,10 +66,21 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("tree_ms", ctypes.c_double), ("map_ms", ctypes.c_double),
+                ("knn_ms", ctypes.c_double), ("eval_ms", ctypes.c_double),
+                ("resolve_ms", ctypes.c_double), ("timestep_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 # Every symbol include/sidm.h declares (tests check the library exports them).
 EXPORTS = ["sidm_footprint", "sidm_create", "sidm_destroy", "sidm_set_stream",
            "sidm_last_error", "sidm_status_string", "sidm_build_tree", "sidm_find_ngb",
-           "sidm_scatter_step", "sidm_pair_timestep", "sidm_sync"]
+           "sidm_scatter_step", "sidm_pair_timestep", "sidm_sync", "sidm_timing_enable",
+           "sidm_timing_read"]
 
 _lib = None
 
@@ -96,6 +107,8 @@ def lib():
         L.sidm_scatter_step.argtypes = [P, ctypes.POINTER(Particles), P, i64, P, P, P, u64, u32, P]
         L.sidm_pair_timestep.argtypes = [P, P, i64, P, P, P]
         L.sidm_sync.argtypes = [P, ctypes.POINTER(Stats)]
+        L.sidm_timing_enable.argtypes = [P, ctypes.c_int]
+        L.sidm_timing_read.argtypes = [P, ctypes.POINTER(Timing)]
         for name in EXPORTS:
             if name not in ("sidm_last_error", "sidm_status_string"):
                 getattr(L, name).restype = ctypes.c_int
@@ -221,6 +234,14 @@ class Context:
         self._check(lib().sidm_pair_timestep(self._h, _ptr(active), int(active.shape[0]),
                                              _ptr(ngb), _ptr(h), _ptr(dt_sidm)),
                     "sidm_pair_timestep")
+
+    def timing_enable(self, on: bool = True):
+        self._check(lib().sidm_timing_enable(self._h, int(bool(on))), "sidm_timing_enable")
+
+    def timing_read(self) -> dict:
+        t = Timing()
+        self._check(lib().sidm_timing_read(self._h, ctypes.byref(t)), "sidm_timing_read")
+        return t.as_dict()
 
     def sync(self) -> dict:
         s = Stats()

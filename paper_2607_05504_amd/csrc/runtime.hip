@@ -49,10 +49,11 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(hist, 256 * nsb, uint32_t);
     ADD(dtot, 256, uint32_t);
     ADD(bounds, 6, unsigned long long);
-    int64_t nleaf = (N + SIDM_LEAF - 1) / SIDM_LEAF, p2 = 2;
-    while (p2 < nleaf) p2 <<= 1;
-    ADD(nodes, 2 * p2 * 6, double);
-    ADD(visit, p2, int32_t);
+    ADD(nodes, tree_node_count(tree_levels(N)) * 6, double);
+    c->knn_batch = NA < SIDM_KNN_BATCH ? NA : SIDM_KNN_BATCH;
+    ADD(knn_list, c->knn_batch * SIDM_KNN_LMAX, int32_t);
+    ADD(knn_nl, c->knn_batch, int32_t);
+    ADD(knn_tb, c->knn_batch, double);
     ADD(flag, N, int32_t);
     ADD(tlist, NA, int32_t); ADD(slot, NA, int32_t);
     ADD(blk, (N + SIDM_SCAN_TILE - 1) / SIDM_SCAN_TILE + 1, int32_t);
@@ -206,10 +207,58 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
     return SIDM_OK;
 }
 
+sidm_status sidm_timing_enable(sidm_ctx *c, int on)
+{
+    if (!c) return SIDM_E_INVAL;
+    if (on && !c->timing) {
+        for (int p = 0; p < 6; ++p)
+            for (int r = 0; r < SIDM_TIMING_RING; ++r)
+                for (int b = 0; b < 2; ++b)
+                    if (!c->ev[p][r][b] && hipEventCreate(&c->ev[p][r][b]) != hipSuccess) {
+                        set_err(c, "timing: hipEventCreate failed");
+                        return SIDM_E_DEVICE;
+                    }
+    }
+    for (int p = 0; p < 6; ++p) c->ev_count[p] = 0;
+    c->timing = on ? 1 : 0;
+    return SIDM_OK;
+}
+
+sidm_status sidm_timing_read(sidm_ctx *c, sidm_timing *out)
+{
+    if (!c || !out) return SIDM_E_INVAL;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "timing_read");
+    double v[6];
+    int samples = 0;
+    for (int p = 0; p < 6; ++p) {
+        double sum = 0.0;
+        for (int r = 0; r < c->ev_count[p]; ++r) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, c->ev[p][r][0], c->ev[p][r][1]) == hipSuccess) sum += ms;
+        }
+        v[p] = c->ev_count[p] ? sum / c->ev_count[p] : 0.0;
+        if (p == PH_KNN) samples = c->ev_count[p];
+        c->ev_count[p] = 0;
+    }
+    out->samples = samples;
+    out->tree_ms = v[PH_TREE];
+    out->map_ms = v[PH_MAP];
+    out->knn_ms = v[PH_KNN];
+    out->eval_ms = v[PH_EVAL];
+    out->resolve_ms = v[PH_RESOLVE];
+    out->timestep_ms = v[PH_TIMESTEP];
+    return SIDM_OK;
+}
+
 sidm_status sidm_destroy(sidm_ctx *c)
 {
     if (!c) return SIDM_E_INVAL;
     (void)hipStreamSynchronize(c->stream);
+    for (int p = 0; p < 6; ++p)
+        for (int r = 0; r < SIDM_TIMING_RING; ++r)
+            for (int b = 0; b < 2; ++b)
+                if (c->ev[p][r][b]) (void)hipEventDestroy(c->ev[p][r][b]);
     (void)hipFree(c->dev_base);
     (void)hipHostFree(c->hstats);
     free(c);
@@ -254,7 +303,9 @@ sidm_status sidm_build_tree(sidm_ctx *c, const sidm_particles *p)
     c->n = p->n;
     c->has_mass = p->mass != nullptr;
     c->m_scalar = p->m_scalar;
+    phase_begin(c, PH_TREE);
     hipError_t e = launch_build_tree(c, p);
+    phase_end(c, PH_TREE);
     if (e != hipSuccess) return hip_fail(c, e, "build_tree");
     c->tree_ok = 1;
     return SIDM_OK;

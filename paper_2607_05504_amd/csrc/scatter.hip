@@ -467,19 +467,23 @@ int grid_for(int64_t n, int cap = 8192)
 }
 
 template <bool P>
-void run_scatter(const StepArgs &A, int64_t n_active, hipStream_t s)
+void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s)
 {
     const int64_t total = n_active * A.k;
     k_step_reset<<<1, 64, 0, s>>>(A.st, A.ctl);
     k_count_cand<<<1, 64, 0, s>>>(A.st, A.nt_dev, A.k);
+    phase_begin(c, PH_EVAL);
     k_eval<P><<<grid_for(total), kBlock, 0, s>>>(A);
+    phase_end(c, PH_EVAL);
     const int g = grid_for(A.cap_acc < total ? A.cap_acc : total, 2048);
+    phase_begin(c, PH_RESOLVE);
     for (int t = 0; t < kMultiPasses; ++t) {
         k_claim1<<<g, kBlock, 0, s>>>(A, t);
         k_claim2<<<g, kBlock, 0, s>>>(A, t);
         k_resolve<P><<<g, kBlock, 0, s>>>(A, t);
     }
     k_finish<P><<<1, 1024, 0, s>>>(A);
+    phase_end(c, PH_RESOLVE);
 }
 
 }  // namespace
@@ -489,8 +493,8 @@ hipError_t launch_scatter(sidm_ctx *c, sidm_particles *p, int64_t n_active, cons
                           uint32_t *cand_info)
 {
     StepArgs A = make_args(c, p, ngb, h, dt, seed, step, cand_info);
-    if (c->cfg.periodic) run_scatter<true>(A, n_active, c->stream);
-    else run_scatter<false>(A, n_active, c->stream);
+    if (c->cfg.periodic) run_scatter<true>(c, A, n_active, c->stream);
+    else run_scatter<false>(c, A, n_active, c->stream);
     return hipGetLastError();
 }
 
@@ -498,6 +502,8 @@ hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, co
                            double *dt_out)
 {
     StepArgs A = make_args(c, nullptr, ngb, h, nullptr, 0, 0, nullptr);
+    phase_begin(c, PH_TIMESTEP);
     k_timestep<<<grid_for(n_active), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm, dt_out);
+    phase_end(c, PH_TIMESTEP);
     return hipGetLastError();
 }

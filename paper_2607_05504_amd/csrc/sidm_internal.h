@@ -6,12 +6,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/sidm.h"
+#include "sidm.h"
 
 #define SIDM_PI 3.14159265358979323846
 #define SIDM_LEAF 32            // particles per tree leaf (consecutive in Morton order)
 #define SIDM_SORT_TILE 2048     // keys per radix-sort workgroup (256 threads x 8)
 #define SIDM_SCAN_TILE 1024     // elements per compaction workgroup
+#define SIDM_TIMING_RING 256    // timed launches per phase between two reads
+#define SIDM_KNN_LMAX 96        // leaves per target list (longer lists walk the tree instead)
+#define SIDM_KNN_BATCH (1 << 20)  // targets per neighbour-search batch
 
 // device-side error bits (latched, reported by sidm_sync)
 #define DERR_INDEX 1u           // an index outside [0, n)
@@ -19,6 +22,41 @@
 #define DERR_OVERFLOW 4u        // accepted-candidate list overflow
 #define DERR_COUNT 8u           // fewer than n_ngb + 1 candidates found
 #define DERR_STALL 16u          // a resolution pass decided nothing (cannot happen)
+
+#define SIDM_TREE_FAN 8         // children per internal tree node
+#define SIDM_MAX_LEVELS 12
+#define SIDM_LEVEL_SHIFT 27     // packed node id: (level << 27) | index within level
+
+// Level layout of the bucket tree: level 0 holds the leaves, level l+1 the
+// parents of groups of SIDM_TREE_FAN consecutive level-l nodes; the top level
+// has one node.  Node (l, q) is stored at nodes[off[l] + q].
+struct TreeLevels {
+    int32_t nlev;
+    int64_t off[SIDM_MAX_LEVELS];
+    int64_t cnt[SIDM_MAX_LEVELS];
+};
+
+inline TreeLevels tree_levels(int64_t n)
+{
+    TreeLevels t = {};
+    int64_t c = (n + SIDM_LEAF - 1) / SIDM_LEAF, off = 0;
+    if (c < 1) c = 1;
+    t.nlev = 0;
+    while (true) {
+        t.off[t.nlev] = off;
+        t.cnt[t.nlev] = c;
+        t.nlev++;
+        off += c;
+        if (c == 1 && t.nlev > 1) break;
+        c = (c + SIDM_TREE_FAN - 1) / SIDM_TREE_FAN;
+    }
+    return t;
+}
+
+inline int64_t tree_node_count(const TreeLevels &t)
+{
+    return t.off[t.nlev - 1] + t.cnt[t.nlev - 1];
+}
 
 struct DevStats {
     unsigned long long n_cand, n_accept0, n_events, n_flagged, n_p_ge_1, n_recheck;
@@ -62,10 +100,16 @@ struct sidm_ctx {
     uint32_t *dtot;          // [256]
     unsigned long long *bounds;   // ordered-u64 encodings of min x,y,z / max x,y,z
 
-    // bucket tree: implicit binary tree over 2^p2log leaves, node 1 = root
-    int64_t nleaf, p2;
-    double *nodes;           // [2*p2][6]  lo x,y,z, hi x,y,z
-    int32_t *visit;          // [p2] bottom-up arrival counters
+    // bucket tree: leaves of SIDM_LEAF consecutive particles (level 0) and
+    // levels of SIDM_TREE_FAN-ary parents above them, boxes level after level
+    TreeLevels lv;
+    double *nodes;           // [nodes][6]  lo x,y,z, hi x,y,z
+
+    // neighbour search: per-target leaf lists, processed in batches of knn_batch
+    int64_t knn_batch;
+    int32_t *knn_list;       // [knn_batch][SIDM_KNN_LMAX]
+    int32_t *knn_nl;         // [knn_batch]
+    double *knn_tb;          // [knn_batch]
 
     // active set in Morton order
     int32_t *flag;           // [cap_n] caller slot of an active particle, or -1
@@ -81,6 +125,11 @@ struct sidm_ctx {
 
     DevStats *dstats;
     unsigned int *derr;
+    // opt-in event timing of the main kernels: up to SIDM_TIMING_RING launches
+    // of each phase are bracketed between two sidm_timing_read calls
+    int timing;
+    hipEvent_t ev[6][SIDM_TIMING_RING][2];
+    int ev_count[6];
     void *dev_base;          // the one device allocation every buffer above lives in
     DevStats *hstats;        // pinned host copy
     unsigned int *herr;
@@ -199,6 +248,22 @@ __device__ __forceinline__ uint64_t direction_word(const Philox4 &x, bool target
 __device__ __forceinline__ double unit_from_word(uint64_t w)
 {
     return (double)(w >> 11) * 0x1.0p-53;
+}
+
+// phases timed by sidm_timing
+enum { PH_TREE = 0, PH_MAP = 1, PH_KNN = 2, PH_EVAL = 3, PH_RESOLVE = 4, PH_TIMESTEP = 5 };
+
+inline void phase_begin(sidm_ctx *c, int ph)
+{
+    if (c->timing && c->ev_count[ph] < SIDM_TIMING_RING)
+        (void)hipEventRecord(c->ev[ph][c->ev_count[ph]][0], c->stream);
+}
+inline void phase_end(sidm_ctx *c, int ph)
+{
+    if (c->timing && c->ev_count[ph] < SIDM_TIMING_RING) {
+        (void)hipEventRecord(c->ev[ph][c->ev_count[ph]][1], c->stream);
+        c->ev_count[ph]++;
+    }
 }
 
 // ---------------------------------------------------------------------------

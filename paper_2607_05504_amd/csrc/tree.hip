@@ -2,8 +2,8 @@
 // paper's sec. 4.3, rebuilt every step on the GPU):
 //   bounds -> 48-bit Morton keys -> LSD radix sort (8-bit digits, stable) ->
 //   gather of a Morton-ordered structure-of-arrays snapshot ->
-//   bucket leaves of SIDM_LEAF consecutive particles -> bottom-up boxes of an
-//   implicit binary tree over the leaves.
+//   bucket leaves of SIDM_LEAF consecutive particles -> boxes of an implicit
+//   SIDM_TREE_FAN-ary tree over the leaves, one level per launch.
 // Also maps the caller's active list onto Morton order (flag + compaction).
 #include "sidm_internal.h"
 
@@ -33,28 +33,34 @@ int grid_for(int64_t n, int block = kBlock, int cap = 4096)
 }
 
 // --- bounds (open boundaries) ------------------------------------------------
-__global__ void k_bounds(const double *__restrict__ x, const double *__restrict__ y,
-                         const double *__restrict__ z, int64_t n, unsigned long long *bounds)
+__global__ __launch_bounds__(256) void k_bounds(const double *__restrict__ x,
+                                                const double *__restrict__ y,
+                                                const double *__restrict__ z, int64_t n,
+                                                unsigned long long *bounds)
 {
-    unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0, 0, 0};
+    __shared__ unsigned long long part[4][6];
+    unsigned long long v[6] = {~0ull, ~0ull, ~0ull, 0, 0, 0};
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x) {
         unsigned long long a = ordered_u64(x[t]), b = ordered_u64(y[t]), c = ordered_u64(z[t]);
-        mn[0] = min(mn[0], a); mn[1] = min(mn[1], b); mn[2] = min(mn[2], c);
-        mx[0] = max(mx[0], a); mx[1] = max(mx[1], b); mx[2] = max(mx[2], c);
+        v[0] = min(v[0], a); v[1] = min(v[1], b); v[2] = min(v[2], c);
+        v[3] = max(v[3], a); v[4] = max(v[4], b); v[5] = max(v[5], c);
     }
-    // wave reduction, then one atomic per wave
     for (int off = 32; off > 0; off >>= 1) {
         for (int d = 0; d < 3; ++d) {
-            mn[d] = min(mn[d], (unsigned long long)__shfl_xor((long long)mn[d], off));
-            mx[d] = max(mx[d], (unsigned long long)__shfl_xor((long long)mx[d], off));
+            v[d] = min(v[d], (unsigned long long)__shfl_xor((long long)v[d], off));
+            v[3 + d] = max(v[3 + d], (unsigned long long)__shfl_xor((long long)v[3 + d], off));
         }
     }
-    if ((threadIdx.x & 63) == 0) {
-        for (int d = 0; d < 3; ++d) {
-            atomicMin(&bounds[d], mn[d]);
-            atomicMax(&bounds[3 + d], mx[d]);
-        }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int d = 0; d < 6; ++d) part[w][d] = v[d];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int d = threadIdx.x;
+        unsigned long long r = part[0][d];
+        for (int q = 1; q < 4; ++q) r = d < 3 ? min(r, part[q][d]) : max(r, part[q][d]);
+        if (d < 3) atomicMin(&bounds[d], r); else atomicMax(&bounds[d], r);
     }
 }
 
@@ -223,41 +229,53 @@ __global__ void k_gather(int64_t n, const int32_t *__restrict__ order, const dou
     }
 }
 
-// --- leaf boxes and bottom-up propagation ----------------------------------------------
-__device__ __forceinline__ double load_coherent(const double *p)
+// --- bucket tree boxes --------------------------------------------------------------
+// Two leaves per wavefront: lane l holds particle (leaf*32 + l%32); min/max by
+// butterfly shuffles within each half-wave.
+__global__ __launch_bounds__(256) void k_leaf_boxes(int64_t n, int64_t nleaf,
+                                                    const double *__restrict__ xs,
+                                                    const double *__restrict__ ys,
+                                                    const double *__restrict__ zs, double *nodes)
 {
-    unsigned long long b = __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double(b);
+    const int64_t leaf = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
+    const int sub = threadIdx.x & 31;
+    const int64_t s = leaf * SIDM_LEAF + sub;
+    const bool in = leaf < nleaf && s < n;
+    double v[6];
+    if (in) {
+        v[0] = v[3] = xs[s];
+        v[1] = v[4] = ys[s];
+        v[2] = v[5] = zs[s];
+    } else {
+        v[0] = v[1] = v[2] = INFINITY;
+        v[3] = v[4] = v[5] = -INFINITY;
+    }
+    for (int off = 16; off > 0; off >>= 1) {
+        for (int d = 0; d < 3; ++d) {
+            v[d] = fmin(v[d], __shfl_xor(v[d], off));
+            v[3 + d] = fmax(v[3 + d], __shfl_xor(v[3 + d], off));
+        }
+    }
+    if (sub < 6 && leaf < nleaf) nodes[leaf * 6 + sub] = v[sub];
 }
 
-__global__ void k_boxes(int64_t n, int64_t p2, const double *__restrict__ xs,
-                        const double *__restrict__ ys, const double *__restrict__ zs,
-                        double *nodes, int32_t *visit)
+// Boxes of level l from the boxes of level l-1 (one thread per node).
+__global__ void k_level_boxes(double *nodes, int64_t off_child, int64_t cnt_child, int64_t off,
+                              int64_t cnt)
 {
-    int64_t leaf = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (leaf >= p2) return;
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    int64_t s0 = leaf * SIDM_LEAF, s1 = s0 + SIDM_LEAF < n ? s0 + SIDM_LEAF : n;
-    for (int64_t s = s0; s < s1; ++s) {
-        double p[3] = {xs[s], ys[s], zs[s]};
-        for (int d = 0; d < 3; ++d) { lo[d] = fmin(lo[d], p[d]); hi[d] = fmax(hi[d], p[d]); }
-    }
-    int64_t node = p2 + leaf;
-    for (int d = 0; d < 3; ++d) { nodes[node * 6 + d] = lo[d]; nodes[node * 6 + 3 + d] = hi[d]; }
-    while (node > 1) {
-        __threadfence();
-        int64_t parent = node >> 1;
-        int old = atomicAdd(&visit[parent], 1);
-        if (old == 0) return;          // the sibling's thread finishes the parent
-        __threadfence();
-        const double *a = nodes + (2 * parent) * 6, *b = nodes + (2 * parent + 1) * 6;
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= cnt) return;
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int c = 0; c < SIDM_TREE_FAN; ++c) {
+        const int64_t ch = q * SIDM_TREE_FAN + c;
+        if (ch >= cnt_child) break;
+        const double *b = nodes + (off_child + ch) * 6;
         for (int d = 0; d < 3; ++d) {
-            nodes[parent * 6 + d] = fmin(load_coherent(a + d), load_coherent(b + d));
-            nodes[parent * 6 + 3 + d] = fmax(load_coherent(a + 3 + d), load_coherent(b + 3 + d));
+            v[d] = fmin(v[d], b[d]);
+            v[3 + d] = fmax(v[3 + d], b[3 + d]);
         }
-        node = parent;
     }
+    for (int d = 0; d < 6; ++d) nodes[(off + q) * 6 + d] = v[d];
 }
 
 // --- active set -> Morton order --------------------------------------------------------
@@ -366,12 +384,10 @@ hipError_t launch_build_tree(sidm_ctx *c, const sidm_particles *p)
     const int64_t n = p->n;
     const sidm_config &cfg = c->cfg;
     if (!cfg.periodic) {
-        unsigned long long init[6] = {~0ull, ~0ull, ~0ull, 0, 0, 0};
-        // tiny fill through a kernel (no memset nodes in captured graphs)
+        // tiny fills through a kernel (no memset nodes in captured graphs)
         launch_fill_u64(c->bounds, ~0ull, 3, s);
         launch_fill_u64(c->bounds + 3, 0ull, 3, s);
-        (void)init;
-        k_bounds<<<grid_for(n, kBlock, 1024), kBlock, 0, s>>>(p->x, p->y, p->z, n, c->bounds);
+        k_bounds<<<grid_for(n, kBlock, 256), kBlock, 0, s>>>(p->x, p->y, p->z, n, c->bounds);
     }
     k_morton<<<grid_for(n), kBlock, 0, s>>>(p->x, p->y, p->z, n, cfg.periodic, cfg.box,
                                              c->bounds, c->key0, c->val0);
@@ -390,14 +406,14 @@ hipError_t launch_build_tree(sidm_ctx *c, const sidm_particles *p)
     k_gather<<<grid_for(n), kBlock, 0, s>>>(n, vin, p->x, p->y, p->z, p->vx, p->vy, p->vz, p->mass,
                                             p->id, p->state, c->xs, c->ys, c->zs, c->vxs, c->vys,
                                             c->vzs, c->ms, c->ids, c->sts, c->perm, c->inv);
-    int64_t nleaf = (n + SIDM_LEAF - 1) / SIDM_LEAF;
-    int64_t p2 = 1;
-    while (p2 < nleaf) p2 <<= 1;
-    if (p2 < 2) p2 = 2;
-    c->nleaf = nleaf;
-    c->p2 = p2;
-    launch_fill_i32(c->visit, 0, p2, s);
-    k_boxes<<<(int)((p2 + 255) / 256), 256, 0, s>>>(n, p2, c->xs, c->ys, c->zs, c->nodes, c->visit);
+    c->lv = tree_levels(n);
+    const TreeLevels &lv = c->lv;
+    const int64_t nleaf = lv.cnt[0];
+    k_leaf_boxes<<<(unsigned)((nleaf * 32 + 255) / 256), 256, 0, s>>>(n, nleaf, c->xs, c->ys, c->zs,
+                                                                     c->nodes);
+    for (int l = 1; l < lv.nlev; ++l)
+        k_level_boxes<<<(unsigned)((lv.cnt[l] + 255) / 256), 256, 0, s>>>(
+            c->nodes, lv.off[l - 1], lv.cnt[l - 1], lv.off[l], lv.cnt[l]);
     return hipGetLastError();
 }
 
@@ -405,6 +421,7 @@ hipError_t launch_map_active(sidm_ctx *c, const int32_t *active, int64_t n_activ
 {
     hipStream_t s = c->stream;
     const int64_t n = c->n;
+    phase_begin(c, PH_MAP);
     launch_fill_i32(c->flag, -1, n, s);
     k_mark_active<<<grid_for(n_active), kBlock, 0, s>>>(active, n_active, n, c->inv, c->flag,
                                                         c->derr);
@@ -412,5 +429,6 @@ hipError_t launch_map_active(sidm_ctx *c, const int32_t *active, int64_t n_activ
     k_count_active<<<nblk, 256, 0, s>>>(c->flag, n, c->blk);
     k_scan_blocks<<<1, 1024, 0, s>>>(c->blk, nblk, c->nt_dev);
     k_compact_active<<<nblk, 256, 0, s>>>(c->flag, n, c->blk, c->tlist, c->slot);
+    phase_end(c, PH_MAP);
     return hipGetLastError();
 }

@@ -283,7 +283,7 @@ def hernquist_halo(n: int = 1_000_000, ic_seed: int = 102, philox_seed: int = 2,
 
 
 def hernquist_bins(w: Workload, active_frac: float = 0.125, dt_max: float = 2.0,
-                   n_ngb: int = 32, c_sidm: float = 0.1) -> Workload:
+                   n_ngb: int = 32, c_sidm: float = 0.1, safety: float = 0.5) -> Workload:
     """Power-of-two timestep bins from the local collision time, and the
     active set of one synchronisation point with at most ``active_frac`` of the
     particles active.
@@ -291,7 +291,9 @@ def hernquist_bins(w: Workload, active_frac: float = 0.125, dt_max: float = 2.0,
     Each particle's target step is the paper's collision-time scaling of the
     per-pair criterion (section 4.4): dt ~ (3 N_ngb C / 16) / (rho sigma(v) v),
     evaluated with the analytic density and the Maxwellian mean relative speed
-    4 sigma_1D / sqrt(pi) at the particle's radius.  Bin b holds steps
+    4 sigma_1D / sqrt(pi) at the particle's radius, times ``safety``: the
+    scaling uses the mean relative speed where the criterion uses the largest
+    one, and the factor 1/2 keeps most steps below the per-pair bound.  Bin b holds steps
     dt_max / 2^b; the active set is every particle in bins >= b*, b* being the
     smallest bin for which at most ``active_frac`` of all particles are in bins
     >= b*.
@@ -299,7 +301,7 @@ def hernquist_bins(w: Workload, active_frac: float = 0.125, dt_max: float = 2.0,
     r = np.sqrt(w.x ** 2 + w.y ** 2 + w.z ** 2)
     vbar = 4.0 * hernquist_sigma_r(r) / math.sqrt(math.pi)
     sig = w.sigma0 / (1.0 + (vbar / w.w0) ** 2) ** 2
-    dt_t = (3.0 * n_ngb * c_sidm / 16.0) / (hernquist_density(r) * sig * vbar)
+    dt_t = safety * (3.0 * n_ngb * c_sidm / 16.0) / (hernquist_density(r) * sig * vbar)
     b = np.ceil(np.log2(dt_max / dt_t)).clip(0, 40).astype(np.int64)
     counts = np.bincount(b, minlength=41)
     tail = np.cumsum(counts[::-1])[::-1]          # particles in bins >= b
