@@ -9,16 +9,18 @@
 //              (N_ngb+1)-th neighbour comes from the target's window of
 //              Morton-order neighbours: the window's (N_ngb+1)-th smallest r^2,
 //              bracketed in FP32 rounded up, so the bound never falls below the
-//              exact value.  Each lane then walks the tree on its own (every
-//              visit tests all children of a node at once, nearest first) and
-//              records every leaf whose box lies within T, nearest first.
+//              exact value.  The wavefront then walks the tree level by level
+//              against the box enclosing all its targets' spheres (64 children
+//              tested per round, one coalesced load), and each lane keeps the
+//              leaves that meet its own sphere.
 //
 //  k_knn_team  a team of 16 lanes per target, four targets per wavefront.  The
-//              team walks its leaf list, re-testing each leaf against the
-//              current radius; a leaf's particles are loaded 16 at a time
+//              team loads the gaps of its whole leaf list at once and takes the
+//              leaves nearest first until the nearest left lies beyond the
+//              current radius; a leaf's particles are tested 16 at a time
 //              (coalesced) and those within the radius are appended to a short
 //              LDS list.  When the list fills it is sorted (register bitonic
-//              network, 4 keys per lane) and cut back to N_ngb+1, which
+//              network, E keys per lane) and cut back to N_ngb+1, which
 //              tightens the radius.  A target whose list overflowed walks the
 //              tree from the root instead (same loop).
 //
@@ -80,6 +82,24 @@ __device__ __forceinline__ double node_gap2(const double *__restrict__ nodes, in
     double gy = axis_gap<PERIODIC>(ly, hy, py, box);
     double gz = axis_gap<PERIODIC>(lz, hz, pz, box);
     return (gx * gx + gy * gy) + gz * gz;
+}
+
+// squared gap to a box held in registers; +inf for an empty box
+template <bool PERIODIC>
+__device__ __forceinline__ double box_gap2(const double *bx, double px, double py, double pz, double box)
+{
+    if (!(bx[0] <= bx[3])) return INFINITY;
+    double gx = axis_gap<PERIODIC>(bx[0], bx[3], px, box);
+    double gy = axis_gap<PERIODIC>(bx[1], bx[4], py, box);
+    double gz = axis_gap<PERIODIC>(bx[2], bx[5], pz, box);
+    return (gx * gx + gy * gy) + gz * gz;
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // branch-free minimum-image separation^2, identical rounding to sep2<>
@@ -173,17 +193,40 @@ __device__ __forceinline__ double window_bound(const KnnArgs &A, int64_t i, int6
 // ---------------------------------------------------------------------------
 constexpr int kStackA = SIDM_MAX_LEVELS * (SIDM_TREE_FAN - 1) + 1;
 
+constexpr int kFront = 512;               // frontier capacity of the level walk
+
+__device__ __forceinline__ double wave_min(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+// does [lo, hi] (or a periodic image of it) meet [glo, ghi]?
+template <bool PERIODIC>
+__device__ __forceinline__ bool interval_meets(double lo, double hi, double glo, double ghi, double box)
+{
+    bool m = hi >= glo && lo <= ghi;
+    if (PERIODIC) m = m || (hi - box >= glo && lo - box <= ghi) || (hi + box >= glo && lo + box <= ghi);
+    return m;
+}
+
 template <bool PERIODIC, int W>
 __global__ __launch_bounds__(64) void k_knn_list(KnnArgs A, int64_t base)
 {
-    __shared__ int32_t s_st[kStackA * 64];
+    __shared__ int32_t s_fr[2][kFront];
+    __shared__ double s_hit[64 * 6];
     const int nt = *A.nt_dev;
     const int lane = threadIdx.x;
     const int64_t bb = (int64_t)blockIdx.x * 64 + lane;
     const int64_t b = base + bb;
     const bool valid = b < nt && bb < A.batch;
-    if (!valid) return;
-    const int32_t i = A.tlist[b];
+    if (!__any(valid)) return;
+    const int32_t i = A.tlist[valid ? b : base + (int64_t)blockIdx.x * 64];
     const double px = A.xs[i], py = A.ys[i], pz = A.zs[i];
     const double box = A.box;
     const int64_t n = A.n;
@@ -198,46 +241,73 @@ __global__ __launch_bounds__(64) void k_knn_list(KnnArgs A, int64_t base)
     const double T = fmin(window_bound<PERIODIC, W>(A, i, wl, px, py, pz, K1),
                           window_bound<PERIODIC, W>(A, i, wr, px, py, pz, K1));
 
-    // per-lane walk: each visit tests all children of a node, nearest first
+    // group box: every lane's sphere, padded far beyond rounding, so a box a
+    // lane needs always meets it
+    const double R = sqrt(T) * (1.0 + 1e-9) + (fabs(px) + fabs(py) + fabs(pz) + box) * 1e-14;
+    const double gxl = wave_min(valid ? px - R : INFINITY), gxh = wave_max(valid ? px + R : -INFINITY);
+    const double gyl = wave_min(valid ? py - R : INFINITY), gyh = wave_max(valid ? py + R : -INFINITY);
+    const double gzl = wave_min(valid ? pz - R : INFINITY), gzh = wave_max(valid ? pz + R : -INFINITY);
+
+    // level-synchronous walk: every round tests up to 64 children (one per
+    // lane, one coalesced load); surviving internal nodes form the next
+    // frontier, surviving leaves are offered to each lane's own sphere
     int32_t *lst = A.list + bb * SIDM_KNN_LMAX;
     int nl = 0;
-    bool ovf = false;
-    int sp = 1;
-    s_st[lane] = (A.lv.nlev - 1) << SIDM_LEVEL_SHIFT;   // the root
-    while (sp > 0 && !ovf) {
-        --sp;
-        const int32_t e = s_st[sp * 64 + lane];
-        const int cl = (e >> SIDM_LEVEL_SHIFT) - 1;      // level of the children
-        const int64_t q0 = (int64_t)(e & kIdxMask) * SIDM_TREE_FAN;
+    bool ovf = false, wave_ovf = false;
+    int cur = 0, fn = 1;
+    s_fr[0][0] = 0;                                   // the root (top level, index 0)
+    for (int lvl = A.lv.nlev - 1; lvl > 0 && !wave_ovf; --lvl) {
+        const int cl = lvl - 1;
         const int64_t ccnt = A.lv.cnt[cl], coff = A.lv.off[cl];
-        double g[SIDM_TREE_FAN];
-        int32_t id[SIDM_TREE_FAN];
+        int nxt = 0;
+        const int total = fn * SIDM_TREE_FAN;
+        for (int c0 = 0; c0 < total; c0 += 64) {
+            const int t = c0 + lane;
+            bool hit = false;
+            int64_t q = 0;
+            double bx[6];
+            wave_sync();
+            if (t < total) {
+                q = (int64_t)s_fr[cur][t / SIDM_TREE_FAN] * SIDM_TREE_FAN + t % SIDM_TREE_FAN;
+                if (q < ccnt) {
+                    const double *nb = A.nodes + (coff + q) * 6;
 #pragma unroll
-        for (int c = 0; c < SIDM_TREE_FAN; ++c) {
-            const int64_t q = q0 + c;
-            id[c] = (int32_t)q;
-            g[c] = q < ccnt ? node_gap2<PERIODIC>(A.nodes, coff + q, px, py, pz, box) : INFINITY;
-        }
-        sort8(g, id);
-        if (cl == 0) {
-#pragma unroll
-            for (int c = 0; c < SIDM_TREE_FAN; ++c) {
-                if (g[c] <= T && g[c] < INFINITY) {
-                    if (nl < SIDM_KNN_LMAX) lst[nl++] = id[c];
-                    else ovf = true;
+                    for (int d = 0; d < 6; ++d) bx[d] = nb[d];
+                    hit = bx[0] <= bx[3] && interval_meets<PERIODIC>(bx[0], bx[3], gxl, gxh, box) &&
+                          interval_meets<PERIODIC>(bx[1], bx[4], gyl, gyh, box) &&
+                          interval_meets<PERIODIC>(bx[2], bx[5], gzl, gzh, box);
                 }
             }
-        } else {
+            const uint64_t m = __ballot(hit);
+            const int rank = __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+            const int nh = __popcll(m);
+            if (cl > 0) {
+                if (nxt + nh > kFront) { wave_ovf = true; break; }
+                if (hit) s_fr[cur ^ 1][nxt + rank] = (int32_t)q;
+                nxt += nh;
+            } else {
+                // leaves: stage the hit boxes, then each lane keeps the ones
+                // within its own sphere
+                if (hit) {
 #pragma unroll
-            for (int c = SIDM_TREE_FAN - 1; c >= 0; --c) {
-                if (g[c] <= T && g[c] < INFINITY) {
-                    s_st[sp * 64 + lane] = (cl << SIDM_LEVEL_SHIFT) | id[c];
-                    ++sp;
+                    for (int d = 0; d < 6; ++d) s_hit[rank * 6 + d] = bx[d];
+                    s_fr[cur ^ 1][rank] = (int32_t)q;
+                }
+                wave_sync();
+                for (int h = 0; h < nh; ++h) {
+                    const double g = box_gap2<PERIODIC>(s_hit + h * 6, px, py, pz, box);
+                    if (valid && g <= T) {
+                        if (nl < SIDM_KNN_LMAX) lst[nl++] = s_fr[cur ^ 1][h];
+                        else ovf = true;
+                    }
                 }
             }
         }
+        cur ^= 1;
+        fn = nxt;
     }
-    A.nl[bb] = ovf ? -1 : nl;
+    if (!valid) return;
+    A.nl[bb] = (ovf || wave_ovf) ? -1 : nl;
     A.tb[bb] = T;
 }
 
@@ -248,13 +318,6 @@ __global__ __launch_bounds__(64) void k_knn_list(KnnArgs A, int64_t base)
 __device__ __forceinline__ bool key_lt(double ra, uint32_t ia, double rb, uint32_t ib)
 {
     return ra < rb || (ra == rb && ia < ib);
-}
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // One compare-exchange stage (k = 2^LK, distance d = 2^LD) of an ascending
@@ -319,12 +382,13 @@ __device__ __forceinline__ void team_sort(double (&r)[E], uint32_t (&id)[E], int
     bitonic_levels<E, 1, LOGN>(r, id, jj, tl);
 }
 
+constexpr int kStackB = 7 * 9 + 1;       // deepest walk: 10 levels (n < 2^31) of 8-ary nodes
+
 template <bool PERIODIC, int E>
 __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
 {
     constexpr int N = 16 * E;                 // list capacity
-    constexpr int SCAP = SIDM_KNN_LMAX + kStackA;
-    __shared__ int32_t s_stack[16][SCAP];
+    __shared__ int32_t s_stack[16][kStackB];  // only the overflow walk uses it
     __shared__ double s_r2[16][N];
     __shared__ uint32_t s_id[16][N];
     __shared__ int32_t s_j[16][N];
@@ -346,19 +410,28 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
     int32_t *L_j = s_j[team];
     int32_t *stk = s_stack[team];
 
-    // work stack: the leaf list (nearest on top), or the root on overflow.
-    // Entries are packed (level << SIDM_LEVEL_SHIFT) | index; leaves are level 0.
+    // leaves come from the target's list (nearest first), read 16 at a time
+    // with one lane per leaf box; a target whose list overflowed walks the
+    // tree from the root with a stack (packed (level << SIDM_LEVEL_SHIFT) | index)
     const int nl = A.nl[bb];
-    int sp;
-    if (nl >= 0) {
-        const int32_t *lst = A.list + bb * SIDM_KNN_LMAX;
-        for (int t = tl; t < nl; t += 16) stk[nl - 1 - t] = lst[t];
-        sp = nl;
-    } else {
+    const int32_t *lst = A.list + bb * SIDM_KNN_LMAX;
+    const bool walk = nl < 0;
+    int sp = 0;
+    if (walk) {
         if (tl == 0) stk[0] = (A.lv.nlev - 1) << SIDM_LEVEL_SHIFT;
         sp = 1;
     }
-    wave_sync();
+    // gaps of the whole list (one round of loads); leaves are then taken
+    // nearest first, and the walk ends when the nearest left is beyond T
+    constexpr int kPer = (SIDM_KNN_LMAX + 15) / 16;
+    double lg[kPer];
+    int32_t lf[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int t = q * 16 + tl;
+        lf[q] = (!walk && t < nl) ? lst[t] : -1;
+        lg[q] = lf[q] >= 0 ? node_gap2<PERIODIC>(A.nodes, lf[q], px, py, pz, box) : INFINITY;
+    }
 
     double T = A.tb[bb];
     int count = 0;
@@ -368,9 +441,14 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
     const uint64_t below = (tl == 0) ? 0ull : ((1ull << tl) - 1ull);
     int64_t cur_s0 = 0;
     int cur_m = 0, cur_off = 0;
-    bool done = false;
+    double q1x = 0, q1y = 0, q1z = 0, q0x = 0, q0y = 0, q0z = 0;
+    bool done = false, finished = false;
+    wave_sync();
     while (true) {
-        if (done || count + 16 > N) {
+        // the teams of a wavefront sort together whenever one of them must
+        // (sorting is idempotent), so the network runs once for all four
+        const bool want = !finished && (done || count + 16 > N);
+        if (__any(want) && !finished) {
             // sort the list, keep the best K1, tighten the radius
             wave_sync();
 #pragma unroll
@@ -389,55 +467,92 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
             wave_sync();
             if (count >= K1) T = L_r2[K1 - 1];
             count = count < K1 ? count : K1;
-            if (done) break;
+            if (done) finished = true;
         }
+        if (__all(finished)) break;
+        if (finished) continue;
         if (cur_off >= cur_m) {
             // next leaf within the radius
             cur_m = 0;
             cur_off = 0;
-            while (sp > 0) {
-                --sp;
-                const int32_t e = stk[sp];
-                const int lvl = e >> SIDM_LEVEL_SHIFT;
-                const int64_t q = e & kIdxMask;
-                const double d2 = node_gap2<PERIODIC>(A.nodes, A.lv.off[lvl] + q, px, py, pz, box);
-                if (!(d2 <= T)) continue;
-                if (lvl == 0) {
-                    cur_s0 = q * SIDM_LEAF;
-                    cur_m = (int)((n - cur_s0) < SIDM_LEAF ? (n - cur_s0) : SIDM_LEAF);
-                    break;
-                }
-                // overflow path: push the children within the radius
-                const int cl = lvl - 1;
-                const int64_t cq = q * SIDM_TREE_FAN + tl;
-                double gc = INFINITY;
-                if (tl < SIDM_TREE_FAN && cq < A.lv.cnt[cl])
-                    gc = node_gap2<PERIODIC>(A.nodes, A.lv.off[cl] + cq, px, py, pz, box);
-                const bool ok = gc <= T && gc < INFINITY;
-                // rank among the passing children by (gap, index); nearest on top
-                int rank = 0;
+            while (true) {
+                if (!walk) {
+                    // team argmin over (gap, lane, slot)
+                    double bg = INFINITY;
+                    int bq = 0;
 #pragma unroll
-                for (int s2 = 0; s2 < SIDM_TREE_FAN; ++s2) {
-                    const double go = __shfl(gc, s2, 16);
-                    const bool oo = go <= T && go < INFINITY;
-                    rank += oo && (go < gc || (go == gc && s2 < tl));
+                    for (int q = 0; q < kPer; ++q)
+                        if (lg[q] < bg) { bg = lg[q]; bq = q; }
+                    int bl = tl;
+                    for (int off = 1; off < 16; off <<= 1) {
+                        const double og = __shfl_xor(bg, off);
+                        const int ol = __shfl_xor(bl, off), oq = __shfl_xor(bq, off);
+                        if (og < bg || (og == bg && ol < bl)) { bg = og; bl = ol; bq = oq; }
+                    }
+                    if (!(bg <= T)) break;
+                    int32_t leaf = -1;
+#pragma unroll
+                    for (int q = 0; q < kPer; ++q)
+                        if (q == bq) leaf = lf[q];
+                    leaf = __shfl(leaf, bl, 16);
+                    if (tl == bl) {
+#pragma unroll
+                        for (int q = 0; q < kPer; ++q)
+                            if (q == bq) lg[q] = INFINITY;
+                    }
+                    cur_s0 = (int64_t)leaf * SIDM_LEAF;
+                } else {
+                    if (sp == 0) break;
+                    --sp;
+                    const int32_t e = stk[sp];
+                    const int lvl = e >> SIDM_LEVEL_SHIFT;
+                    const int64_t q = e & kIdxMask;
+                    const double d2 = node_gap2<PERIODIC>(A.nodes, A.lv.off[lvl] + q, px, py, pz, box);
+                    if (!(d2 <= T)) continue;
+                    if (lvl > 0) {
+                        // push the children within the radius, nearest on top
+                        const int cl = lvl - 1;
+                        const int64_t cq = q * SIDM_TREE_FAN + tl;
+                        double gc = INFINITY;
+                        if (tl < SIDM_TREE_FAN && cq < A.lv.cnt[cl])
+                            gc = node_gap2<PERIODIC>(A.nodes, A.lv.off[cl] + cq, px, py, pz, box);
+                        const bool ok = gc <= T && gc < INFINITY;
+                        int rank = 0;
+#pragma unroll
+                        for (int s2 = 0; s2 < SIDM_TREE_FAN; ++s2) {
+                            const double go = __shfl(gc, s2, 16);
+                            const bool oo = go <= T && go < INFINITY;
+                            rank += oo && (go < gc || (go == gc && s2 < tl));
+                        }
+                        const uint64_t m = (__ballot(ok) >> (wteam * 16)) & 0xffffull;
+                        const int np = __popcll(m);
+                        wave_sync();
+                        if (ok) stk[sp + np - 1 - rank] = (cl << SIDM_LEVEL_SHIFT) | (int32_t)cq;
+                        sp += np;
+                        wave_sync();
+                        continue;
+                    }
+                    cur_s0 = q * SIDM_LEAF;
                 }
-                const uint64_t m = (__ballot(ok) >> (wteam * 16)) & 0xffffull;
-                const int np = __popcll(m);
-                wave_sync();
-                if (ok) stk[sp + np - 1 - rank] = (cl << SIDM_LEVEL_SHIFT) | (int32_t)cq;
-                sp += np;
-                wave_sync();
+                cur_m = (int)((n - cur_s0) < SIDM_LEAF ? (n - cur_s0) : SIDM_LEAF);
+                // both 16-particle halves of the leaf in one round of loads
+                const int64_t j0 = cur_s0 + (tl < cur_m ? tl : 0);
+                const int64_t j1 = cur_s0 + (tl + 16 < cur_m ? tl + 16 : 0);
+                q0x = A.xs[j0]; q0y = A.ys[j0]; q0z = A.zs[j0];
+                q1x = A.xs[j1]; q1y = A.ys[j1]; q1z = A.zs[j1];
+                break;
             }
             if (cur_m == 0) { done = true; continue; }
         }
         // 16 particles of the current leaf
         const int c = cur_off + tl;
         const int64_t j = cur_s0 + c;
+        const bool first = cur_off == 0;
         bool pass = false;
         double r2 = 0.0;
         if (c < cur_m) {
-            r2 = sep2_sel<PERIODIC>(px, py, pz, A.xs[j], A.ys[j], A.zs[j], box);
+            r2 = sep2_sel<PERIODIC>(px, py, pz, first ? q0x : q1x, first ? q0y : q1y,
+                                    first ? q0z : q1z, box);
             pass = r2 <= T && j != i;
         }
         const uint64_t mask = (__ballot(pass) >> (wteam * 16)) & 0xffffull;

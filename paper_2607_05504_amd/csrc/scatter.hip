@@ -154,82 +154,122 @@ __device__ void kick(const StepArgs &A, int32_t i, int32_t j)
 }
 
 // ----------------------------------------------------------------------------
-// Evaluation 0: every candidate with the step-start velocities
+// Evaluation 0: every candidate with the step-start velocities.  Accepted
+// candidates are staged in LDS and appended to the list in bulk, and the
+// statistics are reduced per workgroup, so global atomics stay per workgroup.
 // ----------------------------------------------------------------------------
+constexpr int kStage = 512;                // staged accepted candidates per workgroup
+
+struct StagedAcc {
+    int32_t i[kStage], j[kStage], cand[kStage];
+    double u[kStage], W[kStage], dt[kStage];
+    uint64_t prio[kStage], idpair[kStage];
+};
+
+__device__ void flush_staged(const StepArgs &A, StagedAcc &S, int n, int32_t &base_s)
+{
+    if (threadIdx.x == 0) base_s = atomicAdd(&A.ctl[CTL_COUNT0], n);
+    __syncthreads();
+    const int64_t base = base_s;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int64_t pos = base + t;
+        if (pos >= A.cap_acc) { atomicOr(A.derr, DERR_OVERFLOW); continue; }
+        const int32_t i = S.i[t], j = S.j[t];
+        A.L0.i[pos] = i; A.L0.j[pos] = j; A.L0.cand[pos] = S.cand[t];
+        A.L0.u[pos] = S.u[t]; A.L0.W[pos] = S.W[t]; A.L0.dt[pos] = S.dt[t];
+        A.L0.prio[pos] = S.prio[t]; A.L0.idpair[pos] = S.idpair[t];
+        A.c1a[i] = ~0ull; A.c1a[j] = ~0ull;
+        A.c2a[i] = ~0ull; A.c2a[j] = ~0ull;
+    }
+    __syncthreads();
+}
+
 template <bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
 {
+    __shared__ StagedAcc S;
+    __shared__ int s_n;
+    __shared__ int32_t s_base;
+    __shared__ unsigned long long s_red[4][4];
     const int64_t nt = *A.nt_dev;
     const int64_t total = nt * A.k;
-    unsigned long long maxp = 0;
+    unsigned long long maxp = 0, n_fl = 0, n_ge1 = 0, n_acc = 0;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
     for (int64_t c0 = blockIdx.x * (int64_t)blockDim.x; c0 < total;
          c0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = c0 + threadIdx.x;
-        const bool in = c < total;
-        bool acc = false, flagged = false, pge1 = false;
-        int32_t i = 0, j = 0, a = 0;
-        int s = 0;
-        double u = 0, W = 0, dta = 0;
-        uint32_t idi = 0, idj = 0;
-        if (in) {
+        if (c < total) {
             const int64_t b = c / A.k;
-            s = (int)(c - b * A.k);
-            i = A.tlist[b];
-            a = A.slot[b];
+            const int s = (int)(c - b * A.k);
+            const int32_t i = A.tlist[b];
+            const int32_t a = A.slot[b];
             const int32_t jc = A.ngb[(int64_t)a * A.k + s];
             if (jc < 0 || jc >= A.n) {
                 atomicOr(A.derr, DERR_INDEX);
             } else {
-                j = A.inv[jc];
+                const int32_t j = A.inv[jc];
                 const double r = sqrt(sep2<PERIODIC>(A.xs[i], A.ys[i], A.zs[i], A.xs[j], A.ys[j],
                                                      A.zs[j], A.box));
-                W = cubic_spline(r, A.h[a]);
+                const double W = cubic_spline(r, A.h[a]);
                 const double w = rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
                 const double sig = xsec_sigma(w, A.xsec, A.s0, A.w0);
-                dta = A.dt[a];
+                const double dta = A.dt[a];
                 const double P = pair_prob(mass_of(A, j), sig, w, W, dta);
-                idi = A.ids[i];
-                idj = A.ids[j];
-                Philox4 x = pair_draw(A.seed, A.step, idi, idj, PURPOSE_DECIDE);
-                u = unit_from_word(direction_word(x, idi < idj));
-                acc = u < P;
-                flagged = fabs(P - u) < A.band;
-                pge1 = P >= 1.0;
-                unsigned long long pb = (unsigned long long)__double_as_longlong(P);
+                const uint32_t idi = A.ids[i], idj = A.ids[j];
+                const Philox4 x = pair_draw(A.seed, A.step, idi, idj, PURPOSE_DECIDE);
+                const double u = unit_from_word(direction_word(x, idi < idj));
+                const bool acc = u < P;
+                const bool flagged = fabs(P - u) < A.band;
+                n_fl += flagged;
+                n_ge1 += P >= 1.0;
+                n_acc += acc;
+                const unsigned long long pb = (unsigned long long)__double_as_longlong(P);
                 maxp = pb > maxp ? pb : maxp;
                 if (A.cand_info)
                     A.cand_info[(int64_t)a * A.k + s] =
                         (acc ? SIDM_CAND_ACCEPT0 : 0u) | (flagged ? SIDM_CAND_FLAGGED : 0u);
+                if (acc) {
+                    const Philox4 xp = pair_draw(A.seed, A.step, idi, idj, PURPOSE_PRIORITY);
+                    const int t = atomicAdd(&s_n, 1);      // LDS; kStage >= 2 * blockDim
+                    S.i[t] = i; S.j[t] = j; S.cand[t] = a * A.k + s;
+                    S.u[t] = u; S.W[t] = W; S.dt[t] = dta;
+                    S.prio[t] = direction_word(xp, idi < idj);
+                    S.idpair[t] = ((uint64_t)idi << 32) | idj;
+                }
             }
         }
-        wave_count(&A.st->n_flagged, flagged);
-        wave_count(&A.st->n_p_ge_1, pge1);
-        wave_count(&A.st->n_accept0, acc);
-        int64_t pos = wave_append(&A.ctl[CTL_COUNT0], acc);
-        if (acc) {
-            if (pos >= A.cap_acc) {
-                atomicOr(A.derr, DERR_OVERFLOW);
-            } else {
-                Philox4 x = pair_draw(A.seed, A.step, idi, idj, PURPOSE_PRIORITY);
-                A.L0.i[pos] = i;
-                A.L0.j[pos] = j;
-                A.L0.cand[pos] = a * A.k + s;
-                A.L0.u[pos] = u;
-                A.L0.W[pos] = W;
-                A.L0.dt[pos] = dta;
-                A.L0.prio[pos] = direction_word(x, idi < idj);
-                A.L0.idpair[pos] = ((uint64_t)idi << 32) | idj;
-                A.c1a[i] = ~0ull; A.c1a[j] = ~0ull;
-                A.c2a[i] = ~0ull; A.c2a[j] = ~0ull;
-            }
+        __syncthreads();
+        const int n_st = s_n;
+        if (n_st > kStage - kBlock) {              // the next round might not fit
+            flush_staged(A, S, n_st, s_base);
+            if (threadIdx.x == 0) s_n = 0;
+            __syncthreads();
         }
     }
-    // wave max of P, one atomic per wave
+    if (s_n > 0) flush_staged(A, S, s_n, s_base);
+    // workgroup reduction of the statistics, one atomic each
     for (int off = 32; off > 0; off >>= 1) {
-        unsigned long long o = (unsigned long long)__shfl_xor((long long)maxp, off);
+        const unsigned long long o = (unsigned long long)__shfl_xor((long long)maxp, off);
         maxp = o > maxp ? o : maxp;
+        n_fl += (unsigned long long)__shfl_xor((long long)n_fl, off);
+        n_ge1 += (unsigned long long)__shfl_xor((long long)n_ge1, off);
+        n_acc += (unsigned long long)__shfl_xor((long long)n_acc, off);
     }
-    if (wave_lane() == 0 && maxp) atomicMax(&A.st->max_p_bits, maxp);
+    const int w = threadIdx.x >> 6;
+    if (wave_lane() == 0) { s_red[w][0] = maxp; s_red[w][1] = n_fl; s_red[w][2] = n_ge1; s_red[w][3] = n_acc; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = 0, f = 0, g = 0, q = 0;
+        for (int v = 0; v < kBlock / 64; ++v) {
+            m = s_red[v][0] > m ? s_red[v][0] : m;
+            f += s_red[v][1]; g += s_red[v][2]; q += s_red[v][3];
+        }
+        if (m) atomicMax(&A.st->max_p_bits, m);
+        if (f) atomicAdd(&A.st->n_flagged, f);
+        if (g) atomicAdd(&A.st->n_p_ge_1, g);
+        if (q) atomicAdd(&A.st->n_accept0, q);
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -411,8 +451,51 @@ __global__ void k_count_cand(DevStats *st, const int32_t *nt_dev, int k)
 }
 
 // ----------------------------------------------------------------------------
-// Per-pair timestep (Eq. sidm_timestep) with the current velocities
+// Per-pair timestep (Eq. sidm_timestep) with the current velocities.  One
+// thread per (target, neighbour) and a shuffle max over the target's lanes
+// when n_ngb is a power of two up to 64; one thread per target otherwise.
 // ----------------------------------------------------------------------------
+__device__ __forceinline__ double pair_rate(const StepArgs &A, double vix, double viy, double viz,
+                                            int32_t jc)
+{
+    if (jc < 0 || jc >= A.n) { atomicOr(A.derr, DERR_INDEX); return 0.0; }
+    const int32_t j = A.inv[jc];
+    const double w = rel_speed(vix, viy, viz, A.vxs[j], A.vys[j], A.vzs[j]);
+    return w * xsec_sigma(w, A.xsec, A.s0, A.w0);
+}
+
+__device__ __forceinline__ double dt_from_rate(const StepArgs &A, int32_t i, double h, double rmax,
+                                               double c_sidm)
+{
+    const double W0 = cubic_spline(0.0, h);
+    return rmax > 0.0 ? (2.0 * c_sidm) / ((mass_of(A, i) * W0) * rmax) : INFINITY;
+}
+
+__global__ __launch_bounds__(kBlock) void k_timestep_group(StepArgs A, double c_sidm, double *dt_out)
+{
+    const int64_t nt = *A.nt_dev;
+    const int64_t total = nt * A.k;
+    for (int64_t c0 = blockIdx.x * (int64_t)blockDim.x; c0 < total;
+         c0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = c0 + threadIdx.x;
+        const bool in = c < total;
+        const int64_t b = in ? c / A.k : 0;
+        const int s = (int)(c - b * A.k);
+        double rate = 0.0;
+        int32_t i = 0, a = 0;
+        if (in) {
+            i = A.tlist[b];
+            a = A.slot[b];
+            rate = pair_rate(A, A.vxs[i], A.vys[i], A.vzs[i], A.ngb[(int64_t)a * A.k + s]);
+        }
+        for (int off = 1; off < A.k; off <<= 1) {
+            const double o = __shfl_xor(rate, off);
+            rate = o > rate ? o : rate;
+        }
+        if (in && s == 0) dt_out[a] = dt_from_rate(A, i, A.h[a], rate, c_sidm);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_timestep(StepArgs A, double c_sidm, double *dt_out)
 {
     const int64_t nt = *A.nt_dev;
@@ -422,15 +505,10 @@ __global__ __launch_bounds__(kBlock) void k_timestep(StepArgs A, double c_sidm, 
         const double vix = A.vxs[i], viy = A.vys[i], viz = A.vzs[i];
         double rmax = 0.0;
         for (int s = 0; s < A.k; ++s) {
-            const int32_t jc = A.ngb[(int64_t)a * A.k + s];
-            if (jc < 0 || jc >= A.n) { atomicOr(A.derr, DERR_INDEX); continue; }
-            const int32_t j = A.inv[jc];
-            const double w = rel_speed(vix, viy, viz, A.vxs[j], A.vys[j], A.vzs[j]);
-            const double ws = w * xsec_sigma(w, A.xsec, A.s0, A.w0);
-            rmax = ws > rmax ? ws : rmax;
+            const double r = pair_rate(A, vix, viy, viz, A.ngb[(int64_t)a * A.k + s]);
+            rmax = r > rmax ? r : rmax;
         }
-        const double W0 = cubic_spline(0.0, A.h[a]);
-        dt_out[a] = rmax > 0.0 ? (2.0 * c_sidm) / ((mass_of(A, i) * W0) * rmax) : INFINITY;
+        dt_out[a] = dt_from_rate(A, i, A.h[a], rmax, c_sidm);
     }
 }
 
@@ -473,7 +551,7 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
     k_step_reset<<<1, 64, 0, s>>>(A.st, A.ctl);
     k_count_cand<<<1, 64, 0, s>>>(A.st, A.nt_dev, A.k);
     phase_begin(c, PH_EVAL);
-    k_eval<P><<<grid_for(total), kBlock, 0, s>>>(A);
+    k_eval<P><<<grid_for(total, 2048), kBlock, 0, s>>>(A);
     phase_end(c, PH_EVAL);
     const int g = grid_for(A.cap_acc < total ? A.cap_acc : total, 2048);
     phase_begin(c, PH_RESOLVE);
@@ -503,7 +581,11 @@ hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, co
 {
     StepArgs A = make_args(c, nullptr, ngb, h, nullptr, 0, 0, nullptr);
     phase_begin(c, PH_TIMESTEP);
-    k_timestep<<<grid_for(n_active), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm, dt_out);
+    const int k = A.k;
+    if (k <= 64 && (k & (k - 1)) == 0)
+        k_timestep_group<<<grid_for(n_active * k), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm, dt_out);
+    else
+        k_timestep<<<grid_for(n_active), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm, dt_out);
     phase_end(c, PH_TIMESTEP);
     return hipGetLastError();
 }
