@@ -56,25 +56,62 @@ def touched_count(ngb: np.ndarray, active: np.ndarray) -> int:
 
 
 def cpu_baseline(w, seconds_hint: float = 15.0) -> dict:
-    """The CPU oracle, as it stands, on a bounded sample of the same workload
-    (a prefix of the active list, same particles), single thread."""
+    """The CPU oracle, as it stands, single thread, on a bounded sample of the
+    same workload: the whole active set when a step of it takes well under a
+    minute (repeated until about seconds_hint of work is timed), else a prefix
+    of the active list sized for about seconds_hint."""
     import oracle
     oracle.build(force=False)
-    # calibrate on a small prefix, then size the sample for ~seconds_hint
-    n0 = min(w.n_active, 2000)
-    t0 = time.perf_counter()
-    oracle.full_step(w.subset_active(n0), workers=1)
-    t_small = time.perf_counter() - t0
-    per = t_small / n0
-    n_s = int(min(w.n_active, max(n0, seconds_hint / max(per, 1e-9))))
+    # cost model t = a + b * n_active from two prefixes (the fixed part is
+    # the candidate gathering over all particles)
+    n0 = min(w.n_active, 1000)
+    n1 = min(w.n_active, 8000)
+    t = []
+    for m in (n0, n1):
+        t0 = time.perf_counter()
+        oracle.full_step(w.subset_active(m), workers=1)
+        t.append(time.perf_counter() - t0)
+    per = max((t[1] - t[0]) / max(n1 - n0, 1), 1e-9)
+    fixed = max(t[0] - per * n0, 0.0)
+    t_full = fixed + per * w.n_active
+    if t_full <= 2 * seconds_hint:
+        n_s = w.n_active
+    else:
+        n_s = int(max(n1, (seconds_hint - fixed) / per))
     ws = w.subset_active(n_s)
+    reps = 0
     t0 = time.perf_counter()
-    oracle.full_step(ws, workers=1)
-    dt = time.perf_counter() - t0
+    while reps < 20 and (reps == 0 or time.perf_counter() - t0 < seconds_hint):
+        oracle.full_step(ws, workers=1)
+        reps += 1
+    dt = (time.perf_counter() - t0) / reps
+    what = "all" if n_s == w.n_active else f"the first {n_s} of"
     return {"value": n_s / dt, "unit": "active particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_s} of {w.n_active} active particles of the same workload "
-                      f"(all {w.n} particles as neighbours), one full step "
-                      f"(neighbours + scatter + timestep), {dt:.1f} s"}
+            "sample": f"{what} {w.n_active} active particles of the same workload (all {w.n} "
+                      f"particles as neighbours), one full step (neighbours + scatter + "
+                      f"timestep), {reps} run(s) of {dt:.2f} s each"}
+
+
+def copy_probe(mib: int) -> None:
+    """A plain copy of known size: its read and write bytes are exactly
+    mib MiB each, which scales the counters of the other kernels."""
+    import torch
+    torch.cuda.set_device(0)
+    n = mib * (1 << 20) // 8
+    src = torch.arange(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms = []
+    for _ in range(3):
+        ev[0].record()
+        dst.copy_(src)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    assert bool(torch.equal(dst, src))
+    print(json.dumps({"copy_probe_mib": mib, "bytes_read": n * 8, "bytes_written": n * 8,
+                      "ms": ms, "gbs": 2 * n * 8 / (min(ms) * 1e-3) / 1e9}))
 
 
 def main():
@@ -86,14 +123,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="per-kernel HBM traffic measured with rocprofv3 counters")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times "
+                         "(calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     import torch
-    from paper_2607_05504_amd import Context, runner
+    from paper_2607_05504_amd import Context, profsum, runner
 
     torch.cuda.set_device(0)
     w, desc = make_workload(args.workload)
@@ -146,7 +189,8 @@ def main():
         try:
             tr = json.load(open(args.traffic))
             ent = tr.get(args.workload, {}).get(dom)
-            if ent:
+            # a figure taken on another version of the kernel source is stale
+            if ent and ent.get("source") == profsum.source_hash():
                 traffic = ent.get("bytes_per_launch")
         except Exception:
             traffic = None
