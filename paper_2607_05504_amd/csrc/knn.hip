@@ -15,13 +15,16 @@
 //              leaves that meet its own sphere.
 //
 //  k_knn_team  a team of 16 lanes per target, four targets per wavefront.  The
-//              team loads the gaps of its whole leaf list at once and takes the
-//              leaves nearest first until the nearest left lies beyond the
-//              current radius; a leaf's particles are tested 16 at a time
-//              (coalesced) and those within the radius are appended to a short
-//              LDS list.  When the list fills it is sorted (register bitonic
-//              network, E keys per lane) and cut back to N_ngb+1, which
-//              tightens the radius.  A target whose list overflowed walks the
+//              team keys its leaf list by gap (FP32 rounded down, packed with
+//              the leaf index into one 64-bit word) and takes the leaves
+//              nearest first until the nearest left lies beyond the current
+//              radius.  A leaf's 32 particles are tested at once (two per
+//              lane), with the next leaf's positions already requested; those
+//              within the radius are appended to an LDS list of 16*E.  When it
+//              fills, the list is sorted on r^2 (register bitonic network, E
+//              keys per lane; runs of equal r^2 are then placed by ID) and cut
+//              back to N_ngb+1, which tightens the radius.  A target whose list
+//              overflowed, or whose wavefront gave up its group walk, walks the
 //              tree from the root instead (same loop).
 //
 // Pruning is exact-conservative: a box gap is computed with the same rounded
@@ -194,6 +197,7 @@ __device__ __forceinline__ double window_bound(const KnnArgs &A, int64_t i, int6
 constexpr int kStackA = SIDM_MAX_LEVELS * (SIDM_TREE_FAN - 1) + 1;
 
 constexpr int kFront = 512;               // frontier capacity of the level walk
+constexpr int kLeafHits = 640;            // leaves a wavefront tests before its targets walk alone
 
 __device__ __forceinline__ double wave_min(double v)
 {
@@ -213,6 +217,79 @@ __device__ __forceinline__ bool interval_meets(double lo, double hi, double glo,
     bool m = hi >= glo && lo <= ghi;
     if (PERIODIC) m = m || (hi - box >= glo && lo - box <= ghi) || (hi + box >= glo && lo + box <= ghi);
     return m;
+}
+
+// Level-synchronous walk of the tree for the lanes with member set, against
+// the box enclosing their spheres: every round tests up to 64 children (one
+// per lane, one coalesced load); surviving internal nodes form the next
+// frontier, surviving leaves are offered to each member's own sphere and
+// appended to its list.  Returns true if the walk gave up (frontier or leaf
+// count too large), in which case the members' lists are incomplete.
+template <bool PERIODIC>
+__device__ __forceinline__ bool group_walk(const KnnArgs &A, int32_t (&s_fr)[2][kFront],
+                                           double *s_hit, bool member, double px, double py,
+                                           double pz, double T, double R, int32_t *lst, int &nl,
+                                           bool &ovf)
+{
+    const int lane = threadIdx.x;
+    const double box = A.box;
+    const double gxl = wave_min(member ? px - R : INFINITY), gxh = wave_max(member ? px + R : -INFINITY);
+    const double gyl = wave_min(member ? py - R : INFINITY), gyh = wave_max(member ? py + R : -INFINITY);
+    const double gzl = wave_min(member ? pz - R : INFINITY), gzh = wave_max(member ? pz + R : -INFINITY);
+    int cur = 0, fn = 1, hits = 0;
+    wave_sync();
+    if (lane == 0) s_fr[0][0] = 0;                    // the root (top level, index 0)
+    for (int lvl = A.lv.nlev - 1; lvl > 0; --lvl) {
+        const int cl = lvl - 1;
+        const int64_t ccnt = A.lv.cnt[cl], coff = A.lv.off[cl];
+        int nxt = 0;
+        const int total = fn * SIDM_TREE_FAN;
+        for (int c0 = 0; c0 < total; c0 += 64) {
+            const int t = c0 + lane;
+            bool hit = false;
+            int64_t q = 0;
+            double bx[6];
+            wave_sync();
+            if (t < total) {
+                q = (int64_t)s_fr[cur][t / SIDM_TREE_FAN] * SIDM_TREE_FAN + t % SIDM_TREE_FAN;
+                if (q < ccnt) {
+                    const double *nb = A.nodes + (coff + q) * 6;
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) bx[d] = nb[d];
+                    hit = bx[0] <= bx[3] && interval_meets<PERIODIC>(bx[0], bx[3], gxl, gxh, box) &&
+                          interval_meets<PERIODIC>(bx[1], bx[4], gyl, gyh, box) &&
+                          interval_meets<PERIODIC>(bx[2], bx[5], gzl, gzh, box);
+                }
+            }
+            const uint64_t m = __ballot(hit);
+            const int rank = __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+            const int nh = __popcll(m);
+            if (cl > 0) {
+                if (nxt + nh > kFront) return true;
+                if (hit) s_fr[cur ^ 1][nxt + rank] = (int32_t)q;
+                nxt += nh;
+            } else {
+                hits += nh;
+                if (hits > kLeafHits) return true;
+                if (hit) {
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) s_hit[rank * 6 + d] = bx[d];
+                    s_fr[cur ^ 1][rank] = (int32_t)q;
+                }
+                wave_sync();
+                for (int h = 0; h < nh; ++h) {
+                    const double g = box_gap2<PERIODIC>(s_hit + h * 6, px, py, pz, box);
+                    if (member && g <= T) {
+                        if (nl < SIDM_KNN_LMAX) lst[nl++] = s_fr[cur ^ 1][h];
+                        else ovf = true;
+                    }
+                }
+            }
+        }
+        cur ^= 1;
+        fn = nxt;
+    }
+    return false;
 }
 
 template <bool PERIODIC, int W>
@@ -241,73 +318,18 @@ __global__ __launch_bounds__(64) void k_knn_list(KnnArgs A, int64_t base)
     const double T = fmin(window_bound<PERIODIC, W>(A, i, wl, px, py, pz, K1),
                           window_bound<PERIODIC, W>(A, i, wr, px, py, pz, K1));
 
-    // group box: every lane's sphere, padded far beyond rounding, so a box a
-    // lane needs always meets it
+    // sphere radius padded far beyond rounding, so a box a lane needs always
+    // meets the group box
     const double R = sqrt(T) * (1.0 + 1e-9) + (fabs(px) + fabs(py) + fabs(pz) + box) * 1e-14;
-    const double gxl = wave_min(valid ? px - R : INFINITY), gxh = wave_max(valid ? px + R : -INFINITY);
-    const double gyl = wave_min(valid ? py - R : INFINITY), gyh = wave_max(valid ? py + R : -INFINITY);
-    const double gzl = wave_min(valid ? pz - R : INFINITY), gzh = wave_max(valid ? pz + R : -INFINITY);
-
-    // level-synchronous walk: every round tests up to 64 children (one per
-    // lane, one coalesced load); surviving internal nodes form the next
-    // frontier, surviving leaves are offered to each lane's own sphere
     int32_t *lst = A.list + bb * SIDM_KNN_LMAX;
     int nl = 0;
-    bool ovf = false, wave_ovf = false;
-    int cur = 0, fn = 1;
-    s_fr[0][0] = 0;                                   // the root (top level, index 0)
-    for (int lvl = A.lv.nlev - 1; lvl > 0 && !wave_ovf; --lvl) {
-        const int cl = lvl - 1;
-        const int64_t ccnt = A.lv.cnt[cl], coff = A.lv.off[cl];
-        int nxt = 0;
-        const int total = fn * SIDM_TREE_FAN;
-        for (int c0 = 0; c0 < total; c0 += 64) {
-            const int t = c0 + lane;
-            bool hit = false;
-            int64_t q = 0;
-            double bx[6];
-            wave_sync();
-            if (t < total) {
-                q = (int64_t)s_fr[cur][t / SIDM_TREE_FAN] * SIDM_TREE_FAN + t % SIDM_TREE_FAN;
-                if (q < ccnt) {
-                    const double *nb = A.nodes + (coff + q) * 6;
-#pragma unroll
-                    for (int d = 0; d < 6; ++d) bx[d] = nb[d];
-                    hit = bx[0] <= bx[3] && interval_meets<PERIODIC>(bx[0], bx[3], gxl, gxh, box) &&
-                          interval_meets<PERIODIC>(bx[1], bx[4], gyl, gyh, box) &&
-                          interval_meets<PERIODIC>(bx[2], bx[5], gzl, gzh, box);
-                }
-            }
-            const uint64_t m = __ballot(hit);
-            const int rank = __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-            const int nh = __popcll(m);
-            if (cl > 0) {
-                if (nxt + nh > kFront) { wave_ovf = true; break; }
-                if (hit) s_fr[cur ^ 1][nxt + rank] = (int32_t)q;
-                nxt += nh;
-            } else {
-                // leaves: stage the hit boxes, then each lane keeps the ones
-                // within its own sphere
-                if (hit) {
-#pragma unroll
-                    for (int d = 0; d < 6; ++d) s_hit[rank * 6 + d] = bx[d];
-                    s_fr[cur ^ 1][rank] = (int32_t)q;
-                }
-                wave_sync();
-                for (int h = 0; h < nh; ++h) {
-                    const double g = box_gap2<PERIODIC>(s_hit + h * 6, px, py, pz, box);
-                    if (valid && g <= T) {
-                        if (nl < SIDM_KNN_LMAX) lst[nl++] = s_fr[cur ^ 1][h];
-                        else ovf = true;
-                    }
-                }
-            }
-        }
-        cur ^= 1;
-        fn = nxt;
-    }
+    bool ovf = false;
+    // targets spread far apart (a jump of the Morton curve) would make the
+    // group walk too long: then they walk the tree one by one in the second
+    // kernel
+    if (group_walk<PERIODIC>(A, s_fr, s_hit, valid, px, py, pz, T, R, lst, nl, ovf)) ovf = true;
     if (!valid) return;
-    A.nl[bb] = (ovf || wave_ovf) ? -1 : nl;
+    A.nl[bb] = ovf ? -1 : nl;
     A.tb[bb] = T;
 }
 
@@ -384,13 +406,137 @@ __device__ __forceinline__ void team_sort(double (&r)[E], uint32_t (&id)[E], int
 
 constexpr int kStackB = 7 * 9 + 1;       // deepest walk: 10 levels (n < 2^31) of 8-ary nodes
 
+// One compare-exchange stage on r^2 alone (payload jj), same layout as
+// bitonic_stage.  Equal keys are left in place, so no payload is duplicated.
+template <int E, int LK, int LD>
+__device__ __forceinline__ void rstage(double (&r)[E], int32_t (&jj)[E], int tl)
+{
+    constexpr int k = 1 << LK, d = 1 << LD;
+    if constexpr (d < E) {
+#pragma unroll
+        for (int a = 0; a < E; ++a) {
+            const int bq = a ^ d;
+            if (bq > a) {
+                const bool up = (((tl * E + a) & k) == 0);
+                const double ra = r[a], rb = r[bq];
+                const bool sw = up ? (rb < ra) : (ra < rb);
+                const int32_t ja = jj[a], jb = jj[bq];
+                r[a] = sw ? rb : ra; r[bq] = sw ? ra : rb;
+                jj[a] = sw ? jb : ja; jj[bq] = sw ? ja : jb;
+            }
+        }
+    } else {
+        constexpr int ld = d / E;
+        const bool lower = (tl & ld) == 0;
+#pragma unroll
+        for (int a = 0; a < E; ++a) {
+            const double orr = __shfl_xor(r[a], ld);
+            const int32_t oj = __shfl_xor(jj[a], ld);
+            const bool up = (((tl * E + a) & k) == 0);
+            const bool take = (lower == up) ? (orr < r[a]) : (r[a] < orr);
+            r[a] = take ? orr : r[a];
+            jj[a] = take ? oj : jj[a];
+        }
+    }
+}
+
+template <int E, int LK, int LD>
+__device__ __forceinline__ void rmerge_steps(double (&r)[E], int32_t (&jj)[E], int tl)
+{
+    rstage<E, LK, LD>(r, jj, tl);
+    if constexpr (LD > 0) rmerge_steps<E, LK, LD - 1>(r, jj, tl);
+}
+
+template <int E, int LK, int LOGN>
+__device__ __forceinline__ void rlevels(double (&r)[E], int32_t (&jj)[E], int tl)
+{
+    rmerge_steps<E, LK, LK - 1>(r, jj, tl);
+    if constexpr (LK < LOGN) rlevels<E, LK + 1, LOGN>(r, jj, tl);
+}
+
+template <int E>
+__device__ __forceinline__ void team_sort_r2(double (&r)[E], int32_t (&jj)[E], int tl)
+{
+    constexpr int LOGN = (E == 4) ? 6 : 7;
+    rlevels<E, 1, LOGN>(r, jj, tl);
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
+{
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Nearest remaining leaf of the team's list: keys are (gap rounded down to
+// FP32, leaf) packed so that one 64-bit minimum orders them; the key taken is
+// retired.  Returns -1 once the nearest remaining gap exceeds T (then every
+// remaining gap does, since the rounded gaps never exceed the exact ones).
+template <int KP>
+__device__ __forceinline__ int32_t pick_nearest(uint64_t (&lk)[KP], double T)
+{
+    uint64_t m = lk[0];
+#pragma unroll
+    for (int q = 1; q < KP; ++q) m = lk[q] < m ? lk[q] : m;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+        const uint64_t o = shfl_xor_u64(m, off);
+        m = o < m ? o : m;
+    }
+    if (m == ~0ull) return -1;
+#pragma unroll
+    for (int q = 0; q < KP; ++q)
+        if (lk[q] == m) lk[q] = ~0ull;
+    const float gf = __uint_as_float((uint32_t)(m >> 32));
+    if ((double)gf > T) return -1;
+    return (int32_t)(uint32_t)m;
+}
+
+// Next leaf of a root walk (targets whose list overflowed): pops the LDS
+// stack, pushing the children within T nearest on top; -1 when empty.
+template <bool PERIODIC>
+__device__ __forceinline__ int32_t walk_next(const KnnArgs &A, int32_t *stk, int &sp, double T,
+                                             double px, double py, double pz, int tl, int wteam)
+{
+    const double box = A.box;
+    while (sp > 0) {
+        --sp;
+        const int32_t e = stk[sp];
+        const int lvl = e >> SIDM_LEVEL_SHIFT;
+        const int64_t q = e & kIdxMask;
+        const double d2 = node_gap2<PERIODIC>(A.nodes, A.lv.off[lvl] + q, px, py, pz, box);
+        if (!(d2 <= T)) continue;
+        if (lvl == 0) return (int32_t)q;
+        const int cl = lvl - 1;
+        const int64_t cq = q * SIDM_TREE_FAN + tl;
+        double gc = INFINITY;
+        if (tl < SIDM_TREE_FAN && cq < A.lv.cnt[cl])
+            gc = node_gap2<PERIODIC>(A.nodes, A.lv.off[cl] + cq, px, py, pz, box);
+        const bool ok = gc <= T && gc < INFINITY;
+        int rank = 0;
+#pragma unroll
+        for (int s2 = 0; s2 < SIDM_TREE_FAN; ++s2) {
+            const double go = __shfl(gc, s2, 16);
+            const bool oo = go <= T && go < INFINITY;
+            rank += oo && (go < gc || (go == gc && s2 < tl));
+        }
+        const uint64_t m = (__ballot(ok) >> (wteam * 16)) & 0xffffull;
+        const int np = __popcll(m);
+        wave_sync();
+        if (ok) stk[sp + np - 1 - rank] = (cl << SIDM_LEVEL_SHIFT) | (int32_t)cq;
+        sp += np;
+        wave_sync();
+    }
+    return -1;
+}
+
 template <bool PERIODIC, int E>
 __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
 {
     constexpr int N = 16 * E;                 // list capacity
+    constexpr int KP = (SIDM_KNN_LMAX + 15) / 16;
     __shared__ int32_t s_stack[16][kStackB];  // only the overflow walk uses it
     __shared__ double s_r2[16][N];
-    __shared__ uint32_t s_id[16][N];
     __shared__ int32_t s_j[16][N];
 
     const int team = threadIdx.x >> 4, tl = threadIdx.x & 15;
@@ -404,15 +550,12 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
     const double box = A.box;
     const int64_t n = A.n;
     const int K1 = A.k + 1;
-    const uint32_t *__restrict__ ids = A.ids;
     double *L_r2 = s_r2[team];
-    uint32_t *L_id = s_id[team];
     int32_t *L_j = s_j[team];
     int32_t *stk = s_stack[team];
+    const uint64_t below = (tl == 0) ? 0ull : ((1ull << tl) - 1ull);
 
-    // leaves come from the target's list (nearest first), read 16 at a time
-    // with one lane per leaf box; a target whose list overflowed walks the
-    // tree from the root with a stack (packed (level << SIDM_LEVEL_SHIFT) | index)
+    // the leaf list of the first kernel, or a walk from the root if it overflowed
     const int nl = A.nl[bb];
     const int32_t *lst = A.list + bb * SIDM_KNN_LMAX;
     const bool walk = nl < 0;
@@ -421,149 +564,131 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
         if (tl == 0) stk[0] = (A.lv.nlev - 1) << SIDM_LEVEL_SHIFT;
         sp = 1;
     }
-    // gaps of the whole list (one round of loads); leaves are then taken
-    // nearest first, and the walk ends when the nearest left is beyond T
-    constexpr int kPer = (SIDM_KNN_LMAX + 15) / 16;
-    double lg[kPer];
-    int32_t lf[kPer];
+    uint64_t lk[KP];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
+    for (int q = 0; q < KP; ++q) {
         const int t = q * 16 + tl;
-        lf[q] = (!walk && t < nl) ? lst[t] : -1;
-        lg[q] = lf[q] >= 0 ? node_gap2<PERIODIC>(A.nodes, lf[q], px, py, pz, box) : INFINITY;
+        lk[q] = ~0ull;
+        if (!walk && t < nl) {
+            const int32_t leaf = lst[t];
+            const double g = node_gap2<PERIODIC>(A.nodes, leaf, px, py, pz, box);
+            lk[q] = ((uint64_t)__float_as_uint(__double2float_rd(g)) << 32) | (uint32_t)leaf;
+        }
     }
-
     double T = A.tb[bb];
-    int count = 0;
-    double r[E];
-    uint32_t id[E];
-    int32_t jj[E];
-    const uint64_t below = (tl == 0) ? 0ull : ((1ull << tl) - 1ull);
-    int64_t cur_s0 = 0;
-    int cur_m = 0, cur_off = 0;
-    double q1x = 0, q1y = 0, q1z = 0, q0x = 0, q0y = 0, q0z = 0;
-    bool done = false, finished = false;
     wave_sync();
+
+    // leaf = 32 particles, two per lane (tl and tl + 16); the next leaf's
+    // positions are requested before the current one is tested.  cur = -2
+    // before the first leaf is picked, -1 once none is left.
+    int32_t cur = -2;
+    double c0x = 0, c0y = 0, c0z = 0, c1x = 0, c1y = 0, c1z = 0;
+    int count = 0;
+    bool finished = false;
+    double r[E];
+    int32_t jj[E];
     while (true) {
+        int32_t nxt = -1;
+        double n0x = 0, n0y = 0, n0z = 0, n1x = 0, n1y = 0, n1z = 0;
+        if (cur != -1) {
+            nxt = walk ? walk_next<PERIODIC>(A, stk, sp, T, px, py, pz, tl, wteam) : pick_nearest<KP>(lk, T);
+            if (nxt >= 0) {
+                const int64_t s0 = (int64_t)nxt * SIDM_LEAF;
+                const int64_t j0 = s0 + tl < n ? s0 + tl : s0, j1 = s0 + 16 + tl < n ? s0 + 16 + tl : s0;
+                n0x = A.xs[j0]; n0y = A.ys[j0]; n0z = A.zs[j0];
+                n1x = A.xs[j1]; n1y = A.ys[j1]; n1z = A.zs[j1];
+            }
+        }
+        if (cur >= 0) {
+            const int64_t s0 = (int64_t)cur * SIDM_LEAF;
+            const int64_t j0 = s0 + tl, j1 = s0 + 16 + tl;
+            const double r0 = sep2_sel<PERIODIC>(px, py, pz, c0x, c0y, c0z, box);
+            const double r1 = sep2_sel<PERIODIC>(px, py, pz, c1x, c1y, c1z, box);
+            const bool p0 = j0 < n && r0 <= T && j0 != i;
+            const bool p1 = j1 < n && r1 <= T && j1 != i;
+            const uint64_t m0 = (__ballot(p0) >> (wteam * 16)) & 0xffffull;
+            const uint64_t m1 = (__ballot(p1) >> (wteam * 16)) & 0xffffull;
+            const int c0 = __popcll(m0);
+            if (p0) {
+                const int pos = count + __popcll(m0 & below);
+                L_r2[pos] = r0;
+                L_j[pos] = (int32_t)j0;
+            }
+            if (p1) {
+                const int pos = count + c0 + __popcll(m1 & below);
+                L_r2[pos] = r1;
+                L_j[pos] = (int32_t)j1;
+            }
+            count += c0 + __popcll(m1);
+        }
         // the teams of a wavefront sort together whenever one of them must
         // (sorting is idempotent), so the network runs once for all four
-        const bool want = !finished && (done || count + 16 > N);
-        if (__any(want) && !finished) {
-            // sort the list, keep the best K1, tighten the radius
-            wave_sync();
+        const bool done = cur == -1;
+        const bool want = !finished && (done || count + 32 > N);
+        if (__any(want)) {
+            if (!finished) {
+                wave_sync();
 #pragma unroll
-            for (int q = 0; q < E; ++q) {
-                const int e = tl * E + q;
-                if (e < count) { r[q] = L_r2[e]; id[q] = L_id[e]; jj[q] = L_j[e]; }
-                else { r[q] = INFINITY; id[q] = 0xffffffffu; jj[q] = -1; }
-            }
-            team_sort<E>(r, id, jj, tl);
-            wave_sync();
+                for (int q = 0; q < E; ++q) {
+                    const int e = tl * E + q;
+                    if (e < count) { r[q] = L_r2[e]; jj[q] = L_j[e]; }
+                    else { r[q] = INFINITY; jj[q] = -1; }
+                }
+                team_sort_r2<E>(r, jj, tl);
+                // equal r^2 within the first K1 places: order those by ID
+                // (exact ties, e.g. on a lattice; sorting on the full key)
+                const double nx0 = __shfl(r[0], (tl + 1) & 15, 16);
+                bool tie = false;
 #pragma unroll
-            for (int q = 0; q < E; ++q) {
-                const int e = tl * E + q;
-                if (e < K1) { L_r2[e] = r[q]; L_id[e] = id[q]; L_j[e] = jj[q]; }
+                for (int q = 0; q < E; ++q) {
+                    const int e = tl * E + q;
+                    const double nv = q + 1 < E ? r[q + 1] : nx0;
+                    tie = tie || (e < K1 && e + 1 < count && tl * E + q + 1 < N && r[q] == nv);
+                }
+                wave_sync();
+                if ((__ballot(tie) >> (wteam * 16)) & 0xffffull) {
+                    // rare: place each element of a run of equal r^2 by its
+                    // rank in (ID, index) within the run
+#pragma unroll
+                    for (int q = 0; q < E; ++q) { L_r2[tl * E + q] = r[q]; L_j[tl * E + q] = jj[q]; }
+                    wave_sync();
+                    int np[E];
+                    for (int q = 0; q < E; ++q) {
+                        const int e = tl * E + q;
+                        np[q] = e;
+                        if (!(r[q] < INFINITY)) continue;
+                        int rs = e, re = e + 1;
+                        while (rs > 0 && L_r2[rs - 1] == r[q]) --rs;
+                        while (re < N && L_r2[re] == r[q]) ++re;
+                        if (re - rs == 1) continue;
+                        const uint32_t mid = A.ids[jj[q]];
+                        int rank = rs;
+                        for (int f = rs; f < re; ++f) {
+                            const int32_t jf = L_j[f];
+                            const uint32_t idf = A.ids[jf];
+                            rank += (idf < mid) || (idf == mid && jf < jj[q]);
+                        }
+                        np[q] = rank;
+                    }
+                    wave_sync();
+                    for (int q = 0; q < E; ++q)
+                        if (np[q] < K1) { L_r2[np[q]] = r[q]; L_j[np[q]] = jj[q]; }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < E; ++q) {
+                        const int e = tl * E + q;
+                        if (e < K1) { L_r2[e] = r[q]; L_j[e] = jj[q]; }
+                    }
+                }
+                wave_sync();
+                if (count >= K1) T = L_r2[K1 - 1];
+                count = count < K1 ? count : K1;
             }
-            wave_sync();
-            if (count >= K1) T = L_r2[K1 - 1];
-            count = count < K1 ? count : K1;
             if (done) finished = true;
         }
         if (__all(finished)) break;
-        if (finished) continue;
-        if (cur_off >= cur_m) {
-            // next leaf within the radius
-            cur_m = 0;
-            cur_off = 0;
-            while (true) {
-                if (!walk) {
-                    // team argmin over (gap, lane, slot)
-                    double bg = INFINITY;
-                    int bq = 0;
-#pragma unroll
-                    for (int q = 0; q < kPer; ++q)
-                        if (lg[q] < bg) { bg = lg[q]; bq = q; }
-                    int bl = tl;
-                    for (int off = 1; off < 16; off <<= 1) {
-                        const double og = __shfl_xor(bg, off);
-                        const int ol = __shfl_xor(bl, off), oq = __shfl_xor(bq, off);
-                        if (og < bg || (og == bg && ol < bl)) { bg = og; bl = ol; bq = oq; }
-                    }
-                    if (!(bg <= T)) break;
-                    int32_t leaf = -1;
-#pragma unroll
-                    for (int q = 0; q < kPer; ++q)
-                        if (q == bq) leaf = lf[q];
-                    leaf = __shfl(leaf, bl, 16);
-                    if (tl == bl) {
-#pragma unroll
-                        for (int q = 0; q < kPer; ++q)
-                            if (q == bq) lg[q] = INFINITY;
-                    }
-                    cur_s0 = (int64_t)leaf * SIDM_LEAF;
-                } else {
-                    if (sp == 0) break;
-                    --sp;
-                    const int32_t e = stk[sp];
-                    const int lvl = e >> SIDM_LEVEL_SHIFT;
-                    const int64_t q = e & kIdxMask;
-                    const double d2 = node_gap2<PERIODIC>(A.nodes, A.lv.off[lvl] + q, px, py, pz, box);
-                    if (!(d2 <= T)) continue;
-                    if (lvl > 0) {
-                        // push the children within the radius, nearest on top
-                        const int cl = lvl - 1;
-                        const int64_t cq = q * SIDM_TREE_FAN + tl;
-                        double gc = INFINITY;
-                        if (tl < SIDM_TREE_FAN && cq < A.lv.cnt[cl])
-                            gc = node_gap2<PERIODIC>(A.nodes, A.lv.off[cl] + cq, px, py, pz, box);
-                        const bool ok = gc <= T && gc < INFINITY;
-                        int rank = 0;
-#pragma unroll
-                        for (int s2 = 0; s2 < SIDM_TREE_FAN; ++s2) {
-                            const double go = __shfl(gc, s2, 16);
-                            const bool oo = go <= T && go < INFINITY;
-                            rank += oo && (go < gc || (go == gc && s2 < tl));
-                        }
-                        const uint64_t m = (__ballot(ok) >> (wteam * 16)) & 0xffffull;
-                        const int np = __popcll(m);
-                        wave_sync();
-                        if (ok) stk[sp + np - 1 - rank] = (cl << SIDM_LEVEL_SHIFT) | (int32_t)cq;
-                        sp += np;
-                        wave_sync();
-                        continue;
-                    }
-                    cur_s0 = q * SIDM_LEAF;
-                }
-                cur_m = (int)((n - cur_s0) < SIDM_LEAF ? (n - cur_s0) : SIDM_LEAF);
-                // both 16-particle halves of the leaf in one round of loads
-                const int64_t j0 = cur_s0 + (tl < cur_m ? tl : 0);
-                const int64_t j1 = cur_s0 + (tl + 16 < cur_m ? tl + 16 : 0);
-                q0x = A.xs[j0]; q0y = A.ys[j0]; q0z = A.zs[j0];
-                q1x = A.xs[j1]; q1y = A.ys[j1]; q1z = A.zs[j1];
-                break;
-            }
-            if (cur_m == 0) { done = true; continue; }
-        }
-        // 16 particles of the current leaf
-        const int c = cur_off + tl;
-        const int64_t j = cur_s0 + c;
-        const bool first = cur_off == 0;
-        bool pass = false;
-        double r2 = 0.0;
-        if (c < cur_m) {
-            r2 = sep2_sel<PERIODIC>(px, py, pz, first ? q0x : q1x, first ? q0y : q1y,
-                                    first ? q0z : q1z, box);
-            pass = r2 <= T && j != i;
-        }
-        const uint64_t mask = (__ballot(pass) >> (wteam * 16)) & 0xffffull;
-        if (pass) {
-            const int pos = count + __popcll(mask & below);
-            L_r2[pos] = r2;
-            L_id[pos] = ids[j];
-            L_j[pos] = (int32_t)j;
-        }
-        count += __popcll(mask);
-        cur_off += 16;
+        cur = nxt;
+        c0x = n0x; c0y = n0y; c0z = n0z; c1x = n1x; c1y = n1y; c1z = n1z;
     }
 
     const int32_t a = A.slot[b];
@@ -582,7 +707,7 @@ void launch_batches(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipStre
     for (int64_t base = 0; base < n_active; base += nb_cap) {
         KnnArgs A = A0;
         A.batch = (n_active - base) < nb_cap ? (n_active - base) : nb_cap;
-        k_knn_list<P, 16 * E><<<(unsigned)((A.batch + 63) / 64), 64, 0, s>>>(A, base);
+        k_knn_list<P, 64><<<(unsigned)((A.batch + 63) / 64), 64, 0, s>>>(A, base);
         k_knn_team<P, E><<<(unsigned)((A.batch + 15) / 16), 256, 0, s>>>(A, base);
     }
 }
@@ -602,7 +727,7 @@ hipError_t launch_knn(sidm_ctx *c, int64_t n_active, int32_t *ngb, double *h)
     const bool per = c->cfg.periodic != 0;
     const int k1 = A.k + 1;
     phase_begin(c, PH_KNN);
-    if (k1 + 16 <= 64) {
+    if (k1 + 32 <= 64) {
         per ? launch_batches<true, 4>(A, n_active, c->knn_batch, c->stream)
             : launch_batches<false, 4>(A, n_active, c->knn_batch, c->stream);
     } else {
