@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="hernquist1e6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+                    help="mixed: FP32 neighbour test and probabilities on leaf-relative "
+                         "offsets with FP64 rechecks in the bands, FP64 kicks")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="per-kernel HBM traffic measured with rocprofv3 counters")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -136,12 +139,12 @@ def main():
         return
 
     import torch
-    from paper_2607_05504_amd import Context, profsum, runner
+    from paper_2607_05504_amd import FP64, MIXED, Context, profsum, runner
 
     torch.cuda.set_device(0)
     w, desc = make_workload(args.workload)
     ds = runner.upload(w, "cuda:0")
-    cfg = runner.config_for(w)
+    cfg = runner.config_for(w, precision=MIXED if args.precision == "mixed" else FP64)
     ctx = Context(cfg, w.n, w.n_active)
     out = runner.alloc_out(ds, w.n_ngb)
     print(f"[bench] workload {args.workload}: n={w.n} active={w.n_active}", file=sys.stderr,
@@ -188,7 +191,8 @@ def main():
     if os.path.exists(args.traffic):
         try:
             tr = json.load(open(args.traffic))
-            ent = tr.get(args.workload, {}).get(dom)
+            key = args.workload if args.precision == "fp64" else args.workload + ":mixed"
+            ent = tr.get(key, {}).get(dom)
             # a figure taken on another version of the kernel source is stale
             if ent and ent.get("source") == profsum.source_hash():
                 traffic = ent.get("bytes_per_launch")
@@ -202,10 +206,11 @@ def main():
     res = {
         "metric": METRIC, "value": value, "unit": "active particles/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": w.n, "n_active": na,
-                   "n_ngb": k, "precision": "fp64", "touched": n_t},
+                   "n_ngb": k, "precision": args.precision, "touched": n_t},
         "p50_step_ms": float(np.percentile(step_ms, 50)),
         "p99_step_ms": float(np.percentile(step_ms, 99)),
         "phase_ms": {kk: round(v, 5) for kk, v in tim.items() if kk.endswith("_ms")},

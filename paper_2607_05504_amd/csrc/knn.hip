@@ -52,6 +52,8 @@ struct KnnArgs {
     int64_t n, batch;
     int k;
     double box;
+    const float *xo, *yo, *zo;   // mixed form: FP32 offsets from the leaf's box centre
+    double band_r2;              // mixed form: relative widening of the FP32 radius test
 };
 
 constexpr int32_t kIdxMask = (1 << SIDM_LEVEL_SHIFT) - 1;
@@ -530,7 +532,7 @@ __device__ __forceinline__ int32_t walk_next(const KnnArgs &A, int32_t *stk, int
     return -1;
 }
 
-template <bool PERIODIC, int E>
+template <bool PERIODIC, int E, bool MIXED>
 __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
 {
     constexpr int N = 16 * E;                 // list capacity
@@ -583,6 +585,14 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
     // before the first leaf is picked, -1 once none is left.
     int32_t cur = -2;
     double c0x = 0, c0y = 0, c0z = 0, c1x = 0, c1y = 0, c1z = 0;
+    // mixed form: the particles' FP32 offsets and their leaf's box; the test
+    // is in FP32 against a radius widened by band_r2, and the exact FP64 r^2
+    // of the entries that pass is taken when the list is next sorted (kept =
+    // leading entries whose exact r^2 is already in the list)
+    float f0x = 0, f0y = 0, f0z = 0, f1x = 0, f1y = 0, f1z = 0;
+    double cb[6] = {0, 0, 0, 0, 0, 0};
+    const float box32 = (float)box;
+    int kept = 0;
     int count = 0;
     bool finished = false;
     double r[E];
@@ -590,33 +600,65 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
     while (true) {
         int32_t nxt = -1;
         double n0x = 0, n0y = 0, n0z = 0, n1x = 0, n1y = 0, n1z = 0;
+        float g0x = 0, g0y = 0, g0z = 0, g1x = 0, g1y = 0, g1z = 0;
+        double nb6[6] = {0, 0, 0, 0, 0, 0};
         if (cur != -1) {
             nxt = walk ? walk_next<PERIODIC>(A, stk, sp, T, px, py, pz, tl, wteam) : pick_nearest<KP>(lk, T);
             if (nxt >= 0) {
                 const int64_t s0 = (int64_t)nxt * SIDM_LEAF;
                 const int64_t j0 = s0 + tl < n ? s0 + tl : s0, j1 = s0 + 16 + tl < n ? s0 + 16 + tl : s0;
-                n0x = A.xs[j0]; n0y = A.ys[j0]; n0z = A.zs[j0];
-                n1x = A.xs[j1]; n1y = A.ys[j1]; n1z = A.zs[j1];
+                if constexpr (MIXED) {
+                    g0x = A.xo[j0]; g0y = A.yo[j0]; g0z = A.zo[j0];
+                    g1x = A.xo[j1]; g1y = A.yo[j1]; g1z = A.zo[j1];
+                    const double *nb = A.nodes + (int64_t)nxt * 6;
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) nb6[d] = nb[d];
+                } else {
+                    n0x = A.xs[j0]; n0y = A.ys[j0]; n0z = A.zs[j0];
+                    n1x = A.xs[j1]; n1y = A.ys[j1]; n1z = A.zs[j1];
+                }
             }
         }
         if (cur >= 0) {
             const int64_t s0 = (int64_t)cur * SIDM_LEAF;
             const int64_t j0 = s0 + tl, j1 = s0 + 16 + tl;
-            const double r0 = sep2_sel<PERIODIC>(px, py, pz, c0x, c0y, c0z, box);
-            const double r1 = sep2_sel<PERIODIC>(px, py, pz, c1x, c1y, c1z, box);
-            const bool p0 = j0 < n && r0 <= T && j0 != i;
-            const bool p1 = j1 < n && r1 <= T && j1 != i;
+            double r0 = 0.0, r1 = 0.0;
+            bool p0, p1;
+            if constexpr (MIXED) {
+                double dlx = box_centre(cb, 0) - px, dly = box_centre(cb, 1) - py, dlz = box_centre(cb, 2) - pz;
+                if (PERIODIC) {
+                    const double half = 0.5 * box;
+                    dlx = dlx >= half ? dlx - box : (dlx < -half ? dlx + box : dlx);
+                    dly = dly >= half ? dly - box : (dly < -half ? dly + box : dly);
+                    dlz = dlz >= half ? dlz - box : (dlz < -half ? dlz + box : dlz);
+                }
+                const float ex = (float)dlx, ey = (float)dly, ez = (float)dlz;
+                float ax = ex + f0x, ay = ey + f0y, az = ez + f0z;
+                float bx = ex + f1x, by = ey + f1y, bz = ez + f1z;
+                if (PERIODIC) {
+                    ax = wrap32(ax, box32); ay = wrap32(ay, box32); az = wrap32(az, box32);
+                    bx = wrap32(bx, box32); by = wrap32(by, box32); bz = wrap32(bz, box32);
+                }
+                const float T32 = __double2float_ru(T * (1.0 + A.band_r2));
+                p0 = j0 < n && (ax * ax + ay * ay) + az * az <= T32 && j0 != i;
+                p1 = j1 < n && (bx * bx + by * by) + bz * bz <= T32 && j1 != i;
+            } else {
+                r0 = sep2_sel<PERIODIC>(px, py, pz, c0x, c0y, c0z, box);
+                r1 = sep2_sel<PERIODIC>(px, py, pz, c1x, c1y, c1z, box);
+                p0 = j0 < n && r0 <= T && j0 != i;
+                p1 = j1 < n && r1 <= T && j1 != i;
+            }
             const uint64_t m0 = (__ballot(p0) >> (wteam * 16)) & 0xffffull;
             const uint64_t m1 = (__ballot(p1) >> (wteam * 16)) & 0xffffull;
             const int c0 = __popcll(m0);
             if (p0) {
                 const int pos = count + __popcll(m0 & below);
-                L_r2[pos] = r0;
+                if (!MIXED) L_r2[pos] = r0;
                 L_j[pos] = (int32_t)j0;
             }
             if (p1) {
                 const int pos = count + c0 + __popcll(m1 & below);
-                L_r2[pos] = r1;
+                if (!MIXED) L_r2[pos] = r1;
                 L_j[pos] = (int32_t)j1;
             }
             count += c0 + __popcll(m1);
@@ -631,8 +673,15 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
 #pragma unroll
                 for (int q = 0; q < E; ++q) {
                     const int e = tl * E + q;
-                    if (e < count) { r[q] = L_r2[e]; jj[q] = L_j[e]; }
-                    else { r[q] = INFINITY; jj[q] = -1; }
+                    if (e < count) {
+                        jj[q] = L_j[e];
+                        if (MIXED && e >= kept) {
+                            const int32_t j = jj[q];
+                            r[q] = sep2_sel<PERIODIC>(px, py, pz, A.xs[j], A.ys[j], A.zs[j], box);
+                        } else {
+                            r[q] = L_r2[e];
+                        }
+                    } else { r[q] = INFINITY; jj[q] = -1; }
                 }
                 team_sort_r2<E>(r, jj, tl);
                 // equal r^2 within the first K1 places: order those by ID
@@ -683,12 +732,16 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
                 wave_sync();
                 if (count >= K1) T = L_r2[K1 - 1];
                 count = count < K1 ? count : K1;
+                kept = count;
             }
             if (done) finished = true;
         }
         if (__all(finished)) break;
         cur = nxt;
         c0x = n0x; c0y = n0y; c0z = n0z; c1x = n1x; c1y = n1y; c1z = n1z;
+        f0x = g0x; f0y = g0y; f0z = g0z; f1x = g1x; f1y = g1y; f1z = g1z;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) cb[d] = nb6[d];
     }
 
     const int32_t a = A.slot[b];
@@ -701,14 +754,14 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
     for (int e = tl; e < A.k; e += 16) out[e] = A.perm[L_j[e]];
 }
 
-template <bool P, int E>
+template <bool P, int E, bool M>
 void launch_batches(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipStream_t s)
 {
     for (int64_t base = 0; base < n_active; base += nb_cap) {
         KnnArgs A = A0;
         A.batch = (n_active - base) < nb_cap ? (n_active - base) : nb_cap;
         k_knn_list<P, 64><<<(unsigned)((A.batch + 63) / 64), 64, 0, s>>>(A, base);
-        k_knn_team<P, E><<<(unsigned)((A.batch + 15) / 16), 256, 0, s>>>(A, base);
+        k_knn_team<P, E, M><<<(unsigned)((A.batch + 15) / 16), 256, 0, s>>>(A, base);
     }
 }
 
@@ -724,15 +777,22 @@ hipError_t launch_knn(sidm_ctx *c, int64_t n_active, int32_t *ngb, double *h)
     A.list = c->knn_list; A.nl = c->knn_nl; A.tb = c->knn_tb;
     A.lv = c->lv;
     A.n = c->n; A.k = c->cfg.n_ngb; A.box = c->cfg.box; A.batch = 0;
+    A.xo = c->xo; A.yo = c->yo; A.zo = c->zo;
+    A.band_r2 = c->cfg.band_r2;
     const bool per = c->cfg.periodic != 0;
-    const int k1 = A.k + 1;
+    const bool mixed = c->cfg.precision == SIDM_MIXED;
+    const bool small = A.k + 1 + 32 <= 64;       // list of 64 suffices for k <= 31
     phase_begin(c, PH_KNN);
-    if (k1 + 32 <= 64) {
-        per ? launch_batches<true, 4>(A, n_active, c->knn_batch, c->stream)
-            : launch_batches<false, 4>(A, n_active, c->knn_batch, c->stream);
-    } else {
-        per ? launch_batches<true, 8>(A, n_active, c->knn_batch, c->stream)
-            : launch_batches<false, 8>(A, n_active, c->knn_batch, c->stream);
+    const int sel = (per ? 4 : 0) | (small ? 2 : 0) | (mixed ? 1 : 0);
+    switch (sel) {
+    case 0: launch_batches<false, 8, false>(A, n_active, c->knn_batch, c->stream); break;
+    case 1: launch_batches<false, 8, true>(A, n_active, c->knn_batch, c->stream); break;
+    case 2: launch_batches<false, 4, false>(A, n_active, c->knn_batch, c->stream); break;
+    case 3: launch_batches<false, 4, true>(A, n_active, c->knn_batch, c->stream); break;
+    case 4: launch_batches<true, 8, false>(A, n_active, c->knn_batch, c->stream); break;
+    case 5: launch_batches<true, 8, true>(A, n_active, c->knn_batch, c->stream); break;
+    case 6: launch_batches<true, 4, false>(A, n_active, c->knn_batch, c->stream); break;
+    default: launch_batches<true, 4, true>(A, n_active, c->knn_batch, c->stream); break;
     }
     phase_end(c, PH_KNN);
     return hipGetLastError();

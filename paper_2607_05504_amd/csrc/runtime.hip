@@ -50,6 +50,9 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(dtot, 256, uint32_t);
     ADD(bounds, 6, unsigned long long);
     ADD(nodes, tree_node_count(tree_levels(N)) * 6, double);
+    if (c->cfg.precision == SIDM_MIXED) {
+        ADD(xo, N, float); ADD(yo, N, float); ADD(zo, N, float);
+    }
     c->knn_batch = NA < SIDM_KNN_BATCH ? NA : SIDM_KNN_BATCH;
     ADD(knn_list, c->knn_batch * SIDM_KNN_LMAX, int32_t);
     ADD(knn_nl, c->knn_batch, int32_t);

@@ -50,6 +50,11 @@ struct StepArgs {
     unsigned int *derr;
     int64_t n, cap_acc;
     double m_scalar, box, s0, w0, eps, delta, band;
+    // mixed form: FP32 offsets from the leaf box centres, and the relative
+    // |P - u| band inside which an FP32 decision is redone in FP64
+    const float *xo, *yo, *zo;
+    const double *nodes;
+    double band_p;
     uint64_t seed;
     uint32_t step;
     int k, periodic, xsec, model, has_mass;
@@ -184,16 +189,42 @@ __device__ void flush_staged(const StepArgs &A, StagedAcc &S, int n, int32_t &ba
     __syncthreads();
 }
 
-template <bool PERIODIC>
+// FP32 forms of the kernel and cross-section (mixed form)
+__device__ __forceinline__ float cubic_spline32(float r, float h)
+{
+    const float norm = 8.0f / ((float)SIDM_PI * ((h * h) * h));
+    const float q = r / h;
+    if (q <= 0.5f) {
+        const float q2 = q * q;
+        return norm * ((1.0f - 6.0f * q2) + 6.0f * (q2 * q));
+    }
+    if (q <= 1.0f) {
+        const float t = 1.0f - q;
+        return norm * (2.0f * ((t * t) * t));
+    }
+    return 0.0f;
+}
+
+__device__ __forceinline__ float xsec_sigma32(float w, int xsec, float s0, float w0)
+{
+    if (xsec == SIDM_XSEC_YUKAWA) {
+        const float x = w / w0;
+        const float d = 1.0f + x * x;
+        return s0 / (d * d);
+    }
+    return s0;
+}
+
+template <bool PERIODIC, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
 {
     __shared__ StagedAcc S;
     __shared__ int s_n;
     __shared__ int32_t s_base;
-    __shared__ unsigned long long s_red[4][4];
+    __shared__ unsigned long long s_red[4][5];
     const int64_t nt = *A.nt_dev;
     const int64_t total = nt * A.k;
-    unsigned long long maxp = 0, n_fl = 0, n_ge1 = 0, n_acc = 0;
+    unsigned long long maxp = 0, n_fl = 0, n_ge1 = 0, n_acc = 0, n_rc = 0;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
     for (int64_t c0 = blockIdx.x * (int64_t)blockDim.x; c0 < total;
@@ -209,18 +240,55 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                 atomicOr(A.derr, DERR_INDEX);
             } else {
                 const int32_t j = A.inv[jc];
-                const double r = sqrt(sep2<PERIODIC>(A.xs[i], A.ys[i], A.zs[i], A.xs[j], A.ys[j],
-                                                     A.zs[j], A.box));
-                const double W = cubic_spline(r, A.h[a]);
-                const double w = rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
-                const double sig = xsec_sigma(w, A.xsec, A.s0, A.w0);
                 const double dta = A.dt[a];
-                const double P = pair_prob(mass_of(A, j), sig, w, W, dta);
                 const uint32_t idi = A.ids[i], idj = A.ids[j];
                 const Philox4 x = pair_draw(A.seed, A.step, idi, idj, PURPOSE_DECIDE);
                 const double u = unit_from_word(direction_word(x, idi < idj));
+                double P = 0.0, W = 0.0;
+                bool exact = true;
+                if constexpr (MIXED) {
+                    // FP32: separation from the two leaves' box centres plus
+                    // the particles' FP32 offsets; relative speed from the
+                    // FP64 velocity difference rounded to FP32
+                    const double *bi = A.nodes + (int64_t)(i / SIDM_LEAF) * 6;
+                    const double *bj = A.nodes + (int64_t)(j / SIDM_LEAF) * 6;
+                    const float bx = (float)A.box;
+                    float dx = (float)(box_centre(bj, 0) - box_centre(bi, 0)) + (A.xo[j] - A.xo[i]);
+                    float dy = (float)(box_centre(bj, 1) - box_centre(bi, 1)) + (A.yo[j] - A.yo[i]);
+                    float dz = (float)(box_centre(bj, 2) - box_centre(bi, 2)) + (A.zo[j] - A.zo[i]);
+                    if (PERIODIC) { dx = wrap32(dx, bx); dy = wrap32(dy, bx); dz = wrap32(dz, bx); }
+                    const float r32 = sqrtf((dx * dx + dy * dy) + dz * dz);
+                    const float h32 = (float)A.h[a];
+                    const float vx = (float)(A.vxs[i] - A.vxs[j]), vy = (float)(A.vys[i] - A.vys[j]),
+                                vz = (float)(A.vzs[i] - A.vzs[j]);
+                    const float w32 = sqrtf((vx * vx + vy * vy) + vz * vz);
+                    const float s32 = xsec_sigma32(w32, A.xsec, (float)A.s0, (float)A.w0);
+                    const float f = (((0.5f * (float)mass_of(A, j)) * s32) * w32) * (float)dta;
+                    const float P32 = f * cubic_spline32(r32, h32);
+                    // band on the scale of P at the kernel's centre value, so
+                    // the absolute FP32 error of W near its support edge is covered
+                    const float Pmax = f * (8.0f / ((float)SIDM_PI * ((h32 * h32) * h32)));
+                    const double near = A.band_p * fmax((double)Pmax, u) + A.band;
+                    P = (double)P32;
+                    exact = fabs(P - u) <= near;
+                }
+                if (exact) {
+                    const double r = sqrt(sep2<PERIODIC>(A.xs[i], A.ys[i], A.zs[i], A.xs[j], A.ys[j],
+                                                         A.zs[j], A.box));
+                    W = cubic_spline(r, A.h[a]);
+                    const double w = rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
+                    const double sig = xsec_sigma(w, A.xsec, A.s0, A.w0);
+                    P = pair_prob(mass_of(A, j), sig, w, W, dta);
+                    n_rc += MIXED;
+                }
                 const bool acc = u < P;
-                const bool flagged = fabs(P - u) < A.band;
+                const bool flagged = exact && fabs(P - u) < A.band;
+                if (MIXED && acc && !exact) {
+                    // accepted on the FP32 value: the passes need the FP64 W
+                    const double r = sqrt(sep2<PERIODIC>(A.xs[i], A.ys[i], A.zs[i], A.xs[j], A.ys[j],
+                                                         A.zs[j], A.box));
+                    W = cubic_spline(r, A.h[a]);
+                }
                 n_fl += flagged;
                 n_ge1 += P >= 1.0;
                 n_acc += acc;
@@ -255,16 +323,20 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
         n_fl += (unsigned long long)__shfl_xor((long long)n_fl, off);
         n_ge1 += (unsigned long long)__shfl_xor((long long)n_ge1, off);
         n_acc += (unsigned long long)__shfl_xor((long long)n_acc, off);
+        n_rc += (unsigned long long)__shfl_xor((long long)n_rc, off);
     }
     const int w = threadIdx.x >> 6;
-    if (wave_lane() == 0) { s_red[w][0] = maxp; s_red[w][1] = n_fl; s_red[w][2] = n_ge1; s_red[w][3] = n_acc; }
+    if (wave_lane() == 0) {
+        s_red[w][0] = maxp; s_red[w][1] = n_fl; s_red[w][2] = n_ge1; s_red[w][3] = n_acc; s_red[w][4] = n_rc;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long m = 0, f = 0, g = 0, q = 0;
+        unsigned long long m = 0, f = 0, g = 0, q = 0, rc = 0;
         for (int v = 0; v < kBlock / 64; ++v) {
             m = s_red[v][0] > m ? s_red[v][0] : m;
-            f += s_red[v][1]; g += s_red[v][2]; q += s_red[v][3];
+            f += s_red[v][1]; g += s_red[v][2]; q += s_red[v][3]; rc += s_red[v][4];
         }
+        if (rc) atomicAdd(&A.st->n_recheck, rc);
         if (m) atomicMax(&A.st->max_p_bits, m);
         if (f) atomicAdd(&A.st->n_flagged, f);
         if (g) atomicAdd(&A.st->n_p_ge_1, g);
@@ -534,6 +606,7 @@ StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const dou
     A.seed = seed; A.step = step;
     A.k = c->cfg.n_ngb; A.periodic = c->cfg.periodic; A.xsec = c->cfg.xsec;
     A.model = c->cfg.model; A.has_mass = c->has_mass;
+    A.xo = c->xo; A.yo = c->yo; A.zo = c->zo; A.nodes = c->nodes; A.band_p = c->cfg.band_p;
     return A;
 }
 
@@ -544,14 +617,14 @@ int grid_for(int64_t n, int cap = 8192)
     return (int)(g > cap ? cap : g);
 }
 
-template <bool P>
+template <bool P, bool M>
 void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s)
 {
     const int64_t total = n_active * A.k;
     k_step_reset<<<1, 64, 0, s>>>(A.st, A.ctl);
     k_count_cand<<<1, 64, 0, s>>>(A.st, A.nt_dev, A.k);
     phase_begin(c, PH_EVAL);
-    k_eval<P><<<grid_for(total, 2048), kBlock, 0, s>>>(A);
+    k_eval<P, M><<<grid_for(total, 2048), kBlock, 0, s>>>(A);
     phase_end(c, PH_EVAL);
     const int g = grid_for(A.cap_acc < total ? A.cap_acc : total, 2048);
     phase_begin(c, PH_RESOLVE);
@@ -571,8 +644,14 @@ hipError_t launch_scatter(sidm_ctx *c, sidm_particles *p, int64_t n_active, cons
                           uint32_t *cand_info)
 {
     StepArgs A = make_args(c, p, ngb, h, dt, seed, step, cand_info);
-    if (c->cfg.periodic) run_scatter<true>(c, A, n_active, c->stream);
-    else run_scatter<false>(c, A, n_active, c->stream);
+    const bool mixed = c->cfg.precision == SIDM_MIXED;
+    if (c->cfg.periodic) {
+        mixed ? run_scatter<true, true>(c, A, n_active, c->stream)
+              : run_scatter<true, false>(c, A, n_active, c->stream);
+    } else {
+        mixed ? run_scatter<false, true>(c, A, n_active, c->stream)
+              : run_scatter<false, false>(c, A, n_active, c->stream);
+    }
     return hipGetLastError();
 }
 

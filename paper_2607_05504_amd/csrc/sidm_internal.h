@@ -104,6 +104,9 @@ struct sidm_ctx {
     // levels of SIDM_TREE_FAN-ary parents above them, boxes level after level
     TreeLevels lv;
     double *nodes;           // [nodes][6]  lo x,y,z, hi x,y,z
+    // mixed form only: FP32 offsets of each particle from its leaf's box
+    // centre 0.5 (lo + hi), the centre itself rounded as that FP64 expression
+    float *xo, *yo, *zo;
 
     // neighbour search: per-target leaf lists, processed in batches of knn_batch
     int64_t knn_batch;
@@ -274,6 +277,20 @@ hipError_t launch_build_tree(sidm_ctx *c, const sidm_particles *p);
 hipError_t launch_map_active(sidm_ctx *c, const int32_t *active, int64_t n_active);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+
+// FP32 minimum image of an offset already reduced to about [-L, L) (mixed form)
+__device__ __forceinline__ float wrap32(float d, float box)
+{
+    const float half = 0.5f * box;
+    return d >= half ? d - box : (d < -half ? d + box : d);
+}
+
+// centre of a box stored as lo x,y,z, hi x,y,z (the reference point of the
+// FP32 offsets of the mixed form)
+__device__ __forceinline__ double box_centre(const double *b, int d)
+{
+    return 0.5 * (b[d] + b[d + 3]);
+}
 // knn.hip
 hipError_t launch_knn(sidm_ctx *c, int64_t n_active, int32_t *ngb, double *h);
 // scatter.hip

@@ -378,6 +378,22 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+// Mixed form: each particle's offset from its leaf's box centre, in FP32.
+__global__ __launch_bounds__(256) void k_leaf_offsets(int64_t n, const double *__restrict__ xs,
+                                                      const double *__restrict__ ys,
+                                                      const double *__restrict__ zs,
+                                                      const double *__restrict__ nodes, float *xo,
+                                                      float *yo, float *zo)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const double *b = nodes + (j / SIDM_LEAF) * 6;
+        xo[j] = (float)(xs[j] - box_centre(b, 0));
+        yo[j] = (float)(ys[j] - box_centre(b, 1));
+        zo[j] = (float)(zs[j] - box_centre(b, 2));
+    }
+}
+
 hipError_t launch_build_tree(sidm_ctx *c, const sidm_particles *p)
 {
     hipStream_t s = c->stream;
@@ -414,6 +430,9 @@ hipError_t launch_build_tree(sidm_ctx *c, const sidm_particles *p)
     for (int l = 1; l < lv.nlev; ++l)
         k_level_boxes<<<(unsigned)((lv.cnt[l] + 255) / 256), 256, 0, s>>>(
             c->nodes, lv.off[l - 1], lv.cnt[l - 1], lv.off[l], lv.cnt[l]);
+    if (cfg.precision == SIDM_MIXED)
+        k_leaf_offsets<<<grid_for(n), kBlock, 0, s>>>(n, c->xs, c->ys, c->zs, c->nodes, c->xo,
+                                                      c->yo, c->zo);
     return hipGetLastError();
 }
 

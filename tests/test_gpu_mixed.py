@@ -1,0 +1,109 @@
+"""The mixed-precision form (FP32 neighbour test and probabilities on
+leaf-relative offsets, FP64 recheck inside the bands, FP64 kicks) against the
+oracle and against the plain FP64 form on the GPU."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_05504_amd as sidm
+    sidm.lib()
+
+
+from gpu_helpers import gpu_step, assert_parity  # noqa: E402
+from paper_2607_05504_amd import MIXED  # noqa: E402
+
+
+def _announce(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _small_halo(n, two_state=False):
+    h = W.hernquist_halo(n, ic_seed=202, philox_seed=12, two_state=two_state)
+    return W.hernquist_bins(h, active_frac=0.25)
+
+
+@pytest.mark.parametrize("case", ["uniform32k", "halo20k", "two_state20k", "ragged_periodic",
+                                  "ragged_open", "lattice8"])
+def test_mixed_with_bands_equals_oracle(case):
+    """With the default bands (1e-5 relative) every FP32 decision that could
+    differ from FP64 is redone in FP64: results identical to the oracle."""
+    if case == "uniform32k":
+        w = W.uniform_box(32768)
+    elif case == "halo20k":
+        w = _small_halo(20000)
+    elif case == "two_state20k":
+        w = _small_halo(20000, two_state=True)
+    elif case == "ragged_periodic":
+        w = W.uniform_box(5003, ic_seed=31, scatters_per_particle=0.3).subset_active(4097)
+    elif case == "ragged_open":
+        w = _small_halo(2049)
+    else:
+        w = W.uniform_box(512, lattice=True, scatters_per_particle=0.5)
+    _announce(f"mixed {case} n={w.n} active={w.n_active}")
+    ref = oracle.full_step(w)
+    g = gpu_step(w, precision=MIXED)
+    assert_parity(w, g, ref, mixed=True)
+
+
+def _energy_momentum(w, g):
+    v2 = g["vx"] ** 2 + g["vy"] ** 2 + g["vz"] ** 2
+    e = 0.5 * w.mass * v2.sum() + w.mass * w.delta * g["state"].astype(np.float64).sum()
+    p = w.mass * np.array([g["vx"].sum(), g["vy"].sum(), g["vz"].sum()])
+    return e, p
+
+
+def mixed_error_report(w, band):
+    """Per-result error of the mixed form against plain FP64 on the GPU."""
+    f = gpu_step(w)
+    m = gpu_step(w, precision=MIXED, band_r2=band, band_p=band)
+    ngb_mis = float(np.mean(np.any(f["ngb"] != m["ngb"], axis=1)))
+    dec = (f["info"] & 3) != (m["info"] & 3)
+    vscale = max(np.abs(f[c]).max() for c in ("vx", "vy", "vz"))
+    verr = max(np.abs(f[c] - m[c]).max() for c in ("vx", "vy", "vz")) / vscale
+    e0, p0 = _energy_momentum(w, dict(vx=w.vx, vy=w.vy, vz=w.vz, state=w.state))
+    ef, pf = _energy_momentum(w, f)
+    em, pm = _energy_momentum(w, m)
+    pscale = w.mass * np.abs(np.concatenate([w.vx, w.vy, w.vz])).sum()
+    return dict(ngb_mismatch_rate=ngb_mis, decision_mismatch_rate=float(dec.mean()),
+                max_rel_velocity_error=float(verr),
+                energy_drift_fp64=abs(ef - e0) / e0, energy_drift_mixed=abs(em - e0) / e0,
+                momentum_drift_fp64=float(np.abs(pf - p0).max() / pscale),
+                momentum_drift_mixed=float(np.abs(pm - p0).max() / pscale),
+                rechecked=m["stats"]["n_recheck"], candidates=m["stats"]["n_cand"])
+
+
+def test_mixed_full_size_halo_equals_fp64():
+    """The 10^6 Hernquist halo with ~1/8 active: the mixed form with its
+    default bands gives the same neighbours, decisions and velocities as the
+    FP64 form (which the parity tests tie to the oracle)."""
+    w = W.hernquist_bins(W.hernquist_halo(1_000_000))
+    _announce(f"mixed vs fp64 hernquist 1e6 active={w.n_active}")
+    r = mixed_error_report(w, 1e-5)
+    print("[mixed bands=1e-5]", r, flush=True)
+    assert r["ngb_mismatch_rate"] == 0.0
+    assert r["decision_mismatch_rate"] == 0.0
+    assert r["max_rel_velocity_error"] == 0.0
+    assert r["energy_drift_mixed"] < 1e-12 and r["momentum_drift_mixed"] < 1e-12
+
+
+def test_mixed_without_bands_error_is_small():
+    """With the bands set to zero the FP32 results stand unchecked; the
+    per-result error against FP64 is stated and must stay small, and the
+    kicks (FP64) still conserve energy and momentum."""
+    w = W.uniform_box(32768, scatters_per_particle=0.05)
+    _announce("mixed bands=0 uniform 32k")
+    r = mixed_error_report(w, 0.0)
+    print("[mixed bands=0]", r, flush=True)
+    assert r["ngb_mismatch_rate"] <= 1e-3
+    assert r["decision_mismatch_rate"] <= 1e-4
+    assert r["energy_drift_mixed"] < 1e-12 and r["momentum_drift_mixed"] < 1e-12
