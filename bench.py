@@ -114,6 +114,49 @@ def copy_probe(mib: int) -> None:
                       "ms": ms, "gbs": 2 * n * 8 / (min(ms) * 1e-3) / 1e9}))
 
 
+def run_serving(args) -> dict:
+    """The served form: a Poisson stream of independent Hernquist haloes,
+    continuous batching over slots, admission by HBM budget."""
+    import concurrent.futures as cf
+    import torch
+    import workloads as W
+    from paper_2607_05504_amd import FP64, MIXED
+    from paper_2607_05504_amd.serve import Server, ServeConfig
+    torch.cuda.set_device(0)
+    reqs = W.serving_requests(args.requests, rate=args.rate, n_max=args.n_max, steps=args.req_steps)
+    # initial conditions generated before the stream starts (host work, not timed)
+    with cf.ThreadPoolExecutor(8) as ex:
+        wl = dict(zip([r.rid for r in reqs], ex.map(W.request_workload, reqs)))
+    print(f"[bench] serving: {len(reqs)} requests generated", file=sys.stderr, flush=True)
+    prec = MIXED if args.precision == "mixed" else FP64
+    # warm-up: one small request through the whole path
+    srv = Server(ServeConfig(n_slots=args.slots, hbm_budget=args.budget_gib << 30, precision=prec))
+    wreq = W.Request(rid=-1, arrival=0.0, n=10000, s0=W.hernquist_s0(), ic_seed=99, philox_seed=99,
+                     steps=2)
+    srv.run([wreq], W.request_workload)
+    torch.cuda.synchronize()
+    rep = srv.run(reqs, lambda r: wl[r.rid])
+    torch.cuda.synchronize()
+    srv.close()
+    n_steps = sum(r.steps for r in reqs)
+    return {
+        "metric": METRIC, "value": rep["throughput"], "unit": "active particles/s",
+        "n_gpus": 1, "steps": n_steps, "warmup": 1,
+        "ms_per_step": rep["wall_s"] * 1e3 / max(n_steps, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": "serving", "requests": len(reqs), "rate_per_s": args.rate,
+                   "n_range": [1e4, args.n_max], "steps_per_request": args.req_steps,
+                   "slots": args.slots, "hbm_budget_gib": args.budget_gib,
+                   "precision": args.precision},
+        "p50_step_ms": rep["p50_step_ms"], "p99_step_ms": rep["p99_step_ms"],
+        "p50_request_s": rep["p50_request_s"], "p99_request_s": rep["p99_request_s"],
+        "mean_admission_wait_s": rep["mean_admission_wait_s"],
+        "max_admission_wait_s": rep["max_admission_wait_s"],
+        "wall_s": rep["wall_s"], "particle_steps": rep["particle_steps"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +169,12 @@ def main():
                          "offsets with FP64 rechecks in the bands, FP64 kicks")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="per-kernel HBM traffic measured with rocprofv3 counters")
+    ap.add_argument("--requests", type=int, default=200, help="serving: requests in the stream")
+    ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second")
+    ap.add_argument("--n-max", type=float, default=2e5, help="serving: largest halo (N)")
+    ap.add_argument("--req-steps", type=int, default=64, help="serving: steps per request")
+    ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
+    ap.add_argument("--budget-gib", type=int, default=4, help="serving: HBM budget")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times "
                          "(calibrates the HBM byte counters) and exit")
@@ -136,6 +185,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.workload == "serving":
+        print(json.dumps(run_serving(args)))
         return
 
     import torch

@@ -14,6 +14,11 @@
  *                       and momentum/energy-conserving kicks (sec. 4.1, 4.5)
  *   sidm_pair_timestep  per-pair timestep bound (Eq. sidm_timestep, sec. 4.4)
  *
+ * and, for the served form (many independent haloes stepped concurrently,
+ * one context and stream each), sidm_advance_hernquist: the global step
+ * length from the per-pair bounds and a leapfrog step in a fixed halo
+ * potential between scattering steps.
+ *
  * Conventions shared by every call:
  *   - All array arguments are DEVICE pointers on the context's device, owned
  *     by the caller (for example torch tensors' data_ptr()).  The library
@@ -136,6 +141,12 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
                         void *hip_stream, sidm_ctx **out);
 sidm_status sidm_destroy(sidm_ctx *ctx);
 sidm_status sidm_set_stream(sidm_ctx *ctx, void *hip_stream);
+/* Replace the context's configuration (for example sigma0 of the next halo a
+ * pooled context serves).  n_ngb and precision fix the context's memory layout
+ * and must not change (SIDM_E_INVAL otherwise, context unchanged).  The next
+ * step needs a new sidm_build_tree.  Host-side only; call it between steps
+ * (work already enqueued keeps the old values). */
+sidm_status sidm_reconfigure(sidm_ctx *ctx, const sidm_config *cfg);
 
 /* Last error message of the context (host-side text), "" if none. */
 const char *sidm_last_error(const sidm_ctx *ctx);
@@ -170,6 +181,22 @@ sidm_status sidm_scatter_step(sidm_ctx *ctx, sidm_particles *p, const int32_t *a
  * the current (post-kick) velocities; +inf when the maximum is 0. */
 sidm_status sidm_pair_timestep(sidm_ctx *ctx, const int32_t *active, int64_t n_active,
                                const int32_t *ngb, const double *h, double *dt_sidm);
+
+/* Served form: the step between two scattering steps of an isolated halo
+ * that has no gravity solver of its own.  The step length d is the largest
+ * dt_cap / 2^b (b >= 0) not above min(dt_sidm[0..n_active)) -- the per-pair
+ * bounds sidm_pair_timestep just wrote (sec. 4.4) -- or dt_cap if
+ * n_active == 0.  d is written to dt_next[0..n_active) (the dt of the next
+ * sidm_scatter_step; may be NULL) and to *dt_step (device scalar; may be
+ * NULL).  Then all n particles take one kick-drift-kick step of length d in
+ * the Hernquist potential Phi(r) = -gm / (r + a) (positions and velocities
+ * updated in place; caller-owned device arrays of n doubles each).  Needs
+ * dt_cap > 0, gm >= 0, a > 0, n <= cap_n; asynchronous on the context's
+ * stream, no allocation. */
+sidm_status sidm_advance_hernquist(sidm_ctx *ctx, double *x, double *y, double *z, double *vx,
+                                   double *vy, double *vz, int64_t n, const double *dt_sidm,
+                                   int64_t n_active, double dt_cap, double gm, double a,
+                                   double *dt_next, double *dt_step);
 
 /* Wait for the context's stream, copy the statistics of the last
  * sidm_scatter_step into *out (may be NULL) and return the latched device

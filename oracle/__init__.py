@@ -217,3 +217,46 @@ def full_step(w, brute: Optional[bool] = None, band: float = 1e-9, workers: int 
     dt = pair_timestep(w, ngb, h, vx, vy, vz)
     return dict(ngb=ngb, h=h, vx=vx, vy=vy, vz=vz, state=st, info=info, stats=stats,
                 dt_sidm=dt)
+
+
+def step_length(dt_sidm, dt_cap: float) -> float:
+    """Global step of the served form: the largest dt_cap / 2^b (b = 0..62)
+    not above the smallest per-pair bound (sec. 4.4 bound; powers of two as in
+    the hierarchical steps of sec. 3.2); dt_cap if there is no bound."""
+    m = float(np.min(dt_sidm)) if len(dt_sidm) else np.inf
+    d = float(dt_cap)
+    b = 0
+    while not d <= m and b < 62:
+        d *= 0.5
+        b += 1
+    return d
+
+
+def advance_hernquist(x, y, z, vx, vy, vz, dt_sidm, dt_cap: float, gm: float, a: float):
+    """Served form, between two scattering steps: one kick-drift-kick leapfrog
+    step of length step_length(dt_sidm, dt_cap) in the Hernquist (1990)
+    potential Phi = -gm / (r + a), whose acceleration is
+    -gm / (r (r + a)^2) times the position vector.  Returns new arrays and d."""
+    d = step_length(dt_sidm, dt_cap)
+    hd = 0.5 * d
+
+    def force(px, py, pz):
+        r = np.sqrt((px * px + py * py) + pz * pz)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            f = np.where(r > 0.0, -gm / (r * ((r + a) * (r + a))), 0.0)
+        return f
+
+    x, y, z = (np.asarray(v, dtype=np.float64).copy() for v in (x, y, z))
+    vx, vy, vz = (np.asarray(v, dtype=np.float64).copy() for v in (vx, vy, vz))
+    f = force(x, y, z)
+    vx = vx + hd * (f * x)
+    vy = vy + hd * (f * y)
+    vz = vz + hd * (f * z)
+    x = x + d * vx
+    y = y + d * vy
+    z = z + d * vz
+    f = force(x, y, z)
+    vx = vx + hd * (f * x)
+    vy = vy + hd * (f * y)
+    vz = vz + hd * (f * z)
+    return x, y, z, vx, vy, vz, d

@@ -77,10 +77,10 @@ class Timing(ctypes.Structure):
 
 
 # Every symbol include/sidm.h declares (tests check the library exports them).
-EXPORTS = ["sidm_footprint", "sidm_create", "sidm_destroy", "sidm_set_stream",
+EXPORTS = ["sidm_footprint", "sidm_create", "sidm_destroy", "sidm_set_stream", "sidm_reconfigure",
            "sidm_last_error", "sidm_status_string", "sidm_build_tree", "sidm_find_ngb",
-           "sidm_scatter_step", "sidm_pair_timestep", "sidm_sync", "sidm_timing_enable",
-           "sidm_timing_read"]
+           "sidm_scatter_step", "sidm_pair_timestep", "sidm_advance_hernquist", "sidm_sync",
+           "sidm_timing_enable", "sidm_timing_read"]
 
 _lib = None
 
@@ -98,6 +98,7 @@ def lib():
         L.sidm_create.argtypes = [CP, i64, i64, P, ctypes.POINTER(ctypes.c_void_p)]
         L.sidm_destroy.argtypes = [P]
         L.sidm_set_stream.argtypes = [P, P]
+        L.sidm_reconfigure.argtypes = [P, CP]
         L.sidm_last_error.argtypes = [P]
         L.sidm_last_error.restype = ctypes.c_char_p
         L.sidm_status_string.argtypes = [ctypes.c_int]
@@ -106,6 +107,8 @@ def lib():
         L.sidm_find_ngb.argtypes = [P, P, i64, P, P]
         L.sidm_scatter_step.argtypes = [P, ctypes.POINTER(Particles), P, i64, P, P, P, u64, u32, P]
         L.sidm_pair_timestep.argtypes = [P, P, i64, P, P, P]
+        d = ctypes.c_double
+        L.sidm_advance_hernquist.argtypes = [P, P, P, P, P, P, P, i64, P, i64, d, d, d, P, P]
         L.sidm_sync.argtypes = [P, ctypes.POINTER(Stats)]
         L.sidm_timing_enable.argtypes = [P, ctypes.c_int]
         L.sidm_timing_read.argtypes = [P, ctypes.POINTER(Timing)]
@@ -187,6 +190,10 @@ class Context:
         self._check(lib().sidm_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)),
                     "sidm_set_stream")
 
+    def reconfigure(self, cfg: Config):
+        self._check(lib().sidm_reconfigure(self._h, ctypes.byref(cfg)), "sidm_reconfigure")
+        self.cfg = cfg
+
     # -- the four calls of the step ----------------------------------------------
     def build_tree(self, x, y, z, vx, vy, vz, ids, state=None, mass=None, m_scalar=0.0):
         torch = self._torch
@@ -234,6 +241,20 @@ class Context:
         self._check(lib().sidm_pair_timestep(self._h, _ptr(active), int(active.shape[0]),
                                              _ptr(ngb), _ptr(h), _ptr(dt_sidm)),
                     "sidm_pair_timestep")
+
+    def advance_hernquist(self, x, y, z, vx, vy, vz, dt_sidm, n_active: int, dt_cap: float,
+                          gm: float, a: float, dt_next=None, dt_step=None):
+        """Served form: global step length from the per-pair bounds, then one
+        kick-drift-kick step in the potential -gm / (r + a)."""
+        torch = self._torch
+        f64 = torch.float64
+        for t, nm in ((x, "x"), (y, "y"), (z, "z"), (vx, "vx"), (vy, "vy"), (vz, "vz"),
+                      (dt_sidm, "dt_sidm"), (dt_next, "dt_next"), (dt_step, "dt_step")):
+            self._dev(t, f64, nm)
+        self._check(lib().sidm_advance_hernquist(
+            self._h, _ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), int(x.shape[0]),
+            _ptr(dt_sidm), int(n_active), float(dt_cap), float(gm), float(a), _ptr(dt_next),
+            _ptr(dt_step)), "sidm_advance_hernquist")
 
     def timing_enable(self, on: bool = True):
         self._check(lib().sidm_timing_enable(self._h, int(bool(on))), "sidm_timing_enable")

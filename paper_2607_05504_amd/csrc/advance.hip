@@ -1,0 +1,99 @@
+// Served form: the step between two scattering steps of an isolated halo.
+//
+// The paper's SIDM step sits inside a gravity code (sec. 3); a halo served
+// here has no gravity solver, so between scattering steps the particles
+// move in the fixed potential of a Hernquist (1990) halo,
+// Phi(r) = -G M / (r + a), with one kick-drift-kick leapfrog step.  The step
+// length is global (one timestep for the whole halo): the largest
+// dt_cap / 2^b not above the smallest per-pair bound of the scattering step
+// just done (sec. 4.4), so that the next scattering step respects it.
+//
+//   k_min_dt   block-reduced minimum of dt_sidm into one ordered 64-bit word
+//   k_advance  every thread derives the same step length from that word,
+//              writes it as the next step's dt of the active particles, and
+//              moves its particles: v += g dt/2, x += v dt, v += g dt/2
+#include "sidm_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+int grid_for(int64_t n, int cap = 2048)
+{
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    return (int)(g > cap ? cap : g);
+}
+
+__global__ __launch_bounds__(kBlock) void k_min_dt(const double *__restrict__ dt, int64_t n,
+                                                   unsigned long long *out)
+{
+    __shared__ unsigned long long s_min[kBlock / 64];
+    unsigned long long m = ~0ull;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlock) {
+        const unsigned long long v = ordered_u64(dt[t]);
+        m = v < m ? v : m;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = (unsigned long long)__shfl_xor((long long)m, off);
+        m = o < m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) m = s_min[w] < m ? s_min[w] : m;
+        atomicMin(out, m);
+    }
+}
+
+// largest dt_cap / 2^b (b = 0..62) not above bound; the smallest one if none is
+__device__ __forceinline__ double step_length(double bound, double dt_cap)
+{
+    double d = dt_cap;
+    for (int b = 0; b < 62 && !(d <= bound); ++b) d *= 0.5;
+    return d;
+}
+
+__global__ __launch_bounds__(kBlock) void k_advance(double *x, double *y, double *z, double *vx,
+                                                    double *vy, double *vz, int64_t n,
+                                                    int64_t n_active,
+                                                    const unsigned long long *minword,
+                                                    double dt_cap, double gm, double a,
+                                                    double *dt_next, double *dt_step)
+{
+    const double d = step_length(from_ordered_u64(*minword), dt_cap);
+    const double hd = 0.5 * d;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && dt_step) *dt_step = d;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlock) {
+        if (t < n_active && dt_next) dt_next[t] = d;
+        double px = x[t], py = y[t], pz = z[t];
+        double ux = vx[t], uy = vy[t], uz = vz[t];
+        // acceleration -G M / (r (r + a)^2) times the position vector
+        double r = sqrt((px * px + py * py) + pz * pz);
+        double f = r > 0.0 ? -gm / (r * ((r + a) * (r + a))) : 0.0;
+        ux += hd * (f * px); uy += hd * (f * py); uz += hd * (f * pz);
+        px += d * ux; py += d * uy; pz += d * uz;
+        r = sqrt((px * px + py * py) + pz * pz);
+        f = r > 0.0 ? -gm / (r * ((r + a) * (r + a))) : 0.0;
+        ux += hd * (f * px); uy += hd * (f * py); uz += hd * (f * pz);
+        x[t] = px; y[t] = py; z[t] = pz;
+        vx[t] = ux; vy[t] = uy; vz[t] = uz;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_advance(sidm_ctx *c, double *x, double *y, double *z, double *vx, double *vy,
+                          double *vz, int64_t n, const double *dt_sidm, int64_t n_active,
+                          double dt_cap, double gm, double a, double *dt_next, double *dt_step)
+{
+    hipStream_t s = c->stream;
+    hipError_t e = launch_fill_u64(c->adv_min, ~0ull, 1, s);
+    if (e != hipSuccess) return e;
+    if (n_active > 0) k_min_dt<<<grid_for(n_active), kBlock, 0, s>>>(dt_sidm, n_active, c->adv_min);
+    k_advance<<<grid_for(n), kBlock, 0, s>>>(x, y, z, vx, vy, vz, n, n_active, c->adv_min, dt_cap,
+                                            gm, a, dt_next, dt_step);
+    return hipGetLastError();
+}

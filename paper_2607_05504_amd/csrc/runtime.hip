@@ -72,6 +72,7 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(acc_count, 8, int32_t);
     ADD(dstats, 1, DevStats);
     ADD(derr, 1, unsigned int);
+    ADD(adv_min, 1, unsigned long long);
 #undef ADD
 }
 
@@ -275,6 +276,22 @@ sidm_status sidm_set_stream(sidm_ctx *c, void *hip_stream)
     return SIDM_OK;
 }
 
+sidm_status sidm_reconfigure(sidm_ctx *c, const sidm_config *cfg)
+{
+    if (!c || !cfg) return SIDM_E_INVAL;
+    if (check_config(cfg) != SIDM_OK) {
+        set_err(c, "reconfigure: invalid configuration");
+        return SIDM_E_INVAL;
+    }
+    if (cfg->n_ngb != c->cfg.n_ngb || cfg->precision != c->cfg.precision) {
+        set_err(c, "reconfigure: n_ngb and precision fix the context's layout");
+        return SIDM_E_INVAL;
+    }
+    c->cfg = *cfg;
+    c->tree_ok = 0;          // a new configuration needs a new snapshot
+    return SIDM_OK;
+}
+
 const char *sidm_last_error(const sidm_ctx *c)
 {
     return c ? c->err : "null context";
@@ -391,6 +408,36 @@ sidm_status sidm_pair_timestep(sidm_ctx *c, const int32_t *active, int64_t n_act
     hipError_t e = launch_map_active(c, active, n_active);
     if (e == hipSuccess) e = launch_timestep(c, n_active, ngb, h, dt_sidm);
     if (e != hipSuccess) return hip_fail(c, e, "pair_timestep");
+    return SIDM_OK;
+}
+
+sidm_status sidm_advance_hernquist(sidm_ctx *c, double *x, double *y, double *z, double *vx,
+                                   double *vy, double *vz, int64_t n, const double *dt_sidm,
+                                   int64_t n_active, double dt_cap, double gm, double a,
+                                   double *dt_next, double *dt_step)
+{
+    if (!c) return SIDM_E_INVAL;
+    if (n < 0 || n > c->cap_n || n_active < 0 || n_active > n) {
+        set_err(c, "advance_hernquist: n=%lld n_active=%lld cap_n=%lld", (long long)n,
+                (long long)n_active, (long long)c->cap_n);
+        return SIDM_E_INVAL;
+    }
+    if (n > 0 && (!x || !y || !z || !vx || !vy || !vz)) {
+        set_err(c, "advance_hernquist: NULL particle array");
+        return SIDM_E_INVAL;
+    }
+    if (n_active > 0 && !dt_sidm) {
+        set_err(c, "advance_hernquist: NULL dt_sidm");
+        return SIDM_E_INVAL;
+    }
+    if (!(dt_cap > 0.0) || !(dt_cap < 1e300) || !(gm >= 0.0) || !(a > 0.0)) {
+        set_err(c, "advance_hernquist: need dt_cap > 0, gm >= 0, a > 0");
+        return SIDM_E_INVAL;
+    }
+    if (n == 0) return SIDM_OK;
+    hipError_t e = launch_advance(c, x, y, z, vx, vy, vz, n, dt_sidm, n_active, dt_cap, gm, a,
+                                  dt_next, dt_step);
+    if (e != hipSuccess) return hip_fail(c, e, "advance_hernquist");
     return SIDM_OK;
 }
 

@@ -128,6 +128,7 @@ struct sidm_ctx {
 
     DevStats *dstats;
     unsigned int *derr;
+    unsigned long long *adv_min;   // served form: smallest per-pair bound of a step
     // opt-in event timing of the main kernels: up to SIDM_TIMING_RING launches
     // of each phase are bracketed between two sidm_timing_read calls
     int timing;
@@ -299,3 +300,7 @@ hipError_t launch_scatter(sidm_ctx *c, sidm_particles *p, int64_t n_active, cons
                           uint32_t *cand_info);
 hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, const double *h,
                            double *dt_out);
+// advance.hip
+hipError_t launch_advance(sidm_ctx *c, double *x, double *y, double *z, double *vx, double *vy,
+                          double *vz, int64_t n, const double *dt_sidm, int64_t n_active,
+                          double dt_cap, double gm, double a, double *dt_next, double *dt_step);

@@ -366,3 +366,59 @@ def test_pass_indices_match_parallel_matching_rounds():
         ws = set(winners)
         remaining = [c for c in remaining if c not in ws]
     assert rnd == stats["n_passes"]
+
+
+# ---------------------------------------------------------------------------
+# Served form: step length and the leapfrog step in the halo potential
+# ---------------------------------------------------------------------------
+
+def test_step_length_is_largest_power_of_two_below_bound():
+    """Brute force over b: the chosen step is dt_cap / 2^b with the smallest
+    b whose step does not exceed the bound."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    for _ in range(200):
+        cap = float(rng.uniform(0.1, 2.0))
+        bound = float(cap * 2.0 ** rng.uniform(-20, 2))
+        d = oracle.step_length(np.array([bound * 3, bound, bound * 2]), cap)
+        cands = [cap / 2 ** b for b in range(63) if cap / 2 ** b <= bound]
+        assert d == cands[0]
+    assert oracle.step_length(np.array([]), 0.25) == 0.25
+    assert oracle.step_length(np.array([np.inf]), 0.25) == 0.25
+
+
+def test_leapfrog_free_drift_and_reversibility():
+    """gm = 0 is a free drift; the kick-drift-kick step is time-reversible
+    (reversing the velocities after a step and stepping again returns the
+    start to rounding)."""
+    rng = np.random.Generator(np.random.PCG64(6))
+    x, y, z, vx, vy, vz = (rng.normal(size=100) for _ in range(6))
+    out = oracle.advance_hernquist(x, y, z, vx, vy, vz, np.array([0.01]), 0.25, 0.0, 1.0)
+    d = out[6]
+    assert d == 0.25 / 32
+    np.testing.assert_array_equal(out[0], x + d * vx)
+    np.testing.assert_array_equal(out[3], vx)
+    fwd = oracle.advance_hernquist(x, y, z, vx, vy, vz, np.array([0.01]), 0.25, 1.0, 1.0)
+    back = oracle.advance_hernquist(fwd[0], fwd[1], fwd[2], -fwd[3], -fwd[4], -fwd[5],
+                                    np.array([0.01]), 0.25, 1.0, 1.0)
+    np.testing.assert_allclose(back[0], x, atol=1e-13)
+    np.testing.assert_allclose(-back[3], vx, atol=1e-13)
+
+
+def test_leapfrog_circular_orbit_energy():
+    """A circular orbit in the Hernquist potential (v_c^2 = G M r / (r + a)^2)
+    keeps its radius and energy to O(d^2) over many leapfrog steps."""
+    r0 = 1.0
+    vc = math.sqrt(r0 / (r0 + 1.0) ** 2)
+    x, y, z = np.array([r0]), np.array([0.0]), np.array([0.0])
+    vx, vy, vz = np.array([0.0]), np.array([vc]), np.array([0.0])
+
+    def energy(x, y, z, vx, vy, vz):
+        r = np.sqrt(x * x + y * y + z * z)
+        return 0.5 * (vx * vx + vy * vy + vz * vz) - 1.0 / (r + 1.0)
+    e0 = energy(x, y, z, vx, vy, vz)
+    for _ in range(2000):
+        x, y, z, vx, vy, vz, d = oracle.advance_hernquist(x, y, z, vx, vy, vz,
+                                                          np.array([0.01]), 0.25, 1.0, 1.0)
+    r = float(np.sqrt(x * x + y * y + z * z)[0])
+    assert abs(r - r0) < 1e-4
+    assert abs(float((energy(x, y, z, vx, vy, vz) - e0)[0])) < 1e-6

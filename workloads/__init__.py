@@ -315,3 +315,45 @@ def hernquist_bins(w: Workload, active_frac: float = 0.125, dt_max: float = 2.0,
     out.meta = dict(w.meta, b_star=b_star, dt_max=dt_max,
                     active_fraction=act.size / w.n)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Serving stream: independent Hernquist haloes arriving at random times
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the stream starts
+    n: int                  # particles
+    s0: float               # cross-section normalisation (Yukawa-like, w0 = 0.5)
+    ic_seed: int
+    philox_seed: int
+    steps: int
+
+
+def serving_requests(n_requests: int = 1000, rate: float = 20.0, n_min: float = 1e4,
+                     n_max: float = 2e6, s0_decades: float = 2.0, steps: int = 64,
+                     seed: int = 7) -> list:
+    """Poisson arrivals at ``rate`` per second (exponential gaps from ``seed``);
+    request r: N log-uniform in [n_min, n_max], s0 = hernquist_s0() times a
+    log-uniform factor spanning ``s0_decades`` decades centred on 1, IC seed
+    100000 + r, Philox seed 1000 + r."""
+    rng = _rng(seed)
+    gaps = rng.exponential(1.0 / rate, n_requests)
+    t = np.cumsum(gaps) - gaps[0]
+    logn = rng.uniform(math.log10(n_min), math.log10(n_max), n_requests)
+    logs = rng.uniform(-0.5 * s0_decades, 0.5 * s0_decades, n_requests)
+    base = hernquist_s0()
+    return [Request(rid=r, arrival=float(t[r]), n=int(round(10.0 ** logn[r])),
+                    s0=float(base * 10.0 ** logs[r]), ic_seed=100000 + r,
+                    philox_seed=1000 + r, steps=steps) for r in range(n_requests)]
+
+
+def request_workload(req: Request, dt_cap: float = 0.25) -> Workload:
+    """The halo of one request: all particles active, every dt = dt_cap (the
+    first step; later steps take theirs from the per-pair bounds)."""
+    w = hernquist_halo(req.n, ic_seed=req.ic_seed, philox_seed=req.philox_seed, s0=req.s0)
+    w.dt = np.full(w.n, dt_cap)
+    w.name = f"request{req.rid}_n{req.n}"
+    return w
