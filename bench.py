@@ -46,6 +46,11 @@ def make_workload(name: str):
         w = W.hernquist_halo(4_000_000, ic_seed=104, philox_seed=4, two_state=True)
         w.dt = np.full(w.n, 1e-3)
         desc = "two-state Hernquist halo N=4e6, all active, dt=1e-3, FP64"
+    elif name == "clustered256":
+        w = W.clustered_box()
+        desc = ("clustered periodic box 256^3: 2000 NFW haloes (c=10, dN/dM~M^-1.9 over 3 "
+                "decades, 70% of the mass) + uniform background, Maxwellian at the local "
+                "Jeans dispersion, const sigma/m, all active, FP64")
     else:
         raise SystemExit(f"unknown workload {name}")
     return w, desc

@@ -318,6 +318,103 @@ def hernquist_bins(w: Workload, active_frac: float = 0.125, dt_max: float = 2.0,
 
 
 # ---------------------------------------------------------------------------
+# Clustered periodic box: NFW haloes plus a uniform background
+# ---------------------------------------------------------------------------
+
+def nfw_mu(x):
+    """Enclosed-mass shape of the NFW profile: ln(1 + x) - x / (1 + x)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.log1p(x) - x / (1.0 + x)
+
+
+def nfw_sigma_r_table(c: float = 10.0, n: int = 512):
+    """Isotropic Jeans radial dispersion of an NFW halo of concentration c in
+    units of sqrt(G M_200 / r_200), on a log grid of x = r / r_s in
+    [1e-3, c]:  sigma^2(x) = c x (1+x)^2 / mu(c) * int_x^inf mu(t) / (t^3 (1+t)^2) dt
+    (the profile continues beyond r_200 for the pressure integral)."""
+    from scipy import integrate
+    xs = np.logspace(-3, math.log10(c), n)
+
+    def f(t):
+        return float(nfw_mu(t)) / (t ** 3 * (1.0 + t) ** 2)
+    tail = np.array([integrate.quad(f, x, np.inf, limit=200)[0] for x in xs])
+    s2 = c * xs * (1.0 + xs) ** 2 / float(nfw_mu(c)) * tail
+    return xs, np.sqrt(s2)
+
+
+def clustered_box(n: int = 256 ** 3, n_halo: int = 2000, ic_seed: int = 103,
+                  philox_seed: int = 3, halo_frac: float = 0.7, slope: float = 1.9,
+                  decades: float = 3.0, conc: float = 10.0, events_per_particle: float = 0.005,
+                  dt: float = 1.0, n_ngb: int = 32, step: int = 0) -> Workload:
+    """Periodic unit box, total mass 1 (mean density 1): n_halo NFW haloes
+    (concentration conc) with masses from dN/dM ~ M^-slope over `decades`
+    decades, rescaled to carry halo_frac of the mass, and a uniform
+    background for the rest.  r_200 from a mean density of 200; radii from the
+    inverse of mu(x) / mu(c); isotropic Maxwellian velocities at the local
+    isotropic-Jeans dispersion; background dispersion sqrt(G M_min / r_200,min)
+    / sqrt(2).  All active, constant sigma/m set so that the expected number
+    of scatters per particle is events_per_particle, from the rate
+    rho (sigma/m) <w> dt with each particle's analytic local density
+    (its halo's profile plus the background) and Maxwellian <w> = 4 sigma /
+    sqrt(pi) at its dispersion."""
+    rng = _rng(ic_seed)
+    # halo masses: inverse CDF of a power law on [1, 10^decades], then rescaled
+    u = rng.random(n_halo)
+    a1 = 1.0 - slope
+    lo, hi = 1.0, 10.0 ** decades
+    m_rel = (lo ** a1 + u * (hi ** a1 - lo ** a1)) ** (1.0 / a1)
+    m_h = m_rel * (halo_frac / m_rel.sum())
+    mp = 1.0 / n
+    counts = np.maximum(1, np.round(m_h / mp).astype(np.int64))
+    n_halo_p = int(counts.sum())
+    if n_halo_p > n:
+        raise ValueError("haloes hold more particles than n")
+    n_bg = n - n_halo_p
+    r200 = (3.0 * m_h / (4.0 * math.pi * 200.0)) ** (1.0 / 3.0)
+    centre = rng.random((n_halo, 3))
+    # radii: inverse CDF of mu(x)/mu(c) by interpolation on a fine grid
+    xg = np.concatenate([[0.0], np.logspace(-5, math.log10(conc), 4000)])
+    cdf = nfw_mu(xg) / float(nfw_mu(conc))
+    hid = np.repeat(np.arange(n_halo), counts)
+    x_in = np.interp(rng.random(n_halo_p), cdf, xg)
+    ux, uy, uz = _isotropic(rng, n_halo_p)
+    rs = r200[hid] / conc
+    rr = x_in * rs
+    pos = np.empty((n, 3))
+    pos[:n_halo_p, 0] = centre[hid, 0] + rr * ux
+    pos[:n_halo_p, 1] = centre[hid, 1] + rr * uy
+    pos[:n_halo_p, 2] = centre[hid, 2] + rr * uz
+    pos[n_halo_p:] = rng.random((n_bg, 3))
+    pos = np.mod(pos, 1.0)
+    pos[pos >= 1.0] = 0.0
+    # velocities
+    xt, st = nfw_sigma_r_table(conc)
+    v200 = np.sqrt(m_h / r200)
+    sig = np.empty(n)
+    sig[:n_halo_p] = np.interp(np.clip(x_in, xt[0], xt[-1]), xt, st) * v200[hid]
+    i_min = int(np.argmin(m_h))
+    sig[n_halo_p:] = math.sqrt(m_h[i_min] / r200[i_min]) / math.sqrt(2.0)
+    v = rng.normal(0.0, 1.0, (n, 3)) * sig[:, None]
+    # analytic local density for the cross-section normalisation
+    rho = np.full(n, 1.0 - halo_frac)
+    rho_s = m_h / (4.0 * math.pi * (r200 / conc) ** 3 * float(nfw_mu(conc)))
+    xx = np.maximum(x_in, 1e-4)
+    rho[:n_halo_p] += rho_s[hid] / (xx * (1.0 + xx) ** 2)
+    mean_rate = float(np.mean(rho * 4.0 * sig / math.sqrt(math.pi))) * dt
+    sigma_m = events_per_particle / mean_rate
+    perm = rng.permutation(n)                      # storage order unrelated to structure
+    pos, v = pos[perm], v[perm]
+    return Workload(
+        name=f"clustered_box_n{n}", x=pos[:, 0].copy(), y=pos[:, 1].copy(), z=pos[:, 2].copy(),
+        vx=v[:, 0].copy(), vy=v[:, 1].copy(), vz=v[:, 2].copy(), mass=mp,
+        id=np.arange(n, dtype=np.uint32), state=np.zeros(n, dtype=np.uint8),
+        active=np.arange(n, dtype=np.int32), dt=np.full(n, dt), periodic=True, box=1.0,
+        n_ngb=n_ngb, xsec=XSEC_CONST, sigma0=sigma_m, seed=philox_seed, step=step,
+        meta=dict(ic_seed=ic_seed, n_halo=n_halo, n_halo_particles=n_halo_p,
+                  m_min=float(m_h.min()), m_max=float(m_h.max())))
+
+
+# ---------------------------------------------------------------------------
 # Serving stream: independent Hernquist haloes arriving at random times
 # ---------------------------------------------------------------------------
 
