@@ -47,7 +47,7 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(val0, N, int32_t); ADD(val1, N, int32_t);
     const int64_t nsb = (N + SIDM_SORT_TILE - 1) / SIDM_SORT_TILE;
     ADD(hist, 256 * nsb, uint32_t);
-    ADD(dtot, 256, uint32_t);
+    ADD(dtot, 6 * 256, uint32_t);
     ADD(bounds, 6, unsigned long long);
     ADD(nodes, tree_node_count(tree_levels(N)) * 6, double);
     if (c->cfg.precision == SIDM_MIXED) {

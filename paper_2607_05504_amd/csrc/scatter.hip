@@ -22,7 +22,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMultiPasses = 4;        // passes run as grid-wide kernels
-constexpr int kFinisherMax = 4096;     // shorter lists go to the one-workgroup finisher
+constexpr int kFinisherMax = 256;      // shorter lists go to the one-workgroup finisher
 
 // control block: [0..1] list counts, [2] completed passes, [3] hand-off flag
 enum { CTL_COUNT0 = 0, CTL_COUNT1 = 1, CTL_PASS = 2, CTL_HANDOFF = 3 };

@@ -97,7 +97,7 @@ struct sidm_ctx {
     uint64_t *key0, *key1;
     int32_t *val0, *val1;
     uint32_t *hist;          // [256][n_sort_blocks]
-    uint32_t *dtot;          // [256]
+    uint32_t *dtot;          // [6][256] digit totals of every pass
     unsigned long long *bounds;   // ordered-u64 encodings of min x,y,z / max x,y,z
 
     // bucket tree: leaves of SIDM_LEAF consecutive particles (level 0) and
