@@ -122,42 +122,6 @@ __device__ __forceinline__ double sep2_sel(double xi, double yi, double zi, doub
     return (dx * dx + dy * dy) + dz * dz;
 }
 
-// Morton-order window of W other particles around sorted index i
-template <int W>
-__device__ __forceinline__ void seed_window(int64_t i, int64_t n, int64_t &w0, int64_t &w1)
-{
-    w0 = i - W / 2;
-    if (w0 + W + 1 > n) w0 = n - (W + 1);
-    if (w0 < 0) w0 = 0;
-    w1 = w0 + W + 1 < n ? w0 + W + 1 : n;
-}
-
-__device__ __forceinline__ void cswap(double &ga, int32_t &ia, double &gb, int32_t &ib)
-{
-    const bool sw = gb < ga;
-    const double g = sw ? gb : ga;
-    gb = sw ? ga : gb;
-    ga = g;
-    const int32_t t = sw ? ib : ia;
-    ib = sw ? ia : ib;
-    ia = t;
-}
-
-// ascending sort of 8 (gap, id) pairs: Batcher's odd-even merge network
-__device__ __forceinline__ void sort8(double (&g)[8], int32_t (&id)[8])
-{
-    cswap(g[0], id[0], g[1], id[1]); cswap(g[2], id[2], g[3], id[3]);
-    cswap(g[4], id[4], g[5], id[5]); cswap(g[6], id[6], g[7], id[7]);
-    cswap(g[0], id[0], g[2], id[2]); cswap(g[1], id[1], g[3], id[3]);
-    cswap(g[4], id[4], g[6], id[6]); cswap(g[5], id[5], g[7], id[7]);
-    cswap(g[1], id[1], g[2], id[2]); cswap(g[5], id[5], g[6], id[6]);
-    cswap(g[0], id[0], g[4], id[4]); cswap(g[1], id[1], g[5], id[5]);
-    cswap(g[2], id[2], g[6], id[6]); cswap(g[3], id[3], g[7], id[7]);
-    cswap(g[2], id[2], g[4], id[4]); cswap(g[3], id[3], g[5], id[5]);
-    cswap(g[1], id[1], g[2], id[2]); cswap(g[3], id[3], g[4], id[4]);
-    cswap(g[5], id[5], g[6], id[6]);
-}
-
 // Upper bound on the K1-th smallest r^2 among the other particles of the
 // Morton-order window [w0, w0 + W], bracketed in FP32 with values rounded up
 // (so no count exceeds the exact one); +inf if fewer than K1 fit in FP32.
@@ -338,78 +302,12 @@ __global__ __launch_bounds__(64) void k_knn_list(KnnArgs A, int64_t base)
 // ---------------------------------------------------------------------------
 // Kernel B: exact selection by a 16-lane team per target
 // ---------------------------------------------------------------------------
-// key order (r^2, id): a < b
-__device__ __forceinline__ bool key_lt(double ra, uint32_t ia, double rb, uint32_t ib)
-{
-    return ra < rb || (ra == rb && ia < ib);
-}
-
-// One compare-exchange stage (k = 2^LK, distance d = 2^LD) of an ascending
-// bitonic sort of 16*E keys held E per lane (lane tl holds keys tl*E ..
-// tl*E+E-1) across a team of 16 lanes.
-template <int E, int LK, int LD>
-__device__ __forceinline__ void bitonic_stage(double (&r)[E], uint32_t (&id)[E], int32_t (&jj)[E], int tl)
-{
-    constexpr int k = 1 << LK, d = 1 << LD;
-    if constexpr (d < E) {
-#pragma unroll
-        for (int a = 0; a < E; ++a) {
-            const int bq = a ^ d;
-            if (bq > a) {
-                const bool up = (((tl * E + a) & k) == 0);
-                const bool gt = key_lt(r[bq], id[bq], r[a], id[a]);
-                const bool sw = gt == up;
-                const double ra = r[a], rb = r[bq];
-                const uint32_t ia = id[a], ib = id[bq];
-                const int32_t ja = jj[a], jb = jj[bq];
-                r[a] = sw ? rb : ra; r[bq] = sw ? ra : rb;
-                id[a] = sw ? ib : ia; id[bq] = sw ? ia : ib;
-                jj[a] = sw ? jb : ja; jj[bq] = sw ? ja : jb;
-            }
-        }
-    } else {
-        constexpr int ld = d / E;
-#pragma unroll
-        for (int a = 0; a < E; ++a) {
-            const double orr = __shfl_xor(r[a], ld);
-            const uint32_t oid = (uint32_t)__shfl_xor((int)id[a], ld);
-            const int32_t oj = __shfl_xor(jj[a], ld);
-            const bool up = (((tl * E + a) & k) == 0);
-            const bool lower = (tl & ld) == 0;
-            const bool take = (lower == up) ? key_lt(orr, oid, r[a], id[a])
-                                            : key_lt(r[a], id[a], orr, oid);
-            r[a] = take ? orr : r[a];
-            id[a] = take ? oid : id[a];
-            jj[a] = take ? oj : jj[a];
-        }
-    }
-}
-
-template <int E, int LK, int LD>
-__device__ __forceinline__ void bitonic_merge_steps(double (&r)[E], uint32_t (&id)[E], int32_t (&jj)[E], int tl)
-{
-    bitonic_stage<E, LK, LD>(r, id, jj, tl);
-    if constexpr (LD > 0) bitonic_merge_steps<E, LK, LD - 1>(r, id, jj, tl);
-}
-
-template <int E, int LK, int LOGN>
-__device__ __forceinline__ void bitonic_levels(double (&r)[E], uint32_t (&id)[E], int32_t (&jj)[E], int tl)
-{
-    bitonic_merge_steps<E, LK, LK - 1>(r, id, jj, tl);
-    if constexpr (LK < LOGN) bitonic_levels<E, LK + 1, LOGN>(r, id, jj, tl);
-}
-
-template <int E>
-__device__ __forceinline__ void team_sort(double (&r)[E], uint32_t (&id)[E], int32_t (&jj)[E], int tl)
-{
-    constexpr int LOGN = (E == 4) ? 6 : 7;     // 16*E keys
-    bitonic_levels<E, 1, LOGN>(r, id, jj, tl);
-}
-
 constexpr int kStackB = 7 * 9 + 1;       // deepest walk: 10 levels (n < 2^31) of 8-ary nodes
 
-// One compare-exchange stage on r^2 alone (payload jj), same layout as
-// bitonic_stage.  Equal keys are left in place, so no payload is duplicated.
+// One compare-exchange stage (k = 2^LK, distance d = 2^LD) of an ascending
+// bitonic sort on r^2 alone (payload jj) of TS*E keys held E per lane (lane tl
+// of a team of TS lanes holds keys tl*E .. tl*E+E-1).  Equal keys are left in
+// place, so no payload is duplicated.
 template <int E, int LK, int LD>
 __device__ __forceinline__ void rstage(double (&r)[E], int32_t (&jj)[E], int tl)
 {
@@ -456,11 +354,12 @@ __device__ __forceinline__ void rlevels(double (&r)[E], int32_t (&jj)[E], int tl
     if constexpr (LK < LOGN) rlevels<E, LK + 1, LOGN>(r, jj, tl);
 }
 
-template <int E>
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+template <int E, int TS>
 __device__ __forceinline__ void team_sort_r2(double (&r)[E], int32_t (&jj)[E], int tl)
 {
-    constexpr int LOGN = (E == 4) ? 6 : 7;
-    rlevels<E, 1, LOGN>(r, jj, tl);
+    rlevels<E, 1, ilog2(TS * E)>(r, jj, tl);
 }
 
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
@@ -474,14 +373,14 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
 // FP32, leaf) packed so that one 64-bit minimum orders them; the key taken is
 // retired.  Returns -1 once the nearest remaining gap exceeds T (then every
 // remaining gap does, since the rounded gaps never exceed the exact ones).
-template <int KP>
+template <int KP, int TS>
 __device__ __forceinline__ int32_t pick_nearest(uint64_t (&lk)[KP], double T)
 {
     uint64_t m = lk[0];
 #pragma unroll
     for (int q = 1; q < KP; ++q) m = lk[q] < m ? lk[q] : m;
 #pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
+    for (int off = 1; off < TS; off <<= 1) {
         const uint64_t o = shfl_xor_u64(m, off);
         m = o < m ? o : m;
     }
@@ -496,7 +395,7 @@ __device__ __forceinline__ int32_t pick_nearest(uint64_t (&lk)[KP], double T)
 
 // Next leaf of a root walk (targets whose list overflowed): pops the LDS
 // stack, pushing the children within T nearest on top; -1 when empty.
-template <bool PERIODIC>
+template <bool PERIODIC, int TS>
 __device__ __forceinline__ int32_t walk_next(const KnnArgs &A, int32_t *stk, int &sp, double T,
                                              double px, double py, double pz, int tl, int wteam)
 {
@@ -518,11 +417,11 @@ __device__ __forceinline__ int32_t walk_next(const KnnArgs &A, int32_t *stk, int
         int rank = 0;
 #pragma unroll
         for (int s2 = 0; s2 < SIDM_TREE_FAN; ++s2) {
-            const double go = __shfl(gc, s2, 16);
+            const double go = __shfl(gc, s2, TS);
             const bool oo = go <= T && go < INFINITY;
             rank += oo && (go < gc || (go == gc && s2 < tl));
         }
-        const uint64_t m = (__ballot(ok) >> (wteam * 16)) & 0xffffull;
+        const uint64_t m = (__ballot(ok) >> (wteam * TS)) & ((1ull << TS) - 1ull);
         const int np = __popcll(m);
         wave_sync();
         if (ok) stk[sp + np - 1 - rank] = (cl << SIDM_LEVEL_SHIFT) | (int32_t)cq;
@@ -532,19 +431,22 @@ __device__ __forceinline__ int32_t walk_next(const KnnArgs &A, int32_t *stk, int
     return -1;
 }
 
-template <bool PERIODIC, int E, bool MIXED>
+template <bool PERIODIC, int E, bool MIXED, int TS>
 __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
 {
-    constexpr int N = 16 * E;                 // list capacity
-    constexpr int KP = (SIDM_KNN_LMAX + 15) / 16;
-    __shared__ int32_t s_stack[16][kStackB];  // only the overflow walk uses it
-    __shared__ double s_r2[16][N];
-    __shared__ int32_t s_j[16][N];
+    constexpr int N = TS * E;                 // list capacity
+    constexpr int KP = (SIDM_KNN_LMAX + TS - 1) / TS;
+    constexpr int PPL = SIDM_LEAF / TS;       // particles of a leaf per lane
+    constexpr int NT = 256 / TS;              // teams per workgroup
+    constexpr uint64_t TMASK = (TS == 64) ? ~0ull : ((1ull << TS) - 1ull);
+    __shared__ int32_t s_stack[NT][kStackB];  // only the overflow walk uses it
+    __shared__ double s_r2[NT][N];
+    __shared__ int32_t s_j[NT][N];
 
-    const int team = threadIdx.x >> 4, tl = threadIdx.x & 15;
-    const int wteam = team & 3;               // team within the wavefront
+    const int team = threadIdx.x / TS, tl = threadIdx.x % TS;
+    const int wteam = team % (64 / TS);       // team within the wavefront
     const int nt = *A.nt_dev;
-    const int64_t bb = (int64_t)blockIdx.x * 16 + team;
+    const int64_t bb = (int64_t)blockIdx.x * NT + team;
     const int64_t b = base + bb;
     if (!(b < nt && bb < A.batch)) return;    // whole team
     const int32_t i = A.tlist[b];
@@ -569,7 +471,7 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
     uint64_t lk[KP];
 #pragma unroll
     for (int q = 0; q < KP; ++q) {
-        const int t = q * 16 + tl;
+        const int t = q * TS + tl;
         lk[q] = ~0ull;
         if (!walk && t < nl) {
             const int32_t leaf = lst[t];
@@ -580,16 +482,18 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
     double T = A.tb[bb];
     wave_sync();
 
-    // leaf = 32 particles, two per lane (tl and tl + 16); the next leaf's
+    // leaf = 32 particles, PPL per lane (tl, tl + TS, ...); the next leaf's
     // positions are requested before the current one is tested.  cur = -2
     // before the first leaf is picked, -1 once none is left.
-    int32_t cur = -2;
-    double c0x = 0, c0y = 0, c0z = 0, c1x = 0, c1y = 0, c1z = 0;
     // mixed form: the particles' FP32 offsets and their leaf's box; the test
     // is in FP32 against a radius widened by band_r2, and the exact FP64 r^2
     // of the entries that pass is taken when the list is next sorted (kept =
     // leading entries whose exact r^2 is already in the list)
-    float f0x = 0, f0y = 0, f0z = 0, f1x = 0, f1y = 0, f1z = 0;
+    int32_t cur = -2;
+    double cx[PPL], cy[PPL], cz[PPL];
+    float fx[PPL], fy[PPL], fz[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) { cx[q] = cy[q] = cz[q] = 0.0; fx[q] = fy[q] = fz[q] = 0.0f; }
     double cb[6] = {0, 0, 0, 0, 0, 0};
     const float box32 = (float)box;
     int kept = 0;
@@ -599,31 +503,33 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
     int32_t jj[E];
     while (true) {
         int32_t nxt = -1;
-        double n0x = 0, n0y = 0, n0z = 0, n1x = 0, n1y = 0, n1z = 0;
-        float g0x = 0, g0y = 0, g0z = 0, g1x = 0, g1y = 0, g1z = 0;
+        double nx[PPL], ny[PPL], nz[PPL];
+        float gx[PPL], gy[PPL], gz[PPL];
         double nb6[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) { nx[q] = ny[q] = nz[q] = 0.0; gx[q] = gy[q] = gz[q] = 0.0f; }
         if (cur != -1) {
-            nxt = walk ? walk_next<PERIODIC>(A, stk, sp, T, px, py, pz, tl, wteam) : pick_nearest<KP>(lk, T);
+            nxt = walk ? walk_next<PERIODIC, TS>(A, stk, sp, T, px, py, pz, tl, wteam)
+                       : pick_nearest<KP, TS>(lk, T);
             if (nxt >= 0) {
                 const int64_t s0 = (int64_t)nxt * SIDM_LEAF;
-                const int64_t j0 = s0 + tl < n ? s0 + tl : s0, j1 = s0 + 16 + tl < n ? s0 + 16 + tl : s0;
+#pragma unroll
+                for (int q = 0; q < PPL; ++q) {
+                    const int64_t j = s0 + q * TS + tl < n ? s0 + q * TS + tl : s0;
+                    if constexpr (MIXED) { gx[q] = A.xo[j]; gy[q] = A.yo[j]; gz[q] = A.zo[j]; }
+                    else { nx[q] = A.xs[j]; ny[q] = A.ys[j]; nz[q] = A.zs[j]; }
+                }
                 if constexpr (MIXED) {
-                    g0x = A.xo[j0]; g0y = A.yo[j0]; g0z = A.zo[j0];
-                    g1x = A.xo[j1]; g1y = A.yo[j1]; g1z = A.zo[j1];
                     const double *nb = A.nodes + (int64_t)nxt * 6;
 #pragma unroll
                     for (int d = 0; d < 6; ++d) nb6[d] = nb[d];
-                } else {
-                    n0x = A.xs[j0]; n0y = A.ys[j0]; n0z = A.zs[j0];
-                    n1x = A.xs[j1]; n1y = A.ys[j1]; n1z = A.zs[j1];
                 }
             }
         }
         if (cur >= 0) {
             const int64_t s0 = (int64_t)cur * SIDM_LEAF;
-            const int64_t j0 = s0 + tl, j1 = s0 + 16 + tl;
-            double r0 = 0.0, r1 = 0.0;
-            bool p0, p1;
+            double rq[PPL];
+            bool pq[PPL];
             if constexpr (MIXED) {
                 double dlx = box_centre(cb, 0) - px, dly = box_centre(cb, 1) - py, dlz = box_centre(cb, 2) - pz;
                 if (PERIODIC) {
@@ -633,40 +539,38 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
                     dlz = dlz >= half ? dlz - box : (dlz < -half ? dlz + box : dlz);
                 }
                 const float ex = (float)dlx, ey = (float)dly, ez = (float)dlz;
-                float ax = ex + f0x, ay = ey + f0y, az = ez + f0z;
-                float bx = ex + f1x, by = ey + f1y, bz = ez + f1z;
-                if (PERIODIC) {
-                    ax = wrap32(ax, box32); ay = wrap32(ay, box32); az = wrap32(az, box32);
-                    bx = wrap32(bx, box32); by = wrap32(by, box32); bz = wrap32(bz, box32);
-                }
                 const float T32 = __double2float_ru(T * (1.0 + A.band_r2));
-                p0 = j0 < n && (ax * ax + ay * ay) + az * az <= T32 && j0 != i;
-                p1 = j1 < n && (bx * bx + by * by) + bz * bz <= T32 && j1 != i;
+#pragma unroll
+                for (int q = 0; q < PPL; ++q) {
+                    float ax = ex + fx[q], ay = ey + fy[q], az = ez + fz[q];
+                    if (PERIODIC) { ax = wrap32(ax, box32); ay = wrap32(ay, box32); az = wrap32(az, box32); }
+                    const int64_t j = s0 + q * TS + tl;
+                    rq[q] = 0.0;
+                    pq[q] = j < n && (ax * ax + ay * ay) + az * az <= T32 && j != i;
+                }
             } else {
-                r0 = sep2_sel<PERIODIC>(px, py, pz, c0x, c0y, c0z, box);
-                r1 = sep2_sel<PERIODIC>(px, py, pz, c1x, c1y, c1z, box);
-                p0 = j0 < n && r0 <= T && j0 != i;
-                p1 = j1 < n && r1 <= T && j1 != i;
+#pragma unroll
+                for (int q = 0; q < PPL; ++q) {
+                    const int64_t j = s0 + q * TS + tl;
+                    rq[q] = sep2_sel<PERIODIC>(px, py, pz, cx[q], cy[q], cz[q], box);
+                    pq[q] = j < n && rq[q] <= T && j != i;
+                }
             }
-            const uint64_t m0 = (__ballot(p0) >> (wteam * 16)) & 0xffffull;
-            const uint64_t m1 = (__ballot(p1) >> (wteam * 16)) & 0xffffull;
-            const int c0 = __popcll(m0);
-            if (p0) {
-                const int pos = count + __popcll(m0 & below);
-                if (!MIXED) L_r2[pos] = r0;
-                L_j[pos] = (int32_t)j0;
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) {
+                const uint64_t m = (__ballot(pq[q]) >> (wteam * TS)) & TMASK;
+                if (pq[q]) {
+                    const int pos = count + __popcll(m & below);
+                    if (!MIXED) L_r2[pos] = rq[q];
+                    L_j[pos] = (int32_t)(s0 + q * TS + tl);
+                }
+                count += __popcll(m);
             }
-            if (p1) {
-                const int pos = count + c0 + __popcll(m1 & below);
-                if (!MIXED) L_r2[pos] = r1;
-                L_j[pos] = (int32_t)j1;
-            }
-            count += c0 + __popcll(m1);
         }
         // the teams of a wavefront sort together whenever one of them must
-        // (sorting is idempotent), so the network runs once for all four
+        // (sorting is idempotent), so the network runs once for all of them
         const bool done = cur == -1;
-        const bool want = !finished && (done || count + 32 > N);
+        const bool want = !finished && (done || count + SIDM_LEAF > N);
         if (__any(want)) {
             if (!finished) {
                 wave_sync();
@@ -683,21 +587,20 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
                         }
                     } else { r[q] = INFINITY; jj[q] = -1; }
                 }
-                team_sort_r2<E>(r, jj, tl);
-                // equal r^2 within the first K1 places: order those by ID
-                // (exact ties, e.g. on a lattice; sorting on the full key)
-                const double nx0 = __shfl(r[0], (tl + 1) & 15, 16);
+                team_sort_r2<E, TS>(r, jj, tl);
+                // equal r^2 within the first K1 places: placed by ID below
+                const double nx0 = __shfl(r[0], (tl + 1) % TS, TS);
                 bool tie = false;
 #pragma unroll
                 for (int q = 0; q < E; ++q) {
                     const int e = tl * E + q;
                     const double nv = q + 1 < E ? r[q + 1] : nx0;
-                    tie = tie || (e < K1 && e + 1 < count && tl * E + q + 1 < N && r[q] == nv);
+                    tie = tie || (e < K1 && e + 1 < count && e + 1 < N && r[q] == nv);
                 }
                 wave_sync();
-                if ((__ballot(tie) >> (wteam * 16)) & 0xffffull) {
-                    // rare: place each element of a run of equal r^2 by its
-                    // rank in (ID, index) within the run
+                if ((__ballot(tie) >> (wteam * TS)) & TMASK) {
+                    // rare (exact ties, e.g. on a lattice): place each element
+                    // of a run of equal r^2 by its rank in (ID, index) in the run
 #pragma unroll
                     for (int q = 0; q < E; ++q) { L_r2[tl * E + q] = r[q]; L_j[tl * E + q] = jj[q]; }
                     wave_sync();
@@ -738,8 +641,11 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
         }
         if (__all(finished)) break;
         cur = nxt;
-        c0x = n0x; c0y = n0y; c0z = n0z; c1x = n1x; c1y = n1y; c1z = n1z;
-        f0x = g0x; f0y = g0y; f0z = g0z; f1x = g1x; f1y = g1y; f1z = g1z;
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+            cx[q] = nx[q]; cy[q] = ny[q]; cz[q] = nz[q];
+            fx[q] = gx[q]; fy[q] = gy[q]; fz[q] = gz[q];
+        }
 #pragma unroll
         for (int d = 0; d < 6; ++d) cb[d] = nb6[d];
     }
@@ -751,17 +657,20 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
     }
     if (tl == 0) A.h[a] = sqrt(T);
     int32_t *out = A.ngb + (int64_t)a * A.k;
-    for (int e = tl; e < A.k; e += 16) out[e] = A.perm[L_j[e]];
+    for (int e = tl; e < A.k; e += TS) out[e] = A.perm[L_j[e]];
 }
 
-template <bool P, int E, bool M>
+constexpr int kTeam = 16;                 // lanes per target in the team kernel (8 measured slower)
+
+// teams of TS lanes; the list holds TS * E entries
+template <bool P, int E, bool M, int TS>
 void launch_batches(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipStream_t s)
 {
     for (int64_t base = 0; base < n_active; base += nb_cap) {
         KnnArgs A = A0;
         A.batch = (n_active - base) < nb_cap ? (n_active - base) : nb_cap;
         k_knn_list<P, 64><<<(unsigned)((A.batch + 63) / 64), 64, 0, s>>>(A, base);
-        k_knn_team<P, E, M><<<(unsigned)((A.batch + 15) / 16), 256, 0, s>>>(A, base);
+        k_knn_team<P, E, M, TS><<<(unsigned)((A.batch + 256 / TS - 1) / (256 / TS)), 256, 0, s>>>(A, base);
     }
 }
 
@@ -784,15 +693,16 @@ hipError_t launch_knn(sidm_ctx *c, int64_t n_active, int32_t *ngb, double *h)
     const bool small = A.k + 1 + 32 <= 64;       // list of 64 suffices for k <= 31
     phase_begin(c, PH_KNN);
     const int sel = (per ? 4 : 0) | (small ? 2 : 0) | (mixed ? 1 : 0);
+    constexpr int B = 128 / kTeam, S = 64 / kTeam;   // lists of 128 and 64 entries
     switch (sel) {
-    case 0: launch_batches<false, 8, false>(A, n_active, c->knn_batch, c->stream); break;
-    case 1: launch_batches<false, 8, true>(A, n_active, c->knn_batch, c->stream); break;
-    case 2: launch_batches<false, 4, false>(A, n_active, c->knn_batch, c->stream); break;
-    case 3: launch_batches<false, 4, true>(A, n_active, c->knn_batch, c->stream); break;
-    case 4: launch_batches<true, 8, false>(A, n_active, c->knn_batch, c->stream); break;
-    case 5: launch_batches<true, 8, true>(A, n_active, c->knn_batch, c->stream); break;
-    case 6: launch_batches<true, 4, false>(A, n_active, c->knn_batch, c->stream); break;
-    default: launch_batches<true, 4, true>(A, n_active, c->knn_batch, c->stream); break;
+    case 0: launch_batches<false, B, false, kTeam>(A, n_active, c->knn_batch, c->stream); break;
+    case 1: launch_batches<false, B, true, kTeam>(A, n_active, c->knn_batch, c->stream); break;
+    case 2: launch_batches<false, S, false, kTeam>(A, n_active, c->knn_batch, c->stream); break;
+    case 3: launch_batches<false, S, true, kTeam>(A, n_active, c->knn_batch, c->stream); break;
+    case 4: launch_batches<true, B, false, kTeam>(A, n_active, c->knn_batch, c->stream); break;
+    case 5: launch_batches<true, B, true, kTeam>(A, n_active, c->knn_batch, c->stream); break;
+    case 6: launch_batches<true, S, false, kTeam>(A, n_active, c->knn_batch, c->stream); break;
+    default: launch_batches<true, S, true, kTeam>(A, n_active, c->knn_batch, c->stream); break;
     }
     phase_end(c, PH_KNN);
     return hipGetLastError();

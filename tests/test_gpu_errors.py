@@ -1,0 +1,131 @@
+"""Error paths and degenerate inputs through the C ABI on the GPU.
+
+Every bad input here is one the library itself turns into an error: the host
+checks reject sizes and call order before anything is enqueued, and the
+kernels test every index against its range before using it (a duplicate or
+out-of-range active entry, an out-of-range neighbour index) and latch a bit
+that sidm_sync reports.  After a reported error the context stays usable."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_05504_amd as sidm
+    sidm.lib()
+
+
+def _announce(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _setup(n=2000, n_active=None):
+    from paper_2607_05504_amd import Context, runner
+    w = W.uniform_box(n, ic_seed=55, scatters_per_particle=0.2)
+    if n_active is not None:
+        w = w.subset_active(n_active)
+    ds = runner.upload(w, "cuda")
+    ctx = Context(runner.config_for(w), w.n, max(1, w.n_active))
+    out = runner.alloc_out(ds, w.n_ngb, with_info=True)
+    ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state, m_scalar=ds.mass)
+    return w, ds, ctx, out
+
+
+def _sync_error(ctx):
+    from paper_2607_05504_amd import SidmError
+    with pytest.raises(SidmError) as e:
+        ctx.sync()
+    return str(e.value)
+
+
+def test_duplicate_active_is_reported_and_context_recovers():
+    _announce("duplicate active entry")
+    w, ds, ctx, out = _setup()
+    act = ds.active.clone()
+    act[10] = act[11]
+    ctx.find_ngb(act, out.ngb, out.h)
+    assert "duplicate" in _sync_error(ctx)
+    ctx.find_ngb(ds.active, out.ngb, out.h)
+    ctx.sync()
+    ngb, h = oracle.find_ngb(w)
+    assert np.array_equal(out.ngb.cpu().numpy(), ngb)
+    assert np.array_equal(out.h.cpu().numpy(), h)
+    ctx.close()
+
+
+def test_active_index_out_of_range_is_reported():
+    _announce("active index out of range")
+    w, ds, ctx, out = _setup()
+    act = ds.active.clone()
+    act[5] = w.n + 7
+    act[6] = -3
+    ctx.find_ngb(act, out.ngb, out.h)
+    assert "index" in _sync_error(ctx)
+    ctx.close()
+
+
+def test_bad_neighbour_index_is_reported():
+    _announce("neighbour index out of range in scatter_step and pair_timestep")
+    w, ds, ctx, out = _setup()
+    ctx.find_ngb(ds.active, out.ngb, out.h)
+    ctx.sync()
+    bad = out.ngb.clone()
+    bad[3, 4] = -1
+    bad[7, 0] = w.n
+    ctx.scatter_step(ds.active, bad, out.h, ds.dt, w.seed, w.step)
+    assert "index" in _sync_error(ctx)
+    ctx.pair_timestep(ds.active, bad, out.h, out.dt_sidm)
+    assert "index" in _sync_error(ctx)
+    ctx.close()
+
+
+def test_host_errors_return_before_anything_runs():
+    import torch
+    from paper_2607_05504_amd import (SIDM_E_CAPACITY, SIDM_E_INVAL, SIDM_E_STATE, Context,
+                                      SidmError, make_config, runner)
+    _announce("host-side errors")
+    w = W.uniform_box(500, ic_seed=56)
+    ds = runner.upload(w, "cuda")
+    ctx = Context(runner.config_for(w), w.n, 100)
+    out = runner.alloc_out(ds, w.n_ngb)
+    with pytest.raises(SidmError) as e:        # find_ngb before build_tree
+        ctx.find_ngb(ds.active[:50], out.ngb[:50], out.h[:50])
+    assert e.value.status == SIDM_E_STATE
+    ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state, m_scalar=ds.mass)
+    with pytest.raises(SidmError) as e:        # more active particles than the capacity
+        ctx.find_ngb(ds.active, out.ngb, out.h)
+    assert e.value.status == SIDM_E_CAPACITY
+    with pytest.raises(SidmError) as e:        # too few particles for n_ngb + 1 neighbours
+        small = runner.upload(W.uniform_box(33, ic_seed=57), "cuda")
+        ctx.build_tree(small.x, small.y, small.z, small.vx, small.vy, small.vz, small.ids,
+                       state=small.state, m_scalar=small.mass)
+    assert e.value.status == SIDM_E_INVAL
+    with pytest.raises(SidmError) as e:        # the layout-fixing n_ngb cannot change
+        ctx.reconfigure(make_config(n_ngb=16, periodic=True, box=1.0, sigma0=1.0))
+    assert e.value.status == SIDM_E_INVAL
+    ctx.sync()                                 # nothing was enqueued by the failed calls
+    ctx.close()
+    torch.cuda.synchronize()
+
+
+def test_empty_active_set_changes_nothing():
+    import torch
+    _announce("empty active set")
+    w, ds, ctx, out = _setup()
+    v0 = ds.vx.clone()
+    empty = ds.active[:0]
+    ctx.find_ngb(empty, out.ngb[:0], out.h[:0])
+    ctx.scatter_step(empty, out.ngb[:0], out.h[:0], ds.dt[:0], w.seed, w.step)
+    ctx.pair_timestep(empty, out.ngb[:0], out.h[:0], out.dt_sidm[:0])
+    st = ctx.sync()
+    assert st["error"] == 0 and st["n_events"] == 0
+    assert torch.equal(ds.vx, v0)
+    ctx.close()
