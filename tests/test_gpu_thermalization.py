@@ -1,0 +1,89 @@
+"""Many steps of the GPU path against closed forms (the thermalisation test of
+the paper's sec. 5.2): a mono-speed start in a uniform periodic box, with a
+free drift between steps (done here by the test driver, not by the library)
+so that particles meet new neighbours, as in the paper's box
+
+- scatters at the rate rho (sigma/m) <w> dt with <w> = 4 v0 / 3,
+- relaxes to a Maxwell-Boltzmann distribution of the same energy
+  (1D dispersion v0 / sqrt(3)),
+- whose mean relative speed 4 sigma_1D / sqrt(pi) = 4 v0 / sqrt(3 pi) lowers
+  the rate by the factor sqrt(3 / pi),
+- and conserves energy and momentum to rounding over all steps."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_05504_amd as sidm
+    sidm.lib()
+
+
+def test_mono_speed_box_thermalises():
+    from scipy import stats as sps
+    from paper_2607_05504_amd import Context, runner
+    n, s, steps = 32768, 0.02, 600
+    w = W.uniform_box(n, ic_seed=77, philox_seed=9, scatters_per_particle=s, mono_speed=True)
+    print(f"[case] thermalisation n={n} steps={steps}", flush=True)
+    ds = runner.upload(w, "cuda")
+    ctx = Context(runner.config_for(w), w.n, w.n_active)
+    out = runner.alloc_out(ds, w.n_ngb)
+    v = lambda: np.stack([ds.vx.cpu().numpy(), ds.vy.cpu().numpy(), ds.vz.cpu().numpy()])
+    v0 = v()
+    e0 = 0.5 * w.mass * float((v0 ** 2).sum())
+    p0 = w.mass * v0.sum(axis=1)
+    events = []
+    import torch
+    for t in range(steps):
+        runner.run_step(ctx, ds, out, w.seed, t)
+        st = ctx.sync()
+        assert st["error"] == 0
+        events.append(st["n_events"])
+        # free drift of about 1.5 mean spacings, wrapped into [0, 1)
+        for x, vv in ((ds.x, ds.vx), (ds.y, ds.vy), (ds.z, ds.vz)):
+            y = torch.remainder(x + 0.05 * vv, 1.0)
+            x.copy_(torch.where(y >= 1.0, y - 1.0, y))
+    v1 = v()
+    ctx.close()
+    events = np.array(events, dtype=np.float64)
+    e_mid = 0.5 * w.mass * float((v1 ** 2).sum())
+    rng = np.random.Generator(np.random.PCG64(3))
+    a, b = rng.integers(0, n, 200000), rng.integers(0, n, 200000)
+    wmean = float(np.sqrt(((v1[:, a] - v1[:, b]) ** 2).sum(axis=0)).mean())
+    print(f"[thermo] events0 {events[0]:.0f} expect0 {s * n / 2:.0f} late {events[steps // 2:].mean():.1f} "
+          f"E1/E0 {e_mid / e0:.15f} <w>_late {wmean:.4f} (MB {4 / math.sqrt(3 * math.pi):.4f}) "
+          f"sd {v1.std():.4f}", flush=True)
+    # first steps (still mono-speed): each particle takes part in s scatters
+    # on average, two per event.  Accepted candidates are re-evaluated after
+    # earlier kicks of the step while step-start rejections stand, which
+    # lowers the count by about s/4 relative (0.5% here; 4% at s = 0.2)
+    expect0 = s * n / 2.0
+    first = events[:10].mean()
+    assert abs(first - expect0) < 0.03 * expect0, (first, expect0)
+    # relaxed: Maxwellian of the same energy, sigma_1D = v0 / sqrt(3)
+    sig = 1.0 / math.sqrt(3.0)
+    ks = sps.kstest(v1[0] / sig, "norm")
+    assert ks.pvalue > 1e-3, ks
+    speeds0 = np.sqrt((v0 ** 2).sum(axis=0))
+    assert np.allclose(speeds0, 1.0)
+    # the rate falls from <w> = 4/3 v0 to 4 sigma_1D / sqrt(pi) = 4 / sqrt(3 pi) v0
+    # (over the second half: ~330 events a step, so about 0.35% statistical
+    # error on the mean; 1.5% allowed, and 1.0 lies 2.3% away)
+    late = events[steps // 2:].mean()
+    ratio = late / expect0
+    expect_ratio = (4.0 / math.sqrt(3.0 * math.pi)) / (4.0 / 3.0)
+    assert abs(ratio - expect_ratio) < 0.015, (ratio, expect_ratio)
+    # conservation over all steps
+    e1 = 0.5 * w.mass * float((v1 ** 2).sum())
+    assert abs(e1 - e0) <= 1e-12 * e0
+    p1 = w.mass * v1.sum(axis=1)
+    assert np.abs(p1 - p0).max() <= 1e-12 * w.mass * np.abs(v0).sum()
