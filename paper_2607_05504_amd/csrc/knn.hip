@@ -431,12 +431,13 @@ __device__ __forceinline__ int32_t walk_next(const KnnArgs &A, int32_t *stk, int
     return -1;
 }
 
-template <bool PERIODIC, int E, bool MIXED, int TS>
+template <bool PERIODIC, int E, bool MIXED, int TS, int LPI>
 __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
 {
     constexpr int N = TS * E;                 // list capacity
     constexpr int KP = (SIDM_KNN_LMAX + TS - 1) / TS;
     constexpr int PPL = SIDM_LEAF / TS;       // particles of a leaf per lane
+    constexpr int PS = PPL * LPI;             // particles per lane per step (LPI leaves)
     constexpr int NT = 256 / TS;              // teams per workgroup
     constexpr uint64_t TMASK = (TS == 64) ? ~0ull : ((1ull << TS) - 1ull);
     __shared__ int32_t s_stack[NT][kStackB];  // only the overflow walk uses it
@@ -489,12 +490,18 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
     // is in FP32 against a radius widened by band_r2, and the exact FP64 r^2
     // of the entries that pass is taken when the list is next sorted (kept =
     // leading entries whose exact r^2 is already in the list)
-    int32_t cur = -2;
-    double cx[PPL], cy[PPL], cz[PPL];
-    float fx[PPL], fy[PPL], fz[PPL];
+    int32_t cur[LPI];
+    double cx[PS], cy[PS], cz[PS];
+    float fx[PS], fy[PS], fz[PS];
+    double cb[LPI][6];
 #pragma unroll
-    for (int q = 0; q < PPL; ++q) { cx[q] = cy[q] = cz[q] = 0.0; fx[q] = fy[q] = fz[q] = 0.0f; }
-    double cb[6] = {0, 0, 0, 0, 0, 0};
+    for (int u = 0; u < LPI; ++u) {
+        cur[u] = -2;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) cb[u][d] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PS; ++q) { cx[q] = cy[q] = cz[q] = 0.0; fx[q] = fy[q] = fz[q] = 0.0f; }
     const float box32 = (float)box;
     int kept = 0;
     int count = 0;
@@ -502,36 +509,50 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
     double r[E];
     int32_t jj[E];
     while (true) {
-        int32_t nxt = -1;
-        double nx[PPL], ny[PPL], nz[PPL];
-        float gx[PPL], gy[PPL], gz[PPL];
-        double nb6[6] = {0, 0, 0, 0, 0, 0};
+        int32_t nxt[LPI];
+        double nx[PS], ny[PS], nz[PS];
+        float gx[PS], gy[PS], gz[PS];
+        double nb6[LPI][6];
 #pragma unroll
-        for (int q = 0; q < PPL; ++q) { nx[q] = ny[q] = nz[q] = 0.0; gx[q] = gy[q] = gz[q] = 0.0f; }
-        if (cur != -1) {
-            nxt = walk ? walk_next<PERIODIC, TS>(A, stk, sp, T, px, py, pz, tl, wteam)
-                       : pick_nearest<KP, TS>(lk, T);
-            if (nxt >= 0) {
-                const int64_t s0 = (int64_t)nxt * SIDM_LEAF;
+        for (int u = 0; u < LPI; ++u) {
+            nxt[u] = -1;
 #pragma unroll
-                for (int q = 0; q < PPL; ++q) {
-                    const int64_t j = s0 + q * TS + tl < n ? s0 + q * TS + tl : s0;
-                    if constexpr (MIXED) { gx[q] = A.xo[j]; gy[q] = A.yo[j]; gz[q] = A.zo[j]; }
-                    else { nx[q] = A.xs[j]; ny[q] = A.ys[j]; nz[q] = A.zs[j]; }
-                }
-                if constexpr (MIXED) {
-                    const double *nb = A.nodes + (int64_t)nxt * 6;
+            for (int d = 0; d < 6; ++d) nb6[u][d] = 0.0;
+        }
 #pragma unroll
-                    for (int d = 0; d < 6; ++d) nb6[d] = nb[d];
+        for (int q = 0; q < PS; ++q) { nx[q] = ny[q] = nz[q] = 0.0; gx[q] = gy[q] = gz[q] = 0.0f; }
+        if (cur[0] != -1) {
+#pragma unroll
+            for (int u = 0; u < LPI; ++u) {
+                if (u > 0 && nxt[u - 1] < 0) break;
+                nxt[u] = walk ? walk_next<PERIODIC, TS>(A, stk, sp, T, px, py, pz, tl, wteam)
+                              : pick_nearest<KP, TS>(lk, T);
+                if (nxt[u] >= 0) {
+                    const int64_t s0 = (int64_t)nxt[u] * SIDM_LEAF;
+#pragma unroll
+                    for (int q = 0; q < PPL; ++q) {
+                        const int64_t j = s0 + q * TS + tl < n ? s0 + q * TS + tl : s0;
+                        const int qq = u * PPL + q;
+                        if constexpr (MIXED) { gx[qq] = A.xo[j]; gy[qq] = A.yo[j]; gz[qq] = A.zo[j]; }
+                        else { nx[qq] = A.xs[j]; ny[qq] = A.ys[j]; nz[qq] = A.zs[j]; }
+                    }
+                    if constexpr (MIXED) {
+                        const double *nb = A.nodes + (int64_t)nxt[u] * 6;
+#pragma unroll
+                        for (int d = 0; d < 6; ++d) nb6[u][d] = nb[d];
+                    }
                 }
             }
         }
-        if (cur >= 0) {
-            const int64_t s0 = (int64_t)cur * SIDM_LEAF;
+#pragma unroll
+        for (int u = 0; u < LPI; ++u) {
+            if (cur[u] < 0) continue;
+            const int64_t s0 = (int64_t)cur[u] * SIDM_LEAF;
             double rq[PPL];
             bool pq[PPL];
             if constexpr (MIXED) {
-                double dlx = box_centre(cb, 0) - px, dly = box_centre(cb, 1) - py, dlz = box_centre(cb, 2) - pz;
+                double dlx = box_centre(cb[u], 0) - px, dly = box_centre(cb[u], 1) - py,
+                       dlz = box_centre(cb[u], 2) - pz;
                 if (PERIODIC) {
                     const double half = 0.5 * box;
                     dlx = dlx >= half ? dlx - box : (dlx < -half ? dlx + box : dlx);
@@ -542,7 +563,8 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
                 const float T32 = __double2float_ru(T * (1.0 + A.band_r2));
 #pragma unroll
                 for (int q = 0; q < PPL; ++q) {
-                    float ax = ex + fx[q], ay = ey + fy[q], az = ez + fz[q];
+                    const int qq = u * PPL + q;
+                    float ax = ex + fx[qq], ay = ey + fy[qq], az = ez + fz[qq];
                     if (PERIODIC) { ax = wrap32(ax, box32); ay = wrap32(ay, box32); az = wrap32(az, box32); }
                     const int64_t j = s0 + q * TS + tl;
                     rq[q] = 0.0;
@@ -551,8 +573,9 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
             } else {
 #pragma unroll
                 for (int q = 0; q < PPL; ++q) {
+                    const int qq = u * PPL + q;
                     const int64_t j = s0 + q * TS + tl;
-                    rq[q] = sep2_sel<PERIODIC>(px, py, pz, cx[q], cy[q], cz[q], box);
+                    rq[q] = sep2_sel<PERIODIC>(px, py, pz, cx[qq], cy[qq], cz[qq], box);
                     pq[q] = j < n && rq[q] <= T && j != i;
                 }
             }
@@ -567,13 +590,18 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
                 count += __popcll(m);
             }
         }
-        // the teams of a wavefront sort together whenever one of them must
-        // (sorting is idempotent), so the network runs once for all of them
-        const bool done = cur == -1;
-        const bool want = !finished && (done || count + SIDM_LEAF > N);
-        if (__any(want)) {
-            if (!finished) {
-                wave_sync();
+        // A team whose list might not hold the next step cuts it: the new
+        // radius is the K1-th smallest r^2 rounded up to FP32, found by
+        // bisection on team-wide counts (no sort), and entries above it are
+        // dropped.  Teams that have run out of leaves wait; once all teams of
+        // the wavefront have, they sort their lists together (exact FP64
+        // r^2, equal values placed by ID) and keep the first K1.
+        if (cur[0] == -1) finished = true;
+        const bool need = !finished && count + LPI * SIDM_LEAF > N;
+        const bool all_done = __all(finished);
+        if (all_done || __any(need)) {
+            wave_sync();
+            if (all_done || need) {
 #pragma unroll
                 for (int q = 0; q < E; ++q) {
                     const int e = tl * E + q;
@@ -587,6 +615,63 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
                         }
                     } else { r[q] = INFINITY; jj[q] = -1; }
                 }
+            }
+            bool bad = false;
+            if (need) {
+                float f[E];
+                uint32_t lo = 0xffffffffu, hi = 0u;
+#pragma unroll
+                for (int q = 0; q < E; ++q) {
+                    f[q] = __double2float_ru(r[q]);
+                    if (tl * E + q < count) {
+                        const uint32_t bv = __float_as_uint(f[q]);
+                        lo = bv < lo ? bv : lo;
+                        hi = bv > hi ? bv : hi;
+                    }
+                }
+                for (int off = 1; off < TS; off <<= 1) {
+                    const uint32_t ol = (uint32_t)__shfl_xor((int)lo, off);
+                    const uint32_t oh = (uint32_t)__shfl_xor((int)hi, off);
+                    lo = ol < lo ? ol : lo;
+                    hi = oh > hi ? oh : hi;
+                }
+                // smallest bracket end with >= K1 values at or below it; stop
+                // once few enough remain (the final sort orders the rest)
+                int c_hi = count;
+                for (int it = 0; it < 32 && lo < hi && c_hi > K1 + 8; ++it) {
+                    const uint32_t mid = lo + ((hi - lo) >> 1);
+                    const float fm = __uint_as_float(mid);
+                    int c = 0;
+#pragma unroll
+                    for (int q = 0; q < E; ++q) c += f[q] <= fm;
+                    for (int off = 1; off < TS; off <<= 1) c += __shfl_xor(c, off);
+                    if (c >= K1) { hi = mid; c_hi = c; } else { lo = mid + 1; }
+                }
+                const float Tf = __uint_as_float(hi);
+                // too many equal values to make room: sort and cut instead
+                bad = c_hi > N - LPI * SIDM_LEAF;
+                int mine = 0;
+#pragma unroll
+                for (int q = 0; q < E; ++q) mine += f[q] <= Tf;
+                int pre = mine;                        // inclusive prefix over the team
+                for (int off = 1; off < TS; off <<= 1) {
+                    const int o = __shfl_up(pre, off, TS);
+                    if (tl >= off) pre += o;
+                }
+                int pos = pre - mine;
+                wave_sync();
+                if (!bad) {
+#pragma unroll
+                    for (int q = 0; q < E; ++q) {
+                        if (f[q] <= Tf) { L_r2[pos] = r[q]; L_j[pos] = jj[q]; ++pos; }
+                    }
+                    count = __shfl(pre, TS - 1, TS);
+                    kept = count;
+                    T = fmin(T, (double)Tf);
+                }
+            }
+            const bool sort_now = all_done || (need && bad);
+            if (sort_now) {
                 team_sort_r2<E, TS>(r, jj, tl);
                 // equal r^2 within the first K1 places: placed by ID below
                 const double nx0 = __shfl(r[0], (tl + 1) % TS, TS);
@@ -632,22 +717,26 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
                         if (e < K1) { L_r2[e] = r[q]; L_j[e] = jj[q]; }
                     }
                 }
-                wave_sync();
+            }
+            wave_sync();
+            if (sort_now) {
                 if (count >= K1) T = L_r2[K1 - 1];
                 count = count < K1 ? count : K1;
                 kept = count;
             }
-            if (done) finished = true;
+            if (all_done) break;
         }
-        if (__all(finished)) break;
-        cur = nxt;
 #pragma unroll
-        for (int q = 0; q < PPL; ++q) {
+        for (int u = 0; u < LPI; ++u) {
+            cur[u] = nxt[u];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) cb[u][d] = nb6[u][d];
+        }
+#pragma unroll
+        for (int q = 0; q < PS; ++q) {
             cx[q] = nx[q]; cy[q] = ny[q]; cz[q] = nz[q];
             fx[q] = gx[q]; fy[q] = gy[q]; fz[q] = gz[q];
         }
-#pragma unroll
-        for (int d = 0; d < 6; ++d) cb[d] = nb6[d];
     }
 
     const int32_t a = A.slot[b];
@@ -662,16 +751,26 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
 
 constexpr int kTeam = 16;                 // lanes per target in the team kernel (8 measured slower)
 
-// teams of TS lanes; the list holds TS * E entries
-template <bool P, int E, bool M, int TS>
-void launch_batches(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipStream_t s)
+constexpr int kLeavesPerStep = 1;          // leaves a team tests per step of its loop
+
+// teams of TS lanes; the list holds TS * E entries; LPI leaves per step
+template <bool P, int E, bool M, int TS, int LPI>
+void launch_batches_l(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipStream_t s)
 {
     for (int64_t base = 0; base < n_active; base += nb_cap) {
         KnnArgs A = A0;
         A.batch = (n_active - base) < nb_cap ? (n_active - base) : nb_cap;
         k_knn_list<P, 64><<<(unsigned)((A.batch + 63) / 64), 64, 0, s>>>(A, base);
-        k_knn_team<P, E, M, TS><<<(unsigned)((A.batch + 256 / TS - 1) / (256 / TS)), 256, 0, s>>>(A, base);
+        k_knn_team<P, E, M, TS, LPI><<<(unsigned)((A.batch + 256 / TS - 1) / (256 / TS)), 256, 0, s>>>(A, base);
     }
+}
+
+template <bool P, int E, bool M, int TS>
+void launch_batches(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipStream_t s)
+{
+    // two leaves a step where the list leaves room for them after a cut
+    constexpr int LPI = (TS * E >= 2 * SIDM_LEAF + 48) ? kLeavesPerStep : 1;
+    launch_batches_l<P, E, M, TS, LPI>(A0, n_active, nb_cap, s);
 }
 
 }  // namespace
