@@ -432,7 +432,8 @@ __device__ __forceinline__ int32_t walk_next(const KnnArgs &A, int32_t *stk, int
 }
 
 template <bool PERIODIC, int E, bool MIXED, int TS, int LPI>
-__global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void k_knn_team(KnnArgs A, int64_t base)
 {
     constexpr int N = TS * E;                 // list capacity
     constexpr int KP = (SIDM_KNN_LMAX + TS - 1) / TS;
@@ -487,9 +488,8 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
     // positions are requested before the current one is tested.  cur = -2
     // before the first leaf is picked, -1 once none is left.
     // mixed form: the particles' FP32 offsets and their leaf's box; the test
-    // is in FP32 against a radius widened by band_r2, and the exact FP64 r^2
-    // of the entries that pass is taken when the list is next sorted (kept =
-    // leading entries whose exact r^2 is already in the list)
+    // is in FP32 against a radius widened by band_r2, the list holds FP32
+    // r^2 until the final sort, which takes the exact FP64 r^2 of each entry
     int32_t cur[LPI];
     double cx[PS], cy[PS], cz[PS];
     float fx[PS], fy[PS], fz[PS];
@@ -503,7 +503,6 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
 #pragma unroll
     for (int q = 0; q < PS; ++q) { cx[q] = cy[q] = cz[q] = 0.0; fx[q] = fy[q] = fz[q] = 0.0f; }
     const float box32 = (float)box;
-    int kept = 0;
     int count = 0;
     bool finished = false;
     double r[E];
@@ -567,8 +566,9 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
                     float ax = ex + fx[qq], ay = ey + fy[qq], az = ez + fz[qq];
                     if (PERIODIC) { ax = wrap32(ax, box32); ay = wrap32(ay, box32); az = wrap32(az, box32); }
                     const int64_t j = s0 + q * TS + tl;
-                    rq[q] = 0.0;
-                    pq[q] = j < n && (ax * ax + ay * ay) + az * az <= T32 && j != i;
+                    const float v = (ax * ax + ay * ay) + az * az;
+                    rq[q] = (double)v;
+                    pq[q] = j < n && v <= T32 && j != i;
                 }
             } else {
 #pragma unroll
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
                 const uint64_t m = (__ballot(pq[q]) >> (wteam * TS)) & TMASK;
                 if (pq[q]) {
                     const int pos = count + __popcll(m & below);
-                    if (!MIXED) L_r2[pos] = rq[q];
+                    L_r2[pos] = rq[q];
                     L_j[pos] = (int32_t)(s0 + q * TS + tl);
                 }
                 count += __popcll(m);
@@ -605,24 +605,21 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
 #pragma unroll
                 for (int q = 0; q < E; ++q) {
                     const int e = tl * E + q;
-                    if (e < count) {
-                        jj[q] = L_j[e];
-                        if (MIXED && e >= kept) {
-                            const int32_t j = jj[q];
-                            r[q] = sep2_sel<PERIODIC>(px, py, pz, A.xs[j], A.ys[j], A.zs[j], box);
-                        } else {
-                            r[q] = L_r2[e];
-                        }
-                    } else { r[q] = INFINITY; jj[q] = -1; }
+                    if (e < count) { jj[q] = L_j[e]; r[q] = L_r2[e]; }
+                    else { r[q] = INFINITY; jj[q] = -1; }
                 }
             }
             bool bad = false;
             if (need) {
-                float f[E];
+                // FP64: the exact r^2 rounded up.  Mixed: the FP32 r^2 widened
+                // by band_r2 both ways; the radius is the K1-th smallest upper
+                // bound and an entry goes only if its lower bound exceeds it
+                float f[E], fl[E];
                 uint32_t lo = 0xffffffffu, hi = 0u;
 #pragma unroll
                 for (int q = 0; q < E; ++q) {
-                    f[q] = __double2float_ru(r[q]);
+                    f[q] = MIXED ? __double2float_ru(r[q] * (1.0 + A.band_r2)) : __double2float_ru(r[q]);
+                    fl[q] = MIXED ? __double2float_rd(r[q] * (1.0 - A.band_r2)) : f[q];
                     if (tl * E + q < count) {
                         const uint32_t bv = __float_as_uint(f[q]);
                         lo = bv < lo ? bv : lo;
@@ -652,7 +649,7 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
                 bad = c_hi > N - LPI * SIDM_LEAF;
                 int mine = 0;
 #pragma unroll
-                for (int q = 0; q < E; ++q) mine += f[q] <= Tf;
+                for (int q = 0; q < E; ++q) mine += fl[q] <= Tf;
                 int pre = mine;                        // inclusive prefix over the team
                 for (int off = 1; off < TS; off <<= 1) {
                     const int o = __shfl_up(pre, off, TS);
@@ -663,15 +660,23 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
                 if (!bad) {
 #pragma unroll
                     for (int q = 0; q < E; ++q) {
-                        if (f[q] <= Tf) { L_r2[pos] = r[q]; L_j[pos] = jj[q]; ++pos; }
+                        if (fl[q] <= Tf) { L_r2[pos] = r[q]; L_j[pos] = jj[q]; ++pos; }
                     }
                     count = __shfl(pre, TS - 1, TS);
-                    kept = count;
                     T = fmin(T, (double)Tf);
                 }
             }
             const bool sort_now = all_done || (need && bad);
             if (sort_now) {
+                if constexpr (MIXED) {
+                    // the ranking is FP64: exact r^2 of every entry
+#pragma unroll
+                    for (int q = 0; q < E; ++q)
+                        if (jj[q] >= 0) {
+                            const int32_t j = jj[q];
+                            r[q] = sep2_sel<PERIODIC>(px, py, pz, A.xs[j], A.ys[j], A.zs[j], box);
+                        }
+                }
                 team_sort_r2<E, TS>(r, jj, tl);
                 // equal r^2 within the first K1 places: placed by ID below
                 const double nx0 = __shfl(r[0], (tl + 1) % TS, TS);
@@ -722,7 +727,6 @@ __global__ __launch_bounds__(256) void k_knn_team(KnnArgs A, int64_t base)
             if (sort_now) {
                 if (count >= K1) T = L_r2[K1 - 1];
                 count = count < K1 ? count : K1;
-                kept = count;
             }
             if (all_done) break;
         }
