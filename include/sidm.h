@@ -198,6 +198,14 @@ sidm_status sidm_advance_hernquist(sidm_ctx *ctx, double *x, double *y, double *
                                    int64_t n_active, double dt_cap, double gm, double a,
                                    double *dt_next, double *dt_step);
 
+/* Free drift between scattering steps of a box without gravity (the
+ * thermalisation box of sec. 5.2): x += v dt for all n particles, wrapped
+ * into [0, box) when the configuration is periodic.  Caller-owned device
+ * arrays of n doubles; needs a finite dt >= 0 and n <= cap_n; asynchronous on
+ * the context's stream, no allocation. */
+sidm_status sidm_drift(sidm_ctx *ctx, double *x, double *y, double *z, const double *vx,
+                       const double *vy, const double *vz, int64_t n, double dt);
+
 /* Wait for the context's stream, copy the statistics of the last
  * sidm_scatter_step into *out (may be NULL) and return the latched device
  * error (SIDM_OK if none).  Clears the latched error. */

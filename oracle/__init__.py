@@ -260,3 +260,17 @@ def advance_hernquist(x, y, z, vx, vy, vz, dt_sidm, dt_cap: float, gm: float, a:
     vy = vy + hd * (f * y)
     vz = vz + hd * (f * z)
     return x, y, z, vx, vy, vz, d
+
+
+def drift(x, y, z, vx, vy, vz, dt: float, periodic: bool, box: float):
+    """Free drift between scattering steps (the thermalisation box of the
+    paper's sec. 5.2 moves its particles ballistically): x + dt v, wrapped into
+    [0, box) when periodic."""
+    out = []
+    for p, v in ((x, vx), (y, vy), (z, vz)):
+        q = np.asarray(p, dtype=np.float64) + dt * np.asarray(v, dtype=np.float64)
+        if periodic:
+            q = q - box * np.floor(q / box)
+            q = np.where(q >= box, q - box, np.where(q < 0.0, 0.0, q))
+        out.append(q)
+    return tuple(out)

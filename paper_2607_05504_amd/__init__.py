@@ -79,7 +79,8 @@ class Timing(ctypes.Structure):
 # Every symbol include/sidm.h declares (tests check the library exports them).
 EXPORTS = ["sidm_footprint", "sidm_create", "sidm_destroy", "sidm_set_stream", "sidm_reconfigure",
            "sidm_last_error", "sidm_status_string", "sidm_build_tree", "sidm_find_ngb",
-           "sidm_scatter_step", "sidm_pair_timestep", "sidm_advance_hernquist", "sidm_sync",
+           "sidm_scatter_step", "sidm_pair_timestep", "sidm_advance_hernquist", "sidm_drift",
+           "sidm_sync",
            "sidm_timing_enable", "sidm_timing_read"]
 
 _lib = None
@@ -109,6 +110,7 @@ def lib():
         L.sidm_pair_timestep.argtypes = [P, P, i64, P, P, P]
         d = ctypes.c_double
         L.sidm_advance_hernquist.argtypes = [P, P, P, P, P, P, P, i64, P, i64, d, d, d, P, P]
+        L.sidm_drift.argtypes = [P, P, P, P, P, P, P, i64, d]
         L.sidm_sync.argtypes = [P, ctypes.POINTER(Stats)]
         L.sidm_timing_enable.argtypes = [P, ctypes.c_int]
         L.sidm_timing_read.argtypes = [P, ctypes.POINTER(Timing)]
@@ -255,6 +257,14 @@ class Context:
             self._h, _ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), int(x.shape[0]),
             _ptr(dt_sidm), int(n_active), float(dt_cap), float(gm), float(a), _ptr(dt_next),
             _ptr(dt_step)), "sidm_advance_hernquist")
+
+    def drift(self, x, y, z, vx, vy, vz, dt: float):
+        """Free drift x += v dt (wrapped into the periodic box)."""
+        f64 = self._torch.float64
+        for t, nm in ((x, "x"), (y, "y"), (z, "z"), (vx, "vx"), (vy, "vy"), (vz, "vz")):
+            self._dev(t, f64, nm)
+        self._check(lib().sidm_drift(self._h, _ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy),
+                                     _ptr(vz), int(x.shape[0]), float(dt)), "sidm_drift")
 
     def timing_enable(self, on: bool = True):
         self._check(lib().sidm_timing_enable(self._h, int(bool(on))), "sidm_timing_enable")

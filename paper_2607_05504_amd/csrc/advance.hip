@@ -12,6 +12,8 @@
 //   k_advance  every thread derives the same step length from that word,
 //              writes it as the next step's dt of the active particles, and
 //              moves its particles: v += g dt/2, x += v dt, v += g dt/2
+//   k_drift    a free drift for boxes without gravity (the thermalisation box
+//              of sec. 5.2), wrapped into the periodic box
 #include "sidm_internal.h"
 
 namespace {
@@ -83,7 +85,36 @@ __global__ __launch_bounds__(kBlock) void k_advance(double *x, double *y, double
     }
 }
 
+// free drift x += v dt, wrapped into [0, L) in a periodic box
+__global__ __launch_bounds__(kBlock) void k_drift(double *x, double *y, double *z,
+                                                  const double *__restrict__ vx,
+                                                  const double *__restrict__ vy,
+                                                  const double *__restrict__ vz, int64_t n,
+                                                  double dt, int periodic, double box)
+{
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlock) {
+        double p[3] = {x[t] + dt * vx[t], y[t] + dt * vy[t], z[t] + dt * vz[t]};
+        if (periodic) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                double q = p[d] - box * floor(p[d] / box);
+                p[d] = q >= box ? q - box : (q < 0.0 ? 0.0 : q);
+            }
+        }
+        x[t] = p[0]; y[t] = p[1]; z[t] = p[2];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_drift(sidm_ctx *c, double *x, double *y, double *z, const double *vx,
+                        const double *vy, const double *vz, int64_t n, double dt)
+{
+    k_drift<<<grid_for(n), kBlock, 0, c->stream>>>(x, y, z, vx, vy, vz, n, dt, c->cfg.periodic,
+                                                   c->cfg.box);
+    return hipGetLastError();
+}
 
 hipError_t launch_advance(sidm_ctx *c, double *x, double *y, double *z, double *vx, double *vy,
                           double *vz, int64_t n, const double *dt_sidm, int64_t n_active,

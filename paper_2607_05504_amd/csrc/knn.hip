@@ -163,7 +163,7 @@ __device__ __forceinline__ double window_bound(const KnnArgs &A, int64_t i, int6
 constexpr int kStackA = SIDM_MAX_LEVELS * (SIDM_TREE_FAN - 1) + 1;
 
 constexpr int kFront = 512;               // frontier capacity of the level walk
-constexpr int kLeafHits = 640;            // leaves a wavefront tests before its targets walk alone
+constexpr int kLeafHits = 960;            // leaves a wavefront tests before its targets walk alone
 
 __device__ __forceinline__ double wave_min(double v)
 {

@@ -441,6 +441,28 @@ sidm_status sidm_advance_hernquist(sidm_ctx *c, double *x, double *y, double *z,
     return SIDM_OK;
 }
 
+sidm_status sidm_drift(sidm_ctx *c, double *x, double *y, double *z, const double *vx,
+                       const double *vy, const double *vz, int64_t n, double dt)
+{
+    if (!c) return SIDM_E_INVAL;
+    if (n < 0 || n > c->cap_n) {
+        set_err(c, "drift: n=%lld cap_n=%lld", (long long)n, (long long)c->cap_n);
+        return SIDM_E_INVAL;
+    }
+    if (n > 0 && (!x || !y || !z || !vx || !vy || !vz)) {
+        set_err(c, "drift: NULL particle array");
+        return SIDM_E_INVAL;
+    }
+    if (!(dt >= 0.0) || !(dt < 1e300)) {
+        set_err(c, "drift: need a finite dt >= 0");
+        return SIDM_E_INVAL;
+    }
+    if (n == 0) return SIDM_OK;
+    hipError_t e = launch_drift(c, x, y, z, vx, vy, vz, n, dt);
+    if (e != hipSuccess) return hip_fail(c, e, "drift");
+    return SIDM_OK;
+}
+
 sidm_status sidm_sync(sidm_ctx *c, sidm_stats *out)
 {
     if (!c) return SIDM_E_INVAL;

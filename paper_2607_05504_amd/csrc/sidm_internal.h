@@ -304,3 +304,5 @@ hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, co
 hipError_t launch_advance(sidm_ctx *c, double *x, double *y, double *z, double *vx, double *vy,
                           double *vz, int64_t n, const double *dt_sidm, int64_t n_active,
                           double dt_cap, double gm, double a, double *dt_next, double *dt_step);
+hipError_t launch_drift(sidm_ctx *c, double *x, double *y, double *z, const double *vx,
+                        const double *vy, const double *vz, int64_t n, double dt);

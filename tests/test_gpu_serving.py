@@ -46,6 +46,21 @@ def test_advance_matches_oracle():
     ctx.close()
 
 
+def test_drift_matches_oracle():
+    import torch
+    from paper_2607_05504_amd import Context, runner
+    w = W.uniform_box(20000, ic_seed=302)
+    _announce("drift n=20000 periodic")
+    ds = runner.upload(w, "cuda")
+    ctx = Context(runner.config_for(w), w.n, w.n)
+    ctx.drift(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, 0.37)
+    ctx.sync()
+    ref = oracle.drift(w.x, w.y, w.z, w.vx, w.vy, w.vz, 0.37, True, 1.0)
+    for k, f in enumerate(("x", "y", "z")):
+        np.testing.assert_array_equal(getattr(ds, f).cpu().numpy(), ref[k])
+    ctx.close()
+
+
 def _reqs(ns, steps, gap=0.0, s0_scale=(1.0, 3.0, 0.3, 10.0, 0.1, 2.0)):
     base = W.hernquist_s0()
     return [W.Request(rid=r, arrival=r * gap, n=n, s0=base * s0_scale[r % len(s0_scale)],

@@ -422,3 +422,18 @@ def test_leapfrog_circular_orbit_energy():
     r = float(np.sqrt(x * x + y * y + z * z)[0])
     assert abs(r - r0) < 1e-4
     assert abs(float((energy(x, y, z, vx, vy, vz) - e0)[0])) < 1e-6
+
+
+def test_drift_wraps_into_the_box():
+    """Free drift: exact x + dt v in an open box; in a periodic box the result
+    lies in [0, L) and differs from x + dt v by a whole number of box lengths."""
+    rng = np.random.Generator(np.random.PCG64(8))
+    x, y, z = (rng.random(1000) for _ in range(3))
+    vx, vy, vz = (rng.normal(0, 3.0, 1000) for _ in range(3))
+    ox = oracle.drift(x, y, z, vx, vy, vz, 0.7, False, 1.0)
+    np.testing.assert_array_equal(ox[0], x + 0.7 * vx)
+    px = oracle.drift(x, y, z, vx, vy, vz, 0.7, True, 1.0)
+    for q, p, v in zip(px, (x, y, z), (vx, vy, vz)):
+        assert q.min() >= 0.0 and q.max() < 1.0
+        k = (p + 0.7 * v) - q
+        np.testing.assert_allclose(k, np.round(k), atol=1e-12)
