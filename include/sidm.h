@@ -75,7 +75,8 @@ typedef enum {
 } sidm_status;
 
 enum { SIDM_KERNEL_CUBIC_SPLINE = 0 };
-enum { SIDM_XSEC_CONST = 0, SIDM_XSEC_YUKAWA = 1 };
+enum { SIDM_XSEC_CONST = 0, SIDM_XSEC_YUKAWA = 1, SIDM_XSEC_TABLE = 2 };
+#define SIDM_XSEC_TABLE_MAX 256   /* nodes of a tabulated cross-section */
 enum { SIDM_MODEL_ELASTIC = 0, SIDM_MODEL_EPS = 1, SIDM_MODEL_TWO_STATE = 2 };
 enum { SIDM_FP64 = 0, SIDM_MIXED = 1 };
 
@@ -90,7 +91,8 @@ typedef struct {
     int32_t kernel;       /* SIDM_KERNEL_CUBIC_SPLINE                                     */
     int32_t periodic;     /* 1: periodic cube [0, box)^3 with minimum image; 0: open      */
     int32_t xsec;         /* SIDM_XSEC_CONST: sigma/m = sigma0;
-                             SIDM_XSEC_YUKAWA: sigma0 / (1 + (w/w0)^2)^2                  */
+                             SIDM_XSEC_YUKAWA: sigma0 / (1 + (w/w0)^2)^2;
+                             SIDM_XSEC_TABLE: the table below                              */
     int32_t model;        /* SIDM_MODEL_ELASTIC (eps = 1), SIDM_MODEL_EPS (constant eps),
                              SIDM_MODEL_TWO_STATE (ground/excited, gap delta per unit mass) */
     int32_t precision;    /* SIDM_FP64, or SIDM_MIXED (FP32 search/probability with an
@@ -102,6 +104,15 @@ typedef struct {
     double flag_band;     /* evaluations with |P - u| < flag_band are flagged (1e-9)      */
     double band_r2;       /* mixed form: relative r^2 band rechecked in FP64              */
     double band_p;        /* mixed form: relative |P - u| band rechecked in FP64          */
+    /* SIDM_XSEC_TABLE (a tabulated sigma(w)/m, as for a velocity-dependent model
+     * given as a table, sec. 6): xsec_n nodes (2..SIDM_XSEC_TABLE_MAX) at
+     * strictly increasing speeds xsec_w > 0 (typically log-spaced) with values
+     * xsec_sigma >= 0; between nodes sigma is linear in w, outside the range it
+     * is the end value.  HOST pointers, copied into the context by sidm_create
+     * and sidm_reconfigure (not read afterwards); ignored for other xsec. */
+    int32_t xsec_n;
+    const double *xsec_w;
+    const double *xsec_sigma;
 } sidm_config;
 
 typedef struct {

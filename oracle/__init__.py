@@ -22,6 +22,7 @@ _SRC = os.path.join(_HERE, "sidm_oracle.c")
 _LIB = os.path.join(_HERE, "libsidm_oracle.so")
 _lib = None
 
+XSEC_TABLE = 2
 CAND_ACCEPT0 = 1
 CAND_SCATTER = 2
 CAND_FLAGGED = 4
@@ -75,6 +76,8 @@ def lib():
         L.oref_pair_timestep.restype = i32
         L.oref_kick_pair.argtypes = [i32, i32, P, dbl, P, P, P, P, P, i32, dbl, dbl, u64, u32]
         L.oref_kick_pair.restype = None
+        L.oref_set_table.argtypes = [P, P, i32]
+        L.oref_set_table.restype = i32
         _lib = L
     return _lib
 
@@ -106,6 +109,20 @@ def kernel(r: float, h: float) -> float:
 
 def sigma(w: float, xsec: int, s0: float, w0: float) -> float:
     return lib().oref_sigma(w, xsec, s0, w0)
+
+
+def set_table(table_w, table_sigma) -> None:
+    """Load a tabulated cross-section (used when xsec is the table model)."""
+    tw = np.ascontiguousarray(table_w, dtype=np.float64)
+    ts = np.ascontiguousarray(table_sigma, dtype=np.float64)
+    st = lib().oref_set_table(_p(tw), _p(ts), int(tw.shape[0]))
+    if st != 0:
+        raise ValueError("invalid cross-section table")
+
+
+def _use_table(w) -> None:
+    if getattr(w, "table_w", None) is not None and int(w.xsec) == XSEC_TABLE:
+        set_table(w.table_w, w.table_sigma)
 
 
 def r2(pi, pj, periodic: bool, box: float) -> float:
@@ -162,6 +179,7 @@ def scatter_step(w, ngb, h, band: float = 1e-9, want_info: bool = True):
     """One scattering step on copies of w's velocities/states.
 
     Returns (vx, vy, vz, state, cand_info uint32[n_active, k] | None, stats dict)."""
+    _use_table(w)
     L = lib()
     x, y, z = _c(w.x, np.float64), _c(w.y, np.float64), _c(w.z, np.float64)
     vx, vy, vz = (np.array(w.vx, dtype=np.float64), np.array(w.vy, dtype=np.float64),
@@ -187,6 +205,7 @@ def scatter_step(w, ngb, h, band: float = 1e-9, want_info: bool = True):
 
 
 def pair_timestep(w, ngb, h, vx=None, vy=None, vz=None):
+    _use_table(w)
     L = lib()
     vx = _c(w.vx if vx is None else vx, np.float64)
     vy = _c(w.vy if vy is None else vy, np.float64)

@@ -52,6 +52,8 @@
 /* scatter models / cross-sections (integer values shared with the Python side) */
 #define OREF_XSEC_CONST 0
 #define OREF_XSEC_YUKAWA 1
+#define OREF_XSEC_TABLE 2
+#define OREF_TABLE_MAX 256
 #define OREF_MODEL_ELASTIC 0
 #define OREF_MODEL_EPS 1
 #define OREF_MODEL_TWO_STATE 2
@@ -163,8 +165,40 @@ double oref_kernel(double r, double h)
     return 0.0;
 }
 
+/* tabulated cross-section: node speeds (increasing) and values, set by
+ * oref_set_table before a step that uses it */
+static double oref_tw[OREF_TABLE_MAX], oref_ts[OREF_TABLE_MAX];
+static int oref_tn = 0;
+
+int oref_set_table(const double *w, const double *s, int n)
+{
+    if (n < 2 || n > OREF_TABLE_MAX) return OREF_E_INVAL;
+    for (int q = 0; q < n; ++q) {
+        if (!(w[q] > 0.0) || (q > 0 && !(w[q] > w[q - 1])) || !(s[q] >= 0.0)) return OREF_E_INVAL;
+        oref_tw[q] = w[q];
+        oref_ts[q] = s[q];
+    }
+    oref_tn = n;
+    return OREF_OK;
+}
+
+/* sigma/m of the table at speed w: the end value outside the nodes, else the
+ * straight line through the two nodes that bracket w (tw[k] <= w < tw[k+1]),
+ * found here by a linear scan */
+static double oref_sigma_table(double w)
+{
+    const int n = oref_tn;
+    if (!(w > oref_tw[0])) return oref_ts[0];
+    if (!(w < oref_tw[n - 1])) return oref_ts[n - 1];
+    int k = 0;
+    while (!(oref_tw[k + 1] > w)) ++k;
+    const double f = (w - oref_tw[k]) / (oref_tw[k + 1] - oref_tw[k]);
+    return oref_ts[k] + f * (oref_ts[k + 1] - oref_ts[k]);
+}
+
 double oref_sigma(double w, int xsec, double s0, double w0)
 {
+    if (xsec == OREF_XSEC_TABLE) return oref_sigma_table(w);
     if (xsec == OREF_XSEC_YUKAWA) {
         double x = w / w0;
         double d = 1.0 + x * x;

@@ -9,7 +9,10 @@ from __future__ import annotations
 
 import ctypes
 import os
+
 from typing import Optional
+
+import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsidm.so")
@@ -23,7 +26,7 @@ SIDM_E_OVERFLOW = -5
 SIDM_E_STATE = -6
 
 KERNEL_CUBIC_SPLINE = 0
-XSEC_CONST, XSEC_YUKAWA = 0, 1
+XSEC_CONST, XSEC_YUKAWA, XSEC_TABLE = 0, 1, 2
 MODEL_ELASTIC, MODEL_EPS, MODEL_TWO_STATE = 0, 1, 2
 FP64, MIXED = 0, 1
 
@@ -45,7 +48,9 @@ class Config(ctypes.Structure):
                 ("box", ctypes.c_double), ("sigma0", ctypes.c_double), ("w0", ctypes.c_double),
                 ("eps", ctypes.c_double), ("delta", ctypes.c_double),
                 ("c_sidm", ctypes.c_double), ("flag_band", ctypes.c_double),
-                ("band_r2", ctypes.c_double), ("band_p", ctypes.c_double)]
+                ("band_r2", ctypes.c_double), ("band_p", ctypes.c_double),
+                ("xsec_n", ctypes.c_int32), ("xsec_w", ctypes.c_void_p),
+                ("xsec_sigma", ctypes.c_void_p)]
 
 
 class Particles(ctypes.Structure):
@@ -123,10 +128,23 @@ def lib():
 
 def make_config(n_ngb=32, periodic=False, box=0.0, xsec=XSEC_CONST, sigma0=0.0, w0=1.0,
                 model=MODEL_ELASTIC, eps=1.0, delta=0.0, c_sidm=0.1, precision=FP64,
-                flag_band=1e-9, band_r2=1e-5, band_p=1e-5) -> Config:
-    return Config(int(n_ngb), KERNEL_CUBIC_SPLINE, int(bool(periodic)), int(xsec), int(model),
-                  int(precision), float(box), float(sigma0), float(w0), float(eps), float(delta),
-                  float(c_sidm), float(flag_band), float(band_r2), float(band_p))
+                flag_band=1e-9, band_r2=1e-5, band_p=1e-5, table_w=None,
+                table_sigma=None) -> Config:
+    """A sidm_config.  table_w / table_sigma (numpy arrays) give a tabulated
+    cross-section (xsec = XSEC_TABLE); the Config keeps them alive."""
+    tw = ts = None
+    n_t = 0
+    if table_w is not None:
+        tw = np.ascontiguousarray(table_w, dtype=np.float64)
+        ts = np.ascontiguousarray(table_sigma, dtype=np.float64)
+        n_t = int(tw.shape[0])
+    c = Config(int(n_ngb), KERNEL_CUBIC_SPLINE, int(bool(periodic)), int(xsec), int(model),
+               int(precision), float(box), float(sigma0), float(w0), float(eps), float(delta),
+               float(c_sidm), float(flag_band), float(band_r2), float(band_p), n_t,
+               tw.ctypes.data if tw is not None else None,
+               ts.ctypes.data if ts is not None else None)
+    c._tables = (tw, ts)
+    return c
 
 
 def footprint(cfg: Config, cap_n: int, cap_active: int) -> int:

@@ -72,6 +72,7 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(acc_count, 8, int32_t);
     ADD(dstats, 1, DevStats);
     ADD(derr, 1, unsigned int);
+    ADD(xt_w, SIDM_XSEC_TABLE_MAX, double); ADD(xt_s, SIDM_XSEC_TABLE_MAX, double);
     ADD(adv_min, 1, unsigned long long);
 #undef ADD
 }
@@ -91,7 +92,18 @@ sidm_status check_config(const sidm_config *cfg)
     if (cfg->n_ngb < 1 || cfg->n_ngb > 64) return SIDM_E_INVAL;
     if (cfg->kernel != SIDM_KERNEL_CUBIC_SPLINE) return SIDM_E_INVAL;
     if (cfg->periodic && !(cfg->box > 0.0)) return SIDM_E_INVAL;
-    if (cfg->xsec != SIDM_XSEC_CONST && cfg->xsec != SIDM_XSEC_YUKAWA) return SIDM_E_INVAL;
+    if (cfg->xsec != SIDM_XSEC_CONST && cfg->xsec != SIDM_XSEC_YUKAWA &&
+        cfg->xsec != SIDM_XSEC_TABLE)
+        return SIDM_E_INVAL;
+    if (cfg->xsec == SIDM_XSEC_TABLE) {
+        if (cfg->xsec_n < 2 || cfg->xsec_n > SIDM_XSEC_TABLE_MAX || !cfg->xsec_w || !cfg->xsec_sigma)
+            return SIDM_E_INVAL;
+        for (int q = 0; q < cfg->xsec_n; ++q) {
+            if (!(cfg->xsec_sigma[q] >= 0.0) || !(cfg->xsec_sigma[q] < 1e300)) return SIDM_E_INVAL;
+            if (!(cfg->xsec_w[q] > 0.0) || !(cfg->xsec_w[q] < 1e300)) return SIDM_E_INVAL;
+            if (q > 0 && !(cfg->xsec_w[q] > cfg->xsec_w[q - 1])) return SIDM_E_INVAL;
+        }
+    }
     if (cfg->xsec == SIDM_XSEC_YUKAWA && !(cfg->w0 > 0.0)) return SIDM_E_INVAL;
     if (cfg->model < SIDM_MODEL_ELASTIC || cfg->model > SIDM_MODEL_TWO_STATE) return SIDM_E_INVAL;
     if (cfg->precision != SIDM_FP64 && cfg->precision != SIDM_MIXED) return SIDM_E_INVAL;
@@ -137,6 +149,22 @@ const char *sidm_status_string(sidm_status s)
     case SIDM_E_STATE: return "call out of order";
     }
     return "unknown status";
+}
+
+// the tabulated cross-section into the context (its host pointers are not
+// kept: the caller's arrays may go away after sidm_create / sidm_reconfigure)
+static hipError_t copy_table(sidm_ctx *c)
+{
+    if (c->cfg.xsec != SIDM_XSEC_TABLE) {
+        c->cfg.xsec_w = c->cfg.xsec_sigma = nullptr;
+        return hipSuccess;
+    }
+    const size_t b = (size_t)c->cfg.xsec_n * sizeof(double);
+    hipError_t e = hipMemcpyAsync(c->xt_w, c->cfg.xsec_w, b, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->xt_s, c->cfg.xsec_sigma, b, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    c->cfg.xsec_w = c->cfg.xsec_sigma = nullptr;
+    return e;
 }
 
 sidm_status sidm_footprint(const sidm_config *cfg, int64_t cap_n, int64_t cap_active, size_t *bytes)
@@ -199,7 +227,8 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
     launch_fill_i32((int32_t *)c->derr, 0, 1, s);
     launch_fill_i32(c->acc_count, 0, 8, s);
     launch_fill_i32((int32_t *)c->dstats, 0, (int64_t)(sizeof(DevStats) / 4), s);
-    hipError_t e = hipStreamSynchronize(s);
+    hipError_t e = copy_table(c);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(base);
         (void)hipHostFree(c->hstats);
@@ -289,6 +318,9 @@ sidm_status sidm_reconfigure(sidm_ctx *c, const sidm_config *cfg)
     }
     c->cfg = *cfg;
     c->tree_ok = 0;          // a new configuration needs a new snapshot
+    hipError_t e = copy_table(c);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reconfigure");
     return SIDM_OK;
 }
 

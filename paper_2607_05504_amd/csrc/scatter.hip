@@ -55,10 +55,19 @@ struct StepArgs {
     const float *xo, *yo, *zo;
     const double *nodes;
     double band_p;
+    // tabulated cross-section (SIDM_XSEC_TABLE)
+    const double *xt_w, *xt_s;
+    int xt_n;
     uint64_t seed;
     uint32_t step;
     int k, periodic, xsec, model, has_mass;
 };
+
+__device__ __forceinline__ double sigma_of(const StepArgs &A, double w)
+{
+    if (A.xsec == SIDM_XSEC_TABLE) return xsec_table(w, A.xt_w, A.xt_s, A.xt_n);
+    return xsec_sigma(w, A.xsec, A.s0, A.w0);
+}
 
 __device__ __forceinline__ double mass_of(const StepArgs &A, int32_t s)
 {
@@ -262,7 +271,9 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                     const float vx = (float)(A.vxs[i] - A.vxs[j]), vy = (float)(A.vys[i] - A.vys[j]),
                                 vz = (float)(A.vzs[i] - A.vzs[j]);
                     const float w32 = sqrtf((vx * vx + vy * vy) + vz * vz);
-                    const float s32 = xsec_sigma32(w32, A.xsec, (float)A.s0, (float)A.w0);
+                    const float s32 = A.xsec == SIDM_XSEC_TABLE
+                                          ? (float)sigma_of(A, (double)w32)
+                                          : xsec_sigma32(w32, A.xsec, (float)A.s0, (float)A.w0);
                     const float f = (((0.5f * (float)mass_of(A, j)) * s32) * w32) * (float)dta;
                     const float P32 = f * cubic_spline32(r32, h32);
                     // band on the scale of P at the kernel's centre value, so
@@ -277,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                                                          A.zs[j], A.box));
                     W = cubic_spline(r, A.h[a]);
                     const double w = rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
-                    const double sig = xsec_sigma(w, A.xsec, A.s0, A.w0);
+                    const double sig = sigma_of(A, w);
                     P = pair_prob(mass_of(A, j), sig, w, W, dta);
                     n_rc += MIXED;
                 }
@@ -395,7 +406,7 @@ __device__ bool resolve_entry(const StepArgs &A, int t, int64_t e, int32_t *next
                      load_claim(&c2[i]) == ip && load_claim(&c2[j]) == ip;
     if (win) {
         const double w = rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
-        const double sig = xsec_sigma(w, A.xsec, A.s0, A.w0);
+        const double sig = sigma_of(A, w);
         const double P = pair_prob(mass_of(A, j), sig, w, L.W[e], L.dt[e]);
         const double u = L.u[e];
         const bool flagged = fabs(P - u) < A.band;
@@ -533,7 +544,7 @@ __device__ __forceinline__ double pair_rate(const StepArgs &A, double vix, doubl
     if (jc < 0 || jc >= A.n) { atomicOr(A.derr, DERR_INDEX); return 0.0; }
     const int32_t j = A.inv[jc];
     const double w = rel_speed(vix, viy, viz, A.vxs[j], A.vys[j], A.vzs[j]);
-    return w * xsec_sigma(w, A.xsec, A.s0, A.w0);
+    return w * sigma_of(A, w);
 }
 
 __device__ __forceinline__ double dt_from_rate(const StepArgs &A, int32_t i, double h, double rmax,
@@ -607,6 +618,7 @@ StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const dou
     A.k = c->cfg.n_ngb; A.periodic = c->cfg.periodic; A.xsec = c->cfg.xsec;
     A.model = c->cfg.model; A.has_mass = c->has_mass;
     A.xo = c->xo; A.yo = c->yo; A.zo = c->zo; A.nodes = c->nodes; A.band_p = c->cfg.band_p;
+    A.xt_w = c->xt_w; A.xt_s = c->xt_s; A.xt_n = c->cfg.xsec_n;
     return A;
 }
 

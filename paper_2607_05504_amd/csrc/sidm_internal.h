@@ -128,6 +128,7 @@ struct sidm_ctx {
 
     DevStats *dstats;
     unsigned int *derr;
+    double *xt_w, *xt_s;     // tabulated cross-section nodes [SIDM_XSEC_TABLE_MAX]
     unsigned long long *adv_min;   // served form: smallest per-pair bound of a step
     // opt-in event timing of the main kernels: up to SIDM_TIMING_RING launches
     // of each phase are bracketed between two sidm_timing_read calls
@@ -190,6 +191,21 @@ __device__ __forceinline__ double cubic_spline(double r, double h)
         return norm * (2.0 * ((t * t) * t));
     }
     return 0.0;
+}
+
+// Tabulated sigma(w)/m: linear in w between nodes tw[0..n) (increasing), the
+// end values outside; the node pair is found by bisection.
+__device__ __forceinline__ double xsec_table(double w, const double *tw, const double *ts, int n)
+{
+    if (!(w > tw[0])) return ts[0];
+    if (!(w < tw[n - 1])) return ts[n - 1];
+    int lo = 0, hi = n - 1;                // tw[lo] <= w < tw[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tw[mid] <= w) lo = mid; else hi = mid;
+    }
+    const double f = (w - tw[lo]) / (tw[hi] - tw[lo]);
+    return ts[lo] + f * (ts[hi] - ts[lo]);
 }
 
 __device__ __forceinline__ double xsec_sigma(double w, int xsec, double s0, double w0)

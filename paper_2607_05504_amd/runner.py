@@ -64,7 +64,9 @@ def upload(w, device="cuda") -> DeviceState:
 def config_for(w, precision=FP64, **kw):
     return make_config(n_ngb=w.n_ngb, periodic=w.periodic, box=w.box, xsec=w.xsec,
                        sigma0=w.sigma0, w0=w.w0, model=w.model, eps=w.eps, delta=w.delta,
-                       c_sidm=w.c_sidm, precision=precision, **kw)
+                       c_sidm=w.c_sidm, precision=precision,
+                       table_w=getattr(w, "table_w", None),
+                       table_sigma=getattr(w, "table_sigma", None), **kw)
 
 
 def alloc_out(ds: DeviceState, k: int, with_info: bool = False) -> StepOut:

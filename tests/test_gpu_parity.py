@@ -119,3 +119,24 @@ def test_determinism_and_permutation():
     for f in ("vx", "vy", "vz"):
         assert np.array_equal(c[f], a[f][perm]), f
     assert np.array_equal(c["info"], a["info"][order])
+
+
+@pytest.mark.parametrize("case", ["halo_table", "box_table_mixed"])
+def test_tabulated_cross_section(case):
+    """sigma(w)/m given as a 64-node table (linear in w between log-spaced
+    nodes): the same parity bar as the closed-form models."""
+    from paper_2607_05504_amd import MIXED, FP64
+    if case == "halo_table":
+        w = W.with_table(W.hernquist_bins(W.hernquist_halo(20000, ic_seed=206, philox_seed=16),
+                                          active_frac=0.25))
+        prec = FP64
+    else:
+        w = W.uniform_box(5000, ic_seed=207, scatters_per_particle=0.3)
+        w.xsec, w.w0 = W.XSEC_YUKAWA, 1.0
+        w = W.with_table(w)
+        prec = MIXED
+    _announce(f"tabulated cross-section {case} n={w.n} active={w.n_active}")
+    ref = oracle.full_step(w)
+    g = gpu_step(w, precision=prec)
+    assert_parity(w, g, ref, mixed=(prec == MIXED))
+    assert g["stats"]["n_events"] > 0

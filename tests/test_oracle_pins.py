@@ -437,3 +437,39 @@ def test_drift_wraps_into_the_box():
         assert q.min() >= 0.0 and q.max() < 1.0
         k = (p + 0.7 * v) - q
         np.testing.assert_allclose(k, np.round(k), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Tabulated cross-section
+# ---------------------------------------------------------------------------
+
+def test_table_interpolation_is_piecewise_linear_in_w():
+    """At the nodes the table's values, between them the straight line (checked
+    against numpy's linear interpolation), the end values outside."""
+    tw, ts = W.yukawa_table(3.0, 0.5, n_nodes=40)
+    oracle.set_table(tw, ts)
+    for v, s in zip(tw, ts):
+        assert oracle.sigma(float(v), W.XSEC_TABLE, 0.0, 1.0) == s
+    rng = np.random.Generator(np.random.PCG64(12))
+    ws = np.exp(rng.uniform(math.log(tw[0]), math.log(tw[-1]), 2000))
+    got = np.array([oracle.sigma(float(v), W.XSEC_TABLE, 0.0, 1.0) for v in ws])
+    np.testing.assert_allclose(got, np.interp(ws, tw, ts), rtol=1e-13, atol=1e-15)
+    assert oracle.sigma(0.0, W.XSEC_TABLE, 0.0, 1.0) == ts[0]
+    assert oracle.sigma(float(tw[-1]) * 10, W.XSEC_TABLE, 0.0, 1.0) == ts[-1]
+
+
+def test_dense_table_reproduces_the_model():
+    """A 256-node table of the Yukawa-like model agrees with the closed form
+    to within the linear-interpolation error bound max|sigma''| h^2 / 8."""
+    s0, w0 = 2.0, 0.5
+    tw, ts = W.yukawa_table(s0, w0, n_nodes=256)
+    oracle.set_table(tw, ts)
+    ws = np.logspace(-2.9, 1.9, 3000)
+    got = np.array([oracle.sigma(float(v), W.XSEC_TABLE, 0.0, 1.0) for v in ws])
+    exact = s0 / (1.0 + (ws / w0) ** 2) ** 2
+    k = np.searchsorted(tw, ws) - 1
+    h = tw[k + 1] - tw[k]
+    # |sigma''| <= 12 s0 / w0^2 for this model
+    bound = 12.0 * s0 / w0 ** 2 * h ** 2 / 8.0
+    assert np.all(np.abs(got - exact) <= bound + 1e-15)
+    assert np.max(np.abs(got - exact) / exact) < 1e-2     # 0.5% in the w^-4 tail

@@ -33,6 +33,7 @@ import numpy as np
 # integer values are part of the C ABI and of the oracle's interface).
 XSEC_CONST = 0
 XSEC_YUKAWA = 1
+XSEC_TABLE = 2
 MODEL_ELASTIC = 0
 MODEL_EPS = 1
 MODEL_TWO_STATE = 2
@@ -65,6 +66,8 @@ class Workload:
     seed: int = 1
     step: int = 0
     meta: dict = dataclasses.field(default_factory=dict)
+    table_w: Optional[np.ndarray] = None       # tabulated sigma(w)/m: node speeds
+    table_sigma: Optional[np.ndarray] = None   # and values (xsec = XSEC_TABLE)
 
     @property
     def n(self) -> int:
@@ -314,6 +317,30 @@ def hernquist_bins(w: Workload, active_frac: float = 0.125, dt_max: float = 2.0,
     out.name = w.name + "_bins"
     out.meta = dict(w.meta, b_star=b_star, dt_max=dt_max,
                     active_fraction=act.size / w.n)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Tabulated cross-section (a velocity-dependent model given as a table)
+# ---------------------------------------------------------------------------
+
+def yukawa_table(s0: float, w0: float, n_nodes: int = 64, w_min: float = 1e-3,
+                 w_max: float = 1e2):
+    """Nodes log-spaced in [w_min, w_max] with the values of
+    s0 / (1 + (w/w0)^2)^2 at the nodes: a table standing in for the tabulated
+    cross-sections of the paper's cosmological runs (whose table is not
+    available)."""
+    tw = np.logspace(math.log10(w_min), math.log10(w_max), n_nodes)
+    ts = s0 / (1.0 + (tw / w0) ** 2) ** 2
+    return tw, ts
+
+
+def with_table(w: Workload, n_nodes: int = 64) -> Workload:
+    """The same workload with its Yukawa-like cross-section given as a table."""
+    out = w.copy()
+    out.table_w, out.table_sigma = yukawa_table(w.sigma0, w.w0, n_nodes)
+    out.xsec = XSEC_TABLE
+    out.name = w.name + "_table"
     return out
 
 
