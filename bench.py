@@ -174,6 +174,8 @@ def main():
                          "offsets with FP64 rechecks in the bands, FP64 kicks")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="per-kernel HBM traffic measured with rocprofv3 counters")
+    ap.add_argument("--refit", action="store_true",
+                    help="after the first step, reuse the tree's order (sidm_refit_tree)")
     ap.add_argument("--requests", type=int, default=200, help="serving: requests in the stream")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second")
     ap.add_argument("--n-max", type=float, default=2e5, help="serving: largest halo (N)")
@@ -208,7 +210,7 @@ def main():
           flush=True)
 
     for t in range(args.warmup):
-        runner.run_step(ctx, ds, out, w.seed, w.step + t)
+        runner.run_step(ctx, ds, out, w.seed, w.step + t, refit=args.refit and t > 0)
     ctx.sync()
     torch.cuda.synchronize()
 
@@ -221,7 +223,8 @@ def main():
     t0 = time.perf_counter()
     for t in range(args.steps):
         ev[t][0].record()
-        runner.run_step(ctx, ds, out, w.seed, w.step + args.warmup + t)
+        runner.run_step(ctx, ds, out, w.seed, w.step + args.warmup + t,
+                        refit=args.refit and args.warmup + t > 0)
         ev[t][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -267,7 +270,8 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": w.n, "n_active": na,
-                   "n_ngb": k, "precision": args.precision, "touched": n_t},
+                   "n_ngb": k, "precision": args.precision, "touched": n_t,
+                   "tree": "refit" if args.refit else "rebuilt every step"},
         "p50_step_ms": float(np.percentile(step_ms, 50)),
         "p99_step_ms": float(np.percentile(step_ms, 99)),
         "phase_ms": {kk: round(v, 5) for kk, v in tim.items() if kk.endswith("_ms")},

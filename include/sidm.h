@@ -171,6 +171,14 @@ const char *sidm_status_string(sidm_status s);
  * and the last call of the step.  Requires n_ngb + 2 <= n <= cap_n. */
 sidm_status sidm_build_tree(sidm_ctx *ctx, const sidm_particles *p);
 
+/* Tree reuse across steps: the snapshot and every box are rebuilt from the
+ * particles' current positions and velocities, in the Morton order of the
+ * last sidm_build_tree (no sort).  Results stay exact; the search slows as
+ * the particles move away from that order.  Requires a sidm_build_tree of the
+ * same number of particles earlier on this context (SIDM_E_STATE otherwise);
+ * other requirements as for sidm_build_tree. */
+sidm_status sidm_refit_tree(sidm_ctx *ctx, const sidm_particles *p);
+
 /* For every active particle a (0 <= a < n_active, active[a] a particle
  * index, no duplicates): ngb[a*n_ngb + s] = its s-th nearest neighbour
  * (ascending (r^2, id)), h[a] = distance of the (n_ngb+1)-th. */

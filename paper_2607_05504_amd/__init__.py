@@ -84,7 +84,8 @@ class Timing(ctypes.Structure):
 # Every symbol include/sidm.h declares (tests check the library exports them).
 EXPORTS = ["sidm_footprint", "sidm_create", "sidm_destroy", "sidm_set_stream", "sidm_reconfigure",
            "sidm_last_error", "sidm_status_string", "sidm_build_tree", "sidm_find_ngb",
-           "sidm_scatter_step", "sidm_pair_timestep", "sidm_advance_hernquist", "sidm_drift",
+           "sidm_refit_tree", "sidm_scatter_step", "sidm_pair_timestep",
+           "sidm_advance_hernquist", "sidm_drift",
            "sidm_sync",
            "sidm_timing_enable", "sidm_timing_read"]
 
@@ -110,6 +111,7 @@ def lib():
         L.sidm_status_string.argtypes = [ctypes.c_int]
         L.sidm_status_string.restype = ctypes.c_char_p
         L.sidm_build_tree.argtypes = [P, ctypes.POINTER(Particles)]
+        L.sidm_refit_tree.argtypes = [P, ctypes.POINTER(Particles)]
         L.sidm_find_ngb.argtypes = [P, P, i64, P, P]
         L.sidm_scatter_step.argtypes = [P, ctypes.POINTER(Particles), P, i64, P, P, P, u64, u32, P]
         L.sidm_pair_timestep.argtypes = [P, P, i64, P, P, P]
@@ -216,6 +218,13 @@ class Context:
 
     # -- the four calls of the step ----------------------------------------------
     def build_tree(self, x, y, z, vx, vy, vz, ids, state=None, mass=None, m_scalar=0.0):
+        self._tree_call("sidm_build_tree", x, y, z, vx, vy, vz, ids, state, mass, m_scalar)
+
+    def refit_tree(self, x, y, z, vx, vy, vz, ids, state=None, mass=None, m_scalar=0.0):
+        """Tree reuse: snapshot and boxes in the order of the last build_tree."""
+        self._tree_call("sidm_refit_tree", x, y, z, vx, vy, vz, ids, state, mass, m_scalar)
+
+    def _tree_call(self, fn, x, y, z, vx, vy, vz, ids, state, mass, m_scalar):
         torch = self._torch
         f64 = torch.float64
         arrs = dict(x=self._dev(x, f64, "x"), y=self._dev(y, f64, "y"), z=self._dev(z, f64, "z"),
@@ -227,7 +236,7 @@ class Context:
                       _ptr(arrs["vy"]), _ptr(arrs["vz"]), _ptr(arrs["mass"]), float(m_scalar),
                       _ptr(arrs["id"]), _ptr(arrs["state"]), int(x.shape[0]))
         self._particles = (p, arrs)      # keep tensors alive while the snapshot is in use
-        self._check(lib().sidm_build_tree(self._h, ctypes.byref(p)), "sidm_build_tree")
+        self._check(getattr(lib(), fn)(self._h, ctypes.byref(p)), fn)
 
     def find_ngb(self, active, ngb, h):
         torch = self._torch

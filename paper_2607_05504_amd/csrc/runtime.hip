@@ -329,29 +329,57 @@ const char *sidm_last_error(const sidm_ctx *c)
     return c ? c->err : "null context";
 }
 
-sidm_status sidm_build_tree(sidm_ctx *c, const sidm_particles *p)
+static sidm_status check_particles(sidm_ctx *c, const sidm_particles *p, const char *who)
 {
-    if (!c) return SIDM_E_INVAL;
     if (!p || !p->x || !p->y || !p->z || !p->vx || !p->vy || !p->vz || !p->id) {
-        set_err(c, "build_tree: NULL particle array");
+        set_err(c, "%s: NULL particle array", who);
         return SIDM_E_INVAL;
     }
     if (p->n < c->cfg.n_ngb + 2) {
-        set_err(c, "build_tree: n=%lld < n_ngb+2", (long long)p->n);
+        set_err(c, "%s: n=%lld < n_ngb+2", who, (long long)p->n);
         return SIDM_E_INVAL;
     }
     if (p->n > c->cap_n) {
-        set_err(c, "build_tree: n=%lld above capacity %lld", (long long)p->n, (long long)c->cap_n);
+        set_err(c, "%s: n=%lld above capacity %lld", who, (long long)p->n, (long long)c->cap_n);
         return SIDM_E_CAPACITY;
     }
     if (!p->mass && !(p->m_scalar > 0.0)) {
-        set_err(c, "build_tree: no mass array and m_scalar <= 0");
+        set_err(c, "%s: no mass array and m_scalar <= 0", who);
         return SIDM_E_INVAL;
     }
     if (c->cfg.model == SIDM_MODEL_TWO_STATE && !p->state) {
-        set_err(c, "build_tree: two-state model needs a state array");
+        set_err(c, "%s: two-state model needs a state array", who);
         return SIDM_E_INVAL;
     }
+    return SIDM_OK;
+}
+
+sidm_status sidm_refit_tree(sidm_ctx *c, const sidm_particles *p)
+{
+    if (!c) return SIDM_E_INVAL;
+    sidm_status st = check_particles(c, p, "refit_tree");
+    if (st != SIDM_OK) return st;
+    if (c->sorted_n != p->n) {
+        set_err(c, "refit_tree: needs a sidm_build_tree of the same %lld particles first",
+                (long long)p->n);
+        return SIDM_E_STATE;
+    }
+    c->n = p->n;
+    c->has_mass = p->mass != nullptr;
+    c->m_scalar = p->m_scalar;
+    phase_begin(c, PH_TREE);
+    hipError_t e = launch_refit_tree(c, p);
+    phase_end(c, PH_TREE);
+    if (e != hipSuccess) return hip_fail(c, e, "refit_tree");
+    c->tree_ok = 1;
+    return SIDM_OK;
+}
+
+sidm_status sidm_build_tree(sidm_ctx *c, const sidm_particles *p)
+{
+    if (!c) return SIDM_E_INVAL;
+    sidm_status st = check_particles(c, p, "build_tree");
+    if (st != SIDM_OK) return st;
     c->n = p->n;
     c->has_mass = p->mass != nullptr;
     c->m_scalar = p->m_scalar;
@@ -360,6 +388,7 @@ sidm_status sidm_build_tree(sidm_ctx *c, const sidm_particles *p)
     phase_end(c, PH_TREE);
     if (e != hipSuccess) return hip_fail(c, e, "build_tree");
     c->tree_ok = 1;
+    c->sorted_n = p->n;
     return SIDM_OK;
 }
 

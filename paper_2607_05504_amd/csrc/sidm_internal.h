@@ -85,6 +85,7 @@ struct sidm_ctx {
     // snapshot of the particles in Morton order
     int64_t n;
     int tree_ok;
+    int64_t sorted_n;        // particles of the last full sort (0: none)
     int has_mass;
     double m_scalar;         // particle mass when no per-particle array is given
     double *xs, *ys, *zs, *vxs, *vys, *vzs, *ms;
@@ -291,6 +292,7 @@ inline void phase_end(sidm_ctx *c, int ph)
 // ---------------------------------------------------------------------------
 // tree.hip
 hipError_t launch_build_tree(sidm_ctx *c, const sidm_particles *p);
+hipError_t launch_refit_tree(sidm_ctx *c, const sidm_particles *p);
 hipError_t launch_map_active(sidm_ctx *c, const int32_t *active, int64_t n_active);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);

@@ -478,6 +478,18 @@ hipError_t launch_build_tree(sidm_ctx *c, const sidm_particles *p)
     }
     // six passes: the sorted order is back in key0/val0
     k_inverse<<<grid_for(n), kBlock, 0, s>>>(n, vin, c->perm, c->inv);
+    return launch_refit_tree(c, p);
+}
+
+// Snapshot in the order of the last sort, then the boxes bottom-up.  Alone
+// (sidm_refit_tree) it reuses that order for particles that have moved: the
+// boxes are those of the current positions, so searches stay exact; only the
+// tree's tightness degrades as the order ages.
+hipError_t launch_refit_tree(sidm_ctx *c, const sidm_particles *p)
+{
+    hipStream_t s = c->stream;
+    const int64_t n = p->n;
+    const sidm_config &cfg = c->cfg;
     // the scatter form wins while the snapshot (61 B a particle) fits the
     // caches that combine its scattered stores (measured: 10^6 faster,
     // 1.7e7 slower than the gather form)

@@ -80,10 +80,12 @@ def alloc_out(ds: DeviceState, k: int, with_info: bool = False) -> StepOut:
                               if with_info else None))
 
 
-def run_step(ctx: Context, ds: DeviceState, out: StepOut, seed: int, step: int):
-    """One whole step (all four calls) on ctx's stream; no host synchronisation."""
-    ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state,
-                   m_scalar=ds.mass)
+def run_step(ctx: Context, ds: DeviceState, out: StepOut, seed: int, step: int,
+             refit: bool = False):
+    """One whole step (all four calls) on ctx's stream; no host synchronisation.
+    refit: reuse the order of the last tree build (sidm_refit_tree)."""
+    tree = ctx.refit_tree if refit else ctx.build_tree
+    tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state, m_scalar=ds.mass)
     ctx.find_ngb(ds.active, out.ngb, out.h)
     ctx.scatter_step(ds.active, out.ngb, out.h, ds.dt, seed, step, cand_info=out.cand_info)
     ctx.pair_timestep(ds.active, out.ngb, out.h, out.dt_sidm)

@@ -140,3 +140,51 @@ def test_tabulated_cross_section(case):
     g = gpu_step(w, precision=prec)
     assert_parity(w, g, ref, mixed=(prec == MIXED))
     assert g["stats"]["n_events"] > 0
+
+
+@pytest.mark.parametrize("case", ["box", "halo"])
+def test_refit_after_particles_moved(case):
+    """Tree reuse: after the particles have moved (drift in the periodic box,
+    leapfrog steps in the halo) sidm_refit_tree keeps the old order, and the
+    step still matches the oracle on the new positions exactly."""
+    import torch
+    from paper_2607_05504_amd import Context, runner
+    if case == "box":
+        w = W.uniform_box(20000, ic_seed=208, scatters_per_particle=0.1)
+    else:
+        w = W.hernquist_bins(W.hernquist_halo(20000, ic_seed=209, philox_seed=18), active_frac=0.25)
+    _announce(f"refit after motion: {case} n={w.n}")
+    ds = runner.upload(w, "cuda")
+    ctx = Context(runner.config_for(w), w.n, w.n_active)
+    out = runner.alloc_out(ds, w.n_ngb, with_info=True)
+    ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state, m_scalar=ds.mass)
+    dts = torch.full((w.n,), 0.01, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        if case == "box":
+            ctx.drift(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, 0.05)
+        else:
+            ctx.advance_hernquist(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, dts, w.n, 0.25, 1.0, 1.0)
+    ctx.refit_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state, m_scalar=ds.mass)
+    ctx.find_ngb(ds.active, out.ngb, out.h)
+    ctx.scatter_step(ds.active, out.ngb, out.h, ds.dt, w.seed, w.step, cand_info=out.cand_info)
+    ctx.pair_timestep(ds.active, out.ngb, out.h, out.dt_sidm)
+    stats = ctx.sync()
+    moved = w.copy()
+    moved.x, moved.y, moved.z = ds.x.cpu().numpy(), ds.y.cpu().numpy(), ds.z.cpu().numpy()
+    torch.cuda.synchronize()
+    # the oracle starts from the moved positions and the pre-step velocities
+    pre = runner.upload(w, "cuda")
+    for _ in range(3):
+        if case == "box":
+            ctx.drift(pre.x, pre.y, pre.z, pre.vx, pre.vy, pre.vz, 0.05)
+        else:
+            ctx.advance_hernquist(pre.x, pre.y, pre.z, pre.vx, pre.vy, pre.vz, dts, w.n, 0.25, 1.0, 1.0)
+    ctx.sync()
+    moved.vx, moved.vy, moved.vz = pre.vx.cpu().numpy(), pre.vy.cpu().numpy(), pre.vz.cpu().numpy()
+    ref = oracle.full_step(moved)
+    g = dict(ngb=out.ngb.cpu().numpy(), h=out.h.cpu().numpy(), vx=ds.vx.cpu().numpy(),
+             vy=ds.vy.cpu().numpy(), vz=ds.vz.cpu().numpy(), state=ds.state.cpu().numpy(),
+             dt_sidm=out.dt_sidm.cpu().numpy(),
+             info=out.cand_info.cpu().numpy().view(np.uint32), stats=stats)
+    assert_parity(moved, g, ref)
+    ctx.close()
