@@ -77,7 +77,7 @@ typedef enum {
 enum { SIDM_KERNEL_CUBIC_SPLINE = 0 };
 enum { SIDM_XSEC_CONST = 0, SIDM_XSEC_YUKAWA = 1, SIDM_XSEC_TABLE = 2 };
 #define SIDM_XSEC_TABLE_MAX 256   /* nodes of a tabulated cross-section */
-enum { SIDM_MODEL_ELASTIC = 0, SIDM_MODEL_EPS = 1, SIDM_MODEL_TWO_STATE = 2 };
+enum { SIDM_MODEL_ELASTIC = 0, SIDM_MODEL_EPS = 1, SIDM_MODEL_TWO_STATE = 2, SIDM_MODEL_BEAM = 3 };
 enum { SIDM_FP64 = 0, SIDM_MIXED = 1 };
 
 /* per-candidate info word (optional output of sidm_scatter_step) */
@@ -94,7 +94,10 @@ typedef struct {
                              SIDM_XSEC_YUKAWA: sigma0 / (1 + (w/w0)^2)^2;
                              SIDM_XSEC_TABLE: the table below                              */
     int32_t model;        /* SIDM_MODEL_ELASTIC (eps = 1), SIDM_MODEL_EPS (constant eps),
-                             SIDM_MODEL_TWO_STATE (ground/excited, gap delta per unit mass) */
+                             SIDM_MODEL_TWO_STATE (ground/excited, gap delta per unit mass),
+                             SIDM_MODEL_BEAM (the fixed-target beam test of sec. 5.1:
+                             state 1 = beam, 0 = target; only beam-target pairs scatter,
+                             elastically, and the target does not recoil) */
     int32_t precision;    /* SIDM_FP64, or SIDM_MIXED (FP32 search/probability with an
                              FP64 recheck inside the bands below; kicks stay FP64)        */
     double box;           /* periodic box side L                                          */

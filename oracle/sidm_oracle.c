@@ -35,7 +35,8 @@
  *                   sphere and outgoing relative speed eps * w (sec. 4.1);
  *                   eps = 1 elastic, constant eps, or a two-state model whose
  *                   eps follows from the energy gap (sec. 4.1 relates eps to
- *                   the energy released or absorbed)
+ *                   the energy released or absorbed); or the fixed-target
+ *                   beam test of sec. 5.1 (no recoil of the target)
  *   timestep        dt_i = C_SIDM * 2 / (m_DM W(0, h_i) (v sigma/m)_max)
  *                   (Eq. sidm_timestep)
  */
@@ -57,6 +58,9 @@
 #define OREF_MODEL_ELASTIC 0
 #define OREF_MODEL_EPS 1
 #define OREF_MODEL_TWO_STATE 2
+#define OREF_MODEL_BEAM 3        /* fixed-target beam test (sec. 5.1): state 1 = beam,
+                                    0 = target; only beam-target pairs scatter and
+                                    the target does not recoil */
 
 /* per-candidate info word */
 #define OREF_CAND_ACCEPT0 1u   /* accepted by the step-start evaluation        */
@@ -334,6 +338,24 @@ static double scatter_eps(const phys_t *ph, double m_a, double m_b, double w,
 static void do_kick(const phys_t *ph, int32_t i, int32_t j, const double *mass, double m_scalar,
                     double *vx, double *vy, double *vz, uint8_t *state, const uint32_t *id)
 {
+    if (ph->model == OREF_MODEL_BEAM) {
+        /* no recoil: the target (state 0) is the infinitely heavy limit of the
+         * kick below -- its velocity stays, the beam particle's velocity
+         * relative to it turns to the drawn direction with unchanged speed
+         * (+e if the beam particle is the candidate's target i, -e if it is j) */
+        uint32_t xb[4];
+        pair_draw(ph->seed, ph->step, id[i], id[j],
+                  id[i] < id[j] ? PURPOSE_DIR_LO_HI : PURPOSE_DIR_HI_LO, xb);
+        double eb[3];
+        direction_from_draw(xb, eb);
+        double w = rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
+        if (state[i] == 1) {
+            vx[i] = vx[j] + w * eb[0]; vy[i] = vy[j] + w * eb[1]; vz[i] = vz[j] + w * eb[2];
+        } else {
+            vx[j] = vx[i] - w * eb[0]; vy[j] = vy[i] - w * eb[1]; vz[j] = vz[i] - w * eb[2];
+        }
+        return;
+    }
     double mi = mass ? mass[i] : m_scalar;
     double mj = mass ? mass[j] : m_scalar;
     uint32_t x[4];
@@ -416,6 +438,7 @@ int oref_scatter_step(int64_t n, const double *x, const double *y, const double 
             double sig = oref_sigma(w, xsec, s0, w0);
             double mj = mass ? mass[j] : m_scalar;
             double P = pair_probability(mj, sig, w, W, dt[a]);
+            if (model == OREF_MODEL_BEAM && state[i] == state[j]) P = 0.0;
             double u = oref_uniform_decision(seed, step, id[i], id[j]);
             if (P > st.max_p) st.max_p = P;
             if (P >= 1.0) st.n_p_ge_1++;
@@ -457,6 +480,7 @@ int oref_scatter_step(int64_t n, const double *x, const double *y, const double 
         double w = rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
         double sig = oref_sigma(w, xsec, s0, w0);
         double P = pair_probability(c->m_j, sig, w, c->W, c->dt);
+        if (model == OREF_MODEL_BEAM && state[i] == state[j]) P = 0.0;
         if (fabs(P - c->u) < band) {
             st.n_flagged++;
             if (cand_info) cand_info[c->c] |= OREF_CAND_FLAGGED;

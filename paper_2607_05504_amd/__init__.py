@@ -27,7 +27,7 @@ SIDM_E_STATE = -6
 
 KERNEL_CUBIC_SPLINE = 0
 XSEC_CONST, XSEC_YUKAWA, XSEC_TABLE = 0, 1, 2
-MODEL_ELASTIC, MODEL_EPS, MODEL_TWO_STATE = 0, 1, 2
+MODEL_ELASTIC, MODEL_EPS, MODEL_TWO_STATE, MODEL_BEAM = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 
 CAND_ACCEPT0 = 1

@@ -105,7 +105,7 @@ sidm_status check_config(const sidm_config *cfg)
         }
     }
     if (cfg->xsec == SIDM_XSEC_YUKAWA && !(cfg->w0 > 0.0)) return SIDM_E_INVAL;
-    if (cfg->model < SIDM_MODEL_ELASTIC || cfg->model > SIDM_MODEL_TWO_STATE) return SIDM_E_INVAL;
+    if (cfg->model < SIDM_MODEL_ELASTIC || cfg->model > SIDM_MODEL_BEAM) return SIDM_E_INVAL;
     if (cfg->precision != SIDM_FP64 && cfg->precision != SIDM_MIXED) return SIDM_E_INVAL;
     if (!(cfg->c_sidm > 0.0)) return SIDM_E_INVAL;
     if (!(cfg->flag_band >= 0.0)) return SIDM_E_INVAL;
@@ -347,8 +347,8 @@ static sidm_status check_particles(sidm_ctx *c, const sidm_particles *p, const c
         set_err(c, "%s: no mass array and m_scalar <= 0", who);
         return SIDM_E_INVAL;
     }
-    if (c->cfg.model == SIDM_MODEL_TWO_STATE && !p->state) {
-        set_err(c, "%s: two-state model needs a state array", who);
+    if ((c->cfg.model == SIDM_MODEL_TWO_STATE || c->cfg.model == SIDM_MODEL_BEAM) && !p->state) {
+        set_err(c, "%s: the two-state and beam models need a state array", who);
         return SIDM_E_INVAL;
     }
     return SIDM_OK;

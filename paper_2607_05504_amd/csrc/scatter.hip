@@ -128,6 +128,34 @@ __device__ double scatter_eps(const StepArgs &A, double ma, double mb, double w,
 
 // Kick of the pair (i, j) in Morton order, centre-of-momentum frame, direction
 // uniform on the sphere from the pair's direction draw.
+// beam model: only pairs of different populations scatter
+__device__ __forceinline__ bool pair_allowed(const StepArgs &A, int32_t i, int32_t j)
+{
+    return A.model != SIDM_MODEL_BEAM || A.sts[i] != A.sts[j];
+}
+
+// Fixed-target limit (beam model): the target (state 0) keeps its velocity;
+// the beam particle's velocity relative to it turns to the drawn direction
+// with unchanged speed (+e if the beam particle is i, -e if it is j: the
+// limit of the centre-of-momentum kick for an infinitely heavy target).
+__device__ void kick_beam(const StepArgs &A, int32_t i, int32_t j, double ex, double ey, double ez)
+{
+    const double vix = A.vxs[i], viy = A.vys[i], viz = A.vzs[i];
+    const double vjx = A.vxs[j], vjy = A.vys[j], vjz = A.vzs[j];
+    const double w = rel_speed(vix, viy, viz, vjx, vjy, vjz);
+    if (A.sts[i] == 1) {
+        const double nx = vjx + w * ex, ny = vjy + w * ey, nz = vjz + w * ez;
+        A.vxs[i] = nx; A.vys[i] = ny; A.vzs[i] = nz;
+        const int32_t oi = A.perm[i];
+        A.vx[oi] = nx; A.vy[oi] = ny; A.vz[oi] = nz;
+    } else {
+        const double nx = vix - w * ex, ny = viy - w * ey, nz = viz - w * ez;
+        A.vxs[j] = nx; A.vys[j] = ny; A.vzs[j] = nz;
+        const int32_t oj = A.perm[j];
+        A.vx[oj] = nx; A.vy[oj] = ny; A.vz[oj] = nz;
+    }
+}
+
 __device__ void kick(const StepArgs &A, int32_t i, int32_t j)
 {
     const uint32_t idi = A.ids[i], idj = A.ids[j];
@@ -140,6 +168,7 @@ __device__ void kick(const StepArgs &A, int32_t i, int32_t j)
     double s2 = 1.0 - cth * cth;
     double sth = sqrt(s2 > 0.0 ? s2 : 0.0);
     double ex = sth * cos(phi), ey = sth * sin(phi), ez = cth;
+    if (A.model == SIDM_MODEL_BEAM) { kick_beam(A, i, j, ex, ey, ez); return; }
 
     const double mi = mass_of(A, i), mj = mass_of(A, j);
     const double vix = A.vxs[i], viy = A.vys[i], viz = A.vzs[i];
@@ -280,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                     // the absolute FP32 error of W near its support edge is covered
                     const float Pmax = f * (8.0f / ((float)SIDM_PI * ((h32 * h32) * h32)));
                     const double near = A.band_p * fmax((double)Pmax, u) + A.band;
-                    P = (double)P32;
+                    P = pair_allowed(A, i, j) ? (double)P32 : 0.0;
                     exact = fabs(P - u) <= near;
                 }
                 if (exact) {
@@ -290,6 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                     const double w = rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
                     const double sig = sigma_of(A, w);
                     P = pair_prob(mass_of(A, j), sig, w, W, dta);
+                    if (!pair_allowed(A, i, j)) P = 0.0;
                     n_rc += MIXED;
                 }
                 const bool acc = u < P;
@@ -407,7 +437,7 @@ __device__ bool resolve_entry(const StepArgs &A, int t, int64_t e, int32_t *next
     if (win) {
         const double w = rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
         const double sig = sigma_of(A, w);
-        const double P = pair_prob(mass_of(A, j), sig, w, L.W[e], L.dt[e]);
+        const double P = pair_allowed(A, i, j) ? pair_prob(mass_of(A, j), sig, w, L.W[e], L.dt[e]) : 0.0;
         const double u = L.u[e];
         const bool flagged = fabs(P - u) < A.band;
         const bool hit = u < P;

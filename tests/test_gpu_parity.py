@@ -188,3 +188,13 @@ def test_refit_after_particles_moved(case):
              info=out.cand_info.cpu().numpy().view(np.uint32), stats=stats)
     assert_parity(moved, g, ref)
     ctx.close()
+
+
+def test_beam_model_small():
+    """The fixed-target beam model (sec. 5.1): the same parity bar."""
+    w = W.beam_lattice(n_side=10, n_beam=1500, rate_dt=0.3)
+    _announce(f"beam lattice n={w.n}")
+    ref = oracle.full_step(w)
+    g = gpu_step(w)
+    assert_parity(w, g, ref)
+    assert g["stats"]["n_events"] > 0

@@ -86,3 +86,43 @@ def test_mono_speed_box_thermalises():
     assert abs(e1 - e0) <= 1e-12 * e0
     p1 = w.mass * v1.sum(axis=1)
     assert np.abs(p1 - p0).max() <= 1e-12 * w.mass * np.abs(v0).sum()
+
+
+def test_beam_through_lattice():
+    """The paper's deflection test (sec. 5.1): beam particles crossing a
+    static lattice with fixed targets survive unscattered as
+    exp(-Gamma T), Gamma = rho_target (sigma/m) v, keep their speed, and leave
+    with directions uniform in cos(theta) about the beam axis."""
+    from scipy import stats as sps
+    from paper_2607_05504_amd import Context, runner
+    steps, gdt = 60, 0.05
+    w = W.beam_lattice(n_side=20, n_beam=8000, rate_dt=gdt)
+    n_t, n_b = w.meta["n_target"], w.meta["n_beam"]
+    print(f"[case] beam through lattice targets={n_t} beam={n_b} steps={steps}", flush=True)
+    ds = runner.upload(w, "cuda")
+    ctx = Context(runner.config_for(w), w.n, w.n_active)
+    out = runner.alloc_out(ds, w.n_ngb)
+    survivors = []
+    for t in range(steps):
+        runner.run_step(ctx, ds, out, w.seed, t)
+        ctx.drift(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, 0.01)
+        st = ctx.sync()
+        assert st["error"] == 0
+        vx = ds.vx[n_t:].cpu().numpy()
+        vy = ds.vy[n_t:].cpu().numpy()
+        survivors.append(int(np.sum((vx == 1.0) & (vy == 0.0))))
+    v = np.stack([ds.vx.cpu().numpy(), ds.vy.cpu().numpy(), ds.vz.cpu().numpy()])
+    ctx.close()
+    assert np.all(v[:, :n_t] == 0.0), "a target recoiled"
+    speed = np.sqrt((v[:, n_t:] ** 2).sum(axis=0))
+    np.testing.assert_allclose(speed, 1.0, rtol=1e-12)
+    for t in (9, 29, 59):
+        p = math.exp(-gdt * (t + 1))
+        expect = n_b * p
+        sd = math.sqrt(n_b * p * (1 - p))
+        print(f"[beam] step {t + 1}: survivors {survivors[t]} expected {expect:.1f} +- {sd:.1f}",
+              flush=True)
+        assert abs(survivors[t] - expect) < 5 * sd + 0.01 * expect, (t, survivors[t], expect)
+    scattered = ~((v[0, n_t:] == 1.0) & (v[1, n_t:] == 0.0))
+    cth = v[0, n_t:][scattered] / speed[scattered]
+    assert sps.kstest(cth, sps.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3

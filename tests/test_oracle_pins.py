@@ -473,3 +473,43 @@ def test_dense_table_reproduces_the_model():
     bound = 12.0 * s0 / w0 ** 2 * h ** 2 / 8.0
     assert np.all(np.abs(got - exact) <= bound + 1e-15)
     assert np.max(np.abs(got - exact) / exact) < 1e-2     # 0.5% in the w^-4 tail
+
+
+# ---------------------------------------------------------------------------
+# Fixed-target beam model (the deflection test of the paper's sec. 5.1)
+# ---------------------------------------------------------------------------
+
+def test_beam_kick_keeps_target_and_speed_and_is_isotropic():
+    """No recoil: the target keeps its velocity, the beam particle keeps its
+    speed relative to it, and the new direction is uniform in cos(theta)."""
+    from scipy import stats as sps
+    cth = []
+    for s in range(3000):
+        vx = np.array([0.1, 2.0]); vy = np.array([-0.2, 0.0]); vz = np.array([0.3, 0.0])
+        st = np.array([0, 1], dtype=np.uint8)
+        ids = np.array([5, 9 + s], dtype=np.uint32)
+        i, j = (0, 1) if s % 2 else (1, 0)
+        w0 = math.sqrt((2.0 - 0.1) ** 2 + 0.2 ** 2 + 0.3 ** 2)
+        oracle.kick_pair(i, j, vx, vy, vz, st, ids, 1.0, W.MODEL_BEAM, 1.0, 0.0, 77, s)
+        assert (vx[0], vy[0], vz[0]) == (0.1, -0.2, 0.3)
+        rel = np.array([vx[1] - 0.1, vy[1] + 0.2, vz[1] - 0.3])
+        assert abs(np.linalg.norm(rel) - w0) < 1e-13 * w0
+        cth.append(rel[2] / w0)
+    assert sps.kstest(np.array(cth), sps.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
+
+
+def test_beam_model_scatters_only_beam_target_pairs():
+    """A small beam-lattice step: no target moves, no kicked beam particle
+    changes speed, and every event pairs a beam particle with a target."""
+    w = W.beam_lattice(n_side=8, n_beam=600, rate_dt=0.3)
+    r = oracle.full_step(w)
+    n_t = w.meta["n_target"]
+    assert np.all(r["vx"][:n_t] == 0.0) and np.all(r["vy"][:n_t] == 0.0)
+    sp = np.sqrt(r["vx"][n_t:] ** 2 + r["vy"][n_t:] ** 2 + r["vz"][n_t:] ** 2)
+    np.testing.assert_allclose(sp, 1.0, rtol=1e-13)
+    assert r["stats"]["n_events"] > 0
+    hit = (r["info"] & oracle.CAND_SCATTER) != 0
+    a_idx, s_idx = np.nonzero(hit)
+    i = w.active[a_idx]
+    j = r["ngb"][a_idx, s_idx]
+    assert np.all(w.state[i] != w.state[j])

@@ -37,6 +37,7 @@ XSEC_TABLE = 2
 MODEL_ELASTIC = 0
 MODEL_EPS = 1
 MODEL_TWO_STATE = 2
+MODEL_BEAM = 3
 
 
 @dataclasses.dataclass
@@ -318,6 +319,42 @@ def hernquist_bins(w: Workload, active_frac: float = 0.125, dt_max: float = 2.0,
     out.meta = dict(w.meta, b_star=b_star, dt_max=dt_max,
                     active_fraction=act.size / w.n)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Beam through a static lattice (the deflection test of the paper's sec. 5.1)
+# ---------------------------------------------------------------------------
+
+def beam_lattice(n_side: int = 20, n_beam: int = 8000, ic_seed: int = 105, philox_seed: int = 5,
+                 speed: float = 1.0, rate_dt: float = 0.05, dt: float = 1.0,
+                 n_ngb: int = 32) -> Workload:
+    """Periodic unit box: n_side^3 targets at rest on a cubic lattice (state 0)
+    and n_beam beam particles at uniform random positions moving along +x with
+    the same speed (state 1); equal masses, total mass 1, all active.
+    sigma/m is set so that a beam particle scatters with probability about
+    rate_dt per step: Gamma dt = rho_target (sigma/m) v dt = rate_dt."""
+    rng = _rng(ic_seed)
+    n_t = n_side ** 3
+    g = (np.arange(n_side, dtype=np.float64) + 0.5) / n_side
+    gx, gy, gz = np.meshgrid(g, g, g, indexing="ij")
+    n = n_t + n_beam
+    x = np.concatenate([gx.ravel(), rng.random(n_beam)])
+    y = np.concatenate([gy.ravel(), rng.random(n_beam)])
+    z = np.concatenate([gz.ravel(), rng.random(n_beam)])
+    vx = np.concatenate([np.zeros(n_t), np.full(n_beam, speed)])
+    vy = np.zeros(n)
+    vz = np.zeros(n)
+    state = np.concatenate([np.zeros(n_t, dtype=np.uint8), np.ones(n_beam, dtype=np.uint8)])
+    m = 1.0 / n
+    rho_t = n_t * m
+    sigma_m = rate_dt / (rho_t * speed * dt)
+    return Workload(
+        name=f"beam_lattice_{n_side}_{n_beam}", x=x, y=y, z=z, vx=vx, vy=vy, vz=vz, mass=m,
+        id=np.arange(n, dtype=np.uint32), state=state, active=np.arange(n, dtype=np.int32),
+        dt=np.full(n, dt), periodic=True, box=1.0, n_ngb=n_ngb, xsec=XSEC_CONST,
+        sigma0=sigma_m, model=MODEL_BEAM, seed=philox_seed,
+        meta=dict(ic_seed=ic_seed, n_target=n_t, n_beam=n_beam, rho_target=rho_t,
+                  gamma_dt=rate_dt))
 
 
 # ---------------------------------------------------------------------------
