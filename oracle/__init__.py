@@ -78,6 +78,22 @@ def lib():
         L.oref_kick_pair.restype = None
         L.oref_set_table.argtypes = [P, P, i32]
         L.oref_set_table.restype = i32
+        L.oref_overlap_exact.argtypes = [dbl, dbl, dbl]
+        L.oref_overlap_exact.restype = dbl
+        L.oref_overlap_g.argtypes = [dbl, dbl, dbl]
+        L.oref_overlap_g.restype = dbl
+        L.oref_overlap_table.argtypes = [P]
+        L.oref_overlap_table.restype = None
+        L.oref_find_overlap.argtypes = [i64, P, P, P, i32, dbl, P, i64, P, i32, P, P]
+        L.oref_find_overlap.restype = i64
+        L.oref_scatter_overlap.argtypes = ([i64, P, P, P, P, P, P, P, dbl, P, P, i32, dbl,
+                                            P, i64, P, i32, P, P, P,
+                                            i32, dbl, dbl, i32, dbl, dbl, u64, u32, dbl,
+                                            P, ctypes.POINTER(_Stats)])
+        L.oref_scatter_overlap.restype = i32
+        L.oref_pair_timestep_overlap.argtypes = [i64, P, P, P, P, dbl, P, i64, P, i32, P, P,
+                                                 i32, dbl, dbl, dbl, P]
+        L.oref_pair_timestep_overlap.restype = i32
         _lib = L
     return _lib
 
@@ -293,3 +309,96 @@ def drift(x, y, z, vx, vy, vz, dt: float, periodic: bool, box: float):
             q = np.where(q >= box, q - box, np.where(q < 0.0, 0.0, q))
         out.append(q)
     return tuple(out)
+
+
+# ---------------------------------------------------------------------------
+# Kernel-overlap estimator (the paper's Eq. kernelOverlap and its appendix)
+OVERLAP_NA = 64     # alpha nodes a / 128, a = 0..64, over [0, 1/2]
+OVERLAP_NR = 256    # rho nodes b / 256, b = 0..256, over [0, 1]
+
+
+def overlap_exact(hi: float, hj: float, r: float) -> float:
+    """Overlap integral of two cubic splines, by quadrature exact for its
+    piecewise-polynomial integrand (no table)."""
+    return lib().oref_overlap_exact(float(hi), float(hj), float(r))
+
+
+def overlap_g(hi: float, hj: float, r: float) -> float:
+    """g_ij of the estimator: the tabulated dimensionless overlap, bilinear."""
+    return lib().oref_overlap_g(float(hi), float(hj), float(r))
+
+
+def overlap_table() -> np.ndarray:
+    """The oracle's table ghat[alpha node, rho node]."""
+    out = np.zeros((OVERLAP_NA + 1, OVERLAP_NR + 1), dtype=np.float64)
+    lib().oref_overlap_table(_p(out))
+    return out
+
+
+def smoothing_lengths(w, workers: int = -1) -> np.ndarray:
+    """h of every particle (active or not), in particle order."""
+    _, h = find_ngb(w, targets=np.arange(w.n, dtype=np.int32), workers=workers)
+    return h
+
+
+def find_overlap(w, h_all, max_ngb: int, targets=None):
+    """Overlap partners (r_ij < h_i + h_j) of ``targets`` (default w.active) by
+    brute force, in increasing particle index.  Returns (ngb int32[n_t,
+    max_ngb] padded with -1, count int32[n_t])."""
+    tg = _c(w.active if targets is None else targets, np.int32)
+    x, y, z = _c(w.x, np.float64), _c(w.y, np.float64), _c(w.z, np.float64)
+    ha = _c(h_all, np.float64)
+    ngb = np.full((tg.size, max_ngb), -1, dtype=np.int32)
+    cnt = np.zeros(tg.size, dtype=np.int32)
+    lib().oref_find_overlap(w.n, _p(x), _p(y), _p(z), int(w.periodic), float(w.box), _p(ha),
+                            tg.size, _p(tg), int(max_ngb), _p(ngb), _p(cnt))
+    return ngb, cnt
+
+
+def scatter_overlap(w, h_all, ngb, count, band: float = 1e-9, want_info: bool = True):
+    """One scattering step with the overlap estimator on copies of w's
+    velocities/states.  Returns (vx, vy, vz, state, cand_info | None, stats)."""
+    _use_table(w)
+    x, y, z = _c(w.x, np.float64), _c(w.y, np.float64), _c(w.z, np.float64)
+    vx, vy, vz = (np.array(w.vx, dtype=np.float64), np.array(w.vy, dtype=np.float64),
+                  np.array(w.vz, dtype=np.float64))
+    st = np.array(w.state, dtype=np.uint8)
+    ids = _c(w.id, np.uint32)
+    act = _c(w.active, np.int32)
+    ngb = _c(ngb, np.int32)
+    cnt = _c(count, np.int32)
+    ha = _c(h_all, np.float64)
+    dt = _c(w.dt, np.float64)
+    m = ngb.shape[1]
+    info = np.zeros((act.size, m), dtype=np.uint32) if want_info else None
+    stats = _Stats()
+    rc = lib().oref_scatter_overlap(w.n, _p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), None,
+                                    float(w.mass), _p(ids), _p(st), int(w.periodic),
+                                    float(w.box), _p(ha), act.size, _p(act), m, _p(ngb),
+                                    _p(cnt), _p(dt), int(w.xsec), float(w.sigma0),
+                                    float(w.w0), int(w.model), float(w.eps), float(w.delta),
+                                    int(w.seed), int(w.step), float(band), _p(info),
+                                    ctypes.byref(stats))
+    if rc != 0:
+        raise ValueError(f"oref_scatter_overlap failed ({rc})")
+    sd = {f: getattr(stats, f) for f, _ in _Stats._fields_}
+    return vx, vy, vz, st, info, sd
+
+
+def pair_timestep_overlap(w, h_all, ngb, count, vx=None, vy=None, vz=None):
+    _use_table(w)
+    vx = _c(w.vx if vx is None else vx, np.float64)
+    vy = _c(w.vy if vy is None else vy, np.float64)
+    vz = _c(w.vz if vz is None else vz, np.float64)
+    act = _c(w.active, np.int32)
+    ngb = _c(ngb, np.int32)
+    cnt = _c(count, np.int32)
+    ha = _c(h_all, np.float64)
+    out = np.zeros(act.size, dtype=np.float64)
+    rc = lib().oref_pair_timestep_overlap(w.n, _p(vx), _p(vy), _p(vz), None, float(w.mass),
+                                          _p(ha), act.size, _p(act), ngb.shape[1], _p(ngb),
+                                          _p(cnt), int(w.xsec), float(w.sigma0), float(w.w0),
+                                          float(w.c_sidm), _p(out))
+    if rc != 0:
+        raise ValueError(f"oref_pair_timestep_overlap failed ({rc})")
+    return out

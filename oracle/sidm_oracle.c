@@ -39,6 +39,11 @@
  *                   beam test of sec. 5.1 (no recoil of the target)
  *   timestep        dt_i = C_SIDM * 2 / (m_DM W(0, h_i) (v sigma/m)_max)
  *                   (Eq. sidm_timestep)
+ *   overlap         the kernel-overlap estimator (Eq. kernelOverlap and the
+ *                   appendix on it): partners are all j with
+ *                   r_ij < h_i + h_j, and g_ij is the overlap integral of the
+ *                   two splines, read from a table of the dimensionless
+ *                   overlap ghat(h_i/(h_i+h_j), r_ij/(h_i+h_j))
  */
 #include <math.h>
 #include <stdint.h>
@@ -407,33 +412,41 @@ typedef struct {
  * v and state are updated in place.  cand_info[n_active*k] (optional) gets the
  * per-candidate flags/pass index.  band: |P - u| < band flags an evaluation.
  */
-int oref_scatter_step(int64_t n, const double *x, const double *y, const double *z,
-                      double *vx, double *vy, double *vz, const double *mass, double m_scalar,
-                      const uint32_t *id, uint8_t *state, int periodic, double box,
-                      int64_t n_active, const int32_t *active, int k,
-                      const int32_t *ngb, const double *h, const double *dt,
-                      int xsec, double s0, double w0, int model, double eps, double delta,
-                      uint64_t seed, uint32_t step, double band,
-                      uint32_t *cand_info, oref_stats *stats)
+double oref_overlap_g(double hi, double hj, double r);
+
+/*
+ * Shared by both estimators.  Row a of ngb (stride entries) holds the
+ * partners of active[a]; count[a] of them are used (all stride when count is
+ * NULL).  The geometric factor is W(r_ij, h[a]) (one-sided), or the
+ * tabulated overlap of h_all[i] and h_all[j] when h_all is given.
+ */
+static int scatter_core(int64_t n, const double *x, const double *y, const double *z,
+                        double *vx, double *vy, double *vz, const double *mass, double m_scalar,
+                        const uint32_t *id, uint8_t *state, int periodic, double box,
+                        int64_t n_active, const int32_t *active, int stride, const int32_t *count,
+                        const int32_t *ngb, const double *h, const double *h_all, const double *dt,
+                        int xsec, double s0, double w0, int model, double eps, double delta,
+                        uint64_t seed, uint32_t step, double band,
+                        uint32_t *cand_info, oref_stats *stats)
 {
-    if (n < k + 2 || k < 1) return OREF_E_INVAL;
     phys_t ph = {xsec, s0, w0, model, eps, delta, seed, step};
-    int64_t n_cand = n_active * (int64_t)k;
     oref_stats st; memset(&st, 0, sizeof st);
-    st.n_cand = n_cand;
     int64_t cap = 1024, n_acc = 0;
     acc_t *acc = (acc_t *)malloc((size_t)cap * sizeof(acc_t));
     if (!acc) return OREF_E_NOMEM;
-    if (cand_info) memset(cand_info, 0, (size_t)n_cand * sizeof(uint32_t));
+    if (cand_info) memset(cand_info, 0, (size_t)(n_active * (int64_t)stride) * sizeof(uint32_t));
 
     /* evaluation 0: every candidate with the step-start velocities */
     for (int64_t a = 0; a < n_active; ++a) {
         int32_t i = active[a];
-        double mi_unused = 0; (void)mi_unused;
-        for (int s = 0; s < k; ++s) {
-            int32_t j = ngb[a * k + s];
+        int len = stride;
+        if (count && count[a] < len) len = count[a];
+        st.n_cand += len;
+        for (int s = 0; s < len; ++s) {
+            int64_t ci = a * (int64_t)stride + s;
+            int32_t j = ngb[ci];
             double r = sqrt(oref_r2(x[i], y[i], z[i], x[j], y[j], z[j], periodic, box));
-            double W = oref_kernel(r, h[a]);
+            double W = h_all ? oref_overlap_g(h_all[i], h_all[j], r) : oref_kernel(r, h[a]);
             double w = rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
             double sig = oref_sigma(w, xsec, s0, w0);
             double mj = mass ? mass[j] : m_scalar;
@@ -444,7 +457,7 @@ int oref_scatter_step(int64_t n, const double *x, const double *y, const double 
             if (P >= 1.0) st.n_p_ge_1++;
             if (fabs(P - u) < band) {
                 st.n_flagged++;
-                if (cand_info) cand_info[a * k + s] |= OREF_CAND_FLAGGED;
+                if (cand_info) cand_info[ci] |= OREF_CAND_FLAGGED;
             }
             if (u < P) {
                 if (n_acc == cap) {
@@ -455,10 +468,10 @@ int oref_scatter_step(int64_t n, const double *x, const double *y, const double 
                 }
                 uint32_t xr[4];
                 pair_draw(seed, step, id[i], id[j], PURPOSE_PRIORITY, xr);
-                acc_t e = {a * k + s, i, j, u, W, mj, dt[a],
+                acc_t e = {ci, i, j, u, W, mj, dt[a],
                            direction_word(xr, id[i] < id[j]), id[i], id[j]};
                 acc[n_acc++] = e;
-                if (cand_info) cand_info[a * k + s] |= OREF_CAND_ACCEPT0;
+                if (cand_info) cand_info[ci] |= OREF_CAND_ACCEPT0;
             }
         }
     }
@@ -498,6 +511,21 @@ int oref_scatter_step(int64_t n, const double *x, const double *y, const double 
     return OREF_OK;
 }
 
+int oref_scatter_step(int64_t n, const double *x, const double *y, const double *z,
+                      double *vx, double *vy, double *vz, const double *mass, double m_scalar,
+                      const uint32_t *id, uint8_t *state, int periodic, double box,
+                      int64_t n_active, const int32_t *active, int k,
+                      const int32_t *ngb, const double *h, const double *dt,
+                      int xsec, double s0, double w0, int model, double eps, double delta,
+                      uint64_t seed, uint32_t step, double band,
+                      uint32_t *cand_info, oref_stats *stats)
+{
+    if (n < k + 2 || k < 1) return OREF_E_INVAL;
+    return scatter_core(n, x, y, z, vx, vy, vz, mass, m_scalar, id, state, periodic, box,
+                        n_active, active, k, NULL, ngb, h, NULL, dt, xsec, s0, w0, model, eps,
+                        delta, seed, step, band, cand_info, stats);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Per-pair timestep (Eq. sidm_timestep), with the current velocities:        */
 /* dt_i = C 2 / (m_DM W(0,h_i) max_j w_ij sigma(w_ij)/m); +inf if the max is 0 */
@@ -532,4 +560,251 @@ void oref_kick_pair(int32_t i, int32_t j, const double *mass, double m_scalar,
 {
     phys_t ph = {0, 0.0, 1.0, model, eps, delta, seed, step};
     do_kick(&ph, i, j, mass, m_scalar, vx, vy, vz, state, id);
+}
+
+/* ======================================================================== */
+/* Kernel-overlap estimator (Eq. kernelOverlap; the appendix comparing it   */
+/* with the one-sided spline)                                                */
+/* ======================================================================== */
+#define OREF_OVL_NA 64      /* alpha = a / (2 NA), a = 0..NA, over [0, 1/2] */
+#define OREF_OVL_NR 256     /* rho = b / NR, b = 0..NR, over [0, 1]          */
+
+/* n-point Gauss-Legendre nodes and weights on [-1, 1]: the roots of P_n by
+ * Newton's method from the usual cosine guesses, P_n and P_{n-1} from the
+ * three-term recurrence, weight 2 / ((1 - x^2) P_n'(x)^2) */
+static void gauss_legendre(int n, double *xn, double *wn)
+{
+    for (int i = 0; i < n; ++i) {
+        double t = cos(OREF_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 1; k < n; ++k) {
+                double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+            double step = p1 / dp;
+            t -= step;
+            if (fabs(step) < 1e-17) break;
+        }
+        xn[i] = t;
+        wn[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+static double gl4x[4], gl4w[4], gl8x[8], gl8w[8];
+static int gl_ready = 0;
+
+static void gl_init(void)
+{
+    if (gl_ready) return;
+    gauss_legendre(4, gl4x, gl4w);
+    gauss_legendre(8, gl8x, gl8w);
+    gl_ready = 1;
+}
+
+/* int_a^b t W(t, hj) dt; the integrand is a polynomial of degree 4 on each
+ * side of hj/2, so a 4-point rule per piece is exact */
+static double inner_integral(double a, double b, double hj)
+{
+    if (b > hj) b = hj;
+    if (!(a < b)) return 0.0;
+    double cut[3] = {a, b, b};
+    int nc = 2;
+    if (a < 0.5 * hj && 0.5 * hj < b) { cut[1] = 0.5 * hj; cut[2] = b; nc = 3; }
+    double sum = 0.0;
+    for (int p = 0; p + 1 < nc; ++p) {
+        double mid = 0.5 * (cut[p] + cut[p + 1]), half = 0.5 * (cut[p + 1] - cut[p]);
+        for (int q = 0; q < 4; ++q) {
+            double t = mid + half * gl4x[q];
+            sum += half * gl4w[q] * (t * oref_kernel(t, hj));
+        }
+    }
+    return sum;
+}
+
+/* sort a short array in place */
+static void sort_small(double *v, int n)
+{
+    for (int a = 1; a < n; ++a) {
+        double t = v[a];
+        int b = a - 1;
+        while (b >= 0 && v[b] > t) { v[b + 1] = v[b]; --b; }
+        v[b + 1] = t;
+    }
+}
+
+/*
+ * g(hi, hj, r) = int W(|x - x_i|, hi) W(|x - x_j|, hj) d^3x with r = |x_i - x_j|
+ * (Eq. kernelOverlap), evaluated without tables.  In spherical coordinates
+ * about x_i, with s = |x - x_i| and t = |x - x_j|, the volume element is
+ * (2 pi / r) s t ds dt, so for r > 0
+ *     g = (2 pi / r) int_0^hi s W(s, hi) [ int_{|r-s|}^{r+s} t W(t, hj) dt ] ds,
+ * and g(r = 0) = 4 pi int s^2 W(s, hi) W(s, hj) ds.  The outer integrand is a
+ * piecewise polynomial of degree <= 9 whose pieces end where s, |r - s| or
+ * r + s meet hi/2, hj/2 or hj; an 8-point rule per piece is exact.
+ */
+double oref_overlap_exact(double hi, double hj, double r)
+{
+    gl_init();
+    if (!(hi > 0.0) || !(hj > 0.0) || !(r < hi + hj)) return 0.0;
+    if (r == 0.0) {
+        double top = hi < hj ? hi : hj;
+        double cut[4] = {0.0, 0.5 * hi, 0.5 * hj, top};
+        sort_small(cut, 4);
+        double sum = 0.0;
+        for (int p = 0; p < 3; ++p) {
+            double lo = cut[p], hi2 = cut[p + 1] < top ? cut[p + 1] : top;
+            if (!(hi2 > lo)) continue;
+            double mid = 0.5 * (lo + hi2), half = 0.5 * (hi2 - lo);
+            for (int q = 0; q < 8; ++q) {
+                double s = mid + half * gl8x[q];
+                sum += half * gl8w[q] * ((s * s) * oref_kernel(s, hi) * oref_kernel(s, hj));
+            }
+        }
+        return 4.0 * OREF_PI * sum;
+    }
+    double cand[10] = {0.0, hi, 0.5 * hi, r, r - 0.5 * hj, r + 0.5 * hj, r - hj, r + hj,
+                       0.5 * hj - r, hj - r};
+    double cut[10];
+    int nc = 0;
+    for (int c = 0; c < 10; ++c)
+        if (cand[c] >= 0.0 && cand[c] <= hi) cut[nc++] = cand[c];
+    sort_small(cut, nc);
+    double sum = 0.0;
+    for (int p = 0; p + 1 < nc; ++p) {
+        if (!(cut[p + 1] > cut[p])) continue;
+        double mid = 0.5 * (cut[p] + cut[p + 1]), half = 0.5 * (cut[p + 1] - cut[p]);
+        for (int q = 0; q < 8; ++q) {
+            double s = mid + half * gl8x[q];
+            double in = inner_integral(fabs(r - s), r + s, hj);
+            sum += half * gl8w[q] * (s * oref_kernel(s, hi) * in);
+        }
+    }
+    return (2.0 * OREF_PI / r) * sum;
+}
+
+/* Table of the dimensionless overlap ghat(alpha, rho) = H^3 g(alpha H,
+ * (1 - alpha) H, rho H), H = h_i + h_j, which by symmetry needs only
+ * alpha = min(h_i, h_j) / H in [0, 1/2].  alpha = 0 is the limit of a point
+ * partner, g = W(r, H). */
+static double ovl_tab[(OREF_OVL_NA + 1) * (OREF_OVL_NR + 1)];
+static int ovl_ready = 0;
+
+static void ovl_build(void)
+{
+    if (ovl_ready) return;
+    for (int a = 0; a <= OREF_OVL_NA; ++a) {
+        double al = (double)a / (2.0 * OREF_OVL_NA);
+        for (int b = 0; b <= OREF_OVL_NR; ++b) {
+            double rho = (double)b / OREF_OVL_NR;
+            ovl_tab[a * (OREF_OVL_NR + 1) + b] =
+                a == 0 ? oref_kernel(rho, 1.0) : oref_overlap_exact(al, 1.0 - al, rho);
+        }
+    }
+    ovl_ready = 1;
+}
+
+void oref_overlap_table(double *out)
+{
+    ovl_build();
+    memcpy(out, ovl_tab, sizeof ovl_tab);
+}
+
+/* g_ij of the estimator: the table, bilinear in (alpha, rho), over H^3;
+ * zero for r >= h_i + h_j */
+double oref_overlap_g(double hi, double hj, double r)
+{
+    ovl_build();
+    double H = hi + hj;
+    double al = (hi < hj ? hi : hj) / H;
+    double rho = r / H;
+    if (!(rho < 1.0)) return 0.0;
+    double fa = al * (2.0 * OREF_OVL_NA), fr = rho * OREF_OVL_NR;
+    int ia = (int)fa, ir = (int)fr;
+    if (ia > OREF_OVL_NA - 1) ia = OREF_OVL_NA - 1;
+    if (ir > OREF_OVL_NR - 1) ir = OREF_OVL_NR - 1;
+    double ta = fa - ia, tr = fr - ir;
+    const double *t0 = ovl_tab + ia * (OREF_OVL_NR + 1) + ir;
+    const double *t1 = t0 + (OREF_OVL_NR + 1);
+    double g0 = t0[0] + tr * (t0[1] - t0[0]);
+    double g1 = t1[0] + tr * (t1[1] - t1[0]);
+    return (g0 + ta * (g1 - g0)) / ((H * H) * H);
+}
+
+/*
+ * Partners of the overlap estimator by brute force: every j != i with
+ * r_ij < h_i + h_j (tested as r^2 < (h_i + h_j)^2), in increasing j.  Row a
+ * holds up to max_ngb of them, padded with -1; count[a] is the full number.
+ * Returns the largest count.
+ */
+int64_t oref_find_overlap(int64_t n, const double *x, const double *y, const double *z,
+                          int periodic, double box, const double *h_all, int64_t n_active,
+                          const int32_t *active, int32_t max_ngb, int32_t *ngb, int32_t *count)
+{
+    int64_t most = 0;
+    for (int64_t a = 0; a < n_active; ++a) {
+        int32_t i = active[a];
+        int32_t c = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r2 = oref_r2(x[i], y[i], z[i], x[j], y[j], z[j], periodic, box);
+            double s = h_all[i] + h_all[j];
+            if (r2 < s * s) {
+                if (c < max_ngb) ngb[a * (int64_t)max_ngb + c] = (int32_t)j;
+                c++;
+            }
+        }
+        for (int32_t t = c; t < max_ngb; ++t) ngb[a * (int64_t)max_ngb + t] = -1;
+        count[a] = c;
+        if (c > most) most = c;
+    }
+    return most;
+}
+
+int oref_scatter_overlap(int64_t n, const double *x, const double *y, const double *z,
+                         double *vx, double *vy, double *vz, const double *mass, double m_scalar,
+                         const uint32_t *id, uint8_t *state, int periodic, double box,
+                         const double *h_all, int64_t n_active, const int32_t *active,
+                         int32_t max_ngb, const int32_t *ngb, const int32_t *count,
+                         const double *dt, int xsec, double s0, double w0, int model, double eps,
+                         double delta, uint64_t seed, uint32_t step, double band,
+                         uint32_t *cand_info, oref_stats *stats)
+{
+    if (max_ngb < 1 || !h_all || !count) return OREF_E_INVAL;
+    return scatter_core(n, x, y, z, vx, vy, vz, mass, m_scalar, id, state, periodic, box,
+                        n_active, active, max_ngb, count, ngb, NULL, h_all, dt, xsec, s0, w0,
+                        model, eps, delta, seed, step, band, cand_info, stats);
+}
+
+/*
+ * Per-pair timestep with the overlap estimator: the bound of Eq. sidm_timestep
+ * with the kernel's centre value W(0, h_i) replaced by the pair's overlap at
+ * zero separation, g_ij(0) (the largest value g_ij takes):
+ *     dt_i = C_SIDM * 2 / (m_i max_j [g_ij(0) w_ij sigma(w_ij)/m]),
+ * so that P(i|j) <= C_SIDM for every partner while the velocities hold.
+ */
+int oref_pair_timestep_overlap(int64_t n, const double *vx, const double *vy, const double *vz,
+                               const double *mass, double m_scalar, const double *h_all,
+                               int64_t n_active, const int32_t *active, int32_t max_ngb,
+                               const int32_t *ngb, const int32_t *count, int xsec, double s0,
+                               double w0, double c_sidm, double *dt_out)
+{
+    (void)n;
+    for (int64_t a = 0; a < n_active; ++a) {
+        int32_t i = active[a];
+        int len = count[a] < max_ngb ? count[a] : max_ngb;
+        double qmax = 0.0;
+        for (int s = 0; s < len; ++s) {
+            int32_t j = ngb[a * (int64_t)max_ngb + s];
+            double w = rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
+            double q = oref_overlap_g(h_all[i], h_all[j], 0.0) * (w * oref_sigma(w, xsec, s0, w0));
+            if (q > qmax) qmax = q;
+        }
+        double mi = mass ? mass[i] : m_scalar;
+        dt_out[a] = qmax > 0.0 ? (2.0 * c_sidm) / (mi * qmax) : INFINITY;
+    }
+    return OREF_OK;
 }
