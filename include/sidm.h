@@ -70,7 +70,7 @@ typedef enum {
     SIDM_E_NOMEM = -2,     /* device allocation failed in sidm_create                  */
     SIDM_E_DEVICE = -3,    /* HIP runtime error                                        */
     SIDM_E_CAPACITY = -4,  /* n or n_active above the context's capacity               */
-    SIDM_E_OVERFLOW = -5,  /* accepted-candidate list overflowed (results invalid)     */
+    SIDM_E_OVERFLOW = -5,  /* accepted-candidate list or an overlap row overflowed     */
     SIDM_E_STATE = -6      /* call out of order (e.g. find_ngb before build_tree)      */
 } sidm_status;
 
@@ -79,6 +79,13 @@ enum { SIDM_XSEC_CONST = 0, SIDM_XSEC_YUKAWA = 1, SIDM_XSEC_TABLE = 2 };
 #define SIDM_XSEC_TABLE_MAX 256   /* nodes of a tabulated cross-section */
 enum { SIDM_MODEL_ELASTIC = 0, SIDM_MODEL_EPS = 1, SIDM_MODEL_TWO_STATE = 2, SIDM_MODEL_BEAM = 3 };
 enum { SIDM_FP64 = 0, SIDM_MIXED = 1 };
+/* scattering-rate estimator (sec. 4.2): the fiducial one-sided kernel, or the
+ * kernel overlap of Eq. kernelOverlap (the *_overlap calls) */
+enum { SIDM_EST_ONE_SIDED = 0, SIDM_EST_OVERLAP = 1 };
+/* the overlap estimator's table of ghat(alpha, rho): alpha = a / (2 NA),
+ * a = 0..NA; rho = b / NR, b = 0..NR; stored alpha-major */
+#define SIDM_OVERLAP_NA 64
+#define SIDM_OVERLAP_NR 256
 
 /* per-candidate info word (optional output of sidm_scatter_step) */
 #define SIDM_CAND_ACCEPT0 1u   /* accepted by the step-start evaluation          */
@@ -116,6 +123,12 @@ typedef struct {
     int32_t xsec_n;
     const double *xsec_w;
     const double *xsec_sigma;
+    /* SIDM_EST_ONE_SIDED (0; sidm_scatter_step's g_ij = W(r_ij, h_i)) or
+     * SIDM_EST_OVERLAP, which also reserves what the *_overlap calls need (a
+     * Morton-ordered copy of every particle's h, the largest h of every tree
+     * node, the ghat table; 8 bytes a particle more) and requires
+     * precision SIDM_FP64. */
+    int32_t estimator;
 } sidm_config;
 
 typedef struct {
@@ -203,6 +216,60 @@ sidm_status sidm_scatter_step(sidm_ctx *ctx, sidm_particles *p, const int32_t *a
  * the current (post-kick) velocities; +inf when the maximum is 0. */
 sidm_status sidm_pair_timestep(sidm_ctx *ctx, const int32_t *active, int64_t n_active,
                                const int32_t *ngb, const double *h, double *dt_sidm);
+
+/* ---- Kernel-overlap estimator (Eq. kernelOverlap; the paper's appendix on
+ * the overlap kernel) -------------------------------------------------------
+ * g_ij is the overlap integral of the two particles' cubic splines,
+ * int W(|x - x_i|, h_i) W(|x - x_j|, h_j) d^3x, non-zero for r_ij < h_i + h_j.
+ * These calls need a context created with estimator SIDM_EST_OVERLAP
+ * (SIDM_E_STATE otherwise) and a sidm_build_tree of the current positions.
+ * h_all[n] (device, caller order) holds every particle's smoothing length,
+ * active or not (> 0 and finite; for example sidm_find_ngb's h over all
+ * particles, or the last value of those not active now). */
+
+/* Partners of the active particles: for active[a] = i, every j != i with
+ * r_ij < h_i + h_j, tested as r^2 < (h_i + h_j)^2 in FP64 with r^2 as in
+ * sidm_find_ngb.  The tree's nodes first get the largest h below them (the
+ * search region is h_i + that h_max).  Row a of ngb (max_ngb >= 1 entries,
+ * caller indices) receives min(count[a], max_ngb) partners in an order fixed
+ * by the tree (not sorted), count[a] their full number.  A row longer than
+ * max_ngb keeps its first max_ngb and latches SIDM_E_OVERFLOW (sidm_sync);
+ * an h that is not > 0 and finite latches SIDM_E_INVAL. */
+sidm_status sidm_find_overlap(sidm_ctx *ctx, const double *h_all, const int32_t *active,
+                              int64_t n_active, int32_t max_ngb, int32_t *ngb, int32_t *count);
+
+/* Scattering step with the overlap estimator: sidm_scatter_step with the
+ * partners of row a being the first min(count[a], max_ngb) entries of
+ * ngb[a*max_ngb ...] (rows as sidm_find_overlap writes them; their order does
+ * not matter) and, in place of W(r_ij, h_i),
+ *     g_ij = ghat(alpha, rho) / H^3,  H = h_i + h_j,
+ *     alpha = min(h_i, h_j) / H,  rho = r_ij / H,
+ * with ghat(alpha, rho) = H^3 g at h_i = alpha H, h_j = (1 - alpha) H (the
+ * pair symmetry g_ij = g_ji leaves alpha in [0, 1/2]; alpha = 0 is a point
+ * partner, ghat = W(rho, 1)) computed at the table nodes when the context is
+ * created and read bilinearly: with fa = alpha 2 NA, fr = rho NR,
+ * ia = min(floor(fa), NA-1), ir = min(floor(fr), NR-1), ta = fa - ia,
+ * tr = fr - ir:  g0 = T[ia][ir] + tr (T[ia][ir+1] - T[ia][ir]),
+ * g1 likewise from row ia+1,  ghat = g0 + ta (g1 - g0);  0 for rho >= 1.
+ * h_all as given to sidm_find_overlap; cand_info (optional) has
+ * n_active*max_ngb entries, slot a*max_ngb + s. */
+sidm_status sidm_scatter_overlap(sidm_ctx *ctx, sidm_particles *p, const double *h_all,
+                                 const int32_t *active, int64_t n_active, int32_t max_ngb,
+                                 const int32_t *ngb, const int32_t *count, const double *dt,
+                                 uint64_t seed, uint32_t step, uint32_t *cand_info);
+
+/* Per-pair timestep with the overlap estimator: Eq. sidm_timestep with the
+ * kernel's centre value W(0, h_i) replaced by each pair's g_ij at zero
+ * separation (the largest value g_ij takes):
+ *     dt_sidm[a] = c_sidm * 2 / (m_i max_j [g_ij(0) (w_ij sigma(w_ij)/m)])
+ * over the partners of row a, with the current velocities; +inf if 0. */
+sidm_status sidm_pair_timestep_overlap(sidm_ctx *ctx, const double *h_all, const int32_t *active,
+                                       int64_t n_active, int32_t max_ngb, const int32_t *ngb,
+                                       const int32_t *count, double *dt_sidm);
+
+/* Copy the context's ghat table, (NA+1) x (NR+1) doubles alpha-major, to
+ * HOST memory host_out (waits for the context's stream). */
+sidm_status sidm_overlap_table(sidm_ctx *ctx, double *host_out);
 
 /* Served form: the step between two scattering steps of an isolated halo
  * that has no gravity solver of its own.  The step length d is the largest

@@ -29,6 +29,8 @@ KERNEL_CUBIC_SPLINE = 0
 XSEC_CONST, XSEC_YUKAWA, XSEC_TABLE = 0, 1, 2
 MODEL_ELASTIC, MODEL_EPS, MODEL_TWO_STATE, MODEL_BEAM = 0, 1, 2, 3
 FP64, MIXED = 0, 1
+EST_ONE_SIDED, EST_OVERLAP = 0, 1
+OVERLAP_NA, OVERLAP_NR = 64, 256
 
 CAND_ACCEPT0 = 1
 CAND_SCATTER = 2
@@ -50,7 +52,7 @@ class Config(ctypes.Structure):
                 ("c_sidm", ctypes.c_double), ("flag_band", ctypes.c_double),
                 ("band_r2", ctypes.c_double), ("band_p", ctypes.c_double),
                 ("xsec_n", ctypes.c_int32), ("xsec_w", ctypes.c_void_p),
-                ("xsec_sigma", ctypes.c_void_p)]
+                ("xsec_sigma", ctypes.c_void_p), ("estimator", ctypes.c_int32)]
 
 
 class Particles(ctypes.Structure):
@@ -86,6 +88,8 @@ EXPORTS = ["sidm_footprint", "sidm_create", "sidm_destroy", "sidm_set_stream", "
            "sidm_last_error", "sidm_status_string", "sidm_build_tree", "sidm_find_ngb",
            "sidm_refit_tree", "sidm_scatter_step", "sidm_pair_timestep",
            "sidm_advance_hernquist", "sidm_drift",
+           "sidm_find_overlap", "sidm_scatter_overlap", "sidm_pair_timestep_overlap",
+           "sidm_overlap_table",
            "sidm_sync",
            "sidm_timing_enable", "sidm_timing_read"]
 
@@ -118,6 +122,11 @@ def lib():
         d = ctypes.c_double
         L.sidm_advance_hernquist.argtypes = [P, P, P, P, P, P, P, i64, P, i64, d, d, d, P, P]
         L.sidm_drift.argtypes = [P, P, P, P, P, P, P, i64, d]
+        L.sidm_find_overlap.argtypes = [P, P, P, i64, ctypes.c_int32, P, P]
+        L.sidm_scatter_overlap.argtypes = [P, ctypes.POINTER(Particles), P, P, i64,
+                                           ctypes.c_int32, P, P, P, u64, u32, P]
+        L.sidm_pair_timestep_overlap.argtypes = [P, P, P, i64, ctypes.c_int32, P, P, P]
+        L.sidm_overlap_table.argtypes = [P, P]
         L.sidm_sync.argtypes = [P, ctypes.POINTER(Stats)]
         L.sidm_timing_enable.argtypes = [P, ctypes.c_int]
         L.sidm_timing_read.argtypes = [P, ctypes.POINTER(Timing)]
@@ -131,9 +140,10 @@ def lib():
 def make_config(n_ngb=32, periodic=False, box=0.0, xsec=XSEC_CONST, sigma0=0.0, w0=1.0,
                 model=MODEL_ELASTIC, eps=1.0, delta=0.0, c_sidm=0.1, precision=FP64,
                 flag_band=1e-9, band_r2=1e-5, band_p=1e-5, table_w=None,
-                table_sigma=None) -> Config:
+                table_sigma=None, estimator=EST_ONE_SIDED) -> Config:
     """A sidm_config.  table_w / table_sigma (numpy arrays) give a tabulated
-    cross-section (xsec = XSEC_TABLE); the Config keeps them alive."""
+    cross-section (xsec = XSEC_TABLE); the Config keeps them alive.
+    estimator = EST_OVERLAP reserves what the overlap-estimator calls need."""
     tw = ts = None
     n_t = 0
     if table_w is not None:
@@ -144,7 +154,7 @@ def make_config(n_ngb=32, periodic=False, box=0.0, xsec=XSEC_CONST, sigma0=0.0, 
                int(precision), float(box), float(sigma0), float(w0), float(eps), float(delta),
                float(c_sidm), float(flag_band), float(band_r2), float(band_p), n_t,
                tw.ctypes.data if tw is not None else None,
-               ts.ctypes.data if ts is not None else None)
+               ts.ctypes.data if ts is not None else None, int(estimator))
     c._tables = (tw, ts)
     return c
 
@@ -270,6 +280,52 @@ class Context:
         self._check(lib().sidm_pair_timestep(self._h, _ptr(active), int(active.shape[0]),
                                              _ptr(ngb), _ptr(h), _ptr(dt_sidm)),
                     "sidm_pair_timestep")
+
+    # --- kernel-overlap estimator -------------------------------------------
+    def find_overlap(self, h_all, active, ngb, count):
+        """Partners with r_ij < h_i + h_j: ngb int32[n_active, max_ngb] (rows in
+        tree order), count int32[n_active] (full counts)."""
+        torch = self._torch
+        self._dev(h_all, torch.float64, "h_all")
+        self._dev(active, torch.int32, "active")
+        self._dev(ngb, torch.int32, "ngb")
+        self._dev(count, torch.int32, "count")
+        self._check(lib().sidm_find_overlap(self._h, _ptr(h_all), _ptr(active),
+                                            int(active.shape[0]), int(ngb.shape[1]), _ptr(ngb),
+                                            _ptr(count)), "sidm_find_overlap")
+
+    def scatter_overlap(self, h_all, active, ngb, count, dt, seed: int, step: int,
+                        cand_info=None):
+        torch = self._torch
+        if self._particles is None:
+            raise SidmError(SIDM_E_STATE, "scatter_overlap before build_tree")
+        for t, dtp, nm in ((h_all, torch.float64, "h_all"), (active, torch.int32, "active"),
+                           (ngb, torch.int32, "ngb"), (count, torch.int32, "count"),
+                           (dt, torch.float64, "dt"), (cand_info, torch.int32, "cand_info")):
+            self._dev(t, dtp, nm)
+        p = self._particles[0]
+        self._check(lib().sidm_scatter_overlap(self._h, ctypes.byref(p), _ptr(h_all),
+                                               _ptr(active), int(active.shape[0]),
+                                               int(ngb.shape[1]), _ptr(ngb), _ptr(count),
+                                               _ptr(dt), int(seed) & (2**64 - 1),
+                                               int(step) & (2**32 - 1), _ptr(cand_info)),
+                    "sidm_scatter_overlap")
+
+    def pair_timestep_overlap(self, h_all, active, ngb, count, dt_sidm):
+        torch = self._torch
+        for t, dtp, nm in ((h_all, torch.float64, "h_all"), (active, torch.int32, "active"),
+                           (ngb, torch.int32, "ngb"), (count, torch.int32, "count"),
+                           (dt_sidm, torch.float64, "dt_sidm")):
+            self._dev(t, dtp, nm)
+        self._check(lib().sidm_pair_timestep_overlap(self._h, _ptr(h_all), _ptr(active),
+                                                     int(active.shape[0]), int(ngb.shape[1]),
+                                                     _ptr(ngb), _ptr(count), _ptr(dt_sidm)),
+                    "sidm_pair_timestep_overlap")
+
+    def overlap_table(self) -> np.ndarray:
+        out = np.zeros((OVERLAP_NA + 1, OVERLAP_NR + 1), dtype=np.float64)
+        self._check(lib().sidm_overlap_table(self._h, out.ctypes.data), "sidm_overlap_table")
+        return out
 
     def advance_hernquist(self, x, y, z, vx, vy, vz, dt_sidm, n_active: int, dt_cap: float,
                           gm: float, a: float, dt_next=None, dt_step=None):

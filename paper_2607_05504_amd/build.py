@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsidm.so")
-SOURCES = ["runtime.hip", "tree.hip", "knn.hip", "scatter.hip", "advance.hip"]
+SOURCES = ["runtime.hip", "tree.hip", "knn.hip", "scatter.hip", "advance.hip", "overlap.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -58,37 +58,6 @@ struct KnnArgs {
 
 constexpr int32_t kIdxMask = (1 << SIDM_LEVEL_SHIFT) - 1;
 
-// gap along one axis between point p and a box [lo, hi], as a particle's
-// separation would round (min over the periodic images)
-template <bool PERIODIC>
-__device__ __forceinline__ double axis_gap(double lo, double hi, double p, double box)
-{
-    double a = lo - p, b = hi - p;
-    double g = a > 0.0 ? a : (b < 0.0 ? -b : 0.0);
-    if (PERIODIC) {
-        double am = a - box, bm = b - box;   // image shifted by -L
-        double gm = am > 0.0 ? am : (bm < 0.0 ? -bm : 0.0);
-        double ap = a + box, bp = b + box;   // image shifted by +L
-        double gp = ap > 0.0 ? ap : (bp < 0.0 ? -bp : 0.0);
-        g = fmin(g, fmin(gm, gp));
-    }
-    return g;
-}
-
-// squared gap to the box stored at nodes[g]; +inf for an empty box
-template <bool PERIODIC>
-__device__ __forceinline__ double node_gap2(const double *__restrict__ nodes, int64_t g, double px,
-                                            double py, double pz, double box)
-{
-    const double *nb = nodes + g * 6;
-    const double lx = nb[0], ly = nb[1], lz = nb[2], hx = nb[3], hy = nb[4], hz = nb[5];
-    if (!(lx <= hx)) return INFINITY;
-    double gx = axis_gap<PERIODIC>(lx, hx, px, box);
-    double gy = axis_gap<PERIODIC>(ly, hy, py, box);
-    double gz = axis_gap<PERIODIC>(lz, hz, pz, box);
-    return (gx * gx + gy * gy) + gz * gz;
-}
-
 // squared gap to a box held in registers; +inf for an empty box
 template <bool PERIODIC>
 __device__ __forceinline__ double box_gap2(const double *bx, double px, double py, double pz, double box)

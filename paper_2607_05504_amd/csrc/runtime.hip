@@ -74,6 +74,11 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(derr, 1, unsigned int);
     ADD(xt_w, SIDM_XSEC_TABLE_MAX, double); ADD(xt_s, SIDM_XSEC_TABLE_MAX, double);
     ADD(adv_min, 1, unsigned long long);
+    if (c->cfg.estimator == SIDM_EST_OVERLAP) {
+        ADD(hs, N, double);
+        ADD(hmax, tree_node_count(tree_levels(N)), double);
+        ADD(gtab, (SIDM_OVERLAP_NA + 1) * (SIDM_OVERLAP_NR + 1), double);
+    }
 #undef ADD
 }
 
@@ -109,6 +114,9 @@ sidm_status check_config(const sidm_config *cfg)
     if (cfg->precision != SIDM_FP64 && cfg->precision != SIDM_MIXED) return SIDM_E_INVAL;
     if (!(cfg->c_sidm > 0.0)) return SIDM_E_INVAL;
     if (!(cfg->flag_band >= 0.0)) return SIDM_E_INVAL;
+    if (cfg->estimator != SIDM_EST_ONE_SIDED && cfg->estimator != SIDM_EST_OVERLAP)
+        return SIDM_E_INVAL;
+    if (cfg->estimator == SIDM_EST_OVERLAP && cfg->precision != SIDM_FP64) return SIDM_E_INVAL;
     return SIDM_OK;
 }
 
@@ -123,7 +131,7 @@ sidm_status hip_fail(sidm_ctx *c, hipError_t e, const char *what)
 sidm_status status_from_bits(unsigned int bits)
 {
     if (!bits) return SIDM_OK;
-    if (bits & DERR_OVERFLOW) return SIDM_E_OVERFLOW;
+    if (bits & (DERR_OVERFLOW | DERR_NGB_OVERFLOW)) return SIDM_E_OVERFLOW;
     return SIDM_E_INVAL;
 }
 
@@ -145,7 +153,7 @@ const char *sidm_status_string(sidm_status s)
     case SIDM_E_NOMEM: return "out of device memory";
     case SIDM_E_DEVICE: return "HIP runtime error";
     case SIDM_E_CAPACITY: return "capacity exceeded";
-    case SIDM_E_OVERFLOW: return "accepted-candidate list overflow";
+    case SIDM_E_OVERFLOW: return "accepted-candidate list or overlap row overflow";
     case SIDM_E_STATE: return "call out of order";
     }
     return "unknown status";
@@ -228,6 +236,7 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
     launch_fill_i32(c->acc_count, 0, 8, s);
     launch_fill_i32((int32_t *)c->dstats, 0, (int64_t)(sizeof(DevStats) / 4), s);
     hipError_t e = copy_table(c);
+    if (e == hipSuccess && c->cfg.estimator == SIDM_EST_OVERLAP) e = launch_overlap_table(c);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(base);
@@ -312,8 +321,9 @@ sidm_status sidm_reconfigure(sidm_ctx *c, const sidm_config *cfg)
         set_err(c, "reconfigure: invalid configuration");
         return SIDM_E_INVAL;
     }
-    if (cfg->n_ngb != c->cfg.n_ngb || cfg->precision != c->cfg.precision) {
-        set_err(c, "reconfigure: n_ngb and precision fix the context's layout");
+    if (cfg->n_ngb != c->cfg.n_ngb || cfg->precision != c->cfg.precision ||
+        cfg->estimator != c->cfg.estimator) {
+        set_err(c, "reconfigure: n_ngb, precision and estimator fix the context's layout");
         return SIDM_E_INVAL;
     }
     c->cfg = *cfg;
@@ -472,6 +482,107 @@ sidm_status sidm_pair_timestep(sidm_ctx *c, const int32_t *active, int64_t n_act
     return SIDM_OK;
 }
 
+static sidm_status check_overlap(sidm_ctx *c, const double *h_all, const int32_t *active,
+                                 int64_t n_active, int32_t max_ngb, const void *ngb,
+                                 const int32_t *count, const char *who)
+{
+    if (c->cfg.estimator != SIDM_EST_OVERLAP) {
+        set_err(c, "%s: the context was created without estimator SIDM_EST_OVERLAP", who);
+        return SIDM_E_STATE;
+    }
+    sidm_status st = check_active(c, active, n_active, who);
+    if (st != SIDM_OK) return st;
+    if (max_ngb < 1) {
+        set_err(c, "%s: max_ngb=%d < 1", who, (int)max_ngb);
+        return SIDM_E_INVAL;
+    }
+    if (n_active > 0 && (!h_all || !ngb || !count)) {
+        set_err(c, "%s: NULL h_all/ngb/count", who);
+        return SIDM_E_INVAL;
+    }
+    if (n_active * (int64_t)max_ngb > (int64_t)INT32_MAX) {
+        set_err(c, "%s: n_active * max_ngb = %lld does not fit the 32-bit slot index", who,
+                (long long)(n_active * (int64_t)max_ngb));
+        return SIDM_E_CAPACITY;
+    }
+    return SIDM_OK;
+}
+
+sidm_status sidm_find_overlap(sidm_ctx *c, const double *h_all, const int32_t *active,
+                              int64_t n_active, int32_t max_ngb, int32_t *ngb, int32_t *count)
+{
+    if (!c) return SIDM_E_INVAL;
+    sidm_status st = check_overlap(c, h_all, active, n_active, max_ngb, ngb, count, "find_overlap");
+    if (st != SIDM_OK) return st;
+    if (n_active == 0) return SIDM_OK;
+    hipError_t e = launch_map_active(c, active, n_active);
+    if (e == hipSuccess) e = launch_find_overlap(c, h_all, n_active, max_ngb, ngb, count);
+    if (e != hipSuccess) return hip_fail(c, e, "find_overlap");
+    return SIDM_OK;
+}
+
+sidm_status sidm_scatter_overlap(sidm_ctx *c, sidm_particles *p, const double *h_all,
+                                 const int32_t *active, int64_t n_active, int32_t max_ngb,
+                                 const int32_t *ngb, const int32_t *count, const double *dt,
+                                 uint64_t seed, uint32_t step, uint32_t *cand_info)
+{
+    if (!c) return SIDM_E_INVAL;
+    sidm_status st = check_overlap(c, h_all, active, n_active, max_ngb, ngb, count,
+                                   "scatter_overlap");
+    if (st != SIDM_OK) return st;
+    if (!p || p->n != c->n || !p->vx || !p->vy || !p->vz) {
+        set_err(c, "scatter_overlap: particles do not match the tree snapshot");
+        return SIDM_E_INVAL;
+    }
+    if ((c->cfg.model == SIDM_MODEL_TWO_STATE || c->cfg.model == SIDM_MODEL_BEAM) && !p->state) {
+        set_err(c, "scatter_overlap: the two-state and beam models need a state array");
+        return SIDM_E_INVAL;
+    }
+    if (n_active > 0 && !dt) {
+        set_err(c, "scatter_overlap: NULL dt");
+        return SIDM_E_INVAL;
+    }
+    hipError_t e = launch_map_active(c, active, n_active);
+    if (e == hipSuccess)
+        e = launch_scatter_overlap(c, p, n_active, h_all, max_ngb, ngb, count, dt, seed, step,
+                                   cand_info);
+    if (e != hipSuccess) return hip_fail(c, e, "scatter_overlap");
+    return SIDM_OK;
+}
+
+sidm_status sidm_pair_timestep_overlap(sidm_ctx *c, const double *h_all, const int32_t *active,
+                                       int64_t n_active, int32_t max_ngb, const int32_t *ngb,
+                                       const int32_t *count, double *dt_sidm)
+{
+    if (!c) return SIDM_E_INVAL;
+    sidm_status st = check_overlap(c, h_all, active, n_active, max_ngb, ngb, count,
+                                   "pair_timestep_overlap");
+    if (st != SIDM_OK) return st;
+    if (n_active > 0 && !dt_sidm) {
+        set_err(c, "pair_timestep_overlap: NULL dt_sidm");
+        return SIDM_E_INVAL;
+    }
+    if (n_active == 0) return SIDM_OK;
+    hipError_t e = launch_map_active(c, active, n_active);
+    if (e == hipSuccess) e = launch_timestep_overlap(c, n_active, h_all, max_ngb, ngb, count, dt_sidm);
+    if (e != hipSuccess) return hip_fail(c, e, "pair_timestep_overlap");
+    return SIDM_OK;
+}
+
+sidm_status sidm_overlap_table(sidm_ctx *c, double *host_out)
+{
+    if (!c || !host_out) return SIDM_E_INVAL;
+    if (c->cfg.estimator != SIDM_EST_OVERLAP) {
+        set_err(c, "overlap_table: the context was created without estimator SIDM_EST_OVERLAP");
+        return SIDM_E_STATE;
+    }
+    const size_t b = (size_t)(SIDM_OVERLAP_NA + 1) * (SIDM_OVERLAP_NR + 1) * sizeof(double);
+    hipError_t e = hipMemcpyAsync(host_out, c->gtab, b, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "overlap_table");
+    return SIDM_OK;
+}
+
 sidm_status sidm_advance_hernquist(sidm_ctx *c, double *x, double *y, double *z, double *vx,
                                    double *vy, double *vz, int64_t n, const double *dt_sidm,
                                    int64_t n_active, double dt_cap, double gm, double a,
@@ -550,11 +661,14 @@ sidm_status sidm_sync(sidm_ctx *c, sidm_stats *out)
         out->max_p = mp;
     }
     if (bits) {
-        set_err(c, "device error bits 0x%x (%s%s%s%s%s)", bits, (bits & DERR_INDEX) ? "index " : "",
+        set_err(c, "device error bits 0x%x (%s%s%s%s%s%s%s)", bits,
+                (bits & DERR_INDEX) ? "index " : "",
                 (bits & DERR_DUPLICATE) ? "duplicate-active " : "",
                 (bits & DERR_OVERFLOW) ? "accepted-overflow " : "",
                 (bits & DERR_COUNT) ? "too-few-neighbours " : "",
-                (bits & DERR_STALL) ? "stalled-resolution " : "");
+                (bits & DERR_STALL) ? "stalled-resolution " : "",
+                (bits & DERR_NGB_OVERFLOW) ? "overlap-row-overflow " : "",
+                (bits & DERR_BAD_H) ? "bad-smoothing-length " : "");
         launch_fill_i32((int32_t *)c->derr, 0, 1, c->stream);
         (void)hipStreamSynchronize(c->stream);
     }

@@ -58,6 +58,12 @@ struct StepArgs {
     // tabulated cross-section (SIDM_XSEC_TABLE)
     const double *xt_w, *xt_s;
     int xt_n;
+    // candidate rows: stride entries a row (n_ngb for the one-sided
+    // estimator); the overlap estimator's rows hold count[a] partners and
+    // take g_ij from every particle's h (h_all, caller order) and the table
+    int stride;
+    const int32_t *cnt;
+    const double *h_all, *gtab;
     uint64_t seed;
     uint32_t step;
     int k, periodic, xsec, model, has_mass;
@@ -253,27 +259,36 @@ __device__ __forceinline__ float xsec_sigma32(float w, int xsec, float s0, float
     return s0;
 }
 
-template <bool PERIODIC, bool MIXED>
+template <bool PERIODIC, bool MIXED, bool OVERLAP>
 __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
 {
     __shared__ StagedAcc S;
     __shared__ int s_n;
     __shared__ int32_t s_base;
-    __shared__ unsigned long long s_red[4][5];
+    __shared__ unsigned long long s_red[4][6];
     const int64_t nt = *A.nt_dev;
-    const int64_t total = nt * A.k;
-    unsigned long long maxp = 0, n_fl = 0, n_ge1 = 0, n_acc = 0, n_rc = 0;
+    const int64_t total = nt * A.stride;
+    unsigned long long maxp = 0, n_fl = 0, n_ge1 = 0, n_acc = 0, n_rc = 0, n_cd = 0;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
     for (int64_t c0 = blockIdx.x * (int64_t)blockDim.x; c0 < total;
          c0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = c0 + threadIdx.x;
-        if (c < total) {
-            const int64_t b = c / A.k;
-            const int s = (int)(c - b * A.k);
+        bool live = c < total;
+        int64_t b = 0;
+        int s = 0;
+        int32_t a = 0;
+        if (live) {
+            b = c / A.stride;
+            s = (int)(c - b * A.stride);
+            a = A.slot[b];
+            if (OVERLAP) live = s < A.cnt[a];
+        }
+        if (live) {
             const int32_t i = A.tlist[b];
-            const int32_t a = A.slot[b];
-            const int32_t jc = A.ngb[(int64_t)a * A.k + s];
+            const int64_t ci = (int64_t)a * A.stride + s;
+            const int32_t jc = A.ngb[ci];
+            n_cd += 1;
             if (jc < 0 || jc >= A.n) {
                 atomicOr(A.derr, DERR_INDEX);
             } else {
@@ -315,7 +330,8 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                 if (exact) {
                     const double r = sqrt(sep2<PERIODIC>(A.xs[i], A.ys[i], A.zs[i], A.xs[j], A.ys[j],
                                                          A.zs[j], A.box));
-                    W = cubic_spline(r, A.h[a]);
+                    W = OVERLAP ? overlap_g(A.gtab, A.h_all[A.perm[i]], A.h_all[jc], r)
+                                : cubic_spline(r, A.h[a]);
                     const double w = rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
                     const double sig = sigma_of(A, w);
                     P = pair_prob(mass_of(A, j), sig, w, W, dta);
@@ -336,12 +352,12 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                 const unsigned long long pb = (unsigned long long)__double_as_longlong(P);
                 maxp = pb > maxp ? pb : maxp;
                 if (A.cand_info)
-                    A.cand_info[(int64_t)a * A.k + s] =
+                    A.cand_info[ci] =
                         (acc ? SIDM_CAND_ACCEPT0 : 0u) | (flagged ? SIDM_CAND_FLAGGED : 0u);
                 if (acc) {
                     const Philox4 xp = pair_draw(A.seed, A.step, idi, idj, PURPOSE_PRIORITY);
                     const int t = atomicAdd(&s_n, 1);      // LDS; kStage >= 2 * blockDim
-                    S.i[t] = i; S.j[t] = j; S.cand[t] = a * A.k + s;
+                    S.i[t] = i; S.j[t] = j; S.cand[t] = (int32_t)ci;
                     S.u[t] = u; S.W[t] = W; S.dt[t] = dta;
                     S.prio[t] = direction_word(xp, idi < idj);
                     S.idpair[t] = ((uint64_t)idi << 32) | idj;
@@ -365,18 +381,22 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
         n_ge1 += (unsigned long long)__shfl_xor((long long)n_ge1, off);
         n_acc += (unsigned long long)__shfl_xor((long long)n_acc, off);
         n_rc += (unsigned long long)__shfl_xor((long long)n_rc, off);
+        n_cd += (unsigned long long)__shfl_xor((long long)n_cd, off);
     }
     const int w = threadIdx.x >> 6;
     if (wave_lane() == 0) {
         s_red[w][0] = maxp; s_red[w][1] = n_fl; s_red[w][2] = n_ge1; s_red[w][3] = n_acc; s_red[w][4] = n_rc;
+        s_red[w][5] = n_cd;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long m = 0, f = 0, g = 0, q = 0, rc = 0;
+        unsigned long long m = 0, f = 0, g = 0, q = 0, rc = 0, cd = 0;
         for (int v = 0; v < kBlock / 64; ++v) {
             m = s_red[v][0] > m ? s_red[v][0] : m;
             f += s_red[v][1]; g += s_red[v][2]; q += s_red[v][3]; rc += s_red[v][4];
+            cd += s_red[v][5];
         }
+        if (OVERLAP && cd) atomicAdd(&A.st->n_cand, cd);
         if (rc) atomicAdd(&A.st->n_recheck, rc);
         if (m) atomicMax(&A.st->max_p_bits, m);
         if (f) atomicAdd(&A.st->n_flagged, f);
@@ -625,6 +645,29 @@ __global__ __launch_bounds__(kBlock) void k_timestep(StepArgs A, double c_sidm, 
     }
 }
 
+// Overlap estimator: dt_i = 2 C_SIDM / (m_i max_j [g_ij(0) (w_ij sigma(w_ij)/m)])
+// over the partners of the target's row; one thread per target.
+__global__ __launch_bounds__(kBlock) void k_timestep_overlap(StepArgs A, double c_sidm, double *dt_out)
+{
+    const int64_t nt = *A.nt_dev;
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nt;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = A.tlist[b], a = A.slot[b];
+        const double vix = A.vxs[i], viy = A.vys[i], viz = A.vzs[i];
+        const double hi = A.h_all[A.perm[i]];
+        const int len = A.cnt[a] < A.stride ? A.cnt[a] : A.stride;
+        double qmax = 0.0;
+        for (int s = 0; s < len; ++s) {
+            const int32_t jc = A.ngb[(int64_t)a * A.stride + s];
+            const double rate = pair_rate(A, vix, viy, viz, jc);
+            if (jc < 0 || jc >= A.n) continue;
+            const double q = overlap_g(A.gtab, hi, A.h_all[jc], 0.0) * rate;
+            qmax = q > qmax ? q : qmax;
+        }
+        dt_out[a] = qmax > 0.0 ? (2.0 * c_sidm) / (mass_of(A, i) * qmax) : INFINITY;
+    }
+}
+
 StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const double *h,
                    const double *dt, uint64_t seed, uint32_t step, uint32_t *cand_info)
 {
@@ -649,6 +692,7 @@ StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const dou
     A.model = c->cfg.model; A.has_mass = c->has_mass;
     A.xo = c->xo; A.yo = c->yo; A.zo = c->zo; A.nodes = c->nodes; A.band_p = c->cfg.band_p;
     A.xt_w = c->xt_w; A.xt_s = c->xt_s; A.xt_n = c->cfg.xsec_n;
+    A.stride = A.k; A.cnt = nullptr; A.h_all = nullptr; A.gtab = c->gtab;
     return A;
 }
 
@@ -659,14 +703,14 @@ int grid_for(int64_t n, int cap = 8192)
     return (int)(g > cap ? cap : g);
 }
 
-template <bool P, bool M>
+template <bool P, bool M, bool O = false>
 void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s)
 {
-    const int64_t total = n_active * A.k;
+    const int64_t total = n_active * A.stride;
     k_step_reset<<<1, 64, 0, s>>>(A.st, A.ctl);
-    k_count_cand<<<1, 64, 0, s>>>(A.st, A.nt_dev, A.k);
+    if (!O) k_count_cand<<<1, 64, 0, s>>>(A.st, A.nt_dev, A.k);
     phase_begin(c, PH_EVAL);
-    k_eval<P, M><<<grid_for(total, 2048), kBlock, 0, s>>>(A);
+    k_eval<P, M, O><<<grid_for(total, 2048), kBlock, 0, s>>>(A);
     phase_end(c, PH_EVAL);
     const int g = grid_for(A.cap_acc < total ? A.cap_acc : total, 2048);
     phase_begin(c, PH_RESOLVE);
@@ -707,6 +751,30 @@ hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, co
         k_timestep_group<<<grid_for(n_active * k), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm, dt_out);
     else
         k_timestep<<<grid_for(n_active), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm, dt_out);
+    phase_end(c, PH_TIMESTEP);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_overlap(sidm_ctx *c, sidm_particles *p, int64_t n_active,
+                                  const double *h_all, int32_t max_ngb, const int32_t *ngb,
+                                  const int32_t *count, const double *dt, uint64_t seed,
+                                  uint32_t step, uint32_t *cand_info)
+{
+    StepArgs A = make_args(c, p, ngb, nullptr, dt, seed, step, cand_info);
+    A.stride = max_ngb; A.cnt = count; A.h_all = h_all;
+    if (c->cfg.periodic) run_scatter<true, false, true>(c, A, n_active, c->stream);
+    else run_scatter<false, false, true>(c, A, n_active, c->stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_timestep_overlap(sidm_ctx *c, int64_t n_active, const double *h_all,
+                                   int32_t max_ngb, const int32_t *ngb, const int32_t *count,
+                                   double *dt_out)
+{
+    StepArgs A = make_args(c, nullptr, ngb, nullptr, nullptr, 0, 0, nullptr);
+    A.stride = max_ngb; A.cnt = count; A.h_all = h_all;
+    phase_begin(c, PH_TIMESTEP);
+    k_timestep_overlap<<<grid_for(n_active), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm, dt_out);
     phase_end(c, PH_TIMESTEP);
     return hipGetLastError();
 }

@@ -22,6 +22,8 @@
 #define DERR_OVERFLOW 4u        // accepted-candidate list overflow
 #define DERR_COUNT 8u           // fewer than n_ngb + 1 candidates found
 #define DERR_STALL 16u          // a resolution pass decided nothing (cannot happen)
+#define DERR_NGB_OVERFLOW 32u   // an overlap row longer than its buffer
+#define DERR_BAD_H 64u          // a smoothing length that is not > 0 and finite
 
 #define SIDM_TREE_FAN 8         // children per internal tree node
 #define SIDM_MAX_LEVELS 12
@@ -130,6 +132,9 @@ struct sidm_ctx {
     DevStats *dstats;
     unsigned int *derr;
     double *xt_w, *xt_s;     // tabulated cross-section nodes [SIDM_XSEC_TABLE_MAX]
+    // overlap estimator only: every particle's h in Morton order, the largest
+    // h below every tree node, and the ghat table
+    double *hs, *hmax, *gtab;
     unsigned long long *adv_min;   // served form: smallest per-pair bound of a step
     // opt-in event timing of the main kernels: up to SIDM_TIMING_RING launches
     // of each phase are bracketed between two sidm_timing_read calls
@@ -176,6 +181,37 @@ __device__ __forceinline__ double sep2(double xi, double yi, double zi, double x
     return (dx * dx + dy * dy) + dz * dz;
 }
 
+// gap along one axis between point p and a box [lo, hi], as a particle's
+// separation would round (min over the periodic images)
+template <bool PERIODIC>
+__device__ __forceinline__ double axis_gap(double lo, double hi, double p, double box)
+{
+    double a = lo - p, b = hi - p;
+    double g = a > 0.0 ? a : (b < 0.0 ? -b : 0.0);
+    if (PERIODIC) {
+        double am = a - box, bm = b - box;   // image shifted by -L
+        double gm = am > 0.0 ? am : (bm < 0.0 ? -bm : 0.0);
+        double ap = a + box, bp = b + box;   // image shifted by +L
+        double gp = ap > 0.0 ? ap : (bp < 0.0 ? -bp : 0.0);
+        g = fmin(g, fmin(gm, gp));
+    }
+    return g;
+}
+
+// squared gap to the box stored at nodes[g]; +inf for an empty box
+template <bool PERIODIC>
+__device__ __forceinline__ double node_gap2(const double *__restrict__ nodes, int64_t g, double px,
+                                            double py, double pz, double box)
+{
+    const double *nb = nodes + g * 6;
+    const double lx = nb[0], ly = nb[1], lz = nb[2], hx = nb[3], hy = nb[4], hz = nb[5];
+    if (!(lx <= hx)) return INFINITY;
+    double gx = axis_gap<PERIODIC>(lx, hx, px, box);
+    double gy = axis_gap<PERIODIC>(ly, hy, py, box);
+    double gz = axis_gap<PERIODIC>(lz, hz, pz, box);
+    return (gx * gx + gy * gy) + gz * gz;
+}
+
 // Cubic spline kernel W_CS(r, h) with support radius h.
 __device__ __forceinline__ double cubic_spline(double r, double h)
 {
@@ -217,6 +253,28 @@ __device__ __forceinline__ double xsec_sigma(double w, int xsec, double s0, doub
         return s0 / (d * d);
     }
     return s0;
+}
+
+// g_ij of the overlap estimator: the ghat table (SIDM_OVERLAP_NA+1 rows of
+// SIDM_OVERLAP_NR+1) read bilinearly at alpha = min(h_i, h_j)/H,
+// rho = r/H, over H^3 (H = h_i + h_j); zero for r >= H
+__device__ __forceinline__ double overlap_g(const double *__restrict__ tab, double hi, double hj,
+                                            double r)
+{
+    const double H = hi + hj;
+    const double al = (hi < hj ? hi : hj) / H;
+    const double rho = r / H;
+    if (!(rho < 1.0)) return 0.0;
+    const double fa = al * (2.0 * SIDM_OVERLAP_NA), fr = rho * SIDM_OVERLAP_NR;
+    int ia = (int)fa, ir = (int)fr;
+    if (ia > SIDM_OVERLAP_NA - 1) ia = SIDM_OVERLAP_NA - 1;
+    if (ir > SIDM_OVERLAP_NR - 1) ir = SIDM_OVERLAP_NR - 1;
+    const double ta = fa - ia, tr = fr - ir;
+    const double *t0 = tab + ia * (SIDM_OVERLAP_NR + 1) + ir;
+    const double *t1 = t0 + (SIDM_OVERLAP_NR + 1);
+    const double g0 = t0[0] + tr * (t0[1] - t0[0]);
+    const double g1 = t1[0] + tr * (t1[1] - t1[0]);
+    return (g0 + ta * (g1 - g0)) / ((H * H) * H);
 }
 
 __device__ __forceinline__ double rel_speed(double ax, double ay, double az, double bx,
@@ -318,6 +376,17 @@ hipError_t launch_scatter(sidm_ctx *c, sidm_particles *p, int64_t n_active, cons
                           uint32_t *cand_info);
 hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, const double *h,
                            double *dt_out);
+hipError_t launch_scatter_overlap(sidm_ctx *c, sidm_particles *p, int64_t n_active,
+                                  const double *h_all, int32_t max_ngb, const int32_t *ngb,
+                                  const int32_t *count, const double *dt, uint64_t seed,
+                                  uint32_t step, uint32_t *cand_info);
+hipError_t launch_timestep_overlap(sidm_ctx *c, int64_t n_active, const double *h_all,
+                                   int32_t max_ngb, const int32_t *ngb, const int32_t *count,
+                                   double *dt_out);
+// overlap.hip
+hipError_t launch_overlap_table(sidm_ctx *c);
+hipError_t launch_find_overlap(sidm_ctx *c, const double *h_all, int64_t n_active,
+                               int32_t max_ngb, int32_t *ngb, int32_t *count);
 // advance.hip
 hipError_t launch_advance(sidm_ctx *c, double *x, double *y, double *z, double *vx, double *vy,
                           double *vz, int64_t n, const double *dt_sidm, int64_t n_active,

@@ -89,3 +89,46 @@ def run_step(ctx: Context, ds: DeviceState, out: StepOut, seed: int, step: int,
     ctx.find_ngb(ds.active, out.ngb, out.h)
     ctx.scatter_step(ds.active, out.ngb, out.h, ds.dt, seed, step, cand_info=out.cand_info)
     ctx.pair_timestep(ds.active, out.ngb, out.h, out.dt_sidm)
+
+
+@dataclasses.dataclass
+class OverlapOut:
+    everyone: "torch.Tensor"     # int32[n] 0..n-1 (all particles as targets)
+    ngb_all: "torch.Tensor"      # int32[n, n_ngb] neighbour lists of every particle
+    h_all: "torch.Tensor"        # float64[n] every particle's smoothing length
+    ngb: "torch.Tensor"          # int32[n_active, max_ngb] overlap partners
+    count: "torch.Tensor"        # int32[n_active]
+    dt_sidm: "torch.Tensor"
+    cand_info: Optional["torch.Tensor"]
+
+
+def alloc_overlap(ds: DeviceState, k: int, max_ngb: int, with_info: bool = False) -> OverlapOut:
+    import torch
+    dev = ds.x.device
+    n, na = ds.n, ds.n_active
+    return OverlapOut(
+        everyone=torch.arange(n, dtype=torch.int32, device=dev),
+        ngb_all=torch.empty((n, k), dtype=torch.int32, device=dev),
+        h_all=torch.empty(n, dtype=torch.float64, device=dev),
+        ngb=torch.empty((na, max_ngb), dtype=torch.int32, device=dev),
+        count=torch.empty(na, dtype=torch.int32, device=dev),
+        dt_sidm=torch.empty(na, dtype=torch.float64, device=dev),
+        cand_info=(torch.empty((na, max_ngb), dtype=torch.int32, device=dev)
+                   if with_info else None))
+
+
+def run_overlap_step(ctx: Context, ds: DeviceState, out: OverlapOut, seed: int, step: int,
+                     smoothing: bool = True):
+    """One step with the kernel-overlap estimator: the tree, every particle's
+    h (sidm_find_ngb over all particles; skipped when smoothing is False and
+    out.h_all already holds them), the overlap partners of the active ones,
+    the scattering step and the per-pair timestep.  The context needs
+    capacity for all particles as targets (cap_active = n)."""
+    ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state,
+                   m_scalar=ds.mass)
+    if smoothing:
+        ctx.find_ngb(out.everyone, out.ngb_all, out.h_all)
+    ctx.find_overlap(out.h_all, ds.active, out.ngb, out.count)
+    ctx.scatter_overlap(out.h_all, ds.active, out.ngb, out.count, ds.dt, seed, step,
+                        cand_info=out.cand_info)
+    ctx.pair_timestep_overlap(out.h_all, ds.active, out.ngb, out.count, out.dt_sidm)

@@ -81,3 +81,20 @@ def test_library_does_not_reference_the_oracle():
     out = subprocess.run(["nm", "-D", sidm.LIB_PATH], capture_output=True, text=True,
                          check=True).stdout
     assert "oref_" not in out
+
+
+def test_overlap_estimator_config():
+    L = sidm.lib()
+    out = ctypes.c_size_t()
+    one = sidm.make_config(n_ngb=32, periodic=True, box=1.0, sigma0=1.0)
+    ovl = sidm.make_config(n_ngb=32, periodic=True, box=1.0, sigma0=1.0,
+                           estimator=sidm.EST_OVERLAP)
+    n = 1 << 20
+    a, b = sidm.footprint(one, n, n), sidm.footprint(ovl, n, n)
+    # every particle's h, the node maxima and the ghat table
+    assert 8 * n < b - a < 10 * n + 4 * (sidm.OVERLAP_NA + 1) * (sidm.OVERLAP_NR + 1) * 8
+    bad = sidm.make_config(n_ngb=32, periodic=True, box=1.0, sigma0=1.0,
+                           estimator=sidm.EST_OVERLAP, precision=sidm.MIXED)
+    assert L.sidm_footprint(ctypes.byref(bad), 1000, 100, ctypes.byref(out)) == sidm.SIDM_E_INVAL
+    bad = sidm.make_config(n_ngb=32, periodic=True, box=1.0, sigma0=1.0, estimator=7)
+    assert L.sidm_footprint(ctypes.byref(bad), 1000, 100, ctypes.byref(out)) == sidm.SIDM_E_INVAL
