@@ -174,6 +174,11 @@ def main():
                          "offsets with FP64 rechecks in the bands, FP64 kicks")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="per-kernel HBM traffic measured with rocprofv3 counters")
+    ap.add_argument("--estimator", choices=("one-sided", "overlap"), default="one-sided",
+                    help="scattering-rate estimator: the fiducial one-sided kernel, or the "
+                         "kernel overlap (partners r < h_i + h_j, tabulated overlap integral)")
+    ap.add_argument("--max-ngb", type=int, default=384,
+                    help="overlap estimator: partner buffer per active particle")
     ap.add_argument("--refit", action="store_true",
                     help="after the first step, reuse the tree's order (sidm_refit_tree)")
     ap.add_argument("--requests", type=int, default=200, help="serving: requests in the stream")
@@ -198,19 +203,35 @@ def main():
         return
 
     import torch
-    from paper_2607_05504_amd import FP64, MIXED, Context, profsum, runner
+    from paper_2607_05504_amd import EST_OVERLAP, FP64, MIXED, Context, profsum, runner
 
     torch.cuda.set_device(0)
     w, desc = make_workload(args.workload)
     ds = runner.upload(w, "cuda:0")
-    cfg = runner.config_for(w, precision=MIXED if args.precision == "mixed" else FP64)
-    ctx = Context(cfg, w.n, w.n_active)
-    out = runner.alloc_out(ds, w.n_ngb)
-    print(f"[bench] workload {args.workload}: n={w.n} active={w.n_active}", file=sys.stderr,
-          flush=True)
+    overlap = args.estimator == "overlap"
+    cfg = runner.config_for(w, precision=MIXED if args.precision == "mixed" else FP64,
+                            estimator=EST_OVERLAP if overlap else 0)
+    print(f"[bench] workload {args.workload}: n={w.n} active={w.n_active} "
+          f"estimator {args.estimator}", file=sys.stderr, flush=True)
+    if overlap:
+        # every particle's h once before the timed steps (untimed, as the
+        # inactive particles' h of earlier steps); each step then finds the
+        # active particles' h and updates them before the overlap walk
+        ctx = Context(cfg, w.n, w.n)
+        out = runner.alloc_overlap(ds, w.n_ngb, args.max_ngb)
+
+        def one_step(t, first=False):
+            runner.run_overlap_step(ctx, ds, out, w.seed, t,
+                                    smoothing="all" if first else "active")
+    else:
+        ctx = Context(cfg, w.n, w.n_active)
+        out = runner.alloc_out(ds, w.n_ngb)
+
+        def one_step(t, first=False):
+            runner.run_step(ctx, ds, out, w.seed, t, refit=args.refit and not first)
 
     for t in range(args.warmup):
-        runner.run_step(ctx, ds, out, w.seed, w.step + t, refit=args.refit and t > 0)
+        one_step(w.step + t, first=t == 0)
     ctx.sync()
     torch.cuda.synchronize()
 
@@ -223,8 +244,7 @@ def main():
     t0 = time.perf_counter()
     for t in range(args.steps):
         ev[t][0].record()
-        runner.run_step(ctx, ds, out, w.seed, w.step + args.warmup + t,
-                        refit=args.refit and args.warmup + t > 0)
+        one_step(w.step + args.warmup + t, first=args.warmup + t == 0)
         ev[t][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -235,15 +255,32 @@ def main():
     na, k = w.n_active, w.n_ngb
     ms_per_step = wall * 1e3 / args.steps
     value = na / (wall / args.steps)
-    ngb_np = out.ngb.cpu().numpy()
-    n_t = touched_count(ngb_np, w.active)
+    if overlap:
+        ngb_np = out.ngb_k.cpu().numpy()
+        cnt = out.count.cpu().numpy()
+        rows = out.ngb.cpu().numpy()
+        n_t = touched_count(ngb_np, w.active)
+        n_to = int(np.unique(np.concatenate([rows[rows >= 0], w.active])).size)
+        c_tot = int(cnt.sum())
+    else:
+        ngb_np = out.ngb.cpu().numpy()
+        n_t = touched_count(ngb_np, w.active)
 
     # algorithmic bytes per launch (FP64 form)
     knn_bytes = (4 + 4 * k + 8) * na + 24 * n_t
-    eval_bytes = (4 * k + 20) * na + 52 * n_t
-    ts_bytes = (4 * k + 20) * na + 24 * n_t
-    kern = {"knn": (tim["knn_ms"], knn_bytes), "eval": (tim["eval_ms"], eval_bytes),
-            "timestep": (tim["timestep_ms"], ts_bytes)}
+    if overlap:
+        # walk: target index, x, h and the h update; rows and counts out;
+        # partners' x and h; plus h of every particle into the tree's order
+        ovl_bytes = (4 + 32 + 8 + 4) * na + 4 * c_tot + 32 * n_to + 20 * w.n
+        eval_bytes = 20 * na + 4 * c_tot + 68 * n_to
+        ts_bytes = 20 * na + 4 * c_tot + 32 * n_to
+        kern = {"knn": (tim["knn_ms"], knn_bytes), "overlap": (tim["overlap_ms"], ovl_bytes),
+                "eval": (tim["eval_ms"], eval_bytes), "timestep": (tim["timestep_ms"], ts_bytes)}
+    else:
+        eval_bytes = (4 * k + 20) * na + 52 * n_t
+        ts_bytes = (4 * k + 20) * na + 24 * n_t
+        kern = {"knn": (tim["knn_ms"], knn_bytes), "eval": (tim["eval_ms"], eval_bytes),
+                "timestep": (tim["timestep_ms"], ts_bytes)}
     dom = max(kern, key=lambda n: kern[n][0])
     dom_ms, dom_bytes = kern[dom]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
@@ -263,6 +300,8 @@ def main():
                 "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": dom_ms}
 
     ngb_scatter_ms = tim["knn_ms"] + tim["eval_ms"] + tim["resolve_ms"] + 3 * tim["map_ms"]
+    if overlap:
+        ngb_scatter_ms += tim["overlap_ms"] + tim["map_ms"]
     res = {
         "metric": METRIC, "value": value, "unit": "active particles/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -271,7 +310,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": w.n, "n_active": na,
                    "n_ngb": k, "precision": args.precision, "touched": n_t,
-                   "tree": "refit" if args.refit else "rebuilt every step"},
+                   "tree": "refit" if args.refit else "rebuilt every step",
+                   "estimator": args.estimator},
         "p50_step_ms": float(np.percentile(step_ms, 50)),
         "p99_step_ms": float(np.percentile(step_ms, 99)),
         "phase_ms": {kk: round(v, 5) for kk, v in tim.items() if kk.endswith("_ms")},
@@ -280,7 +320,10 @@ def main():
         "events_last_step": stats["n_events"], "passes_last_step": stats["n_passes"],
         "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
+    if overlap:
+        res["overlap_partners_mean"] = c_tot / max(na, 1)
+        res["overlap_partners_max"] = int(cnt.max()) if na else 0
+    if not args.no_cpu_baseline and not overlap:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res))
 

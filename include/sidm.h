@@ -227,7 +227,11 @@ sidm_status sidm_pair_timestep(sidm_ctx *ctx, const int32_t *active, int64_t n_a
  * active or not (> 0 and finite; for example sidm_find_ngb's h over all
  * particles, or the last value of those not active now). */
 
-/* Partners of the active particles: for active[a] = i, every j != i with
+/* Partners of the active particles.  If h_active is not NULL, it holds the
+ * new smoothing lengths of the active particles (h_active[a] for active[a],
+ * for example sidm_find_ngb's h) and is first written into h_all, which is
+ * then read as every particle's h (so h_all is in/out).  For active[a] = i,
+ * the partners are every j != i with
  * r_ij < h_i + h_j, tested as r^2 < (h_i + h_j)^2 in FP64 with r^2 as in
  * sidm_find_ngb.  The tree's nodes first get the largest h below them (the
  * search region is h_i + that h_max).  Row a of ngb (max_ngb >= 1 entries,
@@ -235,8 +239,9 @@ sidm_status sidm_pair_timestep(sidm_ctx *ctx, const int32_t *active, int64_t n_a
  * by the tree (not sorted), count[a] their full number.  A row longer than
  * max_ngb keeps its first max_ngb and latches SIDM_E_OVERFLOW (sidm_sync);
  * an h that is not > 0 and finite latches SIDM_E_INVAL. */
-sidm_status sidm_find_overlap(sidm_ctx *ctx, const double *h_all, const int32_t *active,
-                              int64_t n_active, int32_t max_ngb, int32_t *ngb, int32_t *count);
+sidm_status sidm_find_overlap(sidm_ctx *ctx, double *h_all, const int32_t *active,
+                              const double *h_active, int64_t n_active, int32_t max_ngb,
+                              int32_t *ngb, int32_t *count);
 
 /* Scattering step with the overlap estimator: sidm_scatter_step with the
  * partners of row a being the first min(count[a], max_ngb) entries of
@@ -315,6 +320,7 @@ typedef struct {
     double eval_ms;       /* the candidate-evaluation kernel                       */
     double resolve_ms;    /* all resolution passes (grid passes and finisher)      */
     double timestep_ms;   /* the per-pair timestep kernel                          */
+    double overlap_ms;    /* sidm_find_overlap: h update, node h_max and the walk  */
 } sidm_timing;
 
 sidm_status sidm_timing_enable(sidm_ctx *ctx, int on);

@@ -77,7 +77,8 @@ class Timing(ctypes.Structure):
     _fields_ = [("samples", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("tree_ms", ctypes.c_double), ("map_ms", ctypes.c_double),
                 ("knn_ms", ctypes.c_double), ("eval_ms", ctypes.c_double),
-                ("resolve_ms", ctypes.c_double), ("timestep_ms", ctypes.c_double)]
+                ("resolve_ms", ctypes.c_double), ("timestep_ms", ctypes.c_double),
+                ("overlap_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -122,7 +123,7 @@ def lib():
         d = ctypes.c_double
         L.sidm_advance_hernquist.argtypes = [P, P, P, P, P, P, P, i64, P, i64, d, d, d, P, P]
         L.sidm_drift.argtypes = [P, P, P, P, P, P, P, i64, d]
-        L.sidm_find_overlap.argtypes = [P, P, P, i64, ctypes.c_int32, P, P]
+        L.sidm_find_overlap.argtypes = [P, P, P, P, i64, ctypes.c_int32, P, P]
         L.sidm_scatter_overlap.argtypes = [P, ctypes.POINTER(Particles), P, P, i64,
                                            ctypes.c_int32, P, P, P, u64, u32, P]
         L.sidm_pair_timestep_overlap.argtypes = [P, P, P, i64, ctypes.c_int32, P, P, P]
@@ -282,15 +283,17 @@ class Context:
                     "sidm_pair_timestep")
 
     # --- kernel-overlap estimator -------------------------------------------
-    def find_overlap(self, h_all, active, ngb, count):
+    def find_overlap(self, h_all, active, ngb, count, h_active=None):
         """Partners with r_ij < h_i + h_j: ngb int32[n_active, max_ngb] (rows in
-        tree order), count int32[n_active] (full counts)."""
+        tree order), count int32[n_active] (full counts).  h_active (optional)
+        is first written into h_all at the active particles."""
         torch = self._torch
         self._dev(h_all, torch.float64, "h_all")
+        self._dev(h_active, torch.float64, "h_active")
         self._dev(active, torch.int32, "active")
         self._dev(ngb, torch.int32, "ngb")
         self._dev(count, torch.int32, "count")
-        self._check(lib().sidm_find_overlap(self._h, _ptr(h_all), _ptr(active),
+        self._check(lib().sidm_find_overlap(self._h, _ptr(h_all), _ptr(active), _ptr(h_active),
                                             int(active.shape[0]), int(ngb.shape[1]), _ptr(ngb),
                                             _ptr(count)), "sidm_find_overlap")
 

@@ -12,6 +12,7 @@
 //                   outer integrand is a polynomial of degree <= 9 between
 //                   breakpoints, so a 5-point Gauss-Legendre rule per piece is
 //                   exact.  alpha = 0 is a point partner: ghat = W(rho, 1).
+//  k_update_h       (optional) the active particles' new h into h_all
 //  k_gather_h       every particle's h into Morton order (each checked > 0 and
 //                   finite), then k_leaf_hmax / k_level_hmax: the largest h
 //                   below every node of the tree, level after level (the
@@ -123,6 +124,20 @@ __global__ __launch_bounds__(kBlock) void k_overlap_table(double *tab)
     const double al = (double)a / (2.0 * SIDM_OVERLAP_NA);
     const double rho = (double)b / SIDM_OVERLAP_NR;
     tab[t] = a == 0 ? cubic_spline(rho, 1.0) : overlap_exact(al, 1.0 - al, rho);
+}
+
+// the active particles' new smoothing lengths into every particle's h
+__global__ __launch_bounds__(kBlock) void k_update_h(const int32_t *__restrict__ active,
+                                                     const double *__restrict__ h_active,
+                                                     int64_t n_active, int64_t n, double *h_all,
+                                                     unsigned int *derr)
+{
+    for (int64_t a = blockIdx.x * (int64_t)kBlock + threadIdx.x; a < n_active;
+         a += (int64_t)gridDim.x * kBlock) {
+        const int32_t i = active[a];
+        if (i < 0 || i >= n) { atomicOr(derr, DERR_INDEX); continue; }
+        h_all[i] = h_active[a];
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather_h(int64_t n, const int32_t *__restrict__ perm,
@@ -269,12 +284,17 @@ hipError_t launch_overlap_table(sidm_ctx *c)
     return hipGetLastError();
 }
 
-hipError_t launch_find_overlap(sidm_ctx *c, const double *h_all, int64_t n_active,
-                               int32_t max_ngb, int32_t *ngb, int32_t *count)
+hipError_t launch_find_overlap(sidm_ctx *c, double *h_all, const int32_t *active,
+                               const double *h_active, int64_t n_active, int32_t max_ngb,
+                               int32_t *ngb, int32_t *count)
 {
     hipStream_t s = c->stream;
     const int64_t n = c->n;
     const TreeLevels &lv = c->lv;
+    phase_begin(c, PH_OVERLAP);
+    if (h_active)
+        k_update_h<<<grid_for(n_active), kBlock, 0, s>>>(active, h_active, n_active, n, h_all,
+                                                         c->derr);
     k_gather_h<<<grid_for(n), kBlock, 0, s>>>(n, c->perm, h_all, c->hs, c->derr);
     const int64_t nleaf = lv.cnt[0];
     k_leaf_hmax<<<(unsigned)((nleaf * 32 + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, nleaf, c->hs,
@@ -288,9 +308,8 @@ hipError_t launch_find_overlap(sidm_ctx *c, const double *h_all, int64_t n_activ
     A.ngb = ngb; A.count = count; A.derr = c->derr;
     A.lv = lv; A.n = n; A.box = c->cfg.box; A.max_ngb = max_ngb;
     const unsigned grid = (unsigned)((n_active + kBlock / kTeamO - 1) / (kBlock / kTeamO));
-    phase_begin(c, PH_KNN);
     if (c->cfg.periodic) k_overlap<true><<<grid, kBlock, 0, s>>>(A);
     else k_overlap<false><<<grid, kBlock, 0, s>>>(A);
-    phase_end(c, PH_KNN);
+    phase_end(c, PH_OVERLAP);
     return hipGetLastError();
 }

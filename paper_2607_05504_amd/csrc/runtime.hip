@@ -253,7 +253,7 @@ sidm_status sidm_timing_enable(sidm_ctx *c, int on)
 {
     if (!c) return SIDM_E_INVAL;
     if (on && !c->timing) {
-        for (int p = 0; p < 6; ++p)
+        for (int p = 0; p < SIDM_PHASES; ++p)
             for (int r = 0; r < SIDM_TIMING_RING; ++r)
                 for (int b = 0; b < 2; ++b)
                     if (!c->ev[p][r][b] && hipEventCreate(&c->ev[p][r][b]) != hipSuccess) {
@@ -261,7 +261,7 @@ sidm_status sidm_timing_enable(sidm_ctx *c, int on)
                         return SIDM_E_DEVICE;
                     }
     }
-    for (int p = 0; p < 6; ++p) c->ev_count[p] = 0;
+    for (int p = 0; p < SIDM_PHASES; ++p) c->ev_count[p] = 0;
     c->timing = on ? 1 : 0;
     return SIDM_OK;
 }
@@ -271,9 +271,9 @@ sidm_status sidm_timing_read(sidm_ctx *c, sidm_timing *out)
     if (!c || !out) return SIDM_E_INVAL;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "timing_read");
-    double v[6];
+    double v[SIDM_PHASES];
     int samples = 0;
-    for (int p = 0; p < 6; ++p) {
+    for (int p = 0; p < SIDM_PHASES; ++p) {
         double sum = 0.0;
         for (int r = 0; r < c->ev_count[p]; ++r) {
             float ms = 0.0f;
@@ -290,6 +290,7 @@ sidm_status sidm_timing_read(sidm_ctx *c, sidm_timing *out)
     out->eval_ms = v[PH_EVAL];
     out->resolve_ms = v[PH_RESOLVE];
     out->timestep_ms = v[PH_TIMESTEP];
+    out->overlap_ms = v[PH_OVERLAP];
     return SIDM_OK;
 }
 
@@ -297,7 +298,7 @@ sidm_status sidm_destroy(sidm_ctx *c)
 {
     if (!c) return SIDM_E_INVAL;
     (void)hipStreamSynchronize(c->stream);
-    for (int p = 0; p < 6; ++p)
+    for (int p = 0; p < SIDM_PHASES; ++p)
         for (int r = 0; r < SIDM_TIMING_RING; ++r)
             for (int b = 0; b < 2; ++b)
                 if (c->ev[p][r][b]) (void)hipEventDestroy(c->ev[p][r][b]);
@@ -508,15 +509,17 @@ static sidm_status check_overlap(sidm_ctx *c, const double *h_all, const int32_t
     return SIDM_OK;
 }
 
-sidm_status sidm_find_overlap(sidm_ctx *c, const double *h_all, const int32_t *active,
-                              int64_t n_active, int32_t max_ngb, int32_t *ngb, int32_t *count)
+sidm_status sidm_find_overlap(sidm_ctx *c, double *h_all, const int32_t *active,
+                              const double *h_active, int64_t n_active, int32_t max_ngb,
+                              int32_t *ngb, int32_t *count)
 {
     if (!c) return SIDM_E_INVAL;
     sidm_status st = check_overlap(c, h_all, active, n_active, max_ngb, ngb, count, "find_overlap");
     if (st != SIDM_OK) return st;
     if (n_active == 0) return SIDM_OK;
     hipError_t e = launch_map_active(c, active, n_active);
-    if (e == hipSuccess) e = launch_find_overlap(c, h_all, n_active, max_ngb, ngb, count);
+    if (e == hipSuccess)
+        e = launch_find_overlap(c, h_all, active, h_active, n_active, max_ngb, ngb, count);
     if (e != hipSuccess) return hip_fail(c, e, "find_overlap");
     return SIDM_OK;
 }

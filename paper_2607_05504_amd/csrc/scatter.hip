@@ -646,25 +646,39 @@ __global__ __launch_bounds__(kBlock) void k_timestep(StepArgs A, double c_sidm, 
 }
 
 // Overlap estimator: dt_i = 2 C_SIDM / (m_i max_j [g_ij(0) (w_ij sigma(w_ij)/m)])
-// over the partners of the target's row; one thread per target.
+// over the partners of the target's row.  A team of kTeamT lanes per target
+// strides over its row; the maximum is taken by shuffles within the team.
+constexpr int kTeamT = 16;
+
 __global__ __launch_bounds__(kBlock) void k_timestep_overlap(StepArgs A, double c_sidm, double *dt_out)
 {
     const int64_t nt = *A.nt_dev;
-    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nt;
-         b += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t i = A.tlist[b], a = A.slot[b];
-        const double vix = A.vxs[i], viy = A.vys[i], viz = A.vzs[i];
-        const double hi = A.h_all[A.perm[i]];
-        const int len = A.cnt[a] < A.stride ? A.cnt[a] : A.stride;
+    const int tl = threadIdx.x % kTeamT;
+    const int64_t teams = (int64_t)gridDim.x * (kBlock / kTeamT);
+    for (int64_t b0 = (int64_t)blockIdx.x * (kBlock / kTeamT); b0 < nt; b0 += teams) {
+        const int64_t b = b0 + threadIdx.x / kTeamT;     // team-uniform
         double qmax = 0.0;
-        for (int s = 0; s < len; ++s) {
-            const int32_t jc = A.ngb[(int64_t)a * A.stride + s];
-            const double rate = pair_rate(A, vix, viy, viz, jc);
-            if (jc < 0 || jc >= A.n) continue;
-            const double q = overlap_g(A.gtab, hi, A.h_all[jc], 0.0) * rate;
-            qmax = q > qmax ? q : qmax;
+        int32_t i = 0, a = 0;
+        if (b < nt) {
+            i = A.tlist[b];
+            a = A.slot[b];
+            const double vix = A.vxs[i], viy = A.vys[i], viz = A.vzs[i];
+            const double hi = A.h_all[A.perm[i]];
+            const int len = A.cnt[a] < A.stride ? A.cnt[a] : A.stride;
+            for (int s = tl; s < len; s += kTeamT) {
+                const int32_t jc = A.ngb[(int64_t)a * A.stride + s];
+                const double rate = pair_rate(A, vix, viy, viz, jc);
+                if (jc < 0 || jc >= A.n) continue;
+                const double q = overlap_g(A.gtab, hi, A.h_all[jc], 0.0) * rate;
+                qmax = q > qmax ? q : qmax;
+            }
         }
-        dt_out[a] = qmax > 0.0 ? (2.0 * c_sidm) / (mass_of(A, i) * qmax) : INFINITY;
+        for (int off = 1; off < kTeamT; off <<= 1) {
+            const double o = __shfl_xor(qmax, off);
+            qmax = o > qmax ? o : qmax;
+        }
+        if (b < nt && tl == 0)
+            dt_out[a] = qmax > 0.0 ? (2.0 * c_sidm) / (mass_of(A, i) * qmax) : INFINITY;
     }
 }
 
@@ -774,7 +788,8 @@ hipError_t launch_timestep_overlap(sidm_ctx *c, int64_t n_active, const double *
     StepArgs A = make_args(c, nullptr, ngb, nullptr, nullptr, 0, 0, nullptr);
     A.stride = max_ngb; A.cnt = count; A.h_all = h_all;
     phase_begin(c, PH_TIMESTEP);
-    k_timestep_overlap<<<grid_for(n_active), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm, dt_out);
+    k_timestep_overlap<<<grid_for(n_active * kTeamT), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm,
+                                                                             dt_out);
     phase_end(c, PH_TIMESTEP);
     return hipGetLastError();
 }

@@ -13,6 +13,7 @@
 #define SIDM_SORT_TILE 2048     // keys per radix-sort workgroup (256 threads x 8)
 #define SIDM_SCAN_TILE 1024     // elements per compaction workgroup
 #define SIDM_TIMING_RING 256    // timed launches per phase between two reads
+#define SIDM_PHASES 7           // timed phases (PH_* below)
 #define SIDM_KNN_LMAX 96        // leaves per target list (longer lists walk the tree instead)
 #define SIDM_KNN_BATCH (1 << 20)  // targets per neighbour-search batch
 
@@ -139,8 +140,8 @@ struct sidm_ctx {
     // opt-in event timing of the main kernels: up to SIDM_TIMING_RING launches
     // of each phase are bracketed between two sidm_timing_read calls
     int timing;
-    hipEvent_t ev[6][SIDM_TIMING_RING][2];
-    int ev_count[6];
+    hipEvent_t ev[SIDM_PHASES][SIDM_TIMING_RING][2];
+    int ev_count[SIDM_PHASES];
     void *dev_base;          // the one device allocation every buffer above lives in
     DevStats *hstats;        // pinned host copy
     unsigned int *herr;
@@ -330,7 +331,8 @@ __device__ __forceinline__ double unit_from_word(uint64_t w)
 }
 
 // phases timed by sidm_timing
-enum { PH_TREE = 0, PH_MAP = 1, PH_KNN = 2, PH_EVAL = 3, PH_RESOLVE = 4, PH_TIMESTEP = 5 };
+enum { PH_TREE = 0, PH_MAP = 1, PH_KNN = 2, PH_EVAL = 3, PH_RESOLVE = 4, PH_TIMESTEP = 5,
+       PH_OVERLAP = 6 };
 
 inline void phase_begin(sidm_ctx *c, int ph)
 {
@@ -385,8 +387,9 @@ hipError_t launch_timestep_overlap(sidm_ctx *c, int64_t n_active, const double *
                                    double *dt_out);
 // overlap.hip
 hipError_t launch_overlap_table(sidm_ctx *c);
-hipError_t launch_find_overlap(sidm_ctx *c, const double *h_all, int64_t n_active,
-                               int32_t max_ngb, int32_t *ngb, int32_t *count);
+hipError_t launch_find_overlap(sidm_ctx *c, double *h_all, const int32_t *active,
+                               const double *h_active, int64_t n_active, int32_t max_ngb,
+                               int32_t *ngb, int32_t *count);
 // advance.hip
 hipError_t launch_advance(sidm_ctx *c, double *x, double *y, double *z, double *vx, double *vy,
                           double *vz, int64_t n, const double *dt_sidm, int64_t n_active,

@@ -96,6 +96,8 @@ class OverlapOut:
     everyone: "torch.Tensor"     # int32[n] 0..n-1 (all particles as targets)
     ngb_all: "torch.Tensor"      # int32[n, n_ngb] neighbour lists of every particle
     h_all: "torch.Tensor"        # float64[n] every particle's smoothing length
+    ngb_k: "torch.Tensor"        # int32[n_active, n_ngb] neighbours of the active ones
+    h_k: "torch.Tensor"          # float64[n_active] their new smoothing lengths
     ngb: "torch.Tensor"          # int32[n_active, max_ngb] overlap partners
     count: "torch.Tensor"        # int32[n_active]
     dt_sidm: "torch.Tensor"
@@ -110,6 +112,8 @@ def alloc_overlap(ds: DeviceState, k: int, max_ngb: int, with_info: bool = False
         everyone=torch.arange(n, dtype=torch.int32, device=dev),
         ngb_all=torch.empty((n, k), dtype=torch.int32, device=dev),
         h_all=torch.empty(n, dtype=torch.float64, device=dev),
+        ngb_k=torch.empty((na, k), dtype=torch.int32, device=dev),
+        h_k=torch.empty(na, dtype=torch.float64, device=dev),
         ngb=torch.empty((na, max_ngb), dtype=torch.int32, device=dev),
         count=torch.empty(na, dtype=torch.int32, device=dev),
         dt_sidm=torch.empty(na, dtype=torch.float64, device=dev),
@@ -118,17 +122,21 @@ def alloc_overlap(ds: DeviceState, k: int, max_ngb: int, with_info: bool = False
 
 
 def run_overlap_step(ctx: Context, ds: DeviceState, out: OverlapOut, seed: int, step: int,
-                     smoothing: bool = True):
-    """One step with the kernel-overlap estimator: the tree, every particle's
-    h (sidm_find_ngb over all particles; skipped when smoothing is False and
-    out.h_all already holds them), the overlap partners of the active ones,
-    the scattering step and the per-pair timestep.  The context needs
-    capacity for all particles as targets (cap_active = n)."""
+                     smoothing: str = "all"):
+    """One step with the kernel-overlap estimator: the tree, smoothing
+    lengths, the overlap partners of the active particles, the scattering
+    step and the per-pair timestep.  smoothing = "all": every particle's h
+    from sidm_find_ngb over all of them (the context needs cap_active = n);
+    "active": only the active particles' h, written into out.h_all by
+    sidm_find_overlap (the others keep the values out.h_all holds)."""
     ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state,
                    m_scalar=ds.mass)
-    if smoothing:
+    if smoothing == "all":
         ctx.find_ngb(out.everyone, out.ngb_all, out.h_all)
-    ctx.find_overlap(out.h_all, ds.active, out.ngb, out.count)
+        ctx.find_overlap(out.h_all, ds.active, out.ngb, out.count)
+    else:
+        ctx.find_ngb(ds.active, out.ngb_k, out.h_k)
+        ctx.find_overlap(out.h_all, ds.active, out.ngb, out.count, h_active=out.h_k)
     ctx.scatter_overlap(out.h_all, ds.active, out.ngb, out.count, ds.dt, seed, step,
                         cand_info=out.cand_info)
     ctx.pair_timestep_overlap(out.h_all, ds.active, out.ngb, out.count, out.dt_sidm)

@@ -201,3 +201,31 @@ def test_bad_smoothing_length_and_wrong_context():
     plain.sync()
     plain.close()
     torch.cuda.synchronize()
+
+
+def test_active_smoothing_update_path():
+    """Stale h in h_all at the active particles: sidm_find_overlap with the
+    active particles' new h (h_active) writes them into h_all first, and the
+    partners are those of the true smoothing lengths."""
+    import torch
+    from paper_2607_05504_amd import runner
+    w = W.hernquist_bins(W.hernquist_halo(30000, ic_seed=87, philox_seed=6))
+    _announce(f"overlap with the active h update, active={w.n_active}")
+    h_true = oracle.smoothing_lengths(w)
+    ngb_ref, cnt_ref = oracle.find_overlap(w, h_true, 1024)
+    ds = runner.upload(w, "cuda")
+    ctx = _ctx(w)
+    out = runner.alloc_overlap(ds, w.n_ngb, 1024)
+    stale = h_true.copy()
+    stale[w.active] *= 1.37
+    out.h_all.copy_(torch.from_numpy(stale))
+    runner.run_overlap_step(ctx, ds, out, w.seed, w.step, smoothing="active")
+    st = ctx.sync()
+    assert st["error"] == 0
+    assert np.array_equal(out.h_all.cpu().numpy(), h_true)
+    cnt = out.count.cpu().numpy()
+    assert np.array_equal(cnt, cnt_ref)
+    g = out.ngb.cpu().numpy()
+    for a in range(w.n_active):
+        assert np.array_equal(np.sort(g[a, :cnt[a]]), ngb_ref[a, :cnt[a]])
+    ctx.close()
