@@ -5,14 +5,15 @@
 // Two kernels per batch of targets, over the bucket tree (leaves of SIDM_LEAF
 // Morton-consecutive particles, SIDM_TREE_FAN-ary parents):
 //
-//  k_knn_list  one lane per target.  A valid upper bound T on r^2 of the
-//              (N_ngb+1)-th neighbour comes from the target's window of
-//              Morton-order neighbours: the window's (N_ngb+1)-th smallest r^2,
-//              bracketed in FP32 rounded up, so the bound never falls below the
-//              exact value.  The wavefront then walks the tree level by level
-//              against the box enclosing all its targets' spheres (64 children
-//              tested per round, one coalesced load), and each lane keeps the
-//              leaves that meet its own sphere.
+//  k_knn_list  eight lanes per target, eight targets per wavefront.  A valid
+//              upper bound T on r^2 of the (N_ngb+1)-th neighbour comes from
+//              the target's Morton-order neighbours (64 on each side): their
+//              (N_ngb+1)-th smallest r^2, bracketed in FP32 rounded up, so the
+//              bound never falls below the exact value.  The wavefront then
+//              walks the tree level by level against the box enclosing all its
+//              targets' spheres (64 children tested per round, one coalesced
+//              load), and each target's lanes keep the leaves that meet its
+//              own sphere.
 //
 //  k_knn_team  a team of 16 lanes per target, four targets per wavefront.  The
 //              team keys its leaf list by gap (FP32 rounded down, packed with
@@ -91,39 +92,57 @@ __device__ __forceinline__ double sep2_sel(double xi, double yi, double zi, doub
     return (dx * dx + dy * dy) + dz * dz;
 }
 
-// Upper bound on the K1-th smallest r^2 among the other particles of the
-// Morton-order window [w0, w0 + W], bracketed in FP32 with values rounded up
-// (so no count exceeds the exact one); +inf if fewer than K1 fit in FP32.
-template <bool PERIODIC, int W>
-__device__ __forceinline__ double window_bound(const KnnArgs &A, int64_t i, int64_t w0, double px,
-                                               double py, double pz, int K1)
+// Upper bound on the K1-th smallest r^2, found by the LT lanes of a target:
+// the K1-th smallest of the FP32 r^2 (rounded up) of the other particles
+// within W places of the target in Morton order (W before and W after,
+// shifted inward at the ends of the order).  Any K1 other particles bound the
+// K1-th nearest from above, and rounding up keeps the bound valid.  +inf if
+// fewer than K1 values are finite.
+template <bool PERIODIC, int LT, int W>
+__device__ __forceinline__ double window_bound(const KnnArgs &A, int64_t i, double px, double py,
+                                               double pz, int K1, int sub)
 {
-    float r2f[W + 1];
-    float lo = INFINITY, hi = 0.0f;
+    constexpr int PER = (2 * W + 1 + LT - 1) / LT;
+    const int64_t n = A.n;
+    int64_t w0 = i - W;
+    if (w0 > n - 1 - 2 * W) w0 = n - 1 - 2 * W;
+    if (w0 < 0) w0 = 0;
+    float v[PER];
+    uint32_t lo = 0xffffffffu, hi = 0u;
 #pragma unroll
-    for (int t = 0; t <= W; ++t) {
-        const int64_t j = w0 + t;
-        float v = INFINITY;
-        if (j < A.n && j != i)
-            v = __double2float_ru(sep2_sel<PERIODIC>(px, py, pz, A.xs[j], A.ys[j], A.zs[j], A.box));
-        r2f[t] = v;
-        if (v < INFINITY) { lo = fminf(lo, v); hi = fmaxf(hi, v); }
+    for (int q = 0; q < PER; ++q) {
+        const int64_t j = w0 + q * LT + sub;
+        v[q] = INFINITY;
+        if (j < n && j <= w0 + 2 * W && j != i)
+            v[q] = __double2float_ru(sep2_sel<PERIODIC>(px, py, pz, A.xs[j], A.ys[j], A.zs[j], A.box));
+        if (v[q] < INFINITY) {
+            const uint32_t bv = __float_as_uint(v[q]);
+            lo = bv < lo ? bv : lo;
+            hi = bv > hi ? bv : hi;
+        }
     }
-    int c_lo = 0, c_hi = 0;
-#pragma unroll
-    for (int t = 0; t <= W; ++t) { c_lo += r2f[t] <= lo; c_hi += r2f[t] <= hi; }
-    if (c_hi < K1) return INFINITY;
-    if (c_lo >= K1) return (double)lo;
-    for (int it = 0; it < 12; ++it) {
-        const uint32_t bl = __float_as_uint(lo), bh = __float_as_uint(hi);
-        if (bh - bl <= 1) break;
-        const float mid = __uint_as_float(bl + ((bh - bl) >> 1));
+    for (int off = 1; off < LT; off <<= 1) {
+        const uint32_t ol = (uint32_t)__shfl_xor((int)lo, off);
+        const uint32_t oh = (uint32_t)__shfl_xor((int)hi, off);
+        lo = ol < lo ? ol : lo;
+        hi = oh > hi ? oh : hi;
+    }
+    auto count_le = [&](uint32_t bits) {
+        const float f = __uint_as_float(bits);
         int c = 0;
 #pragma unroll
-        for (int t = 0; t <= W; ++t) c += r2f[t] <= mid;
-        if (c >= K1) hi = mid; else lo = mid;
+        for (int q = 0; q < PER; ++q) c += v[q] <= f;
+        for (int off = 1; off < LT; off <<= 1) c += __shfl_xor(c, off);
+        return c;
+    };
+    if (lo > hi || count_le(hi) < K1) return INFINITY;
+    // bisection on the FP32 bit patterns (monotone for values >= 0): the
+    // smallest bracket end with >= K1 values at or below it; hi always has
+    for (int it = 0; it < 14 && lo < hi; ++it) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (count_le(mid) >= K1) hi = mid; else lo = mid + 1;
     }
-    return (double)hi;
+    return (double)__uint_as_float(hi);
 }
 
 // ---------------------------------------------------------------------------
@@ -157,14 +176,15 @@ __device__ __forceinline__ bool interval_meets(double lo, double hi, double glo,
 // Level-synchronous walk of the tree for the lanes with member set, against
 // the box enclosing their spheres: every round tests up to 64 children (one
 // per lane, one coalesced load); surviving internal nodes form the next
-// frontier, surviving leaves are offered to each member's own sphere and
-// appended to its list.  Returns true if the walk gave up (frontier or leaf
-// count too large), in which case the members' lists are incomplete.
-template <bool PERIODIC>
+// frontier, surviving leaves are offered to each member's own sphere (the LT
+// lanes of a target take every LT-th leaf) and appended to its list; nl
+// counts them all, also past the list's capacity.  Returns true if the walk
+// gave up (frontier or leaf count too large), in which case the members'
+// lists are incomplete.
+template <bool PERIODIC, int LT>
 __device__ __forceinline__ bool group_walk(const KnnArgs &A, int32_t (&s_fr)[2][kFront],
                                            double *s_hit, bool member, double px, double py,
-                                           double pz, double T, double R, int32_t *lst, int &nl,
-                                           bool &ovf)
+                                           double pz, double T, double R, int32_t *lst, int &nl)
 {
     const int lane = threadIdx.x;
     const double box = A.box;
@@ -212,12 +232,17 @@ __device__ __forceinline__ bool group_walk(const KnnArgs &A, int32_t (&s_fr)[2][
                     s_fr[cur ^ 1][rank] = (int32_t)q;
                 }
                 wave_sync();
-                for (int h = 0; h < nh; ++h) {
-                    const double g = box_gap2<PERIODIC>(s_hit + h * 6, px, py, pz, box);
-                    if (member && g <= T) {
-                        if (nl < SIDM_KNN_LMAX) lst[nl++] = s_fr[cur ^ 1][h];
-                        else ovf = true;
-                    }
+                const int sub = lane % LT;
+                const uint64_t mine = (LT == 64) ? ~0ull : ((1ull << LT) - 1ull);
+                for (int h0 = 0; h0 < nh; h0 += LT) {
+                    const int h = h0 + sub;
+                    bool ok = false;
+                    if (h < nh)
+                        ok = member && box_gap2<PERIODIC>(s_hit + h * 6, px, py, pz, box) <= T;
+                    const uint64_t m = (__ballot(ok) >> (lane - sub)) & mine;
+                    const int pos = nl + __popcll(m & ((1ull << sub) - 1ull));
+                    if (ok && pos < SIDM_KNN_LMAX) lst[pos] = s_fr[cur ^ 1][h];
+                    nl += __popcll(m);
                 }
             }
         }
@@ -227,44 +252,34 @@ __device__ __forceinline__ bool group_walk(const KnnArgs &A, int32_t (&s_fr)[2][
     return false;
 }
 
-template <bool PERIODIC, int W>
+template <bool PERIODIC, int LT>
 __global__ __launch_bounds__(64) void k_knn_list(KnnArgs A, int64_t base)
 {
+    constexpr int G = 64 / LT;                // targets per wavefront
     __shared__ int32_t s_fr[2][kFront];
     __shared__ double s_hit[64 * 6];
     const int nt = *A.nt_dev;
-    const int lane = threadIdx.x;
-    const int64_t bb = (int64_t)blockIdx.x * 64 + lane;
+    const int lane = threadIdx.x, sub = lane % LT;
+    const int64_t bb = (int64_t)blockIdx.x * G + lane / LT;
     const int64_t b = base + bb;
     const bool valid = b < nt && bb < A.batch;
     if (!__any(valid)) return;
-    const int32_t i = A.tlist[valid ? b : base + (int64_t)blockIdx.x * 64];
+    const int32_t i = A.tlist[valid ? b : base + (int64_t)blockIdx.x * G];
     const double px = A.xs[i], py = A.ys[i], pz = A.zs[i];
     const double box = A.box;
-    const int64_t n = A.n;
-    const int K1 = A.k + 1;
-
-    // bound: the smaller of two one-sided windows' K1-th smallest r^2 (the
-    // W Morton-order particles before and after the target), so a target at a
-    // jump of the curve still gets the bound of its compact side
-    const int64_t wmax = n - (W + 1) > 0 ? n - (W + 1) : 0;
-    const int64_t wl = i - W < 0 ? 0 : (i - W > wmax ? wmax : i - W);
-    const int64_t wr = i > wmax ? wmax : i;
-    const double T = fmin(window_bound<PERIODIC, W>(A, i, wl, px, py, pz, K1),
-                          window_bound<PERIODIC, W>(A, i, wr, px, py, pz, K1));
+    const double T = window_bound<PERIODIC, LT, 64>(A, i, px, py, pz, A.k + 1, sub);
 
     // sphere radius padded far beyond rounding, so a box a lane needs always
     // meets the group box
     const double R = sqrt(T) * (1.0 + 1e-9) + (fabs(px) + fabs(py) + fabs(pz) + box) * 1e-14;
     int32_t *lst = A.list + bb * SIDM_KNN_LMAX;
     int nl = 0;
-    bool ovf = false;
     // targets spread far apart (a jump of the Morton curve) would make the
     // group walk too long: then they walk the tree one by one in the second
-    // kernel
-    if (group_walk<PERIODIC>(A, s_fr, s_hit, valid, px, py, pz, T, R, lst, nl, ovf)) ovf = true;
-    if (!valid) return;
-    A.nl[bb] = ovf ? -1 : nl;
+    // kernel, as do targets with more than SIDM_KNN_LMAX leaves
+    const bool gave_up = group_walk<PERIODIC, LT>(A, s_fr, s_hit, valid, px, py, pz, T, R, lst, nl);
+    if (!valid || sub != 0) return;
+    A.nl[bb] = (gave_up || nl > SIDM_KNN_LMAX) ? -1 : nl;
     A.tb[bb] = T;
 }
 
@@ -725,6 +740,7 @@ void k_knn_team(KnnArgs A, int64_t base)
 constexpr int kTeam = 16;                 // lanes per target in the team kernel (8 measured slower)
 
 constexpr int kLeavesPerStep = 1;          // leaves a team tests per step of its loop
+constexpr int kListLanes = 8;              // lanes per target in the leaf-list kernel
 
 // teams of TS lanes; the list holds TS * E entries; LPI leaves per step
 template <bool P, int E, bool M, int TS, int LPI>
@@ -733,7 +749,8 @@ void launch_batches_l(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipSt
     for (int64_t base = 0; base < n_active; base += nb_cap) {
         KnnArgs A = A0;
         A.batch = (n_active - base) < nb_cap ? (n_active - base) : nb_cap;
-        k_knn_list<P, 64><<<(unsigned)((A.batch + 63) / 64), 64, 0, s>>>(A, base);
+        constexpr int G = 64 / kListLanes;
+        k_knn_list<P, kListLanes><<<(unsigned)((A.batch + G - 1) / G), 64, 0, s>>>(A, base);
         k_knn_team<P, E, M, TS, LPI><<<(unsigned)((A.batch + 256 / TS - 1) / (256 / TS)), 256, 0, s>>>(A, base);
     }
 }
