@@ -5,7 +5,7 @@
 // Two kernels per batch of targets, over the bucket tree (leaves of SIDM_LEAF
 // Morton-consecutive particles, SIDM_TREE_FAN-ary parents):
 //
-//  k_knn_list  eight lanes per target, eight targets per wavefront.  A valid
+//  k_knn_list  sixteen lanes per target, four targets per wavefront.  A valid
 //              upper bound T on r^2 of the (N_ngb+1)-th neighbour comes from
 //              the target's Morton-order neighbours (64 on each side): their
 //              (N_ngb+1)-th smallest r^2, bracketed in FP32 rounded up, so the
@@ -740,7 +740,7 @@ void k_knn_team(KnnArgs A, int64_t base)
 constexpr int kTeam = 16;                 // lanes per target in the team kernel (8 measured slower)
 
 constexpr int kLeavesPerStep = 1;          // leaves a team tests per step of its loop
-constexpr int kListLanes = 8;              // lanes per target in the leaf-list kernel
+constexpr int kListLanes = 16;             // lanes per target in the leaf-list kernel (measured: 2, 4, 8, 32, 64 slower on the 10^6 halo)
 
 // teams of TS lanes; the list holds TS * E entries; LPI leaves per step
 template <bool P, int E, bool M, int TS, int LPI>
