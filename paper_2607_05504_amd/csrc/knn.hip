@@ -416,7 +416,7 @@ __device__ __forceinline__ int32_t walk_next(const KnnArgs &A, int32_t *stk, int
 }
 
 template <bool PERIODIC, int E, bool MIXED, int TS, int LPI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MIXED ? 3 : 4)))
 void k_knn_team(KnnArgs A, int64_t base)
 {
     constexpr int N = TS * E;                 // list capacity
