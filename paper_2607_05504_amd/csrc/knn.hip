@@ -253,18 +253,20 @@ __device__ __forceinline__ bool group_walk(const KnnArgs &A, int32_t (&s_fr)[2][
 }
 
 template <bool PERIODIC, int LT>
-__global__ __launch_bounds__(64) void k_knn_list(KnnArgs A, int64_t base)
+__global__ __launch_bounds__(64) void k_knn_list(KnnArgs A, int64_t base, int64_t nblk)
 {
     constexpr int G = 64 / LT;                // targets per wavefront
     __shared__ int32_t s_fr[2][kFront];
     __shared__ double s_hit[64 * 6];
+    const int64_t blk = xcd_block(nblk);
+    if (blk < 0) return;
     const int nt = *A.nt_dev;
     const int lane = threadIdx.x, sub = lane % LT;
-    const int64_t bb = (int64_t)blockIdx.x * G + lane / LT;
+    const int64_t bb = blk * G + lane / LT;
     const int64_t b = base + bb;
     const bool valid = b < nt && bb < A.batch;
     if (!__any(valid)) return;
-    const int32_t i = A.tlist[valid ? b : base + (int64_t)blockIdx.x * G];
+    const int32_t i = A.tlist[valid ? b : base + blk * G];
     const double px = A.xs[i], py = A.ys[i], pz = A.zs[i];
     const double box = A.box;
     const double T = window_bound<PERIODIC, LT, 64>(A, i, px, py, pz, A.k + 1, sub);
@@ -417,7 +419,7 @@ __device__ __forceinline__ int32_t walk_next(const KnnArgs &A, int32_t *stk, int
 
 template <bool PERIODIC, int E, bool MIXED, int TS, int LPI>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MIXED ? 3 : 4)))
-void k_knn_team(KnnArgs A, int64_t base)
+void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
 {
     constexpr int N = TS * E;                 // list capacity
     constexpr int KP = (SIDM_KNN_LMAX + TS - 1) / TS;
@@ -432,7 +434,9 @@ void k_knn_team(KnnArgs A, int64_t base)
     const int team = threadIdx.x / TS, tl = threadIdx.x % TS;
     const int wteam = team % (64 / TS);       // team within the wavefront
     const int nt = *A.nt_dev;
-    const int64_t bb = (int64_t)blockIdx.x * NT + team;
+    const int64_t blk = xcd_block(nblk);
+    if (blk < 0) return;                      // whole workgroup
+    const int64_t bb = blk * NT + team;
     const int64_t b = base + bb;
     if (!(b < nt && bb < A.batch)) return;    // whole team
     const int32_t i = A.tlist[b];
@@ -750,8 +754,9 @@ void launch_batches_l(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipSt
         KnnArgs A = A0;
         A.batch = (n_active - base) < nb_cap ? (n_active - base) : nb_cap;
         constexpr int G = 64 / kListLanes;
-        k_knn_list<P, kListLanes><<<(unsigned)((A.batch + G - 1) / G), 64, 0, s>>>(A, base);
-        k_knn_team<P, E, M, TS, LPI><<<(unsigned)((A.batch + 256 / TS - 1) / (256 / TS)), 256, 0, s>>>(A, base);
+        const int64_t gl = (A.batch + G - 1) / G, gt = (A.batch + 256 / TS - 1) / (256 / TS);
+        k_knn_list<P, kListLanes><<<xcd_grid(gl), 64, 0, s>>>(A, base, gl);
+        k_knn_team<P, E, M, TS, LPI><<<xcd_grid(gt), 256, 0, s>>>(A, base, gt);
     }
 }
 

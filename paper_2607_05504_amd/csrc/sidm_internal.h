@@ -213,6 +213,31 @@ __device__ __forceinline__ double node_gap2(const double *__restrict__ nodes, in
     return (gx * gx + gy * gy) + gz * gz;
 }
 
+// XCD-aware block order.  The 8 XCDs of an MI355X each have their own L2, and
+// a launch deals its workgroups to them round-robin (workgroup b to XCD
+// b % 8).  Launched with xcd_grid(g) workgroups, xcd_block maps them so that
+// each XCD runs runs of SIDM_XCD_RUN consecutive logical blocks (spatially
+// close targets share an L2), the runs dealt round-robin so that the XCDs'
+// loads stay balanced.  Returns -1 for the padding workgroups, which must do
+// nothing.
+#define SIDM_XCDS 8
+#ifndef SIDM_XCD_RUN
+#define SIDM_XCD_RUN 16
+#endif
+inline unsigned xcd_grid(int64_t g)
+{
+    const int64_t span = (int64_t)SIDM_XCDS * SIDM_XCD_RUN;
+    return (unsigned)((g + span - 1) / span * span);
+}
+__device__ __forceinline__ int64_t xcd_block(int64_t g)
+{
+    const int64_t b = blockIdx.x;
+    const int64_t x = b % SIDM_XCDS, k = b / SIDM_XCDS;     // k-th workgroup on XCD x
+    const int64_t logical = (k / SIDM_XCD_RUN) * (SIDM_XCDS * SIDM_XCD_RUN) + x * SIDM_XCD_RUN +
+                            k % SIDM_XCD_RUN;
+    return logical < g ? logical : -1;
+}
+
 // Cubic spline kernel W_CS(r, h) with support radius h.
 __device__ __forceinline__ double cubic_spline(double r, double h)
 {
