@@ -229,3 +229,48 @@ def test_active_smoothing_update_path():
     for a in range(w.n_active):
         assert np.array_equal(np.sort(g[a, :cnt[a]]), ngb_ref[a, :cnt[a]])
     ctx.close()
+
+
+@pytest.mark.parametrize("n,periodic", [(40, True), (100, True), (257, False), (1000, True)])
+def test_small_and_wide_kernels(n, periodic):
+    """Ragged small inputs; in the periodic boxes h_i + h_j exceeds half the
+    box for most pairs, so partners are found through the periodic images
+    (minimum image, as the oracle defines r_ij)."""
+    w = W.uniform_box(n, ic_seed=90 + n) if periodic else W.hernquist_halo(n, ic_seed=90 + n)
+    ref = _oracle(w, 1024)
+    max_ngb = max(int(ref["count"].max()), 1)
+    _announce(f"overlap small n={n} periodic={periodic} max_ngb={max_ngb} "
+              f"max h={ref['h_all'].max():.3f}")
+    g, ctx, ds, out = _run(w, max_ngb)
+    ctx.close()
+    assert g["stats"]["error"] == 0
+    assert np.array_equal(g["h_all"], ref["h_all"])
+    assert np.array_equal(g["count"], ref["count"])
+    gr, rr = _sorted_rows(g["ngb"], g["count"]), _sorted_rows(ref["ngb"], ref["count"])
+    for a in range(len(gr)):
+        assert np.array_equal(gr[a], rr[a]), f"row {a} differs"
+    vs = max(np.abs(ref[f]).max() for f in ("vx", "vy", "vz"))
+    for f in ("vx", "vy", "vz"):
+        assert np.abs(g[f] - ref[f]).max() <= 1e-12 * vs, f
+    assert g["stats"]["n_events"] == ref["stats"]["n_events"]
+
+
+def test_empty_active_set():
+    import torch
+    from paper_2607_05504_amd import runner
+    w = W.uniform_box(2000, ic_seed=88)
+    _announce("overlap with no active particle")
+    ds = runner.upload(w, "cuda")
+    ctx = _ctx(w)
+    out = runner.alloc_overlap(ds, w.n_ngb, 64)
+    ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state, m_scalar=ds.mass)
+    ctx.find_ngb(out.everyone, out.ngb_all, out.h_all)
+    v0 = ds.vx.clone()
+    none = ds.active[:0]
+    ctx.find_overlap(out.h_all, none, out.ngb[:0], out.count[:0])
+    ctx.scatter_overlap(out.h_all, none, out.ngb[:0], out.count[:0], ds.dt[:0], w.seed, w.step)
+    ctx.pair_timestep_overlap(out.h_all, none, out.ngb[:0], out.count[:0], out.dt_sidm[:0])
+    st = ctx.sync()
+    assert st["error"] == 0 and st["n_events"] == 0 and st["n_cand"] == 0
+    assert torch.equal(ds.vx, v0)
+    ctx.close()
