@@ -146,10 +146,8 @@ __device__ __forceinline__ double window_bound(const KnnArgs &A, int64_t i, doub
 }
 
 // ---------------------------------------------------------------------------
-// Kernel A: radius bound and per-target leaf list (one lane per target)
+// Kernel A: radius bound and per-target leaf list (a lane team per target)
 // ---------------------------------------------------------------------------
-constexpr int kStackA = SIDM_MAX_LEVELS * (SIDM_TREE_FAN - 1) + 1;
-
 constexpr int kFront = 512;               // frontier capacity of the level walk
 constexpr int kLeafHits = 960;            // leaves a wavefront tests before its targets walk alone
 
