@@ -31,6 +31,13 @@
  *     entry, an overflowing accepted list) are latched in the context and
  *     returned by sidm_sync (and by the next call that checks them).
  *   - Indices in `active` and `ngb` are in the caller's particle order.
+ *   - Every call that takes `active` first maps the active set into the
+ *     tree's order.  Given active == NULL (and n_active > 0) a call reuses the
+ *     mapping of the previous call on the context instead, which must have
+ *     had the same n_active, with no sidm_build_tree, sidm_refit_tree or
+ *     sidm_reconfigure since (SIDM_E_STATE otherwise): for example
+ *     sidm_scatter_step and sidm_pair_timestep after sidm_find_ngb of the
+ *     same step.
  *   - A context is not thread-safe.  Distinct contexts are independent and
  *     may run concurrently on different streams.
  *

@@ -168,6 +168,12 @@ def footprint(cfg: Config, cap_n: int, cap_active: int) -> int:
     return int(out.value)
 
 
+def _act(active, reuse: bool):
+    """The active list's pointer, or NULL to reuse the mapping of the previous
+    call on the context (its length still gives n_active)."""
+    return None if reuse else _ptr(active)
+
+
 def _ptr(t) -> Optional[int]:
     if t is None:
         return None
@@ -257,7 +263,8 @@ class Context:
         self._check(lib().sidm_find_ngb(self._h, _ptr(active), int(active.shape[0]), _ptr(ngb),
                                         _ptr(h)), "sidm_find_ngb")
 
-    def scatter_step(self, active, ngb, h, dt, seed: int, step: int, cand_info=None):
+    def scatter_step(self, active, ngb, h, dt, seed: int, step: int, cand_info=None,
+                     reuse_active: bool = False):
         torch = self._torch
         if self._particles is None:
             raise SidmError(SIDM_E_STATE, "scatter_step before build_tree")
@@ -267,23 +274,23 @@ class Context:
         self._dev(dt, torch.float64, "dt")
         self._dev(cand_info, torch.int32, "cand_info")
         p = self._particles[0]
-        self._check(lib().sidm_scatter_step(self._h, ctypes.byref(p), _ptr(active),
+        self._check(lib().sidm_scatter_step(self._h, ctypes.byref(p), _act(active, reuse_active),
                                             int(active.shape[0]), _ptr(ngb), _ptr(h), _ptr(dt),
                                             int(seed) & (2**64 - 1), int(step) & (2**32 - 1),
                                             _ptr(cand_info)), "sidm_scatter_step")
 
-    def pair_timestep(self, active, ngb, h, dt_sidm):
+    def pair_timestep(self, active, ngb, h, dt_sidm, reuse_active: bool = False):
         torch = self._torch
         self._dev(active, torch.int32, "active")
         self._dev(ngb, torch.int32, "ngb")
         self._dev(h, torch.float64, "h")
         self._dev(dt_sidm, torch.float64, "dt_sidm")
-        self._check(lib().sidm_pair_timestep(self._h, _ptr(active), int(active.shape[0]),
+        self._check(lib().sidm_pair_timestep(self._h, _act(active, reuse_active), int(active.shape[0]),
                                              _ptr(ngb), _ptr(h), _ptr(dt_sidm)),
                     "sidm_pair_timestep")
 
     # --- kernel-overlap estimator -------------------------------------------
-    def find_overlap(self, h_all, active, ngb, count, h_active=None):
+    def find_overlap(self, h_all, active, ngb, count, h_active=None, reuse_active: bool = False):
         """Partners with r_ij < h_i + h_j: ngb int32[n_active, max_ngb] (rows in
         tree order), count int32[n_active] (full counts).  h_active (optional)
         is first written into h_all at the active particles."""
@@ -293,12 +300,13 @@ class Context:
         self._dev(active, torch.int32, "active")
         self._dev(ngb, torch.int32, "ngb")
         self._dev(count, torch.int32, "count")
-        self._check(lib().sidm_find_overlap(self._h, _ptr(h_all), _ptr(active), _ptr(h_active),
+        self._check(lib().sidm_find_overlap(self._h, _ptr(h_all), _act(active, reuse_active),
+                                            _ptr(h_active),
                                             int(active.shape[0]), int(ngb.shape[1]), _ptr(ngb),
                                             _ptr(count)), "sidm_find_overlap")
 
     def scatter_overlap(self, h_all, active, ngb, count, dt, seed: int, step: int,
-                        cand_info=None):
+                        cand_info=None, reuse_active: bool = False):
         torch = self._torch
         if self._particles is None:
             raise SidmError(SIDM_E_STATE, "scatter_overlap before build_tree")
@@ -308,19 +316,21 @@ class Context:
             self._dev(t, dtp, nm)
         p = self._particles[0]
         self._check(lib().sidm_scatter_overlap(self._h, ctypes.byref(p), _ptr(h_all),
-                                               _ptr(active), int(active.shape[0]),
+                                               _act(active, reuse_active), int(active.shape[0]),
                                                int(ngb.shape[1]), _ptr(ngb), _ptr(count),
                                                _ptr(dt), int(seed) & (2**64 - 1),
                                                int(step) & (2**32 - 1), _ptr(cand_info)),
                     "sidm_scatter_overlap")
 
-    def pair_timestep_overlap(self, h_all, active, ngb, count, dt_sidm):
+    def pair_timestep_overlap(self, h_all, active, ngb, count, dt_sidm,
+                              reuse_active: bool = False):
         torch = self._torch
         for t, dtp, nm in ((h_all, torch.float64, "h_all"), (active, torch.int32, "active"),
                            (ngb, torch.int32, "ngb"), (count, torch.int32, "count"),
                            (dt_sidm, torch.float64, "dt_sidm")):
             self._dev(t, dtp, nm)
-        self._check(lib().sidm_pair_timestep_overlap(self._h, _ptr(h_all), _ptr(active),
+        self._check(lib().sidm_pair_timestep_overlap(self._h, _ptr(h_all),
+                                                     _act(active, reuse_active),
                                                      int(active.shape[0]), int(ngb.shape[1]),
                                                      _ptr(ngb), _ptr(count), _ptr(dt_sidm)),
                     "sidm_pair_timestep_overlap")

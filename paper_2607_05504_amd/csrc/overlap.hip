@@ -126,18 +126,19 @@ __global__ __launch_bounds__(kBlock) void k_overlap_table(double *tab)
     tab[t] = a == 0 ? cubic_spline(rho, 1.0) : overlap_exact(al, 1.0 - al, rho);
 }
 
-// the active particles' new smoothing lengths into every particle's h
-__global__ __launch_bounds__(kBlock) void k_update_h(const int32_t *__restrict__ active,
+// the active particles' new smoothing lengths into every particle's h, through
+// the active set's mapping (target b: Morton index tlist[b], slot slot[b])
+__global__ __launch_bounds__(kBlock) void k_update_h(const int32_t *__restrict__ tlist,
+                                                     const int32_t *__restrict__ slot,
+                                                     const int32_t *__restrict__ nt_dev,
+                                                     const int32_t *__restrict__ perm,
                                                      const double *__restrict__ h_active,
-                                                     int64_t n_active, int64_t n, double *h_all,
-                                                     unsigned int *derr)
+                                                     double *h_all)
 {
-    for (int64_t a = blockIdx.x * (int64_t)kBlock + threadIdx.x; a < n_active;
-         a += (int64_t)gridDim.x * kBlock) {
-        const int32_t i = active[a];
-        if (i < 0 || i >= n) { atomicOr(derr, DERR_INDEX); continue; }
-        h_all[i] = h_active[a];
-    }
+    const int64_t nt = *nt_dev;
+    for (int64_t b = blockIdx.x * (int64_t)kBlock + threadIdx.x; b < nt;
+         b += (int64_t)gridDim.x * kBlock)
+        h_all[perm[tlist[b]]] = h_active[slot[b]];
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather_h(int64_t n, const int32_t *__restrict__ perm,
@@ -284,17 +285,16 @@ hipError_t launch_overlap_table(sidm_ctx *c)
     return hipGetLastError();
 }
 
-hipError_t launch_find_overlap(sidm_ctx *c, double *h_all, const int32_t *active,
-                               const double *h_active, int64_t n_active, int32_t max_ngb,
-                               int32_t *ngb, int32_t *count)
+hipError_t launch_find_overlap(sidm_ctx *c, double *h_all, const double *h_active,
+                               int64_t n_active, int32_t max_ngb, int32_t *ngb, int32_t *count)
 {
     hipStream_t s = c->stream;
     const int64_t n = c->n;
     const TreeLevels &lv = c->lv;
     phase_begin(c, PH_OVERLAP);
     if (h_active)
-        k_update_h<<<grid_for(n_active), kBlock, 0, s>>>(active, h_active, n_active, n, h_all,
-                                                         c->derr);
+        k_update_h<<<grid_for(n_active), kBlock, 0, s>>>(c->tlist, c->slot, c->nt_dev, c->perm,
+                                                         h_active, h_all);
     k_gather_h<<<grid_for(n), kBlock, 0, s>>>(n, c->perm, h_all, c->hs, c->derr);
     const int64_t nleaf = lv.cnt[0];
     k_leaf_hmax<<<(unsigned)((nleaf * 32 + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, nleaf, c->hs,

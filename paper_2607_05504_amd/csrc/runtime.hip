@@ -329,6 +329,7 @@ sidm_status sidm_reconfigure(sidm_ctx *c, const sidm_config *cfg)
     }
     c->cfg = *cfg;
     c->tree_ok = 0;          // a new configuration needs a new snapshot
+    c->map_valid = 0;
     hipError_t e = copy_table(c);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "reconfigure");
@@ -381,6 +382,7 @@ sidm_status sidm_refit_tree(sidm_ctx *c, const sidm_particles *p)
     phase_begin(c, PH_TREE);
     hipError_t e = launch_refit_tree(c, p);
     phase_end(c, PH_TREE);
+    c->map_valid = 0;
     if (e != hipSuccess) return hip_fail(c, e, "refit_tree");
     c->tree_ok = 1;
     return SIDM_OK;
@@ -397,6 +399,7 @@ sidm_status sidm_build_tree(sidm_ctx *c, const sidm_particles *p)
     phase_begin(c, PH_TREE);
     hipError_t e = launch_build_tree(c, p);
     phase_end(c, PH_TREE);
+    c->map_valid = 0;
     if (e != hipSuccess) return hip_fail(c, e, "build_tree");
     c->tree_ok = 1;
     c->sorted_n = p->n;
@@ -409,9 +412,14 @@ static sidm_status check_active(sidm_ctx *c, const int32_t *active, int64_t n_ac
         set_err(c, "%s: sidm_build_tree has not been called", who);
         return SIDM_E_STATE;
     }
-    if (n_active < 0 || (n_active > 0 && !active)) {
+    if (n_active < 0) {
         set_err(c, "%s: bad active list", who);
         return SIDM_E_INVAL;
+    }
+    if (n_active > 0 && !active && !(c->map_valid && c->map_n == n_active)) {
+        set_err(c, "%s: active == NULL needs an active set of %lld mapped by an earlier call "
+                   "since the last tree build", who, (long long)n_active);
+        return SIDM_E_STATE;
     }
     if (n_active > c->n) {
         set_err(c, "%s: n_active=%lld > n=%lld", who, (long long)n_active, (long long)c->n);
@@ -425,6 +433,21 @@ static sidm_status check_active(sidm_ctx *c, const int32_t *active, int64_t n_ac
     return SIDM_OK;
 }
 
+// The active set in the tree's order: mapped from `active`, or (active ==
+// NULL, checked by check_active) the mapping of the previous call reused.
+// An empty set is always mapped, so the device-side target count is 0.
+static hipError_t map_active(sidm_ctx *c, const int32_t *active, int64_t n_active)
+{
+    if (!active && n_active > 0) return hipSuccess;
+    c->map_valid = 0;
+    hipError_t e = launch_map_active(c, active, n_active);
+    if (e == hipSuccess) {
+        c->map_valid = 1;
+        c->map_n = n_active;
+    }
+    return e;
+}
+
 sidm_status sidm_find_ngb(sidm_ctx *c, const int32_t *active, int64_t n_active, int32_t *ngb, double *h)
 {
     if (!c) return SIDM_E_INVAL;
@@ -435,7 +458,7 @@ sidm_status sidm_find_ngb(sidm_ctx *c, const int32_t *active, int64_t n_active, 
         return SIDM_E_INVAL;
     }
     if (n_active == 0) return SIDM_OK;
-    hipError_t e = launch_map_active(c, active, n_active);
+    hipError_t e = map_active(c, active, n_active);
     if (e == hipSuccess) e = launch_knn(c, n_active, ngb, h);
     if (e != hipSuccess) return hip_fail(c, e, "find_ngb");
     return SIDM_OK;
@@ -460,7 +483,7 @@ sidm_status sidm_scatter_step(sidm_ctx *c, sidm_particles *p, const int32_t *act
         set_err(c, "scatter_step: NULL ngb/h/dt");
         return SIDM_E_INVAL;
     }
-    hipError_t e = launch_map_active(c, active, n_active);
+    hipError_t e = map_active(c, active, n_active);
     if (e == hipSuccess) e = launch_scatter(c, p, n_active, ngb, h, dt, seed, step, cand_info);
     if (e != hipSuccess) return hip_fail(c, e, "scatter_step");
     return SIDM_OK;
@@ -477,7 +500,7 @@ sidm_status sidm_pair_timestep(sidm_ctx *c, const int32_t *active, int64_t n_act
         return SIDM_E_INVAL;
     }
     if (n_active == 0) return SIDM_OK;
-    hipError_t e = launch_map_active(c, active, n_active);
+    hipError_t e = map_active(c, active, n_active);
     if (e == hipSuccess) e = launch_timestep(c, n_active, ngb, h, dt_sidm);
     if (e != hipSuccess) return hip_fail(c, e, "pair_timestep");
     return SIDM_OK;
@@ -517,9 +540,9 @@ sidm_status sidm_find_overlap(sidm_ctx *c, double *h_all, const int32_t *active,
     sidm_status st = check_overlap(c, h_all, active, n_active, max_ngb, ngb, count, "find_overlap");
     if (st != SIDM_OK) return st;
     if (n_active == 0) return SIDM_OK;
-    hipError_t e = launch_map_active(c, active, n_active);
+    hipError_t e = map_active(c, active, n_active);
     if (e == hipSuccess)
-        e = launch_find_overlap(c, h_all, active, h_active, n_active, max_ngb, ngb, count);
+        e = launch_find_overlap(c, h_all, h_active, n_active, max_ngb, ngb, count);
     if (e != hipSuccess) return hip_fail(c, e, "find_overlap");
     return SIDM_OK;
 }
@@ -545,7 +568,7 @@ sidm_status sidm_scatter_overlap(sidm_ctx *c, sidm_particles *p, const double *h
         set_err(c, "scatter_overlap: NULL dt");
         return SIDM_E_INVAL;
     }
-    hipError_t e = launch_map_active(c, active, n_active);
+    hipError_t e = map_active(c, active, n_active);
     if (e == hipSuccess)
         e = launch_scatter_overlap(c, p, n_active, h_all, max_ngb, ngb, count, dt, seed, step,
                                    cand_info);
@@ -566,7 +589,7 @@ sidm_status sidm_pair_timestep_overlap(sidm_ctx *c, const double *h_all, const i
         return SIDM_E_INVAL;
     }
     if (n_active == 0) return SIDM_OK;
-    hipError_t e = launch_map_active(c, active, n_active);
+    hipError_t e = map_active(c, active, n_active);
     if (e == hipSuccess) e = launch_timestep_overlap(c, n_active, h_all, max_ngb, ngb, count, dt_sidm);
     if (e != hipSuccess) return hip_fail(c, e, "pair_timestep_overlap");
     return SIDM_OK;

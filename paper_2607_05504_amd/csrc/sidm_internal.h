@@ -124,6 +124,8 @@ struct sidm_ctx {
     int32_t *slot;           // [cap_active] its position in the caller's active list
     int32_t *blk;            // compaction block counts / offsets
     int32_t *nt_dev;         // number of compacted targets
+    int map_valid;           // the arrays above hold the mapping of map_n targets
+    int64_t map_n;           //   made since the last tree build (reusable: active == NULL)
 
     // conflict resolution
     AccList acc[2];
@@ -412,9 +414,8 @@ hipError_t launch_timestep_overlap(sidm_ctx *c, int64_t n_active, const double *
                                    double *dt_out);
 // overlap.hip
 hipError_t launch_overlap_table(sidm_ctx *c);
-hipError_t launch_find_overlap(sidm_ctx *c, double *h_all, const int32_t *active,
-                               const double *h_active, int64_t n_active, int32_t max_ngb,
-                               int32_t *ngb, int32_t *count);
+hipError_t launch_find_overlap(sidm_ctx *c, double *h_all, const double *h_active,
+                               int64_t n_active, int32_t max_ngb, int32_t *ngb, int32_t *count);
 // advance.hip
 hipError_t launch_advance(sidm_ctx *c, double *x, double *y, double *z, double *vx, double *vy,
                           double *vz, int64_t n, const double *dt_sidm, int64_t n_active,

@@ -87,8 +87,10 @@ def run_step(ctx: Context, ds: DeviceState, out: StepOut, seed: int, step: int,
     tree = ctx.refit_tree if refit else ctx.build_tree
     tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state, m_scalar=ds.mass)
     ctx.find_ngb(ds.active, out.ngb, out.h)
-    ctx.scatter_step(ds.active, out.ngb, out.h, ds.dt, seed, step, cand_info=out.cand_info)
-    ctx.pair_timestep(ds.active, out.ngb, out.h, out.dt_sidm)
+    # the later calls reuse find_ngb's mapping of the active set
+    ctx.scatter_step(ds.active, out.ngb, out.h, ds.dt, seed, step, cand_info=out.cand_info,
+                     reuse_active=True)
+    ctx.pair_timestep(ds.active, out.ngb, out.h, out.dt_sidm, reuse_active=True)
 
 
 @dataclasses.dataclass
@@ -136,7 +138,9 @@ def run_overlap_step(ctx: Context, ds: DeviceState, out: OverlapOut, seed: int, 
         ctx.find_overlap(out.h_all, ds.active, out.ngb, out.count)
     else:
         ctx.find_ngb(ds.active, out.ngb_k, out.h_k)
-        ctx.find_overlap(out.h_all, ds.active, out.ngb, out.count, h_active=out.h_k)
+        ctx.find_overlap(out.h_all, ds.active, out.ngb, out.count, h_active=out.h_k,
+                         reuse_active=True)
     ctx.scatter_overlap(out.h_all, ds.active, out.ngb, out.count, ds.dt, seed, step,
-                        cand_info=out.cand_info)
-    ctx.pair_timestep_overlap(out.h_all, ds.active, out.ngb, out.count, out.dt_sidm)
+                        cand_info=out.cand_info, reuse_active=True)
+    ctx.pair_timestep_overlap(out.h_all, ds.active, out.ngb, out.count, out.dt_sidm,
+                              reuse_active=True)

@@ -129,3 +129,41 @@ def test_empty_active_set_changes_nothing():
     assert st["error"] == 0 and st["n_events"] == 0
     assert torch.equal(ds.vx, v0)
     ctx.close()
+
+
+def test_active_mapping_reuse_rules():
+    """active == NULL reuses the previous call's mapping of the active set:
+    refused (nothing enqueued) right after a tree build or with another
+    n_active; after find_ngb it gives the results of an explicit list."""
+    import torch
+    from paper_2607_05504_amd import SIDM_E_STATE, SidmError
+    _announce("active-set mapping reuse")
+    w, ds, ctx, out = _setup(n_active=1500)
+    with pytest.raises(SidmError) as e:            # nothing mapped since the tree build
+        ctx.scatter_step(ds.active, out.ngb, out.h, ds.dt, w.seed, w.step, reuse_active=True)
+    assert e.value.status == SIDM_E_STATE
+    ctx.find_ngb(ds.active, out.ngb, out.h)
+    with pytest.raises(SidmError) as e:            # another n_active
+        ctx.pair_timestep(ds.active[:100], out.ngb[:100], out.h[:100], out.dt_sidm[:100],
+                          reuse_active=True)
+    assert e.value.status == SIDM_E_STATE
+    v0 = [t.clone() for t in (ds.vx, ds.vy, ds.vz)]
+    ctx.scatter_step(ds.active, out.ngb, out.h, ds.dt, w.seed, w.step, reuse_active=True)
+    ctx.pair_timestep(ds.active, out.ngb, out.h, out.dt_sidm, reuse_active=True)
+    st = ctx.sync()
+    got = [t.clone() for t in (ds.vx, ds.vy, ds.vz)] + [out.dt_sidm.clone()]
+    # the same step with explicit lists on the step-start velocities
+    for t, t0 in zip((ds.vx, ds.vy, ds.vz), v0):
+        t.copy_(t0)
+    ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state, m_scalar=ds.mass)
+    with pytest.raises(SidmError) as e:            # the new tree dropped the mapping
+        ctx.pair_timestep(ds.active, out.ngb, out.h, out.dt_sidm, reuse_active=True)
+    assert e.value.status == SIDM_E_STATE
+    ctx.find_ngb(ds.active, out.ngb, out.h)
+    ctx.scatter_step(ds.active, out.ngb, out.h, ds.dt, w.seed, w.step)
+    ctx.pair_timestep(ds.active, out.ngb, out.h, out.dt_sidm)
+    st2 = ctx.sync()
+    for a, b in zip(got, (ds.vx, ds.vy, ds.vz, out.dt_sidm)):
+        assert torch.equal(a, b)
+    assert st["n_events"] == st2["n_events"] > 0
+    ctx.close()
