@@ -83,11 +83,20 @@ __device__ __forceinline__ uint64_t quant16(double v, double lo, double scale)
     return (uint64_t)q;
 }
 
-__global__ void k_morton(const double *__restrict__ x, const double *__restrict__ y,
-                         const double *__restrict__ z, int64_t n, int periodic, double box,
-                         const unsigned long long *__restrict__ bounds, uint64_t *key,
-                         int32_t *val)
+// Keys of one sort tile per workgroup, with the digit counts the sort needs:
+// the totals of every 8-bit digit of every pass into dtot[pass * 256 + digit]
+// (they do not depend on the keys' order; dtot must start at zero), and this
+// tile's counts of the first pass's digits into hist[digit * nblk + tile].
+__global__ __launch_bounds__(256) void k_morton(const double *__restrict__ x,
+                                                const double *__restrict__ y,
+                                                const double *__restrict__ z, int64_t n,
+                                                int periodic, double box,
+                                                const unsigned long long *__restrict__ bounds,
+                                                uint64_t *key, int32_t *val, uint32_t *dtot,
+                                                uint32_t *hist, int nblk)
 {
+    __shared__ uint32_t cnt[6 * 256];
+    for (int q = threadIdx.x; q < 6 * 256; q += 256) cnt[q] = 0;
     double lo[3], scale[3];
     for (int d = 0; d < 3; ++d) {
         double l = periodic ? 0.0 : from_ordered_u64(bounds[d]);
@@ -96,14 +105,24 @@ __global__ void k_morton(const double *__restrict__ x, const double *__restrict_
         lo[d] = l;
         scale[d] = ext > 0.0 ? 65536.0 / ext : 0.0;
     }
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x) {
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * SIDM_SORT_TILE;
+    for (int r = 0; r < SIDM_SORT_TILE / 256; ++r) {
+        const int64_t t = base + r * 256 + threadIdx.x;
+        if (t >= n) break;
         uint64_t a = quant16(x[t], lo[0], scale[0]);
         uint64_t b = quant16(y[t], lo[1], scale[1]);
         uint64_t c = quant16(z[t], lo[2], scale[2]);
-        key[t] = (spread16(a) << 2) | (spread16(b) << 1) | spread16(c);
+        const uint64_t k = (spread16(a) << 2) | (spread16(b) << 1) | spread16(c);
+        key[t] = k;
         val[t] = (int32_t)t;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) atomicAdd(&cnt[p * 256 + ((k >> (8 * p)) & 255u)], 1u);
     }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+    for (int q = threadIdx.x; q < 6 * 256; q += 256)
+        if (cnt[q]) atomicAdd(&dtot[q], cnt[q]);
 }
 
 // --- LSD radix sort, 8-bit digits ------------------------------------------------
@@ -120,24 +139,6 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t *__restrict__
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
-}
-
-// Totals of every 8-bit digit of every pass at once (they do not depend on
-// the order the keys are in): dtot[pass * 256 + digit].
-__global__ __launch_bounds__(256) void k_digit_totals(const uint64_t *__restrict__ key, int64_t n,
-                                                      uint32_t *dtot)
-{
-    __shared__ uint32_t cnt[6 * 256];
-    for (int q = threadIdx.x; q < 6 * 256; q += 256) cnt[q] = 0;
-    __syncthreads();
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) {
-        const uint64_t k = key[t];
-#pragma unroll
-        for (int p = 0; p < 6; ++p) atomicAdd(&cnt[p * 256 + ((k >> (8 * p)) & 255u)], 1u);
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < 6 * 256; q += 256)
-        if (cnt[q]) atomicAdd(&dtot[q], cnt[q]);
 }
 
 // one workgroup per digit: exclusive scan over blocks plus the digit's base
@@ -286,12 +287,16 @@ __global__ void k_scatter_snapshot(int64_t n, const int32_t *__restrict__ inv,
 
 // --- bucket tree boxes --------------------------------------------------------------
 // Two leaves per wavefront: lane l holds particle (leaf*32 + l%32); min/max by
-// butterfly shuffles within each half-wave.
+// butterfly shuffles within each half-wave.  A workgroup's 8 leaves are the
+// children of one level-1 node, whose box it writes too (at nodes[off1 + b]).
 __global__ __launch_bounds__(256) void k_leaf_boxes(int64_t n, int64_t nleaf,
                                                     const double *__restrict__ xs,
                                                     const double *__restrict__ ys,
-                                                    const double *__restrict__ zs, double *nodes)
+                                                    const double *__restrict__ zs, double *nodes,
+                                                    int64_t off1, int64_t cnt1)
 {
+    static_assert(SIDM_TREE_FAN * SIDM_LEAF == 256, "a workgroup covers one level-1 node");
+    __shared__ double s_box[SIDM_TREE_FAN][6];
     const int64_t leaf = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
     const int sub = threadIdx.x & 31;
     const int64_t s = leaf * SIDM_LEAF + sub;
@@ -311,7 +316,40 @@ __global__ __launch_bounds__(256) void k_leaf_boxes(int64_t n, int64_t nleaf,
             v[3 + d] = fmax(v[3 + d], __shfl_xor(v[3 + d], off));
         }
     }
-    if (sub < 6 && leaf < nleaf) nodes[leaf * 6 + sub] = v[sub];
+    if (sub < 6) {
+        if (leaf < nleaf) nodes[leaf * 6 + sub] = v[sub];
+        s_box[threadIdx.x >> 5][sub] = v[sub];     // an empty box past the last leaf
+    }
+    __syncthreads();
+    if (threadIdx.x < 6 && (int64_t)blockIdx.x < cnt1) {
+        const int d = threadIdx.x;
+        double r = s_box[0][d];
+        for (int c = 1; c < SIDM_TREE_FAN; ++c) r = d < 3 ? fmin(r, s_box[c][d]) : fmax(r, s_box[c][d]);
+        nodes[(off1 + blockIdx.x) * 6 + d] = r;
+    }
+}
+
+// The small upper levels in one workgroup, level after level from `from`.
+__global__ __launch_bounds__(1024) void k_top_levels(double *nodes, TreeLevels lv, int from)
+{
+    for (int l = from; l < lv.nlev; ++l) {
+        const int64_t off_child = lv.off[l - 1], cnt_child = lv.cnt[l - 1];
+        for (int64_t q = threadIdx.x; q < lv.cnt[l]; q += 1024) {
+            double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+            for (int c = 0; c < SIDM_TREE_FAN; ++c) {
+                const int64_t ch = q * SIDM_TREE_FAN + c;
+                if (ch >= cnt_child) break;
+                const double *b = nodes + (off_child + ch) * 6;
+                for (int d = 0; d < 3; ++d) {
+                    v[d] = fmin(v[d], b[d]);
+                    v[3 + d] = fmax(v[3 + d], b[3 + d]);
+                }
+            }
+            for (int d = 0; d < 6; ++d) nodes[(lv.off[l] + q) * 6 + d] = v[d];
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
 }
 
 // Boxes of level l from the boxes of level l-1 (one thread per node).
@@ -462,15 +500,14 @@ hipError_t launch_build_tree(sidm_ctx *c, const sidm_particles *p)
         launch_fill_u64(c->bounds + 3, 0ull, 3, s);
         k_bounds<<<grid_for(n, kBlock, 256), kBlock, 0, s>>>(p->x, p->y, p->z, n, c->bounds);
     }
-    k_morton<<<grid_for(n), kBlock, 0, s>>>(p->x, p->y, p->z, n, cfg.periodic, cfg.box,
-                                             c->bounds, c->key0, c->val0);
     const int nblk = (int)((n + SIDM_SORT_TILE - 1) / SIDM_SORT_TILE);
+    launch_fill_i32((int32_t *)c->dtot, 0, 6 * 256, s);
+    k_morton<<<nblk, 256, 0, s>>>(p->x, p->y, p->z, n, cfg.periodic, cfg.box, c->bounds, c->key0,
+                                  c->val0, c->dtot, c->hist, nblk);
     uint64_t *kin = c->key0, *kout = c->key1;
     int32_t *vin = c->val0, *vout = c->val1;
-    launch_fill_i32((int32_t *)c->dtot, 0, 6 * 256, s);
-    k_digit_totals<<<grid_for(n, 256, 1024), 256, 0, s>>>(kin, n, c->dtot);
     for (int shift = 0; shift < 48; shift += 8) {
-        k_radix_hist<<<nblk, 256, 0, s>>>(kin, n, shift, c->hist, nblk);
+        if (shift > 0) k_radix_hist<<<nblk, 256, 0, s>>>(kin, n, shift, c->hist, nblk);
         k_radix_scan<<<256, 256, 0, s>>>(c->hist, c->dtot + (shift / 8) * 256, nblk);
         k_radix_scatter<<<nblk, 256, 0, s>>>(kin, vin, kout, vout, n, shift, c->hist, nblk);
         uint64_t *tk = kin; kin = kout; kout = tk;
@@ -505,11 +542,15 @@ hipError_t launch_refit_tree(sidm_ctx *c, const sidm_particles *p)
     c->lv = tree_levels(n);
     const TreeLevels &lv = c->lv;
     const int64_t nleaf = lv.cnt[0];
+    // leaves and level 1 together, then the big levels one launch each, then
+    // the small ones in a single workgroup
     k_leaf_boxes<<<(unsigned)((nleaf * 32 + 255) / 256), 256, 0, s>>>(n, nleaf, c->xs, c->ys, c->zs,
-                                                                     c->nodes);
-    for (int l = 1; l < lv.nlev; ++l)
+                                                                     c->nodes, lv.off[1], lv.cnt[1]);
+    int l = 2;
+    for (; l < lv.nlev && lv.cnt[l] > 8192; ++l)
         k_level_boxes<<<(unsigned)((lv.cnt[l] + 255) / 256), 256, 0, s>>>(
             c->nodes, lv.off[l - 1], lv.cnt[l - 1], lv.off[l], lv.cnt[l]);
+    if (l < lv.nlev) k_top_levels<<<1, 1024, 0, s>>>(c->nodes, lv, l);
     if (cfg.precision == SIDM_MIXED)
         k_leaf_offsets<<<grid_for(n), kBlock, 0, s>>>(n, c->xs, c->ys, c->zs, c->nodes, c->xo,
                                                       c->yo, c->zo);
