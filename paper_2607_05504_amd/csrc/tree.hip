@@ -185,7 +185,11 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *hist, const uint32
     }
 }
 
-// Stable scatter: items are ranked in tile order (round-major, then wave, then lane).
+// Stable scatter: items are ranked in tile order (round-major, then wave,
+// then lane) within their digit.  The tile is first reordered by digit in LDS
+// and then written out, so a digit's items go to consecutive addresses.
+constexpr int kRounds = SIDM_SORT_TILE / 256;
+
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restrict__ kin,
                                                        const int32_t *__restrict__ vin,
                                                        uint64_t *kout, int32_t *vout, int64_t n,
@@ -194,37 +198,73 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restric
     __shared__ uint32_t goff[256];
     __shared__ uint32_t run[256];
     __shared__ uint32_t wc[4][256];
+    __shared__ uint64_t s_key[SIDM_SORT_TILE];
+    __shared__ int32_t s_val[SIDM_SORT_TILE];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     goff[t] = hist[(int64_t)t * nblk + blockIdx.x];
     run[t] = 0;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int64_t base = (int64_t)blockIdx.x * SIDM_SORT_TILE;
-    for (int r = 0; r < SIDM_SORT_TILE / 256; ++r) {
-        int64_t idx = base + r * 256 + t;
-        bool valid = idx < n;
-        uint64_t k = valid ? kin[idx] : 0;
-        int32_t v = valid ? vin[idx] : 0;
-        uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const int64_t base = (int64_t)blockIdx.x * SIDM_SORT_TILE;
+    uint64_t kk[kRounds];
+    int32_t vv[kRounds];
+    uint32_t rk[kRounds];                      // rank within the digit in the tile
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t idx = base + r * 256 + t;
+        const bool valid = idx < n;
+        const uint64_t k = valid ? kin[idx] : 0;
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        kk[r] = k;
+        vv[r] = valid ? vin[idx] : 0;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            uint64_t m = __ballot((d >> b) & 1u);
+            const uint64_t m = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
-        uint32_t wrank = __popcll(peers & lt_mask);
+        const uint32_t wrank = __popcll(peers & lt_mask);
         for (int q = 0; q < 4; ++q) wc[q][t] = 0;
         __syncthreads();
         if (valid && wrank == 0) wc[w][d] = __popcll(peers);
         __syncthreads();
-        if (valid) {
-            uint32_t pos = goff[d] + run[d] + wrank;
-            for (int q = 0; q < w; ++q) pos += wc[q][d];
-            kout[pos] = k;
-            vout[pos] = v;
-        }
+        uint32_t pos = run[d] + wrank;
+        for (int q = 0; q < w; ++q) pos += wc[q][d];
+        rk[r] = valid ? pos : 0xffffffffu;
         __syncthreads();
         run[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
         __syncthreads();
+    }
+    // run[d] now counts the tile's items of digit d: exclusive prefix = where
+    // digit d starts in the tile (Hillis-Steele in wc[0], wc[1])
+    uint32_t *sa = wc[0], *sb = wc[1];
+    sa[t] = run[t];
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        sb[t] = sa[t] + (t >= off ? sa[t - off] : 0u);
+        __syncthreads();
+        uint32_t *tmp = sa; sa = sb; sb = tmp;
+    }
+    const uint32_t start_t = sa[t] - run[t];   // exclusive prefix of digit t
+    __syncthreads();
+    wc[2][t] = start_t;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        if (rk[r] != 0xffffffffu) {
+            const uint32_t d = (uint32_t)(kk[r] >> shift) & 255u;
+            const uint32_t lp = wc[2][d] + rk[r];
+            s_key[lp] = kk[r];
+            s_val[lp] = vv[r];
+        }
+    }
+    __syncthreads();
+    const int64_t cnt = n - base < SIDM_SORT_TILE ? n - base : SIDM_SORT_TILE;
+    for (int i = t; i < cnt; i += 256) {
+        const uint64_t k = s_key[i];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t pos = goff[d] + (uint32_t)i - wc[2][d];
+        kout[pos] = k;
+        vout[pos] = s_val[i];
     }
 }
 
