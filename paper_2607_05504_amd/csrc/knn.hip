@@ -415,8 +415,14 @@ __device__ __forceinline__ int32_t walk_next(const KnnArgs &A, int32_t *stk, int
     return -1;
 }
 
+// false: a step's leaves are tested as soon as their positions arrive, with no
+// leaf of the next step in flight.  Requesting the next leaf ahead held more
+// registers than the latency it hid was worth (measured slower at 10^6 and
+// 256^3: the occupancy hides the latency instead)
+constexpr bool kPrefetchLeaf = false;
+
 template <bool PERIODIC, int E, bool MIXED, int TS, int LPI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MIXED ? 3 : 4)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
 {
     constexpr int N = TS * E;                 // list capacity
@@ -527,6 +533,20 @@ void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
                         for (int d = 0; d < 6; ++d) nb6[u][d] = nb[d];
                     }
                 }
+            }
+        }
+        if constexpr (!kPrefetchLeaf) {
+            // the picked leaves are tested in this step (their loads waited on)
+#pragma unroll
+            for (int u = 0; u < LPI; ++u) {
+                cur[u] = nxt[u];
+#pragma unroll
+                for (int d = 0; d < 6; ++d) cb[u][d] = nb6[u][d];
+            }
+#pragma unroll
+            for (int q = 0; q < PS; ++q) {
+                cx[q] = nx[q]; cy[q] = ny[q]; cz[q] = nz[q];
+                fx[q] = gx[q]; fy[q] = gy[q]; fz[q] = gz[q];
             }
         }
 #pragma unroll
@@ -741,7 +761,7 @@ void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
 
 constexpr int kTeam = 16;                 // lanes per target in the team kernel (8 measured slower)
 
-constexpr int kLeavesPerStep = 1;          // leaves a team tests per step of its loop
+constexpr int kLeavesPerStep = 2;          // leaves a team tests per step of its loop
 constexpr int kListLanes = 16;             // lanes per target in the leaf-list kernel (measured: 2, 4, 8, 32, 64 slower on the 10^6 halo)
 
 // teams of TS lanes; the list holds TS * E entries; LPI leaves per step
