@@ -18,13 +18,16 @@
 //  k_knn_team  a team of 16 lanes per target, four targets per wavefront.  The
 //              team keys its leaf list by gap (FP32 rounded down, packed with
 //              the leaf index into one 64-bit word) and takes the leaves
-//              nearest first until the nearest left lies beyond the current
-//              radius.  A leaf's 32 particles are tested at once (two per
-//              lane), with the next leaf's positions already requested; those
-//              within the radius are appended to an LDS list of 16*E.  When it
-//              fills, the list is sorted on r^2 (register bitonic network, E
-//              keys per lane; runs of equal r^2 are then placed by ID) and cut
-//              back to N_ngb+1, which tightens the radius.  A target whose list
+//              nearest first, two a step, until the nearest left lies beyond
+//              the current radius.  A step's 64 particles (four per lane) are
+//              requested together and tested when they arrive; those within
+//              the radius are appended to an LDS list of 16*E.  When the list
+//              might not hold the next step it is cut: the radius becomes the
+//              (N_ngb+1)-th smallest r^2 rounded up to FP32, found by
+//              bisection on team-wide counts, and the entries above it go.  At
+//              the end the teams of a wavefront sort their lists on r^2
+//              (register bitonic network, E keys per lane; runs of equal r^2
+//              are then placed by ID) and keep N_ngb+1.  A target whose list
 //              overflowed, or whose wavefront gave up its group walk, walks the
 //              tree from the root instead (same loop).
 //
@@ -476,9 +479,10 @@ void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
     double T = A.tb[bb];
     wave_sync();
 
-    // leaf = 32 particles, PPL per lane (tl, tl + TS, ...); the next leaf's
-    // positions are requested before the current one is tested.  cur = -2
-    // before the first leaf is picked, -1 once none is left.
+    // leaf = 32 particles, PPL per lane (tl, tl + TS, ...); a step picks LPI
+    // leaves, requests their positions and tests them (with kPrefetchLeaf the
+    // next step's leaves are requested before the current ones are tested).
+    // cur = -2 before the first leaf is picked, -1 once none is left.
     // mixed form: the particles' FP32 offsets and their leaf's box; the test
     // is in FP32 against a radius widened by band_r2, the list holds FP32
     // r^2 until the final sort, which takes the exact FP64 r^2 of each entry
