@@ -22,6 +22,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMultiPasses = 4;        // passes run as grid-wide kernels
+constexpr int kEvalGrid = 6 * 256;     // evaluation workgroups (measured: 2048 and 16384 slower)
 constexpr int kFinisherMax = 256;      // shorter lists go to the one-workgroup finisher
 
 // control block: [0..1] list counts, [2] completed passes, [3] hand-off flag
@@ -724,7 +725,9 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
     k_step_reset<<<1, 64, 0, s>>>(A.st, A.ctl);
     if (!O) k_count_cand<<<1, 64, 0, s>>>(A.st, A.nt_dev, A.k);
     phase_begin(c, PH_EVAL);
-    k_eval<P, M, O><<<grid_for(total, 2048), kBlock, 0, s>>>(A);
+    // as many workgroups as are resident at once (the staging buffer's LDS
+    // allows six per CU), each striding over the candidates
+    k_eval<P, M, O><<<grid_for(total, kEvalGrid), kBlock, 0, s>>>(A);
     phase_end(c, PH_EVAL);
     const int g = grid_for(A.cap_acc < total ? A.cap_acc : total, 2048);
     phase_begin(c, PH_RESOLVE);
