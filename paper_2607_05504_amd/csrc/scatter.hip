@@ -22,7 +22,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMultiPasses = 4;        // passes run as grid-wide kernels
-constexpr int kEvalGrid = 6 * 256;     // evaluation workgroups (measured: 2048 and 16384 slower)
+constexpr int kEvalGrid = 6 * 256;     // evaluation workgroups at least (fewer were slower)
 constexpr int kFinisherMax = 256;      // shorter lists go to the one-workgroup finisher
 
 // control block: [0..1] list counts, [2] completed passes, [3] hand-off flag
@@ -725,9 +725,13 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
     k_step_reset<<<1, 64, 0, s>>>(A.st, A.ctl);
     if (!O) k_count_cand<<<1, 64, 0, s>>>(A.st, A.nt_dev, A.k);
     phase_begin(c, PH_EVAL);
-    // as many workgroups as are resident at once (the staging buffer's LDS
-    // allows six per CU), each striding over the candidates
-    k_eval<P, M, O><<<grid_for(total, kEvalGrid), kBlock, 0, s>>>(A);
+    // at least as many workgroups as are resident at once (the staging
+    // buffer's LDS allows six per CU), more for long candidate lists (about
+    // 2048 candidates a workgroup, at most 16384 workgroups), each striding
+    // over the candidates
+    int64_t ge = total / 2048;
+    ge = ge > 16384 ? 16384 : ge;
+    k_eval<P, M, O><<<ge > kEvalGrid ? (int)ge : grid_for(total, kEvalGrid), kBlock, 0, s>>>(A);
     phase_end(c, PH_EVAL);
     const int g = grid_for(A.cap_acc < total ? A.cap_acc : total, 2048);
     phase_begin(c, PH_RESOLVE);
@@ -765,7 +769,8 @@ hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, co
     phase_begin(c, PH_TIMESTEP);
     const int k = A.k;
     if (k <= 64 && (k & (k - 1)) == 0)
-        k_timestep_group<<<grid_for(n_active * k), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm, dt_out);
+        k_timestep_group<<<grid_for(n_active * k, 65536), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm,
+                                                                             dt_out);
     else
         k_timestep<<<grid_for(n_active), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm, dt_out);
     phase_end(c, PH_TIMESTEP);
