@@ -136,6 +136,13 @@ def set_table(table_w, table_sigma) -> None:
         raise ValueError("invalid cross-section table")
 
 
+def _masses(w):
+    """Per-particle masses of w (an optional ``masses`` array), else None:
+    the scalar w.mass is used."""
+    m = getattr(w, "masses", None)
+    return None if m is None else np.ascontiguousarray(m, dtype=np.float64)
+
+
 def _use_table(w) -> None:
     if getattr(w, "table_w", None) is not None and int(w.xsec) == XSEC_TABLE:
         set_table(w.table_w, w.table_sigma)
@@ -208,7 +215,7 @@ def scatter_step(w, ngb, h, band: float = 1e-9, want_info: bool = True):
     dt = _c(w.dt, np.float64)
     info = np.zeros((act.size, w.n_ngb), dtype=np.uint32) if want_info else None
     stats = _Stats()
-    rc = L.oref_scatter_step(w.n, _p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), None,
+    rc = L.oref_scatter_step(w.n, _p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), _p(_masses(w)),
                              float(w.mass), _p(ids), _p(st), int(w.periodic), float(w.box),
                              act.size, _p(act), w.n_ngb, _p(ngb), _p(h), _p(dt),
                              int(w.xsec), float(w.sigma0), float(w.w0), int(w.model),
@@ -230,7 +237,7 @@ def pair_timestep(w, ngb, h, vx=None, vy=None, vz=None):
     ngb = _c(ngb, np.int32)
     h = _c(h, np.float64)
     out = np.zeros(act.size, dtype=np.float64)
-    rc = L.oref_pair_timestep(w.n, _p(vx), _p(vy), _p(vz), None, float(w.mass), act.size,
+    rc = L.oref_pair_timestep(w.n, _p(vx), _p(vy), _p(vz), _p(_masses(w)), float(w.mass), act.size,
                               _p(act), w.n_ngb, _p(ngb), _p(h), int(w.xsec),
                               float(w.sigma0), float(w.w0), float(w.c_sidm), _p(out))
     if rc != 0:

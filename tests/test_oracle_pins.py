@@ -513,3 +513,24 @@ def test_beam_model_scatters_only_beam_target_pairs():
     i = w.active[a_idx]
     j = r["ngb"][a_idx, s_idx]
     assert np.all(w.state[i] != w.state[j])
+
+
+def test_step_with_unequal_masses_conserves_momentum_and_energy():
+    # a mass array: P uses m_j, the kick both masses (v_com weighted), the
+    # timestep m_i; sum m v and sum 1/2 m v^2 are kept by every elastic kick
+    w = W.uniform_box(3000, ic_seed=35, scatters_per_particle=1.0)
+    rng = np.random.Generator(np.random.PCG64(17))
+    w.masses = w.mass * rng.uniform(0.5, 1.5, w.n)
+    r = oracle.full_step(w, brute=True)
+    assert r["stats"]["n_events"] > 100
+    m = w.masses
+    for f in ("vx", "vy", "vz"):
+        assert abs(float((m * r[f]).sum() - (m * getattr(w, f)).sum())) <= \
+            1e-13 * float((m * np.abs(getattr(w, f))).sum())
+    e0 = float((m * (w.vx ** 2 + w.vy ** 2 + w.vz ** 2)).sum())
+    e1 = float((m * (r["vx"] ** 2 + r["vy"] ** 2 + r["vz"] ** 2)).sum())
+    assert e1 == pytest.approx(e0, rel=1e-13)
+    # and the masses matter: the same step with the scalar mass differs
+    w2 = W.uniform_box(3000, ic_seed=35, scatters_per_particle=1.0)
+    r2 = oracle.full_step(w2, brute=True)
+    assert not np.array_equal(r["vx"], r2["vx"])
