@@ -18,6 +18,7 @@ def _gpu():
 
 
 from gpu_helpers import gpu_step, assert_parity  # noqa: E402
+from paper_2607_05504_amd import FP64, MIXED  # noqa: E402
 
 
 def _announce(msg):
@@ -142,20 +143,21 @@ def test_tabulated_cross_section(case):
     assert g["stats"]["n_events"] > 0
 
 
-@pytest.mark.parametrize("case", ["box", "halo"])
-def test_refit_after_particles_moved(case):
+@pytest.mark.parametrize("case,prec", [("box", FP64), ("halo", FP64), ("halo", MIXED)])
+def test_refit_after_particles_moved(case, prec):
     """Tree reuse: after the particles have moved (drift in the periodic box,
     leapfrog steps in the halo) sidm_refit_tree keeps the old order, and the
-    step still matches the oracle on the new positions exactly."""
+    step still matches the oracle on the new positions exactly (the mixed
+    form's leaf offsets are refitted too)."""
     import torch
     from paper_2607_05504_amd import Context, runner
     if case == "box":
         w = W.uniform_box(20000, ic_seed=208, scatters_per_particle=0.1)
     else:
         w = W.hernquist_bins(W.hernquist_halo(20000, ic_seed=209, philox_seed=18), active_frac=0.25)
-    _announce(f"refit after motion: {case} n={w.n}")
+    _announce(f"refit after motion: {case} n={w.n} precision={prec}")
     ds = runner.upload(w, "cuda")
-    ctx = Context(runner.config_for(w), w.n, w.n_active)
+    ctx = Context(runner.config_for(w, precision=prec), w.n, w.n_active)
     out = runner.alloc_out(ds, w.n_ngb, with_info=True)
     ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state, m_scalar=ds.mass)
     dts = torch.full((w.n,), 0.01, dtype=torch.float64, device="cuda")
@@ -186,7 +188,7 @@ def test_refit_after_particles_moved(case):
              vy=ds.vy.cpu().numpy(), vz=ds.vz.cpu().numpy(), state=ds.state.cpu().numpy(),
              dt_sidm=out.dt_sidm.cpu().numpy(),
              info=out.cand_info.cpu().numpy().view(np.uint32), stats=stats)
-    assert_parity(moved, g, ref)
+    assert_parity(moved, g, ref, mixed=(prec == MIXED))
     ctx.close()
 
 
