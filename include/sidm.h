@@ -263,8 +263,10 @@ sidm_status sidm_find_overlap(sidm_ctx *ctx, double *h_all, const int32_t *activ
  * ia = min(floor(fa), NA-1), ir = min(floor(fr), NR-1), ta = fa - ia,
  * tr = fr - ir:  g0 = T[ia][ir] + tr (T[ia][ir+1] - T[ia][ir]),
  * g1 likewise from row ia+1,  ghat = g0 + ta (g1 - g0);  0 for rho >= 1.
- * h_all as given to sidm_find_overlap; cand_info (optional) has
- * n_active*max_ngb entries, slot a*max_ngb + s. */
+ * h_all as given to sidm_find_overlap (the Morton-order copy of it that the
+ * call made is read while the tree and the h_all address are unchanged,
+ * else gathered again); cand_info (optional) has n_active*max_ngb entries,
+ * slot a*max_ngb + s. */
 sidm_status sidm_scatter_overlap(sidm_ctx *ctx, sidm_particles *p, const double *h_all,
                                  const int32_t *active, int64_t n_active, int32_t max_ngb,
                                  const int32_t *ngb, const int32_t *count, const double *dt,
@@ -274,7 +276,8 @@ sidm_status sidm_scatter_overlap(sidm_ctx *ctx, sidm_particles *p, const double 
  * kernel's centre value W(0, h_i) replaced by each pair's g_ij at zero
  * separation (the largest value g_ij takes):
  *     dt_sidm[a] = c_sidm * 2 / (m_i max_j [g_ij(0) (w_ij sigma(w_ij)/m)])
- * over the partners of row a, with the current velocities; +inf if 0. */
+ * over the partners of row a, with the current velocities; +inf if 0.
+ * h_all as for sidm_scatter_overlap. */
 sidm_status sidm_pair_timestep_overlap(sidm_ctx *ctx, const double *h_all, const int32_t *active,
                                        int64_t n_active, int32_t max_ngb, const int32_t *ngb,
                                        const int32_t *count, double *dt_sidm);

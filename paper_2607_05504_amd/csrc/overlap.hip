@@ -17,23 +17,39 @@
 //                   finite), then k_leaf_hmax / k_level_hmax: the largest h
 //                   below every node of the tree, level after level (the
 //                   tree update between the two walks the paper describes)
-//  k_overlap        a team of 8 lanes per active particle walks the tree from
-//                   the root (one node per step, its 8 children tested by the
-//                   8 lanes), opening a child whose box lies closer than
-//                   h_i + h_max(child), and tests a leaf's 32 particles four
-//                   per lane, appending each j with r_ij^2 < (h_i + h_j)^2 to
-//                   the target's row.
+//  k_overlap        one wavefront per group of 4 targets consecutive in Morton
+//                   order.  The group walks the tree once against its bounding
+//                   sphere (centre c, radius rg): a node is opened when its box
+//                   lies closer to c than hg + h_max(node) + rg, hg the group's
+//                   largest h, up to 8 nodes popped per step (64 lanes, one per
+//                   child).  A leaf that passes gets the mask of the targets i
+//                   whose own test, box closer than h_i + h_max(leaf), it
+//                   passes, and is listed in LDS unless that mask is empty.
+//                   The listed leaves are then read two at a time (32 lanes
+//                   each, the next pair's particles loaded while this pair is
+//                   tested), and each target in the pair's masks tests all 64
+//                   particles, appending each j with r_ij^2 < (h_i + h_j)^2 to
+//                   its row.  A leaf's particles are thus read once for the
+//                   whole group.
 //
 // The pruning is conservative under rounding: a box gap rounds like a
 // particle separation (never above it) and h_i + h_j <= h_i + h_max rounds
-// monotonically, so no partner is skipped; the result is the definition.
+// monotonically, so the per-target leaf test skips no partner; the group test
+// only widens it (by the margins given at its use).  The result is the
+// definition.
 #include "sidm_internal.h"
 
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kTeamO = SIDM_TREE_FAN;      // lanes per target: one per child of a node
-constexpr int kStackO = (SIDM_TREE_FAN - 1) * (SIDM_MAX_LEVELS - 1) + 1;   // depth-first bound
+constexpr int kWaves = kBlock / 64;
+constexpr int kGroup = 4;                   // targets per wavefront in the walk
+// The walk pops up to 8 nodes at a time from the top of a stack kept sorted
+// by depth (children go above the rest, those of lower entries lower), so a
+// level's nodes are pushed only once none of that level is left: at most
+// 64 per level below the root.
+constexpr int kStackG = 64 * (SIDM_MAX_LEVELS - 1);
+constexpr int kLeafCap = 192;              // leaves listed per batch (a walk step adds <= 64)
 
 // F(x) = int_0^x q w(q) dq for the unit-support spline w(q) = W(q, 1)
 __device__ double spline_moment(double x)
@@ -196,7 +212,7 @@ struct OvlArgs {
     int32_t *ngb, *count;
     unsigned int *derr;
     TreeLevels lv;
-    int64_t n;
+    int64_t n, nblk;
     double box;
     int32_t max_ngb;
 };
@@ -204,68 +220,202 @@ struct OvlArgs {
 template <bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void k_overlap(OvlArgs A)
 {
-    __shared__ int32_t s_stk[kBlock / kTeamO][kStackO];
-    const int team = threadIdx.x / kTeamO, tl = threadIdx.x % kTeamO;
-    const int wteam = (threadIdx.x & 63) / kTeamO;
-    const int64_t b = (int64_t)blockIdx.x * (kBlock / kTeamO) + team;
-    if (b >= *A.nt_dev) return;                 // whole teams leave together
-    int32_t *stk = s_stk[team];
-    const int32_t i = A.tlist[b], a = A.slot[b];
-    const double px = A.xs[i], py = A.ys[i], pz = A.zs[i], hi = A.hs[i];
+    __shared__ int32_t s_stk[kWaves][kStackG];
+    __shared__ int32_t s_leaf[kWaves][kLeafCap];
+    __shared__ int32_t s_lmsk[kWaves][kLeafCap];
+    __shared__ double s_tgt[kWaves][kGroup][4];
+    __shared__ int64_t s_off[SIDM_MAX_LEVELS], s_cnt[SIDM_MAX_LEVELS];
+    if (threadIdx.x < SIDM_MAX_LEVELS) {
+        s_off[threadIdx.x] = A.lv.off[threadIdx.x];
+        s_cnt[threadIdx.x] = A.lv.cnt[threadIdx.x];
+    }
+    __syncthreads();
+    const int64_t blk = xcd_block(A.nblk);
+    if (blk < 0) return;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nt = *A.nt_dev;
+    const int64_t b0 = (blk * kWaves + wv) * kGroup;
+    if (b0 >= nt) return;                       // whole wavefronts leave together
+    const int ng = nt - b0 < kGroup ? (int)(nt - b0) : kGroup;
+    int32_t *stk = s_stk[wv], *lbuf = s_leaf[wv], *lmsk = s_lmsk[wv];
+    double (*tgt)[4] = s_tgt[wv];
     const double box = A.box;
-    const uint64_t below = (1ull << tl) - 1ull;
-    int32_t *row = A.ngb + (int64_t)a * A.max_ngb;
-    int64_t cnt = 0;
-    const int top = A.lv.nlev - 1;
-    if (tl == 0) stk[0] = top << SIDM_LEVEL_SHIFT;
-    int sp = 1;
-    wave_lds_sync();
-    while (sp > 0) {
-        const int32_t e = stk[--sp];
-        const int lvl = e >> SIDM_LEVEL_SHIFT;
-        const int64_t q = e & ((1 << SIDM_LEVEL_SHIFT) - 1);
-        if (lvl == 0) {
-            const int64_t j0 = q * SIDM_LEAF;
+    const int64_t n = A.n;
+    const uint64_t below = (1ull << lane) - 1ull;
+
+    // the group's targets: Morton index, row, and (x, y, z, h) in LDS; the
+    // padding slots of a short last group repeat its first target
+    int32_t ti[kGroup], ta[kGroup], cnt[kGroup];
 #pragma unroll
-            for (int rep = 0; rep < SIDM_LEAF / kTeamO; ++rep) {
-                const int64_t j = j0 + rep * kTeamO + tl;
+    for (int t = 0; t < kGroup; ++t) {
+        const int64_t b = b0 + (t < ng ? t : 0);
+        ti[t] = A.tlist[b];
+        ta[t] = A.slot[b];
+        cnt[t] = 0;
+    }
+    double mx = 0.0, my = 0.0, mz = 0.0, mh = 0.0;  // lane t < kGroup: target t
+    {
+        int32_t it = ti[0];
+#pragma unroll
+        for (int t = 1; t < kGroup; ++t)
+            if (lane == t) it = ti[t];
+        if (lane < kGroup) {
+            mx = A.xs[it]; my = A.ys[it]; mz = A.zs[it]; mh = A.hs[it];
+            tgt[lane][0] = mx; tgt[lane][1] = my; tgt[lane][2] = mz; tgt[lane][3] = mh;
+        }
+    }
+    // bounding sphere of the group (centre c, radius rg) and its largest h
+    double lx = mx, ux = mx, ly = my, uy = my, lz = mz, uz = mz, hg = mh;
+    if (lane >= kGroup) { lx = ly = lz = INFINITY; ux = uy = uz = -INFINITY; }
+#pragma unroll
+    for (int off = 1; off < kGroup; off <<= 1) {
+        lx = fmin(lx, __shfl_xor(lx, off)); ux = fmax(ux, __shfl_xor(ux, off));
+        ly = fmin(ly, __shfl_xor(ly, off)); uy = fmax(uy, __shfl_xor(uy, off));
+        lz = fmin(lz, __shfl_xor(lz, off)); uz = fmax(uz, __shfl_xor(uz, off));
+        hg = fmax(hg, __shfl_xor(hg, off));
+    }
+    const double cx = __shfl(0.5 * (lx + ux), 0), cy = __shfl(0.5 * (ly + uy), 0),
+                 cz = __shfl(0.5 * (lz + uz), 0);
+    double d2 = 0.0;
+    if (lane < kGroup) {
+        const double dx = mx - cx, dy = my - cy, dz = mz - cz;
+        d2 = (dx * dx + dy * dy) + dz * dz;
+    }
+#pragma unroll
+    for (int off = 1; off < kGroup; off <<= 1) d2 = fmax(d2, __shfl_xor(d2, off));
+    // A node can hold a partner of some target only if its box lies closer to
+    // c than hg + h_max(node) + rg (triangle inequality); the relative and, in
+    // a periodic box, absolute margins of 2^-40 cover every rounding.
+    constexpr double kRel = 1.0 + 0x1p-40;
+    const double r0 = __shfl((hg + sqrt(d2)) * kRel + (PERIODIC ? box * 0x1p-40 : 0.0), 0);
+    wave_lds_sync();
+
+    int sp = 1, nl = 0;
+    if (lane == 0) stk[0] = (A.lv.nlev - 1) << SIDM_LEVEL_SHIFT;
+    wave_lds_sync();
+    while (true) {
+        // Walk until the stack is empty or the leaf list could overflow.  Pop
+        // the top k <= 8 nodes; lane 8e + c tests child c of popped node e
+        // (e = 0 the lowest in the stack).  An accepted leaf carries the mask
+        // of the targets whose own test (gap < h_i + h_max(leaf)) it passes,
+        // and is dropped when that mask is empty.
+        while (sp > 0 && nl <= kLeafCap - 64) {
+            const int k = sp < 8 ? sp : 8;
+            const int e = lane >> 3, ch = lane & 7;
+            bool okN = false, okL = false;
+            int32_t ent = 0, tm = 0;
+            if (e < k) {
+                const int32_t pe = stk[sp - k + e];
+                const int cl = (pe >> SIDM_LEVEL_SHIFT) - 1;
+                const int64_t cq = (int64_t)(pe & ((1 << SIDM_LEVEL_SHIFT) - 1)) * SIDM_TREE_FAN + ch;
+                if (cq < s_cnt[cl]) {
+                    const int64_t g = s_off[cl] + cq;
+                    const double *nb = A.nodes + g * 6;
+                    const double bx0 = nb[0], by0 = nb[1], bz0 = nb[2];
+                    const double bx1 = nb[3], by1 = nb[4], bz1 = nb[5];
+                    const double hm = A.hmax[g];
+                    if (bx0 <= bx1) {
+                        const double gx = axis_gap<PERIODIC>(bx0, bx1, cx, box);
+                        const double gy = axis_gap<PERIODIC>(by0, by1, cy, box);
+                        const double gz = axis_gap<PERIODIC>(bz0, bz1, cz, box);
+                        const double R = r0 + hm * kRel;
+                        if ((gx * gx + gy * gy) + gz * gz < R * R) {
+                            if (cl > 0) {
+                                okN = true;
+                                ent = (cl << SIDM_LEVEL_SHIFT) | (int32_t)cq;
+                            } else {
+#pragma unroll
+                                for (int t = 0; t < kGroup; ++t) {
+                                    const double *T = tgt[t];
+                                    const double ex = axis_gap<PERIODIC>(bx0, bx1, T[0], box);
+                                    const double ey = axis_gap<PERIODIC>(by0, by1, T[1], box);
+                                    const double ez = axis_gap<PERIODIC>(bz0, bz1, T[2], box);
+                                    const double Rt = T[3] + hm;
+                                    if (t < ng && (ex * ex + ey * ey) + ez * ez < Rt * Rt)
+                                        tm |= 1 << t;
+                                }
+                                okL = tm != 0;
+                                ent = (int32_t)cq;
+                            }
+                        }
+                    }
+                }
+            }
+            const uint64_t mN = __ballot(okN), mL = __ballot(okL);
+            const int base = sp - k, np = __popcll(mN);
+            if (base + np > kStackG) {          // cannot happen: see kStackG
+                if (lane == 0) atomicOr(A.derr, DERR_STALL);
+                sp = 0;
+                nl = 0;
+                break;
+            }
+            wave_lds_sync();
+            if (okN) stk[base + __popcll(mN & below)] = ent;
+            if (okL) {
+                const int at = nl + __popcll(mL & below);
+                lbuf[at] = ent;
+                lmsk[at] = tm;
+            }
+            sp = base + np;
+            nl += __popcll(mL);
+            wave_lds_sync();
+        }
+        // The listed leaves two at a time (lanes 0-31 one, 32-63 the other),
+        // the next pair's particles loaded while this pair is tested; an odd
+        // leaf waits for the next batch unless the walk is done.
+        const int avail = sp == 0 ? nl : (nl & ~1);
+        const int half = lane >> 5, lt = lane & 31;
+        const int32_t lf = half < avail ? lbuf[half] : -1;
+        int64_t j = (int64_t)lf * SIDM_LEAF + lt;
+        bool valid = lf >= 0 && j < n;
+        double xj = 0.0, yj = 0.0, zj = 0.0, hj = 0.0;
+        int32_t pj = 0;
+        if (valid) { xj = A.xs[j]; yj = A.ys[j]; zj = A.zs[j]; hj = A.hs[j]; pj = A.perm[j]; }
+        for (int u = 0; u < avail; u += 2) {
+            const int need = __builtin_amdgcn_readfirstlane(lmsk[u] | (u + 1 < avail ? lmsk[u + 1] : 0));
+            // next pair
+            int32_t lf2 = -1;
+            if (u + 2 + half < avail) lf2 = lbuf[u + 2 + half];
+            const int64_t j2 = (int64_t)lf2 * SIDM_LEAF + lt;
+            const bool valid2 = lf2 >= 0 && j2 < n;
+            double xj2 = 0.0, yj2 = 0.0, zj2 = 0.0, hj2 = 0.0;
+            int32_t pj2 = 0;
+            if (valid2) { xj2 = A.xs[j2]; yj2 = A.ys[j2]; zj2 = A.zs[j2]; hj2 = A.hs[j2]; pj2 = A.perm[j2]; }
+#pragma unroll
+            for (int t = 0; t < kGroup; ++t) {
+                if (!((need >> t) & 1)) continue;
+                const double *T = tgt[t];
                 bool ok = false;
-                if (j < A.n && j != i) {
-                    const double r2 = sep2<PERIODIC>(px, py, pz, A.xs[j], A.ys[j], A.zs[j], box);
-                    const double s = hi + A.hs[j];
+                if (valid && j != ti[t]) {
+                    const double r2 = sep2<PERIODIC>(T[0], T[1], T[2], xj, yj, zj, box);
+                    const double s = T[3] + hj;
                     ok = r2 < s * s;
                 }
-                const uint64_t m = (__ballot(ok) >> (wteam * kTeamO)) & 0xffull;
+                const uint64_t m = __ballot(ok);
                 if (ok) {
-                    const int64_t pos = cnt + __popcll(m & below);
-                    if (pos < A.max_ngb) row[pos] = A.perm[j];
+                    const int64_t pos = (int64_t)cnt[t] + __popcll(m & below);
+                    if (pos < A.max_ngb) A.ngb[(int64_t)ta[t] * A.max_ngb + pos] = pj;
                 }
-                cnt += __popcll(m);
+                cnt[t] += __popcll(m);
             }
-            continue;
+            j = j2; valid = valid2; xj = xj2; yj = yj2; zj = zj2; hj = hj2; pj = pj2;
         }
-        const int cl = lvl - 1;
-        const int64_t cq = q * SIDM_TREE_FAN + tl;
-        bool ok = false;
-        if (cq < A.lv.cnt[cl]) {
-            const int64_t g = A.lv.off[cl] + cq;
-            const double R = hi + A.hmax[g];
-            ok = node_gap2<PERIODIC>(A.nodes, g, px, py, pz, box) < R * R;
+        if (avail < nl) {                       // carry the odd leaf
+            const int32_t last = lbuf[nl - 1], lastm = lmsk[nl - 1];
+            wave_lds_sync();
+            if (lane == 0) { lbuf[0] = last; lmsk[0] = lastm; }
+            wave_lds_sync();
         }
-        const uint64_t m = (__ballot(ok) >> (wteam * kTeamO)) & 0xffull;
-        const int np = __popcll(m);
-        wave_lds_sync();
-        if (ok && sp + np <= kStackO) stk[sp + __popcll(m & below)] = (cl << SIDM_LEVEL_SHIFT) | (int32_t)cq;
-        if (sp + np > kStackO) {                // cannot happen: depth-first bound
-            if (tl == 0) atomicOr(A.derr, DERR_STALL);
-            break;
-        }
-        sp += np;
-        wave_lds_sync();
+        nl -= avail;
+        if (sp == 0 && nl == 0) break;
     }
-    if (tl == 0) {
-        A.count[a] = (int32_t)(cnt < 0x7fffffff ? cnt : 0x7fffffff);
-        if (cnt > A.max_ngb) atomicOr(A.derr, DERR_NGB_OVERFLOW);
+#pragma unroll
+    for (int t = 0; t < kGroup; ++t) {
+        if (t < ng && lane == t) {
+            A.count[ta[t]] = cnt[t];
+            if (cnt[t] > A.max_ngb) atomicOr(A.derr, DERR_NGB_OVERFLOW);
+        }
     }
 }
 
@@ -285,6 +435,14 @@ hipError_t launch_overlap_table(sidm_ctx *c)
     return hipGetLastError();
 }
 
+hipError_t launch_gather_h(sidm_ctx *c, const double *h_all)
+{
+    k_gather_h<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, c->perm, h_all, c->hs, c->derr);
+    c->hs_valid = 1;
+    c->hs_src = h_all;
+    return hipGetLastError();
+}
+
 hipError_t launch_find_overlap(sidm_ctx *c, double *h_all, const double *h_active,
                                int64_t n_active, int32_t max_ngb, int32_t *ngb, int32_t *count)
 {
@@ -296,6 +454,8 @@ hipError_t launch_find_overlap(sidm_ctx *c, double *h_all, const double *h_activ
         k_update_h<<<grid_for(n_active), kBlock, 0, s>>>(c->tlist, c->slot, c->nt_dev, c->perm,
                                                          h_active, h_all);
     k_gather_h<<<grid_for(n), kBlock, 0, s>>>(n, c->perm, h_all, c->hs, c->derr);
+    c->hs_valid = 1;
+    c->hs_src = h_all;
     const int64_t nleaf = lv.cnt[0];
     k_leaf_hmax<<<(unsigned)((nleaf * 32 + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, nleaf, c->hs,
                                                                                 c->hmax);
@@ -307,7 +467,10 @@ hipError_t launch_find_overlap(sidm_ctx *c, double *h_all, const double *h_activ
     A.perm = c->perm; A.tlist = c->tlist; A.slot = c->slot; A.nt_dev = c->nt_dev;
     A.ngb = ngb; A.count = count; A.derr = c->derr;
     A.lv = lv; A.n = n; A.box = c->cfg.box; A.max_ngb = max_ngb;
-    const unsigned grid = (unsigned)((n_active + kBlock / kTeamO - 1) / (kBlock / kTeamO));
+    const int64_t groups = (n_active + kGroup - 1) / kGroup;
+    A.nblk = (groups + kWaves - 1) / kWaves;
+    if (A.nblk < 1) A.nblk = 1;
+    const unsigned grid = xcd_grid(A.nblk);
     if (c->cfg.periodic) k_overlap<true><<<grid, kBlock, 0, s>>>(A);
     else k_overlap<false><<<grid, kBlock, 0, s>>>(A);
     phase_end(c, PH_OVERLAP);

@@ -330,6 +330,7 @@ sidm_status sidm_reconfigure(sidm_ctx *c, const sidm_config *cfg)
     c->cfg = *cfg;
     c->tree_ok = 0;          // a new configuration needs a new snapshot
     c->map_valid = 0;
+    c->hs_valid = 0;
     hipError_t e = copy_table(c);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "reconfigure");
@@ -383,6 +384,7 @@ sidm_status sidm_refit_tree(sidm_ctx *c, const sidm_particles *p)
     hipError_t e = launch_refit_tree(c, p);
     phase_end(c, PH_TREE);
     c->map_valid = 0;
+    c->hs_valid = 0;
     if (e != hipSuccess) return hip_fail(c, e, "refit_tree");
     c->tree_ok = 1;
     return SIDM_OK;
@@ -400,6 +402,7 @@ sidm_status sidm_build_tree(sidm_ctx *c, const sidm_particles *p)
     hipError_t e = launch_build_tree(c, p);
     phase_end(c, PH_TREE);
     c->map_valid = 0;
+    c->hs_valid = 0;
     if (e != hipSuccess) return hip_fail(c, e, "build_tree");
     c->tree_ok = 1;
     c->sorted_n = p->n;
@@ -569,8 +572,10 @@ sidm_status sidm_scatter_overlap(sidm_ctx *c, sidm_particles *p, const double *h
         return SIDM_E_INVAL;
     }
     hipError_t e = map_active(c, active, n_active);
+    if (e == hipSuccess && n_active > 0 && !(c->hs_valid && c->hs_src == h_all))
+        e = launch_gather_h(c, h_all);
     if (e == hipSuccess)
-        e = launch_scatter_overlap(c, p, n_active, h_all, max_ngb, ngb, count, dt, seed, step,
+        e = launch_scatter_overlap(c, p, n_active, max_ngb, ngb, count, dt, seed, step,
                                    cand_info);
     if (e != hipSuccess) return hip_fail(c, e, "scatter_overlap");
     return SIDM_OK;
@@ -590,7 +595,8 @@ sidm_status sidm_pair_timestep_overlap(sidm_ctx *c, const double *h_all, const i
     }
     if (n_active == 0) return SIDM_OK;
     hipError_t e = map_active(c, active, n_active);
-    if (e == hipSuccess) e = launch_timestep_overlap(c, n_active, h_all, max_ngb, ngb, count, dt_sidm);
+    if (e == hipSuccess && !(c->hs_valid && c->hs_src == h_all)) e = launch_gather_h(c, h_all);
+    if (e == hipSuccess) e = launch_timestep_overlap(c, n_active, max_ngb, ngb, count, dt_sidm);
     if (e != hipSuccess) return hip_fail(c, e, "pair_timestep_overlap");
     return SIDM_OK;
 }

@@ -61,10 +61,10 @@ struct StepArgs {
     int xt_n;
     // candidate rows: stride entries a row (n_ngb for the one-sided
     // estimator); the overlap estimator's rows hold count[a] partners and
-    // take g_ij from every particle's h (h_all, caller order) and the table
+    // take g_ij from every particle's h (hsrt, Morton order) and the table
     int stride;
     const int32_t *cnt;
-    const double *h_all, *gtab;
+    const double *hsrt, *gtab;
     uint64_t seed;
     uint32_t step;
     int k, periodic, xsec, model, has_mass;
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                 if (exact) {
                     const double r = sqrt(sep2<PERIODIC>(A.xs[i], A.ys[i], A.zs[i], A.xs[j], A.ys[j],
                                                          A.zs[j], A.box));
-                    W = OVERLAP ? overlap_g(A.gtab, A.h_all[A.perm[i]], A.h_all[jc], r)
+                    W = OVERLAP ? overlap_g(A.gtab, A.hsrt[i], A.hsrt[j], r)
                                 : cubic_spline(r, A.h[a]);
                     const double w = rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
                     const double sig = sigma_of(A, w);
@@ -664,13 +664,14 @@ __global__ __launch_bounds__(kBlock) void k_timestep_overlap(StepArgs A, double 
             i = A.tlist[b];
             a = A.slot[b];
             const double vix = A.vxs[i], viy = A.vys[i], viz = A.vzs[i];
-            const double hi = A.h_all[A.perm[i]];
+            const double hi = A.hsrt[i];
             const int len = A.cnt[a] < A.stride ? A.cnt[a] : A.stride;
             for (int s = tl; s < len; s += kTeamT) {
                 const int32_t jc = A.ngb[(int64_t)a * A.stride + s];
-                const double rate = pair_rate(A, vix, viy, viz, jc);
-                if (jc < 0 || jc >= A.n) continue;
-                const double q = overlap_g(A.gtab, hi, A.h_all[jc], 0.0) * rate;
+                if (jc < 0 || jc >= A.n) { atomicOr(A.derr, DERR_INDEX); continue; }
+                const int32_t j = A.inv[jc];
+                const double w = rel_speed(vix, viy, viz, A.vxs[j], A.vys[j], A.vzs[j]);
+                const double q = overlap_g(A.gtab, hi, A.hsrt[j], 0.0) * (w * sigma_of(A, w));
                 qmax = q > qmax ? q : qmax;
             }
         }
@@ -707,7 +708,7 @@ StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const dou
     A.model = c->cfg.model; A.has_mass = c->has_mass;
     A.xo = c->xo; A.yo = c->yo; A.zo = c->zo; A.nodes = c->nodes; A.band_p = c->cfg.band_p;
     A.xt_w = c->xt_w; A.xt_s = c->xt_s; A.xt_n = c->cfg.xsec_n;
-    A.stride = A.k; A.cnt = nullptr; A.h_all = nullptr; A.gtab = c->gtab;
+    A.stride = A.k; A.cnt = nullptr; A.hsrt = c->hs; A.gtab = c->gtab;
     return A;
 }
 
@@ -778,23 +779,22 @@ hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, co
 }
 
 hipError_t launch_scatter_overlap(sidm_ctx *c, sidm_particles *p, int64_t n_active,
-                                  const double *h_all, int32_t max_ngb, const int32_t *ngb,
+                                  int32_t max_ngb, const int32_t *ngb,
                                   const int32_t *count, const double *dt, uint64_t seed,
                                   uint32_t step, uint32_t *cand_info)
 {
     StepArgs A = make_args(c, p, ngb, nullptr, dt, seed, step, cand_info);
-    A.stride = max_ngb; A.cnt = count; A.h_all = h_all;
+    A.stride = max_ngb; A.cnt = count;
     if (c->cfg.periodic) run_scatter<true, false, true>(c, A, n_active, c->stream);
     else run_scatter<false, false, true>(c, A, n_active, c->stream);
     return hipGetLastError();
 }
 
-hipError_t launch_timestep_overlap(sidm_ctx *c, int64_t n_active, const double *h_all,
-                                   int32_t max_ngb, const int32_t *ngb, const int32_t *count,
+hipError_t launch_timestep_overlap(sidm_ctx *c, int64_t n_active, int32_t max_ngb, const int32_t *ngb, const int32_t *count,
                                    double *dt_out)
 {
     StepArgs A = make_args(c, nullptr, ngb, nullptr, nullptr, 0, 0, nullptr);
-    A.stride = max_ngb; A.cnt = count; A.h_all = h_all;
+    A.stride = max_ngb; A.cnt = count;
     phase_begin(c, PH_TIMESTEP);
     k_timestep_overlap<<<grid_for(n_active * kTeamT), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm,
                                                                              dt_out);

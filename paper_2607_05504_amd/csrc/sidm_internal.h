@@ -138,6 +138,8 @@ struct sidm_ctx {
     // overlap estimator only: every particle's h in Morton order, the largest
     // h below every tree node, and the ghat table
     double *hs, *hmax, *gtab;
+    int hs_valid;            // hs holds hs_src gathered for the current tree
+    const double *hs_src;
     unsigned long long *adv_min;   // served form: smallest per-pair bound of a step
     // opt-in event timing of the main kernels: up to SIDM_TIMING_RING launches
     // of each phase are bracketed between two sidm_timing_read calls
@@ -405,17 +407,18 @@ hipError_t launch_scatter(sidm_ctx *c, sidm_particles *p, int64_t n_active, cons
                           uint32_t *cand_info);
 hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, const double *h,
                            double *dt_out);
+// (both read every particle's h from the Morton-order copy c->hs)
 hipError_t launch_scatter_overlap(sidm_ctx *c, sidm_particles *p, int64_t n_active,
-                                  const double *h_all, int32_t max_ngb, const int32_t *ngb,
+                                  int32_t max_ngb, const int32_t *ngb,
                                   const int32_t *count, const double *dt, uint64_t seed,
                                   uint32_t step, uint32_t *cand_info);
-hipError_t launch_timestep_overlap(sidm_ctx *c, int64_t n_active, const double *h_all,
-                                   int32_t max_ngb, const int32_t *ngb, const int32_t *count,
+hipError_t launch_timestep_overlap(sidm_ctx *c, int64_t n_active, int32_t max_ngb, const int32_t *ngb, const int32_t *count,
                                    double *dt_out);
 // overlap.hip
 hipError_t launch_overlap_table(sidm_ctx *c);
 hipError_t launch_find_overlap(sidm_ctx *c, double *h_all, const double *h_active,
                                int64_t n_active, int32_t max_ngb, int32_t *ngb, int32_t *count);
+hipError_t launch_gather_h(sidm_ctx *c, const double *h_all);
 // advance.hip
 hipError_t launch_advance(sidm_ctx *c, double *x, double *y, double *z, double *vx, double *vy,
                           double *vz, int64_t n, const double *dt_sidm, int64_t n_active,

@@ -274,3 +274,35 @@ def test_empty_active_set():
     assert st["error"] == 0 and st["n_events"] == 0 and st["n_cand"] == 0
     assert torch.equal(ds.vx, v0)
     ctx.close()
+
+
+def test_h_copy_after_rebuild_and_other_h_array():
+    """The scattering step and the timestep read every particle's h from the
+    Morton-order copy sidm_find_overlap makes; after a new tree, or for an h
+    array at another address, they gather it again.  Both orders give results
+    identical to the plain step."""
+    import torch
+    from paper_2607_05504_amd import runner
+    w = W.hernquist_bins(W.hernquist_halo(20000, ic_seed=89, philox_seed=7))
+    _announce(f"overlap h copy after a rebuild, active={w.n_active}")
+    ref, ctx, ds, out = _run(w, 1024, with_info=False)
+    ctx.close()
+    ds = runner.upload(w, "cuda")
+    ctx = _ctx(w)
+    out = runner.alloc_overlap(ds, w.n_ngb, 1024, with_info=False)
+    tree = lambda: ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids,
+                                  state=ds.state, m_scalar=ds.mass)
+    tree()
+    ctx.find_ngb(out.everyone, out.ngb_all, out.h_all)
+    ctx.find_overlap(out.h_all, ds.active, out.ngb, out.count)
+    tree()                                   # same positions: same tree, stale copy
+    h2 = out.h_all.clone()                   # same values at another address
+    ctx.scatter_overlap(h2, ds.active, out.ngb, out.count, ds.dt, w.seed, w.step)
+    ctx.pair_timestep_overlap(h2, ds.active, out.ngb, out.count, out.dt_sidm)
+    st = ctx.sync()
+    ctx.close()
+    assert st["error"] == 0
+    assert st["n_events"] == ref["stats"]["n_events"]
+    for f in ("vx", "vy", "vz"):
+        assert np.array_equal(getattr(ds, f).cpu().numpy(), ref[f]), f
+    assert np.array_equal(out.dt_sidm.cpu().numpy(), ref["dt_sidm"])
