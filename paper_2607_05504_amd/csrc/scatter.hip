@@ -280,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
         int s = 0;
         int32_t a = 0;
         if (live) {
-            b = c / A.stride;
+            b = total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)A.stride) : c / A.stride;
             s = (int)(c - b * A.stride);
             a = A.slot[b];
             if (OVERLAP) live = s < A.cnt[a];
@@ -728,10 +728,11 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
     phase_begin(c, PH_EVAL);
     // at least as many workgroups as are resident at once (the staging
     // buffer's LDS allows six per CU), more for long candidate lists (about
-    // 2048 candidates a workgroup, at most 16384 workgroups), each striding
-    // over the candidates
+    // 2048 candidates a workgroup, at most 8192 workgroups: more cost more
+    // in flushes and statistics atomics than they gain), each striding over
+    // the candidates
     int64_t ge = total / 2048;
-    ge = ge > 16384 ? 16384 : ge;
+    ge = ge > 8192 ? 8192 : ge;
     k_eval<P, M, O><<<ge > kEvalGrid ? (int)ge : grid_for(total, kEvalGrid), kBlock, 0, s>>>(A);
     phase_end(c, PH_EVAL);
     const int g = grid_for(A.cap_acc < total ? A.cap_acc : total, 2048);

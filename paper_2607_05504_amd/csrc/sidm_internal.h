@@ -319,7 +319,9 @@ __device__ __forceinline__ double pair_prob(double m_j, double sig, double w, do
     return (((0.5 * m_j) * sig) * w * W) * dt;
 }
 
-// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Each round's two
+// products are taken whole (32 x 32 -> 64 bits: one v_mad_u64_u32 each, where
+// separate high and low halves cost two quarter-rate multiplies).
 struct Philox4 { uint32_t x0, x1, x2, x3; };
 
 __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
@@ -328,11 +330,10 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-        uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-        uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-        uint32_t n0 = hi1 ^ c1 ^ k0;
-        uint32_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
     }
     return Philox4{c0, c1, c2, c3};
 }
