@@ -26,8 +26,7 @@
 //                   whose own test, box closer than h_i + h_max(leaf), it
 //                   passes, and is listed in LDS unless that mask is empty.
 //                   The listed leaves are then read two at a time (32 lanes
-//                   each, the next pair's particles loaded while this pair is
-//                   tested), and each target in the pair's masks tests all 64
+//                   each), and each target in the pair's masks tests all 64
 //                   particles, appending each j with r_ij^2 < (h_i + h_j)^2 to
 //                   its row.  A leaf's particles are thus read once for the
 //                   whole group.
@@ -361,27 +360,18 @@ __global__ __launch_bounds__(kBlock) void k_overlap(OvlArgs A)
             nl += __popcll(mL);
             wave_lds_sync();
         }
-        // The listed leaves two at a time (lanes 0-31 one, 32-63 the other),
-        // the next pair's particles loaded while this pair is tested; an odd
-        // leaf waits for the next batch unless the walk is done.
+        // The listed leaves two at a time (lanes 0-31 one, 32-63 the other);
+        // an odd leaf waits for the next batch unless the walk is done.
         const int avail = sp == 0 ? nl : (nl & ~1);
         const int half = lane >> 5, lt = lane & 31;
-        const int32_t lf = half < avail ? lbuf[half] : -1;
-        int64_t j = (int64_t)lf * SIDM_LEAF + lt;
-        bool valid = lf >= 0 && j < n;
-        double xj = 0.0, yj = 0.0, zj = 0.0, hj = 0.0;
-        int32_t pj = 0;
-        if (valid) { xj = A.xs[j]; yj = A.ys[j]; zj = A.zs[j]; hj = A.hs[j]; pj = A.perm[j]; }
         for (int u = 0; u < avail; u += 2) {
             const int need = __builtin_amdgcn_readfirstlane(lmsk[u] | (u + 1 < avail ? lmsk[u + 1] : 0));
-            // next pair
-            int32_t lf2 = -1;
-            if (u + 2 + half < avail) lf2 = lbuf[u + 2 + half];
-            const int64_t j2 = (int64_t)lf2 * SIDM_LEAF + lt;
-            const bool valid2 = lf2 >= 0 && j2 < n;
-            double xj2 = 0.0, yj2 = 0.0, zj2 = 0.0, hj2 = 0.0;
-            int32_t pj2 = 0;
-            if (valid2) { xj2 = A.xs[j2]; yj2 = A.ys[j2]; zj2 = A.zs[j2]; hj2 = A.hs[j2]; pj2 = A.perm[j2]; }
+            const int32_t lf = u + half < avail ? lbuf[u + half] : -1;
+            const int64_t j = (int64_t)lf * SIDM_LEAF + lt;
+            const bool valid = lf >= 0 && j < n;
+            double xj = 0.0, yj = 0.0, zj = 0.0, hj = 0.0;
+            int32_t pj = 0;
+            if (valid) { xj = A.xs[j]; yj = A.ys[j]; zj = A.zs[j]; hj = A.hs[j]; pj = A.perm[j]; }
 #pragma unroll
             for (int t = 0; t < kGroup; ++t) {
                 if (!((need >> t) & 1)) continue;
@@ -399,7 +389,6 @@ __global__ __launch_bounds__(kBlock) void k_overlap(OvlArgs A)
                 }
                 cnt[t] += __popcll(m);
             }
-            j = j2; valid = valid2; xj = xj2; yj = yj2; zj = zj2; hj = hj2; pj = pj2;
         }
         if (avail < nl) {                       // carry the odd leaf
             const int32_t last = lbuf[nl - 1], lastm = lmsk[nl - 1];

@@ -649,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_timestep(StepArgs A, double c_sidm, 
 // Overlap estimator: dt_i = 2 C_SIDM / (m_i max_j [g_ij(0) (w_ij sigma(w_ij)/m)])
 // over the partners of the target's row.  A team of kTeamT lanes per target
 // strides over its row; the maximum is taken by shuffles within the team.
-constexpr int kTeamT = 16;
+constexpr int kTeamT = 32;
 
 __global__ __launch_bounds__(kBlock) void k_timestep_overlap(StepArgs A, double c_sidm, double *dt_out)
 {
@@ -671,7 +671,7 @@ __global__ __launch_bounds__(kBlock) void k_timestep_overlap(StepArgs A, double 
                 if (jc < 0 || jc >= A.n) { atomicOr(A.derr, DERR_INDEX); continue; }
                 const int32_t j = A.inv[jc];
                 const double w = rel_speed(vix, viy, viz, A.vxs[j], A.vys[j], A.vzs[j]);
-                const double q = overlap_g(A.gtab, hi, A.hsrt[j], 0.0) * (w * sigma_of(A, w));
+                const double q = overlap_g0(A.gtab, hi, A.hsrt[j]) * (w * sigma_of(A, w));
                 qmax = q > qmax ? q : qmax;
             }
         }

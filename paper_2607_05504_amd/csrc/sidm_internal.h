@@ -307,6 +307,20 @@ __device__ __forceinline__ double overlap_g(const double *__restrict__ tab, doub
     return (g0 + ta * (g1 - g0)) / ((H * H) * H);
 }
 
+// overlap_g at r = 0, where the radial weight tr is 0 and only the table's
+// first column is read (the same value, bit for bit)
+__device__ __forceinline__ double overlap_g0(const double *__restrict__ tab, double hi, double hj)
+{
+    const double H = hi + hj;
+    const double al = (hi < hj ? hi : hj) / H;
+    const double fa = al * (2.0 * SIDM_OVERLAP_NA);
+    int ia = (int)fa;
+    if (ia > SIDM_OVERLAP_NA - 1) ia = SIDM_OVERLAP_NA - 1;
+    const double ta = fa - ia;
+    const double g0 = tab[ia * (SIDM_OVERLAP_NR + 1)], g1 = tab[(ia + 1) * (SIDM_OVERLAP_NR + 1)];
+    return (g0 + ta * (g1 - g0)) / ((H * H) * H);
+}
+
 __device__ __forceinline__ double rel_speed(double ax, double ay, double az, double bx,
                                             double by, double bz)
 {
