@@ -42,6 +42,7 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(xs, N, double); ADD(ys, N, double); ADD(zs, N, double);
     ADD(vxs, N, double); ADD(vys, N, double); ADD(vzs, N, double); ADD(ms, N, double);
     ADD(ids, N, uint32_t); ADD(sts, N, uint8_t);
+    ADD(rec, N * 8, double);
     ADD(perm, N, int32_t); ADD(inv, N, int32_t);
     ADD(key0, N, uint64_t); ADD(key1, N, uint64_t);
     ADD(val0, N, int32_t); ADD(val1, N, int32_t);

@@ -94,6 +94,7 @@ struct sidm_ctx {
     double *xs, *ys, *zs, *vxs, *vys, *vzs, *ms;
     uint32_t *ids;
     uint8_t *sts;
+    double *rec;             // [cap_n * 8] the caller's particles as 64-byte records
     int32_t *perm;           // sorted -> caller index
     int32_t *inv;            // caller -> sorted index
 

@@ -1,7 +1,8 @@
 // Tree build for the SIDM neighbour search (the dedicated DM-only tree of the
 // paper's sec. 4.3, rebuilt every step on the GPU):
 //   bounds -> 48-bit Morton keys -> LSD radix sort (8-bit digits, stable) ->
-//   gather of a Morton-ordered structure-of-arrays snapshot ->
+//   the particles packed as 64-byte records and gathered into a Morton-ordered
+//   structure-of-arrays snapshot ->
 //   bucket leaves of SIDM_LEAF consecutive particles -> boxes of an implicit
 //   SIDM_TREE_FAN-ary tree over the leaves, one level per launch.
 // Also maps the caller's active list onto Morton order (flag + compaction).
@@ -280,48 +281,56 @@ __global__ void k_inverse(int64_t n, const int32_t *__restrict__ order, int32_t 
     }
 }
 
-// Gather form: sorted slot s reads its particle perm[s] (random loads,
-// coalesced stores).  Used when the arrays are too large for the stores of
-// the scatter form below to combine in the caches.
-__global__ void k_gather(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ x,
-                         const double *__restrict__ y, const double *__restrict__ z,
-                         const double *__restrict__ vx, const double *__restrict__ vy,
-                         const double *__restrict__ vz, const double *__restrict__ mass,
-                         const uint32_t *__restrict__ id, const uint8_t *__restrict__ st,
-                         double *xs, double *ys, double *zs, double *vxs, double *vys, double *vzs,
-                         double *ms, uint32_t *ids, uint8_t *sts)
-{
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t o = perm[s];
-        xs[s] = x[o]; ys[s] = y[o]; zs[s] = z[o];
-        vxs[s] = vx[o]; vys[s] = vy[o]; vzs[s] = vz[o];
-        if (mass) ms[s] = mass[o];
-        ids[s] = id[o];
-        sts[s] = st ? st[o] : (uint8_t)0;
-    }
-}
-
-// Scatter form: each caller particle is read once, in the caller's order (coalesced), and
-// written to its sorted place: the random side is the stores, which do not
-// hold the wavefront up the way dependent random loads would.
-__global__ void k_scatter_snapshot(int64_t n, const int32_t *__restrict__ inv,
-                                   const double *__restrict__ x, const double *__restrict__ y,
-                                   const double *__restrict__ z, const double *__restrict__ vx,
-                                   const double *__restrict__ vy, const double *__restrict__ vz,
-                                   const double *__restrict__ mass, const uint32_t *__restrict__ id,
-                                   const uint8_t *__restrict__ st, double *xs, double *ys,
-                                   double *zs, double *vxs, double *vys, double *vzs, double *ms,
-                                   uint32_t *ids, uint8_t *sts)
+// The snapshot in two passes.  k_pack writes each caller particle as one
+// 64-byte record (x y z vx vy vz m, id | state << 32), reading the caller's
+// arrays in their order; k_gather_rec then fills sorted slot s from record
+// perm[s], four lanes a record (16 bytes each, one 64-byte segment), and
+// writes the sorted arrays coalesced.  One random access a particle instead
+// of one for each of its nine arrays.
+__global__ __launch_bounds__(256) void k_pack(int64_t n, const double *__restrict__ x,
+                                              const double *__restrict__ y,
+                                              const double *__restrict__ z,
+                                              const double *__restrict__ vx,
+                                              const double *__restrict__ vy,
+                                              const double *__restrict__ vz,
+                                              const double *__restrict__ mass,
+                                              const uint32_t *__restrict__ id,
+                                              const uint8_t *__restrict__ st, double2 *rec)
 {
     for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n;
          o += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t s = inv[o];
-        xs[s] = x[o]; ys[s] = y[o]; zs[s] = z[o];
-        vxs[s] = vx[o]; vys[s] = vy[o]; vzs[s] = vz[o];
-        if (mass) ms[s] = mass[o];
-        ids[s] = id[o];
-        sts[s] = st ? st[o] : (uint8_t)0;
+        const uint64_t w = (uint64_t)id[o] | ((uint64_t)(st ? st[o] : 0) << 32);
+        double2 *r = rec + o * 4;
+        r[0] = make_double2(x[o], y[o]);
+        r[1] = make_double2(z[o], vx[o]);
+        r[2] = make_double2(vy[o], vz[o]);
+        r[3] = make_double2(mass ? mass[o] : 0.0, __longlong_as_double((long long)w));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gather_rec(int64_t n, const int32_t *__restrict__ perm,
+                                                    const double2 *__restrict__ rec, int has_mass,
+                                                    double *xs, double *ys, double *zs,
+                                                    double *vxs, double *vys, double *vzs,
+                                                    double *ms, uint32_t *ids, uint8_t *sts)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 4 * n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = t >> 2;
+        const int q = (int)(t & 3);
+        const double2 v = rec[(int64_t)perm[s] * 4 + q];
+        if (q == 0) {
+            xs[s] = v.x; ys[s] = v.y;
+        } else if (q == 1) {
+            zs[s] = v.x; vxs[s] = v.y;
+        } else if (q == 2) {
+            vys[s] = v.x; vzs[s] = v.y;
+        } else {
+            if (has_mass) ms[s] = v.x;
+            const uint64_t w = (uint64_t)__double_as_longlong(v.y);
+            ids[s] = (uint32_t)w;
+            sts[s] = (uint8_t)(w >> 32);
+        }
     }
 }
 
@@ -527,7 +536,6 @@ __global__ __launch_bounds__(256) void k_leaf_offsets(int64_t n, const double *_
     }
 }
 
-constexpr int64_t kScatterMaxN = (int64_t)1 << 21;
 
 hipError_t launch_build_tree(sidm_ctx *c, const sidm_particles *p)
 {
@@ -567,18 +575,11 @@ hipError_t launch_refit_tree(sidm_ctx *c, const sidm_particles *p)
     hipStream_t s = c->stream;
     const int64_t n = p->n;
     const sidm_config &cfg = c->cfg;
-    // the scatter form wins while the snapshot (61 B a particle) fits the
-    // caches that combine its scattered stores (measured: 10^6 faster,
-    // 1.7e7 slower than the gather form)
-    if (n <= kScatterMaxN)
-        k_scatter_snapshot<<<grid_for(n), kBlock, 0, s>>>(n, c->inv, p->x, p->y, p->z, p->vx,
-                                                          p->vy, p->vz, p->mass, p->id, p->state,
-                                                          c->xs, c->ys, c->zs, c->vxs, c->vys,
-                                                          c->vzs, c->ms, c->ids, c->sts);
-    else
-        k_gather<<<grid_for(n), kBlock, 0, s>>>(n, c->perm, p->x, p->y, p->z, p->vx, p->vy, p->vz,
-                                                p->mass, p->id, p->state, c->xs, c->ys, c->zs,
-                                                c->vxs, c->vys, c->vzs, c->ms, c->ids, c->sts);
+    k_pack<<<grid_for(n), kBlock, 0, s>>>(n, p->x, p->y, p->z, p->vx, p->vy, p->vz, p->mass, p->id,
+                                         p->state, (double2 *)c->rec);
+    k_gather_rec<<<grid_for(4 * n), kBlock, 0, s>>>(n, c->perm, (const double2 *)c->rec,
+                                                    p->mass != nullptr, c->xs, c->ys, c->zs,
+                                                    c->vxs, c->vys, c->vzs, c->ms, c->ids, c->sts);
     c->lv = tree_levels(n);
     const TreeLevels &lv = c->lv;
     const int64_t nleaf = lv.cnt[0];
