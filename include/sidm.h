@@ -202,6 +202,16 @@ sidm_status sidm_build_tree(sidm_ctx *ctx, const sidm_particles *p);
  * other requirements as for sidm_build_tree. */
 sidm_status sidm_refit_tree(sidm_ctx *ctx, const sidm_particles *p);
 
+/* The tree's particle order (sec. 4.3: particles sorted along the
+ * space-filling curve): order[s] = caller index of the particle at sorted
+ * position s, for the n particles of the last sidm_build_tree -- ascending
+ * 48-bit Morton keys of the positions quantised to 16 bits an axis over the
+ * bounding box (over [0, box) when periodic), equal keys in caller order.
+ * order: caller-owned device array of n int32.  Asynchronous on the
+ * context's stream; SIDM_E_STATE before the first sidm_build_tree.  For
+ * callers that keep their particles in tree order, and for checking the sort. */
+sidm_status sidm_tree_order(sidm_ctx *ctx, int32_t *order);
+
 /* For every active particle a (0 <= a < n_active, active[a] a particle
  * index, no duplicates): ngb[a*n_ngb + s] = its s-th nearest neighbour
  * (ascending (r^2, id)), h[a] = distance of the (n_ngb+1)-th. */

@@ -87,7 +87,7 @@ class Timing(ctypes.Structure):
 # Every symbol include/sidm.h declares (tests check the library exports them).
 EXPORTS = ["sidm_footprint", "sidm_create", "sidm_destroy", "sidm_set_stream", "sidm_reconfigure",
            "sidm_last_error", "sidm_status_string", "sidm_build_tree", "sidm_find_ngb",
-           "sidm_refit_tree", "sidm_scatter_step", "sidm_pair_timestep",
+           "sidm_refit_tree", "sidm_tree_order", "sidm_scatter_step", "sidm_pair_timestep",
            "sidm_advance_hernquist", "sidm_drift",
            "sidm_find_overlap", "sidm_scatter_overlap", "sidm_pair_timestep_overlap",
            "sidm_overlap_table",
@@ -117,6 +117,7 @@ def lib():
         L.sidm_status_string.restype = ctypes.c_char_p
         L.sidm_build_tree.argtypes = [P, ctypes.POINTER(Particles)]
         L.sidm_refit_tree.argtypes = [P, ctypes.POINTER(Particles)]
+        L.sidm_tree_order.argtypes = [P, P]
         L.sidm_find_ngb.argtypes = [P, P, i64, P, P]
         L.sidm_scatter_step.argtypes = [P, ctypes.POINTER(Particles), P, i64, P, P, P, u64, u32, P]
         L.sidm_pair_timestep.argtypes = [P, P, i64, P, P, P]
@@ -254,6 +255,8 @@ class Context:
                       _ptr(arrs["id"]), _ptr(arrs["state"]), int(x.shape[0]))
         self._particles = (p, arrs)      # keep tensors alive while the snapshot is in use
         self._check(getattr(lib(), fn)(self._h, ctypes.byref(p)), fn)
+        if fn == "sidm_build_tree":
+            self._n_sorted = int(x.shape[0])
 
     def find_ngb(self, active, ngb, h):
         torch = self._torch
@@ -334,6 +337,15 @@ class Context:
                                                      int(active.shape[0]), int(ngb.shape[1]),
                                                      _ptr(ngb), _ptr(count), _ptr(dt_sidm)),
                     "sidm_pair_timestep_overlap")
+
+    def tree_order(self, order):
+        """order[s] = caller index of the particle at sorted position s (the
+        n particles of the last build_tree; a device int32 tensor of n)."""
+        self._dev(order, self._torch.int32, "order")
+        n = getattr(self, "_n_sorted", 0)
+        if order.numel() < n:
+            raise ValueError(f"order: need {n} entries, got {order.numel()}")
+        self._check(lib().sidm_tree_order(self._h, _ptr(order)), "sidm_tree_order")
 
     def overlap_table(self) -> np.ndarray:
         out = np.zeros((OVERLAP_NA + 1, OVERLAP_NR + 1), dtype=np.float64)

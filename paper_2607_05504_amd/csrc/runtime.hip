@@ -410,6 +410,23 @@ sidm_status sidm_build_tree(sidm_ctx *c, const sidm_particles *p)
     return SIDM_OK;
 }
 
+sidm_status sidm_tree_order(sidm_ctx *c, int32_t *order)
+{
+    if (!c) return SIDM_E_INVAL;
+    if (!order) {
+        set_err(c, "tree_order: NULL order");
+        return SIDM_E_INVAL;
+    }
+    if (c->sorted_n <= 0) {
+        set_err(c, "tree_order: sidm_build_tree has not been called");
+        return SIDM_E_STATE;
+    }
+    hipError_t e = hipMemcpyAsync(order, c->perm, (size_t)c->sorted_n * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "tree_order");
+    return SIDM_OK;
+}
+
 static sidm_status check_active(sidm_ctx *c, const int32_t *active, int64_t n_active, const char *who)
 {
     if (!c->tree_ok) {

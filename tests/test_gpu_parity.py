@@ -242,3 +242,54 @@ def test_per_particle_masses(kind):
         w.delta * float((mm * s.astype(np.float64)).sum())
     e0 = e(w.vx, w.vy, w.vz, w.state)
     assert abs(e(g["vx"], g["vy"], g["vz"], g["state"]) - e0) <= 1e-12 * e0
+
+
+def _morton_keys(x, y, z, periodic, box):
+    """48-bit Morton keys as the tree defines them (16 bits an axis over the
+    bounding box, or over [0, box) when periodic), computed here on the CPU."""
+    def spread(v):
+        v = v.astype(np.uint64) & np.uint64(0xffff)
+        r = np.zeros_like(v)
+        for b in range(16):
+            r |= ((v >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b)
+        return r
+    q = []
+    for c in (x, y, z):
+        lo, hi = (0.0, box) if periodic else (c.min(), c.max())
+        ext = hi - lo
+        scale = 65536.0 / ext if ext > 0 else 0.0
+        f = (c - lo) * scale
+        q.append(np.where(f > 0, np.where(f >= 65535.0, 65535.0, np.floor(f)), 0.0).astype(np.uint64))
+    return (spread(q[0]) << np.uint64(2)) | (spread(q[1]) << np.uint64(1)) | spread(q[2])
+
+
+@pytest.mark.parametrize("case", ["halo 3e5", "uniform 2e5 periodic", "ragged 5000+7",
+                                  "halo 3e6"])
+def test_tree_order_is_a_stable_morton_sort(case):
+    """The radix sort: the tree's order is a permutation, ascending in the
+    Morton key, equal keys in caller order -- over 3 sort tiles of 2048 keys
+    (the last one ragged), about a hundred and about fifteen hundred."""
+    import torch
+    from paper_2607_05504_amd import Context, runner
+    w = {"halo 3e5": lambda: W.hernquist_halo(300_000, ic_seed=61),
+         "uniform 2e5 periodic": lambda: W.uniform_box(200_000, ic_seed=62),
+         "ragged 5000+7": lambda: W.uniform_box(5007, ic_seed=63),
+         "halo 3e6": lambda: W.hernquist_halo(3_000_000, ic_seed=64)}[case]()
+    _announce(f"tree order {case} n={w.n}")
+    ds = runner.upload(w, "cuda")
+    ctx = Context(runner.config_for(w), w.n, 1)
+    ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state,
+                   m_scalar=ds.mass)
+    order = torch.empty(w.n, dtype=torch.int32, device="cuda")
+    ctx.tree_order(order)
+    st = ctx.sync()
+    ctx.close()
+    assert st["error"] == 0
+    o = order.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(o), np.arange(w.n))
+    k = _morton_keys(w.x, w.y, w.z, w.periodic, w.box)[o]
+    assert np.all(k[1:] >= k[:-1])
+    ties = k[1:] == k[:-1]
+    assert np.all(o[1:][ties] > o[:-1][ties])
+    ref = np.argsort(_morton_keys(w.x, w.y, w.z, w.periodic, w.box), kind="stable")
+    assert np.array_equal(o, ref)
