@@ -326,11 +326,23 @@ sidm_status sidm_drift(sidm_ctx *ctx, double *x, double *y, double *z, const dou
 sidm_status sidm_sync(sidm_ctx *ctx, sidm_stats *out);
 
 /* ---- Measurement (not part of the method) --------------------------------
- * When enabled, the context brackets its main kernels with HIP events on its
- * stream (up to 256 launches of each between two reads).  sidm_timing_read
- * waits for the stream, reports the mean device time in milliseconds of the
- * launches since the previous read (or enable) and starts a new window.
- * Disabled by default. */
+ * sidm_timing_enable(ctx, phases) brackets the launches of the phases in the
+ * mask (SIDM_TIMING_*; 0 turns timing off) with HIP events on the context's
+ * stream, up to 256 launches of each between two reads; it restarts the
+ * window.  Each bracketed phase leaves the GPU idle for a few microseconds at
+ * its two ends, so time only the phases needed.  sidm_timing_read waits for
+ * the stream, reports the mean device time in milliseconds of the launches
+ * since the previous read (or enable) of each timed phase (0 for the others)
+ * and starts a new window.  Disabled by default; a mask with other bits is
+ * SIDM_E_INVAL. */
+#define SIDM_TIMING_TREE 1
+#define SIDM_TIMING_MAP 2
+#define SIDM_TIMING_KNN 4
+#define SIDM_TIMING_EVAL 8
+#define SIDM_TIMING_RESOLVE 16
+#define SIDM_TIMING_TIMESTEP 32
+#define SIDM_TIMING_OVERLAP 64
+#define SIDM_TIMING_ALL 127
 typedef struct {
     int32_t samples;      /* neighbour-search launches averaged                    */
     int32_t pad;
@@ -343,7 +355,7 @@ typedef struct {
     double overlap_ms;    /* sidm_find_overlap: h update, node h_max and the walk  */
 } sidm_timing;
 
-sidm_status sidm_timing_enable(sidm_ctx *ctx, int on);
+sidm_status sidm_timing_enable(sidm_ctx *ctx, int phases);
 sidm_status sidm_timing_read(sidm_ctx *ctx, sidm_timing *out);
 
 #ifdef __cplusplus

@@ -84,6 +84,10 @@ class Timing(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+# phase masks of Context.timing_enable (SIDM_TIMING_* in include/sidm.h)
+TIMING_TREE, TIMING_MAP, TIMING_KNN, TIMING_EVAL = 1, 2, 4, 8
+TIMING_RESOLVE, TIMING_TIMESTEP, TIMING_OVERLAP, TIMING_ALL = 16, 32, 64, 127
+
 # Every symbol include/sidm.h declares (tests check the library exports them).
 EXPORTS = ["sidm_footprint", "sidm_create", "sidm_destroy", "sidm_set_stream", "sidm_reconfigure",
            "sidm_last_error", "sidm_status_string", "sidm_build_tree", "sidm_find_ngb",
@@ -374,8 +378,13 @@ class Context:
         self._check(lib().sidm_drift(self._h, _ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy),
                                      _ptr(vz), int(x.shape[0]), float(dt)), "sidm_drift")
 
-    def timing_enable(self, on: bool = True):
-        self._check(lib().sidm_timing_enable(self._h, int(bool(on))), "sidm_timing_enable")
+    def timing_enable(self, phases=True):
+        """Time the phases in the mask (TIMING_*); True for all, False or 0 for none."""
+        if phases is True:
+            phases = TIMING_ALL
+        elif phases is False:
+            phases = 0
+        self._check(lib().sidm_timing_enable(self._h, int(phases)), "sidm_timing_enable")
 
     def timing_read(self) -> dict:
         t = Timing()

@@ -250,10 +250,14 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
     return SIDM_OK;
 }
 
-sidm_status sidm_timing_enable(sidm_ctx *c, int on)
+sidm_status sidm_timing_enable(sidm_ctx *c, int phases)
 {
     if (!c) return SIDM_E_INVAL;
-    if (on && !c->timing) {
+    if (phases & ~SIDM_TIMING_ALL) {
+        set_err(c, "timing_enable: unknown phase bits 0x%x", (unsigned)phases);
+        return SIDM_E_INVAL;
+    }
+    if (phases && !c->timing) {
         for (int p = 0; p < SIDM_PHASES; ++p)
             for (int r = 0; r < SIDM_TIMING_RING; ++r)
                 for (int b = 0; b < 2; ++b)
@@ -263,7 +267,7 @@ sidm_status sidm_timing_enable(sidm_ctx *c, int on)
                     }
     }
     for (int p = 0; p < SIDM_PHASES; ++p) c->ev_count[p] = 0;
-    c->timing = on ? 1 : 0;
+    c->timing = phases;
     return SIDM_OK;
 }
 

@@ -144,7 +144,7 @@ struct sidm_ctx {
     unsigned long long *adv_min;   // served form: smallest per-pair bound of a step
     // opt-in event timing of the main kernels: up to SIDM_TIMING_RING launches
     // of each phase are bracketed between two sidm_timing_read calls
-    int timing;
+    int timing;              // mask of the timed phases (bit PH_*)
     hipEvent_t ev[SIDM_PHASES][SIDM_TIMING_RING][2];
     int ev_count[SIDM_PHASES];
     void *dev_base;          // the one device allocation every buffer above lives in
@@ -378,15 +378,18 @@ __device__ __forceinline__ double unit_from_word(uint64_t w)
 // phases timed by sidm_timing
 enum { PH_TREE = 0, PH_MAP = 1, PH_KNN = 2, PH_EVAL = 3, PH_RESOLVE = 4, PH_TIMESTEP = 5,
        PH_OVERLAP = 6 };
+static_assert((1 << PH_TREE) == SIDM_TIMING_TREE && (1 << PH_KNN) == SIDM_TIMING_KNN &&
+                  (1 << PH_OVERLAP) == SIDM_TIMING_OVERLAP && (1 << SIDM_PHASES) - 1 == SIDM_TIMING_ALL,
+              "phase bits of sidm_timing_enable");
 
 inline void phase_begin(sidm_ctx *c, int ph)
 {
-    if (c->timing && c->ev_count[ph] < SIDM_TIMING_RING)
+    if (((c->timing >> ph) & 1) && c->ev_count[ph] < SIDM_TIMING_RING)
         (void)hipEventRecord(c->ev[ph][c->ev_count[ph]][0], c->stream);
 }
 inline void phase_end(sidm_ctx *c, int ph)
 {
-    if (c->timing && c->ev_count[ph] < SIDM_TIMING_RING) {
+    if (((c->timing >> ph) & 1) && c->ev_count[ph] < SIDM_TIMING_RING) {
         (void)hipEventRecord(c->ev[ph][c->ev_count[ph]][1], c->stream);
         c->ev_count[ph]++;
     }

@@ -167,3 +167,42 @@ def test_active_mapping_reuse_rules():
         assert torch.equal(a, b)
     assert st["n_events"] == st2["n_events"] > 0
     ctx.close()
+
+
+def test_timing_mask_times_only_the_chosen_phases():
+    """sidm_timing_enable takes a mask of phases: the ones in it report a
+    mean launch time, the others 0; unknown bits are refused."""
+    from paper_2607_05504_amd import (SIDM_E_INVAL, TIMING_ALL, TIMING_KNN, TIMING_TIMESTEP,
+                                      SidmError)
+    _announce("timing mask")
+    w, ds, ctx, out = _setup(n_active=1500)
+    with pytest.raises(SidmError) as e:
+        ctx.timing_enable(TIMING_ALL + 1)
+    assert e.value.status == SIDM_E_INVAL
+
+    def step():
+        ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state,
+                       m_scalar=ds.mass)
+        ctx.find_ngb(ds.active, out.ngb, out.h)
+        ctx.scatter_step(ds.active, out.ngb, out.h, ds.dt, w.seed, w.step, reuse_active=True)
+        ctx.pair_timestep(ds.active, out.ngb, out.h, out.dt_sidm, reuse_active=True)
+
+    ctx.timing_enable(TIMING_KNN | TIMING_TIMESTEP)
+    step()
+    step()
+    t = ctx.timing_read()
+    assert t["samples"] == 2
+    assert t["knn_ms"] > 0 and t["timestep_ms"] > 0
+    assert t["tree_ms"] == 0 and t["map_ms"] == 0 and t["eval_ms"] == 0
+    assert t["resolve_ms"] == 0 and t["overlap_ms"] == 0
+    ctx.timing_enable(TIMING_ALL)
+    step()
+    t = ctx.timing_read()
+    assert min(t[k] for k in ("tree_ms", "map_ms", "knn_ms", "eval_ms", "resolve_ms",
+                              "timestep_ms")) > 0
+    ctx.timing_enable(0)
+    step()
+    t = ctx.timing_read()
+    assert t["samples"] == 0 and t["knn_ms"] == 0
+    assert ctx.sync()["error"] == 0
+    ctx.close()
