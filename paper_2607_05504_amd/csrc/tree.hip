@@ -188,13 +188,16 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *hist, const uint32
 
 // Stable scatter: items are ranked in tile order (round-major, then wave,
 // then lane) within their digit.  The tile is first reordered by digit in LDS
-// and then written out, so a digit's items go to consecutive addresses.
+// and then written out, so a digit's items go to consecutive addresses.  The
+// last pass (perm != NULL) writes the index maps instead of keys and values:
+// perm[pos] = the caller index that lands at pos, inv[that index] = pos.
 constexpr int kRounds = SIDM_SORT_TILE / 256;
 
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restrict__ kin,
                                                        const int32_t *__restrict__ vin,
                                                        uint64_t *kout, int32_t *vout, int64_t n,
-                                                       int shift, const uint32_t *hist, int nblk)
+                                                       int shift, const uint32_t *hist, int nblk,
+                                                       int32_t *perm, int32_t *inv)
 {
     __shared__ uint32_t goff[256];
     __shared__ uint32_t run[256];
@@ -264,23 +267,18 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restric
         const uint64_t k = s_key[i];
         const uint32_t d = (uint32_t)(k >> shift) & 255u;
         const uint32_t pos = goff[d] + (uint32_t)i - wc[2][d];
-        kout[pos] = k;
-        vout[pos] = s_val[i];
+        if (perm) {
+            const int32_t o = s_val[i];
+            perm[pos] = o;
+            inv[o] = (int32_t)pos;
+        } else {
+            kout[pos] = k;
+            vout[pos] = s_val[i];
+        }
     }
 }
 
 // --- the Morton-ordered snapshot ------------------------------------------------------
-// perm (sorted -> caller) and its inverse
-__global__ void k_inverse(int64_t n, const int32_t *__restrict__ order, int32_t *perm, int32_t *inv)
-{
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t o = order[s];
-        perm[s] = o;
-        inv[o] = (int32_t)s;
-    }
-}
-
 // The snapshot in two passes.  k_pack writes each caller particle as one
 // 64-byte record (x y z vx vy vz m, id | state << 32), reading the caller's
 // arrays in their order; k_gather_rec then fills sorted slot s from record
@@ -557,12 +555,13 @@ hipError_t launch_build_tree(sidm_ctx *c, const sidm_particles *p)
     for (int shift = 0; shift < 48; shift += 8) {
         if (shift > 0) k_radix_hist<<<nblk, 256, 0, s>>>(kin, n, shift, c->hist, nblk);
         k_radix_scan<<<256, 256, 0, s>>>(c->hist, c->dtot + (shift / 8) * 256, nblk);
-        k_radix_scatter<<<nblk, 256, 0, s>>>(kin, vin, kout, vout, n, shift, c->hist, nblk);
+        const bool last = shift == 40;
+        k_radix_scatter<<<nblk, 256, 0, s>>>(kin, vin, kout, vout, n, shift, c->hist, nblk,
+                                             last ? c->perm : nullptr, last ? c->inv : nullptr);
         uint64_t *tk = kin; kin = kout; kout = tk;
         int32_t *tv = vin; vin = vout; vout = tv;
     }
-    // six passes: the sorted order is back in key0/val0
-    k_inverse<<<grid_for(n), kBlock, 0, s>>>(n, vin, c->perm, c->inv);
+    // the last of the six passes wrote perm and inv
     return launch_refit_tree(c, p);
 }
 
