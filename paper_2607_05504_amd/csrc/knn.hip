@@ -465,16 +465,33 @@ void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
         if (tl == 0) stk[0] = (A.lv.nlev - 1) << SIDM_LEVEL_SHIFT;
         sp = 1;
     }
-    uint64_t lk[KP];
+    // the list's entries first, then their boxes, so that the requests of
+    // each stage go out together
+    int32_t lf[KP];
 #pragma unroll
     for (int q = 0; q < KP; ++q) {
         const int t = q * TS + tl;
-        lk[q] = ~0ull;
-        if (!walk && t < nl) {
-            const int32_t leaf = lst[t];
-            const double g = node_gap2<PERIODIC>(A.nodes, leaf, px, py, pz, box);
-            lk[q] = ((uint64_t)__float_as_uint(__double2float_rd(g)) << 32) | (uint32_t)leaf;
-        }
+        lf[q] = (!walk && t < nl) ? lst[t] : -1;
+    }
+    // (an absent entry reads node 0 and is masked, so that no branch holds
+    // the requests back); the gap as node_gap2 computes it
+    double lbx[KP][6];
+#pragma unroll
+    for (int q = 0; q < KP; ++q) {
+        const double *nb = A.nodes + (int64_t)(lf[q] >= 0 ? lf[q] : 0) * 6;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) lbx[q][d] = nb[d];
+    }
+    uint64_t lk[KP];
+#pragma unroll
+    for (int q = 0; q < KP; ++q) {
+        const double gx = axis_gap<PERIODIC>(lbx[q][0], lbx[q][3], px, box);
+        const double gy = axis_gap<PERIODIC>(lbx[q][1], lbx[q][4], py, box);
+        const double gz = axis_gap<PERIODIC>(lbx[q][2], lbx[q][5], pz, box);
+        const double g = lbx[q][0] <= lbx[q][3] ? (gx * gx + gy * gy) + gz * gz : INFINITY;
+        lk[q] = lf[q] >= 0
+                    ? ((uint64_t)__float_as_uint(__double2float_rd(g)) << 32) | (uint32_t)lf[q]
+                    : ~0ull;
     }
     double T = A.tb[bb];
     wave_sync();

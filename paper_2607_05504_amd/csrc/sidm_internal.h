@@ -209,13 +209,15 @@ template <bool PERIODIC>
 __device__ __forceinline__ double node_gap2(const double *__restrict__ nodes, int64_t g, double px,
                                             double py, double pz, double box)
 {
+    // branch-free, so that the six bounds are requested together (an early
+    // return for an empty box made the compiler wait for lo.x and hi.x first)
     const double *nb = nodes + g * 6;
     const double lx = nb[0], ly = nb[1], lz = nb[2], hx = nb[3], hy = nb[4], hz = nb[5];
-    if (!(lx <= hx)) return INFINITY;
     double gx = axis_gap<PERIODIC>(lx, hx, px, box);
     double gy = axis_gap<PERIODIC>(ly, hy, py, box);
     double gz = axis_gap<PERIODIC>(lz, hz, pz, box);
-    return (gx * gx + gy * gy) + gz * gz;
+    const double g2 = (gx * gx + gy * gy) + gz * gz;
+    return lx <= hx ? g2 : INFINITY;
 }
 
 // XCD-aware block order.  The 8 XCDs of an MI355X each have their own L2, and
