@@ -121,11 +121,13 @@ typedef struct {
     double flag_band;     /* evaluations with |P - u| < flag_band are flagged (1e-9)      */
     double band_r2;       /* mixed form: relative r^2 band rechecked in FP64              */
     double band_p;        /* mixed form: relative |P - u| band rechecked in FP64          */
-    /* SIDM_XSEC_TABLE (a tabulated sigma(w)/m, as for a velocity-dependent model
-     * given as a table, sec. 6): xsec_n nodes (2..SIDM_XSEC_TABLE_MAX) at
-     * strictly increasing speeds xsec_w > 0 (typically log-spaced) with values
-     * xsec_sigma >= 0; between nodes sigma is linear in w, outside the range it
-     * is the end value.  HOST pointers, copied into the context by sidm_create
+    /* SIDM_XSEC_TABLE (a tabulated sigma(w)/m of the pair's relative speed,
+     * sec. 4.2, as the velocity-dependent models of sec. 6 are given):
+     * xsec_n nodes (2..SIDM_XSEC_TABLE_MAX) at strictly increasing speeds
+     * xsec_w > 0 with values xsec_sigma >= 0; between the nodes w_k <= w <
+     * w_k+1 sigma is linear in ln w (the interpolation in log velocity the
+     * paper uses), sigma_k + (ln w - ln w_k) / (ln w_k+1 - ln w_k)
+     * (sigma_k+1 - sigma_k); outside the range it is the end value.  HOST pointers, copied into the context by sidm_create
      * and sidm_reconfigure (not read afterwards); ignored for other xsec. */
     int32_t xsec_n;
     const double *xsec_w;

@@ -191,9 +191,10 @@ int oref_set_table(const double *w, const double *s, int n)
     return OREF_OK;
 }
 
-/* sigma/m of the table at speed w: the end value outside the nodes, else the
- * straight line through the two nodes that bracket w (tw[k] <= w < tw[k+1]),
- * found here by a linear scan */
+/* sigma/m of the table at speed w (sec. 4.2: linear interpolation in log
+ * velocity): the end value outside the nodes, else the straight line in ln w
+ * through the two nodes that bracket w (tw[k] <= w < tw[k+1]), found here by
+ * a linear scan */
 static double oref_sigma_table(double w)
 {
     const int n = oref_tn;
@@ -201,7 +202,8 @@ static double oref_sigma_table(double w)
     if (!(w < oref_tw[n - 1])) return oref_ts[n - 1];
     int k = 0;
     while (!(oref_tw[k + 1] > w)) ++k;
-    const double f = (w - oref_tw[k]) / (oref_tw[k + 1] - oref_tw[k]);
+    const double lo = log(oref_tw[k]), hi = log(oref_tw[k + 1]);
+    const double f = (log(w) - lo) / (hi - lo);
     return oref_ts[k] + f * (oref_ts[k + 1] - oref_ts[k]);
 }
 

@@ -6,6 +6,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <cmath>
+
 #include "sidm_internal.h"
 
 namespace {
@@ -74,6 +76,7 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(dstats, 1, DevStats);
     ADD(derr, 1, unsigned int);
     ADD(xt_w, SIDM_XSEC_TABLE_MAX, double); ADD(xt_s, SIDM_XSEC_TABLE_MAX, double);
+    ADD(xt_lw, SIDM_XSEC_TABLE_MAX, double);
     ADD(adv_min, 1, unsigned long long);
     if (c->cfg.estimator == SIDM_EST_OVERLAP) {
         ADD(hs, N, double);
@@ -169,8 +172,11 @@ static hipError_t copy_table(sidm_ctx *c)
         return hipSuccess;
     }
     const size_t b = (size_t)c->cfg.xsec_n * sizeof(double);
+    double lw[SIDM_XSEC_TABLE_MAX];
+    for (int q = 0; q < c->cfg.xsec_n; ++q) lw[q] = std::log(c->cfg.xsec_w[q]);
     hipError_t e = hipMemcpyAsync(c->xt_w, c->cfg.xsec_w, b, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->xt_s, c->cfg.xsec_sigma, b, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->xt_lw, lw, b, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     c->cfg.xsec_w = c->cfg.xsec_sigma = nullptr;
     return e;

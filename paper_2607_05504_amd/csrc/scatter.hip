@@ -57,7 +57,7 @@ struct StepArgs {
     const double *nodes;
     double band_p;
     // tabulated cross-section (SIDM_XSEC_TABLE)
-    const double *xt_w, *xt_s;
+    const double *xt_w, *xt_s, *xt_lw;
     int xt_n;
     // candidate rows: stride entries a row (n_ngb for the one-sided
     // estimator); the overlap estimator's rows hold count[a] partners and
@@ -72,7 +72,7 @@ struct StepArgs {
 
 __device__ __forceinline__ double sigma_of(const StepArgs &A, double w)
 {
-    if (A.xsec == SIDM_XSEC_TABLE) return xsec_table(w, A.xt_w, A.xt_s, A.xt_n);
+    if (A.xsec == SIDM_XSEC_TABLE) return xsec_table(w, A.xt_w, A.xt_lw, A.xt_s, A.xt_n);
     return xsec_sigma(w, A.xsec, A.s0, A.w0);
 }
 
@@ -707,7 +707,7 @@ StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const dou
     A.k = c->cfg.n_ngb; A.periodic = c->cfg.periodic; A.xsec = c->cfg.xsec;
     A.model = c->cfg.model; A.has_mass = c->has_mass;
     A.xo = c->xo; A.yo = c->yo; A.zo = c->zo; A.nodes = c->nodes; A.band_p = c->cfg.band_p;
-    A.xt_w = c->xt_w; A.xt_s = c->xt_s; A.xt_n = c->cfg.xsec_n;
+    A.xt_w = c->xt_w; A.xt_s = c->xt_s; A.xt_lw = c->xt_lw; A.xt_n = c->cfg.xsec_n;
     A.stride = A.k; A.cnt = nullptr; A.hsrt = c->hs; A.gtab = c->gtab;
     return A;
 }

@@ -136,6 +136,7 @@ struct sidm_ctx {
     DevStats *dstats;
     unsigned int *derr;
     double *xt_w, *xt_s;     // tabulated cross-section nodes [SIDM_XSEC_TABLE_MAX]
+    double *xt_lw;           //   and the natural logarithms of their speeds
     // overlap estimator only: every particle's h in Morton order, the largest
     // h below every tree node, and the ghat table
     double *hs, *hmax, *gtab;
@@ -265,7 +266,10 @@ __device__ __forceinline__ double cubic_spline(double r, double h)
 
 // Tabulated sigma(w)/m: linear in w between nodes tw[0..n) (increasing), the
 // end values outside; the node pair is found by bisection.
-__device__ __forceinline__ double xsec_table(double w, const double *tw, const double *ts, int n)
+// tabulated sigma/m: linear in ln w between the bracketing nodes (tlw holds
+// the nodes' ln w), the end values outside
+__device__ __forceinline__ double xsec_table(double w, const double *tw, const double *tlw,
+                                             const double *ts, int n)
 {
     if (!(w > tw[0])) return ts[0];
     if (!(w < tw[n - 1])) return ts[n - 1];
@@ -274,7 +278,7 @@ __device__ __forceinline__ double xsec_table(double w, const double *tw, const d
         const int mid = (lo + hi) >> 1;
         if (tw[mid] <= w) lo = mid; else hi = mid;
     }
-    const double f = (w - tw[lo]) / (tw[hi] - tw[lo]);
+    const double f = (log(w) - tlw[lo]) / (tlw[hi] - tlw[lo]);
     return ts[lo] + f * (ts[hi] - ts[lo]);
 }
 

@@ -27,11 +27,14 @@ def gpu_step(w, with_info=True, precision=FP64, ctx=None, seed=None, step=None, 
     return res
 
 
-def assert_parity(w, g, ref, vel_rtol=1e-12, dt_rtol=1e-12, mixed=False):
+def assert_parity(w, g, ref, vel_rtol=1e-12, dt_rtol=1e-12, mixed=False, p_rtol=0.0):
     """The parity bar: neighbour sets and h bit-exact; decisions bit-exact
     except on flagged candidates; velocities and dt to 1e-12 relative.
     ``mixed``: the FP32 form, whose unrechecked probabilities are FP32 values,
-    so the largest P is compared to 1e-5 and the P >= 1 count is not."""
+    so the largest P is compared to 1e-5 and the P >= 1 count is not.
+    ``p_rtol``: the largest P to that relative tolerance instead of bit for
+    bit (a tabulated cross-section takes ln w from the device's log, the
+    oracle from the C library's, which may differ in the last bit)."""
     assert np.array_equal(g["ngb"], ref["ngb"]), "neighbour lists differ"
     assert np.array_equal(g["h"], ref["h"]), "smoothing lengths differ"
     gi, ri = g["info"], ref["info"]
@@ -60,5 +63,5 @@ def assert_parity(w, g, ref, vel_rtol=1e-12, dt_rtol=1e-12, mixed=False):
         assert abs(gs["max_p"] - rs["max_p"]) <= 1e-5 * rs["max_p"]
     else:
         assert gs["n_p_ge_1"] == rs["n_p_ge_1"]
-        assert gs["max_p"] == rs["max_p"]
+        assert abs(gs["max_p"] - rs["max_p"]) <= p_rtol * rs["max_p"]
     assert gs["error"] == 0

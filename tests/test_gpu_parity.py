@@ -124,8 +124,10 @@ def test_determinism_and_permutation():
 
 @pytest.mark.parametrize("case", ["halo_table", "box_table_mixed"])
 def test_tabulated_cross_section(case):
-    """sigma(w)/m given as a 64-node table (linear in w between log-spaced
-    nodes): the same parity bar as the closed-form models."""
+    """sigma(w)/m given as a 64-node table (linear in ln w between
+    log-spaced nodes): the same parity bar as the closed-form models, except
+    that ln w comes from two libraries' log, so probabilities and the
+    timestep agree to 1e-13 rather than bit for bit."""
     from paper_2607_05504_amd import MIXED, FP64
     if case == "halo_table":
         w = W.with_table(W.hernquist_bins(W.hernquist_halo(20000, ic_seed=206, philox_seed=16),
@@ -139,7 +141,7 @@ def test_tabulated_cross_section(case):
     _announce(f"tabulated cross-section {case} n={w.n} active={w.n_active}")
     ref = oracle.full_step(w)
     g = gpu_step(w, precision=prec)
-    assert_parity(w, g, ref, mixed=(prec == MIXED))
+    assert_parity(w, g, ref, mixed=(prec == MIXED), p_rtol=1e-13)
     assert g["stats"]["n_events"] > 0
 
 

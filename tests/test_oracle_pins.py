@@ -443,9 +443,10 @@ def test_drift_wraps_into_the_box():
 # Tabulated cross-section
 # ---------------------------------------------------------------------------
 
-def test_table_interpolation_is_piecewise_linear_in_w():
-    """At the nodes the table's values, between them the straight line (checked
-    against numpy's linear interpolation), the end values outside."""
+def test_table_interpolation_is_piecewise_linear_in_log_w():
+    """At the nodes the table's values, between them the straight line in ln w
+    (sec. 4.2: linear interpolation in log velocity; checked against numpy's
+    linear interpolation in ln w), the end values outside."""
     tw, ts = W.yukawa_table(3.0, 0.5, n_nodes=40)
     oracle.set_table(tw, ts)
     for v, s in zip(tw, ts):
@@ -453,26 +454,45 @@ def test_table_interpolation_is_piecewise_linear_in_w():
     rng = np.random.Generator(np.random.PCG64(12))
     ws = np.exp(rng.uniform(math.log(tw[0]), math.log(tw[-1]), 2000))
     got = np.array([oracle.sigma(float(v), W.XSEC_TABLE, 0.0, 1.0) for v in ws])
-    np.testing.assert_allclose(got, np.interp(ws, tw, ts), rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(got, np.interp(np.log(ws), np.log(tw), ts), rtol=1e-12,
+                               atol=1e-15)
     assert oracle.sigma(0.0, W.XSEC_TABLE, 0.0, 1.0) == ts[0]
     assert oracle.sigma(float(tw[-1]) * 10, W.XSEC_TABLE, 0.0, 1.0) == ts[-1]
 
 
+def test_table_reproduces_a_function_linear_in_log_w():
+    """sigma = A + B ln w, tabulated on 12 irregular nodes, comes back exactly
+    (to rounding) at any speed in range: interpolation in log velocity is exact
+    for it, where interpolation in w would be off at second order (about 1% of
+    B here)."""
+    A, B = 8.0, -1.2
+    tw = np.array([0.01, 0.013, 0.05, 0.2, 0.21, 0.9, 1.7, 3.0, 8.0, 20.0, 55.0, 90.0])
+    ts = A + B * np.log(tw)
+    oracle.set_table(tw, ts)
+    rng = np.random.Generator(np.random.PCG64(13))
+    ws = np.exp(rng.uniform(math.log(tw[0]), math.log(tw[-1]), 3000))
+    got = np.array([oracle.sigma(float(v), W.XSEC_TABLE, 0.0, 1.0) for v in ws])
+    np.testing.assert_allclose(got, A + B * np.log(ws), rtol=1e-12, atol=1e-13)
+    lin = np.interp(ws, tw, ts)
+    assert np.max(np.abs(lin - (A + B * np.log(ws)))) > 0.01 * abs(B)
+
+
 def test_dense_table_reproduces_the_model():
     """A 256-node table of the Yukawa-like model agrees with the closed form
-    to within the linear-interpolation error bound max|sigma''| h^2 / 8."""
+    to within the bound of linear interpolation in x = ln w,
+    max|d^2 sigma/dx^2| dx^2 / 8."""
     s0, w0 = 2.0, 0.5
     tw, ts = W.yukawa_table(s0, w0, n_nodes=256)
     oracle.set_table(tw, ts)
     ws = np.logspace(-2.9, 1.9, 3000)
     got = np.array([oracle.sigma(float(v), W.XSEC_TABLE, 0.0, 1.0) for v in ws])
     exact = s0 / (1.0 + (ws / w0) ** 2) ** 2
-    k = np.searchsorted(tw, ws) - 1
-    h = tw[k + 1] - tw[k]
-    # |sigma''| <= 12 s0 / w0^2 for this model
-    bound = 12.0 * s0 / w0 ** 2 * h ** 2 / 8.0
-    assert np.all(np.abs(got - exact) <= bound + 1e-15)
-    assert np.max(np.abs(got - exact) / exact) < 1e-2     # 0.5% in the w^-4 tail
+    # d^2 sigma / dx^2 = s0 y^2 (16 y^2 - 8) / (1 + y^2)^4 with y = w / w0
+    y = np.logspace(-6, 6, 200001)
+    sxx = np.max(np.abs(s0 * y ** 2 * (16 * y ** 2 - 8) / (1 + y ** 2) ** 4))
+    dx = np.max(np.diff(np.log(tw)))
+    assert np.all(np.abs(got - exact) <= sxx * dx ** 2 / 8.0 + 1e-15)
+    assert np.max(np.abs(got - exact) / exact) < 1e-2     # 0.4% in the w^-4 tail
 
 
 # ---------------------------------------------------------------------------
