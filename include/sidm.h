@@ -138,6 +138,17 @@ typedef struct {
      * node, the ghat table; 8 bytes a particle more) and requires
      * precision SIDM_FP64. */
     int32_t estimator;
+    /* Stored -> physical units (sec. 4.2: cosmological runs store comoving
+     * coordinates and velocities and evaluate the pair rate in physical
+     * units).  Separations and smoothing lengths are multiplied by
+     * len_to_phys (the scale factor a for comoving positions) and relative
+     * speeds by vel_to_phys (the factor of the caller's velocity variable)
+     * wherever W, g_ij, sigma(w), P, the two-state energy balance and the
+     * timestep use them; the search and the kick stay in stored units (the
+     * kick changes no speed but through eps).  dt is taken as given.  0 (or
+     * 1) for physical storage; otherwise > 0 and finite (SIDM_E_INVAL). */
+    double len_to_phys;
+    double vel_to_phys;
 } sidm_config;
 
 typedef struct {

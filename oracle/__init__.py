@@ -78,6 +78,8 @@ def lib():
         L.oref_kick_pair.restype = None
         L.oref_set_table.argtypes = [P, P, i32]
         L.oref_set_table.restype = i32
+        L.oref_set_units.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.oref_set_units.restype = i32
         L.oref_overlap_exact.argtypes = [dbl, dbl, dbl]
         L.oref_overlap_exact.restype = dbl
         L.oref_overlap_g.argtypes = [dbl, dbl, dbl]
@@ -143,9 +145,18 @@ def _masses(w):
     return None if m is None else np.ascontiguousarray(m, dtype=np.float64)
 
 
+def set_units(len_to_phys: float = 1.0, vel_to_phys: float = 1.0) -> None:
+    """Stored -> physical factors for separations and smoothing lengths, and
+    for relative speeds (sec. 4.2: comoving storage, physical pair rate)."""
+    if lib().oref_set_units(float(len_to_phys), float(vel_to_phys)) != 0:
+        raise ValueError("unit factors must be > 0 and finite")
+
+
 def _use_table(w) -> None:
+    """The workload's tabulated cross-section (if any) and unit factors."""
     if getattr(w, "table_w", None) is not None and int(w.xsec) == XSEC_TABLE:
         set_table(w.table_w, w.table_sigma)
+    set_units(getattr(w, "len_to_phys", 1.0), getattr(w, "vel_to_phys", 1.0))
 
 
 def r2(pi, pj, periodic: bool, box: float) -> float:
@@ -247,6 +258,7 @@ def pair_timestep(w, ngb, h, vx=None, vy=None, vz=None):
 
 def kick_pair(i, j, vx, vy, vz, state, ids, mass, model, eps, delta, seed, step):
     """Kick particles i and j in place (arrays are modified)."""
+    set_units(1.0, 1.0)                  # a pair kick in physical units
     lib().oref_kick_pair(int(i), int(j), None, float(mass), _p(vx), _p(vy), _p(vz),
                          _p(state), _p(ids), int(model), float(eps), float(delta),
                          int(seed), int(step))

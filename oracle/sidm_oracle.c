@@ -174,6 +174,22 @@ double oref_kernel(double r, double h)
     return 0.0;
 }
 
+/* Stored -> physical units (sec. 4.2: in cosmological runs coordinates and
+ * velocities are comoving, and the pair rate is evaluated in physical units,
+ * separations and smoothing lengths times one factor, relative speeds times
+ * another; both 1 for physical storage), set by oref_set_units. */
+static double oref_len = 1.0, oref_vel = 1.0;
+
+int oref_set_units(double len_to_phys, double vel_to_phys)
+{
+    if (!(len_to_phys > 0.0) || !(len_to_phys < 1e300) || !(vel_to_phys > 0.0) ||
+        !(vel_to_phys < 1e300))
+        return OREF_E_INVAL;
+    oref_len = len_to_phys;
+    oref_vel = vel_to_phys;
+    return OREF_OK;
+}
+
 /* tabulated cross-section: node speeds (increasing) and values, set by
  * oref_set_table before a step that uses it */
 static double oref_tw[OREF_TABLE_MAX], oref_ts[OREF_TABLE_MAX];
@@ -373,7 +389,9 @@ static void do_kick(const phys_t *ph, int32_t i, int32_t j, const double *mass, 
     direction_from_draw(x, e);
     double w = rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
     uint8_t si = state ? state[i] : 0, sj = state ? state[j] : 0, nsi, nsj;
-    double eps = scatter_eps(ph, mi, mj, w, si, sj, id[i], id[j], x[0] & 1u, &nsi, &nsj);
+    /* the energy balance in physical speed; the kick itself in stored units */
+    double eps = scatter_eps(ph, mi, mj, oref_vel * w, si, sj, id[i], id[j], x[0] & 1u, &nsi,
+                             &nsj);
     double M = mi + mj;
     double vcx = (mi * vx[i] + mj * vx[j]) / M;
     double vcy = (mi * vy[i] + mj * vy[j]) / M;
@@ -447,9 +465,11 @@ static int scatter_core(int64_t n, const double *x, const double *y, const doubl
         for (int s = 0; s < len; ++s) {
             int64_t ci = a * (int64_t)stride + s;
             int32_t j = ngb[ci];
-            double r = sqrt(oref_r2(x[i], y[i], z[i], x[j], y[j], z[j], periodic, box));
-            double W = h_all ? oref_overlap_g(h_all[i], h_all[j], r) : oref_kernel(r, h[a]);
-            double w = rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
+            /* physical separation, smoothing lengths and relative speed */
+            double r = oref_len * sqrt(oref_r2(x[i], y[i], z[i], x[j], y[j], z[j], periodic, box));
+            double W = h_all ? oref_overlap_g(oref_len * h_all[i], oref_len * h_all[j], r)
+                             : oref_kernel(r, oref_len * h[a]);
+            double w = oref_vel * rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
             double sig = oref_sigma(w, xsec, s0, w0);
             double mj = mass ? mass[j] : m_scalar;
             double P = pair_probability(mj, sig, w, W, dt[a]);
@@ -492,7 +512,7 @@ static int scatter_core(int64_t n, const double *x, const double *y, const doubl
         int32_t pass = 1 + (last_pass[i] > last_pass[j] ? last_pass[i] : last_pass[j]);
         last_pass[i] = last_pass[j] = pass;
         if (pass > st.n_passes) st.n_passes = pass;
-        double w = rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
+        double w = oref_vel * rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
         double sig = oref_sigma(w, xsec, s0, w0);
         double P = pair_probability(c->m_j, sig, w, c->W, c->dt);
         if (model == OREF_MODEL_BEAM && state[i] == state[j]) P = 0.0;
@@ -544,12 +564,12 @@ int oref_pair_timestep(int64_t n, const double *vx, const double *vy, const doub
         double rmax = 0.0;
         for (int s = 0; s < k; ++s) {
             int32_t j = ngb[a * k + s];
-            double w = rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
+            double w = oref_vel * rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
             double ws = w * oref_sigma(w, xsec, s0, w0);
             if (ws > rmax) rmax = ws;
         }
         double mi = mass ? mass[i] : m_scalar;
-        double W0 = oref_kernel(0.0, h[a]);
+        double W0 = oref_kernel(0.0, oref_len * h[a]);
         dt_out[a] = rmax > 0.0 ? (2.0 * c_sidm) / ((mi * W0) * rmax) : INFINITY;
     }
     return OREF_OK;
@@ -801,8 +821,9 @@ int oref_pair_timestep_overlap(int64_t n, const double *vx, const double *vy, co
         double qmax = 0.0;
         for (int s = 0; s < len; ++s) {
             int32_t j = ngb[a * (int64_t)max_ngb + s];
-            double w = rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
-            double q = oref_overlap_g(h_all[i], h_all[j], 0.0) * (w * oref_sigma(w, xsec, s0, w0));
+            double w = oref_vel * rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
+            double q = oref_overlap_g(oref_len * h_all[i], oref_len * h_all[j], 0.0) *
+                       (w * oref_sigma(w, xsec, s0, w0));
             if (q > qmax) qmax = q;
         }
         double mi = mass ? mass[i] : m_scalar;

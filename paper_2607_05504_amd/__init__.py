@@ -52,7 +52,8 @@ class Config(ctypes.Structure):
                 ("c_sidm", ctypes.c_double), ("flag_band", ctypes.c_double),
                 ("band_r2", ctypes.c_double), ("band_p", ctypes.c_double),
                 ("xsec_n", ctypes.c_int32), ("xsec_w", ctypes.c_void_p),
-                ("xsec_sigma", ctypes.c_void_p), ("estimator", ctypes.c_int32)]
+                ("xsec_sigma", ctypes.c_void_p), ("estimator", ctypes.c_int32),
+                ("len_to_phys", ctypes.c_double), ("vel_to_phys", ctypes.c_double)]
 
 
 class Particles(ctypes.Structure):
@@ -146,10 +147,13 @@ def lib():
 def make_config(n_ngb=32, periodic=False, box=0.0, xsec=XSEC_CONST, sigma0=0.0, w0=1.0,
                 model=MODEL_ELASTIC, eps=1.0, delta=0.0, c_sidm=0.1, precision=FP64,
                 flag_band=1e-9, band_r2=1e-5, band_p=1e-5, table_w=None,
-                table_sigma=None, estimator=EST_ONE_SIDED) -> Config:
+                table_sigma=None, estimator=EST_ONE_SIDED, len_to_phys=1.0,
+                vel_to_phys=1.0) -> Config:
     """A sidm_config.  table_w / table_sigma (numpy arrays) give a tabulated
     cross-section (xsec = XSEC_TABLE); the Config keeps them alive.
-    estimator = EST_OVERLAP reserves what the overlap-estimator calls need."""
+    estimator = EST_OVERLAP reserves what the overlap-estimator calls need.
+    len_to_phys / vel_to_phys: stored -> physical factors of lengths and
+    relative speeds (comoving storage)."""
     tw = ts = None
     n_t = 0
     if table_w is not None:
@@ -160,7 +164,8 @@ def make_config(n_ngb=32, periodic=False, box=0.0, xsec=XSEC_CONST, sigma0=0.0, 
                int(precision), float(box), float(sigma0), float(w0), float(eps), float(delta),
                float(c_sidm), float(flag_band), float(band_r2), float(band_p), n_t,
                tw.ctypes.data if tw is not None else None,
-               ts.ctypes.data if ts is not None else None, int(estimator))
+               ts.ctypes.data if ts is not None else None, int(estimator),
+               float(len_to_phys), float(vel_to_phys))
     c._tables = (tw, ts)
     return c
 

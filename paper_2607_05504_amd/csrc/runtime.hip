@@ -95,9 +95,20 @@ void set_err(sidm_ctx *c, const char *fmt, ...)
     va_end(ap);
 }
 
+// a stored -> physical factor: 0 (read as 1) or > 0 and finite
+bool unit_factor_ok(double f) { return f == 0.0 || (f > 0.0 && f < 1e300); }
+
+void normalize_units(sidm_config &cfg)
+{
+    if (cfg.len_to_phys == 0.0) cfg.len_to_phys = 1.0;
+    if (cfg.vel_to_phys == 0.0) cfg.vel_to_phys = 1.0;
+}
+
 sidm_status check_config(const sidm_config *cfg)
 {
     if (!cfg) return SIDM_E_INVAL;
+    if (!unit_factor_ok(cfg->len_to_phys) || !unit_factor_ok(cfg->vel_to_phys))
+        return SIDM_E_INVAL;
     if (cfg->n_ngb < 1 || cfg->n_ngb > 64) return SIDM_E_INVAL;
     if (cfg->kernel != SIDM_KERNEL_CUBIC_SPLINE) return SIDM_E_INVAL;
     if (cfg->periodic && !(cfg->box > 0.0)) return SIDM_E_INVAL;
@@ -209,6 +220,7 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
     sidm_ctx *c = (sidm_ctx *)calloc(1, sizeof(sidm_ctx));
     if (!c) return SIDM_E_NOMEM;
     c->cfg = *cfg;
+    normalize_units(c->cfg);
     c->cap_n = cap_n;
     c->cap_active = cap_active;
     c->stream = (hipStream_t)hip_stream;
@@ -339,6 +351,7 @@ sidm_status sidm_reconfigure(sidm_ctx *c, const sidm_config *cfg)
         return SIDM_E_INVAL;
     }
     c->cfg = *cfg;
+    normalize_units(c->cfg);
     c->tree_ok = 0;          // a new configuration needs a new snapshot
     c->map_valid = 0;
     c->hs_valid = 0;

@@ -65,6 +65,9 @@ struct StepArgs {
     int stride;
     const int32_t *cnt;
     const double *hsrt, *gtab;
+    // stored -> physical factors of lengths and relative speeds (comoving
+    // storage): W, g_ij, sigma, P, the two-state balance and dt are physical
+    double lphys, vphys;
     uint64_t seed;
     uint32_t step;
     int k, periodic, xsec, model, has_mass;
@@ -182,7 +185,9 @@ __device__ void kick(const StepArgs &A, int32_t i, int32_t j)
     const double vjx = A.vxs[j], vjy = A.vys[j], vjz = A.vzs[j];
     const double w = rel_speed(vix, viy, viz, vjx, vjy, vjz);
     uint8_t nsi, nsj;
-    double eps = scatter_eps(A, mi, mj, w, A.sts[i], A.sts[j], idi, idj, x.x0 & 1u, nsi, nsj);
+    // the energy balance in physical speed; the kick itself in stored units
+    double eps = scatter_eps(A, mi, mj, A.vphys * w, A.sts[i], A.sts[j], idi, idj, x.x0 & 1u,
+                             nsi, nsj);
     double M = mi + mj;
     double vcx = (mi * vix + mj * vjx) / M;
     double vcy = (mi * viy + mj * vjy) / M;
@@ -311,11 +316,11 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                     float dy = (float)(box_centre(bj, 1) - box_centre(bi, 1)) + (A.yo[j] - A.yo[i]);
                     float dz = (float)(box_centre(bj, 2) - box_centre(bi, 2)) + (A.zo[j] - A.zo[i]);
                     if (PERIODIC) { dx = wrap32(dx, bx); dy = wrap32(dy, bx); dz = wrap32(dz, bx); }
-                    const float r32 = sqrtf((dx * dx + dy * dy) + dz * dz);
-                    const float h32 = (float)A.h[a];
+                    const float r32 = (float)A.lphys * sqrtf((dx * dx + dy * dy) + dz * dz);
+                    const float h32 = (float)(A.lphys * A.h[a]);
                     const float vx = (float)(A.vxs[i] - A.vxs[j]), vy = (float)(A.vys[i] - A.vys[j]),
                                 vz = (float)(A.vzs[i] - A.vzs[j]);
-                    const float w32 = sqrtf((vx * vx + vy * vy) + vz * vz);
+                    const float w32 = (float)A.vphys * sqrtf((vx * vx + vy * vy) + vz * vz);
                     const float s32 = A.xsec == SIDM_XSEC_TABLE
                                           ? (float)sigma_of(A, (double)w32)
                                           : xsec_sigma32(w32, A.xsec, (float)A.s0, (float)A.w0);
@@ -329,11 +334,13 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                     exact = fabs(P - u) <= near;
                 }
                 if (exact) {
-                    const double r = sqrt(sep2<PERIODIC>(A.xs[i], A.ys[i], A.zs[i], A.xs[j], A.ys[j],
-                                                         A.zs[j], A.box));
-                    W = OVERLAP ? overlap_g(A.gtab, A.hsrt[i], A.hsrt[j], r)
-                                : cubic_spline(r, A.h[a]);
-                    const double w = rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
+                    // physical separation, smoothing lengths and relative speed
+                    const double r = A.lphys * sqrt(sep2<PERIODIC>(A.xs[i], A.ys[i], A.zs[i],
+                                                                   A.xs[j], A.ys[j], A.zs[j], A.box));
+                    W = OVERLAP ? overlap_g(A.gtab, A.lphys * A.hsrt[i], A.lphys * A.hsrt[j], r)
+                                : cubic_spline(r, A.lphys * A.h[a]);
+                    const double w = A.vphys * rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j],
+                                                         A.vys[j], A.vzs[j]);
                     const double sig = sigma_of(A, w);
                     P = pair_prob(mass_of(A, j), sig, w, W, dta);
                     if (!pair_allowed(A, i, j)) P = 0.0;
@@ -343,9 +350,9 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                 const bool flagged = exact && fabs(P - u) < A.band;
                 if (MIXED && acc && !exact) {
                     // accepted on the FP32 value: the passes need the FP64 W
-                    const double r = sqrt(sep2<PERIODIC>(A.xs[i], A.ys[i], A.zs[i], A.xs[j], A.ys[j],
-                                                         A.zs[j], A.box));
-                    W = cubic_spline(r, A.h[a]);
+                    const double r = A.lphys * sqrt(sep2<PERIODIC>(A.xs[i], A.ys[i], A.zs[i],
+                                                                   A.xs[j], A.ys[j], A.zs[j], A.box));
+                    W = cubic_spline(r, A.lphys * A.h[a]);
                 }
                 n_fl += flagged;
                 n_ge1 += P >= 1.0;
@@ -456,7 +463,8 @@ __device__ bool resolve_entry(const StepArgs &A, int t, int64_t e, int32_t *next
     const bool win = load_claim(&c1[i]) == pr && load_claim(&c1[j]) == pr &&
                      load_claim(&c2[i]) == ip && load_claim(&c2[j]) == ip;
     if (win) {
-        const double w = rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
+        const double w = A.vphys * rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j],
+                                             A.vzs[j]);
         const double sig = sigma_of(A, w);
         const double P = pair_allowed(A, i, j) ? pair_prob(mass_of(A, j), sig, w, L.W[e], L.dt[e]) : 0.0;
         const double u = L.u[e];
@@ -594,14 +602,14 @@ __device__ __forceinline__ double pair_rate(const StepArgs &A, double vix, doubl
 {
     if (jc < 0 || jc >= A.n) { atomicOr(A.derr, DERR_INDEX); return 0.0; }
     const int32_t j = A.inv[jc];
-    const double w = rel_speed(vix, viy, viz, A.vxs[j], A.vys[j], A.vzs[j]);
+    const double w = A.vphys * rel_speed(vix, viy, viz, A.vxs[j], A.vys[j], A.vzs[j]);
     return w * sigma_of(A, w);
 }
 
 __device__ __forceinline__ double dt_from_rate(const StepArgs &A, int32_t i, double h, double rmax,
                                                double c_sidm)
 {
-    const double W0 = cubic_spline(0.0, h);
+    const double W0 = cubic_spline(0.0, A.lphys * h);
     return rmax > 0.0 ? (2.0 * c_sidm) / ((mass_of(A, i) * W0) * rmax) : INFINITY;
 }
 
@@ -664,14 +672,14 @@ __global__ __launch_bounds__(kBlock) void k_timestep_overlap(StepArgs A, double 
             i = A.tlist[b];
             a = A.slot[b];
             const double vix = A.vxs[i], viy = A.vys[i], viz = A.vzs[i];
-            const double hi = A.hsrt[i];
+            const double hi = A.lphys * A.hsrt[i];
             const int len = A.cnt[a] < A.stride ? A.cnt[a] : A.stride;
             for (int s = tl; s < len; s += kTeamT) {
                 const int32_t jc = A.ngb[(int64_t)a * A.stride + s];
                 if (jc < 0 || jc >= A.n) { atomicOr(A.derr, DERR_INDEX); continue; }
                 const int32_t j = A.inv[jc];
-                const double w = rel_speed(vix, viy, viz, A.vxs[j], A.vys[j], A.vzs[j]);
-                const double q = overlap_g0(A.gtab, hi, A.hsrt[j]) * (w * sigma_of(A, w));
+                const double w = A.vphys * rel_speed(vix, viy, viz, A.vxs[j], A.vys[j], A.vzs[j]);
+                const double q = overlap_g0(A.gtab, hi, A.lphys * A.hsrt[j]) * (w * sigma_of(A, w));
                 qmax = q > qmax ? q : qmax;
             }
         }
@@ -709,6 +717,7 @@ StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const dou
     A.xo = c->xo; A.yo = c->yo; A.zo = c->zo; A.nodes = c->nodes; A.band_p = c->cfg.band_p;
     A.xt_w = c->xt_w; A.xt_s = c->xt_s; A.xt_lw = c->xt_lw; A.xt_n = c->cfg.xsec_n;
     A.stride = A.k; A.cnt = nullptr; A.hsrt = c->hs; A.gtab = c->gtab;
+    A.lphys = c->cfg.len_to_phys; A.vphys = c->cfg.vel_to_phys;
     return A;
 }
 

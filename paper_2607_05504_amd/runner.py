@@ -66,7 +66,9 @@ def config_for(w, precision=FP64, **kw):
                        sigma0=w.sigma0, w0=w.w0, model=w.model, eps=w.eps, delta=w.delta,
                        c_sidm=w.c_sidm, precision=precision,
                        table_w=getattr(w, "table_w", None),
-                       table_sigma=getattr(w, "table_sigma", None), **kw)
+                       table_sigma=getattr(w, "table_sigma", None),
+                       len_to_phys=getattr(w, "len_to_phys", 1.0),
+                       vel_to_phys=getattr(w, "vel_to_phys", 1.0), **kw)
 
 
 def alloc_out(ds: DeviceState, k: int, with_info: bool = False) -> StepOut:

@@ -78,6 +78,13 @@ def _oracle(w, max_ngb):
                 stats=stats, dt_sidm=dt)
 
 
+def _comoving(w):
+    # lengths and relative speeds stored in units that convert to physical
+    # ones by factors that round (sec. 4.2)
+    import dataclasses
+    return dataclasses.replace(w, len_to_phys=0.37, vel_to_phys=1.9)
+
+
 def _check_decisions(gi, ri):
     flagged = ((gi | ri) & oracle.CAND_FLAGGED) != 0
     same = (gi == ri) | flagged
@@ -92,6 +99,8 @@ WORKLOADS = {
         W.hernquist_halo(30000, ic_seed=83, philox_seed=4)),
     "Hernquist two-state, 3000 active": lambda: W.hernquist_halo(
         20000, ic_seed=84, philox_seed=5, two_state=True).subset_active(3000),
+    "Hernquist two-state, comoving storage": lambda: _comoving(W.hernquist_halo(
+        20000, ic_seed=85, philox_seed=6, two_state=True).subset_active(3000)),
 }
 
 

@@ -295,3 +295,24 @@ def test_tree_order_is_a_stable_morton_sort(case):
     assert np.all(o[1:][ties] > o[:-1][ties])
     ref = np.argsort(_morton_keys(w.x, w.y, w.z, w.periodic, w.box), kind="stable")
     assert np.array_equal(o, ref)
+
+
+@pytest.mark.parametrize("case", ["halo two-state FP64", "halo two-state mixed",
+                                  "periodic box FP64"])
+def test_comoving_storage(case):
+    """Comoving storage (sec. 4.2): lengths and relative speeds converted to
+    physical units by factors that round (0.37, 1.9) inside W, sigma, P, the
+    two-state energy balance and the timestep; the same parity bar."""
+    import dataclasses
+    if case.startswith("halo"):
+        w = W.hernquist_bins(W.hernquist_halo(20000, ic_seed=210, philox_seed=19, two_state=True),
+                             active_frac=0.25)
+    else:
+        w = W.uniform_box(8000, ic_seed=211, scatters_per_particle=0.2)
+    w = dataclasses.replace(w, len_to_phys=0.37, vel_to_phys=1.9)
+    prec = MIXED if "mixed" in case else FP64
+    _announce(f"comoving storage {case} n={w.n} active={w.n_active}")
+    ref = oracle.full_step(w)
+    g = gpu_step(w, precision=prec)
+    assert_parity(w, g, ref, mixed=(prec == MIXED))
+    assert g["stats"]["n_events"] > 0

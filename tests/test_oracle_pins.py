@@ -554,3 +554,62 @@ def test_step_with_unequal_masses_conserves_momentum_and_energy():
     w2 = W.uniform_box(3000, ic_seed=35, scatters_per_particle=1.0)
     r2 = oracle.full_step(w2, brute=True)
     assert not np.array_equal(r["vx"], r2["vx"])
+
+
+# ---------------------------------------------------------------------------
+# Comoving storage (sec. 4.2: the pair rate in physical units)
+# ---------------------------------------------------------------------------
+
+def _stored_and_physical(L, V, two_state):
+    import dataclasses
+    base = W.hernquist_halo(4000, ic_seed=71, philox_seed=9, two_state=two_state)
+    base = W.hernquist_bins(base, active_frac=0.3)
+    stored = dataclasses.replace(base, len_to_phys=L, vel_to_phys=V)
+    phys = dataclasses.replace(base, x=base.x * L, y=base.y * L, z=base.z * L,
+                               vx=base.vx * V, vy=base.vy * V, vz=base.vz * V,
+                               state=base.state.copy())
+    stored.state = base.state.copy()
+    return stored, phys
+
+
+@pytest.mark.parametrize("two_state", [False, True])
+def test_comoving_storage_with_power_of_two_factors_is_exact(two_state):
+    """Particles stored in units where the physical positions are L x and the
+    physical velocities V v (L, V powers of two, so that every scaled value is
+    exact) step exactly like the same particles stored in physical units:
+    same neighbours, h scaled by L, same decisions and states, velocities and
+    timesteps scaled exactly.  A conversion missing from any term (r, h, w in
+    sigma, in P, in the two-state energy balance or in the timestep) breaks it."""
+    L, V = 0.25, 4.0
+    a, b = _stored_and_physical(L, V, two_state)
+    ra, rb = oracle.full_step(a), oracle.full_step(b)
+    assert np.array_equal(ra["ngb"], rb["ngb"])
+    assert np.array_equal(ra["h"] * L, rb["h"])
+    assert np.array_equal(ra["info"], rb["info"])
+    assert ra["stats"]["n_events"] == rb["stats"]["n_events"] > 0
+    for f in ("vx", "vy", "vz"):
+        assert np.array_equal(ra[f] * V, rb[f]), f
+    assert np.array_equal(ra["state"], rb["state"])
+    assert np.array_equal(ra["dt_sidm"], rb["dt_sidm"])
+
+
+def test_comoving_storage_with_general_factors():
+    """The same equivalence with factors that round (L = 0.37, V = 1.9): on
+    the same neighbour lists, decisions agree away from the flagged band and
+    velocities and timesteps to 1e-12 relative."""
+    L, V = 0.37, 1.9
+    a, b = _stored_and_physical(L, V, True)
+    ngb, h = oracle.find_ngb(a)
+    va = oracle.scatter_step(a, ngb, h)
+    vb = oracle.scatter_step(b, ngb, h * L)
+    ia, ib = va[4], vb[4]
+    flagged = ((ia | ib) & oracle.CAND_FLAGGED) != 0
+    assert np.all((ia == ib) | flagged)
+    assert va[5]["n_events"] == vb[5]["n_events"] > 0
+    scale = max(np.abs(vb[f]).max() for f in range(3))
+    for f in range(3):
+        assert np.abs(va[f] * V - vb[f]).max() <= 1e-12 * scale
+    assert np.array_equal(va[3], vb[3])
+    da = oracle.pair_timestep(a, ngb, h, *va[:3])
+    db = oracle.pair_timestep(b, ngb, h * L, *vb[:3])
+    np.testing.assert_allclose(da, db, rtol=1e-12)

@@ -67,6 +67,8 @@ class Workload:
     seed: int = 1
     step: int = 0
     meta: dict = dataclasses.field(default_factory=dict)
+    len_to_phys: float = 1.0    # stored -> physical separations and smoothing lengths
+    vel_to_phys: float = 1.0    # stored -> physical relative speeds
     table_w: Optional[np.ndarray] = None       # tabulated sigma(w)/m: node speeds
     table_sigma: Optional[np.ndarray] = None   # and values (xsec = XSEC_TABLE)
 
