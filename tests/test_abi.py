@@ -98,3 +98,16 @@ def test_overlap_estimator_config():
     assert L.sidm_footprint(ctypes.byref(bad), 1000, 100, ctypes.byref(out)) == sidm.SIDM_E_INVAL
     bad = sidm.make_config(n_ngb=32, periodic=True, box=1.0, sigma0=1.0, estimator=7)
     assert L.sidm_footprint(ctypes.byref(bad), 1000, 100, ctypes.byref(out)) == sidm.SIDM_E_INVAL
+
+
+def test_unit_factors_are_checked():
+    """Comoving storage: the stored -> physical factors are 0 (read as 1) or
+    > 0 and finite; anything else is refused before anything runs."""
+    L = sidm.lib()
+    out = ctypes.c_size_t()
+    for lf, vf in ((0.0, 0.0), (1.0, 1.0), (0.37, 1.9)):
+        ok = sidm.make_config(n_ngb=32, len_to_phys=lf, vel_to_phys=vf)
+        assert L.sidm_footprint(ctypes.byref(ok), 1000, 100, ctypes.byref(out)) == sidm.SIDM_OK
+    for lf, vf in ((-1.0, 1.0), (1.0, -0.5), (float("inf"), 1.0), (1.0, float("nan"))):
+        bad = sidm.make_config(n_ngb=32, len_to_phys=lf, vel_to_phys=vf)
+        assert L.sidm_footprint(ctypes.byref(bad), 1000, 100, ctypes.byref(out)) == sidm.SIDM_E_INVAL
