@@ -264,10 +264,9 @@ __device__ __forceinline__ double cubic_spline(double r, double h)
     return 0.0;
 }
 
-// Tabulated sigma(w)/m: linear in w between nodes tw[0..n) (increasing), the
-// end values outside; the node pair is found by bisection.
-// tabulated sigma/m: linear in ln w between the bracketing nodes (tlw holds
-// the nodes' ln w), the end values outside
+// Tabulated sigma(w)/m over nodes tw[0..n) (increasing): linear in ln w
+// between the bracketing nodes (found by bisection; tlw holds the nodes'
+// ln w), the end values outside.
 __device__ __forceinline__ double xsec_table(double w, const double *tw, const double *tlw,
                                              const double *ts, int n)
 {
