@@ -212,13 +212,15 @@ __device__ void kick(const StepArgs &A, int32_t i, int32_t j)
 // Evaluation 0: every candidate with the step-start velocities.  Accepted
 // candidates are staged in LDS and appended to the list in bulk, and the
 // statistics are reduced per workgroup, so global atomics stay per workgroup.
+// A staged entry keeps only what cannot be looked up again (the candidate's
+// index c = b * stride + s, its draw u and its W); the flush recomputes the
+// rest, so that the buffer is small and more workgroups are resident.
 // ----------------------------------------------------------------------------
 constexpr int kStage = 512;                // staged accepted candidates per workgroup
 
 struct StagedAcc {
-    int32_t i[kStage], j[kStage], cand[kStage];
-    double u[kStage], W[kStage], dt[kStage];
-    uint64_t prio[kStage], idpair[kStage];
+    int64_t c[kStage];
+    double u[kStage], W[kStage];
 };
 
 __device__ void flush_staged(const StepArgs &A, StagedAcc &S, int n, int32_t &base_s)
@@ -229,10 +231,18 @@ __device__ void flush_staged(const StepArgs &A, StagedAcc &S, int n, int32_t &ba
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         const int64_t pos = base + t;
         if (pos >= A.cap_acc) { atomicOr(A.derr, DERR_OVERFLOW); continue; }
-        const int32_t i = S.i[t], j = S.j[t];
-        A.L0.i[pos] = i; A.L0.j[pos] = j; A.L0.cand[pos] = S.cand[t];
-        A.L0.u[pos] = S.u[t]; A.L0.W[pos] = S.W[t]; A.L0.dt[pos] = S.dt[t];
-        A.L0.prio[pos] = S.prio[t]; A.L0.idpair[pos] = S.idpair[t];
+        const int64_t c = S.c[t];
+        const int64_t b = c / A.stride;
+        const int s = (int)(c - b * A.stride);
+        const int32_t a = A.slot[b], i = A.tlist[b];
+        const int64_t ci = (int64_t)a * A.stride + s;
+        const int32_t j = A.inv[A.ngb[ci]];    // checked in range when it was evaluated
+        const uint32_t idi = A.ids[i], idj = A.ids[j];
+        const Philox4 xp = pair_draw(A.seed, A.step, idi, idj, PURPOSE_PRIORITY);
+        A.L0.i[pos] = i; A.L0.j[pos] = j; A.L0.cand[pos] = (int32_t)ci;
+        A.L0.u[pos] = S.u[t]; A.L0.W[pos] = S.W[t]; A.L0.dt[pos] = A.dt[a];
+        A.L0.prio[pos] = direction_word(xp, idi < idj);
+        A.L0.idpair[pos] = ((uint64_t)idi << 32) | idj;
         A.c1a[i] = ~0ull; A.c1a[j] = ~0ull;
         A.c2a[i] = ~0ull; A.c2a[j] = ~0ull;
     }
@@ -363,12 +373,8 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                     A.cand_info[ci] =
                         (acc ? SIDM_CAND_ACCEPT0 : 0u) | (flagged ? SIDM_CAND_FLAGGED : 0u);
                 if (acc) {
-                    const Philox4 xp = pair_draw(A.seed, A.step, idi, idj, PURPOSE_PRIORITY);
                     const int t = atomicAdd(&s_n, 1);      // LDS; kStage >= 2 * blockDim
-                    S.i[t] = i; S.j[t] = j; S.cand[t] = (int32_t)ci;
-                    S.u[t] = u; S.W[t] = W; S.dt[t] = dta;
-                    S.prio[t] = direction_word(xp, idi < idj);
-                    S.idpair[t] = ((uint64_t)idi << 32) | idj;
+                    S.c[t] = c; S.u[t] = u; S.W[t] = W;
                 }
             }
         }
