@@ -18,7 +18,12 @@
  *                   smoothing length h_i = distance of the (N_ngb+1)-th
  *                   (reading of the "32 +- 5" bisection of sec. 4.2/4.5)
  *   kernel          cubic spline W_CS(q, h) (sec. 4.2)
- *   cross-section   sigma/m constant, or s0 / (1 + (w/w0)^2)^2 (sec. 5.2)
+ *   cross-section   sigma/m constant, or s0 / (1 + (w/w0)^2)^2 (sec. 5.2),
+ *                   or a table interpolated linearly in log velocity (sec. 4.2)
+ *   units           separations, smoothing lengths and relative speeds are
+ *                   converted to physical units by two factors before they
+ *                   enter W, g_ij, sigma, P, the two-state balance and dt
+ *                   (sec. 4.2: comoving storage, physical pair rate)
  *   rate, P         Gamma(i|j) = m_j (sigma/m) |v_i - v_j| g_ij with the
  *                   one-sided g_ij = W(x_j - x_i, h_i)   (Eqs. rate, oneSided)
  *                   P(i|j) = Gamma(i|j) dt_i / 2        (Eq. probabilityScatter)
