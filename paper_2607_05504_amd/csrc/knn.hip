@@ -112,12 +112,30 @@ __device__ __forceinline__ double window_bound(const KnnArgs &A, int64_t i, doub
     if (w0 < 0) w0 = 0;
     float v[PER];
     uint32_t lo = 0xffffffffu, hi = 0u;
+    // positions requested three at a time (indices clamped into range, the
+    // clamped results masked), then their separations
+    constexpr int CH = 3;
+#pragma unroll
+    for (int q0 = 0; q0 < PER; q0 += CH) {
+        double wx[CH], wy[CH], wz[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            int64_t j = w0 + (q0 + u) * LT + sub;
+            if (j > n - 1) j = n - 1;
+            if (q0 + u < PER) { wx[u] = A.xs[j]; wy[u] = A.ys[j]; wz[u] = A.zs[j]; }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int q = q0 + u;
+            if (q >= PER) break;
+            const int64_t j = w0 + q * LT + sub;
+            v[q] = (j < n && j <= w0 + 2 * W && j != i)
+                       ? __double2float_ru(sep2_sel<PERIODIC>(px, py, pz, wx[u], wy[u], wz[u], A.box))
+                       : INFINITY;
+        }
+    }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int64_t j = w0 + q * LT + sub;
-        v[q] = INFINITY;
-        if (j < n && j <= w0 + 2 * W && j != i)
-            v[q] = __double2float_ru(sep2_sel<PERIODIC>(px, py, pz, A.xs[j], A.ys[j], A.zs[j], A.box));
         if (v[q] < INFINITY) {
             const uint32_t bv = __float_as_uint(v[q]);
             lo = bv < lo ? bv : lo;
