@@ -315,3 +315,36 @@ def test_h_copy_after_rebuild_and_other_h_array():
     for f in ("vx", "vy", "vz"):
         assert np.array_equal(getattr(ds, f).cpu().numpy(), ref[f]), f
     assert np.array_equal(out.dt_sidm.cpu().numpy(), ref["dt_sidm"])
+
+
+def test_wide_kernels_fill_the_leaf_list():
+    """Smoothing lengths of 0.3 box in a periodic box of 8000 particles (250
+    leaves): every group of targets accepts nearly every leaf, so the walk
+    lists more leaves than one batch holds and processes them in batches
+    (an odd leaf carried over), with the stack at its widest.  Counts exact,
+    rows equal as sets (about 6000 partners each)."""
+    import torch
+    from paper_2607_05504_amd import runner
+    w = W.uniform_box(8000, ic_seed=91).subset_active(500)
+    h = np.full(w.n, 0.3 * w.box)
+    h[::7] = 0.31 * w.box                    # not all equal
+    max_ngb = w.n
+    _announce(f"overlap wide kernels n={w.n} active={w.n_active} h=0.3 box")
+    ref_ngb, ref_cnt = oracle.find_overlap(w, h, max_ngb)
+    ds = runner.upload(w, "cuda")
+    ctx = _ctx(w)
+    ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state,
+                   m_scalar=ds.mass)
+    h_all = torch.from_numpy(h).to("cuda")
+    ngb = torch.empty((w.n_active, max_ngb), dtype=torch.int32, device="cuda")
+    cnt = torch.empty(w.n_active, dtype=torch.int32, device="cuda")
+    ctx.find_overlap(h_all, ds.active, ngb, cnt)
+    st = ctx.sync()
+    ctx.close()
+    assert st["error"] == 0
+    g_cnt = cnt.cpu().numpy()
+    assert np.array_equal(g_cnt, ref_cnt)
+    assert g_cnt.min() > 4000
+    g = ngb.cpu().numpy()
+    for a in range(w.n_active):
+        assert np.array_equal(np.sort(g[a, :g_cnt[a]]), np.sort(ref_ngb[a, :ref_cnt[a]])), a
