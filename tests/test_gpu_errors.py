@@ -206,3 +206,29 @@ def test_timing_mask_times_only_the_chosen_phases():
     assert t["samples"] == 0 and t["knn_ms"] == 0
     assert ctx.sync()["error"] == 0
     ctx.close()
+
+
+def test_accepted_list_overflow_is_reported_and_the_context_recovers():
+    """Every candidate accepted (sigma/m so large that P >> 1) on 40000 active
+    particles: 1.28M accepted candidates against a list of 2^20 entries.  The
+    evaluation's flush drops what does not fit and latches the overflow,
+    sidm_sync reports SIDM_E_OVERFLOW, and after a reconfiguration with a
+    normal cross-section the next step runs clean."""
+    from paper_2607_05504_amd import SIDM_E_OVERFLOW, Context, SidmError, runner
+    w = W.uniform_box(40000, ic_seed=57, scatters_per_particle=0.1)
+    _announce(f"accepted-list overflow n={w.n}")
+    normal = w.sigma0
+    w.sigma0 = normal * 1e7
+    ds = runner.upload(w, "cuda")
+    ctx = Context(runner.config_for(w), w.n, w.n_active)
+    out = runner.alloc_out(ds, w.n_ngb)
+    runner.run_step(ctx, ds, out, w.seed, w.step)
+    with pytest.raises(SidmError) as e:
+        ctx.sync()
+    assert e.value.status == SIDM_E_OVERFLOW
+    w.sigma0 = normal
+    ctx.reconfigure(runner.config_for(w))
+    runner.run_step(ctx, ds, out, w.seed, w.step + 1)
+    st = ctx.sync()
+    assert st["error"] == 0 and st["n_events"] > 0
+    ctx.close()
