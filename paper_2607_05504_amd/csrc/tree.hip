@@ -41,12 +41,24 @@ __global__ __launch_bounds__(256) void k_bounds(const double *__restrict__ x,
 {
     __shared__ unsigned long long part[4][6];
     unsigned long long v[6] = {~0ull, ~0ull, ~0ull, 0, 0, 0};
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        unsigned long long a = ordered_u64(x[t]), b = ordered_u64(y[t]), c = ordered_u64(z[t]);
+    auto take = [&](double px, double py, double pz) {
+        const unsigned long long a = ordered_u64(px), b = ordered_u64(py), c = ordered_u64(pz);
         v[0] = min(v[0], a); v[1] = min(v[1], b); v[2] = min(v[2], c);
         v[3] = max(v[3], a); v[4] = max(v[4], b); v[5] = max(v[5], c);
+    };
+    // four particles a thread per round, their positions requested together
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (; t + 3 * stride < n; t += 4 * stride) {
+        double px[4], py[4], pz[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            px[u] = x[t + u * stride]; py[u] = y[t + u * stride]; pz[u] = z[t + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) take(px[u], py[u], pz[u]);
     }
+    for (; t < n; t += stride) take(x[t], y[t], z[t]);
     for (int off = 32; off > 0; off >>= 1) {
         for (int d = 0; d < 3; ++d) {
             v[d] = min(v[d], (unsigned long long)__shfl_xor((long long)v[d], off));
