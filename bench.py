@@ -132,18 +132,28 @@ def run_serving(args) -> dict:
     from paper_2607_05504_amd.serve import Server, ServeConfig
     torch.cuda.set_device(0)
     reqs = W.serving_requests(args.requests, rate=args.rate, n_max=args.n_max, steps=args.req_steps)
-    # initial conditions generated before the stream starts (host work, not timed)
-    with cf.ThreadPoolExecutor(8) as ex:
-        wl = dict(zip([r.rid for r in reqs], ex.map(W.request_workload, reqs)))
-    print(f"[bench] serving: {len(reqs)} requests generated", file=sys.stderr, flush=True)
+    if args.ic_pool:
+        # one Eddington sample of n_max particles; each request draws a rotated
+        # random subset of it when it is admitted (a few ms of host time)
+        pool = W.hernquist_halo(int(args.n_max), ic_seed=7)
+        make = lambda r: W.request_workload_pooled(r, pool)
+        print(f"[bench] serving: {len(reqs)} requests drawn from a pool of {pool.n}",
+              file=sys.stderr, flush=True)
+    else:
+        # initial conditions generated before the stream starts (host work, not timed)
+        with cf.ThreadPoolExecutor(8) as ex:
+            wl = dict(zip([r.rid for r in reqs], ex.map(W.request_workload, reqs)))
+        make = lambda r: wl[r.rid]
+        print(f"[bench] serving: {len(reqs)} requests generated", file=sys.stderr, flush=True)
     prec = MIXED if args.precision == "mixed" else FP64
     # warm-up: one small request through the whole path
-    srv = Server(ServeConfig(n_slots=args.slots, hbm_budget=args.budget_gib << 30, precision=prec))
+    srv = Server(ServeConfig(n_slots=args.slots, hbm_budget=args.budget_gib << 30, precision=prec,
+                             progress_s=20.0 if args.ic_pool else 0.0))
     wreq = W.Request(rid=-1, arrival=0.0, n=10000, s0=W.hernquist_s0(), ic_seed=99, philox_seed=99,
                      steps=2)
     srv.run([wreq], W.request_workload)
     torch.cuda.synchronize()
-    rep = srv.run(reqs, lambda r: wl[r.rid])
+    rep = srv.run(reqs, make)
     torch.cuda.synchronize()
     srv.close()
     n_steps = sum(r.steps for r in reqs)
@@ -155,6 +165,7 @@ def run_serving(args) -> dict:
         "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": "serving", "requests": len(reqs), "rate_per_s": args.rate,
                    "n_range": [1e4, args.n_max], "steps_per_request": args.req_steps,
+                   "initial_conditions": "pooled subsets" if args.ic_pool else "per request",
                    "slots": args.slots, "hbm_budget_gib": args.budget_gib,
                    "precision": args.precision},
         "p50_step_ms": rep["p50_step_ms"], "p99_step_ms": rep["p99_step_ms"],
@@ -190,6 +201,9 @@ def main():
     ap.add_argument("--req-steps", type=int, default=64, help="serving: steps per request")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
     ap.add_argument("--budget-gib", type=int, default=4, help="serving: HBM budget")
+    ap.add_argument("--ic-pool", action="store_true",
+                    help="serving: draw each request from one Eddington sample of n-max "
+                         "particles (for streams too large to sample one by one)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times "
                          "(calibrates the HBM byte counters) and exit")

@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import sys
 import time
 from typing import Callable, Optional
 
@@ -56,6 +57,7 @@ class ServeConfig:
     gm: float = 1.0
     a: float = 1.0
     keep_results: bool = False     # copy each request's final state to the host
+    progress_s: float = 0.0        # > 0: a progress line on stderr this often
 
 
 @dataclasses.dataclass
@@ -128,9 +130,15 @@ class Server:
         head = None                       # (request, workload) at the head of the queue
         t0 = time.perf_counter()
         first_arrival = pending[0].arrival if pending else 0.0
+        n_total, t_report = len(pending), 0.0
         while pending or any(s is not None for s in slots):
             now = time.perf_counter() - t0
             progressed = False
+            if cfg.progress_s > 0 and now - t_report >= cfg.progress_s:
+                t_report = now
+                busy = sum(s is not None for s in slots)
+                print(f"[serve] t={now:.0f}s done={len(results)}/{n_total} running={busy} "
+                      f"particle-steps={particle_steps:.3g}", file=sys.stderr, flush=True)
             # admission: first come, first served, as slots and memory free up
             while pending and pending[0].arrival <= now:
                 free = [k for k, s in enumerate(slots) if s is None]

@@ -520,3 +520,30 @@ def request_workload(req: Request, dt_cap: float = 0.25) -> Workload:
     w.dt = np.full(w.n, dt_cap)
     w.name = f"request{req.rid}_n{req.n}"
     return w
+
+
+def request_workload_pooled(req: Request, pool: Workload, dt_cap: float = 0.25) -> Workload:
+    """The halo of one request drawn from ``pool``, one large Eddington sample
+    of the same truncated Hernquist halo (``hernquist_halo``): a random subset
+    of req.n of its particles (itself an Eddington sample of that halo, so the
+    particle mass is 1/N) turned by a random rotation, with the request's s0
+    and Philox seed; all particles active, every dt = dt_cap.  For streams
+    whose requests are too many or too large to sample one by one."""
+    if req.n > pool.n:
+        raise ValueError(f"request of {req.n} particles from a pool of {pool.n}")
+    rng = _rng(req.ic_seed)
+    idx = np.sort(rng.choice(pool.n, size=req.n, replace=False))
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))                 # a uniformly random rotation (or reflection)
+    pos = q @ np.stack([pool.x[idx], pool.y[idx], pool.z[idx]])
+    vel = q @ np.stack([pool.vx[idx], pool.vy[idx], pool.vz[idx]])
+    n = int(req.n)
+    return Workload(
+        name=f"request{req.rid}_n{n}_pooled",
+        x=pos[0].copy(), y=pos[1].copy(), z=pos[2].copy(),
+        vx=vel[0].copy(), vy=vel[1].copy(), vz=vel[2].copy(), mass=1.0 / n,
+        id=np.arange(n, dtype=np.uint32), state=np.zeros(n, dtype=np.uint8),
+        active=np.arange(n, dtype=np.int32), dt=np.full(n, dt_cap),
+        periodic=False, box=0.0, n_ngb=pool.n_ngb, xsec=XSEC_YUKAWA, sigma0=req.s0,
+        w0=pool.w0, model=MODEL_ELASTIC, delta=0.0, seed=req.philox_seed, step=0,
+        meta=dict(pool=pool.name, r=np.sqrt(pos[0] ** 2 + pos[1] ** 2 + pos[2] ** 2)))
