@@ -341,7 +341,28 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                     const float Pmax = f * (8.0f / ((float)SIDM_PI * ((h32 * h32) * h32)));
                     const double near = A.band_p * fmax((double)Pmax, u) + A.band;
                     P = pair_allowed(A, i, j) ? (double)P32 : 0.0;
-                    exact = fabs(P - u) <= near;
+                    // The FP32 separation carries rounding errors of the size
+                    // of the two leaves' reach (centre distance plus both
+                    // half-diagonals); below 8 h they move P by less than
+                    // 3e-6 of its centre value, inside band_p.  Leaves reaching
+                    // further (Morton neighbours spread over a jump of the
+                    // curve) take the FP64 evaluation.
+                    double cdx = box_centre(bj, 0) - box_centre(bi, 0);
+                    double cdy = box_centre(bj, 1) - box_centre(bi, 1);
+                    double cdz = box_centre(bj, 2) - box_centre(bi, 2);
+                    if (PERIODIC) {
+                        const double half = 0.5 * A.box;
+                        cdx = cdx >= half ? cdx - A.box : (cdx < -half ? cdx + A.box : cdx);
+                        cdy = cdy >= half ? cdy - A.box : (cdy < -half ? cdy + A.box : cdy);
+                        cdz = cdz >= half ? cdz - A.box : (cdz < -half ? cdz + A.box : cdz);
+                    }
+                    auto half_diag = [](const double *b) {
+                        const double ex = b[3] - b[0], ey = b[4] - b[1], ez = b[5] - b[2];
+                        return 0.5 * sqrt((ex * ex + ey * ey) + ez * ez);
+                    };
+                    const double reach = sqrt((cdx * cdx + cdy * cdy) + cdz * cdz) + half_diag(bi) +
+                                         half_diag(bj);
+                    exact = fabs(P - u) <= near || !(reach <= 8.0 * A.h[a]);
                 }
                 if (exact) {
                     // physical separation, smoothing lengths and relative speed

@@ -133,3 +133,23 @@ def test_overlap_hernquist_1e6_full_size_sampled():
     assert st["n_events"] > 0
     ctx.close()
     torch.cuda.synchronize()
+
+
+def test_mixed_with_a_leaf_spread_over_a_curve_jump():
+    """A served request of 296,348 particles drawn from a pool of 2e6 (the
+    case that exposed it): a target's 33rd neighbour lies in a leaf about 80
+    units across (32 Morton neighbours on both sides of a jump of the curve)
+    whose centre is 59 units away, where FP32 offsets from the centre lose
+    more than band_r2.  Such leaves are tested in FP64, and the mixed step
+    equals the FP64 step (neighbours and h bit for bit, decisions, velocities)."""
+    import workloads as W
+    from gpu_helpers import gpu_step, assert_parity
+    from paper_2607_05504_amd import FP64, MIXED
+    pool = W.hernquist_halo(2_000_000, ic_seed=7)
+    req = W.serving_requests(1000, rate=20.0, n_max=2e6, steps=64)[42]
+    w = W.request_workload_pooled(req, pool)
+    print(f"[case] mixed, leaf over a curve jump: n={w.n}", flush=True)
+    g64 = gpu_step(w, precision=FP64)
+    g32 = gpu_step(w, precision=MIXED)
+    assert g64["stats"]["error"] == 0 and g32["stats"]["error"] == 0
+    assert_parity(w, g32, g64, mixed=True)
