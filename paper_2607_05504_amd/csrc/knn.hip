@@ -603,34 +603,29 @@ void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
                     dly = dly >= half ? dly - box : (dly < -half ? dly + box : dly);
                     dlz = dlz >= half ? dlz - box : (dlz < -half ? dlz + box : dlz);
                 }
-                // The FP32 separation adds the centre's offset and the
-                // particle's, each rounded; its error grows with their size,
-                // the leaf's reach (centre distance plus half-diagonal).  While
-                // the reach is below 16 sqrt(T) the error of r^2 stays below
-                // 7e-6 T, inside band_r2; a leaf reaching further (32 Morton
-                // neighbours spread over a jump of the curve) is tested in FP64.
-                const double hx = cb[u][3] - cb[u][0], hy = cb[u][4] - cb[u][1],
-                             hz = cb[u][5] - cb[u][2];
-                const double reach = sqrt((dlx * dlx + dly * dly) + dlz * dlz) +
-                                     0.5 * sqrt((hx * hx + hy * hy) + hz * hz);
-                if (!(reach * reach <= 256.0 * T)) {
+                // Each FP32 component of the separation a = (centre - target)
+                // + f, f the particle's offset from the leaf centre, errs by
+                // at most 2^-23 (|a| + |f|).  While |a| + |f| stays below
+                // 16 sqrt(T) the error of r^2 stays below 7e-6 T, inside
+                // band_r2; a particle further from its leaf centre (32 Morton
+                // neighbours spread over a jump of the curve) is tested in
+                // FP64.  (|a| + |f|)^2 <= 2 (a^2 + f^2), so no square root.
+                const float ex = (float)dlx, ey = (float)dly, ez = (float)dlz;
+                const float T32 = __double2float_ru(T * (1.0 + A.band_r2));
+                const float Tfar = __double2float_rd(127.0 * T);
 #pragma unroll
-                    for (int q = 0; q < PPL; ++q) {
-                        const int64_t j = s0 + q * TS + tl;
+                for (int q = 0; q < PPL; ++q) {
+                    const int qq = u * PPL + q;
+                    float ax = ex + fx[qq], ay = ey + fy[qq], az = ez + fz[qq];
+                    if (PERIODIC) { ax = wrap32(ax, box32); ay = wrap32(ay, box32); az = wrap32(az, box32); }
+                    const int64_t j = s0 + q * TS + tl;
+                    const float v = (ax * ax + ay * ay) + az * az;
+                    const float f2 = (fx[qq] * fx[qq] + fy[qq] * fy[qq]) + fz[qq] * fz[qq];
+                    if (!(v + f2 <= Tfar)) {
                         const int64_t jc = j < n ? j : s0;
                         rq[q] = sep2_sel<PERIODIC>(px, py, pz, A.xs[jc], A.ys[jc], A.zs[jc], box);
                         pq[q] = j < n && rq[q] <= T && j != i;
-                    }
-                } else {
-                    const float ex = (float)dlx, ey = (float)dly, ez = (float)dlz;
-                    const float T32 = __double2float_ru(T * (1.0 + A.band_r2));
-#pragma unroll
-                    for (int q = 0; q < PPL; ++q) {
-                        const int qq = u * PPL + q;
-                        float ax = ex + fx[qq], ay = ey + fy[qq], az = ez + fz[qq];
-                        if (PERIODIC) { ax = wrap32(ax, box32); ay = wrap32(ay, box32); az = wrap32(az, box32); }
-                        const int64_t j = s0 + q * TS + tl;
-                        const float v = (ax * ax + ay * ay) + az * az;
+                    } else {
                         rq[q] = (double)v;
                         pq[q] = j < n && v <= T32 && j != i;
                     }

@@ -322,11 +322,35 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                     const double *bi = A.nodes + (int64_t)(i / SIDM_LEAF) * 6;
                     const double *bj = A.nodes + (int64_t)(j / SIDM_LEAF) * 6;
                     const float bx = (float)A.box;
-                    float dx = (float)(box_centre(bj, 0) - box_centre(bi, 0)) + (A.xo[j] - A.xo[i]);
-                    float dy = (float)(box_centre(bj, 1) - box_centre(bi, 1)) + (A.yo[j] - A.yo[i]);
-                    float dz = (float)(box_centre(bj, 2) - box_centre(bi, 2)) + (A.zo[j] - A.zo[i]);
+                    double cdx = box_centre(bj, 0) - box_centre(bi, 0);
+                    double cdy = box_centre(bj, 1) - box_centre(bi, 1);
+                    double cdz = box_centre(bj, 2) - box_centre(bi, 2);
+                    if (PERIODIC) {
+                        const double half = 0.5 * A.box;
+                        cdx = cdx >= half ? cdx - A.box : (cdx < -half ? cdx + A.box : cdx);
+                        cdy = cdy >= half ? cdy - A.box : (cdy < -half ? cdy + A.box : cdy);
+                        cdz = cdz >= half ? cdz - A.box : (cdz < -half ? cdz + A.box : cdz);
+                    }
+                    const float oix = A.xo[i], oiy = A.yo[i], oiz = A.zo[i];
+                    const float ojx = A.xo[j], ojy = A.yo[j], ojz = A.zo[j];
+                    float dx = (float)cdx + (ojx - oix);
+                    float dy = (float)cdy + (ojy - oiy);
+                    float dz = (float)cdz + (ojz - oiz);
                     if (PERIODIC) { dx = wrap32(dx, bx); dy = wrap32(dy, bx); dz = wrap32(dz, bx); }
-                    const float r32 = (float)A.lphys * sqrtf((dx * dx + dy * dy) + dz * dz);
+                    const float d2 = (dx * dx + dy * dy) + dz * dz;
+                    // Each FP32 component of the separation errs by at most
+                    // 3 2^-24 (|d| + |o_i| + |o_j|), d the separation and o
+                    // the particles' offsets from their leaf centres; while
+                    // that sum stays below 8 h the error moves P by less than
+                    // 3e-6 of its centre value, inside band_p.  Particles far
+                    // from their leaf centres (Morton neighbours spread over a
+                    // jump of the curve) take the FP64 evaluation.  The sum's
+                    // square is at most 3 (d^2 + o_i^2 + o_j^2).
+                    const float o2 = ((oix * oix + oiy * oiy) + oiz * oiz) +
+                                     ((ojx * ojx + ojy * ojy) + ojz * ojz);
+                    const float hl = (float)A.h[a];
+                    const bool far = !(3.0f * (d2 + o2) <= 63.0f * (hl * hl));
+                    const float r32 = (float)A.lphys * sqrtf(d2);
                     const float h32 = (float)(A.lphys * A.h[a]);
                     const float vx = (float)(A.vxs[i] - A.vxs[j]), vy = (float)(A.vys[i] - A.vys[j]),
                                 vz = (float)(A.vzs[i] - A.vzs[j]);
@@ -341,28 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                     const float Pmax = f * (8.0f / ((float)SIDM_PI * ((h32 * h32) * h32)));
                     const double near = A.band_p * fmax((double)Pmax, u) + A.band;
                     P = pair_allowed(A, i, j) ? (double)P32 : 0.0;
-                    // The FP32 separation carries rounding errors of the size
-                    // of the two leaves' reach (centre distance plus both
-                    // half-diagonals); below 8 h they move P by less than
-                    // 3e-6 of its centre value, inside band_p.  Leaves reaching
-                    // further (Morton neighbours spread over a jump of the
-                    // curve) take the FP64 evaluation.
-                    double cdx = box_centre(bj, 0) - box_centre(bi, 0);
-                    double cdy = box_centre(bj, 1) - box_centre(bi, 1);
-                    double cdz = box_centre(bj, 2) - box_centre(bi, 2);
-                    if (PERIODIC) {
-                        const double half = 0.5 * A.box;
-                        cdx = cdx >= half ? cdx - A.box : (cdx < -half ? cdx + A.box : cdx);
-                        cdy = cdy >= half ? cdy - A.box : (cdy < -half ? cdy + A.box : cdy);
-                        cdz = cdz >= half ? cdz - A.box : (cdz < -half ? cdz + A.box : cdz);
-                    }
-                    auto half_diag = [](const double *b) {
-                        const double ex = b[3] - b[0], ey = b[4] - b[1], ez = b[5] - b[2];
-                        return 0.5 * sqrt((ex * ex + ey * ey) + ez * ez);
-                    };
-                    const double reach = sqrt((cdx * cdx + cdy * cdy) + cdz * cdz) + half_diag(bi) +
-                                         half_diag(bj);
-                    exact = fabs(P - u) <= near || !(reach <= 8.0 * A.h[a]);
+                    exact = far || fabs(P - u) <= near;
                 }
                 if (exact) {
                     // physical separation, smoothing lengths and relative speed
