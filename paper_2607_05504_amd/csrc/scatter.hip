@@ -340,16 +340,18 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
                     const float d2 = (dx * dx + dy * dy) + dz * dz;
                     // Each FP32 component of the separation errs by at most
                     // 3 2^-24 (|d| + |o_i| + |o_j|), d the separation and o
-                    // the particles' offsets from their leaf centres; while
-                    // that sum stays below 8 h the error moves P by less than
-                    // 3e-6 of its centre value, inside band_p.  Particles far
-                    // from their leaf centres (Morton neighbours spread over a
-                    // jump of the curve) take the FP64 evaluation.  The sum's
-                    // square is at most 3 (d^2 + o_i^2 + o_j^2).
+                    // the particles' offsets from their leaf centres.  The
+                    // spline's slope is at most 1.5 W(0) / h, so while that sum
+                    // stays below 12 h the error moves P by less than 5.6e-6 of
+                    // its centre value (under 7e-6 with the other FP32
+                    // roundings), inside band_p.  Particles far from their leaf
+                    // centres (Morton neighbours spread over a jump of the
+                    // curve) take the FP64 evaluation.  The sum's square is at
+                    // most 3 (d^2 + o_i^2 + o_j^2).
                     const float o2 = ((oix * oix + oiy * oiy) + oiz * oiz) +
                                      ((ojx * ojx + ojy * ojy) + ojz * ojz);
                     const float hl = (float)A.h[a];
-                    const bool far = !(3.0f * (d2 + o2) <= 63.0f * (hl * hl));
+                    const bool far = !(3.0f * (d2 + o2) <= 143.0f * (hl * hl));
                     const float r32 = (float)A.lphys * sqrtf(d2);
                     const float h32 = (float)(A.lphys * A.h[a]);
                     const float vx = (float)(A.vxs[i] - A.vxs[j]), vy = (float)(A.vys[i] - A.vys[j]),
