@@ -12,6 +12,15 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Clears, in one launch, the bounding-box accumulators (when the box is
+// found from the particles) and the digit totals of the six sort passes.
+__global__ void k_tree_reset(unsigned long long *bounds, int clear_bounds, uint32_t *dtot, int ndtot)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (clear_bounds && t < 6) bounds[t] = t < 3 ? ~0ull : 0ull;
+    if (t < ndtot) dtot[t] = 0u;
+}
+
 __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n)
 {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
@@ -552,14 +561,12 @@ hipError_t launch_build_tree(sidm_ctx *c, const sidm_particles *p)
     hipStream_t s = c->stream;
     const int64_t n = p->n;
     const sidm_config &cfg = c->cfg;
-    if (!cfg.periodic) {
-        // tiny fills through a kernel (no memset nodes in captured graphs)
-        launch_fill_u64(c->bounds, ~0ull, 3, s);
-        launch_fill_u64(c->bounds + 3, 0ull, 3, s);
+    // tiny clears through a kernel (no memset nodes in captured graphs)
+    k_tree_reset<<<(6 * 256 + kBlock - 1) / kBlock, kBlock, 0, s>>>(c->bounds, cfg.periodic ? 0 : 1,
+                                                                   c->dtot, 6 * 256);
+    if (!cfg.periodic)
         k_bounds<<<grid_for(n, kBlock, 256), kBlock, 0, s>>>(p->x, p->y, p->z, n, c->bounds);
-    }
     const int nblk = (int)((n + SIDM_SORT_TILE - 1) / SIDM_SORT_TILE);
-    launch_fill_i32((int32_t *)c->dtot, 0, 6 * 256, s);
     k_morton<<<nblk, 256, 0, s>>>(p->x, p->y, p->z, n, cfg.periodic, cfg.box, c->bounds, c->key0,
                                   c->val0, c->dtot, c->hist, nblk);
     uint64_t *kin = c->key0, *kout = c->key1;
