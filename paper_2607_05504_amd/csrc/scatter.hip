@@ -610,18 +610,16 @@ __global__ __launch_bounds__(1024) void k_finish(StepArgs A)
     }
 }
 
-__global__ void k_step_reset(DevStats *st, int32_t *ctl)
+// Zeroes the step's statistics and pass counters; with nt_dev given, the
+// candidate count is the number of targets times k.
+__global__ void k_step_reset(DevStats *st, int32_t *ctl, const int32_t *nt_dev, int k)
 {
     if (threadIdx.x == 0) {
         DevStats z = {};
+        if (nt_dev) z.n_cand = (unsigned long long)(*nt_dev) * (unsigned long long)k;
         *st = z;
         ctl[0] = ctl[1] = ctl[2] = ctl[3] = 0;
     }
-}
-
-__global__ void k_count_cand(DevStats *st, const int32_t *nt_dev, int k)
-{
-    if (threadIdx.x == 0) st->n_cand = (unsigned long long)(*nt_dev) * (unsigned long long)k;
 }
 
 // ----------------------------------------------------------------------------
@@ -764,8 +762,7 @@ template <bool P, bool M, bool O = false>
 void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s)
 {
     const int64_t total = n_active * A.stride;
-    k_step_reset<<<1, 64, 0, s>>>(A.st, A.ctl);
-    if (!O) k_count_cand<<<1, 64, 0, s>>>(A.st, A.nt_dev, A.k);
+    k_step_reset<<<1, 64, 0, s>>>(A.st, A.ctl, O ? nullptr : A.nt_dev, A.k);
     phase_begin(c, PH_EVAL);
     // at least as many workgroups as are resident at once (the staging
     // buffer's LDS allows six per CU), more for long candidate lists (about
