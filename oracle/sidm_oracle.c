@@ -30,12 +30,12 @@
  *   random numbers  Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11),
  *                   keyed on the seed, counter = (lower ID, higher ID, step,
  *                   purpose) -- the paper only says a random number is drawn
- *   acceptance      every candidate (i|j) is evaluated once with the
- *                   step-start velocities; accepted ones are then processed
- *                   serially in increasing (priority, id_i, id_j) order, each
- *                   re-evaluated with the current velocities and the same
- *                   draw, so a particle's successive scatters build on each
- *                   other (sec. 4.5, immediate update)
+ *   acceptance      every directed candidate (i|j) takes one turn, in
+ *                   increasing (priority, id_i, id_j) with a Philox priority;
+ *                   at its turn P is computed with the velocities as they are
+ *                   then, so a pair evaluated after a kick of one of its
+ *                   particles sees the kicked velocity (sec. 4.5, immediate
+ *                   update), and it scatters iff u < P
  *   kick            centre-of-momentum kick with a direction uniform on the
  *                   sphere and outgoing relative speed eps * w (sec. 4.1);
  *                   eps = 1 elastic, constant eps, or a two-state model whose
@@ -73,10 +73,10 @@
                                     the target does not recoil */
 
 /* per-candidate info word */
-#define OREF_CAND_ACCEPT0 1u   /* accepted by the step-start evaluation        */
-#define OREF_CAND_SCATTER 2u   /* produced a kick                              */
-#define OREF_CAND_FLAGGED 4u   /* some evaluation had |P - u| < band            */
-/* bits 8..31: index of the resolution pass that decided it (0: not accepted) */
+#define OREF_CAND_ACCEPT0 1u   /* u < P with the step-start velocities (diagnostic) */
+#define OREF_CAND_SCATTER 2u   /* produced a kick at its turn                       */
+#define OREF_CAND_FLAGGED 4u   /* |P - u| < band at its turn                        */
+/* bits 8..31: a kick's depth in the chain of kicks (0: no kick) */
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon et al. 2011): 10 rounds of the 4x32 S-box with the   */
@@ -409,19 +409,19 @@ static void do_kick(const phys_t *ph, int32_t i, int32_t j, const double *mass, 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Scatter step                                                              */
+/* Scatter step (sec. 4.1, 4.5)                                              */
 /* ------------------------------------------------------------------------ */
+/* one directed candidate (i|j): its place in the serial order and its slot */
 typedef struct {
-    int64_t c;          /* candidate index a*k + s */
-    int32_t i, j;       /* particle indices */
-    double u, W, m_j, dt;
-    uint64_t prio;
+    uint64_t prio;      /* priority word of the pair draw */
     uint32_t id_i, id_j;
-} acc_t;
+    int64_t c;          /* candidate slot a*stride + s */
+    int64_t a;          /* its row */
+} cand_ord_t;
 
-static int acc_cmp(const void *pa, const void *pb)
+static int cand_ord_cmp(const void *pa, const void *pb)
 {
-    const acc_t *a = (const acc_t *)pa, *b = (const acc_t *)pb;
+    const cand_ord_t *a = (const cand_ord_t *)pa, *b = (const cand_ord_t *)pb;
     if (a->prio != b->prio) return a->prio < b->prio ? -1 : 1;
     if (a->id_i != b->id_i) return a->id_i < b->id_i ? -1 : 1;
     if (a->id_j != b->id_j) return a->id_j < b->id_j ? -1 : 1;
@@ -433,17 +433,52 @@ typedef struct {
     int32_t n_passes; double max_p;
 } oref_stats;
 
-/*
- * v and state are updated in place.  cand_info[n_active*k] (optional) gets the
- * per-candidate flags/pass index.  band: |P - u| < band flags an evaluation.
- */
 double oref_overlap_g(double hi, double hj, double r);
+
+/* W (one-sided spline or tabulated overlap) and P of candidate slot ci of row
+ * a with the velocities as they are now; all lengths and the relative speed
+ * in physical units */
+static double candidate_probability(const double *x, const double *y, const double *z,
+                                    const double *vx, const double *vy, const double *vz,
+                                    const double *mass, double m_scalar, const uint8_t *state,
+                                    int periodic, double box, int32_t i, int32_t j,
+                                    const double *h, const double *h_all, int64_t a,
+                                    const double *dt, int xsec, double s0, double w0, int model)
+{
+    double r = oref_len * sqrt(oref_r2(x[i], y[i], z[i], x[j], y[j], z[j], periodic, box));
+    double W = h_all ? oref_overlap_g(oref_len * h_all[i], oref_len * h_all[j], r)
+                     : oref_kernel(r, oref_len * h[a]);
+    double w = oref_vel * rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
+    double sig = oref_sigma(w, xsec, s0, w0);
+    double mj = mass ? mass[j] : m_scalar;
+    double P = pair_probability(mj, sig, w, W, dt[a]);
+    if (model == OREF_MODEL_BEAM && state[i] == state[j]) P = 0.0;
+    return P;
+}
 
 /*
  * Shared by both estimators.  Row a of ngb (stride entries) holds the
  * partners of active[a]; count[a] of them are used (all stride when count is
  * NULL).  The geometric factor is W(r_ij, h[a]) (one-sided), or the
  * tabulated overlap of h_all[i] and h_all[j] when h_all is given.
+ *
+ * Sec. 4.5: pairs are processed one after another, and a pair evaluated after
+ * a kick of one of its particles sees the kicked velocity (immediate update).
+ * The paper's order is that of its loop over particles and tasks; here every
+ * directed candidate (i|j) takes its turn in increasing (priority, id_i,
+ * id_j), the priority being a Philox word of the pair, so the order does not
+ * depend on storage.  At its turn a candidate's P is computed with the
+ * current velocities and it scatters iff u < P, u its own decision draw;
+ * every candidate has exactly one turn.
+ *
+ * v and state are updated in place.  cand_info[n_active*stride] (optional):
+ * ACCEPT0 if u < P with the step-start velocities (a diagnostic), FLAGGED if
+ * |P - u| < band at its turn, SCATTER if it kicked, and for a kick its depth
+ * in bits 8..31: 1 + the larger depth of the last earlier kicks of its two
+ * particles (0 for a particle not yet kicked), i.e. the round in which a
+ * parallel matching of the kicks in this order would apply it.  Stats:
+ * n_accept0, n_p_ge_1 and max_p of the step-start evaluation; n_events kicks;
+ * n_flagged flagged turns; n_passes the largest depth.
  */
 static int scatter_core(int64_t n, const double *x, const double *y, const double *z,
                         double *vx, double *vy, double *vz, const double *mass, double m_scalar,
@@ -456,84 +491,67 @@ static int scatter_core(int64_t n, const double *x, const double *y, const doubl
 {
     phys_t ph = {xsec, s0, w0, model, eps, delta, seed, step};
     oref_stats st; memset(&st, 0, sizeof st);
-    int64_t cap = 1024, n_acc = 0;
-    acc_t *acc = (acc_t *)malloc((size_t)cap * sizeof(acc_t));
-    if (!acc) return OREF_E_NOMEM;
     if (cand_info) memset(cand_info, 0, (size_t)(n_active * (int64_t)stride) * sizeof(uint32_t));
 
-    /* evaluation 0: every candidate with the step-start velocities */
+    int64_t n_cand = 0;
+    for (int64_t a = 0; a < n_active; ++a) {
+        int len = stride;
+        if (count && count[a] < len) len = count[a];
+        n_cand += len;
+    }
+    st.n_cand = n_cand;
+    cand_ord_t *ord = (cand_ord_t *)malloc((size_t)(n_cand > 0 ? n_cand : 1) * sizeof(cand_ord_t));
+    int32_t *depth = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+    if (!ord || !depth) { free(ord); free(depth); return OREF_E_NOMEM; }
+
+    /* the step-start evaluation (diagnostics only) and every candidate's key */
+    int64_t t = 0;
     for (int64_t a = 0; a < n_active; ++a) {
         int32_t i = active[a];
         int len = stride;
         if (count && count[a] < len) len = count[a];
-        st.n_cand += len;
         for (int s = 0; s < len; ++s) {
             int64_t ci = a * (int64_t)stride + s;
             int32_t j = ngb[ci];
-            /* physical separation, smoothing lengths and relative speed */
-            double r = oref_len * sqrt(oref_r2(x[i], y[i], z[i], x[j], y[j], z[j], periodic, box));
-            double W = h_all ? oref_overlap_g(oref_len * h_all[i], oref_len * h_all[j], r)
-                             : oref_kernel(r, oref_len * h[a]);
-            double w = oref_vel * rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
-            double sig = oref_sigma(w, xsec, s0, w0);
-            double mj = mass ? mass[j] : m_scalar;
-            double P = pair_probability(mj, sig, w, W, dt[a]);
-            if (model == OREF_MODEL_BEAM && state[i] == state[j]) P = 0.0;
+            double P = candidate_probability(x, y, z, vx, vy, vz, mass, m_scalar, state, periodic,
+                                             box, i, j, h, h_all, a, dt, xsec, s0, w0, model);
             double u = oref_uniform_decision(seed, step, id[i], id[j]);
             if (P > st.max_p) st.max_p = P;
             if (P >= 1.0) st.n_p_ge_1++;
-            if (fabs(P - u) < band) {
-                st.n_flagged++;
-                if (cand_info) cand_info[ci] |= OREF_CAND_FLAGGED;
-            }
             if (u < P) {
-                if (n_acc == cap) {
-                    cap *= 2;
-                    acc_t *nb = (acc_t *)realloc(acc, (size_t)cap * sizeof(acc_t));
-                    if (!nb) { free(acc); return OREF_E_NOMEM; }
-                    acc = nb;
-                }
-                uint32_t xr[4];
-                pair_draw(seed, step, id[i], id[j], PURPOSE_PRIORITY, xr);
-                acc_t e = {ci, i, j, u, W, mj, dt[a],
-                           direction_word(xr, id[i] < id[j]), id[i], id[j]};
-                acc[n_acc++] = e;
+                st.n_accept0++;
                 if (cand_info) cand_info[ci] |= OREF_CAND_ACCEPT0;
             }
+            uint32_t xr[4];
+            pair_draw(seed, step, id[i], id[j], PURPOSE_PRIORITY, xr);
+            cand_ord_t e = {direction_word(xr, id[i] < id[j]), id[i], id[j], ci, a};
+            ord[t++] = e;
         }
     }
-    st.n_accept0 = n_acc;
 
-    /* serial processing in increasing (priority, id_i, id_j) */
-    qsort(acc, (size_t)n_acc, sizeof(acc_t), acc_cmp);
-    /* pass index of each accepted candidate = 1 + the largest pass index of an
-     * earlier (smaller-key) accepted candidate sharing a particle: the round in
-     * which a parallel matching of local minima would decide it. */
-    int32_t *last_pass = (int32_t *)calloc((size_t)n, sizeof(int32_t));
-    if (!last_pass) { free(acc); return OREF_E_NOMEM; }
-    for (int64_t t = 0; t < n_acc; ++t) {
-        acc_t *c = &acc[t];
-        int32_t i = c->i, j = c->j;
-        int32_t pass = 1 + (last_pass[i] > last_pass[j] ? last_pass[i] : last_pass[j]);
-        last_pass[i] = last_pass[j] = pass;
-        if (pass > st.n_passes) st.n_passes = pass;
-        double w = oref_vel * rel_speed(vx[i], vy[i], vz[i], vx[j], vy[j], vz[j]);
-        double sig = oref_sigma(w, xsec, s0, w0);
-        double P = pair_probability(c->m_j, sig, w, c->W, c->dt);
-        if (model == OREF_MODEL_BEAM && state[i] == state[j]) P = 0.0;
-        if (fabs(P - c->u) < band) {
+    /* every candidate at its turn, with the velocities as they are then */
+    qsort(ord, (size_t)n_cand, sizeof(cand_ord_t), cand_ord_cmp);
+    for (t = 0; t < n_cand; ++t) {
+        const cand_ord_t *c = &ord[t];
+        int32_t i = active[c->a], j = ngb[c->c];
+        double P = candidate_probability(x, y, z, vx, vy, vz, mass, m_scalar, state, periodic,
+                                         box, i, j, h, h_all, c->a, dt, xsec, s0, w0, model);
+        double u = oref_uniform_decision(seed, step, id[i], id[j]);
+        if (fabs(P - u) < band) {
             st.n_flagged++;
             if (cand_info) cand_info[c->c] |= OREF_CAND_FLAGGED;
         }
-        if (cand_info) cand_info[c->c] |= (uint32_t)pass << 8;
-        if (c->u < P) {
+        if (u < P) {
             do_kick(&ph, i, j, mass, m_scalar, vx, vy, vz, state, id);
+            int32_t d = 1 + (depth[i] > depth[j] ? depth[i] : depth[j]);
+            depth[i] = depth[j] = d;
+            if (d > st.n_passes) st.n_passes = d;
             st.n_events++;
-            if (cand_info) cand_info[c->c] |= OREF_CAND_SCATTER;
+            if (cand_info) cand_info[c->c] |= OREF_CAND_SCATTER | ((uint32_t)d << 8);
         }
     }
-    free(last_pass);
-    free(acc);
+    free(depth);
+    free(ord);
     if (stats) *stats = st;
     return OREF_OK;
 }
