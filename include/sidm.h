@@ -55,11 +55,15 @@
  *     the lower/higher-ID target, 2 gives the priority.  Of a draw's words,
  *     (x0, x1) serve the lower-ID target and (x2, x3) the higher-ID target;
  *     u = (word >> 11) * 2^-53.
- *   - Every candidate (i|j) is evaluated once with the step-start
- *     velocities (accept iff u < P).  The accepted ones are then applied in
- *     increasing (priority, id_i, id_j) order, each re-evaluated with the
- *     current velocities and the same u.  The device runs this as passes: in
- *     each pass every particle scatters with at most one partner.
+ *   - Every directed candidate (i|j) takes exactly one turn, in increasing
+ *     (priority, id_i, id_j) with the priority word of the pair's draw; at
+ *     its turn P is computed with the velocities (and states) of that moment
+ *     and the candidate scatters iff u < P (sec. 4.5: a pair evaluated after
+ *     a kick of one of its particles sees the updated state).  The result is
+ *     exactly that serial order; the device gets it in parallel (passes in
+ *     which every particle scatters with at most one partner, and rounds
+ *     that check every candidate at its turn against the particles'
+ *     histories within the step, see scatter.hip).
  */
 #ifndef SIDM_H
 #define SIDM_H
@@ -95,13 +99,15 @@ enum { SIDM_EST_ONE_SIDED = 0, SIDM_EST_OVERLAP = 1 };
 #define SIDM_OVERLAP_NR 256
 
 /* per-candidate info word (optional output of sidm_scatter_step) */
-#define SIDM_CAND_ACCEPT0 1u   /* accepted by the step-start evaluation          */
-#define SIDM_CAND_SCATTER 2u   /* produced a kick                                */
-#define SIDM_CAND_FLAGGED 4u   /* an evaluation had |P - u| < flag_band          */
-/* bits 8..31: pass that decided the candidate (0 = not accepted at step start) */
+#define SIDM_CAND_ACCEPT0 1u   /* u < P with the step-start velocities (diagnostic) */
+#define SIDM_CAND_SCATTER 2u   /* kicked at its turn                                */
+#define SIDM_CAND_FLAGGED 4u   /* |P - u| < flag_band at its turn                   */
+/* bits 8..31: a kick's depth, 1 + the larger depth of the last earlier kicks
+ * of its two particles (0 if none): the pass in which a parallel matching of
+ * the kicks in turn order applies it.  0 for a candidate that did not kick. */
 
 typedef struct {
-    int32_t n_ngb;        /* neighbours per target, 1..64 (paper: 32)                    */
+    int32_t n_ngb;        /* neighbours per target, 1..63 (paper: 32)                    */
     int32_t kernel;       /* SIDM_KERNEL_CUBIC_SPLINE                                     */
     int32_t periodic;     /* 1: periodic cube [0, box)^3 with minimum image; 0: open      */
     int32_t xsec;         /* SIDM_XSEC_CONST: sigma/m = sigma0;
@@ -149,6 +155,13 @@ typedef struct {
      * 1) for physical storage; otherwise > 0 and finite (SIDM_E_INVAL). */
     double len_to_phys;
     double vel_to_phys;
+    /* Largest number of candidates one scattering step can list for the
+     * ordered replay of turns: those accepted with the step-start velocities
+     * plus those found to accept only at their turn.  0: an eighth of
+     * cap_active, at least 65536.  A step that needs more latches
+     * SIDM_E_OVERFLOW (sidm_sync).  Device memory grows by about 290 bytes
+     * per listed candidate.  0 .. 2^29. */
+    int64_t max_accept;
 } sidm_config;
 
 typedef struct {
@@ -165,10 +178,10 @@ typedef struct {
     int64_t n_cand;       /* candidates evaluated at step start (n_active * n_ngb)       */
     int64_t n_accept0;    /* accepted at step start                                      */
     int64_t n_events;     /* kicks applied                                               */
-    int64_t n_flagged;    /* evaluations with |P - u| < flag_band                        */
+    int64_t n_flagged;    /* turns with |P - u| < flag_band                              */
     int64_t n_p_ge_1;     /* step-start evaluations with P >= 1 (always accepted)        */
     int64_t n_recheck;    /* mixed form: evaluations redone in FP64                      */
-    int32_t n_passes;     /* resolution passes used                                      */
+    int32_t n_passes;     /* largest kick depth (see SIDM_CAND_* above)                  */
     int32_t error;        /* latched sidm_status of the device, 0 if none                */
     double max_p;         /* largest step-start P                                        */
 } sidm_stats;

@@ -53,7 +53,8 @@ class Config(ctypes.Structure):
                 ("band_r2", ctypes.c_double), ("band_p", ctypes.c_double),
                 ("xsec_n", ctypes.c_int32), ("xsec_w", ctypes.c_void_p),
                 ("xsec_sigma", ctypes.c_void_p), ("estimator", ctypes.c_int32),
-                ("len_to_phys", ctypes.c_double), ("vel_to_phys", ctypes.c_double)]
+                ("len_to_phys", ctypes.c_double), ("vel_to_phys", ctypes.c_double),
+                ("max_accept", ctypes.c_int64)]
 
 
 class Particles(ctypes.Structure):
@@ -148,12 +149,13 @@ def make_config(n_ngb=32, periodic=False, box=0.0, xsec=XSEC_CONST, sigma0=0.0, 
                 model=MODEL_ELASTIC, eps=1.0, delta=0.0, c_sidm=0.1, precision=FP64,
                 flag_band=1e-9, band_r2=1e-5, band_p=1e-5, table_w=None,
                 table_sigma=None, estimator=EST_ONE_SIDED, len_to_phys=1.0,
-                vel_to_phys=1.0) -> Config:
+                vel_to_phys=1.0, max_accept=0) -> Config:
     """A sidm_config.  table_w / table_sigma (numpy arrays) give a tabulated
     cross-section (xsec = XSEC_TABLE); the Config keeps them alive.
     estimator = EST_OVERLAP reserves what the overlap-estimator calls need.
     len_to_phys / vel_to_phys: stored -> physical factors of lengths and
-    relative speeds (comoving storage)."""
+    relative speeds (comoving storage).  max_accept: candidates a step can
+    list for its ordered replay (0: the library's default)."""
     tw = ts = None
     n_t = 0
     if table_w is not None:
@@ -165,7 +167,7 @@ def make_config(n_ngb=32, periodic=False, box=0.0, xsec=XSEC_CONST, sigma0=0.0, 
                float(c_sidm), float(flag_band), float(band_r2), float(band_p), n_t,
                tw.ctypes.data if tw is not None else None,
                ts.ctypes.data if ts is not None else None, int(estimator),
-               float(len_to_phys), float(vel_to_phys))
+               float(len_to_phys), float(vel_to_phys), int(max_accept))
     c._tables = (tw, ts)
     return c
 

@@ -121,7 +121,9 @@ hipError_t launch_advance(sidm_ctx *c, double *x, double *y, double *z, double *
                           double dt_cap, double gm, double a, double *dt_next, double *dt_step)
 {
     hipStream_t s = c->stream;
-    hipError_t e = launch_fill_u64(c->adv_min, ~0ull, 1, s);
+    // the ordered encoding of +inf: with no active particle (or no finite
+    // bound) the step is dt_cap itself
+    hipError_t e = launch_fill_u64(c->adv_min, 0xFFF0000000000000ull, 1, s);
     if (e != hipSuccess) return e;
     if (n_active > 0) k_min_dt<<<grid_for(n_active), kBlock, 0, s>>>(dt_sidm, n_active, c->adv_min);
     k_advance<<<grid_for(n), kBlock, 0, s>>>(x, y, z, vx, vy, vz, n, n_active, c->adv_min, dt_cap,

@@ -15,24 +15,29 @@ namespace {
 // Allocation plan: every buffer the context owns, sized from the capacities.
 struct Plan {
     struct Item { void **dst; size_t bytes; };
-    Item items[64];
+    static constexpr int kMax = 96;
+    Item items[kMax];
     int n = 0;
     size_t total = 0;
     void add(void **dst, size_t bytes)
     {
+        if (n >= kMax) abort();          // a buffer added without raising kMax
         bytes = (bytes + 255) & ~(size_t)255;
         items[n++] = Item{dst, bytes};
         total += bytes;
     }
 };
 
-int64_t acc_capacity(int64_t cap_active, int k)
+// Candidates a step can list (accepted at the step start or at their turn):
+// the configuration's max_accept, else an eighth of the active capacity, at
+// least 65536.  The paper's criterion keeps every P(i|j) below C_SIDM, and the
+// workloads accept about 0.01 to 0.2 candidates per active particle.
+int64_t acc_capacity(const sidm_config &cfg, int64_t cap_active)
 {
-    int64_t full = cap_active * (int64_t)k;
-    const int64_t floor_cap = (int64_t)1 << 20;
-    if (full <= floor_cap) return full > 0 ? full : 1;
-    int64_t quarter = full / 4;
-    return quarter > floor_cap ? quarter : floor_cap;
+    if (cfg.max_accept > 0) return cfg.max_accept;
+    const int64_t floor_cap = (int64_t)1 << 16;
+    const int64_t e = cap_active / 8;
+    return e > floor_cap ? e : floor_cap;
 }
 
 void make_plan(sidm_ctx *c, Plan &P)
@@ -64,15 +69,28 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(tlist, NA, int32_t); ADD(slot, NA, int32_t);
     ADD(blk, (N + SIDM_SCAN_TILE - 1) / SIDM_SCAN_TILE + 1, int32_t);
     ADD(nt_dev, 1, int32_t);
-    const int64_t CA = acc_capacity(NA, k);
+    (void)k;
+    const int64_t CA = acc_capacity(c->cfg, NA);
+    const int64_t CR = 4 * CA;              // each turn writes two records; re-rounds add more
     c->cap_acc = CA;
+    c->cap_rec = CR;
+    ADD(mem.i, CA, int32_t); ADD(mem.j, CA, int32_t); ADD(mem.cand, CA, int32_t);
+    ADD(mem.u, CA, double); ADD(mem.W, CA, double); ADD(mem.dt, CA, double);
+    ADD(mem.prio, CA, uint64_t); ADD(mem.idpair, CA, uint64_t);
+    ADD(mmark, CA, int32_t);
+    ADD(wl[0], CA, int32_t); ADD(wl[1], CA, int32_t);
+    ADD(plist, 2 * CA, int32_t);
+    ADD(trec.prio, CR, uint64_t); ADD(trec.idpair, CR, uint64_t);
+    ADD(trec.vx, CR, double); ADD(trec.vy, CR, double); ADD(trec.vz, CR, double);
+    ADD(trec.mem, CR, int32_t); ADD(trec.prev, CR, int32_t); ADD(trec.part, CR, int32_t);
+    ADD(trec.info, CR, uint32_t);
+    ADD(head, N, int32_t);
+    ADD(tmin, N, unsigned long long);
+    ADD(rstats, 1, RoundStats);
     for (int b = 0; b < 2; ++b) {
-        ADD(acc[b].i, CA, int32_t); ADD(acc[b].j, CA, int32_t); ADD(acc[b].cand, CA, int32_t);
-        ADD(acc[b].u, CA, double); ADD(acc[b].W, CA, double); ADD(acc[b].dt, CA, double);
-        ADD(acc[b].prio, CA, uint64_t); ADD(acc[b].idpair, CA, uint64_t);
         ADD(claim1[b], N, unsigned long long); ADD(claim2[b], N, unsigned long long);
     }
-    ADD(acc_count, 8, int32_t);
+    ADD(acc_count, 16, int32_t);
     ADD(dstats, 1, DevStats);
     ADD(derr, 1, unsigned int);
     ADD(xt_w, SIDM_XSEC_TABLE_MAX, double); ADD(xt_s, SIDM_XSEC_TABLE_MAX, double);
@@ -109,7 +127,8 @@ sidm_status check_config(const sidm_config *cfg)
     if (!cfg) return SIDM_E_INVAL;
     if (!unit_factor_ok(cfg->len_to_phys) || !unit_factor_ok(cfg->vel_to_phys))
         return SIDM_E_INVAL;
-    if (cfg->n_ngb < 1 || cfg->n_ngb > 64) return SIDM_E_INVAL;
+    if (cfg->n_ngb < 1 || cfg->n_ngb > 63) return SIDM_E_INVAL;
+    if (cfg->max_accept < 0 || cfg->max_accept > ((int64_t)1 << 29)) return SIDM_E_INVAL;
     if (cfg->kernel != SIDM_KERNEL_CUBIC_SPLINE) return SIDM_E_INVAL;
     if (cfg->periodic && !(cfg->box > 0.0)) return SIDM_E_INVAL;
     if (cfg->xsec != SIDM_XSEC_CONST && cfg->xsec != SIDM_XSEC_YUKAWA &&
@@ -146,7 +165,7 @@ sidm_status hip_fail(sidm_ctx *c, hipError_t e, const char *what)
 sidm_status status_from_bits(unsigned int bits)
 {
     if (!bits) return SIDM_OK;
-    if (bits & (DERR_OVERFLOW | DERR_NGB_OVERFLOW)) return SIDM_E_OVERFLOW;
+    if (bits & (DERR_OVERFLOW | DERR_NGB_OVERFLOW | DERR_HISTORY)) return SIDM_E_OVERFLOW;
     return SIDM_E_INVAL;
 }
 
@@ -154,6 +173,15 @@ bool test_fail_alloc()
 {
     const char *e = getenv("SIDM_TEST_FAIL_ALLOC");
     return e && e[0] == '1';
+}
+
+// rounds of the scattering step run as grid launches (the rest in one
+// workgroup); tests lower it to exercise the one-workgroup tail
+int test_device_rounds()
+{
+    const char *e = getenv("SIDM_TEST_DEVICE_ROUNDS");
+    if (e && e[0] >= '0' && e[0] <= '9') return atoi(e);
+    return 6;
 }
 
 }  // namespace
@@ -197,6 +225,7 @@ sidm_status sidm_footprint(const sidm_config *cfg, int64_t cap_n, int64_t cap_ac
 {
     if (!bytes || check_config(cfg) != SIDM_OK) return SIDM_E_INVAL;
     if (cap_n < cfg->n_ngb + 2 || cap_active < 0 || cap_active > cap_n) return SIDM_E_INVAL;
+    if (cap_active * (int64_t)cfg->n_ngb > (int64_t)INT32_MAX) return SIDM_E_CAPACITY;
     sidm_ctx tmp;
     memset(&tmp, 0, sizeof tmp);
     tmp.cfg = *cfg;
@@ -217,6 +246,8 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
     if (cap_n < cfg->n_ngb + 2 || cap_n > ((int64_t)1 << 31) - 1 || cap_active < 1 ||
         cap_active > cap_n)
         return SIDM_E_INVAL;
+    // a candidate's slot a * n_ngb + s is kept in 32 bits
+    if (cap_active * (int64_t)cfg->n_ngb > (int64_t)INT32_MAX) return SIDM_E_CAPACITY;
     sidm_ctx *c = (sidm_ctx *)calloc(1, sizeof(sidm_ctx));
     if (!c) return SIDM_E_NOMEM;
     c->cfg = *cfg;
@@ -252,7 +283,12 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
         launch_fill_u64(c->claim2[b], ~0ull, cap_n, s);
     }
     launch_fill_i32((int32_t *)c->derr, 0, 1, s);
-    launch_fill_i32(c->acc_count, 0, 8, s);
+    launch_fill_i32(c->acc_count, 0, 16, s);
+    // histories and replay marks start (and are left by every step) empty
+    launch_fill_i32(c->head, -1, cap_n, s);
+    launch_fill_u64(c->tmin, ~0ull, cap_n, s);
+    launch_fill_i32(c->mmark, 0, c->cap_acc, s);
+    c->dev_rounds = test_device_rounds();
     launch_fill_i32((int32_t *)c->dstats, 0, (int64_t)(sizeof(DevStats) / 4), s);
     hipError_t e = copy_table(c);
     if (e == hipSuccess && c->cfg.estimator == SIDM_EST_OVERLAP) e = launch_overlap_table(c);
@@ -734,14 +770,15 @@ sidm_status sidm_sync(sidm_ctx *c, sidm_stats *out)
         out->max_p = mp;
     }
     if (bits) {
-        set_err(c, "device error bits 0x%x (%s%s%s%s%s%s%s)", bits,
+        set_err(c, "device error bits 0x%x (%s%s%s%s%s%s%s%s)", bits,
                 (bits & DERR_INDEX) ? "index " : "",
                 (bits & DERR_DUPLICATE) ? "duplicate-active " : "",
                 (bits & DERR_OVERFLOW) ? "accepted-overflow " : "",
                 (bits & DERR_COUNT) ? "too-few-neighbours " : "",
                 (bits & DERR_STALL) ? "stalled-resolution " : "",
                 (bits & DERR_NGB_OVERFLOW) ? "overlap-row-overflow " : "",
-                (bits & DERR_BAD_H) ? "bad-smoothing-length " : "");
+                (bits & DERR_BAD_H) ? "bad-smoothing-length " : "",
+                (bits & DERR_HISTORY) ? "history-overflow " : "");
         launch_fill_i32((int32_t *)c->derr, 0, 1, c->stream);
         (void)hipStreamSynchronize(c->stream);
     }

@@ -1,20 +1,38 @@
 // Scattering step of the active particles (paper sec. 4.1, 4.5) and the
 // per-pair timestep bound (sec. 4.4, Eq. sidm_timestep).
 //
-//  k_eval      one thread per candidate (i|j): P(i|j) = 1/2 m_j sigma(w)/m w
-//              W(r_ij, h_i) dt_i (Eqs. rate, oneSided, probabilityScatter),
-//              the Philox decision draw, and wave-aggregated compaction of
-//              the accepted candidates into a list.
-//  passes      the accepted candidates are applied in increasing
-//              (priority, id_i, id_j) order.  A pass lets every candidate that
-//              holds the smallest key at both of its particles re-evaluate P
-//              with the current velocities and kick (these winners form a
-//              matching, so each particle scatters at most once per pass);
-//              the others wait for the next pass.  Claims are 64-bit
-//              integer atomicMin (priority, then the ID pair): no
-//              floating-point atomics, so results do not depend on timing.
-//  finisher    one workgroup runs the remaining passes with barriers when the
-//              list is short, so the step needs no host round trip.
+// Semantics (sec. 4.5, immediate update): every directed candidate (i|j)
+// takes one turn, in increasing key (priority, id_i, id_j); at its turn P is
+// computed with the velocities of that moment and it scatters iff u < P.
+// The step reproduces that serial order exactly, in parallel:
+//
+//  k_eval      one thread per candidate: P(i|j) = 1/2 m_j sigma(w)/m w
+//              W(r_ij, h_i) dt_i (Eqs. rate, oneSided, probabilityScatter)
+//              with the step-start velocities, the Philox decision draw, and
+//              compaction of the accepted candidates into the list of
+//              candidates whose turns are replayed ("listed").
+//  passes      the listed candidates take their turns in key order: a pass
+//              lets every candidate that holds the smallest key at both of
+//              its particles evaluate P with the current velocities and kick
+//              (these winners form a matching, so each particle takes at most
+//              one turn per pass); the others wait.  Claims are 64-bit
+//              integer atomicMin (priority, then the ID pair).  Each turn
+//              appends a record to both particles' histories (key, velocity
+//              before the turn, kicked or not).
+//  k_check     one thread per candidate: a candidate touching a particle with
+//              a history is evaluated at its turn, with the velocities the
+//              histories give at its key.  A candidate that is not listed but
+//              accepts there would have changed the step: it is listed.
+//              If no candidate is, the replayed turns are the serial order
+//              (every unlisted candidate rejects at its turn, so it changes
+//              nothing), and the check's counts are the step's.
+//  k_reround   one workgroup: the turns that a newly listed candidate can
+//              affect (later turns of its particles, closed under sharing a
+//              particle) are rewound -- those particles' velocities restored
+//              from their histories -- and taken again with the new ones;
+//              then the next check.  A bounded number of rounds run as grid
+//              launches, the rest in one workgroup (k_tail) until no
+//              candidate is newly listed.
 //  k_timestep  dt_i = 2 C_SIDM / (m_i W(0, h_i) max_j w_ij sigma(w_ij)/m).
 #include "sidm_internal.h"
 
@@ -25,8 +43,11 @@ constexpr int kMultiPasses = 4;        // passes run as grid-wide kernels
 constexpr int kEvalGrid = 6 * 256;     // evaluation workgroups at least (fewer were slower)
 constexpr int kFinisherMax = 256;      // shorter lists go to the one-workgroup finisher
 
-// control block: [0..1] list counts, [2] completed passes, [3] hand-off flag
-enum { CTL_COUNT0 = 0, CTL_COUNT1 = 1, CTL_PASS = 2, CTL_HANDOFF = 3 };
+// control words: [0..1] pass list counts, [2] completed passes, [3] hand-off
+// flag, [4] listed candidates, [5] turn records, [6] first candidate listed
+// since the last replay, [7] done (no candidate newly listed)
+enum { CTL_COUNT0 = 0, CTL_COUNT1 = 1, CTL_PASS = 2, CTL_HANDOFF = 3, CTL_MEM = 4, CTL_REC = 5,
+       CTL_NEWLO = 6, CTL_DONE = 7 };
 
 struct StepArgs {
     // Morton-ordered snapshot
@@ -43,13 +64,17 @@ struct StepArgs {
     const int32_t *ngb;
     const double *h, *dt;
     uint32_t *cand_info;
-    // resolution
-    AccList L0, L1;
+    // resolution: listed candidates, pass lists, histories
+    AccList M;
+    int32_t *wl0, *wl1, *mmark, *plist, *head;
+    TurnRecords R;
+    unsigned long long *tmin;
+    RoundStats *rs;
     int32_t *ctl;
     unsigned long long *c1a, *c1b, *c2a, *c2b;
     DevStats *st;
     unsigned int *derr;
-    int64_t n, cap_acc;
+    int64_t n, cap_acc, cap_rec;
     double m_scalar, box, s0, w0, eps, delta, band;
     // mixed form: FP32 offsets from the leaf box centres, and the relative
     // |P - u| band inside which an FP32 decision is redone in FP64
@@ -225,7 +250,10 @@ struct StagedAcc {
 
 __device__ void flush_staged(const StepArgs &A, StagedAcc &S, int n, int32_t &base_s)
 {
-    if (threadIdx.x == 0) base_s = atomicAdd(&A.ctl[CTL_COUNT0], n);
+    if (threadIdx.x == 0) {
+        base_s = atomicAdd(&A.ctl[CTL_MEM], n);
+        atomicAdd(&A.ctl[CTL_COUNT0], n);     // the first pass list is every listed candidate
+    }
     __syncthreads();
     const int64_t base = base_s;
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
@@ -239,10 +267,11 @@ __device__ void flush_staged(const StepArgs &A, StagedAcc &S, int n, int32_t &ba
         const int32_t j = A.inv[A.ngb[ci]];    // checked in range when it was evaluated
         const uint32_t idi = A.ids[i], idj = A.ids[j];
         const Philox4 xp = pair_draw(A.seed, A.step, idi, idj, PURPOSE_PRIORITY);
-        A.L0.i[pos] = i; A.L0.j[pos] = j; A.L0.cand[pos] = (int32_t)ci;
-        A.L0.u[pos] = S.u[t]; A.L0.W[pos] = S.W[t]; A.L0.dt[pos] = A.dt[a];
-        A.L0.prio[pos] = direction_word(xp, idi < idj);
-        A.L0.idpair[pos] = ((uint64_t)idi << 32) | idj;
+        A.M.i[pos] = i; A.M.j[pos] = j; A.M.cand[pos] = (int32_t)ci;
+        A.M.u[pos] = S.u[t]; A.M.W[pos] = S.W[t]; A.M.dt[pos] = A.dt[a];
+        A.M.prio[pos] = direction_word(xp, idi < idj);
+        A.M.idpair[pos] = ((uint64_t)idi << 32) | idj;
+        A.wl0[pos] = (int32_t)pos;
         A.c1a[i] = ~0ull; A.c1a[j] = ~0ull;
         A.c2a[i] = ~0ull; A.c2a[j] = ~0ull;
     }
@@ -406,6 +435,8 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
         }
         __syncthreads();
         const int n_st = s_n;
+        // every wave has read s_n before any appends to it again
+        __syncthreads();
         if (n_st > kStage - kBlock) {              // the next round might not fit
             flush_staged(A, S, n_st, s_base);
             if (threadIdx.x == 0) s_n = 0;
@@ -446,14 +477,18 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
 }
 
 // ----------------------------------------------------------------------------
-// Resolution passes: per-entry bodies shared by the grid kernels and the
-// one-workgroup finisher.  Pass t reads list t&1 and claim buffers t&1.
+// Turns of the listed candidates.  Pass t reads work list t&1 (indices into
+// the listed candidates) and claim buffers t&1.
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ const AccList &list_of(const StepArgs &A, int t) { return (t & 1) ? A.L1 : A.L0; }
+__device__ __forceinline__ int32_t *list_of(const StepArgs &A, int t) { return (t & 1) ? A.wl1 : A.wl0; }
 __device__ __forceinline__ unsigned long long *claim1_of(const StepArgs &A, int t) { return (t & 1) ? A.c1b : A.c1a; }
 __device__ __forceinline__ unsigned long long *claim2_of(const StepArgs &A, int t) { return (t & 1) ? A.c2b : A.c2a; }
 
-__device__ __forceinline__ unsigned long long load_claim(const unsigned long long *p)
+__device__ __forceinline__ unsigned long long load_u64(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t load_i32(const int32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -466,61 +501,75 @@ __device__ __forceinline__ int64_t list_count(const StepArgs &A, int t)
 
 __device__ __forceinline__ void claim1_entry(const StepArgs &A, int t, int64_t e)
 {
-    const AccList &L = list_of(A, t);
+    const int32_t m = list_of(A, t)[e];
     unsigned long long *c1 = claim1_of(A, t);
-    unsigned long long pr = L.prio[e];
-    atomicMin(&c1[L.i[e]], pr);
-    atomicMin(&c1[L.j[e]], pr);
+    const unsigned long long pr = A.M.prio[m];
+    atomicMin(&c1[A.M.i[m]], pr);
+    atomicMin(&c1[A.M.j[m]], pr);
 }
 
 __device__ __forceinline__ void claim2_entry(const StepArgs &A, int t, int64_t e)
 {
-    const AccList &L = list_of(A, t);
+    const int32_t m = list_of(A, t)[e];
     const unsigned long long *c1 = claim1_of(A, t);
     unsigned long long *c2 = claim2_of(A, t);
-    const unsigned long long pr = L.prio[e], ip = L.idpair[e];
-    const int32_t i = L.i[e], j = L.j[e];
-    if (load_claim(&c1[i]) == pr) atomicMin(&c2[i], ip);
-    if (load_claim(&c1[j]) == pr) atomicMin(&c2[j], ip);
+    const unsigned long long pr = A.M.prio[m], ip = A.M.idpair[m];
+    const int32_t i = A.M.i[m], j = A.M.j[m];
+    if (load_u64(&c1[i]) == pr) atomicMin(&c2[i], ip);
+    if (load_u64(&c1[j]) == pr) atomicMin(&c2[j], ip);
 }
 
-// returns true if the entry was decided (winner) this pass
-template <bool PERIODIC>
+__device__ __forceinline__ void put_record(const StepArgs &A, int32_t r, int32_t p, uint64_t pr,
+                                           uint64_t ip, int32_t m, int32_t prev, uint32_t info)
+{
+    A.R.prio[r] = pr; A.R.idpair[r] = ip;
+    A.R.vx[r] = A.vxs[p]; A.R.vy[r] = A.vys[p]; A.R.vz[r] = A.vzs[p];
+    A.R.mem[r] = m; A.R.prev[r] = prev; A.R.part[r] = p;
+    A.R.info[r] = info | ((uint32_t)A.sts[p] << 1);
+}
+
+// The turn of listed candidate m = (i|j): P with the current velocities, a
+// record of the turn in both particles' histories, and the kick if u < P.
+// Called only for a pass winner, so no other thread touches i or j.
+__device__ void take_turn(const StepArgs &A, int32_t m)
+{
+    const int32_t i = A.M.i[m], j = A.M.j[m];
+    const double w = A.vphys * rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j], A.vzs[j]);
+    const double sig = sigma_of(A, w);
+    const double P = pair_allowed(A, i, j) ? pair_prob(mass_of(A, j), sig, w, A.M.W[m], A.M.dt[m]) : 0.0;
+    const bool hit = A.M.u[m] < P;
+    const int32_t r = atomicAdd(&A.ctl[CTL_REC], 2);
+    if ((int64_t)r + 2 <= A.cap_rec) {
+        const int32_t hi = A.head[i], hj = A.head[j];
+        const uint32_t di = hi >= 0 ? A.R.info[hi] >> 8 : 0u, dj = hj >= 0 ? A.R.info[hj] >> 8 : 0u;
+        const uint32_t d = 1u + (di > dj ? di : dj);     // depth of this kick
+        const uint64_t pr = A.M.prio[m], ip = A.M.idpair[m];
+        put_record(A, r, i, pr, ip, m, hi, hit ? (1u | (d << 8)) : (di << 8));
+        put_record(A, r + 1, j, pr, ip, m, hj, hit ? (1u | (d << 8)) : (dj << 8));
+        A.head[i] = r;
+        A.head[j] = r + 1;
+    } else {
+        atomicOr(A.derr, DERR_HISTORY);
+    }
+    if (hit) kick(A, i, j);
+}
+
+// returns true if the entry took its turn (a winner) this pass
 __device__ bool resolve_entry(const StepArgs &A, int t, int64_t e, int32_t *next_count)
 {
-    const AccList &L = list_of(A, t);
+    const int32_t m = list_of(A, t)[e];
     const unsigned long long *c1 = claim1_of(A, t), *c2 = claim2_of(A, t);
-    const int32_t i = L.i[e], j = L.j[e];
-    const unsigned long long pr = L.prio[e], ip = L.idpair[e];
-    const bool win = load_claim(&c1[i]) == pr && load_claim(&c1[j]) == pr &&
-                     load_claim(&c2[i]) == ip && load_claim(&c2[j]) == ip;
+    const int32_t i = A.M.i[m], j = A.M.j[m];
+    const unsigned long long pr = A.M.prio[m], ip = A.M.idpair[m];
+    const bool win = load_u64(&c1[i]) == pr && load_u64(&c1[j]) == pr &&
+                     load_u64(&c2[i]) == ip && load_u64(&c2[j]) == ip;
     if (win) {
-        const double w = A.vphys * rel_speed(A.vxs[i], A.vys[i], A.vzs[i], A.vxs[j], A.vys[j],
-                                             A.vzs[j]);
-        const double sig = sigma_of(A, w);
-        const double P = pair_allowed(A, i, j) ? pair_prob(mass_of(A, j), sig, w, L.W[e], L.dt[e]) : 0.0;
-        const double u = L.u[e];
-        const bool flagged = fabs(P - u) < A.band;
-        const bool hit = u < P;
-        if (flagged) atomicAdd(&A.st->n_flagged, 1ull);
-        if (hit) {
-            kick(A, i, j);
-            atomicAdd(&A.st->n_events, 1ull);
-        }
-        if (A.cand_info) {
-            const int32_t cand = L.cand[e];
-            A.cand_info[cand] |= ((uint32_t)(t + 1) << 8) | (hit ? SIDM_CAND_SCATTER : 0u) |
-                                 (flagged ? SIDM_CAND_FLAGGED : 0u);
-        }
+        take_turn(A, m);
         return true;
     }
     // carry over to the next pass, and clear the claims it will use
-    const AccList &N = list_of(A, t + 1);
     const int32_t pos = atomicAdd(next_count, 1);
-    N.i[pos] = i; N.j[pos] = j;
-    N.cand[pos] = L.cand[e];
-    N.u[pos] = L.u[e]; N.W[pos] = L.W[e]; N.dt[pos] = L.dt[e];
-    N.prio[pos] = pr; N.idpair[pos] = ip;
+    list_of(A, t + 1)[pos] = m;
     unsigned long long *n1 = claim1_of(A, t + 1), *n2 = claim2_of(A, t + 1);
     n1[i] = ~0ull; n1[j] = ~0ull;
     n2[i] = ~0ull; n2[j] = ~0ull;
@@ -556,7 +605,6 @@ __global__ __launch_bounds__(kBlock) void k_claim2(StepArgs A, int t)
         claim2_entry(A, t, e);
 }
 
-template <bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void k_resolve(StepArgs A, int t)
 {
     if (A.ctl[CTL_HANDOFF]) return;
@@ -564,61 +612,389 @@ __global__ __launch_bounds__(kBlock) void k_resolve(StepArgs A, int t)
     int32_t *next = &A.ctl[((t + 1) & 1) ? CTL_COUNT1 : CTL_COUNT0];
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
          e += (int64_t)gridDim.x * blockDim.x)
-        resolve_entry<PERIODIC>(A, t, e, next);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        A.ctl[CTL_PASS] = t + 1;
-        atomicMax(&A.st->n_passes, (unsigned)(t + 1));
-    }
+        resolve_entry(A, t, e, next);
+    if (blockIdx.x == 0 && threadIdx.x == 0) A.ctl[CTL_PASS] = t + 1;
 }
 
-// One workgroup finishes whatever passes remain.
-template <bool PERIODIC>
-__global__ __launch_bounds__(1024) void k_finish(StepArgs A)
+__device__ __forceinline__ void wg_sync()
 {
-    __shared__ int64_t s_cnt;
-    __shared__ int s_t;
-    if (threadIdx.x == 0) {
-        s_t = A.ctl[CTL_PASS];
-        s_cnt = list_count(A, s_t);
-    }
+    __threadfence_block();
     __syncthreads();
-    while (s_cnt > 0) {
-        const int t = s_t;
-        const int64_t cnt = s_cnt;
+}
+
+// Passes of one workgroup over work list t0&1 holding cnt0 entries, until
+// every entry has taken its turn.
+struct PassShared { int64_t cnt; int t; };
+
+__device__ void wg_passes(const StepArgs &A, int t0, int64_t cnt0, PassShared &S)
+{
+    if (threadIdx.x == 0) { S.t = t0; S.cnt = cnt0; }
+    __syncthreads();
+    while (S.cnt > 0) {
+        const int t = S.t;
+        const int64_t cnt = S.cnt;
         int32_t *next = &A.ctl[((t + 1) & 1) ? CTL_COUNT1 : CTL_COUNT0];
         if (threadIdx.x == 0) *next = 0;
         for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) claim1_entry(A, t, e);
-        __threadfence_block();
-        __syncthreads();
+        wg_sync();
         for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) claim2_entry(A, t, e);
-        __threadfence_block();
-        __syncthreads();
-        for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) resolve_entry<PERIODIC>(A, t, e, next);
-        __threadfence_block();
-        __syncthreads();
+        wg_sync();
+        for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) resolve_entry(A, t, e, next);
+        wg_sync();
         if (threadIdx.x == 0) {
-            s_t = t + 1;
-            int64_t nc = *next;
-            atomicMax(&A.st->n_passes, (unsigned)(t + 1));
-            if (nc >= cnt) {            // no winner: the global minimum always wins
+            S.t = t + 1;
+            int64_t nc = load_i32(next);
+            if (nc >= cnt) {            // no winner: the smallest key always wins
                 atomicOr(A.derr, DERR_STALL);
                 nc = 0;
             }
-            s_cnt = nc;
+            S.cnt = nc;
         }
         __syncthreads();
     }
 }
 
-// Zeroes the step's statistics and pass counters; with nt_dev given, the
+// Round 1: one workgroup finishes whatever passes the grid left, then sets
+// up the first check.
+__global__ __launch_bounds__(1024) void k_finish(StepArgs A)
+{
+    __shared__ PassShared S;
+    __shared__ int s_t0;
+    __shared__ int64_t s_c0;
+    if (threadIdx.x == 0) {
+        s_t0 = A.ctl[CTL_PASS];
+        s_c0 = list_count(A, s_t0);
+    }
+    __syncthreads();
+    const int t0 = s_t0;
+    const int64_t c0 = s_c0;
+    __syncthreads();
+    wg_passes(A, t0, c0, S);
+    if (threadIdx.x == 0) {
+        const int64_t mcount = A.ctl[CTL_MEM];
+        A.ctl[CTL_NEWLO] = (int32_t)(mcount < A.cap_acc ? mcount : A.cap_acc);
+        *A.rs = RoundStats{};
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Check of a round: every candidate touching a particle with a history is
+// evaluated at its turn.
+// ----------------------------------------------------------------------------
+
+// The history of particle p at key (kp, ki): (tx, ty, tz) its velocity at that
+// turn, rge the earliest record with key >= (kp, ki) (-1 if none), and
+// (sx, sy, sz) its velocity at the step start.  Records go from the latest
+// turn back, with decreasing keys and decreasing record indices.
+__device__ __forceinline__ void history_at(const StepArgs &A, int32_t p, uint64_t kp, uint64_t ki,
+                                           double &tx, double &ty, double &tz, int32_t &rge,
+                                           double &sx, double &sy, double &sz)
+{
+    tx = sx = A.vxs[p];
+    ty = sy = A.vys[p];
+    tz = sz = A.vzs[p];
+    rge = -1;
+    int32_t r = A.head[p], last = 0x7fffffff;
+    while (r >= 0 && r < last) {
+        const uint64_t rp = A.R.prio[r], rq = A.R.idpair[r];
+        const double ax = A.R.vx[r], ay = A.R.vy[r], az = A.R.vz[r];
+        if (rp > kp || (rp == kp && rq >= ki)) { rge = r; tx = ax; ty = ay; tz = az; }
+        sx = ax; sy = ay; sz = az;
+        last = r;
+        r = A.R.prev[r];
+    }
+}
+
+struct CheckAcc {
+    unsigned long long events;
+    long long dflag;
+    unsigned int depth;
+};
+
+template <bool PERIODIC, bool OVERLAP>
+__device__ void check_candidate(const StepArgs &A, int64_t b, int s, int32_t a, CheckAcc &acc)
+{
+    const int32_t i = A.tlist[b];
+    const int64_t ci = (int64_t)a * A.stride + s;
+    const int32_t jc = A.ngb[ci];
+    if (jc < 0 || jc >= A.n) return;          // latched by the evaluation
+    const int32_t j = A.inv[jc];
+    if (A.head[i] < 0 && A.head[j] < 0) return;   // untouched: the step-start decision stands
+    const uint32_t idi = A.ids[i], idj = A.ids[j];
+    const uint64_t kp = direction_word(pair_draw(A.seed, A.step, idi, idj, PURPOSE_PRIORITY), idi < idj);
+    const uint64_t ki = ((uint64_t)idi << 32) | idj;
+    const double u = unit_from_word(direction_word(pair_draw(A.seed, A.step, idi, idj, PURPOSE_DECIDE),
+                                                   idi < idj));
+    double tix, tiy, tiz, six, siy, siz, tjx, tjy, tjz, sjx, sjy, sjz;
+    int32_t ri, rj;
+    history_at(A, i, kp, ki, tix, tiy, tiz, ri, six, siy, siz);
+    history_at(A, j, kp, ki, tjx, tjy, tjz, rj, sjx, sjy, sjz);
+    const double r = A.lphys * sqrt(sep2<PERIODIC>(A.xs[i], A.ys[i], A.zs[i], A.xs[j], A.ys[j],
+                                                   A.zs[j], A.box));
+    const double W = OVERLAP ? overlap_g(A.gtab, A.lphys * A.hsrt[i], A.lphys * A.hsrt[j], r)
+                             : cubic_spline(r, A.lphys * A.h[a]);
+    const bool allowed = pair_allowed(A, i, j);
+    const double mj = mass_of(A, j), dta = A.dt[a];
+    const double wt = A.vphys * rel_speed(tix, tiy, tiz, tjx, tjy, tjz);
+    const double Pt = allowed ? pair_prob(mj, sigma_of(A, wt), wt, W, dta) : 0.0;
+    const double ws = A.vphys * rel_speed(six, siy, siz, sjx, sjy, sjz);
+    const double Ps = allowed ? pair_prob(mj, sigma_of(A, ws), ws, W, dta) : 0.0;
+    const bool listed = ri >= 0 && A.R.prio[ri] == kp && A.R.idpair[ri] == ki;
+    const bool kicked = listed && (A.R.info[ri] & 1u);
+    const uint32_t depth = kicked ? A.R.info[ri] >> 8 : 0u;
+    const bool flag_t = fabs(Pt - u) < A.band, flag_s = fabs(Ps - u) < A.band;
+    if (!listed && u < Pt) {
+        // accepts at its turn but did not take it: list it for the next round
+        const int32_t pos = atomicAdd(&A.ctl[CTL_MEM], 1);
+        if (pos < A.cap_acc) {
+            A.M.i[pos] = i; A.M.j[pos] = j; A.M.cand[pos] = (int32_t)ci;
+            A.M.u[pos] = u; A.M.W[pos] = W; A.M.dt[pos] = dta;
+            A.M.prio[pos] = kp; A.M.idpair[pos] = ki;
+        } else {
+            atomicOr(A.derr, DERR_OVERFLOW);
+        }
+    }
+    acc.events += kicked;
+    acc.dflag += (long long)flag_t - (long long)flag_s;
+    acc.depth = depth > acc.depth ? depth : acc.depth;
+    if (A.cand_info)
+        A.cand_info[ci] = (u < Ps ? SIDM_CAND_ACCEPT0 : 0u) | (flag_t ? SIDM_CAND_FLAGGED : 0u) |
+                          (kicked ? (SIDM_CAND_SCATTER | (depth << 8)) : 0u);
+}
+
+// every candidate of the step, strided over the threads given
+template <bool PERIODIC, bool OVERLAP>
+__device__ void check_range(const StepArgs &A, int64_t first, int64_t stride_threads, CheckAcc &acc)
+{
+    const int64_t nt = *A.nt_dev;
+    const int64_t total = nt * A.stride;
+    for (int64_t c = first; c < total; c += stride_threads) {
+        const int64_t b = c / A.stride;
+        const int s = (int)(c - b * A.stride);
+        const int32_t a = A.slot[b];
+        if (OVERLAP && s >= A.cnt[a]) continue;
+        check_candidate<PERIODIC, OVERLAP>(A, b, s, a, acc);
+    }
+}
+
+// workgroup reduction of a check's counts into the round's counts
+__device__ void add_check_counts(const StepArgs &A, CheckAcc acc, unsigned long long (*red)[3])
+{
+    unsigned long long ev = acc.events, df = (unsigned long long)acc.dflag, dp = acc.depth;
+    for (int off = 32; off > 0; off >>= 1) {
+        ev += (unsigned long long)__shfl_xor((long long)ev, off);
+        df += (unsigned long long)__shfl_xor((long long)df, off);
+        const unsigned long long o = (unsigned long long)__shfl_xor((long long)dp, off);
+        dp = o > dp ? o : dp;
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[w][0] = ev; red[w][1] = df; red[w][2] = dp; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long e = 0, f = 0, d = 0;
+        for (int v = 0; v < (int)(blockDim.x >> 6); ++v) {
+            e += red[v][0]; f += red[v][1];
+            d = red[v][2] > d ? red[v][2] : d;
+        }
+        if (e) atomicAdd(&A.rs->events, e);
+        if (f) atomicAdd((unsigned long long *)&A.rs->dflag, f);
+        if (d) atomicMax(&A.rs->max_depth, (unsigned int)d);
+    }
+}
+
+template <bool PERIODIC, bool OVERLAP>
+__global__ __launch_bounds__(kBlock) void k_check(StepArgs A)
+{
+    __shared__ unsigned long long red[kBlock / 64][3];
+    if (A.ctl[CTL_DONE]) return;
+    CheckAcc acc{0, 0, 0};
+    check_range<PERIODIC, OVERLAP>(A, blockIdx.x * (int64_t)blockDim.x + threadIdx.x,
+                                   (int64_t)gridDim.x * blockDim.x, acc);
+    add_check_counts(A, acc, red);
+}
+
+// ----------------------------------------------------------------------------
+// Re-round: list the newly accepting candidates, rewind the turns they can
+// affect and take them again.  One workgroup.
+// ----------------------------------------------------------------------------
+struct RoundShared {
+    PassShared ps;
+    int go;
+    int32_t lo, hi;          // newly listed candidates [lo, hi)
+    int32_t dl;              // candidates to replay (in work list 0)
+    int32_t pl;              // particles to rewind (in plist)
+    int32_t f0, f1;          // frontier of the closure
+};
+
+__device__ void reround_body(const StepArgs &A, RoundShared &S)
+{
+    const int tid = threadIdx.x, nth = blockDim.x;
+    if (tid == 0) {
+        S.go = 0;
+        if (!load_i32(&A.ctl[CTL_DONE])) {
+            const int32_t mc = load_i32(&A.ctl[CTL_MEM]);
+            const int32_t lo = load_i32(&A.ctl[CTL_NEWLO]);
+            const unsigned int bad = __hip_atomic_load(A.derr, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT) &
+                                     (DERR_OVERFLOW | DERR_HISTORY | DERR_STALL);
+            if (mc > A.cap_acc || mc <= lo || bad) {
+                // nothing newly listed: the last check saw the serial order
+                // (or a buffer overflowed, which is latched: stop)
+                A.ctl[CTL_DONE] = 1;
+            } else {
+                S.go = 1; S.lo = lo; S.hi = mc;
+            }
+        }
+    }
+    __syncthreads();
+    if (!S.go) return;
+    // seeds: the newly listed candidates
+    const int32_t n0 = S.hi - S.lo;
+    for (int32_t q = tid; q < n0; q += nth) {
+        A.mmark[S.lo + q] = 1;
+        A.wl0[q] = S.lo + q;
+    }
+    if (tid == 0) { S.dl = n0; S.pl = 0; S.f0 = 0; S.f1 = n0; }
+    wg_sync();
+    // closure: a turn later than a replayed turn of one of its particles is
+    // replayed too.  tmin[p] is the smallest priority replayed at p; every
+    // turn of p with a priority at least that is marked (equal priorities
+    // with a smaller ID pair included, which only replays one turn more).
+    while (true) {
+        for (int32_t q = S.f0 + tid; q < S.f1; q += nth) {
+            const int32_t m = A.wl0[q];
+            const unsigned long long pr = A.M.prio[m];
+            const int32_t pp[2] = {A.M.i[m], A.M.j[m]};
+            for (int u = 0; u < 2; ++u) {
+                const unsigned long long old = atomicMin(&A.tmin[pp[u]], pr);
+                if (old == ~0ull) A.plist[atomicAdd(&S.pl, 1)] = pp[u];
+            }
+        }
+        wg_sync();
+        for (int32_t q = tid; q < S.pl; q += nth) {
+            const int32_t p = A.plist[q];
+            const unsigned long long tp = load_u64(&A.tmin[p]);
+            int32_t r = A.head[p], last = 0x7fffffff;
+            while (r >= 0 && r < last && A.R.prio[r] >= tp) {
+                const int32_t m2 = A.R.mem[r];
+                if (atomicCAS(&A.mmark[m2], 0, 1) == 0) A.wl0[atomicAdd(&S.dl, 1)] = m2;
+                last = r;
+                r = A.R.prev[r];
+            }
+        }
+        wg_sync();
+        const bool grew = S.dl > S.f1;
+        __syncthreads();
+        if (!grew) break;
+        if (tid == 0) { S.f0 = S.f1; S.f1 = S.dl; }
+        __syncthreads();
+    }
+    // rewind: each particle back to its velocity (and state) before the
+    // earliest replayed turn, its history cut there
+    for (int32_t q = tid; q < S.pl; q += nth) {
+        const int32_t p = A.plist[q];
+        const unsigned long long tp = load_u64(&A.tmin[p]);
+        int32_t r = A.head[p], last = 0x7fffffff, rr = -1;
+        while (r >= 0 && r < last && A.R.prio[r] >= tp) {
+            rr = r;
+            last = r;
+            r = A.R.prev[r];
+        }
+        A.head[p] = r;
+        if (rr >= 0) {
+            const double nx = A.R.vx[rr], ny = A.R.vy[rr], nz = A.R.vz[rr];
+            A.vxs[p] = nx; A.vys[p] = ny; A.vzs[p] = nz;
+            const int32_t op = A.perm[p];
+            A.vx[op] = nx; A.vy[op] = ny; A.vz[op] = nz;
+            if (A.model == SIDM_MODEL_TWO_STATE) {
+                const uint8_t st = (uint8_t)((A.R.info[rr] >> 1) & 0x7fu);
+                A.sts[p] = st;
+                if (A.state) A.state[op] = st;
+            }
+        }
+        atomicExch(&A.tmin[p], ~0ull);
+    }
+    wg_sync();
+    for (int32_t q = tid; q < S.dl; q += nth) {
+        const int32_t m = A.wl0[q];
+        atomicExch(&A.mmark[m], 0);
+        const int32_t i = A.M.i[m], j = A.M.j[m];
+        A.c1a[i] = ~0ull; A.c1a[j] = ~0ull;
+        A.c2a[i] = ~0ull; A.c2a[j] = ~0ull;
+    }
+    wg_sync();
+    wg_passes(A, 0, S.dl, S.ps);
+    wg_sync();
+    if (tid == 0) {
+        A.ctl[CTL_NEWLO] = S.hi;
+        *A.rs = RoundStats{};
+    }
+    wg_sync();
+}
+
+__global__ __launch_bounds__(1024) void k_reround(StepArgs A)
+{
+    __shared__ RoundShared S;
+    reround_body(A, S);
+}
+
+// Rounds left after the grid launches: checks and re-rounds in one workgroup
+// until no candidate is newly listed.  Every round lists at least one more
+// candidate or ends, and the list is bounded, so the loop ends.
+constexpr int kTailRounds = 1 << 16;       // far above any round count seen
+
+template <bool PERIODIC, bool OVERLAP>
+__global__ __launch_bounds__(1024) void k_tail(StepArgs A)
+{
+    __shared__ RoundShared S;
+    __shared__ unsigned long long red[1024 / 64][3];
+    __shared__ int s_done;
+    for (int round = 0;; ++round) {
+        if (threadIdx.x == 0) {
+            s_done = load_i32(&A.ctl[CTL_DONE]);
+            if (!s_done && round >= kTailRounds) {
+                atomicOr(A.derr, DERR_STALL);
+                s_done = 1;
+            }
+        }
+        __syncthreads();
+        if (s_done) break;
+        CheckAcc acc{0, 0, 0};
+        check_range<PERIODIC, OVERLAP>(A, threadIdx.x, blockDim.x, acc);
+        add_check_counts(A, acc, red);
+        wg_sync();
+        reround_body(A, S);
+        wg_sync();
+    }
+}
+
+// End of the step: the last check's counts become the step's, and every
+// history is cleared for the next step.
+__global__ __launch_bounds__(kBlock) void k_step_final(StepArgs A)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const RoundStats r = *A.rs;
+        A.st->n_events = r.events;
+        A.st->n_flagged += (unsigned long long)r.dflag;
+        A.st->n_passes = r.max_depth;
+    }
+    int64_t nr = A.ctl[CTL_REC];
+    nr = nr < A.cap_rec ? nr : A.cap_rec;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nr;
+         r += (int64_t)gridDim.x * blockDim.x)
+        A.head[A.R.part[r]] = -1;
+}
+
+// Zeroes the step's statistics and control words; with nt_dev given, the
 // candidate count is the number of targets times k.
-__global__ void k_step_reset(DevStats *st, int32_t *ctl, const int32_t *nt_dev, int k)
+__global__ void k_step_reset(DevStats *st, int32_t *ctl, RoundStats *rs, const int32_t *nt_dev, int k)
 {
     if (threadIdx.x == 0) {
         DevStats z = {};
         if (nt_dev) z.n_cand = (unsigned long long)(*nt_dev) * (unsigned long long)k;
         *st = z;
-        ctl[0] = ctl[1] = ctl[2] = ctl[3] = 0;
+        *rs = RoundStats{};
+        for (int q = 0; q < 16; ++q) ctl[q] = 0;
     }
 }
 
@@ -733,7 +1109,9 @@ StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const dou
     A.state = p ? p->state : nullptr;
     A.tlist = c->tlist; A.slot = c->slot; A.nt_dev = c->nt_dev;
     A.ngb = ngb; A.h = h; A.dt = dt; A.cand_info = cand_info;
-    A.L0 = c->acc[0]; A.L1 = c->acc[1];
+    A.M = c->mem;
+    A.wl0 = c->wl[0]; A.wl1 = c->wl[1]; A.mmark = c->mmark; A.plist = c->plist; A.head = c->head;
+    A.R = c->trec; A.tmin = c->tmin; A.rs = c->rstats; A.cap_rec = c->cap_rec;
     A.ctl = c->acc_count;
     A.c1a = c->claim1[0]; A.c1b = c->claim1[1]; A.c2a = c->claim2[0]; A.c2b = c->claim2[1];
     A.st = c->dstats; A.derr = c->derr;
@@ -762,7 +1140,7 @@ template <bool P, bool M, bool O = false>
 void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s)
 {
     const int64_t total = n_active * A.stride;
-    k_step_reset<<<1, 64, 0, s>>>(A.st, A.ctl, O ? nullptr : A.nt_dev, A.k);
+    k_step_reset<<<1, 64, 0, s>>>(A.st, A.ctl, A.rs, O ? nullptr : A.nt_dev, A.k);
     phase_begin(c, PH_EVAL);
     // at least as many workgroups as are resident at once (the staging
     // buffer's LDS allows six per CU), more for long candidate lists (about
@@ -771,16 +1149,27 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
     // the candidates
     int64_t ge = total / 2048;
     ge = ge > 8192 ? 8192 : ge;
-    k_eval<P, M, O><<<ge > kEvalGrid ? (int)ge : grid_for(total, kEvalGrid), kBlock, 0, s>>>(A);
+    const int geval = ge > kEvalGrid ? (int)ge : grid_for(total, kEvalGrid);
+    k_eval<P, M, O><<<geval, kBlock, 0, s>>>(A);
     phase_end(c, PH_EVAL);
     const int g = grid_for(A.cap_acc < total ? A.cap_acc : total, 2048);
     phase_begin(c, PH_RESOLVE);
+    // round 1: the turns of the candidates accepted at the step start
     for (int t = 0; t < kMultiPasses; ++t) {
         k_claim1<<<g, kBlock, 0, s>>>(A, t);
         k_claim2<<<g, kBlock, 0, s>>>(A, t);
-        k_resolve<P><<<g, kBlock, 0, s>>>(A, t);
+        k_resolve<<<g, kBlock, 0, s>>>(A, t);
     }
-    k_finish<P><<<1, 1024, 0, s>>>(A);
+    k_finish<<<1, 1024, 0, s>>>(A);
+    // checks and re-rounds until no candidate is newly listed (the kernels of
+    // rounds after that return at once)
+    for (int r = 0; r < c->dev_rounds; ++r) {
+        k_check<P, O><<<geval, kBlock, 0, s>>>(A);
+        k_reround<<<1, 1024, 0, s>>>(A);
+    }
+    k_tail<P, O><<<1, 1024, 0, s>>>(A);
+    const int64_t nrec = A.cap_rec < 2 * total ? A.cap_rec : 2 * total;
+    k_step_final<<<grid_for(nrec, 1024), kBlock, 0, s>>>(A);
     phase_end(c, PH_RESOLVE);
 }
 

@@ -25,6 +25,7 @@
 #define DERR_STALL 16u          // a resolution pass decided nothing (cannot happen)
 #define DERR_NGB_OVERFLOW 32u   // an overlap row longer than its buffer
 #define DERR_BAD_H 64u          // a smoothing length that is not > 0 and finite
+#define DERR_HISTORY 128u       // the scatter histories of a step outgrew their buffer
 
 #define SIDM_TREE_FAN 8         // children per internal tree node
 #define SIDM_MAX_LEVELS 12
@@ -67,10 +68,12 @@ struct DevStats {
     unsigned int n_passes, pad;
 };
 
-// One accepted candidate (i|j), kept in structure-of-arrays form.
+// The candidates (i|j) of a step whose turns are replayed in order (accepted
+// with the step-start velocities, or found to accept at their turn later),
+// kept in structure-of-arrays form.
 struct AccList {
     int32_t *i, *j;          // sorted-order particle indices (target, partner)
-    int32_t *cand;           // a * n_ngb + s  (caller's active slot and neighbour slot)
+    int32_t *cand;           // a * stride + s  (caller's active slot and neighbour slot)
     double *u;               // decision draw
     double *W;               // kernel weight W(r_ij, h_i) (positions do not change)
     double *dt;              // timestep of the target
@@ -78,9 +81,27 @@ struct AccList {
     uint64_t *idpair;        // (id_i << 32) | id_j
 };
 
+// One turn of a listed candidate at one of its two particles: the particle's
+// history within the step is the chain of these records, latest first.
+struct TurnRecords {
+    uint64_t *prio, *idpair; // the candidate's key
+    double *vx, *vy, *vz;    // the particle's velocity just before the turn
+    int32_t *mem;            // index of the candidate in the list
+    int32_t *prev;           // the particle's previous record, -1 if none
+    int32_t *part;           // the particle (sorted index)
+    uint32_t *info;          // bit 0: kicked; bits 1..7: state before; bits 8..: kick depth after
+};
+
+// per-round counts of the check that verifies a round (see scatter.hip)
+struct RoundStats {
+    unsigned long long events;    // listed candidates that kicked
+    long long dflag;              // flagged turns minus flagged step-start evaluations
+    unsigned int max_depth, pad;
+};
+
 struct sidm_ctx {
     sidm_config cfg;
-    int64_t cap_n, cap_active, cap_acc;
+    int64_t cap_n, cap_active, cap_acc, cap_rec;
     int device;
     hipStream_t stream;
     char err[512];
@@ -128,10 +149,18 @@ struct sidm_ctx {
     int map_valid;           // the arrays above hold the mapping of map_n targets
     int64_t map_n;           //   made since the last tree build (reusable: active == NULL)
 
-    // conflict resolution
-    AccList acc[2];
-    int32_t *acc_count;      // [4]: counts of list 0 / 1, pass counter
+    // the turns of the step in (priority, id_i, id_j) order
+    AccList mem;             // [cap_acc] listed candidates
+    int32_t *mmark;          // [cap_acc] 1 while a listed candidate is marked for replay
+    int32_t *wl[2];          // [cap_acc] pass work lists (indices into mem)
+    int32_t *plist;          // [2 cap_acc] particles whose history a re-round rewinds
+    TurnRecords trec;        // [cap_rec] turn records
+    int32_t *head;           // [cap_n] latest turn record of each particle, -1 if none
+    unsigned long long *tmin;     // [cap_n] smallest priority a re-round replays, ~0 if none
+    RoundStats *rstats;
+    int32_t *acc_count;      // [16] control words (list counts, passes, rounds)
     unsigned long long *claim1[2], *claim2[2];   // [cap_n] per-particle claims
+    int dev_rounds;          // rounds run as grid launches before the one-workgroup tail
 
     DevStats *dstats;
     unsigned int *derr;

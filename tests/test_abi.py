@@ -111,3 +111,43 @@ def test_unit_factors_are_checked():
     for lf, vf in ((-1.0, 1.0), (1.0, -0.5), (float("inf"), 1.0), (1.0, float("nan"))):
         bad = sidm.make_config(n_ngb=32, len_to_phys=lf, vel_to_phys=vf)
         assert L.sidm_footprint(ctypes.byref(bad), 1000, 100, ctypes.byref(out)) == sidm.SIDM_E_INVAL
+
+
+def test_candidate_slots_must_fit_32_bits():
+    """A candidate's slot a * n_ngb + s is kept in 32 bits: capacities whose
+    product exceeds 2^31 - 1 are refused (no device needed)."""
+    L = sidm.lib()
+    out = ctypes.c_size_t()
+    cfg = sidm.make_config(n_ngb=32, periodic=True, box=1.0, sigma0=1.0)
+    ok_active = (2**31 - 1) // 32
+    assert L.sidm_footprint(ctypes.byref(cfg), ok_active, ok_active, ctypes.byref(out)) == sidm.SIDM_OK
+    assert (L.sidm_footprint(ctypes.byref(cfg), ok_active + 1, ok_active + 1, ctypes.byref(out))
+            == sidm.SIDM_E_CAPACITY)
+    h = ctypes.c_void_p()
+    assert (L.sidm_create(ctypes.byref(cfg), ok_active + 1, ok_active + 1, None, ctypes.byref(h))
+            == sidm.SIDM_E_CAPACITY)
+    assert not h.value
+
+
+def test_neighbour_count_limits():
+    L = sidm.lib()
+    out = ctypes.c_size_t()
+    for k, want in ((0, sidm.SIDM_E_INVAL), (1, sidm.SIDM_OK), (63, sidm.SIDM_OK),
+                    (64, sidm.SIDM_E_INVAL)):
+        cfg = sidm.make_config(n_ngb=k, periodic=True, box=1.0, sigma0=1.0)
+        assert L.sidm_footprint(ctypes.byref(cfg), 1000, 100, ctypes.byref(out)) == want, k
+
+
+def test_listed_candidate_capacity():
+    """max_accept sizes the list of candidates whose turns are replayed
+    (0: an eighth of the active capacity, at least 65536); about 290 bytes
+    each."""
+    L = sidm.lib()
+    base = sidm.make_config(n_ngb=32, periodic=True, box=1.0, sigma0=1.0)
+    big = sidm.make_config(n_ngb=32, periodic=True, box=1.0, sigma0=1.0, max_accept=1 << 20)
+    n = 1 << 20
+    a, b = sidm.footprint(base, n, n), sidm.footprint(big, n, n)
+    assert 250 * ((1 << 20) - (1 << 17)) < b - a < 330 * ((1 << 20) - (1 << 17))
+    out = ctypes.c_size_t()
+    bad = sidm.make_config(n_ngb=32, periodic=True, box=1.0, sigma0=1.0, max_accept=-1)
+    assert L.sidm_footprint(ctypes.byref(bad), 1000, 100, ctypes.byref(out)) == sidm.SIDM_E_INVAL

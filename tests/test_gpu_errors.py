@@ -210,7 +210,7 @@ def test_timing_mask_times_only_the_chosen_phases():
 
 def test_accepted_list_overflow_is_reported_and_the_context_recovers():
     """Every candidate accepted (sigma/m so large that P >> 1) on 40000 active
-    particles: 1.28M accepted candidates against a list of 2^20 entries.  The
+    particles: 1.28M accepted candidates against a list of 65536 entries.  The
     evaluation's flush drops what does not fit and latches the overflow,
     sidm_sync reports SIDM_E_OVERFLOW, and after a reconfiguration with a
     normal cross-section the next step runs clean."""

@@ -59,11 +59,43 @@ def test_lattice_exact_ties(side):
 
 
 def test_many_scatters_several_passes():
+    """Three scatters per particle: most candidates take their turn after a
+    kick of one of their particles; many that the step-start state rejects
+    accept at their turn and the other way round."""
     w = W.uniform_box(6000, ic_seed=44, scatters_per_particle=3.0)
     _announce("high-probability box")
     ref = oracle.full_step(w)
     g = gpu_step(w)
     assert ref["stats"]["n_passes"] >= 4
+    acc0 = (ref["info"] & oracle.CAND_ACCEPT0) != 0
+    hit = (ref["info"] & oracle.CAND_SCATTER) != 0
+    assert (hit & ~acc0).sum() > 100 and (acc0 & ~hit).sum() > 100
+    assert_parity(w, g, ref)
+
+
+def test_rounds_in_one_workgroup(monkeypatch):
+    """Many scatters per particle, every round after the first in the
+    one-workgroup tail (no grid rounds): the same serial order."""
+    monkeypatch.setenv("SIDM_TEST_DEVICE_ROUNDS", "0")
+    w = W.uniform_box(3000, ic_seed=45, scatters_per_particle=2.0)
+    _announce("rounds in one workgroup")
+    ref = oracle.full_step(w)
+    g = gpu_step(w)
+    assert_parity(w, g, ref)
+    acc0 = (ref["info"] & oracle.CAND_ACCEPT0) != 0
+    hit = (ref["info"] & oracle.CAND_SCATTER) != 0
+    assert (hit & ~acc0).any() and (acc0 & ~hit).any()
+
+
+@pytest.mark.parametrize("k", [1, 8, 16, 31, 48, 63])
+def test_neighbour_counts(k):
+    """n_ngb from 1 to the largest accepted (63): the short-list and long-list
+    forms of the search, and the step on rows of that length."""
+    w = W.uniform_box(3000, ic_seed=90 + k, scatters_per_particle=0.5, n_ngb=k)
+    w = w.subset_active(2111)
+    _announce(f"n_ngb={k}")
+    ref = oracle.full_step(w, brute=True)
+    g = gpu_step(w)
     assert_parity(w, g, ref)
 
 

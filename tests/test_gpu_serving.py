@@ -46,6 +46,31 @@ def test_advance_matches_oracle():
     ctx.close()
 
 
+@pytest.mark.parametrize("case", ["no active particle", "every bound infinite"])
+def test_advance_without_a_finite_bound_takes_dt_cap(case):
+    """No per-pair bound (no active particle, or every bound +inf): the step
+    is dt_cap itself, as the oracle's step rule gives."""
+    import torch
+    from paper_2607_05504_amd import Context, runner
+    w = W.hernquist_halo(5000, ic_seed=303, philox_seed=6)
+    _announce(f"advance_hernquist {case}")
+    ds = runner.upload(w, "cuda")
+    ctx = Context(runner.config_for(w), w.n, w.n)
+    n_act = 0 if case == "no active particle" else w.n
+    dts = torch.full((w.n,), float("inf"), dtype=torch.float64, device="cuda")
+    dt_step = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.advance_hernquist(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, dts, n_act, 0.25, 1.0, 1.0,
+                          dt_step=dt_step)
+    ctx.sync()
+    ref = oracle.advance_hernquist(w.x, w.y, w.z, w.vx, w.vy, w.vz,
+                                   np.full(n_act, np.inf), 0.25, 1.0, 1.0)
+    assert ref[6] == 0.25
+    assert float(dt_step.item()) == 0.25
+    for k, f in enumerate(("x", "y", "z", "vx", "vy", "vz")):
+        np.testing.assert_allclose(getattr(ds, f).cpu().numpy(), ref[k], rtol=1e-14, atol=1e-300)
+    ctx.close()
+
+
 def test_drift_matches_oracle():
     import torch
     from paper_2607_05504_amd import Context, runner
