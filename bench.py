@@ -356,6 +356,7 @@ def main():
         "ngb_scatter_device_ms": ngb_scatter_ms,
         "ngb_scatter_rate": na / (ngb_scatter_ms * 1e-3) if ngb_scatter_ms > 0 else None,
         "events_last_step": stats["n_events"], "passes_last_step": stats["n_passes"],
+        "rounds_last_step": stats["n_rounds"],
         "roofline": roofline,
     }
     if overlap:

@@ -157,9 +157,9 @@ typedef struct {
     double vel_to_phys;
     /* Largest number of candidates one scattering step can list for the
      * ordered replay of turns: those accepted with the step-start velocities
-     * plus those found to accept only at their turn.  0: an eighth of
-     * cap_active, at least 65536.  A step that needs more latches
-     * SIDM_E_OVERFLOW (sidm_sync).  Device memory grows by about 290 bytes
+     * plus those found to accept only at their turn.  A step that needs
+     * more latches SIDM_E_OVERFLOW (sidm_sync).  0: a quarter of
+     * cap_active, at least 65536.  Device memory grows by about 190 bytes
      * per listed candidate.  0 .. 2^29. */
     int64_t max_accept;
 } sidm_config;
@@ -184,6 +184,9 @@ typedef struct {
     int32_t n_passes;     /* largest kick depth (see SIDM_CAND_* above)                  */
     int32_t error;        /* latched sidm_status of the device, 0 if none                */
     double max_p;         /* largest step-start P                                        */
+    int32_t n_rounds;     /* checks of the turn order run (1: the candidates accepted at
+                             the step start were all that acted)                          */
+    int32_t pad;
 } sidm_stats;
 
 typedef struct sidm_ctx sidm_ctx;
@@ -202,8 +205,8 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
 sidm_status sidm_destroy(sidm_ctx *ctx);
 sidm_status sidm_set_stream(sidm_ctx *ctx, void *hip_stream);
 /* Replace the context's configuration (for example sigma0 of the next halo a
- * pooled context serves).  n_ngb and precision fix the context's memory layout
- * and must not change (SIDM_E_INVAL otherwise, context unchanged).  The next
+ * pooled context serves).  n_ngb, precision, estimator and max_accept fix the
+ * context's memory layout and must not change (SIDM_E_INVAL otherwise, context unchanged).  The next
  * step needs a new sidm_build_tree.  Host-side only; call it between steps
  * (work already enqueued keeps the old values). */
 sidm_status sidm_reconfigure(sidm_ctx *ctx, const sidm_config *cfg);

@@ -69,7 +69,8 @@ class Stats(ctypes.Structure):
                 ("n_events", ctypes.c_int64), ("n_flagged", ctypes.c_int64),
                 ("n_p_ge_1", ctypes.c_int64), ("n_recheck", ctypes.c_int64),
                 ("n_passes", ctypes.c_int32), ("error", ctypes.c_int32),
-                ("max_p", ctypes.c_double)]
+                ("max_p", ctypes.c_double), ("n_rounds", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

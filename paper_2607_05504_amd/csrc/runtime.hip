@@ -29,14 +29,15 @@ struct Plan {
 };
 
 // Candidates a step can list (accepted at the step start or at their turn):
-// the configuration's max_accept, else an eighth of the active capacity, at
-// least 65536.  The paper's criterion keeps every P(i|j) below C_SIDM, and the
-// workloads accept about 0.01 to 0.2 candidates per active particle.
+// the configuration's max_accept, else a quarter of the active capacity, at
+// least 65536.  The paper's criterion keeps every P(i|j) below C_SIDM; the
+// benchmark workloads accept about 0.01 to 0.12 candidates per active
+// particle.
 int64_t acc_capacity(const sidm_config &cfg, int64_t cap_active)
 {
     if (cfg.max_accept > 0) return cfg.max_accept;
     const int64_t floor_cap = (int64_t)1 << 16;
-    const int64_t e = cap_active / 8;
+    const int64_t e = cap_active / 4;
     return e > floor_cap ? e : floor_cap;
 }
 
@@ -66,17 +67,19 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(knn_nl, c->knn_batch, int32_t);
     ADD(knn_tb, c->knn_batch, double);
     ADD(flag, N, int32_t);
-    ADD(tlist, NA, int32_t); ADD(slot, NA, int32_t);
+    ADD(tlist, NA, int32_t); ADD(slot, NA, int32_t); ADD(tsort, NA, int32_t);
     ADD(blk, (N + SIDM_SCAN_TILE - 1) / SIDM_SCAN_TILE + 1, int32_t);
     ADD(nt_dev, 1, int32_t);
     (void)k;
     const int64_t CA = acc_capacity(c->cfg, NA);
-    const int64_t CR = 4 * CA;              // each turn writes two records; re-rounds add more
+    // each listed candidate holds at most one record pair (the records of a
+    // rewound turn are freed), so two records per listed candidate suffice
+    const int64_t CR = 2 * CA;
     c->cap_acc = CA;
     c->cap_rec = CR;
     ADD(mem.i, CA, int32_t); ADD(mem.j, CA, int32_t); ADD(mem.cand, CA, int32_t);
     ADD(mem.u, CA, double); ADD(mem.W, CA, double); ADD(mem.dt, CA, double);
-    ADD(mem.prio, CA, uint64_t); ADD(mem.idpair, CA, uint64_t);
+    ADD(mem.prio, CA, uint64_t); ADD(mem.idpair, CA, uint64_t); ADD(mem.rec, CA, int32_t);
     ADD(mmark, CA, int32_t);
     ADD(wl[0], CA, int32_t); ADD(wl[1], CA, int32_t);
     ADD(plist, 2 * CA, int32_t);
@@ -84,9 +87,11 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(trec.vx, CR, double); ADD(trec.vy, CR, double); ADD(trec.vz, CR, double);
     ADD(trec.mem, CR, int32_t); ADD(trec.prev, CR, int32_t); ADD(trec.part, CR, int32_t);
     ADD(trec.info, CR, uint32_t);
+    ADD(rfree, CR / 2, int32_t);
     ADD(head, N, int32_t);
     ADD(tmin, N, unsigned long long);
-    ADD(rstats, 1, RoundStats);
+    ADD(dbits, (N + 31) / 32, uint32_t);
+    ADD(flist, 2 * SIDM_FLAG_CAP, int32_t);
     for (int b = 0; b < 2; ++b) {
         ADD(claim1[b], N, unsigned long long); ADD(claim2[b], N, unsigned long long);
     }
@@ -288,6 +293,7 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
     launch_fill_i32(c->head, -1, cap_n, s);
     launch_fill_u64(c->tmin, ~0ull, cap_n, s);
     launch_fill_i32(c->mmark, 0, c->cap_acc, s);
+    launch_fill_i32((int32_t *)c->dbits, 0, (cap_n + 31) / 32, s);
     c->dev_rounds = test_device_rounds();
     launch_fill_i32((int32_t *)c->dstats, 0, (int64_t)(sizeof(DevStats) / 4), s);
     hipError_t e = copy_table(c);
@@ -382,8 +388,9 @@ sidm_status sidm_reconfigure(sidm_ctx *c, const sidm_config *cfg)
         return SIDM_E_INVAL;
     }
     if (cfg->n_ngb != c->cfg.n_ngb || cfg->precision != c->cfg.precision ||
-        cfg->estimator != c->cfg.estimator) {
-        set_err(c, "reconfigure: n_ngb, precision and estimator fix the context's layout");
+        cfg->estimator != c->cfg.estimator || cfg->max_accept != c->cfg.max_accept) {
+        set_err(c, "reconfigure: n_ngb, precision, estimator and max_accept fix the "
+                   "context's layout");
         return SIDM_E_INVAL;
     }
     c->cfg = *cfg;
@@ -763,6 +770,7 @@ sidm_status sidm_sync(sidm_ctx *c, sidm_stats *out)
         out->n_p_ge_1 = (int64_t)d.n_p_ge_1;
         out->n_recheck = (int64_t)d.n_recheck;
         out->n_passes = (int32_t)d.n_passes;
+        out->n_rounds = (int32_t)d.n_rounds;
         out->error = (int32_t)st;
         unsigned long long mb = d.max_p_bits;
         double mp;

@@ -44,10 +44,12 @@ constexpr int kEvalGrid = 6 * 256;     // evaluation workgroups at least (fewer 
 constexpr int kFinisherMax = 256;      // shorter lists go to the one-workgroup finisher
 
 // control words: [0..1] pass list counts, [2] completed passes, [3] hand-off
-// flag, [4] listed candidates, [5] turn records, [6] first candidate listed
-// since the last replay, [7] done (no candidate newly listed)
+// flag, [4] listed candidates, [5] turn-record pairs ever used (x2), [6]
+// first candidate listed since the last replay, [7] done (no candidate newly
+// listed), [8] free record pairs, [9] re-rounds run, [10] particles of D
+// (in plist), [11] flagged candidates listed for the final count
 enum { CTL_COUNT0 = 0, CTL_COUNT1 = 1, CTL_PASS = 2, CTL_HANDOFF = 3, CTL_MEM = 4, CTL_REC = 5,
-       CTL_NEWLO = 6, CTL_DONE = 7 };
+       CTL_NEWLO = 6, CTL_DONE = 7, CTL_FREE = 8, CTL_ROUNDS = 9, CTL_PL = 10, CTL_FLAG = 11 };
 
 struct StepArgs {
     // Morton-ordered snapshot
@@ -66,10 +68,12 @@ struct StepArgs {
     uint32_t *cand_info;
     // resolution: listed candidates, pass lists, histories
     AccList M;
-    int32_t *wl0, *wl1, *mmark, *plist, *head;
+    int32_t *wl0, *wl1, *mmark, *plist, *head, *rfree;
     TurnRecords R;
     unsigned long long *tmin;
-    RoundStats *rs;
+    uint32_t *dbits;
+    int32_t *flist;
+    const int32_t *tsort;
     int32_t *ctl;
     unsigned long long *c1a, *c1b, *c2a, *c2b;
     DevStats *st;
@@ -271,6 +275,7 @@ __device__ void flush_staged(const StepArgs &A, StagedAcc &S, int n, int32_t &ba
         A.M.u[pos] = S.u[t]; A.M.W[pos] = S.W[t]; A.M.dt[pos] = A.dt[a];
         A.M.prio[pos] = direction_word(xp, idi < idj);
         A.M.idpair[pos] = ((uint64_t)idi << 32) | idj;
+        A.M.rec[pos] = -1;
         A.wl0[pos] = (int32_t)pos;
         A.c1a[i] = ~0ull; A.c1a[j] = ~0ull;
         A.c2a[i] = ~0ull; A.c2a[j] = ~0ull;
@@ -538,7 +543,13 @@ __device__ void take_turn(const StepArgs &A, int32_t m)
     const double sig = sigma_of(A, w);
     const double P = pair_allowed(A, i, j) ? pair_prob(mass_of(A, j), sig, w, A.M.W[m], A.M.dt[m]) : 0.0;
     const bool hit = A.M.u[m] < P;
-    const int32_t r = atomicAdd(&A.ctl[CTL_REC], 2);
+    // a record pair (r at i, r + 1 at j): one a rewind freed, else a new one
+    int32_t r = -1;
+    if (load_i32(&A.ctl[CTL_FREE]) > 0) {
+        const int32_t f = atomicSub(&A.ctl[CTL_FREE], 1);
+        if (f > 0) r = 2 * A.rfree[f - 1];
+    }
+    if (r < 0) r = atomicAdd(&A.ctl[CTL_REC], 2);
     if ((int64_t)r + 2 <= A.cap_rec) {
         const int32_t hi = A.head[i], hj = A.head[j];
         const uint32_t di = hi >= 0 ? A.R.info[hi] >> 8 : 0u, dj = hj >= 0 ? A.R.info[hj] >> 8 : 0u;
@@ -548,6 +559,7 @@ __device__ void take_turn(const StepArgs &A, int32_t m)
         put_record(A, r + 1, j, pr, ip, m, hj, hit ? (1u | (d << 8)) : (dj << 8));
         A.head[i] = r;
         A.head[j] = r + 1;
+        A.M.rec[m] = r;
     } else {
         atomicOr(A.derr, DERR_HISTORY);
     }
@@ -654,38 +666,70 @@ __device__ void wg_passes(const StepArgs &A, int t0, int64_t cnt0, PassShared &S
     }
 }
 
+// D, the particles whose history changed since the last check, is marked by
+// tmin != ~0 (sorted index) and by a bit per caller index, which the check's
+// scan tests against the rows' caller indices without a gather.
+__device__ __forceinline__ void set_dbit(const StepArgs &A, int32_t p)
+{
+    const int32_t c = A.perm[p];
+    atomicOr(&A.dbits[c >> 5], 1u << (c & 31));
+}
+__device__ __forceinline__ void clear_dbit(const StepArgs &A, int32_t p)
+{
+    const int32_t c = A.perm[p];
+    atomicAnd(&A.dbits[c >> 5], ~(1u << (c & 31)));
+}
+__device__ __forceinline__ bool dbit(const StepArgs &A, int32_t c)
+{
+    return (A.dbits[c >> 5] >> (c & 31)) & 1u;
+}
+
 // Round 1: one workgroup finishes whatever passes the grid left, then sets
-// up the first check.
+// up the first check: the particles with a history (those of the listed
+// candidates) become D.
 __global__ __launch_bounds__(1024) void k_finish(StepArgs A)
 {
     __shared__ PassShared S;
     __shared__ int s_t0;
     __shared__ int64_t s_c0;
+    __shared__ int32_t s_pl;
     if (threadIdx.x == 0) {
         s_t0 = A.ctl[CTL_PASS];
         s_c0 = list_count(A, s_t0);
+        s_pl = 0;
     }
     __syncthreads();
     const int t0 = s_t0;
     const int64_t c0 = s_c0;
     __syncthreads();
     wg_passes(A, t0, c0, S);
+    int64_t mc = A.ctl[CTL_MEM];
+    mc = mc < A.cap_acc ? mc : A.cap_acc;
+    for (int64_t m = threadIdx.x; m < mc; m += blockDim.x) {
+        const int32_t pp[2] = {A.M.i[m], A.M.j[m]};
+        for (int u = 0; u < 2; ++u)
+            if (atomicMin(&A.tmin[pp[u]], 0ull) == ~0ull) {
+                A.plist[atomicAdd(&s_pl, 1)] = pp[u];
+                set_dbit(A, pp[u]);
+            }
+    }
+    wg_sync();
     if (threadIdx.x == 0) {
-        const int64_t mcount = A.ctl[CTL_MEM];
-        A.ctl[CTL_NEWLO] = (int32_t)(mcount < A.cap_acc ? mcount : A.cap_acc);
-        *A.rs = RoundStats{};
+        A.ctl[CTL_NEWLO] = (int32_t)mc;
+        A.ctl[CTL_PL] = s_pl;
+        if (A.ctl[CTL_FREE] < 0) A.ctl[CTL_FREE] = 0;
     }
 }
 
 // ----------------------------------------------------------------------------
-// Check of a round: every candidate touching a particle with a history is
-// evaluated at its turn.
+// Check of a round: every candidate touching a particle of D (whose history
+// changed since the last check) is evaluated at its turn.
 // ----------------------------------------------------------------------------
 
 // The history of particle p at key (kp, ki): (tx, ty, tz) its velocity at that
 // turn, rge the earliest record with key >= (kp, ki) (-1 if none), and
 // (sx, sy, sz) its velocity at the step start.  Records go from the latest
-// turn back, with decreasing keys and decreasing record indices.
+// turn back, with decreasing keys (the guard only bounds a corrupted chain).
 __device__ __forceinline__ void history_at(const StepArgs &A, int32_t p, uint64_t kp, uint64_t ki,
                                            double &tx, double &ty, double &tz, int32_t &rge,
                                            double &sx, double &sy, double &sz)
@@ -694,128 +738,117 @@ __device__ __forceinline__ void history_at(const StepArgs &A, int32_t p, uint64_
     ty = sy = A.vys[p];
     tz = sz = A.vzs[p];
     rge = -1;
-    int32_t r = A.head[p], last = 0x7fffffff;
-    while (r >= 0 && r < last) {
+    int32_t r = A.head[p];
+    for (int64_t guard = 0; r >= 0 && guard < A.cap_rec; ++guard) {
         const uint64_t rp = A.R.prio[r], rq = A.R.idpair[r];
         const double ax = A.R.vx[r], ay = A.R.vy[r], az = A.R.vz[r];
         if (rp > kp || (rp == kp && rq >= ki)) { rge = r; tx = ax; ty = ay; tz = az; }
         sx = ax; sy = ay; sz = az;
-        last = r;
         r = A.R.prev[r];
     }
 }
 
-struct CheckAcc {
-    unsigned long long events;
-    long long dflag;
-    unsigned int depth;
+// Candidate slot s of row a (target i, Morton order) at its turn, with the
+// velocities the histories give there and at the step start.
+struct TurnEval {
+    double u, W, Pt, Ps;
+    uint64_t kp, ki;
+    int32_t j, ri;          // partner; earliest record of i at or after the key
 };
 
 template <bool PERIODIC, bool OVERLAP>
-__device__ void check_candidate(const StepArgs &A, int64_t b, int s, int32_t a, CheckAcc &acc)
+__device__ bool eval_turn(const StepArgs &A, int32_t i, int32_t a, int s, TurnEval &T)
 {
-    const int32_t i = A.tlist[b];
     const int64_t ci = (int64_t)a * A.stride + s;
     const int32_t jc = A.ngb[ci];
-    if (jc < 0 || jc >= A.n) return;          // latched by the evaluation
+    if (jc < 0 || jc >= A.n) return false;    // latched by the evaluation
     const int32_t j = A.inv[jc];
-    if (A.head[i] < 0 && A.head[j] < 0) return;   // untouched: the step-start decision stands
     const uint32_t idi = A.ids[i], idj = A.ids[j];
-    const uint64_t kp = direction_word(pair_draw(A.seed, A.step, idi, idj, PURPOSE_PRIORITY), idi < idj);
-    const uint64_t ki = ((uint64_t)idi << 32) | idj;
-    const double u = unit_from_word(direction_word(pair_draw(A.seed, A.step, idi, idj, PURPOSE_DECIDE),
-                                                   idi < idj));
+    T.j = j;
+    T.kp = direction_word(pair_draw(A.seed, A.step, idi, idj, PURPOSE_PRIORITY), idi < idj);
+    T.ki = ((uint64_t)idi << 32) | idj;
+    T.u = unit_from_word(direction_word(pair_draw(A.seed, A.step, idi, idj, PURPOSE_DECIDE),
+                                        idi < idj));
     double tix, tiy, tiz, six, siy, siz, tjx, tjy, tjz, sjx, sjy, sjz;
-    int32_t ri, rj;
-    history_at(A, i, kp, ki, tix, tiy, tiz, ri, six, siy, siz);
-    history_at(A, j, kp, ki, tjx, tjy, tjz, rj, sjx, sjy, sjz);
+    int32_t rj;
+    history_at(A, i, T.kp, T.ki, tix, tiy, tiz, T.ri, six, siy, siz);
+    history_at(A, j, T.kp, T.ki, tjx, tjy, tjz, rj, sjx, sjy, sjz);
     const double r = A.lphys * sqrt(sep2<PERIODIC>(A.xs[i], A.ys[i], A.zs[i], A.xs[j], A.ys[j],
                                                    A.zs[j], A.box));
-    const double W = OVERLAP ? overlap_g(A.gtab, A.lphys * A.hsrt[i], A.lphys * A.hsrt[j], r)
-                             : cubic_spline(r, A.lphys * A.h[a]);
+    T.W = OVERLAP ? overlap_g(A.gtab, A.lphys * A.hsrt[i], A.lphys * A.hsrt[j], r)
+                  : cubic_spline(r, A.lphys * A.h[a]);
     const bool allowed = pair_allowed(A, i, j);
     const double mj = mass_of(A, j), dta = A.dt[a];
     const double wt = A.vphys * rel_speed(tix, tiy, tiz, tjx, tjy, tjz);
-    const double Pt = allowed ? pair_prob(mj, sigma_of(A, wt), wt, W, dta) : 0.0;
+    T.Pt = allowed ? pair_prob(mj, sigma_of(A, wt), wt, T.W, dta) : 0.0;
     const double ws = A.vphys * rel_speed(six, siy, siz, sjx, sjy, sjz);
-    const double Ps = allowed ? pair_prob(mj, sigma_of(A, ws), ws, W, dta) : 0.0;
-    const bool listed = ri >= 0 && A.R.prio[ri] == kp && A.R.idpair[ri] == ki;
-    const bool kicked = listed && (A.R.info[ri] & 1u);
-    const uint32_t depth = kicked ? A.R.info[ri] >> 8 : 0u;
-    const bool flag_t = fabs(Pt - u) < A.band, flag_s = fabs(Ps - u) < A.band;
-    if (!listed && u < Pt) {
+    T.Ps = allowed ? pair_prob(mj, sigma_of(A, ws), ws, T.W, dta) : 0.0;
+    return true;
+}
+
+template <bool PERIODIC, bool OVERLAP>
+__device__ void check_candidate(const StepArgs &A, int32_t i, int32_t a, int s)
+{
+    TurnEval T;
+    if (!eval_turn<PERIODIC, OVERLAP>(A, i, a, s, T)) return;
+    const int64_t ci = (int64_t)a * A.stride + s;
+    const bool listed = T.ri >= 0 && A.R.prio[T.ri] == T.kp && A.R.idpair[T.ri] == T.ki;
+    const bool kicked = listed && (A.R.info[T.ri] & 1u);
+    const uint32_t depth = kicked ? A.R.info[T.ri] >> 8 : 0u;
+    const bool flag_t = fabs(T.Pt - T.u) < A.band, flag_s = fabs(T.Ps - T.u) < A.band;
+    if (!listed && T.u < T.Pt) {
         // accepts at its turn but did not take it: list it for the next round
         const int32_t pos = atomicAdd(&A.ctl[CTL_MEM], 1);
         if (pos < A.cap_acc) {
-            A.M.i[pos] = i; A.M.j[pos] = j; A.M.cand[pos] = (int32_t)ci;
-            A.M.u[pos] = u; A.M.W[pos] = W; A.M.dt[pos] = dta;
-            A.M.prio[pos] = kp; A.M.idpair[pos] = ki;
+            A.M.i[pos] = i; A.M.j[pos] = T.j; A.M.cand[pos] = (int32_t)ci;
+            A.M.u[pos] = T.u; A.M.W[pos] = T.W; A.M.dt[pos] = A.dt[a];
+            A.M.prio[pos] = T.kp; A.M.idpair[pos] = T.ki; A.M.rec[pos] = -1;
         } else {
             atomicOr(A.derr, DERR_OVERFLOW);
         }
     }
-    acc.events += kicked;
-    acc.dflag += (long long)flag_t - (long long)flag_s;
-    acc.depth = depth > acc.depth ? depth : acc.depth;
+    if (flag_t || flag_s) {
+        // counted again at the end of the step with the final histories
+        const int32_t f = atomicAdd(&A.ctl[CTL_FLAG], 1);
+        if (f < SIDM_FLAG_CAP) { A.flist[2 * f] = i; A.flist[2 * f + 1] = (int32_t)ci; }
+        else atomicOr(A.derr, DERR_OVERFLOW);
+    }
     if (A.cand_info)
-        A.cand_info[ci] = (u < Ps ? SIDM_CAND_ACCEPT0 : 0u) | (flag_t ? SIDM_CAND_FLAGGED : 0u) |
+        A.cand_info[ci] = (T.u < T.Ps ? SIDM_CAND_ACCEPT0 : 0u) | (flag_t ? SIDM_CAND_FLAGGED : 0u) |
                           (kicked ? (SIDM_CAND_SCATTER | (depth << 8)) : 0u);
 }
 
-// every candidate of the step, strided over the threads given
+// The check's scan: every candidate whose target or partner is in D, each
+// once.  Rows in the caller's order (coalesced), D tested on the partners'
+// caller indices in the bitmap; first..total strided by the threads given.
 template <bool PERIODIC, bool OVERLAP>
-__device__ void check_range(const StepArgs &A, int64_t first, int64_t stride_threads, CheckAcc &acc)
+__device__ void check_scan(const StepArgs &A, int64_t first, int64_t nthreads)
 {
     const int64_t nt = *A.nt_dev;
     const int64_t total = nt * A.stride;
-    for (int64_t c = first; c < total; c += stride_threads) {
-        const int64_t b = c / A.stride;
-        const int s = (int)(c - b * A.stride);
-        const int32_t a = A.slot[b];
+    for (int64_t c = first; c < total; c += nthreads) {
+        const int64_t a = total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)A.stride) : c / A.stride;
+        const int s = (int)(c - a * A.stride);
         if (OVERLAP && s >= A.cnt[a]) continue;
-        check_candidate<PERIODIC, OVERLAP>(A, b, s, a, acc);
-    }
-}
-
-// workgroup reduction of a check's counts into the round's counts
-__device__ void add_check_counts(const StepArgs &A, CheckAcc acc, unsigned long long (*red)[3])
-{
-    unsigned long long ev = acc.events, df = (unsigned long long)acc.dflag, dp = acc.depth;
-    for (int off = 32; off > 0; off >>= 1) {
-        ev += (unsigned long long)__shfl_xor((long long)ev, off);
-        df += (unsigned long long)__shfl_xor((long long)df, off);
-        const unsigned long long o = (unsigned long long)__shfl_xor((long long)dp, off);
-        dp = o > dp ? o : dp;
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { red[w][0] = ev; red[w][1] = df; red[w][2] = dp; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long e = 0, f = 0, d = 0;
-        for (int v = 0; v < (int)(blockDim.x >> 6); ++v) {
-            e += red[v][0]; f += red[v][1];
-            d = red[v][2] > d ? red[v][2] : d;
-        }
-        if (e) atomicAdd(&A.rs->events, e);
-        if (f) atomicAdd((unsigned long long *)&A.rs->dflag, f);
-        if (d) atomicMax(&A.rs->max_depth, (unsigned int)d);
+        const int32_t jc = A.ngb[c];
+        const int32_t i = A.tsort[a];
+        const bool hit = (jc >= 0 && jc < A.n && dbit(A, jc)) || dbit(A, A.perm[i]);
+        if (hit) check_candidate<PERIODIC, OVERLAP>(A, i, (int32_t)a, s);
     }
 }
 
 template <bool PERIODIC, bool OVERLAP>
 __global__ __launch_bounds__(kBlock) void k_check(StepArgs A)
 {
-    __shared__ unsigned long long red[kBlock / 64][3];
     if (A.ctl[CTL_DONE]) return;
-    CheckAcc acc{0, 0, 0};
-    check_range<PERIODIC, OVERLAP>(A, blockIdx.x * (int64_t)blockDim.x + threadIdx.x,
-                                   (int64_t)gridDim.x * blockDim.x, acc);
-    add_check_counts(A, acc, red);
+    check_scan<PERIODIC, OVERLAP>(A, blockIdx.x * (int64_t)kBlock + threadIdx.x,
+                                  (int64_t)gridDim.x * kBlock);
 }
 
 // ----------------------------------------------------------------------------
 // Re-round: list the newly accepting candidates, rewind the turns they can
-// affect and take them again.  One workgroup.
+// affect and take them again.  One workgroup.  The rewound particles become
+// the next check's D.
 // ----------------------------------------------------------------------------
 struct RoundShared {
     PassShared ps;
@@ -848,6 +881,13 @@ __device__ void reround_body(const StepArgs &A, RoundShared &S)
     }
     __syncthreads();
     if (!S.go) return;
+    // the last check's D is done with
+    const int32_t old_pl = load_i32(&A.ctl[CTL_PL]);
+    for (int32_t q = tid; q < old_pl; q += nth) {
+        const int32_t p = A.plist[q];
+        atomicExch(&A.tmin[p], ~0ull);
+        clear_dbit(A, p);
+    }
     // seeds: the newly listed candidates
     const int32_t n0 = S.hi - S.lo;
     for (int32_t q = tid; q < n0; q += nth) {
@@ -867,18 +907,20 @@ __device__ void reround_body(const StepArgs &A, RoundShared &S)
             const int32_t pp[2] = {A.M.i[m], A.M.j[m]};
             for (int u = 0; u < 2; ++u) {
                 const unsigned long long old = atomicMin(&A.tmin[pp[u]], pr);
-                if (old == ~0ull) A.plist[atomicAdd(&S.pl, 1)] = pp[u];
+                if (old == ~0ull) {
+                    A.plist[atomicAdd(&S.pl, 1)] = pp[u];
+                    set_dbit(A, pp[u]);
+                }
             }
         }
         wg_sync();
         for (int32_t q = tid; q < S.pl; q += nth) {
             const int32_t p = A.plist[q];
             const unsigned long long tp = load_u64(&A.tmin[p]);
-            int32_t r = A.head[p], last = 0x7fffffff;
-            while (r >= 0 && r < last && A.R.prio[r] >= tp) {
+            int32_t r = A.head[p];
+            for (int64_t guard = 0; r >= 0 && guard < A.cap_rec && A.R.prio[r] >= tp; ++guard) {
                 const int32_t m2 = A.R.mem[r];
                 if (atomicCAS(&A.mmark[m2], 0, 1) == 0) A.wl0[atomicAdd(&S.dl, 1)] = m2;
-                last = r;
                 r = A.R.prev[r];
             }
         }
@@ -890,14 +932,17 @@ __device__ void reround_body(const StepArgs &A, RoundShared &S)
         __syncthreads();
     }
     // rewind: each particle back to its velocity (and state) before the
-    // earliest replayed turn, its history cut there
+    // earliest marked turn, its history cut there; tmin stays set, marking
+    // the particle as one of the next check's D
     for (int32_t q = tid; q < S.pl; q += nth) {
         const int32_t p = A.plist[q];
         const unsigned long long tp = load_u64(&A.tmin[p]);
-        int32_t r = A.head[p], last = 0x7fffffff, rr = -1;
-        while (r >= 0 && r < last && A.R.prio[r] >= tp) {
+        int32_t r = A.head[p], rr = -1;
+        for (int64_t guard = 0; r >= 0 && guard < A.cap_rec && A.R.prio[r] >= tp; ++guard) {
+            // a turn's records are cut together (its two particles both
+            // rewind past it): the pair is freed once, at its first record
+            if ((r & 1) == 0) A.rfree[atomicAdd(&A.ctl[CTL_FREE], 1)] = r >> 1;
             rr = r;
-            last = r;
             r = A.R.prev[r];
         }
         A.head[p] = r;
@@ -912,7 +957,6 @@ __device__ void reround_body(const StepArgs &A, RoundShared &S)
                 if (A.state) A.state[op] = st;
             }
         }
-        atomicExch(&A.tmin[p], ~0ull);
     }
     wg_sync();
     for (int32_t q = tid; q < S.dl; q += nth) {
@@ -927,7 +971,10 @@ __device__ void reround_body(const StepArgs &A, RoundShared &S)
     wg_sync();
     if (tid == 0) {
         A.ctl[CTL_NEWLO] = S.hi;
-        *A.rs = RoundStats{};
+        A.ctl[CTL_PL] = S.pl;
+        A.ctl[CTL_ROUNDS] += 1;
+        // pops that found the free stack empty left the count below zero
+        if (A.ctl[CTL_FREE] < 0) A.ctl[CTL_FREE] = 0;
     }
     wg_sync();
 }
@@ -938,16 +985,15 @@ __global__ __launch_bounds__(1024) void k_reround(StepArgs A)
     reround_body(A, S);
 }
 
-// Rounds left after the grid launches: checks and re-rounds in one workgroup
-// until no candidate is newly listed.  Every round lists at least one more
-// candidate or ends, and the list is bounded, so the loop ends.
+// Rounds left after the grid launches: checks and re-rounds in one
+// workgroup until no candidate is newly listed.  Every round lists at least
+// one more candidate or ends, and the list is bounded, so the loop ends.
 constexpr int kTailRounds = 1 << 16;       // far above any round count seen
 
 template <bool PERIODIC, bool OVERLAP>
 __global__ __launch_bounds__(1024) void k_tail(StepArgs A)
 {
     __shared__ RoundShared S;
-    __shared__ unsigned long long red[1024 / 64][3];
     __shared__ int s_done;
     for (int round = 0;; ++round) {
         if (threadIdx.x == 0) {
@@ -959,41 +1005,87 @@ __global__ __launch_bounds__(1024) void k_tail(StepArgs A)
         }
         __syncthreads();
         if (s_done) break;
-        CheckAcc acc{0, 0, 0};
-        check_range<PERIODIC, OVERLAP>(A, threadIdx.x, blockDim.x, acc);
-        add_check_counts(A, acc, red);
+        check_scan<PERIODIC, OVERLAP>(A, threadIdx.x, blockDim.x);
         wg_sync();
         reround_body(A, S);
         wg_sync();
     }
 }
 
-// End of the step: the last check's counts become the step's, and every
-// history is cleared for the next step.
+// End of the step, one workgroup: the kicks and the largest kick depth from
+// the listed candidates' turns, and the flagged count corrected by the
+// candidates a check saw flagged (at the step start or at their turn),
+// evaluated again with the final histories (each once).
+template <bool PERIODIC, bool OVERLAP>
+__global__ __launch_bounds__(1024) void k_final_stats(StepArgs A)
+{
+    __shared__ unsigned long long s_ev;
+    __shared__ long long s_df;
+    __shared__ unsigned int s_dp;
+    if (threadIdx.x == 0) { s_ev = 0; s_df = 0; s_dp = 0; }
+    __syncthreads();
+    int64_t mc = A.ctl[CTL_MEM];
+    mc = mc < A.cap_acc ? mc : A.cap_acc;
+    unsigned long long ev = 0;
+    unsigned int dp = 0;
+    for (int64_t m = threadIdx.x; m < mc; m += blockDim.x) {
+        const int32_t r = A.M.rec[m];
+        if (r < 0) continue;
+        const uint32_t info = A.R.info[r];
+        if (info & 1u) {
+            ++ev;
+            dp = (info >> 8) > dp ? (info >> 8) : dp;
+        }
+    }
+    int nf = A.ctl[CTL_FLAG];
+    nf = nf < SIDM_FLAG_CAP ? nf : SIDM_FLAG_CAP;
+    long long df = 0;
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+        const int32_t i = A.flist[2 * f], ci = A.flist[2 * f + 1];
+        bool first = true;
+        for (int g = 0; g < f && first; ++g) first = A.flist[2 * g + 1] != ci;
+        if (!first) continue;
+        const int32_t a = (int32_t)(ci / A.stride);
+        TurnEval T;
+        if (!eval_turn<PERIODIC, OVERLAP>(A, i, a, (int)(ci - (int64_t)a * A.stride), T)) continue;
+        df += (long long)(fabs(T.Pt - T.u) < A.band) - (long long)(fabs(T.Ps - T.u) < A.band);
+    }
+    if (ev) atomicAdd(&s_ev, ev);
+    if (df) atomicAdd((unsigned long long *)&s_df, (unsigned long long)df);
+    if (dp) atomicMax(&s_dp, dp);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        A.st->n_events = s_ev;
+        A.st->n_flagged += (unsigned long long)s_df;
+        A.st->n_passes = s_dp;
+        A.st->n_rounds = 1u + (unsigned)A.ctl[CTL_ROUNDS];
+    }
+}
+
+// Clears every history and the last check's D for the next step.
 __global__ __launch_bounds__(kBlock) void k_step_final(StepArgs A)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const RoundStats r = *A.rs;
-        A.st->n_events = r.events;
-        A.st->n_flagged += (unsigned long long)r.dflag;
-        A.st->n_passes = r.max_depth;
-    }
     int64_t nr = A.ctl[CTL_REC];
     nr = nr < A.cap_rec ? nr : A.cap_rec;
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nr;
          r += (int64_t)gridDim.x * blockDim.x)
         A.head[A.R.part[r]] = -1;
+    const int32_t np = A.ctl[CTL_PL];
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < np;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        A.tmin[A.plist[q]] = ~0ull;
+        clear_dbit(A, A.plist[q]);
+    }
 }
 
 // Zeroes the step's statistics and control words; with nt_dev given, the
 // candidate count is the number of targets times k.
-__global__ void k_step_reset(DevStats *st, int32_t *ctl, RoundStats *rs, const int32_t *nt_dev, int k)
+__global__ void k_step_reset(DevStats *st, int32_t *ctl, const int32_t *nt_dev, int k)
 {
     if (threadIdx.x == 0) {
         DevStats z = {};
         if (nt_dev) z.n_cand = (unsigned long long)(*nt_dev) * (unsigned long long)k;
         *st = z;
-        *rs = RoundStats{};
         for (int q = 0; q < 16; ++q) ctl[q] = 0;
     }
 }
@@ -1111,7 +1203,8 @@ StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const dou
     A.ngb = ngb; A.h = h; A.dt = dt; A.cand_info = cand_info;
     A.M = c->mem;
     A.wl0 = c->wl[0]; A.wl1 = c->wl[1]; A.mmark = c->mmark; A.plist = c->plist; A.head = c->head;
-    A.R = c->trec; A.tmin = c->tmin; A.rs = c->rstats; A.cap_rec = c->cap_rec;
+    A.R = c->trec; A.tmin = c->tmin; A.cap_rec = c->cap_rec;
+    A.rfree = c->rfree; A.dbits = c->dbits; A.flist = c->flist; A.tsort = c->tsort;
     A.ctl = c->acc_count;
     A.c1a = c->claim1[0]; A.c1b = c->claim1[1]; A.c2a = c->claim2[0]; A.c2b = c->claim2[1];
     A.st = c->dstats; A.derr = c->derr;
@@ -1140,7 +1233,7 @@ template <bool P, bool M, bool O = false>
 void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s)
 {
     const int64_t total = n_active * A.stride;
-    k_step_reset<<<1, 64, 0, s>>>(A.st, A.ctl, A.rs, O ? nullptr : A.nt_dev, A.k);
+    k_step_reset<<<1, 64, 0, s>>>(A.st, A.ctl, O ? nullptr : A.nt_dev, A.k);
     phase_begin(c, PH_EVAL);
     // at least as many workgroups as are resident at once (the staging
     // buffer's LDS allows six per CU), more for long candidate lists (about
@@ -1163,13 +1256,17 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
     k_finish<<<1, 1024, 0, s>>>(A);
     // checks and re-rounds until no candidate is newly listed (the kernels of
     // rounds after that return at once)
+    int64_t dmax = 2 * (A.cap_acc < total ? A.cap_acc : total);
+    dmax = dmax < A.n ? dmax : A.n;
+    const int gcheck = grid_for(total, 8192);
     for (int r = 0; r < c->dev_rounds; ++r) {
-        k_check<P, O><<<geval, kBlock, 0, s>>>(A);
+        k_check<P, O><<<gcheck, kBlock, 0, s>>>(A);
         k_reround<<<1, 1024, 0, s>>>(A);
     }
     k_tail<P, O><<<1, 1024, 0, s>>>(A);
+    k_final_stats<P, O><<<1, 1024, 0, s>>>(A);
     const int64_t nrec = A.cap_rec < 2 * total ? A.cap_rec : 2 * total;
-    k_step_final<<<grid_for(nrec, 1024), kBlock, 0, s>>>(A);
+    k_step_final<<<grid_for(nrec > dmax ? nrec : dmax, 1024), kBlock, 0, s>>>(A);
     phase_end(c, PH_RESOLVE);
 }
 

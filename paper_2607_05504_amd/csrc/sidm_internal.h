@@ -65,7 +65,7 @@ inline int64_t tree_node_count(const TreeLevels &t)
 struct DevStats {
     unsigned long long n_cand, n_accept0, n_events, n_flagged, n_p_ge_1, n_recheck;
     unsigned long long max_p_bits;      // positive doubles order like their bit patterns
-    unsigned int n_passes, pad;
+    unsigned int n_passes, n_rounds;
 };
 
 // The candidates (i|j) of a step whose turns are replayed in order (accepted
@@ -79,6 +79,7 @@ struct AccList {
     double *dt;              // timestep of the target
     uint64_t *prio;          // priority word
     uint64_t *idpair;        // (id_i << 32) | id_j
+    int32_t *rec;            // its turn's record pair (first record), -1 before its turn
 };
 
 // One turn of a listed candidate at one of its two particles: the particle's
@@ -92,12 +93,7 @@ struct TurnRecords {
     uint32_t *info;          // bit 0: kicked; bits 1..7: state before; bits 8..: kick depth after
 };
 
-// per-round counts of the check that verifies a round (see scatter.hip)
-struct RoundStats {
-    unsigned long long events;    // listed candidates that kicked
-    long long dflag;              // flagged turns minus flagged step-start evaluations
-    unsigned int max_depth, pad;
-};
+#define SIDM_FLAG_CAP 4096    // candidates whose flagged status a step re-counts at its end
 
 struct sidm_ctx {
     sidm_config cfg;
@@ -144,6 +140,7 @@ struct sidm_ctx {
     int32_t *flag;           // [cap_n] caller slot of an active particle, or -1
     int32_t *tlist;          // [cap_active] sorted index of the b-th active particle
     int32_t *slot;           // [cap_active] its position in the caller's active list
+    int32_t *tsort;          // [cap_active] sorted index of the particle in caller slot a
     int32_t *blk;            // compaction block counts / offsets
     int32_t *nt_dev;         // number of compacted targets
     int map_valid;           // the arrays above hold the mapping of map_n targets
@@ -154,10 +151,12 @@ struct sidm_ctx {
     int32_t *mmark;          // [cap_acc] 1 while a listed candidate is marked for replay
     int32_t *wl[2];          // [cap_acc] pass work lists (indices into mem)
     int32_t *plist;          // [2 cap_acc] particles whose history a re-round rewinds
-    TurnRecords trec;        // [cap_rec] turn records
+    TurnRecords trec;        // [cap_rec] turn records, in pairs (one per particle of a turn)
+    int32_t *rfree;          // [cap_rec / 2] record pairs a rewind freed
     int32_t *head;           // [cap_n] latest turn record of each particle, -1 if none
     unsigned long long *tmin;     // [cap_n] smallest priority a re-round replays, ~0 if none
-    RoundStats *rstats;
+    uint32_t *dbits;         // [cap_n / 32] bit per caller index: the particle is in D
+    int32_t *flist;          // [2 SIDM_FLAG_CAP] (target, candidate slot) once flagged
     int32_t *acc_count;      // [16] control words (list counts, passes, rounds)
     unsigned long long *claim1[2], *claim2[2];   // [cap_n] per-particle claims
     int dev_rounds;          // rounds run as grid launches before the one-workgroup tail

@@ -88,8 +88,14 @@ class Server:
         self.used = 0                                    # bytes held by running requests
 
     # -- memory --------------------------------------------------------------
+    def _config(self, w, cap):
+        # a request's first step runs at the largest step length before any
+        # per-pair bound exists: far outside the criterion, up to about one
+        # candidate per particle accepts, so the list is sized for that
+        return runner.config_for(w, precision=self.cfg.precision, max_accept=max(cap, 1))
+
     def _ctx_bytes(self, w, cap):
-        return footprint(runner.config_for(w, precision=self.cfg.precision), cap, cap)
+        return footprint(self._config(w, cap), cap, cap)
 
     def _take_ctx(self, w, cap, stream):
         """A context of capacity cap bound to stream, from the pool if one is idle."""
@@ -97,9 +103,9 @@ class Server:
             ctx = self.pool[cap].pop()
             self.pool_mem -= ctx._serve_bytes
             ctx.set_stream(stream)
-            ctx.reconfigure(runner.config_for(w, precision=self.cfg.precision))
+            ctx.reconfigure(self._config(w, cap))
             return ctx
-        ctx = Context(runner.config_for(w, precision=self.cfg.precision), cap, cap, stream=stream)
+        ctx = Context(self._config(w, cap), cap, cap, stream=stream)
         ctx._serve_bytes = self._ctx_bytes(w, cap)
         return ctx
 

@@ -140,14 +140,14 @@ def test_neighbour_count_limits():
 
 def test_listed_candidate_capacity():
     """max_accept sizes the list of candidates whose turns are replayed
-    (0: an eighth of the active capacity, at least 65536); about 290 bytes
+    (0: a quarter of the active capacity, at least 65536); about 190 bytes
     each."""
     L = sidm.lib()
     base = sidm.make_config(n_ngb=32, periodic=True, box=1.0, sigma0=1.0)
     big = sidm.make_config(n_ngb=32, periodic=True, box=1.0, sigma0=1.0, max_accept=1 << 20)
     n = 1 << 20
     a, b = sidm.footprint(base, n, n), sidm.footprint(big, n, n)
-    assert 250 * ((1 << 20) - (1 << 17)) < b - a < 330 * ((1 << 20) - (1 << 17))
+    assert 170 * ((1 << 20) - (1 << 18)) < b - a < 210 * ((1 << 20) - (1 << 18))
     out = ctypes.c_size_t()
     bad = sidm.make_config(n_ngb=32, periodic=True, box=1.0, sigma0=1.0, max_accept=-1)
     assert L.sidm_footprint(ctypes.byref(bad), 1000, 100, ctypes.byref(out)) == sidm.SIDM_E_INVAL
