@@ -341,6 +341,25 @@ sidm_status sidm_advance_hernquist(sidm_ctx *ctx, double *x, double *y, double *
                                    int64_t n_active, double dt_cap, double gm, double a,
                                    double *dt_next, double *dt_step);
 
+/* Allocation-free form of sidm_advance_hernquist, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  It needs no context: the same step
+ * (same arguments and results, bit for bit) on the current HIP device and on
+ * `hip_stream` (hipStream_t, may be NULL).  The reduction's partial minima
+ * live in a fixed device array of the library (4097 64-bit words, 32 KiB,
+ * one copy per GPU held until the process ends), so n_active is limited to
+ * 8,388,608 (SIDM_E_CAPACITY above it, before anything is enqueued; other
+ * argument errors SIDM_E_INVAL as for sidm_advance_hernquist, n <= 2^31 - 1).
+ * The call allocates nothing and clears nothing with hipMemset: every word
+ * of the array it reads it first writes.  Calls that overlap on one GPU
+ * (different streams, or host threads) share that array and race: order
+ * them on one stream.  SIDM_E_DEVICE if a launch fails. */
+sidm_status sidm_advance_hernquist_noalloc(void *hip_stream, double *x, double *y, double *z,
+                                           double *vx, double *vy, double *vz, int64_t n,
+                                           const double *dt_sidm, int64_t n_active,
+                                           double dt_cap, double gm, double a,
+                                           double *dt_next, double *dt_step);
+
 /* Free drift between scattering steps of a box without gravity (the
  * thermalisation box of sec. 5.2): x += v dt for all n particles, wrapped
  * into [0, box) when the configuration is periodic.  Caller-owned device

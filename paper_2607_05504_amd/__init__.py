@@ -95,7 +95,7 @@ TIMING_RESOLVE, TIMING_TIMESTEP, TIMING_OVERLAP, TIMING_ALL = 16, 32, 64, 127
 EXPORTS = ["sidm_footprint", "sidm_create", "sidm_destroy", "sidm_set_stream", "sidm_reconfigure",
            "sidm_last_error", "sidm_status_string", "sidm_build_tree", "sidm_find_ngb",
            "sidm_refit_tree", "sidm_tree_order", "sidm_scatter_step", "sidm_pair_timestep",
-           "sidm_advance_hernquist", "sidm_drift",
+           "sidm_advance_hernquist", "sidm_advance_hernquist_noalloc", "sidm_drift",
            "sidm_find_overlap", "sidm_scatter_overlap", "sidm_pair_timestep_overlap",
            "sidm_overlap_table",
            "sidm_sync",
@@ -130,6 +130,8 @@ def lib():
         L.sidm_pair_timestep.argtypes = [P, P, i64, P, P, P]
         d = ctypes.c_double
         L.sidm_advance_hernquist.argtypes = [P, P, P, P, P, P, P, i64, P, i64, d, d, d, P, P]
+        L.sidm_advance_hernquist_noalloc.argtypes = [P, P, P, P, P, P, P, i64, P, i64, d, d, d,
+                                                     P, P]
         L.sidm_drift.argtypes = [P, P, P, P, P, P, P, i64, d]
         L.sidm_find_overlap.argtypes = [P, P, P, P, i64, ctypes.c_int32, P, P]
         L.sidm_scatter_overlap.argtypes = [P, ctypes.POINTER(Particles), P, P, i64,
@@ -179,6 +181,28 @@ def footprint(cfg: Config, cap_n: int, cap_active: int) -> int:
     if st != SIDM_OK:
         raise SidmError(st, "sidm_footprint")
     return int(out.value)
+
+
+def advance_hernquist_noalloc(x, y, z, vx, vy, vz, dt_sidm, n_active: int, dt_cap: float,
+                              gm: float, a: float, dt_next=None, dt_step=None, stream=None):
+    """sidm_advance_hernquist_noalloc: the served form's step between two
+    scattering steps without a context and without allocating (the
+    reduction's scratch is the library's fixed device array).  Tensors are
+    contiguous float64 on the current device; stream defaults to torch's."""
+    import torch
+    for t, nm in ((x, "x"), (y, "y"), (z, "z"), (vx, "vx"), (vy, "vy"), (vz, "vz"),
+                  (dt_sidm, "dt_sidm"), (dt_next, "dt_next"), (dt_step, "dt_step")):
+        if t is not None and (not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous()):
+            raise ValueError(f"{nm}: need a contiguous float64 device tensor")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    st = lib().sidm_advance_hernquist_noalloc(
+        ctypes.c_void_p(stream.cuda_stream), _ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy),
+        _ptr(vz), int(x.shape[0]), _ptr(dt_sidm), int(n_active), float(dt_cap), float(gm),
+        float(a), _ptr(dt_next), _ptr(dt_step))
+    if st != SIDM_OK:
+        raise SidmError(st, "sidm_advance_hernquist_noalloc: " +
+                        lib().sidm_status_string(st).decode())
 
 
 def _act(active, reuse: bool):
