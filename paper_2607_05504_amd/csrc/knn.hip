@@ -40,6 +40,7 @@
 namespace {
 
 struct KnnArgs {
+    int32_t *jsort;              // the rows in sorted indices too, [target in Morton order][k]
     const double *xs, *ys, *zs;
     const uint32_t *ids;
     const int32_t *perm;
@@ -810,7 +811,12 @@ void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
     }
     if (tl == 0) A.h[a] = sqrt(T);
     int32_t *out = A.ngb + (int64_t)a * A.k;
-    for (int e = tl; e < A.k; e += TS) out[e] = A.perm[L_j[e]];
+    int32_t *srt = A.jsort + b * A.k;
+    for (int e = tl; e < A.k; e += TS) {
+        const int32_t j = L_j[e];
+        out[e] = A.perm[j];
+        srt[e] = j;
+    }
 }
 
 constexpr int kTeam = 16;                 // lanes per target in the team kernel (8 measured slower)
@@ -849,6 +855,7 @@ hipError_t launch_knn(sidm_ctx *c, int64_t n_active, int32_t *ngb, double *h)
     A.ids = c->ids; A.perm = c->perm; A.nodes = c->nodes;
     A.tlist = c->tlist; A.slot = c->slot; A.nt_dev = c->nt_dev;
     A.ngb = ngb; A.h = h; A.derr = c->derr;
+    A.jsort = c->jsort;
     A.list = c->knn_list; A.nl = c->knn_nl; A.tb = c->knn_tb;
     A.lv = c->lv;
     A.n = c->n; A.k = c->cfg.n_ngb; A.box = c->cfg.box; A.batch = 0;

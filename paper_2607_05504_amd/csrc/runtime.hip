@@ -64,13 +64,13 @@ void make_plan(sidm_ctx *c, Plan &P)
     }
     c->knn_batch = NA < SIDM_KNN_BATCH ? NA : SIDM_KNN_BATCH;
     ADD(knn_list, c->knn_batch * SIDM_KNN_LMAX, int32_t);
+    ADD(jsort, NA * (int64_t)k, int32_t);
     ADD(knn_nl, c->knn_batch, int32_t);
     ADD(knn_tb, c->knn_batch, double);
     ADD(flag, N, int32_t);
-    ADD(tlist, NA, int32_t); ADD(slot, NA, int32_t); ADD(tsort, NA, int32_t);
+    ADD(tlist, NA, int32_t); ADD(slot, NA, int32_t);
     ADD(blk, (N + SIDM_SCAN_TILE - 1) / SIDM_SCAN_TILE + 1, int32_t);
     ADD(nt_dev, 1, int32_t);
-    (void)k;
     const int64_t CA = acc_capacity(c->cfg, NA);
     // each listed candidate holds at most one record pair (the records of a
     // rewound turn are freed), so two records per listed candidate suffice
@@ -275,6 +275,8 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
         *P.items[t].dst = base + off;
         off += P.items[t].bytes;
     }
+    c->jsort_ngb = nullptr;
+    c->jsort_knn = 0;
     if (hipHostMalloc((void **)&c->hstats, sizeof(DevStats) + 64, hipHostMallocDefault) != hipSuccess) {
         (void)hipFree(base);
         free(c);
@@ -397,6 +399,8 @@ sidm_status sidm_reconfigure(sidm_ctx *c, const sidm_config *cfg)
     normalize_units(c->cfg);
     c->tree_ok = 0;          // a new configuration needs a new snapshot
     c->map_valid = 0;
+    c->jsort_ngb = nullptr;
+    c->jsort_knn = 0;
     c->hs_valid = 0;
     hipError_t e = copy_table(c);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -447,6 +451,8 @@ sidm_status sidm_refit_tree(sidm_ctx *c, const sidm_particles *p)
     c->n = p->n;
     c->has_mass = p->mass != nullptr;
     c->m_scalar = p->m_scalar;
+    c->jsort_ngb = nullptr;
+    c->jsort_knn = 0;
     phase_begin(c, PH_TREE);
     hipError_t e = launch_refit_tree(c, p);
     phase_end(c, PH_TREE);
@@ -465,6 +471,8 @@ sidm_status sidm_build_tree(sidm_ctx *c, const sidm_particles *p)
     c->n = p->n;
     c->has_mass = p->mass != nullptr;
     c->m_scalar = p->m_scalar;
+    c->jsort_ngb = nullptr;
+    c->jsort_knn = 0;
     phase_begin(c, PH_TREE);
     hipError_t e = launch_build_tree(c, p);
     phase_end(c, PH_TREE);
@@ -527,6 +535,8 @@ static hipError_t map_active(sidm_ctx *c, const int32_t *active, int64_t n_activ
 {
     if (!active && n_active > 0) return hipSuccess;
     c->map_valid = 0;
+    c->jsort_ngb = nullptr;
+    c->jsort_knn = 0;
     hipError_t e = launch_map_active(c, active, n_active);
     if (e == hipSuccess) {
         c->map_valid = 1;
@@ -547,6 +557,9 @@ sidm_status sidm_find_ngb(sidm_ctx *c, const int32_t *active, int64_t n_active, 
     if (n_active == 0) return SIDM_OK;
     hipError_t e = map_active(c, active, n_active);
     if (e == hipSuccess) e = launch_knn(c, n_active, ngb, h);
+    // jsort now holds these rows in sorted indices, for this mapping
+    c->jsort_ngb = nullptr;
+    c->jsort_knn = e == hipSuccess && c->cfg.estimator == SIDM_EST_ONE_SIDED;
     if (e != hipSuccess) return hip_fail(c, e, "find_ngb");
     return SIDM_OK;
 }

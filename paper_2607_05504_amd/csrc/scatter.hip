@@ -73,7 +73,7 @@ struct StepArgs {
     unsigned long long *tmin;
     uint32_t *dbits;
     int32_t *flist;
-    const int32_t *tsort;
+    int32_t *jsort;          // the step's rows in Morton order (sorted indices), or NULL
     int32_t *ctl;
     unsigned long long *c1a, *c1b, *c2a, *c2b;
     DevStats *st;
@@ -111,6 +111,16 @@ __device__ __forceinline__ double sigma_of(const StepArgs &A, double w)
 __device__ __forceinline__ double mass_of(const StepArgs &A, int32_t s)
 {
     return A.has_mass ? A.ms[s] : A.m_scalar;
+}
+
+// Sorted index of the partner of candidate c = b * stride + s (target b in
+// Morton order, caller row a, ci = a * stride + s): from the step's sorted
+// rows when it has them, else through inv (-1 for an index out of range).
+__device__ __forceinline__ int32_t partner(const StepArgs &A, int64_t c, int64_t ci)
+{
+    if (A.jsort) return A.jsort[c];
+    const int32_t jc = A.ngb[ci];
+    return (jc >= 0 && jc < A.n) ? A.inv[jc] : -1;
 }
 
 __device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
@@ -268,7 +278,7 @@ __device__ void flush_staged(const StepArgs &A, StagedAcc &S, int n, int32_t &ba
         const int s = (int)(c - b * A.stride);
         const int32_t a = A.slot[b], i = A.tlist[b];
         const int64_t ci = (int64_t)a * A.stride + s;
-        const int32_t j = A.inv[A.ngb[ci]];    // checked in range when it was evaluated
+        const int32_t j = partner(A, c, ci);   // checked in range when it was evaluated
         const uint32_t idi = A.ids[i], idj = A.ids[j];
         const Philox4 xp = pair_draw(A.seed, A.step, idi, idj, PURPOSE_PRIORITY);
         A.M.i[pos] = i; A.M.j[pos] = j; A.M.cand[pos] = (int32_t)ci;
@@ -337,12 +347,11 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
         if (live) {
             const int32_t i = A.tlist[b];
             const int64_t ci = (int64_t)a * A.stride + s;
-            const int32_t jc = A.ngb[ci];
+            const int32_t j = partner(A, c, ci);
             n_cd += 1;
-            if (jc < 0 || jc >= A.n) {
-                atomicOr(A.derr, DERR_INDEX);
+            if (j < 0) {
+                if (!A.jsort) atomicOr(A.derr, DERR_INDEX);   // else latched by k_rows
             } else {
-                const int32_t j = A.inv[jc];
                 const double dta = A.dt[a];
                 const uint32_t idi = A.ids[i], idj = A.ids[j];
                 const Philox4 x = pair_draw(A.seed, A.step, idi, idj, PURPOSE_DECIDE);
@@ -667,21 +676,18 @@ __device__ void wg_passes(const StepArgs &A, int t0, int64_t cnt0, PassShared &S
 }
 
 // D, the particles whose history changed since the last check, is marked by
-// tmin != ~0 (sorted index) and by a bit per caller index, which the check's
-// scan tests against the rows' caller indices without a gather.
+// tmin != ~0 and by a bit per sorted index, which the check's scan tests.
 __device__ __forceinline__ void set_dbit(const StepArgs &A, int32_t p)
 {
-    const int32_t c = A.perm[p];
-    atomicOr(&A.dbits[c >> 5], 1u << (c & 31));
+    atomicOr(&A.dbits[p >> 5], 1u << (p & 31));
 }
 __device__ __forceinline__ void clear_dbit(const StepArgs &A, int32_t p)
 {
-    const int32_t c = A.perm[p];
-    atomicAnd(&A.dbits[c >> 5], ~(1u << (c & 31)));
+    atomicAnd(&A.dbits[p >> 5], ~(1u << (p & 31)));
 }
-__device__ __forceinline__ bool dbit(const StepArgs &A, int32_t c)
+__device__ __forceinline__ bool dbit(const StepArgs &A, int32_t p)
 {
-    return (A.dbits[c >> 5] >> (c & 31)) & 1u;
+    return (A.dbits[p >> 5] >> (p & 31)) & 1u;
 }
 
 // Round 1: one workgroup finishes whatever passes the grid left, then sets
@@ -757,12 +763,8 @@ struct TurnEval {
 };
 
 template <bool PERIODIC, bool OVERLAP>
-__device__ bool eval_turn(const StepArgs &A, int32_t i, int32_t a, int s, TurnEval &T)
+__device__ void eval_turn(const StepArgs &A, int32_t i, int32_t a, int32_t j, TurnEval &T)
 {
-    const int64_t ci = (int64_t)a * A.stride + s;
-    const int32_t jc = A.ngb[ci];
-    if (jc < 0 || jc >= A.n) return false;    // latched by the evaluation
-    const int32_t j = A.inv[jc];
     const uint32_t idi = A.ids[i], idj = A.ids[j];
     T.j = j;
     T.kp = direction_word(pair_draw(A.seed, A.step, idi, idj, PURPOSE_PRIORITY), idi < idj);
@@ -783,14 +785,13 @@ __device__ bool eval_turn(const StepArgs &A, int32_t i, int32_t a, int s, TurnEv
     T.Pt = allowed ? pair_prob(mj, sigma_of(A, wt), wt, T.W, dta) : 0.0;
     const double ws = A.vphys * rel_speed(six, siy, siz, sjx, sjy, sjz);
     T.Ps = allowed ? pair_prob(mj, sigma_of(A, ws), ws, T.W, dta) : 0.0;
-    return true;
 }
 
 template <bool PERIODIC, bool OVERLAP>
-__device__ void check_candidate(const StepArgs &A, int32_t i, int32_t a, int s)
+__device__ void check_candidate(const StepArgs &A, int32_t i, int32_t a, int s, int32_t j)
 {
     TurnEval T;
-    if (!eval_turn<PERIODIC, OVERLAP>(A, i, a, s, T)) return;
+    eval_turn<PERIODIC, OVERLAP>(A, i, a, j, T);
     const int64_t ci = (int64_t)a * A.stride + s;
     const bool listed = T.ri >= 0 && A.R.prio[T.ri] == T.kp && A.R.idpair[T.ri] == T.ki;
     const bool kicked = listed && (A.R.info[T.ri] & 1u);
@@ -819,21 +820,22 @@ __device__ void check_candidate(const StepArgs &A, int32_t i, int32_t a, int s)
 }
 
 // The check's scan: every candidate whose target or partner is in D, each
-// once.  Rows in the caller's order (coalesced), D tested on the partners'
-// caller indices in the bitmap; first..total strided by the threads given.
+// once; rows in Morton order (spatially close targets, so that the D bits of
+// their partners share cache lines), first..total strided by the threads given.
 template <bool PERIODIC, bool OVERLAP>
 __device__ void check_scan(const StepArgs &A, int64_t first, int64_t nthreads)
 {
     const int64_t nt = *A.nt_dev;
     const int64_t total = nt * A.stride;
     for (int64_t c = first; c < total; c += nthreads) {
-        const int64_t a = total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)A.stride) : c / A.stride;
-        const int s = (int)(c - a * A.stride);
+        const int64_t b = total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)A.stride) : c / A.stride;
+        const int s = (int)(c - b * A.stride);
+        const int32_t a = A.slot[b];
         if (OVERLAP && s >= A.cnt[a]) continue;
-        const int32_t jc = A.ngb[c];
-        const int32_t i = A.tsort[a];
-        const bool hit = (jc >= 0 && jc < A.n && dbit(A, jc)) || dbit(A, A.perm[i]);
-        if (hit) check_candidate<PERIODIC, OVERLAP>(A, i, (int32_t)a, s);
+        const int32_t j = partner(A, c, (int64_t)a * A.stride + s);
+        if (j < 0) continue;
+        const int32_t i = A.tlist[b];
+        if (dbit(A, j) || dbit(A, i)) check_candidate<PERIODIC, OVERLAP>(A, i, a, s, j);
     }
 }
 
@@ -1046,8 +1048,10 @@ __global__ __launch_bounds__(1024) void k_final_stats(StepArgs A)
         for (int g = 0; g < f && first; ++g) first = A.flist[2 * g + 1] != ci;
         if (!first) continue;
         const int32_t a = (int32_t)(ci / A.stride);
+        const int32_t jc = A.ngb[ci];
+        if (jc < 0 || jc >= A.n) continue;
         TurnEval T;
-        if (!eval_turn<PERIODIC, OVERLAP>(A, i, a, (int)(ci - (int64_t)a * A.stride), T)) continue;
+        eval_turn<PERIODIC, OVERLAP>(A, i, a, A.inv[jc], T);
         df += (long long)(fabs(T.Pt - T.u) < A.band) - (long long)(fabs(T.Ps - T.u) < A.band);
     }
     if (ev) atomicAdd(&s_ev, ev);
@@ -1096,10 +1100,9 @@ __global__ void k_step_reset(DevStats *st, int32_t *ctl, const int32_t *nt_dev, 
 // when n_ngb is a power of two up to 64; one thread per target otherwise.
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ double pair_rate(const StepArgs &A, double vix, double viy, double viz,
-                                            int32_t jc)
+                                            int32_t j)
 {
-    if (jc < 0 || jc >= A.n) { atomicOr(A.derr, DERR_INDEX); return 0.0; }
-    const int32_t j = A.inv[jc];
+    if (j < 0) { atomicOr(A.derr, DERR_INDEX); return 0.0; }
     const double w = A.vphys * rel_speed(vix, viy, viz, A.vxs[j], A.vys[j], A.vzs[j]);
     return w * sigma_of(A, w);
 }
@@ -1126,7 +1129,7 @@ __global__ __launch_bounds__(kBlock) void k_timestep_group(StepArgs A, double c_
         if (in) {
             i = A.tlist[b];
             a = A.slot[b];
-            rate = pair_rate(A, A.vxs[i], A.vys[i], A.vzs[i], A.ngb[(int64_t)a * A.k + s]);
+            rate = pair_rate(A, A.vxs[i], A.vys[i], A.vzs[i], partner(A, c, (int64_t)a * A.k + s));
         }
         for (int off = 1; off < A.k; off <<= 1) {
             const double o = __shfl_xor(rate, off);
@@ -1145,7 +1148,8 @@ __global__ __launch_bounds__(kBlock) void k_timestep(StepArgs A, double c_sidm, 
         const double vix = A.vxs[i], viy = A.vys[i], viz = A.vzs[i];
         double rmax = 0.0;
         for (int s = 0; s < A.k; ++s) {
-            const double r = pair_rate(A, vix, viy, viz, A.ngb[(int64_t)a * A.k + s]);
+            const double r = pair_rate(A, vix, viy, viz,
+                                       partner(A, b * A.k + s, (int64_t)a * A.k + s));
             rmax = r > rmax ? r : rmax;
         }
         dt_out[a] = dt_from_rate(A, i, A.h[a], rmax, c_sidm);
@@ -1204,7 +1208,7 @@ StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const dou
     A.M = c->mem;
     A.wl0 = c->wl[0]; A.wl1 = c->wl[1]; A.mmark = c->mmark; A.plist = c->plist; A.head = c->head;
     A.R = c->trec; A.tmin = c->tmin; A.cap_rec = c->cap_rec;
-    A.rfree = c->rfree; A.dbits = c->dbits; A.flist = c->flist; A.tsort = c->tsort;
+    A.rfree = c->rfree; A.dbits = c->dbits; A.flist = c->flist; A.jsort = nullptr;
     A.ctl = c->acc_count;
     A.c1a = c->claim1[0]; A.c1b = c->claim1[1]; A.c2a = c->claim2[0]; A.c2b = c->claim2[1];
     A.st = c->dstats; A.derr = c->derr;
@@ -1227,6 +1231,29 @@ int grid_for(int64_t n, int cap = 8192)
     int64_t g = (n + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
     return (int)(g > cap ? cap : g);
+}
+
+// The step's rows in the tree's order: jsort[b * k + s] = sorted index of
+// ngb[slot[b] * k + s] (-1, latched, for an index out of range).  When
+// jsort holds the neighbour search's rows for this mapping (have = 1) an
+// entry is only checked, perm[jsort] == ngb (partners of nearby targets lie
+// close in the tree's order, so the gather stays in cache), and translated
+// through inv where it differs; else every entry is translated.
+__global__ __launch_bounds__(kBlock) void k_rows(StepArgs A, int have)
+{
+    const int64_t total = (int64_t)(*A.nt_dev) * A.stride;
+    for (int64_t c = blockIdx.x * (int64_t)kBlock + threadIdx.x; c < total;
+         c += (int64_t)gridDim.x * kBlock) {
+        const int64_t b = total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)A.stride) : c / A.stride;
+        const int s = (int)(c - b * A.stride);
+        const int32_t jc = A.ngb[(int64_t)A.slot[b] * A.stride + s];
+        int32_t j = have ? A.jsort[c] : -1;
+        if (j >= 0 && j < A.n && A.perm[j] == jc) continue;
+        j = -1;
+        if (jc >= 0 && jc < A.n) j = A.inv[jc];
+        else atomicOr(A.derr, DERR_INDEX);
+        A.jsort[c] = j;
+    }
 }
 
 template <bool P, bool M, bool O = false>
@@ -1277,6 +1304,11 @@ hipError_t launch_scatter(sidm_ctx *c, sidm_particles *p, int64_t n_active, cons
                           uint32_t *cand_info)
 {
     StepArgs A = make_args(c, p, ngb, h, dt, seed, step, cand_info);
+    A.jsort = c->jsort;
+    const int have = c->jsort_knn || c->jsort_ngb == ngb;
+    k_rows<<<grid_for(n_active * A.stride, 8192), kBlock, 0, c->stream>>>(A, have);
+    c->jsort_ngb = ngb;
+    c->jsort_knn = 0;
     const bool mixed = c->cfg.precision == SIDM_MIXED;
     if (c->cfg.periodic) {
         mixed ? run_scatter<true, true>(c, A, n_active, c->stream)
@@ -1292,6 +1324,8 @@ hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, co
                            double *dt_out)
 {
     StepArgs A = make_args(c, nullptr, ngb, h, nullptr, 0, 0, nullptr);
+    // the rows the scattering step made from the same ngb, if nothing ran since
+    if (ngb && c->jsort_ngb == ngb) A.jsort = c->jsort;
     phase_begin(c, PH_TIMESTEP);
     const int k = A.k;
     if (k <= 64 && (k & (k - 1)) == 0)

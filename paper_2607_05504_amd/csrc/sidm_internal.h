@@ -15,7 +15,7 @@
 #define SIDM_TIMING_RING 256    // timed launches per phase between two reads
 #define SIDM_PHASES 7           // timed phases (PH_* below)
 #define SIDM_KNN_LMAX 96        // leaves per target list (longer lists walk the tree instead)
-#define SIDM_KNN_BATCH (1 << 20)  // targets per neighbour-search batch
+#define SIDM_KNN_BATCH (1 << 22)  // targets per neighbour-search batch
 
 // device-side error bits (latched, reported by sidm_sync)
 #define DERR_INDEX 1u           // an index outside [0, n)
@@ -133,6 +133,14 @@ struct sidm_ctx {
     // neighbour search: per-target leaf lists, processed in batches of knn_batch
     int64_t knn_batch;
     int32_t *knn_list;       // [knn_batch][SIDM_KNN_LMAX]
+    // the rows in the tree's order: jsort[b * n_ngb + s] = sorted index of
+    // neighbour s of the b-th target in Morton order (-1 for an index out of
+    // range).  sidm_find_ngb writes them beside ngb; sidm_scatter_step checks
+    // them against its ngb (translating any entry that differs), and
+    // sidm_pair_timestep reads them given the same ngb while nothing else ran
+    int32_t *jsort;          // [cap_active * n_ngb]
+    const int32_t *jsort_ngb;     // the ngb they match, NULL if none
+    int jsort_knn;           // they are the last sidm_find_ngb's, for the current mapping
     int32_t *knn_nl;         // [knn_batch]
     double *knn_tb;          // [knn_batch]
 
@@ -140,7 +148,6 @@ struct sidm_ctx {
     int32_t *flag;           // [cap_n] caller slot of an active particle, or -1
     int32_t *tlist;          // [cap_active] sorted index of the b-th active particle
     int32_t *slot;           // [cap_active] its position in the caller's active list
-    int32_t *tsort;          // [cap_active] sorted index of the particle in caller slot a
     int32_t *blk;            // compaction block counts / offsets
     int32_t *nt_dev;         // number of compacted targets
     int map_valid;           // the arrays above hold the mapping of map_n targets
@@ -155,7 +162,7 @@ struct sidm_ctx {
     int32_t *rfree;          // [cap_rec / 2] record pairs a rewind freed
     int32_t *head;           // [cap_n] latest turn record of each particle, -1 if none
     unsigned long long *tmin;     // [cap_n] smallest priority a re-round replays, ~0 if none
-    uint32_t *dbits;         // [cap_n / 32] bit per caller index: the particle is in D
+    uint32_t *dbits;         // [cap_n / 32] bit per sorted index: the particle is in D
     int32_t *flist;          // [2 SIDM_FLAG_CAP] (target, candidate slot) once flagged
     int32_t *acc_count;      // [16] control words (list counts, passes, rounds)
     unsigned long long *claim1[2], *claim2[2];   // [cap_n] per-particle claims

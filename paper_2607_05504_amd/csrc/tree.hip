@@ -498,7 +498,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int32_t *blk, int nblk, in
 
 __global__ __launch_bounds__(256) void k_compact_active(const int32_t *__restrict__ flag, int64_t n,
                                                         const int32_t *__restrict__ blk,
-                                                        int32_t *tlist, int32_t *slot, int32_t *tsort)
+                                                        int32_t *tlist, int32_t *slot)
 {
     __shared__ int32_t wsum[4];
     __shared__ int32_t run_s;
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(256) void k_compact_active(const int32_t *__restric
         __syncthreads();
         int32_t pos = run_s + __popcll(m & lt_mask);
         for (int q = 0; q < w; ++q) pos += wsum[q];
-        if (on) { tlist[pos] = (int32_t)s; slot[pos] = f; tsort[f] = (int32_t)s; }
+        if (on) { tlist[pos] = (int32_t)s; slot[pos] = f; }
         __syncthreads();
         if (t == 0) run_s += wsum[0] + wsum[1] + wsum[2] + wsum[3];
         __syncthreads();
@@ -627,7 +627,7 @@ hipError_t launch_map_active(sidm_ctx *c, const int32_t *active, int64_t n_activ
     const int nblk = (int)((n + SIDM_SCAN_TILE - 1) / SIDM_SCAN_TILE);
     k_count_active<<<nblk, 256, 0, s>>>(c->flag, n, c->blk);
     k_scan_blocks<<<1, 1024, 0, s>>>(c->blk, nblk, c->nt_dev);
-    k_compact_active<<<nblk, 256, 0, s>>>(c->flag, n, c->blk, c->tlist, c->slot, c->tsort);
+    k_compact_active<<<nblk, 256, 0, s>>>(c->flag, n, c->blk, c->tlist, c->slot);
     phase_end(c, PH_MAP);
     return hipGetLastError();
 }
