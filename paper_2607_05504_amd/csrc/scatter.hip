@@ -821,30 +821,77 @@ __device__ void check_candidate(const StepArgs &A, int32_t i, int32_t a, int s, 
 
 // The check's scan: every candidate whose target or partner is in D, each
 // once; rows in Morton order (spatially close targets, so that the D bits of
-// their partners share cache lines), first..total strided by the threads given.
+// their partners share cache lines).  The whole workgroup calls it: each
+// round of the loop scans blockDim candidates and queues the hits in LDS;
+// whenever blockDim hits are queued they are evaluated with every thread
+// busy (in the first round about one candidate in a hundred hits on the
+// 256^3 box: evaluated where found, most lanes of a wavefront would wait).
+constexpr int kScanU = 8;          // candidates a thread scans per round of the loop
+
 template <bool PERIODIC, bool OVERLAP>
-__device__ void check_scan(const StepArgs &A, int64_t first, int64_t nthreads)
+__device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk_stride,
+                           int32_t *q, int &qn)
 {
+    const int nth = blockDim.x, tid = threadIdx.x;
     const int64_t nt = *A.nt_dev;
     const int64_t total = nt * A.stride;
-    for (int64_t c = first; c < total; c += nthreads) {
-        const int64_t b = total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)A.stride) : c / A.stride;
+    auto evaluate = [&](int64_t c) {
+        const int64_t b = c / A.stride;
         const int s = (int)(c - b * A.stride);
         const int32_t a = A.slot[b];
-        if (OVERLAP && s >= A.cnt[a]) continue;
         const int32_t j = partner(A, c, (int64_t)a * A.stride + s);
-        if (j < 0) continue;
-        const int32_t i = A.tlist[b];
-        if (dbit(A, j) || dbit(A, i)) check_candidate<PERIODIC, OVERLAP>(A, i, a, s, j);
+        check_candidate<PERIODIC, OVERLAP>(A, A.tlist[b], a, s, j);
+    };
+    if (tid == 0) qn = 0;
+    __syncthreads();
+    // chunks of nth * kScanU candidates; a thread takes kScanU of a chunk,
+    // nth apart, with their loads independent of each other
+    for (int64_t c0 = first_chunk; c0 < total; c0 += chunk_stride) {
+        int64_t cc[kScanU];
+        int32_t jj[kScanU], ii[kScanU];
+#pragma unroll
+        for (int u = 0; u < kScanU; ++u) {
+            const int64_t c = c0 + u * nth + tid;
+            cc[u] = c;
+            jj[u] = -1;
+            ii[u] = 0;
+            if (c < total) {
+                const int64_t b = total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)A.stride)
+                                                     : c / A.stride;
+                const int s = (int)(c - b * A.stride);
+                const int32_t a = A.slot[b];
+                if (!OVERLAP || s < A.cnt[a]) {
+                    jj[u] = partner(A, c, (int64_t)a * A.stride + s);
+                    ii[u] = A.tlist[b];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kScanU; ++u)
+            if (jj[u] >= 0 && (dbit(A, jj[u]) || dbit(A, ii[u]))) q[atomicAdd(&qn, 1)] = (int32_t)cc[u];
+        __syncthreads();
+        int n_q = qn;
+        while (n_q >= nth) {
+            evaluate(q[n_q - nth + tid]);
+            n_q -= nth;
+        }
+        __syncthreads();
+        if (tid == 0) qn = n_q;
+        __syncthreads();
     }
+    const int n_q = qn;
+    if (tid < n_q) evaluate(q[tid]);
+    __syncthreads();
 }
 
 template <bool PERIODIC, bool OVERLAP>
 __global__ __launch_bounds__(kBlock) void k_check(StepArgs A)
 {
+    __shared__ int32_t q[(kScanU + 1) * kBlock];
+    __shared__ int qn;
     if (A.ctl[CTL_DONE]) return;
-    check_scan<PERIODIC, OVERLAP>(A, blockIdx.x * (int64_t)kBlock + threadIdx.x,
-                                  (int64_t)gridDim.x * kBlock);
+    check_scan<PERIODIC, OVERLAP>(A, blockIdx.x * (int64_t)kBlock * kScanU,
+                                  (int64_t)gridDim.x * kBlock * kScanU, q, qn);
 }
 
 // ----------------------------------------------------------------------------
@@ -997,6 +1044,8 @@ __global__ __launch_bounds__(1024) void k_tail(StepArgs A)
 {
     __shared__ RoundShared S;
     __shared__ int s_done;
+    __shared__ int32_t tq[(kScanU + 1) * 1024];
+    __shared__ int tqn;
     for (int round = 0;; ++round) {
         if (threadIdx.x == 0) {
             s_done = load_i32(&A.ctl[CTL_DONE]);
@@ -1007,7 +1056,7 @@ __global__ __launch_bounds__(1024) void k_tail(StepArgs A)
         }
         __syncthreads();
         if (s_done) break;
-        check_scan<PERIODIC, OVERLAP>(A, threadIdx.x, blockDim.x);
+        check_scan<PERIODIC, OVERLAP>(A, 0, (int64_t)blockDim.x * kScanU, tq, tqn);
         wg_sync();
         reround_body(A, S);
         wg_sync();
@@ -1285,7 +1334,7 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
     // rounds after that return at once)
     int64_t dmax = 2 * (A.cap_acc < total ? A.cap_acc : total);
     dmax = dmax < A.n ? dmax : A.n;
-    const int gcheck = grid_for(total, 8192);
+    const int gcheck = grid_for((total + kScanU - 1) / kScanU, 8192);
     for (int r = 0; r < c->dev_rounds; ++r) {
         k_check<P, O><<<gcheck, kBlock, 0, s>>>(A);
         k_reround<<<1, 1024, 0, s>>>(A);
