@@ -20,7 +20,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sidm_oracle.c")
 _LIB = os.path.join(_HERE, "libsidm_oracle.so")
+# the same source built with -fopenmp: the CPU throughput baseline on all
+# cores (identical results; the turns of a step stay serial)
+_LIB_OMP = os.path.join(_HERE, "libsidm_oracle_omp.so")
 _lib = None
+_which = _LIB
 
 XSEC_TABLE = 2
 CAND_ACCEPT0 = 1
@@ -29,13 +33,31 @@ CAND_FLAGGED = 4
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle: no FMA contraction, no fast-math."""
-    if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
+    """Compile the oracle: no FMA contraction, no fast-math; and its OpenMP
+    build."""
+    for out, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out):
+            cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", *extra,
+                   "-fPIC", "-shared", "-o", out + ".tmp", _SRC, "-lm"]
+            subprocess.check_call(cmd)
+            os.replace(out + ".tmp", out)
     return _LIB
+
+
+def use_openmp(threads: int = 0) -> int:
+    """Switch to the OpenMP build (threads > 0 sets its thread count, else
+    all cores); returns the threads it will use."""
+    global _lib, _which
+    if _which != _LIB_OMP:
+        _lib, _which = None, _LIB_OMP
+    return int(lib().oref_threads(int(threads)))
+
+
+def use_serial() -> None:
+    """Back to the single-threaded build (the default)."""
+    global _lib, _which
+    if _which != _LIB:
+        _lib, _which = None, _LIB
 
 
 class _Stats(ctypes.Structure):
@@ -48,12 +70,14 @@ class _Stats(ctypes.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_which) or os.path.getmtime(_which) < os.path.getmtime(_SRC):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(_which)
         P = ctypes.c_void_p
         i64, i32, u32, u64, dbl = (ctypes.c_int64, ctypes.c_int, ctypes.c_uint32,
                                    ctypes.c_uint64, ctypes.c_double)
+        L.oref_threads.argtypes = [i32]
+        L.oref_threads.restype = i32
         L.oref_philox4x32_10.argtypes = [P, P, P]
         L.oref_philox4x32_10.restype = None
         L.oref_uniform_decision.argtypes = [u64, u32, u32, u32]
@@ -164,17 +188,22 @@ def r2(pi, pj, periodic: bool, box: float) -> float:
 
 
 # ---------------------------------------------------------------------------
-def candidate_superset(x, y, z, periodic, box, targets, k, workers=-1):
-    """CSR superset of every target's partners with r <= r_(k+1), from scipy's
-    k-d tree: the (k+2)-th closest point including the target itself bounds
-    r_(k+1); the ball query radius is padded far beyond rounding differences."""
+def kd_tree(x, y, z, periodic, box):
+    """scipy's k-d tree over all particles (the candidate gathering below)."""
     from scipy.spatial import cKDTree
     pts = np.stack([x, y, z], axis=1)
     if periodic:
         pts = np.where(pts >= box, pts - box, pts)
-        kd = cKDTree(pts, boxsize=box)
-    else:
-        kd = cKDTree(pts)
+        return cKDTree(pts, boxsize=box), pts
+    return cKDTree(pts), pts
+
+
+def candidate_superset(x, y, z, periodic, box, targets, k, workers=-1, kd=None):
+    """CSR superset of every target's partners with r <= r_(k+1), from scipy's
+    k-d tree: the (k+2)-th closest point including the target itself bounds
+    r_(k+1); the ball query radius is padded far beyond rounding differences.
+    kd: a tree from kd_tree() of the same particles, else one is built."""
+    kd, pts = kd if kd is not None else kd_tree(x, y, z, periodic, box)
     q = pts[targets]
     d, _ = kd.query(q, k=k + 2, workers=workers)
     rad = d[:, k + 1] * (1.0 + 1e-9) + 1e-300
@@ -186,7 +215,7 @@ def candidate_superset(x, y, z, periodic, box, targets, k, workers=-1):
     return ptr, idx
 
 
-def find_ngb(w, targets=None, brute: Optional[bool] = None, workers: int = -1):
+def find_ngb(w, targets=None, brute: Optional[bool] = None, workers: int = -1, kd=None):
     """Neighbour lists and smoothing lengths of ``targets`` (default: w.active).
 
     Returns (ngb int32[n_t, k], h float64[n_t])."""
@@ -199,7 +228,7 @@ def find_ngb(w, targets=None, brute: Optional[bool] = None, workers: int = -1):
         brute = w.n <= 4096
     ptr = idx = None
     if not brute:
-        ptr, idx = candidate_superset(x, y, z, w.periodic, w.box, tg, k, workers)
+        ptr, idx = candidate_superset(x, y, z, w.periodic, w.box, tg, k, workers, kd=kd)
     ngb = np.zeros((tg.size, k), dtype=np.int32)
     h = np.zeros(tg.size, dtype=np.float64)
     rc = L.oref_find_ngb(w.n, _p(x), _p(y), _p(z), _p(ids), int(w.periodic), float(w.box),
@@ -264,9 +293,10 @@ def kick_pair(i, j, vx, vy, vz, state, ids, mass, model, eps, delta, seed, step)
                          int(seed), int(step))
 
 
-def full_step(w, brute: Optional[bool] = None, band: float = 1e-9, workers: int = -1):
-    """Neighbours, scatter step and per-pair timestep of workload w."""
-    ngb, h = find_ngb(w, brute=brute, workers=workers)
+def full_step(w, brute: Optional[bool] = None, band: float = 1e-9, workers: int = -1, kd=None):
+    """Neighbours, scatter step and per-pair timestep of workload w (kd: a
+    prebuilt kd_tree of its particles)."""
+    ngb, h = find_ngb(w, brute=brute, workers=workers, kd=kd)
     vx, vy, vz, st, info, stats = scatter_step(w, ngb, h, band=band)
     dt = pair_timestep(w, ngb, h, vx, vy, vz)
     return dict(ngb=ngb, h=h, vx=vx, vy=vy, vz=vz, state=st, info=info, stats=stats,

@@ -49,11 +49,19 @@
  *                   r_ij < h_i + h_j, and g_ij is the overlap integral of the
  *                   two splines, read from a table of the dimensionless
  *                   overlap ghat(h_i/(h_i+h_j), r_ij/(h_i+h_j))
+ *
+ * Built with -fopenmp as well (a second library, the CPU throughput
+ * baseline): the loops over targets of the neighbour ranking, of the
+ * step-start evaluation and of the timestep then run on all cores; the turns
+ * stay one after another, so the results are the same bit for bit.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OREF_PI 3.14159265358979323846
 #define OREF_OK 0
@@ -281,30 +289,59 @@ int oref_find_ngb(int64_t n, const double *x, const double *y, const double *z,
                   int32_t *ngb, double *h)
 {
     if (k < 1 || n < k + 2) return OREF_E_INVAL;
-    int64_t cap = n;
-    cand_t *buf = (cand_t *)malloc((size_t)cap * sizeof(cand_t));
-    if (!buf) return OREF_E_NOMEM;
-    int rc = OREF_OK;
-    for (int64_t t = 0; t < n_t; ++t) {
-        int32_t i = targets[t];
-        int64_t m = 0;
-        int64_t lo = cand_ptr ? cand_ptr[t] : 0;
-        int64_t hi = cand_ptr ? cand_ptr[t + 1] : n;
-        for (int64_t c = lo; c < hi; ++c) {
-            int32_t j = cand_ptr ? cand_idx[c] : (int32_t)c;
-            if (j == i) continue;
-            buf[m].r2 = oref_r2(x[i], y[i], z[i], x[j], y[j], z[j], periodic, box);
-            buf[m].id = id[j];
-            buf[m].j = j;
-            ++m;
-        }
-        if (m < k + 1) { rc = OREF_E_INVAL; break; }
-        qsort(buf, (size_t)m, sizeof(cand_t), cand_cmp);
-        for (int s = 0; s < k; ++s) ngb[t * k + s] = buf[s].j;
-        h[t] = sqrt(buf[k].r2);
+    int64_t cap = n;             /* longest candidate row */
+    if (cand_ptr) {
+        cap = 1;
+        for (int64_t t = 0; t < n_t; ++t)
+            if (cand_ptr[t + 1] - cand_ptr[t] > cap) cap = cand_ptr[t + 1] - cand_ptr[t];
     }
-    free(buf);
+    int rc = OREF_OK;
+#pragma omp parallel
+    {
+        cand_t *buf = (cand_t *)malloc((size_t)cap * sizeof(cand_t));
+        if (!buf) {
+#pragma omp atomic write
+            rc = OREF_E_NOMEM;
+        }
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t t = 0; t < n_t; ++t) {
+            if (!buf) continue;
+            int32_t i = targets[t];
+            int64_t m = 0;
+            int64_t lo = cand_ptr ? cand_ptr[t] : 0;
+            int64_t hi = cand_ptr ? cand_ptr[t + 1] : n;
+            for (int64_t c = lo; c < hi; ++c) {
+                int32_t j = cand_ptr ? cand_idx[c] : (int32_t)c;
+                if (j == i) continue;
+                buf[m].r2 = oref_r2(x[i], y[i], z[i], x[j], y[j], z[j], periodic, box);
+                buf[m].id = id[j];
+                buf[m].j = j;
+                ++m;
+            }
+            if (m < k + 1) {
+#pragma omp atomic write
+                rc = OREF_E_INVAL;
+                continue;
+            }
+            qsort(buf, (size_t)m, sizeof(cand_t), cand_cmp);
+            for (int s = 0; s < k; ++s) ngb[t * k + s] = buf[s].j;
+            h[t] = sqrt(buf[k].r2);
+        }
+        free(buf);
+    }
     return rc;
+}
+
+/* threads of the OpenMP build (want > 0 sets them); 1 for the plain build */
+int oref_threads(int want)
+{
+#ifdef _OPENMP
+    if (want > 0) omp_set_num_threads(want);
+    return omp_get_max_threads();
+#else
+    (void)want;
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------------ */
@@ -493,45 +530,54 @@ static int scatter_core(int64_t n, const double *x, const double *y, const doubl
     oref_stats st; memset(&st, 0, sizeof st);
     if (cand_info) memset(cand_info, 0, (size_t)(n_active * (int64_t)stride) * sizeof(uint32_t));
 
-    int64_t n_cand = 0;
+    /* row a's candidates start at row_off[a] in the ordering array */
+    int64_t *row_off = (int64_t *)malloc((size_t)(n_active + 1) * sizeof(int64_t));
+    if (!row_off) return OREF_E_NOMEM;
+    row_off[0] = 0;
     for (int64_t a = 0; a < n_active; ++a) {
         int len = stride;
         if (count && count[a] < len) len = count[a];
-        n_cand += len;
+        row_off[a + 1] = row_off[a] + len;
     }
+    const int64_t n_cand = row_off[n_active];
     st.n_cand = n_cand;
     cand_ord_t *ord = (cand_ord_t *)malloc((size_t)(n_cand > 0 ? n_cand : 1) * sizeof(cand_ord_t));
     int32_t *depth = (int32_t *)calloc((size_t)n, sizeof(int32_t));
-    if (!ord || !depth) { free(ord); free(depth); return OREF_E_NOMEM; }
+    if (!ord || !depth) { free(ord); free(depth); free(row_off); return OREF_E_NOMEM; }
 
     /* the step-start evaluation (diagnostics only) and every candidate's key */
-    int64_t t = 0;
+    double max_p = 0.0;
+    int64_t n_ge1 = 0, n_acc0 = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(max : max_p) reduction(+ : n_ge1, n_acc0)
     for (int64_t a = 0; a < n_active; ++a) {
         int32_t i = active[a];
-        int len = stride;
-        if (count && count[a] < len) len = count[a];
+        int len = (int)(row_off[a + 1] - row_off[a]);
         for (int s = 0; s < len; ++s) {
             int64_t ci = a * (int64_t)stride + s;
             int32_t j = ngb[ci];
             double P = candidate_probability(x, y, z, vx, vy, vz, mass, m_scalar, state, periodic,
                                              box, i, j, h, h_all, a, dt, xsec, s0, w0, model);
             double u = oref_uniform_decision(seed, step, id[i], id[j]);
-            if (P > st.max_p) st.max_p = P;
-            if (P >= 1.0) st.n_p_ge_1++;
+            if (P > max_p) max_p = P;
+            if (P >= 1.0) n_ge1++;
             if (u < P) {
-                st.n_accept0++;
+                n_acc0++;
                 if (cand_info) cand_info[ci] |= OREF_CAND_ACCEPT0;
             }
             uint32_t xr[4];
             pair_draw(seed, step, id[i], id[j], PURPOSE_PRIORITY, xr);
             cand_ord_t e = {direction_word(xr, id[i] < id[j]), id[i], id[j], ci, a};
-            ord[t++] = e;
+            ord[row_off[a] + s] = e;
         }
     }
+    free(row_off);
+    st.max_p = max_p;
+    st.n_p_ge_1 = n_ge1;
+    st.n_accept0 = n_acc0;
 
     /* every candidate at its turn, with the velocities as they are then */
     qsort(ord, (size_t)n_cand, sizeof(cand_ord_t), cand_ord_cmp);
-    for (t = 0; t < n_cand; ++t) {
+    for (int64_t t = 0; t < n_cand; ++t) {
         const cand_ord_t *c = &ord[t];
         int32_t i = active[c->a], j = ngb[c->c];
         double P = candidate_probability(x, y, z, vx, vy, vz, mass, m_scalar, state, periodic,
@@ -582,6 +628,7 @@ int oref_pair_timestep(int64_t n, const double *vx, const double *vy, const doub
                        int xsec, double s0, double w0, double c_sidm, double *dt_out)
 {
     if (n < k + 2 || k < 1) return OREF_E_INVAL;
+#pragma omp parallel for schedule(static)
     for (int64_t a = 0; a < n_active; ++a) {
         int32_t i = active[a];
         double rmax = 0.0;

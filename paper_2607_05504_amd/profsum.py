@@ -68,7 +68,7 @@ def traffic(fd, wd, cfd, cwd, mib, workload, out_json=None) -> str:
              "|---|---:|---:|---:|---:|"]
     names = sorted(set(fetch) | set(write),
                    key=lambda n: -(sum(fetch.get(n, [0])) / max(1, len(fetch.get(n, [1])))))
-    knn_bytes = 0.0
+    knn_total = 0.0
     for n in names:
         f = fetch.get(n, [0.0])
         w = write.get(n, [0.0])
@@ -76,9 +76,14 @@ def traffic(fd, wd, cfd, cwd, mib, workload, out_json=None) -> str:
         mb = (fa * ff + wa * wf) * 1024 / 1e6
         lines.append(f"| {n[:60]} | {len(f)} | {fa:.1f} | {wa:.1f} | {mb:.3f} |")
         if n.split("<")[0] in KNN_KERNELS:
-            knn_bytes += (fa * ff + wa * wf) * 1024
+            knn_total += (fa * ff + wa * wf) * 1024 * len(f)
+    # one neighbour search per scatter step; a search over more targets than
+    # one batch holds is several dispatches of each kernel
+    calls = len(fetch.get("k_step_reset", [])) or 1
+    knn_bytes = knn_total / calls
     lines.append("")
-    lines.append(f"neighbour-search phase HBM traffic per launch: {knn_bytes / 1e6:.3f} MB")
+    lines.append(f"neighbour-search phase HBM traffic per launch ({calls} launches, "
+                 f"all batches of one launch summed): {knn_bytes / 1e6:.3f} MB")
     if out_json:
         tr = json.load(open(out_json)) if os.path.exists(out_json) else {}
         tr.setdefault(workload, {})["knn"] = {"bytes_per_launch": knn_bytes,

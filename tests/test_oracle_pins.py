@@ -721,3 +721,22 @@ def test_comoving_storage_with_general_factors():
     da = oracle.pair_timestep(a, ngb, h, *va[:3])
     db = oracle.pair_timestep(b, ngb, h * L, *vb[:3])
     np.testing.assert_allclose(da, db, rtol=1e-12)
+
+
+def test_openmp_build_gives_the_same_step():
+    """The OpenMP build of the oracle (the all-core CPU baseline) runs the
+    loops over targets in parallel and the turns serially: the same
+    neighbours, decisions, velocities and timesteps bit for bit."""
+    w = W.hernquist_halo(6000, ic_seed=71, two_state=True)
+    w.sigma0 *= 30.0
+    w = w.subset_active(4500)
+    base = oracle.full_step(w, brute=False)
+    try:
+        assert oracle.use_openmp(4) >= 1
+        par = oracle.full_step(w, brute=False)
+    finally:
+        oracle.use_serial()
+    assert base["stats"]["n_events"] > 50
+    for f in ("ngb", "h", "vx", "vy", "vz", "state", "info", "dt_sidm"):
+        assert np.array_equal(base[f], par[f]), f
+    assert base["stats"] == par["stats"]
