@@ -45,6 +45,7 @@ struct KnnArgs {
     const uint32_t *ids;
     const int32_t *perm;
     const double *nodes;
+    const float4 *sbox;          // sub-bucket boxes: [2 s] lo, [2 s + 1] hi
     const int32_t *tlist, *slot;
     const int32_t *nt_dev;
     int32_t *ngb;
@@ -211,6 +212,10 @@ __device__ __forceinline__ bool group_walk(const KnnArgs &A, int32_t (&s_fr)[2][
     const double gxl = wave_min(member ? px - R : INFINITY), gxh = wave_max(member ? px + R : -INFINITY);
     const double gyl = wave_min(member ? py - R : INFINITY), gyh = wave_max(member ? py + R : -INFINITY);
     const double gzl = wave_min(member ? pz - R : INFINITY), gzh = wave_max(member ? pz + R : -INFINITY);
+    // a group box inside the periodic box meets no image of a node, and the
+    // members' spheres inside it meet no image of a leaf: then the walk tests
+    // no images (the same decisions)
+    const bool wrap = PERIODIC && !(gxl > 0.0 && gxh < box && gyl > 0.0 && gyh < box && gzl > 0.0 && gzh < box);
     int cur = 0, fn = 1, hits = 0;
     wave_sync();
     if (lane == 0) s_fr[0][0] = 0;                    // the root (top level, index 0)
@@ -231,9 +236,12 @@ __device__ __forceinline__ bool group_walk(const KnnArgs &A, int32_t (&s_fr)[2][
                     const double *nb = A.nodes + (coff + q) * 6;
 #pragma unroll
                     for (int d = 0; d < 6; ++d) bx[d] = nb[d];
-                    hit = bx[0] <= bx[3] && interval_meets<PERIODIC>(bx[0], bx[3], gxl, gxh, box) &&
-                          interval_meets<PERIODIC>(bx[1], bx[4], gyl, gyh, box) &&
-                          interval_meets<PERIODIC>(bx[2], bx[5], gzl, gzh, box);
+                    hit = wrap ? (bx[0] <= bx[3] && interval_meets<true>(bx[0], bx[3], gxl, gxh, box) &&
+                                  interval_meets<true>(bx[1], bx[4], gyl, gyh, box) &&
+                                  interval_meets<true>(bx[2], bx[5], gzl, gzh, box))
+                               : (bx[0] <= bx[3] && interval_meets<false>(bx[0], bx[3], gxl, gxh, box) &&
+                                  interval_meets<false>(bx[1], bx[4], gyl, gyh, box) &&
+                                  interval_meets<false>(bx[2], bx[5], gzl, gzh, box));
                 }
             }
             const uint64_t m = __ballot(hit);
@@ -258,7 +266,8 @@ __device__ __forceinline__ bool group_walk(const KnnArgs &A, int32_t (&s_fr)[2][
                     const int h = h0 + sub;
                     bool ok = false;
                     if (h < nh)
-                        ok = member && box_gap2<PERIODIC>(s_hit + h * 6, px, py, pz, box) <= T;
+                        ok = member && (wrap ? box_gap2<true>(s_hit + h * 6, px, py, pz, box)
+                                             : box_gap2<false>(s_hit + h * 6, px, py, pz, box)) <= T;
                     const uint64_t m = (__ballot(ok) >> (lane - sub)) & mine;
                     const int pos = nl + __popcll(m & ((1ull << sub) - 1ull));
                     if (ok && pos < SIDM_KNN_LMAX) lst[pos] = s_fr[cur ^ 1][h];
@@ -443,7 +452,7 @@ __device__ __forceinline__ int32_t walk_next(const KnnArgs &A, int32_t *stk, int
 // 256^3: the occupancy hides the latency instead)
 constexpr bool kPrefetchLeaf = false;
 
-template <bool PERIODIC, int E, bool MIXED, int TS, int LPI>
+template <bool PERIODIC, int E, bool MIXED, int TS, int LPI, bool FB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
 {
@@ -477,6 +486,7 @@ void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
 
     // the leaf list of the first kernel, or a walk from the root if it overflowed
     const int nl = A.nl[bb];
+    if (FB && nl >= 0) return;                // done by the sub-bucket kernel
     const int32_t *lst = A.list + bb * SIDM_KNN_LMAX;
     const bool walk = nl < 0;
     int sp = 0;
@@ -819,6 +829,350 @@ void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Kernel B': exact selection by a 16-lane team per target over sub-buckets
+// ---------------------------------------------------------------------------
+// The team takes its leaf list four leaves at a time: lane l tests sub-bucket
+// l % 4 of leaf l / 4 (SIDM_SUB particles, its own box) against the current
+// radius, and the kept sub-buckets' particles are tested two sub-buckets (16
+// particles, one per lane) a round, so that a particle is only tested when
+// its sub-bucket meets the sphere.  Those within the radius go to the team's
+// LDS list of CAP entries.  When a round might not fit, the list is cut as in
+// kernel B (K1-th smallest r^2 rounded up to FP32, found by bisection on
+// team-wide counts).  At the end each entry's place is its rank in
+// (r^2, ID, index) among the entries, found by comparing it with all of them;
+// a list longer than K1 + 16 is first thinned by the same bisection.
+// Targets whose list overflowed in the first kernel, or whose cut could not
+// make room (many equal r^2), are left to kernel B's root walk (nl set to -1).
+constexpr int kSubPerLeaf = SIDM_LEAF / SIDM_SUB;
+constexpr int kRankMax = 48;
+constexpr int kKeepMax = 192;         // kept sub-buckets per target (more: the root walk)
+constexpr int kSubLoads = 4;          // sub-bucket boxes a lane requests at a time
+constexpr int kPairs = 4;             // pairs of sub-buckets a round
+
+template <bool PERIODIC>
+__device__ __forceinline__ double sub_gap2(const float4 &lo, const float4 &hi, double px, double py,
+                                           double pz, double box)
+{
+    const double gx = axis_gap<PERIODIC>((double)lo.x, (double)hi.x, px, box);
+    const double gy = axis_gap<PERIODIC>((double)lo.y, (double)hi.y, py, box);
+    const double gz = axis_gap<PERIODIC>((double)lo.z, (double)hi.z, pz, box);
+    const double g2 = (gx * gx + gy * gy) + gz * gz;
+    return lo.x <= hi.x ? g2 : INFINITY;
+}
+
+// Team-wide K1-th smallest of the FP32 values f (rounded up from r^2) of the
+// team's E-per-lane entries (entry q * TS + tl, those at or past count are
+// +inf): the smallest FP32 value with at least K1 values at or below it,
+// bisected on bit patterns until at most `enough` values remain at or below
+// it (or the bracket closes).  Returns the bound; c_out = values at or below.
+template <int E, int TS>
+__device__ __forceinline__ float team_select(const float (&f)[E], int count, int K1, int enough,
+                                             int tl, int &c_out)
+{
+    uint32_t lo = 0xffffffffu, hi = 0u;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        if (q * TS + tl < count) {
+            const uint32_t bv = __float_as_uint(f[q]);
+            lo = bv < lo ? bv : lo;
+            hi = bv > hi ? bv : hi;
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < TS; off <<= 1) {
+        const uint32_t ol = (uint32_t)__shfl_xor((int)lo, off);
+        const uint32_t oh = (uint32_t)__shfl_xor((int)hi, off);
+        lo = ol < lo ? ol : lo;
+        hi = oh > hi ? oh : hi;
+    }
+    int c_hi = count;
+    for (int it = 0; it < 32 && lo < hi && c_hi > enough; ++it) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        const float fm = __uint_as_float(mid);
+        int c = 0;
+#pragma unroll
+        for (int q = 0; q < E; ++q) c += f[q] <= fm;
+#pragma unroll
+        for (int off = 1; off < TS; off <<= 1) c += __shfl_xor(c, off);
+        if (c >= K1) { hi = mid; c_hi = c; } else { lo = mid + 1; }
+    }
+    c_out = c_hi;
+    return __uint_as_float(hi);
+}
+
+// Keeps the entries whose FP32 value is at most Tf, in order, at the front
+// of the team's list; returns the new count.
+template <int E, int TS>
+__device__ __forceinline__ int team_compact(double *L_r2, int32_t *L_j, const float (&f)[E],
+                                            float Tf, int count, int tl)
+{
+    double r[E];
+    int32_t jj[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int e = q * TS + tl;
+        r[q] = e < count ? L_r2[e] : INFINITY;
+        jj[q] = e < count ? L_j[e] : -1;
+    }
+    int total = 0;
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const bool keep = q * TS + tl < count && f[q] <= Tf;
+        int pre = keep;                        // inclusive prefix over the team
+#pragma unroll
+        for (int off = 1; off < TS; off <<= 1) {
+            const int o = __shfl_up(pre, off, TS);
+            if (tl >= off) pre += o;
+        }
+        if (keep) { L_r2[total + pre - 1] = r[q]; L_j[total + pre - 1] = jj[q]; }
+        total += __shfl(pre, TS - 1, TS);
+    }
+    wave_sync();
+    return total;
+}
+
+// Places each of the team's count entries by its rank in (r^2, ID, index)
+// among them (IDs read only if some r^2 are equal): rank < k goes to row
+// place rank, rank k gives h.  RQ entries per lane (entry q * TS + tl).
+template <int RQ, int TS>
+__device__ __forceinline__ void team_rank_out(const KnnArgs &A, const double *L_r2, const int32_t *L_j,
+                                              uint32_t *L_id, int count, int wteam, int tl,
+                                              int32_t *out, int32_t *srt, int32_t a)
+{
+    double re[RQ];
+    int rank[RQ];
+    bool tie = false;
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+        const int e = q * TS + tl;
+        re[q] = e < count ? L_r2[e] : INFINITY;
+        rank[q] = 0;
+    }
+    for (int f2 = 0; f2 < count; ++f2) {
+        const double rf = L_r2[f2];
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) {
+            rank[q] += rf < re[q];
+            tie = tie || (rf == re[q] && f2 != q * TS + tl);
+        }
+    }
+    if (((__ballot(tie) >> (wteam * TS)) & ((1ull << TS) - 1ull)) != 0ull) {
+        for (int e = tl; e < count; e += TS) L_id[e] = A.ids[L_j[e]];
+        wave_sync();
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) {
+            const int e = q * TS + tl;
+            if (e < count) {
+                const uint32_t ide = L_id[e];
+                const int32_t je = L_j[e];
+                for (int f2 = 0; f2 < count; ++f2) {
+                    if (L_r2[f2] != re[q] || f2 == e) continue;
+                    const uint32_t idf = L_id[f2];
+                    rank[q] += idf < ide || (idf == ide && L_j[f2] < je);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+        const int e = q * TS + tl;
+        if (e < count) {
+            if (rank[q] < A.k) {
+                const int32_t j = L_j[e];
+                out[rank[q]] = A.perm[j];
+                srt[rank[q]] = j;
+            } else if (rank[q] == A.k) {
+                A.h[a] = sqrt(re[q]);
+            }
+        }
+    }
+}
+
+// The scan of kernel B': the list's sub-buckets against the sphere, then
+// their particles into the team's list.  PER: with periodic images; a target
+// whose padded sphere lies inside the box scans without them (no image of a
+// particle within its radius can be nearer, and the separations of those
+// within it round the same), which is bit-identical and cheaper.
+template <bool PER, int CAP>
+__device__ __forceinline__ bool bucket_scan(const KnnArgs &A, int32_t i, double px, double py, double pz,
+                                            const int32_t *lst, int nl, uint32_t *K, double *L_r2,
+                                            int32_t *L_j, int wteam, int tl, double &T, int &count)
+{
+    constexpr int TS = 16;
+    constexpr int E = CAP / TS;
+    const double box = A.box;
+    const int64_t n = A.n;
+    const int K1 = A.k + 1;
+    const uint64_t below = (tl == 0) ? 0ull : ((1ull << tl) - 1ull);
+    bool gave_up = false;
+    // 1. the list's sub-buckets that meet the sphere, into the team's LDS
+    // list K (boxes requested kSubLoads a lane at a time)
+    int nk = 0;
+    const int nsb = nl * kSubPerLeaf;
+    for (int s0 = 0; s0 < nsb; s0 += TS * kSubLoads) {
+        int32_t sbi[kSubLoads];
+        float4 blo[kSubLoads], bhi[kSubLoads];
+#pragma unroll
+        for (int u = 0; u < kSubLoads; ++u) {
+            const int t = s0 + u * TS + tl;
+            const int32_t leaf = t < nsb ? lst[t / kSubPerLeaf] : -1;
+            sbi[u] = leaf >= 0 ? leaf * kSubPerLeaf + t % kSubPerLeaf : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kSubLoads; ++u) {
+            const int64_t q = sbi[u] >= 0 ? sbi[u] : 0;
+            blo[u] = A.sbox[2 * q];
+            bhi[u] = A.sbox[2 * q + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kSubLoads; ++u) {
+            const bool keep = sbi[u] >= 0 && sub_gap2<PER>(blo[u], bhi[u], px, py, pz, box) <= T;
+            const uint32_t km = (uint32_t)(__ballot(keep) >> (wteam * TS)) & 0xffffu;
+            if (keep) {
+                const int pos = nk + __popc(km & (uint32_t)below);
+                if (pos < kKeepMax) K[pos] = (uint32_t)sbi[u];
+            }
+            nk += __popc(km);
+        }
+    }
+    gave_up = nk > kKeepMax;
+    wave_sync();
+    // 2. their particles, kPairs pairs of sub-buckets a round (lanes 0-7 the
+    // first of a pair, 8-15 the second), all positions of a round requested
+    // together
+    for (int k0 = 0; k0 < nk && !gave_up; k0 += 2 * kPairs) {
+        double qx[kPairs], qy[kPairs], qz[kPairs];
+        int64_t jv[kPairs];
+        bool ok[kPairs];
+#pragma unroll
+        for (int u = 0; u < kPairs; ++u) {
+            const int e = k0 + 2 * u + (tl >= SIDM_SUB ? 1 : 0);
+            const int64_t j = e < nk ? (int64_t)K[e] * SIDM_SUB + tl % SIDM_SUB : -1;
+            ok[u] = j >= 0 && j < n && j != i;
+            jv[u] = j;
+            const int64_t jc = ok[u] ? j : i;
+            qx[u] = A.xs[jc]; qy[u] = A.ys[jc]; qz[u] = A.zs[jc];
+        }
+        double r2[kPairs];
+        uint32_t hm[kPairs];
+        int nh = 0;
+#pragma unroll
+        for (int u = 0; u < kPairs; ++u) {
+            r2[u] = sep2_sel<PER>(px, py, pz, qx[u], qy[u], qz[u], box);
+            hm[u] = (uint32_t)(__ballot(ok[u] && r2[u] <= T) >> (wteam * TS)) & 0xffffu;
+            nh += __popc(hm[u]);
+        }
+        if (count + nh > CAP) {
+            // cut: the radius becomes the K1-th smallest r^2 rounded up
+            float f[E];
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const int e = q * TS + tl;
+                f[q] = e < count ? __double2float_ru(L_r2[e]) : INFINITY;
+            }
+            int c_hi;
+            const float Tf = team_select<E, TS>(f, count, K1, K1 + 8, tl, c_hi);
+            if (c_hi > CAP - kPairs * TS) {
+                gave_up = true;                   // too many equal values to make room
+                break;
+            }
+            count = team_compact<E, TS>(L_r2, L_j, f, Tf, count, tl);
+            T = fmin(T, (double)Tf);
+#pragma unroll
+            for (int u = 0; u < kPairs; ++u)
+                hm[u] = (uint32_t)(__ballot(ok[u] && r2[u] <= T) >> (wteam * TS)) & 0xffffu;
+        }
+#pragma unroll
+        for (int u = 0; u < kPairs; ++u) {
+            if ((hm[u] >> tl) & 1u) {
+                const int pos = count + __popc(hm[u] & (uint32_t)below);
+                L_r2[pos] = r2[u];
+                L_j[pos] = (int32_t)jv[u];
+            }
+            count += __popc(hm[u]);
+        }
+    }
+    return gave_up;
+}
+
+template <bool PERIODIC, int CAP>
+__global__ __launch_bounds__(256) void k_knn_bucket(KnnArgs A, int64_t base, int64_t nblk)
+{
+    constexpr int TS = 16;                    // lanes per target
+    constexpr int NT = 256 / TS;              // teams per workgroup
+    constexpr int E = CAP / TS;               // list entries per lane
+    constexpr int CP = CAP + 2;               // padded team stride (teams of a wavefront in other banks)
+    static_assert(CAP % TS == 0 && CAP >= kRankMax + kPairs * TS, "list capacity");
+    __shared__ double s_r2[NT][CP];
+    __shared__ int32_t s_j[NT][CP];
+    // the kept sub-buckets during the scan, the IDs of the entries at the end
+    __shared__ uint32_t s_aux[NT][kKeepMax > CP ? kKeepMax : CP];
+
+    const int team = threadIdx.x / TS, tl = threadIdx.x % TS;
+    const int wteam = team % (64 / TS);
+    const int nt = *A.nt_dev;
+    const int64_t blk = xcd_block(nblk);
+    if (blk < 0) return;
+    const int64_t bb = blk * NT + team;
+    const int64_t b = base + bb;
+    if (!(b < nt && bb < A.batch)) return;    // whole team
+    const int nl = A.nl[bb];
+    if (nl < 0) return;                       // kernel B walks from the root
+    const int32_t i = A.tlist[b];
+    const double px = A.xs[i], py = A.ys[i], pz = A.zs[i];
+    const double box = A.box;
+    const int64_t n = A.n;
+    const int K1 = A.k + 1;
+    double *L_r2 = s_r2[team];
+    int32_t *L_j = s_j[team];
+    const uint64_t below = (tl == 0) ? 0ull : ((1ull << tl) - 1ull);
+    const int32_t *lst = A.list + bb * SIDM_KNN_LMAX;
+    double T = A.tb[bb];
+    int count = 0;
+    bool gave_up;
+    {
+        // padded like the first kernel's sphere: far beyond rounding
+        const double R = sqrt(T) * (1.0 + 1e-9) + (fabs(px) + fabs(py) + fabs(pz) + box) * 1e-14;
+        const bool inside = px - R > 0.0 && px + R < box && py - R > 0.0 && py + R < box &&
+                            pz - R > 0.0 && pz + R < box;
+        if (PERIODIC && !inside)
+            gave_up = bucket_scan<PERIODIC, CAP>(A, i, px, py, pz, lst, nl, s_aux[team], L_r2, L_j, wteam,
+                                                 tl, T, count);
+        else
+            gave_up = bucket_scan<false, CAP>(A, i, px, py, pz, lst, nl, s_aux[team], L_r2, L_j, wteam, tl,
+                                              T, count);
+    }
+    if (gave_up) {
+        if (tl == 0) A.nl[bb] = -1;
+        return;
+    }
+    const int32_t a = A.slot[b];
+    if (count < K1) {                          // cannot happen: T bounds K1 window particles
+        if (tl == 0) atomicOr(A.derr, DERR_COUNT);
+        return;
+    }
+    wave_sync();
+    if (count > K1 + 16) {
+        float f[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int e = q * TS + tl;
+            f[q] = e < count ? __double2float_ru(L_r2[e]) : INFINITY;
+        }
+        int c_hi;
+        const float Tf = team_select<E, TS>(f, count, K1, K1 + 8, tl, c_hi);
+        count = team_compact<E, TS>(L_r2, L_j, f, Tf, count, tl);
+    }
+    int32_t *out = A.ngb + (int64_t)a * A.k;
+    int32_t *srt = A.jsort + b * A.k;
+    if (count <= kRankMax)
+        team_rank_out<(kRankMax + TS - 1) / TS, TS>(A, L_r2, L_j, s_aux[team], count, wteam, tl, out, srt, a);
+    else
+        team_rank_out<E, TS>(A, L_r2, L_j, s_aux[team], count, wteam, tl, out, srt, a);
+}
+
 constexpr int kTeam = 16;                 // lanes per target in the team kernel (8 measured slower)
 
 constexpr int kLeavesPerStep = 2;          // leaves a team tests per step of its loop
@@ -834,7 +1188,17 @@ void launch_batches_l(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipSt
         constexpr int G = 64 / kListLanes;
         const int64_t gl = (A.batch + G - 1) / G, gt = (A.batch + 256 / TS - 1) / (256 / TS);
         k_knn_list<P, kListLanes><<<xcd_grid(gl), 64, 0, s>>>(A, base, gl);
-        k_knn_team<P, E, M, TS, LPI><<<xcd_grid(gt), 256, 0, s>>>(A, base, gt);
+        if constexpr (M) {
+            k_knn_team<P, E, M, TS, LPI, false><<<xcd_grid(gt), 256, 0, s>>>(A, base, gt);
+        } else {
+            // room after a cut (K1 + 8 entries at most, unless r^2 repeat)
+            // for the kPairs * 16 particles of a round
+            if (A.k + 1 + 8 + kPairs * 16 <= 128)
+                k_knn_bucket<P, 128><<<xcd_grid(gt), 256, 0, s>>>(A, base, gt);
+            else
+                k_knn_bucket<P, 144><<<xcd_grid(gt), 256, 0, s>>>(A, base, gt);
+            k_knn_team<P, E, M, TS, LPI, true><<<xcd_grid(gt), 256, 0, s>>>(A, base, gt);
+        }
     }
 }
 
@@ -853,6 +1217,7 @@ hipError_t launch_knn(sidm_ctx *c, int64_t n_active, int32_t *ngb, double *h)
     KnnArgs A;
     A.xs = c->xs; A.ys = c->ys; A.zs = c->zs;
     A.ids = c->ids; A.perm = c->perm; A.nodes = c->nodes;
+    A.sbox = (const float4 *)c->sbox;
     A.tlist = c->tlist; A.slot = c->slot; A.nt_dev = c->nt_dev;
     A.ngb = ngb; A.h = h; A.derr = c->derr;
     A.jsort = c->jsort;

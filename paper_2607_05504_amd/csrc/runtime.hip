@@ -59,6 +59,7 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(dtot, 6 * 256, uint32_t);
     ADD(bounds, 6, unsigned long long);
     ADD(nodes, tree_node_count(tree_levels(N)) * 6, double);
+    ADD(sbox, tree_levels(N).cnt[0] * (SIDM_LEAF / SIDM_SUB) * 8, float);
     if (c->cfg.precision == SIDM_MIXED) {
         ADD(xo, N, float); ADD(yo, N, float); ADD(zo, N, float);
     }

@@ -10,6 +10,7 @@
 
 #define SIDM_PI 3.14159265358979323846
 #define SIDM_LEAF 32            // particles per tree leaf (consecutive in Morton order)
+#define SIDM_SUB 8              // particles per sub-bucket of a leaf (its own box, for the search)
 #define SIDM_SORT_TILE 2048     // keys per radix-sort workgroup (256 threads x 8)
 #define SIDM_SCAN_TILE 1024     // elements per compaction workgroup
 #define SIDM_TIMING_RING 256    // timed launches per phase between two reads
@@ -126,6 +127,8 @@ struct sidm_ctx {
     // levels of SIDM_TREE_FAN-ary parents above them, boxes level after level
     TreeLevels lv;
     double *nodes;           // [nodes][6]  lo x,y,z, hi x,y,z
+    float *sbox;             // [leaves * SIDM_LEAF / SIDM_SUB][8]  sub-bucket boxes, FP32 rounded
+                             // outward: lo x,y,z, 0, hi x,y,z, 0
     // mixed form only: FP32 offsets of each particle from its leaf's box
     // centre 0.5 (lo + hi), the centre itself rounded as that FP64 expression
     float *xo, *yo, *zo;

@@ -355,15 +355,18 @@ __global__ __launch_bounds__(256) void k_gather_rec(int64_t n, const int32_t *__
 
 // --- bucket tree boxes --------------------------------------------------------------
 // Two leaves per wavefront: lane l holds particle (leaf*32 + l%32); min/max by
-// butterfly shuffles within each half-wave.  A workgroup's 8 leaves are the
-// children of one level-1 node, whose box it writes too (at nodes[off1 + b]).
+// butterfly shuffles within each half-wave, over the 8 lanes of a sub-bucket
+// first (its box is written in FP32 rounded outward, so that it contains the
+// exact box), then over the leaf.  A workgroup's 8 leaves are the children of
+// one level-1 node, whose box it writes too (at nodes[off1 + b]).
 __global__ __launch_bounds__(256) void k_leaf_boxes(int64_t n, int64_t nleaf,
                                                     const double *__restrict__ xs,
                                                     const double *__restrict__ ys,
                                                     const double *__restrict__ zs, double *nodes,
-                                                    int64_t off1, int64_t cnt1)
+                                                    float *sbox, int64_t off1, int64_t cnt1)
 {
     static_assert(SIDM_TREE_FAN * SIDM_LEAF == 256, "a workgroup covers one level-1 node");
+    static_assert(SIDM_SUB == 8, "a sub-bucket box is 8 floats, one per lane");
     __shared__ double s_box[SIDM_TREE_FAN][6];
     const int64_t leaf = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
     const int sub = threadIdx.x & 31;
@@ -378,7 +381,15 @@ __global__ __launch_bounds__(256) void k_leaf_boxes(int64_t n, int64_t nleaf,
         v[0] = v[1] = v[2] = INFINITY;
         v[3] = v[4] = v[5] = -INFINITY;
     }
-    for (int off = 16; off > 0; off >>= 1) {
+    for (int off = 1; off < 32; off <<= 1) {
+        if (off == SIDM_SUB && leaf < nleaf) {
+            // lane d of the sub-bucket writes float d of its box
+            const int d = sub % SIDM_SUB;
+            float f = 0.0f;
+            if (d < 3) f = __double2float_rd(v[d]);
+            else if (d >= 4 && d < 7) f = __double2float_ru(v[d - 1]);
+            sbox[(leaf * (SIDM_LEAF / SIDM_SUB) + sub / SIDM_SUB) * 8 + d] = f;
+        }
         for (int d = 0; d < 3; ++d) {
             v[d] = fmin(v[d], __shfl_xor(v[d], off));
             v[3 + d] = fmax(v[3 + d], __shfl_xor(v[3 + d], off));
@@ -603,8 +614,8 @@ hipError_t launch_refit_tree(sidm_ctx *c, const sidm_particles *p)
     const int64_t nleaf = lv.cnt[0];
     // leaves and level 1 together, then the big levels one launch each, then
     // the small ones in a single workgroup
-    k_leaf_boxes<<<(unsigned)((nleaf * 32 + 255) / 256), 256, 0, s>>>(n, nleaf, c->xs, c->ys, c->zs,
-                                                                     c->nodes, lv.off[1], lv.cnt[1]);
+    k_leaf_boxes<<<(unsigned)((nleaf * 32 + 255) / 256), 256, 0, s>>>(
+        n, nleaf, c->xs, c->ys, c->zs, c->nodes, c->sbox, lv.off[1], lv.cnt[1]);
     int l = 2;
     for (; l < lv.nlev && lv.cnt[l] > 8192; ++l)
         k_level_boxes<<<(unsigned)((lv.cnt[l] + 255) / 256), 256, 0, s>>>(
