@@ -53,6 +53,8 @@ struct KnnArgs {
     unsigned int *derr;
     int32_t *list;       // [batch][SIDM_KNN_LMAX] leaf lists
     int32_t *nl;         // [batch] list length, -1 on overflow
+    int32_t *fb_list;    // [batch] targets left to kernel B's root walk
+    int32_t *fb_count;   // their number (cleared by the first kernel)
     double *tb;          // [batch] radius bound from the window
     TreeLevels lv;
     int64_t n, batch;
@@ -101,8 +103,11 @@ __device__ __forceinline__ double sep2_sel(double xi, double yi, double zi, doub
 // the K1-th smallest of the FP32 r^2 (rounded up) of the other particles
 // within W places of the target in Morton order (W before and W after,
 // shifted inward at the ends of the order).  Any K1 other particles bound the
-// K1-th nearest from above, and rounding up keeps the bound valid.  +inf if
-// fewer than K1 values are finite.
+// K1-th nearest from above, and rounding up keeps the bound valid.  The
+// separations take no periodic image: a direct separation is never shorter
+// than the nearest image's, so the bound stays valid, and Morton neighbours
+// are direct neighbours except across a jump of the curve.  +inf if fewer
+// than K1 values are finite.
 template <bool PERIODIC, int LT, int W>
 __device__ __forceinline__ double window_bound(const KnnArgs &A, int64_t i, double px, double py,
                                                double pz, int K1, int sub)
@@ -132,7 +137,7 @@ __device__ __forceinline__ double window_bound(const KnnArgs &A, int64_t i, doub
             if (q >= PER) break;
             const int64_t j = w0 + q * LT + sub;
             v[q] = (j < n && j <= w0 + 2 * W && j != i)
-                       ? __double2float_ru(sep2_sel<PERIODIC>(px, py, pz, wx[u], wy[u], wz[u], A.box))
+                       ? __double2float_ru(sep2_sel<false>(px, py, pz, wx[u], wy[u], wz[u], A.box))
                        : INFINITY;
         }
     }
@@ -287,6 +292,7 @@ __global__ __launch_bounds__(64) void k_knn_list(KnnArgs A, int64_t base, int64_
     constexpr int G = 64 / LT;                // targets per wavefront
     __shared__ int32_t s_fr[2][kFront];
     __shared__ double s_hit[64 * 6];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *A.fb_count = 0;
     const int64_t blk = xcd_block(nblk);
     if (blk < 0) return;
     const int nt = *A.nt_dev;
@@ -452,26 +458,17 @@ __device__ __forceinline__ int32_t walk_next(const KnnArgs &A, int32_t *stk, int
 // 256^3: the occupancy hides the latency instead)
 constexpr bool kPrefetchLeaf = false;
 
-template <bool PERIODIC, int E, bool MIXED, int TS, int LPI, bool FB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
-void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
+// One target of kernel B (its team's lists and stack in LDS).
+template <bool PERIODIC, int E, bool MIXED, int TS, int LPI>
+__device__ __forceinline__ void team_target(const KnnArgs &A, int64_t base, int64_t bb, double *L_r2,
+                                            int32_t *L_j, int32_t *stk, int tl, int wteam)
 {
     constexpr int N = TS * E;                 // list capacity
     constexpr int KP = (SIDM_KNN_LMAX + TS - 1) / TS;
     constexpr int PPL = SIDM_LEAF / TS;       // particles of a leaf per lane
     constexpr int PS = PPL * LPI;             // particles per lane per step (LPI leaves)
-    constexpr int NT = 256 / TS;              // teams per workgroup
     constexpr uint64_t TMASK = (TS == 64) ? ~0ull : ((1ull << TS) - 1ull);
-    __shared__ int32_t s_stack[NT][kStackB];  // only the overflow walk uses it
-    __shared__ double s_r2[NT][N];
-    __shared__ int32_t s_j[NT][N];
-
-    const int team = threadIdx.x / TS, tl = threadIdx.x % TS;
-    const int wteam = team % (64 / TS);       // team within the wavefront
     const int nt = *A.nt_dev;
-    const int64_t blk = xcd_block(nblk);
-    if (blk < 0) return;                      // whole workgroup
-    const int64_t bb = blk * NT + team;
     const int64_t b = base + bb;
     if (!(b < nt && bb < A.batch)) return;    // whole team
     const int32_t i = A.tlist[b];
@@ -479,14 +476,10 @@ void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
     const double box = A.box;
     const int64_t n = A.n;
     const int K1 = A.k + 1;
-    double *L_r2 = s_r2[team];
-    int32_t *L_j = s_j[team];
-    int32_t *stk = s_stack[team];
     const uint64_t below = (tl == 0) ? 0ull : ((1ull << tl) - 1ull);
 
     // the leaf list of the first kernel, or a walk from the root if it overflowed
     const int nl = A.nl[bb];
-    if (FB && nl >= 0) return;                // done by the sub-bucket kernel
     const int32_t *lst = A.list + bb * SIDM_KNN_LMAX;
     const bool walk = nl < 0;
     int sp = 0;
@@ -829,6 +822,36 @@ void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
     }
 }
 
+// Kernel B over a batch (one team per target), or, as the fallback of kernel
+// B', over the targets it left (fb_list), the grid striding over them.
+template <bool PERIODIC, int E, bool MIXED, int TS, int LPI, bool FB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
+{
+    constexpr int N = TS * E;
+    constexpr int NT = 256 / TS;              // teams per workgroup
+    __shared__ int32_t s_stack[NT][kStackB];  // only the overflow walk uses it
+    __shared__ double s_r2[NT][N];
+    __shared__ int32_t s_j[NT][N];
+    const int team = threadIdx.x / TS, tl = threadIdx.x % TS;
+    const int wteam = team % (64 / TS);       // team within the wavefront
+    if constexpr (FB) {
+        const int cnt = *A.fb_count;
+        const int64_t stride = (int64_t)gridDim.x * NT;
+        for (int64_t f0 = 0; f0 < cnt; f0 += stride) {
+            const int64_t idx = f0 + (int64_t)blockIdx.x * NT + team;
+            if (idx < cnt)
+                team_target<PERIODIC, E, MIXED, TS, LPI>(A, base, A.fb_list[idx], s_r2[team], s_j[team],
+                                                         s_stack[team], tl, wteam);
+        }
+    } else {
+        const int64_t blk = xcd_block(nblk);
+        if (blk < 0) return;                  // whole workgroup
+        team_target<PERIODIC, E, MIXED, TS, LPI>(A, base, blk * NT + team, s_r2[team], s_j[team],
+                                                 s_stack[team], tl, wteam);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Kernel B': exact selection by a 16-lane team per target over sub-buckets
 // ---------------------------------------------------------------------------
@@ -846,6 +869,8 @@ void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
 // make room (many equal r^2), are left to kernel B's root walk (nl set to -1).
 constexpr int kSubPerLeaf = SIDM_LEAF / SIDM_SUB;
 constexpr int kRankMax = 48;
+// dword 3 of a raw buffer resource on gfx9-family parts (32-bit data format)
+constexpr int kRsrcWord3 = 0x00020000;
 constexpr int kKeepMax = 192;         // kept sub-buckets per target (more: the root walk)
 constexpr int kSubLoads = 4;          // sub-bucket boxes a lane requests at a time
 constexpr int kPairs = 4;             // pairs of sub-buckets a round
@@ -943,7 +968,6 @@ __device__ __forceinline__ void team_rank_out(const KnnArgs &A, const double *L_
 {
     double re[RQ];
     int rank[RQ];
-    bool tie = false;
 #pragma unroll
     for (int q = 0; q < RQ; ++q) {
         const int e = q * TS + tl;
@@ -953,11 +977,19 @@ __device__ __forceinline__ void team_rank_out(const KnnArgs &A, const double *L_
     for (int f2 = 0; f2 < count; ++f2) {
         const double rf = L_r2[f2];
 #pragma unroll
-        for (int q = 0; q < RQ; ++q) {
-            rank[q] += rf < re[q];
-            tie = tie || (rf == re[q] && f2 != q * TS + tl);
-        }
+        for (int q = 0; q < RQ; ++q) rank[q] += rf < re[q];
     }
+    // equal r^2 share a rank: each entry claims place rank, and a place
+    // claimed twice shows a tie
+#pragma unroll
+    for (int q = 0; q < RQ; ++q)
+        if (q * TS + tl < count) L_id[rank[q]] = (uint32_t)(q * TS + tl);
+    wave_sync();
+    bool tie = false;
+#pragma unroll
+    for (int q = 0; q < RQ; ++q)
+        if (q * TS + tl < count) tie = tie || L_id[rank[q]] != (uint32_t)(q * TS + tl);
+    wave_sync();
     if (((__ballot(tie) >> (wteam * TS)) & ((1ull << TS) - 1ull)) != 0ull) {
         for (int e = tl; e < count; e += TS) L_id[e] = A.ids[L_j[e]];
         wave_sync();
@@ -995,8 +1027,19 @@ __device__ __forceinline__ void team_rank_out(const KnnArgs &A, const double *L_
 // whose padded sphere lies inside the box scans without them (no image of a
 // particle within its radius can be nearer, and the separations of those
 // within it round the same), which is bit-identical and cheaper.
-template <bool PER, int CAP>
-__device__ __forceinline__ bool bucket_scan(const KnnArgs &A, int32_t i, double px, double py, double pz,
+// positions by 32-bit byte offsets into buffer resources (one address for the
+// three loads), for arrays under 4 GiB
+struct PosRsrc {
+    __amdgpu_buffer_rsrc_t x, y, z;
+};
+__device__ __forceinline__ double buf_ld64(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+template <bool PER, bool BUF, int CAP>
+__device__ __forceinline__ bool bucket_scan(const KnnArgs &A, const PosRsrc &pr, int32_t i, double px,
+                                            double py, double pz,
                                             const int32_t *lst, int nl, uint32_t *K, double *L_r2,
                                             int32_t *L_j, int wteam, int tl, double &T, int &count)
 {
@@ -1053,7 +1096,12 @@ __device__ __forceinline__ bool bucket_scan(const KnnArgs &A, int32_t i, double 
             ok[u] = j >= 0 && j < n && j != i;
             jv[u] = j;
             const int64_t jc = ok[u] ? j : i;
-            qx[u] = A.xs[jc]; qy[u] = A.ys[jc]; qz[u] = A.zs[jc];
+            if constexpr (BUF) {
+                const uint32_t off = (uint32_t)jc * 8u;
+                qx[u] = buf_ld64(pr.x, off); qy[u] = buf_ld64(pr.y, off); qz[u] = buf_ld64(pr.z, off);
+            } else {
+                qx[u] = A.xs[jc]; qy[u] = A.ys[jc]; qz[u] = A.zs[jc];
+            }
         }
         double r2[kPairs];
         uint32_t hm[kPairs];
@@ -1119,7 +1167,10 @@ __global__ __launch_bounds__(256) void k_knn_bucket(KnnArgs A, int64_t base, int
     const int64_t b = base + bb;
     if (!(b < nt && bb < A.batch)) return;    // whole team
     const int nl = A.nl[bb];
-    if (nl < 0) return;                       // kernel B walks from the root
+    if (nl < 0) {                             // kernel B walks from the root
+        if (tl == 0) A.fb_list[atomicAdd(A.fb_count, 1)] = (int32_t)bb;
+        return;
+    }
     const int32_t i = A.tlist[b];
     const double px = A.xs[i], py = A.ys[i], pz = A.zs[i];
     const double box = A.box;
@@ -1137,15 +1188,25 @@ __global__ __launch_bounds__(256) void k_knn_bucket(KnnArgs A, int64_t base, int
         const double R = sqrt(T) * (1.0 + 1e-9) + (fabs(px) + fabs(py) + fabs(pz) + box) * 1e-14;
         const bool inside = px - R > 0.0 && px + R < box && py - R > 0.0 && py + R < box &&
                             pz - R > 0.0 && pz + R < box;
+        const bool buf = (uint64_t)n * 8u <= 0xffffffffull;
+        PosRsrc pr;
+        const int nb = buf ? (int)(uint32_t)(n * 8) : 0;
+        pr.x = __builtin_amdgcn_make_buffer_rsrc((void *)A.xs, (short)0, nb, kRsrcWord3);
+        pr.y = __builtin_amdgcn_make_buffer_rsrc((void *)A.ys, (short)0, nb, kRsrcWord3);
+        pr.z = __builtin_amdgcn_make_buffer_rsrc((void *)A.zs, (short)0, nb, kRsrcWord3);
+        uint32_t *K = s_aux[team];
         if (PERIODIC && !inside)
-            gave_up = bucket_scan<PERIODIC, CAP>(A, i, px, py, pz, lst, nl, s_aux[team], L_r2, L_j, wteam,
-                                                 tl, T, count);
+            gave_up = buf ? bucket_scan<PERIODIC, true, CAP>(A, pr, i, px, py, pz, lst, nl, K, L_r2, L_j, wteam, tl, T, count)
+                          : bucket_scan<PERIODIC, false, CAP>(A, pr, i, px, py, pz, lst, nl, K, L_r2, L_j, wteam, tl, T, count);
         else
-            gave_up = bucket_scan<false, CAP>(A, i, px, py, pz, lst, nl, s_aux[team], L_r2, L_j, wteam, tl,
-                                              T, count);
+            gave_up = buf ? bucket_scan<false, true, CAP>(A, pr, i, px, py, pz, lst, nl, K, L_r2, L_j, wteam, tl, T, count)
+                          : bucket_scan<false, false, CAP>(A, pr, i, px, py, pz, lst, nl, K, L_r2, L_j, wteam, tl, T, count);
     }
     if (gave_up) {
-        if (tl == 0) A.nl[bb] = -1;
+        if (tl == 0) {
+            A.nl[bb] = -1;
+            A.fb_list[atomicAdd(A.fb_count, 1)] = (int32_t)bb;
+        }
         return;
     }
     const int32_t a = A.slot[b];
@@ -1175,6 +1236,7 @@ __global__ __launch_bounds__(256) void k_knn_bucket(KnnArgs A, int64_t base, int
 
 constexpr int kTeam = 16;                 // lanes per target in the team kernel (8 measured slower)
 
+constexpr int kFallbackGrid = 2048;       // workgroups of the fallback launch (they stride over its targets)
 constexpr int kLeavesPerStep = 2;          // leaves a team tests per step of its loop
 constexpr int kListLanes = 16;             // lanes per target in the leaf-list kernel (measured: 2, 4, 8, 32, 64 slower on the 10^6 halo)
 
@@ -1197,7 +1259,7 @@ void launch_batches_l(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipSt
                 k_knn_bucket<P, 128><<<xcd_grid(gt), 256, 0, s>>>(A, base, gt);
             else
                 k_knn_bucket<P, 144><<<xcd_grid(gt), 256, 0, s>>>(A, base, gt);
-            k_knn_team<P, E, M, TS, LPI, true><<<xcd_grid(gt), 256, 0, s>>>(A, base, gt);
+            k_knn_team<P, E, M, TS, LPI, true><<<kFallbackGrid, 256, 0, s>>>(A, base, 0);
         }
     }
 }
@@ -1222,6 +1284,7 @@ hipError_t launch_knn(sidm_ctx *c, int64_t n_active, int32_t *ngb, double *h)
     A.ngb = ngb; A.h = h; A.derr = c->derr;
     A.jsort = c->jsort;
     A.list = c->knn_list; A.nl = c->knn_nl; A.tb = c->knn_tb;
+    A.fb_list = c->knn_fb; A.fb_count = c->knn_fbn;
     A.lv = c->lv;
     A.n = c->n; A.k = c->cfg.n_ngb; A.box = c->cfg.box; A.batch = 0;
     A.xo = c->xo; A.yo = c->yo; A.zo = c->zo;

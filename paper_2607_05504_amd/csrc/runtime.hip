@@ -67,6 +67,8 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(knn_list, c->knn_batch * SIDM_KNN_LMAX, int32_t);
     ADD(jsort, NA * (int64_t)k, int32_t);
     ADD(knn_nl, c->knn_batch, int32_t);
+    ADD(knn_fb, c->knn_batch, int32_t);
+    ADD(knn_fbn, 1, int32_t);
     ADD(knn_tb, c->knn_batch, double);
     ADD(flag, N, int32_t);
     ADD(tlist, NA, int32_t); ADD(slot, NA, int32_t);

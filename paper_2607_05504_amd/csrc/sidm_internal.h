@@ -145,6 +145,8 @@ struct sidm_ctx {
     const int32_t *jsort_ngb;     // the ngb they match, NULL if none
     int jsort_knn;           // they are the last sidm_find_ngb's, for the current mapping
     int32_t *knn_nl;         // [knn_batch]
+    int32_t *knn_fb;         // [knn_batch] targets of a batch left to the root walk
+    int32_t *knn_fbn;        // [1] their number
     double *knn_tb;          // [knn_batch]
 
     // active set in Morton order
