@@ -853,27 +853,27 @@ void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
 }
 
 // ---------------------------------------------------------------------------
-// Kernel B': exact selection by a 16-lane team per target over sub-buckets
+// Kernel B': exact selection by one wavefront per target over sub-buckets
 // ---------------------------------------------------------------------------
-// The team takes its leaf list four leaves at a time: lane l tests sub-bucket
-// l % 4 of leaf l / 4 (SIDM_SUB particles, its own box) against the current
-// radius, and the kept sub-buckets' particles are tested two sub-buckets (16
-// particles, one per lane) a round, so that a particle is only tested when
-// its sub-bucket meets the sphere.  Those within the radius go to the team's
-// LDS list of CAP entries.  When a round might not fit, the list is cut as in
-// kernel B (K1-th smallest r^2 rounded up to FP32, found by bisection on
-// team-wide counts).  At the end each entry's place is its rank in
-// (r^2, ID, index) among the entries, found by comparing it with all of them;
-// a list longer than K1 + 16 is first thinned by the same bisection.
-// Targets whose list overflowed in the first kernel, or whose cut could not
-// make room (many equal r^2), are left to kernel B's root walk (nl set to -1).
+// The wavefront tests the sub-buckets of its target's leaf list (SIDM_SUB
+// particles each, their own boxes; 128 a pass) against the radius and lists
+// the kept ones in LDS.  Their particles are then tested kRound per lane a
+// round (8 lanes a sub-bucket, all positions of a round requested together);
+// those within the radius go to the target's LDS list as (r^2 rounded up to
+// FP32, index) in one 64-bit word.  When a round might not fit, the list is
+// cut: the radius becomes the K1-th smallest stored value, found by bisection
+// on wavefront-wide counts (ballots), and larger entries go.  At the end the
+// list is thinned the same way to at most 64 entries, each lane takes one,
+// recomputes its exact r^2, and places it by its rank in (r^2, ID, index)
+// among them.  Targets whose list overflowed in the first kernel, or whose
+// list cannot be cut (many equal r^2), are left to kernel B's root walk.
 constexpr int kSubPerLeaf = SIDM_LEAF / SIDM_SUB;
-constexpr int kRankMax = 48;
+constexpr int kKeepMax = 384;                 // kept sub-buckets per target (more: the root walk)
+constexpr int kRound = 4;                     // particles a lane tests per round
+constexpr int kHitCap = 64 * (kRound + 2);    // list entries per target
+constexpr int kHitQ = kHitCap / 64;           // list entries per lane
 // dword 3 of a raw buffer resource on gfx9-family parts (32-bit data format)
 constexpr int kRsrcWord3 = 0x00020000;
-constexpr int kKeepMax = 192;         // kept sub-buckets per target (more: the root walk)
-constexpr int kSubLoads = 4;          // sub-bucket boxes a lane requests at a time
-constexpr int kPairs = 4;             // pairs of sub-buckets a round
 
 template <bool PERIODIC>
 __device__ __forceinline__ double sub_gap2(const float4 &lo, const float4 &hi, double px, double py,
@@ -886,147 +886,6 @@ __device__ __forceinline__ double sub_gap2(const float4 &lo, const float4 &hi, d
     return lo.x <= hi.x ? g2 : INFINITY;
 }
 
-// Team-wide K1-th smallest of the FP32 values f (rounded up from r^2) of the
-// team's E-per-lane entries (entry q * TS + tl, those at or past count are
-// +inf): the smallest FP32 value with at least K1 values at or below it,
-// bisected on bit patterns until at most `enough` values remain at or below
-// it (or the bracket closes).  Returns the bound; c_out = values at or below.
-template <int E, int TS>
-__device__ __forceinline__ float team_select(const float (&f)[E], int count, int K1, int enough,
-                                             int tl, int &c_out)
-{
-    uint32_t lo = 0xffffffffu, hi = 0u;
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        if (q * TS + tl < count) {
-            const uint32_t bv = __float_as_uint(f[q]);
-            lo = bv < lo ? bv : lo;
-            hi = bv > hi ? bv : hi;
-        }
-    }
-#pragma unroll
-    for (int off = 1; off < TS; off <<= 1) {
-        const uint32_t ol = (uint32_t)__shfl_xor((int)lo, off);
-        const uint32_t oh = (uint32_t)__shfl_xor((int)hi, off);
-        lo = ol < lo ? ol : lo;
-        hi = oh > hi ? oh : hi;
-    }
-    int c_hi = count;
-    for (int it = 0; it < 32 && lo < hi && c_hi > enough; ++it) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        const float fm = __uint_as_float(mid);
-        int c = 0;
-#pragma unroll
-        for (int q = 0; q < E; ++q) c += f[q] <= fm;
-#pragma unroll
-        for (int off = 1; off < TS; off <<= 1) c += __shfl_xor(c, off);
-        if (c >= K1) { hi = mid; c_hi = c; } else { lo = mid + 1; }
-    }
-    c_out = c_hi;
-    return __uint_as_float(hi);
-}
-
-// Keeps the entries whose FP32 value is at most Tf, in order, at the front
-// of the team's list; returns the new count.
-template <int E, int TS>
-__device__ __forceinline__ int team_compact(double *L_r2, int32_t *L_j, const float (&f)[E],
-                                            float Tf, int count, int tl)
-{
-    double r[E];
-    int32_t jj[E];
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int e = q * TS + tl;
-        r[q] = e < count ? L_r2[e] : INFINITY;
-        jj[q] = e < count ? L_j[e] : -1;
-    }
-    int total = 0;
-    wave_sync();
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const bool keep = q * TS + tl < count && f[q] <= Tf;
-        int pre = keep;                        // inclusive prefix over the team
-#pragma unroll
-        for (int off = 1; off < TS; off <<= 1) {
-            const int o = __shfl_up(pre, off, TS);
-            if (tl >= off) pre += o;
-        }
-        if (keep) { L_r2[total + pre - 1] = r[q]; L_j[total + pre - 1] = jj[q]; }
-        total += __shfl(pre, TS - 1, TS);
-    }
-    wave_sync();
-    return total;
-}
-
-// Places each of the team's count entries by its rank in (r^2, ID, index)
-// among them (IDs read only if some r^2 are equal): rank < k goes to row
-// place rank, rank k gives h.  RQ entries per lane (entry q * TS + tl).
-template <int RQ, int TS>
-__device__ __forceinline__ void team_rank_out(const KnnArgs &A, const double *L_r2, const int32_t *L_j,
-                                              uint32_t *L_id, int count, int wteam, int tl,
-                                              int32_t *out, int32_t *srt, int32_t a)
-{
-    double re[RQ];
-    int rank[RQ];
-#pragma unroll
-    for (int q = 0; q < RQ; ++q) {
-        const int e = q * TS + tl;
-        re[q] = e < count ? L_r2[e] : INFINITY;
-        rank[q] = 0;
-    }
-    for (int f2 = 0; f2 < count; ++f2) {
-        const double rf = L_r2[f2];
-#pragma unroll
-        for (int q = 0; q < RQ; ++q) rank[q] += rf < re[q];
-    }
-    // equal r^2 share a rank: each entry claims place rank, and a place
-    // claimed twice shows a tie
-#pragma unroll
-    for (int q = 0; q < RQ; ++q)
-        if (q * TS + tl < count) L_id[rank[q]] = (uint32_t)(q * TS + tl);
-    wave_sync();
-    bool tie = false;
-#pragma unroll
-    for (int q = 0; q < RQ; ++q)
-        if (q * TS + tl < count) tie = tie || L_id[rank[q]] != (uint32_t)(q * TS + tl);
-    wave_sync();
-    if (((__ballot(tie) >> (wteam * TS)) & ((1ull << TS) - 1ull)) != 0ull) {
-        for (int e = tl; e < count; e += TS) L_id[e] = A.ids[L_j[e]];
-        wave_sync();
-#pragma unroll
-        for (int q = 0; q < RQ; ++q) {
-            const int e = q * TS + tl;
-            if (e < count) {
-                const uint32_t ide = L_id[e];
-                const int32_t je = L_j[e];
-                for (int f2 = 0; f2 < count; ++f2) {
-                    if (L_r2[f2] != re[q] || f2 == e) continue;
-                    const uint32_t idf = L_id[f2];
-                    rank[q] += idf < ide || (idf == ide && L_j[f2] < je);
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < RQ; ++q) {
-        const int e = q * TS + tl;
-        if (e < count) {
-            if (rank[q] < A.k) {
-                const int32_t j = L_j[e];
-                out[rank[q]] = A.perm[j];
-                srt[rank[q]] = j;
-            } else if (rank[q] == A.k) {
-                A.h[a] = sqrt(re[q]);
-            }
-        }
-    }
-}
-
-// The scan of kernel B': the list's sub-buckets against the sphere, then
-// their particles into the team's list.  PER: with periodic images; a target
-// whose padded sphere lies inside the box scans without them (no image of a
-// particle within its radius can be nearer, and the separations of those
-// within it round the same), which is bit-identical and cheaper.
 // positions by 32-bit byte offsets into buffer resources (one address for the
 // three loads), for arrays under 4 GiB
 struct PosRsrc {
@@ -1036,202 +895,340 @@ __device__ __forceinline__ double buf_ld64(__amdgpu_buffer_rsrc_t r, uint32_t of
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
-
-template <bool PER, bool BUF, int CAP>
-__device__ __forceinline__ bool bucket_scan(const KnnArgs &A, const PosRsrc &pr, int32_t i, double px,
-                                            double py, double pz,
-                                            const int32_t *lst, int nl, uint32_t *K, double *L_r2,
-                                            int32_t *L_j, int wteam, int tl, double &T, int &count)
+template <bool BUF>
+__device__ __forceinline__ void load_pos(const KnnArgs &A, const PosRsrc &pr, int32_t j, double &x,
+                                         double &y, double &z)
 {
-    constexpr int TS = 16;
-    constexpr int E = CAP / TS;
+    if constexpr (BUF) {
+        const uint32_t off = (uint32_t)j * 8u;
+        x = buf_ld64(pr.x, off); y = buf_ld64(pr.y, off); z = buf_ld64(pr.z, off);
+    } else {
+        x = A.xs[j]; y = A.ys[j]; z = A.zs[j];
+    }
+}
+
+// lanes below this one with their bit set in m
+__device__ __forceinline__ int lanes_below(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, off);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, off);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// K1-th smallest of the FP32 bit patterns f (values >= 0, so the patterns
+// order as the values) of the wavefront's entries q * 64 + lane < count: the
+// smallest pattern with at least K1 entries at or below it, bisected until at
+// most `enough` entries remain at or below it or the bracket closes.
+// c_out = entries at or below the result.
+template <int E>
+__device__ __forceinline__ uint32_t wave_select(const uint32_t (&f)[E], int count, int K1, int enough,
+                                                int &c_out)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t lo = 0xffffffffu, hi = 0u;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        if (q * 64 + lane < count) {
+            lo = f[q] < lo ? f[q] : lo;
+            hi = f[q] > hi ? f[q] : hi;
+        }
+    }
+    lo = wave_min_u32(lo);
+    hi = wave_max_u32(hi);
+    int c_hi = count;
+    for (int it = 0; it < 32 && lo < hi && c_hi > enough; ++it) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        int c = 0;
+#pragma unroll
+        for (int q = 0; q < E; ++q) c += __popcll(__ballot(q * 64 + lane < count && f[q] <= mid));
+        if (c >= K1) { hi = mid; c_hi = c; } else { lo = mid + 1; }
+    }
+    c_out = c_hi;
+    return hi;
+}
+
+// Keeps the entries whose pattern is at most Tf, in order, at the front of
+// the list; returns their number.
+template <int E>
+__device__ __forceinline__ int wave_compact(uint64_t *L, const uint32_t (&f)[E], uint32_t Tf, int count)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t v[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[q] = q * 64 + lane < count ? L[q * 64 + lane] : 0ull;
+    wave_sync();
+    int total = 0;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const bool keep = q * 64 + lane < count && f[q] <= Tf;
+        const uint64_t m = __ballot(keep);
+        if (keep) L[total + lanes_below(m)] = v[q];
+        total += __popcll(m);
+    }
+    wave_sync();
+    return total;
+}
+
+__device__ __forceinline__ uint64_t hit_word(double r2, int32_t j)
+{
+    return ((uint64_t)__float_as_uint(__double2float_ru(r2)) << 32) | (uint32_t)j;
+}
+
+// The scan: returns false if the target must be left to the root walk.
+// PER: with periodic images; a target whose padded sphere lies inside the box
+// scans without them (no image of a particle within its radius can be nearer,
+// and the separations of those within it round the same: bit-identical).
+template <bool PER, bool BUF>
+__device__ __forceinline__ bool wave_scan(const KnnArgs &A, const PosRsrc &pr, int32_t i, double px,
+                                          double py, double pz, const int32_t *lst, int nl, uint32_t *K,
+                                          uint64_t *L, double &T, int &count)
+{
+    const int lane = threadIdx.x & 63;
     const double box = A.box;
     const int64_t n = A.n;
     const int K1 = A.k + 1;
-    const uint64_t below = (tl == 0) ? 0ull : ((1ull << tl) - 1ull);
-    bool gave_up = false;
-    // 1. the list's sub-buckets that meet the sphere, into the team's LDS
-    // list K (boxes requested kSubLoads a lane at a time)
+    // 1. the kept sub-buckets
     int nk = 0;
     const int nsb = nl * kSubPerLeaf;
-    for (int s0 = 0; s0 < nsb; s0 += TS * kSubLoads) {
-        int32_t sbi[kSubLoads];
-        float4 blo[kSubLoads], bhi[kSubLoads];
+    for (int s0 = 0; s0 < nsb; s0 += 128) {
+        int32_t sbi[2];
+        float4 blo[2], bhi[2];
 #pragma unroll
-        for (int u = 0; u < kSubLoads; ++u) {
-            const int t = s0 + u * TS + tl;
+        for (int u = 0; u < 2; ++u) {
+            const int t = s0 + u * 64 + lane;
             const int32_t leaf = t < nsb ? lst[t / kSubPerLeaf] : -1;
             sbi[u] = leaf >= 0 ? leaf * kSubPerLeaf + t % kSubPerLeaf : -1;
         }
 #pragma unroll
-        for (int u = 0; u < kSubLoads; ++u) {
+        for (int u = 0; u < 2; ++u) {
             const int64_t q = sbi[u] >= 0 ? sbi[u] : 0;
             blo[u] = A.sbox[2 * q];
             bhi[u] = A.sbox[2 * q + 1];
         }
 #pragma unroll
-        for (int u = 0; u < kSubLoads; ++u) {
+        for (int u = 0; u < 2; ++u) {
             const bool keep = sbi[u] >= 0 && sub_gap2<PER>(blo[u], bhi[u], px, py, pz, box) <= T;
-            const uint32_t km = (uint32_t)(__ballot(keep) >> (wteam * TS)) & 0xffffu;
-            if (keep) {
-                const int pos = nk + __popc(km & (uint32_t)below);
-                if (pos < kKeepMax) K[pos] = (uint32_t)sbi[u];
-            }
-            nk += __popc(km);
+            const uint64_t m = __ballot(keep);
+            const int pos = nk + lanes_below(m);
+            if (keep && pos < kKeepMax) K[pos] = (uint32_t)sbi[u];
+            nk += __popcll(m);
         }
     }
-    gave_up = nk > kKeepMax;
+    if (nk > kKeepMax) return false;
     wave_sync();
-    // 2. their particles, kPairs pairs of sub-buckets a round (lanes 0-7 the
-    // first of a pair, 8-15 the second), all positions of a round requested
-    // together
-    for (int k0 = 0; k0 < nk && !gave_up; k0 += 2 * kPairs) {
-        double qx[kPairs], qy[kPairs], qz[kPairs];
-        int64_t jv[kPairs];
-        bool ok[kPairs];
+    // 2. their particles, kRound per lane a round
+    for (int k0 = 0; k0 < nk; k0 += 8 * kRound) {
+        double qx[kRound], qy[kRound], qz[kRound];
+        int32_t jv[kRound];
+        bool ok[kRound];
 #pragma unroll
-        for (int u = 0; u < kPairs; ++u) {
-            const int e = k0 + 2 * u + (tl >= SIDM_SUB ? 1 : 0);
-            const int64_t j = e < nk ? (int64_t)K[e] * SIDM_SUB + tl % SIDM_SUB : -1;
+        for (int u = 0; u < kRound; ++u) {
+            const int e = k0 + u * 8 + (lane >> 3);
+            const int32_t j = e < nk ? (int32_t)K[e] * SIDM_SUB + (lane & 7) : -1;
             ok[u] = j >= 0 && j < n && j != i;
             jv[u] = j;
-            const int64_t jc = ok[u] ? j : i;
-            if constexpr (BUF) {
-                const uint32_t off = (uint32_t)jc * 8u;
-                qx[u] = buf_ld64(pr.x, off); qy[u] = buf_ld64(pr.y, off); qz[u] = buf_ld64(pr.z, off);
-            } else {
-                qx[u] = A.xs[jc]; qy[u] = A.ys[jc]; qz[u] = A.zs[jc];
-            }
+            load_pos<BUF>(A, pr, ok[u] ? j : i, qx[u], qy[u], qz[u]);
         }
-        double r2[kPairs];
-        uint32_t hm[kPairs];
+        double r2[kRound];
+        bool hit[kRound];
         int nh = 0;
 #pragma unroll
-        for (int u = 0; u < kPairs; ++u) {
+        for (int u = 0; u < kRound; ++u) {
             r2[u] = sep2_sel<PER>(px, py, pz, qx[u], qy[u], qz[u], box);
-            hm[u] = (uint32_t)(__ballot(ok[u] && r2[u] <= T) >> (wteam * TS)) & 0xffffu;
-            nh += __popc(hm[u]);
+            hit[u] = ok[u] && r2[u] <= T;
+            nh += __popcll(__ballot(hit[u]));
         }
-        if (count + nh > CAP) {
-            // cut: the radius becomes the K1-th smallest r^2 rounded up
-            float f[E];
+        if (count + nh > kHitCap) {
+            // cut: the radius becomes the K1-th smallest stored value
+            uint32_t f[kHitQ];
 #pragma unroll
-            for (int q = 0; q < E; ++q) {
-                const int e = q * TS + tl;
-                f[q] = e < count ? __double2float_ru(L_r2[e]) : INFINITY;
-            }
+            for (int q = 0; q < kHitQ; ++q)
+                f[q] = q * 64 + lane < count ? (uint32_t)(L[q * 64 + lane] >> 32) : 0xffffffffu;
             int c_hi;
-            const float Tf = team_select<E, TS>(f, count, K1, K1 + 8, tl, c_hi);
-            if (c_hi > CAP - kPairs * TS) {
-                gave_up = true;                   // too many equal values to make room
-                break;
-            }
-            count = team_compact<E, TS>(L_r2, L_j, f, Tf, count, tl);
-            T = fmin(T, (double)Tf);
+            const uint32_t Tf = wave_select<kHitQ>(f, count, K1, K1 + 8, c_hi);
+            if (c_hi > kHitCap - 64 * kRound) return false;   // too many equal values
+            count = wave_compact<kHitQ>(L, f, Tf, count);
+            T = fmin(T, (double)__uint_as_float(Tf));
 #pragma unroll
-            for (int u = 0; u < kPairs; ++u)
-                hm[u] = (uint32_t)(__ballot(ok[u] && r2[u] <= T) >> (wteam * TS)) & 0xffffu;
+            for (int u = 0; u < kRound; ++u) hit[u] = ok[u] && r2[u] <= T;
         }
 #pragma unroll
-        for (int u = 0; u < kPairs; ++u) {
-            if ((hm[u] >> tl) & 1u) {
-                const int pos = count + __popc(hm[u] & (uint32_t)below);
-                L_r2[pos] = r2[u];
-                L_j[pos] = (int32_t)jv[u];
-            }
-            count += __popc(hm[u]);
+        for (int u = 0; u < kRound; ++u) {
+            const uint64_t m = __ballot(hit[u]);
+            if (hit[u]) L[count + lanes_below(m)] = hit_word(r2[u], jv[u]);
+            count += __popcll(m);
         }
     }
-    return gave_up;
+    return true;
 }
 
-template <bool PERIODIC, int CAP>
-__global__ __launch_bounds__(256) void k_knn_bucket(KnnArgs A, int64_t base, int64_t nblk)
+// Each lane's entries (RQ each, entry q * 64 + lane < count) placed by rank in
+// (exact r^2, ID, index): rank < k to row place rank, rank k gives h.
+template <bool PER, bool BUF, int RQ>
+__device__ __forceinline__ void wave_rank_out(const KnnArgs &A, const PosRsrc &pr, double px, double py,
+                                              double pz, const uint64_t *L, double *R2, uint32_t *S,
+                                              int count, int32_t *out, int32_t *srt, int32_t a)
 {
-    constexpr int TS = 16;                    // lanes per target
-    constexpr int NT = 256 / TS;              // teams per workgroup
-    constexpr int E = CAP / TS;               // list entries per lane
-    constexpr int CP = CAP + 2;               // padded team stride (teams of a wavefront in other banks)
-    static_assert(CAP % TS == 0 && CAP >= kRankMax + kPairs * TS, "list capacity");
-    __shared__ double s_r2[NT][CP];
-    __shared__ int32_t s_j[NT][CP];
-    // the kept sub-buckets during the scan, the IDs of the entries at the end
-    __shared__ uint32_t s_aux[NT][kKeepMax > CP ? kKeepMax : CP];
+    const int lane = threadIdx.x & 63;
+    double re[RQ];
+    int32_t je[RQ];
+    int rank[RQ];
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+        const int e = q * 64 + lane;
+        je[q] = e < count ? (int32_t)(uint32_t)L[e] : -1;
+        double x = 0.0, y = 0.0, z = 0.0;
+        if (je[q] >= 0) load_pos<BUF>(A, pr, je[q], x, y, z);
+        re[q] = je[q] >= 0 ? sep2_sel<PER>(px, py, pz, x, y, z, A.box) : INFINITY;
+        if (e < count) R2[e] = re[q];
+        rank[q] = 0;
+    }
+    wave_sync();
+    for (int f2 = 0; f2 < count; ++f2) {
+        const double rf = R2[f2];
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) rank[q] += rf < re[q];
+    }
+    // equal r^2 share a rank: each entry claims place rank, and a place
+    // claimed twice shows a tie
+#pragma unroll
+    for (int q = 0; q < RQ; ++q)
+        if (je[q] >= 0) S[rank[q]] = (uint32_t)(q * 64 + lane);
+    wave_sync();
+    bool tie = false;
+#pragma unroll
+    for (int q = 0; q < RQ; ++q)
+        if (je[q] >= 0) tie = tie || S[rank[q]] != (uint32_t)(q * 64 + lane);
+    wave_sync();
+    if (__any(tie)) {
+        uint32_t ide[RQ];
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) {
+            ide[q] = je[q] >= 0 ? A.ids[je[q]] : 0u;
+            if (je[q] >= 0) S[q * 64 + lane] = ide[q];
+        }
+        wave_sync();
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) {
+            if (je[q] < 0) continue;
+            const int e = q * 64 + lane;
+            for (int f2 = 0; f2 < count; ++f2) {
+                if (R2[f2] != re[q] || f2 == e) continue;
+                const uint32_t idf = S[f2];
+                const int32_t jf = (int32_t)(uint32_t)L[f2];
+                rank[q] += idf < ide[q] || (idf == ide[q] && jf < je[q]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+        if (je[q] < 0) continue;
+        if (rank[q] < A.k) {
+            out[rank[q]] = A.perm[je[q]];
+            srt[rank[q]] = je[q];
+        } else if (rank[q] == A.k) {
+            A.h[a] = sqrt(re[q]);
+        }
+    }
+}
 
-    const int team = threadIdx.x / TS, tl = threadIdx.x % TS;
-    const int wteam = team % (64 / TS);
+template <bool PERIODIC, bool BUF>
+__device__ __forceinline__ void wave_target(const KnnArgs &A, int64_t base, int64_t bb, uint32_t *K,
+                                            uint64_t *L, double *R2)
+{
+    const int lane = threadIdx.x & 63;
     const int nt = *A.nt_dev;
-    const int64_t blk = xcd_block(nblk);
-    if (blk < 0) return;
-    const int64_t bb = blk * NT + team;
     const int64_t b = base + bb;
-    if (!(b < nt && bb < A.batch)) return;    // whole team
+    if (!(b < nt && bb < A.batch)) return;
     const int nl = A.nl[bb];
     if (nl < 0) {                             // kernel B walks from the root
-        if (tl == 0) A.fb_list[atomicAdd(A.fb_count, 1)] = (int32_t)bb;
+        if (lane == 0) A.fb_list[atomicAdd(A.fb_count, 1)] = (int32_t)bb;
         return;
     }
     const int32_t i = A.tlist[b];
     const double px = A.xs[i], py = A.ys[i], pz = A.zs[i];
     const double box = A.box;
     const int64_t n = A.n;
-    const int K1 = A.k + 1;
-    double *L_r2 = s_r2[team];
-    int32_t *L_j = s_j[team];
-    const uint64_t below = (tl == 0) ? 0ull : ((1ull << tl) - 1ull);
+    PosRsrc pr;
+    const int nbytes = BUF ? (int)(uint32_t)(n * 8) : 0;
+    pr.x = __builtin_amdgcn_make_buffer_rsrc((void *)A.xs, (short)0, nbytes, kRsrcWord3);
+    pr.y = __builtin_amdgcn_make_buffer_rsrc((void *)A.ys, (short)0, nbytes, kRsrcWord3);
+    pr.z = __builtin_amdgcn_make_buffer_rsrc((void *)A.zs, (short)0, nbytes, kRsrcWord3);
     const int32_t *lst = A.list + bb * SIDM_KNN_LMAX;
     double T = A.tb[bb];
     int count = 0;
-    bool gave_up;
-    {
-        // padded like the first kernel's sphere: far beyond rounding
-        const double R = sqrt(T) * (1.0 + 1e-9) + (fabs(px) + fabs(py) + fabs(pz) + box) * 1e-14;
-        const bool inside = px - R > 0.0 && px + R < box && py - R > 0.0 && py + R < box &&
-                            pz - R > 0.0 && pz + R < box;
-        const bool buf = (uint64_t)n * 8u <= 0xffffffffull;
-        PosRsrc pr;
-        const int nb = buf ? (int)(uint32_t)(n * 8) : 0;
-        pr.x = __builtin_amdgcn_make_buffer_rsrc((void *)A.xs, (short)0, nb, kRsrcWord3);
-        pr.y = __builtin_amdgcn_make_buffer_rsrc((void *)A.ys, (short)0, nb, kRsrcWord3);
-        pr.z = __builtin_amdgcn_make_buffer_rsrc((void *)A.zs, (short)0, nb, kRsrcWord3);
-        uint32_t *K = s_aux[team];
-        if (PERIODIC && !inside)
-            gave_up = buf ? bucket_scan<PERIODIC, true, CAP>(A, pr, i, px, py, pz, lst, nl, K, L_r2, L_j, wteam, tl, T, count)
-                          : bucket_scan<PERIODIC, false, CAP>(A, pr, i, px, py, pz, lst, nl, K, L_r2, L_j, wteam, tl, T, count);
-        else
-            gave_up = buf ? bucket_scan<false, true, CAP>(A, pr, i, px, py, pz, lst, nl, K, L_r2, L_j, wteam, tl, T, count)
-                          : bucket_scan<false, false, CAP>(A, pr, i, px, py, pz, lst, nl, K, L_r2, L_j, wteam, tl, T, count);
-    }
-    if (gave_up) {
-        if (tl == 0) {
+    // padded like the first kernel's sphere: far beyond rounding
+    const double R = sqrt(T) * (1.0 + 1e-9) + (fabs(px) + fabs(py) + fabs(pz) + box) * 1e-14;
+    const bool inside = px - R > 0.0 && px + R < box && py - R > 0.0 && py + R < box && pz - R > 0.0 &&
+                        pz + R < box;
+    const bool per = PERIODIC && !inside;
+    const bool done = per ? wave_scan<PERIODIC, BUF>(A, pr, i, px, py, pz, lst, nl, K, L, T, count)
+                          : wave_scan<false, BUF>(A, pr, i, px, py, pz, lst, nl, K, L, T, count);
+    if (!done) {
+        if (lane == 0) {
             A.nl[bb] = -1;
             A.fb_list[atomicAdd(A.fb_count, 1)] = (int32_t)bb;
         }
         return;
     }
     const int32_t a = A.slot[b];
+    const int K1 = A.k + 1;
     if (count < K1) {                          // cannot happen: T bounds K1 window particles
-        if (tl == 0) atomicOr(A.derr, DERR_COUNT);
+        if (lane == 0) atomicOr(A.derr, DERR_COUNT);
         return;
     }
     wave_sync();
-    if (count > K1 + 16) {
-        float f[E];
+    if (count > 64) {
+        uint32_t f[kHitQ];
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
-            const int e = q * TS + tl;
-            f[q] = e < count ? __double2float_ru(L_r2[e]) : INFINITY;
-        }
+        for (int q = 0; q < kHitQ; ++q)
+            f[q] = q * 64 + lane < count ? (uint32_t)(L[q * 64 + lane] >> 32) : 0xffffffffu;
         int c_hi;
-        const float Tf = team_select<E, TS>(f, count, K1, K1 + 8, tl, c_hi);
-        count = team_compact<E, TS>(L_r2, L_j, f, Tf, count, tl);
+        const uint32_t Tf = wave_select<kHitQ>(f, count, K1, 64, c_hi);
+        count = wave_compact<kHitQ>(L, f, Tf, count);
     }
     int32_t *out = A.ngb + (int64_t)a * A.k;
     int32_t *srt = A.jsort + b * A.k;
-    if (count <= kRankMax)
-        team_rank_out<(kRankMax + TS - 1) / TS, TS>(A, L_r2, L_j, s_aux[team], count, wteam, tl, out, srt, a);
+    uint32_t *S = K;                           // the kept list is done with
+    if (count <= 64) {
+        if (per) wave_rank_out<PERIODIC, BUF, 1>(A, pr, px, py, pz, L, R2, S, count, out, srt, a);
+        else wave_rank_out<false, BUF, 1>(A, pr, px, py, pz, L, R2, S, count, out, srt, a);
+    } else {
+        if (per) wave_rank_out<PERIODIC, BUF, kHitQ>(A, pr, px, py, pz, L, R2, S, count, out, srt, a);
+        else wave_rank_out<false, BUF, kHitQ>(A, pr, px, py, pz, L, R2, S, count, out, srt, a);
+    }
+}
+
+template <bool PERIODIC>
+__global__ __launch_bounds__(256) void k_knn_bucket(KnnArgs A, int64_t base, int64_t nblk)
+{
+    constexpr int NW = 4;                     // wavefronts (targets) per workgroup
+    static_assert(kKeepMax >= kHitCap, "the kept list's space holds the rank places");
+    __shared__ uint32_t s_keep[NW][kKeepMax];
+    __shared__ uint64_t s_hit[NW][kHitCap];
+    __shared__ double s_r2[NW][kHitCap];
+    const int w = threadIdx.x >> 6;
+    const int64_t blk = xcd_block(nblk);
+    if (blk < 0) return;
+    const int64_t bb = blk * NW + w;
+    if ((uint64_t)A.n * 8u <= 0xffffffffull)
+        wave_target<PERIODIC, true>(A, base, bb, s_keep[w], s_hit[w], s_r2[w]);
     else
-        team_rank_out<E, TS>(A, L_r2, L_j, s_aux[team], count, wteam, tl, out, srt, a);
+        wave_target<PERIODIC, false>(A, base, bb, s_keep[w], s_hit[w], s_r2[w]);
 }
 
 constexpr int kTeam = 16;                 // lanes per target in the team kernel (8 measured slower)
@@ -1253,12 +1250,8 @@ void launch_batches_l(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipSt
         if constexpr (M) {
             k_knn_team<P, E, M, TS, LPI, false><<<xcd_grid(gt), 256, 0, s>>>(A, base, gt);
         } else {
-            // room after a cut (K1 + 8 entries at most, unless r^2 repeat)
-            // for the kPairs * 16 particles of a round
-            if (A.k + 1 + 8 + kPairs * 16 <= 128)
-                k_knn_bucket<P, 128><<<xcd_grid(gt), 256, 0, s>>>(A, base, gt);
-            else
-                k_knn_bucket<P, 144><<<xcd_grid(gt), 256, 0, s>>>(A, base, gt);
+            const int64_t gw = (A.batch + 3) / 4;
+            k_knn_bucket<P><<<xcd_grid(gw), 256, 0, s>>>(A, base, gw);
             k_knn_team<P, E, M, TS, LPI, true><<<kFallbackGrid, 256, 0, s>>>(A, base, 0);
         }
     }
