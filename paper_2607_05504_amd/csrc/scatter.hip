@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
     unsigned long long maxp = 0, n_fl = 0, n_ge1 = 0, n_acc = 0, n_rc = 0, n_cd = 0;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
-    for (int64_t c0 = blockIdx.x * (int64_t)blockDim.x; c0 < total;
+    for (int64_t c0 = xcd_stride_block() * (int64_t)blockDim.x; c0 < total;
          c0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = c0 + threadIdx.x;
         bool live = c < total;
@@ -890,7 +890,7 @@ __global__ __launch_bounds__(kBlock) void k_check(StepArgs A)
     __shared__ int32_t q[(kScanU + 1) * kBlock];
     __shared__ int qn;
     if (A.ctl[CTL_DONE]) return;
-    check_scan<PERIODIC, OVERLAP>(A, blockIdx.x * (int64_t)kBlock * kScanU,
+    check_scan<PERIODIC, OVERLAP>(A, xcd_stride_block() * (int64_t)kBlock * kScanU,
                                   (int64_t)gridDim.x * kBlock * kScanU, q, qn);
 }
 
@@ -1167,7 +1167,7 @@ __global__ __launch_bounds__(kBlock) void k_timestep_group(StepArgs A, double c_
 {
     const int64_t nt = *A.nt_dev;
     const int64_t total = nt * A.k;
-    for (int64_t c0 = blockIdx.x * (int64_t)blockDim.x; c0 < total;
+    for (int64_t c0 = xcd_stride_block() * (int64_t)blockDim.x; c0 < total;
          c0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = c0 + threadIdx.x;
         const bool in = c < total;
@@ -1275,11 +1275,12 @@ StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const dou
     return A;
 }
 
+// workgroups for n items, at most cap, a multiple of 8 (see xcd_stride_block)
 int grid_for(int64_t n, int cap = 8192)
 {
     int64_t g = (n + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
-    return (int)(g > cap ? cap : g);
+    return grid8(g > cap ? cap : g);
 }
 
 // The step's rows in the tree's order: jsort[b * k + s] = sorted index of
@@ -1291,7 +1292,7 @@ int grid_for(int64_t n, int cap = 8192)
 __global__ __launch_bounds__(kBlock) void k_rows(StepArgs A, int have)
 {
     const int64_t total = (int64_t)(*A.nt_dev) * A.stride;
-    for (int64_t c = blockIdx.x * (int64_t)kBlock + threadIdx.x; c < total;
+    for (int64_t c = xcd_stride_block() * (int64_t)kBlock + threadIdx.x; c < total;
          c += (int64_t)gridDim.x * kBlock) {
         const int64_t b = total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)A.stride) : c / A.stride;
         const int s = (int)(c - b * A.stride);
@@ -1318,7 +1319,7 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
     // the candidates
     int64_t ge = total / 2048;
     ge = ge > 8192 ? 8192 : ge;
-    const int geval = ge > kEvalGrid ? (int)ge : grid_for(total, kEvalGrid);
+    const int geval = ge > kEvalGrid ? grid8(ge) : grid_for(total, kEvalGrid);
     k_eval<P, M, O><<<geval, kBlock, 0, s>>>(A);
     phase_end(c, PH_EVAL);
     const int g = grid_for(A.cap_acc < total ? A.cap_acc : total, 2048);

@@ -286,6 +286,20 @@ __device__ __forceinline__ int64_t xcd_block(int64_t g)
     return logical < g ? logical : -1;
 }
 
+// Grid-stride loops: the logical block of this workgroup, such that the
+// workgroups of one XCD (dealt b % 8) take consecutive blocks of each stride
+// and the rows they read stay in that XCD's L2.  gridDim.x is a multiple of 8
+// (grid8 on the host).
+__device__ __forceinline__ int64_t xcd_stride_block()
+{
+    const int64_t b = blockIdx.x, per = gridDim.x / SIDM_XCDS;
+    return (b % SIDM_XCDS) * per + b / SIDM_XCDS;
+}
+inline int grid8(int64_t g)
+{
+    return (int)((g + SIDM_XCDS - 1) / SIDM_XCDS * SIDM_XCDS);
+}
+
 // Cubic spline kernel W_CS(r, h) with support radius h.
 __device__ __forceinline__ double cubic_spline(double r, double h)
 {
