@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from workloads import XSEC_YUKAWA
 
 pytestmark = pytest.mark.gpu
 
@@ -62,9 +63,9 @@ def test_mono_speed_box_thermalises():
           f"E1/E0 {e_mid / e0:.15f} <w>_late {wmean:.4f} (MB {4 / math.sqrt(3 * math.pi):.4f}) "
           f"sd {v1.std():.4f}", flush=True)
     # first steps (still mono-speed): each particle takes part in s scatters
-    # on average, two per event.  Accepted candidates are re-evaluated after
-    # earlier kicks of the step while step-start rejections stand, which
-    # lowers the count by about s/4 relative (0.5% here; 4% at s = 0.2)
+    # on average, two per event (every candidate is decided at its turn with
+    # the velocities of that moment, so kicks earlier in the step change the
+    # rate only at second order in s)
     expect0 = s * n / 2.0
     first = events[:10].mean()
     assert abs(first - expect0) < 0.03 * expect0, (first, expect0)
@@ -126,3 +127,167 @@ def test_beam_through_lattice():
     scattered = ~((v[0, n_t:] == 1.0) & (v[1, n_t:] == 0.0))
     cth = v[0, n_t:][scattered] / speed[scattered]
     assert sps.kstest(cth, sps.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
+
+
+# --- Yukawa-like cross-section, the timestep criterion, the overlap estimator
+# (the paper's sec. 5.2 and its appendix on the overlap kernel) ---------------
+
+def _yukawa_w(w, w0):
+    return w / (1.0 + (w / w0) ** 2) ** 2
+
+
+def _mono_mean(f):
+    """<f(w)> over pairs of unit-speed isotropic velocities: w^2 = 2 - 2 cos
+    theta with cos theta uniform, so w has density w / 2 on [0, 2]."""
+    w = np.linspace(0.0, 2.0, 200001)
+    return float(np.trapezoid(f(w) * w / 2.0, w))
+
+
+def _maxwell_mean(f, sigma_1d):
+    """<f(w)> over pairs from a Maxwellian of 1D dispersion sigma_1d (relative
+    velocity Maxwellian with 1D dispersion sqrt(2) sigma_1d)."""
+    s = math.sqrt(2.0) * sigma_1d
+    w = np.linspace(0.0, 14.0 * s, 400001)
+    pdf = math.sqrt(2.0 / math.pi) * w * w / s ** 3 * np.exp(-w * w / (2.0 * s * s))
+    return float(np.trapezoid(f(w) * pdf, w))
+
+
+def _run_box(w, steps, drift, overlap=False, max_ngb=448):
+    """steps of the whole path with a free drift between them; returns the
+    events per step and the velocities at the start and the end."""
+    import torch
+    from paper_2607_05504_amd import Context, EST_OVERLAP, runner
+    ds = runner.upload(w, "cuda")
+    if overlap:
+        ctx = Context(runner.config_for(w, estimator=EST_OVERLAP), w.n, w.n)
+        out = runner.alloc_overlap(ds, w.n_ngb, max_ngb)
+    else:
+        ctx = Context(runner.config_for(w), w.n, w.n_active)
+        out = runner.alloc_out(ds, w.n_ngb)
+    v = lambda: np.stack([ds.vx.cpu().numpy(), ds.vy.cpu().numpy(), ds.vz.cpu().numpy()])
+    v0 = v()
+    events = []
+    for t in range(steps):
+        if overlap:
+            runner.run_overlap_step(ctx, ds, out, w.seed, t)
+        else:
+            runner.run_step(ctx, ds, out, w.seed, t)
+        ctx.drift(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, drift)
+        st = ctx.sync()
+        assert st["error"] == 0, st
+        events.append(st["n_events"])
+    v1 = v()
+    ctx.close()
+    torch.cuda.synchronize()
+    return np.array(events, dtype=np.float64), v0, v1
+
+
+def _relaxed(v0, v1, mass, sigma_1d):
+    """Maxwellian of the start's energy, energy and momentum kept to rounding."""
+    from scipy import stats as sps
+    e0, e1 = 0.5 * mass * float((v0 ** 2).sum()), 0.5 * mass * float((v1 ** 2).sum())
+    assert abs(e1 - e0) <= 1e-12 * e0
+    p0, p1 = mass * v0.sum(axis=1), mass * v1.sum(axis=1)
+    assert np.abs(p1 - p0).max() <= 1e-12 * mass * np.abs(v0).sum()
+    for d in range(3):
+        ks = sps.kstest(v1[d] / sigma_1d, "norm")
+        assert ks.pvalue > 1e-3, (d, ks)
+
+
+def test_yukawa_box_thermalises():
+    """Velocity-dependent cross-section sigma0 / (1 + (w/w0)^2)^2: the first
+    steps scatter at rho <sigma(w) w> over mono-speed pairs, the box relaxes
+    to the Maxwellian of the same energy, and the rate there is
+    rho <sigma(w) w> over Maxwellian pairs (both by quadrature)."""
+    n, s, steps, w0 = 32768, 0.02, 600, 1.0
+    w = W.uniform_box(n, ic_seed=78, philox_seed=11, mono_speed=True)
+    i_mono = _mono_mean(lambda x: _yukawa_w(x, w0))
+    w.xsec, w.w0 = XSEC_YUKAWA, w0
+    w.sigma0 = s / ((1.0 - 1.0 / n) * i_mono * w.dt[0])
+    print(f"[case] Yukawa thermalisation n={n} steps={steps} w0={w0}", flush=True)
+    events, v0, v1 = _run_box(w, steps, 0.05)
+    sig = 1.0 / math.sqrt(3.0)
+    i_mb = _maxwell_mean(lambda x: _yukawa_w(x, w0), sig)
+    expect0 = s * n / 2.0
+    first, late = events[:10].mean(), events[steps // 2:].mean()
+    print(f"[thermo-yukawa] first {first:.1f} expect {expect0:.1f} late/first {late / expect0:.4f} "
+          f"expect {i_mb / i_mono:.4f}", flush=True)
+    assert abs(first - expect0) < 0.03 * expect0, (first, expect0)
+    # second half: ~220 events a step, 0.4% statistical error on the mean
+    assert abs(late / expect0 - i_mb / i_mono) < 0.02 * (i_mb / i_mono), (late, expect0)
+    _relaxed(v0, v1, w.mass, sig)
+
+
+@pytest.mark.parametrize("c_sidm", [0.1, 0.5, 1.0, 2.0, 5.0])
+def test_steps_from_the_timestep_criterion_alone(c_sidm):
+    """Each step's length is the smallest dt the per-pair criterion gives
+    (no other bound): the step-start probabilities stay below C_SIDM (so
+    below 1 for C_SIDM < 1), and the box still relaxes to the Maxwellian of
+    its energy by the same simulated time."""
+    import torch
+    from paper_2607_05504_amd import Context, runner
+    n, w0, t_end = 8192, 1.0, 6.0
+    w = W.uniform_box(n, ic_seed=79, philox_seed=12, mono_speed=True)
+    w.xsec, w.w0, w.c_sidm = XSEC_YUKAWA, w0, c_sidm
+    # about one scatter per particle per unit time at the start
+    w.sigma0 = 1.0 / ((1.0 - 1.0 / n) * _mono_mean(lambda x: _yukawa_w(x, w0)))
+    w.dt = np.zeros(n)
+    print(f"[case] timestep criterion C_SIDM={c_sidm} n={n} t_end={t_end}", flush=True)
+    ds = runner.upload(w, "cuda")
+    ctx = Context(runner.config_for(w), w.n, w.n_active)
+    out = runner.alloc_out(ds, w.n_ngb)
+    v = lambda: np.stack([ds.vx.cpu().numpy(), ds.vy.cpu().numpy(), ds.vz.cpu().numpy()])
+    v0 = v()
+    runner.run_step(ctx, ds, out, w.seed, 0)          # dt = 0: the criterion only
+    assert ctx.sync()["n_events"] == 0
+    t, step, p_max, n_ge1, events = 0.0, 1, 0.0, 0, 0
+    while t < t_end:
+        dt = float(out.dt_sidm.min().item())
+        assert math.isfinite(dt) and dt > 0.0
+        ds.dt.fill_(dt)
+        runner.run_step(ctx, ds, out, w.seed, step)
+        ctx.drift(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, dt)
+        st = ctx.sync()
+        assert st["error"] == 0
+        p_max, n_ge1, events = max(p_max, st["max_p"]), n_ge1 + st["n_p_ge_1"], events + st["n_events"]
+        t += dt
+        step += 1
+        assert step < 4000
+    v1 = v()
+    ctx.close()
+    torch.cuda.synchronize()
+    print(f"[criterion] C={c_sidm} steps {step - 1} max P {p_max:.4f} P>=1 {n_ge1} events/particle "
+          f"{2 * events / n:.2f}", flush=True)
+    assert p_max <= c_sidm * (1.0 + 1e-12)
+    assert p_max > 0.2 * c_sidm                     # the bound is not vacuous
+    if c_sidm < 1.0:
+        assert n_ge1 == 0
+    if c_sidm <= 0.1:
+        # small steps follow the rate: between the mono-speed one (1 a unit
+        # time) and the Maxwellian one (<sigma w> 8% higher), ~2.5% Poisson
+        i_mono = _mono_mean(lambda x: _yukawa_w(x, w0))
+        i_mb = _maxwell_mean(lambda x: _yukawa_w(x, w0), 1.0 / math.sqrt(3.0))
+        epp = 2.0 * events / n
+        assert 0.93 * t <= epp <= 1.07 * t * i_mb / i_mono, (epp, t)
+    _relaxed(v0, v1, w.mass, 1.0 / math.sqrt(3.0))
+
+
+def test_overlap_estimator_thermalises_like_the_spline():
+    """The same mono-speed box with the kernel-overlap estimator: first-step
+    rate and relaxed rate agree with the one-sided spline's closed forms
+    within their statistical errors, and it relaxes to the same Maxwellian."""
+    n, s, steps = 32768, 0.02, 300
+    w = W.uniform_box(n, ic_seed=80, philox_seed=13, scatters_per_particle=s, mono_speed=True)
+    print(f"[case] overlap-estimator thermalisation n={n} steps={steps}", flush=True)
+    events, v0, v1 = _run_box(w, steps, 0.05, overlap=True)
+    expect0 = s * n / 2.0
+    expect_ratio = (4.0 / math.sqrt(3.0 * math.pi)) / (4.0 / 3.0)
+    first, late = events[:10].mean(), events[steps // 2:].mean()
+    print(f"[thermo-overlap] first {first:.1f} expect {expect0:.1f} late/first {late / expect0:.4f} "
+          f"expect {expect_ratio:.4f}", flush=True)
+    # 10 steps of ~330 events: 1.7% statistical error; the overlap estimate's
+    # mean density in a finite box differs from the spline's by O(1/N)
+    assert abs(first - expect0) < 0.06 * expect0, (first, expect0)
+    # 150 steps of ~280 events: 0.5%
+    assert abs(late / expect0 - expect_ratio) < 0.03, (late, expect0)
+    _relaxed(v0, v1, w.mass, 1.0 / math.sqrt(3.0))
