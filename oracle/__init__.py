@@ -53,6 +53,18 @@ def use_openmp(threads: int = 0) -> int:
     return int(lib().oref_threads(int(threads)))
 
 
+_turn_mode = 0
+
+
+def set_turn_mode(mode: int) -> int:
+    """How the scatter step visits the serial order (same results): 0 every
+    candidate in turn (the default), 1 only those whose turn can differ from
+    the step-start evaluation (for steps of many millions of candidates)."""
+    global _turn_mode
+    _turn_mode = int(mode)
+    return int(lib().oref_set_turn_mode(_turn_mode))
+
+
 def use_serial() -> None:
     """Back to the single-threaded build (the default)."""
     global _lib, _which
@@ -78,6 +90,9 @@ def lib():
                                    ctypes.c_uint64, ctypes.c_double)
         L.oref_threads.argtypes = [i32]
         L.oref_threads.restype = i32
+        L.oref_set_turn_mode.argtypes = [i32]
+        L.oref_set_turn_mode.restype = i32
+        L.oref_set_turn_mode(_turn_mode)
         L.oref_philox4x32_10.argtypes = [P, P, P]
         L.oref_philox4x32_10.restype = None
         L.oref_uniform_decision.argtypes = [u64, u32, u32, u32]
@@ -201,17 +216,31 @@ def kd_tree(x, y, z, periodic, box):
 def candidate_superset(x, y, z, periodic, box, targets, k, workers=-1, kd=None):
     """CSR superset of every target's partners with r <= r_(k+1), from scipy's
     k-d tree: the (k+2)-th closest point including the target itself bounds
-    r_(k+1); the ball query radius is padded far beyond rounding differences.
+    r_(k+1), and the radius is padded far beyond rounding differences.  A
+    row is the k+8 closest points when the last of them lies beyond the padded
+    radius (then every point within it is among them), else a ball query.
     kd: a tree from kd_tree() of the same particles, else one is built."""
     kd, pts = kd if kd is not None else kd_tree(x, y, z, periodic, box)
     q = pts[targets]
-    d, _ = kd.query(q, k=k + 2, workers=workers)
+    kk = min(k + 8, len(pts))
+    d, nb = kd.query(q, k=kk, workers=workers)
     rad = d[:, k + 1] * (1.0 + 1e-9) + 1e-300
-    lists = kd.query_ball_point(q, rad, workers=workers, return_sorted=False)
-    counts = np.fromiter((len(l) for l in lists), dtype=np.int64, count=len(lists))
-    ptr = np.zeros(len(lists) + 1, dtype=np.int64)
+    ok = d[:, kk - 1] > rad
+    counts = np.full(len(q), kk, dtype=np.int64)
+    rest = np.flatnonzero(~ok)
+    lists = kd.query_ball_point(q[rest], rad[rest], workers=workers, return_sorted=False) \
+        if rest.size else []
+    for r, l in zip(rest, lists):
+        counts[r] = len(l)
+    ptr = np.zeros(len(q) + 1, dtype=np.int64)
     np.cumsum(counts, out=ptr[1:])
-    idx = np.fromiter((j for l in lists for j in l), dtype=np.int32, count=int(ptr[-1]))
+    idx = np.empty(int(ptr[-1]), dtype=np.int32)
+    okr = np.flatnonzero(ok)
+    # rows of kk entries: their slots in idx
+    pos = (ptr[okr][:, None] + np.arange(kk)[None, :]).ravel()
+    idx[pos] = nb[okr].ravel()
+    for r, l in zip(rest, lists):
+        idx[ptr[r]:ptr[r + 1]] = np.asarray(l, dtype=np.int32)
     return ptr, idx
 
 

@@ -332,6 +332,20 @@ int oref_find_ngb(int64_t n, const double *x, const double *y, const double *z,
     return rc;
 }
 
+/* The order in which the scatter step visits the turns (the result is the
+ * same): 0 visits every candidate in order; 1 visits, in the same order, only
+ * the candidates whose turn can differ from their step-start evaluation --
+ * those accepted at the step start and those touching a particle kicked
+ * earlier in the order.  Every other candidate meets both of its particles
+ * unkicked at its turn, so its P and decision are the step-start ones.  1
+ * exists for steps of many millions of candidates; tests pin it to 0. */
+static int oref_turn_mode = 0;
+int oref_set_turn_mode(int mode)
+{
+    if (mode == 0 || mode == 1) oref_turn_mode = mode;
+    return oref_turn_mode;
+}
+
 /* threads of the OpenMP build (want > 0 sets them); 1 for the plain build */
 int oref_threads(int want)
 {
@@ -493,6 +507,55 @@ static double candidate_probability(const double *x, const double *y, const doub
     return P;
 }
 
+/* Min-heap of turns in cand_ord_cmp order (the event-driven visit). */
+typedef struct { cand_ord_t *e; int64_t n, cap; } turn_heap;
+
+static int heap_push(turn_heap *h, cand_ord_t v)
+{
+    if (h->n == h->cap) {
+        int64_t nc = h->cap ? 2 * h->cap : 1024;
+        cand_ord_t *ne = (cand_ord_t *)realloc(h->e, (size_t)nc * sizeof(cand_ord_t));
+        if (!ne) return -1;
+        h->e = ne; h->cap = nc;
+    }
+    int64_t q = h->n++;
+    while (q > 0) {
+        int64_t p = (q - 1) / 2;
+        if (cand_ord_cmp(&h->e[p], &v) <= 0) break;
+        h->e[q] = h->e[p];
+        q = p;
+    }
+    h->e[q] = v;
+    return 0;
+}
+
+static cand_ord_t heap_pop(turn_heap *h)
+{
+    cand_ord_t top = h->e[0], last = h->e[--h->n];
+    int64_t q = 0;
+    for (;;) {
+        int64_t c = 2 * q + 1;
+        if (c >= h->n) break;
+        if (c + 1 < h->n && cand_ord_cmp(&h->e[c + 1], &h->e[c]) < 0) ++c;
+        if (cand_ord_cmp(&last, &h->e[c]) <= 0) break;
+        h->e[q] = h->e[c];
+        q = c;
+    }
+    if (h->n > 0) h->e[q] = last;
+    return top;
+}
+
+/* row of dense candidate index d (row_off[a] <= d < row_off[a + 1]) */
+static int64_t row_of(const int64_t *row_off, int64_t n_active, int64_t d)
+{
+    int64_t lo = 0, hi = n_active - 1;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo + 1) / 2;
+        if (row_off[mid] <= d) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 /*
  * Shared by both estimators.  Row a of ngb (stride entries) holds the
  * partners of active[a]; count[a] of them are used (all stride when count is
@@ -517,6 +580,146 @@ static double candidate_probability(const double *x, const double *y, const doub
  * n_accept0, n_p_ge_1 and max_p of the step-start evaluation; n_events kicks;
  * n_flagged flagged turns; n_passes the largest depth.
  */
+/* The scatter step visiting only the turns that can differ from their
+ * step-start evaluation (oref_turn_mode 1; see oref_set_turn_mode).  Same
+ * arguments as scatter_core, plus its row offsets. */
+static int scatter_events(int64_t n, const double *x, const double *y, const double *z,
+                          double *vx, double *vy, double *vz, const double *mass, double m_scalar,
+                          const uint32_t *id, uint8_t *state, int periodic, double box,
+                          int64_t n_active, const int32_t *active, int stride,
+                          const int32_t *ngb, const double *h, const double *h_all, const double *dt,
+                          const phys_t *ph, double band, const int64_t *row_off, int64_t n_cand,
+                          uint32_t *cand_info, oref_stats *st)
+{
+    enum { F_ACC0 = 1, F_FLAG0 = 2, F_QUEUED = 4, F_FLAGT = 8 };
+    const int xsec = ph->xsec, model = ph->model;
+    const double s0 = ph->s0, w0 = ph->w0;
+    const uint64_t seed = ph->seed;
+    const uint32_t step = ph->step;
+    uint8_t *fl = (uint8_t *)calloc((size_t)(n_cand > 0 ? n_cand : 1), 1);
+    int32_t *a_of = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    int64_t *rstart = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *rlist = (int64_t *)malloc((size_t)(n_cand > 0 ? n_cand : 1) * sizeof(int64_t));
+    int32_t *depth = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+    turn_heap hp = {NULL, 0, 0};
+    int rc = OREF_OK;
+    if (!fl || !a_of || !rstart || !rlist || !depth) { rc = OREF_E_NOMEM; goto done; }
+
+    /* step-start evaluation of every candidate */
+    double max_p = 0.0;
+    int64_t n_ge1 = 0, n_acc0 = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(max : max_p) reduction(+ : n_ge1, n_acc0)
+    for (int64_t a = 0; a < n_active; ++a) {
+        int32_t i = active[a];
+        for (int64_t d = row_off[a]; d < row_off[a + 1]; ++d) {
+            int64_t ci = a * (int64_t)stride + (d - row_off[a]);
+            int32_t j = ngb[ci];
+            double P = candidate_probability(x, y, z, vx, vy, vz, mass, m_scalar, state, periodic,
+                                             box, i, j, h, h_all, a, dt, xsec, s0, w0, model);
+            double u = oref_uniform_decision(seed, step, id[i], id[j]);
+            if (P > max_p) max_p = P;
+            if (P >= 1.0) n_ge1++;
+            uint8_t f = 0;
+            if (u < P) { f |= F_ACC0; n_acc0++; }
+            if (fabs(P - u) < band) f |= F_FLAG0;
+            fl[d] = f;
+        }
+    }
+    st->max_p = max_p;
+    st->n_p_ge_1 = n_ge1;
+    st->n_accept0 = n_acc0;
+
+    /* the candidates touching each particle: its own row, and the rows that
+     * list it (a reverse index of the partners) */
+    for (int64_t p = 0; p < n; ++p) a_of[p] = -1;
+    for (int64_t a = 0; a < n_active; ++a) a_of[active[a]] = (int32_t)a;
+    for (int64_t a = 0; a < n_active; ++a)
+        for (int64_t d = row_off[a]; d < row_off[a + 1]; ++d)
+            rstart[ngb[a * (int64_t)stride + (d - row_off[a])] + 1]++;
+    for (int64_t p = 0; p < n; ++p) rstart[p + 1] += rstart[p];
+    {
+        int64_t *cur = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+        if (!cur) { rc = OREF_E_NOMEM; goto done; }
+        memcpy(cur, rstart, (size_t)n * sizeof(int64_t));
+        for (int64_t a = 0; a < n_active; ++a)
+            for (int64_t d = row_off[a]; d < row_off[a + 1]; ++d)
+                rlist[cur[ngb[a * (int64_t)stride + (d - row_off[a])]]++] = d;
+        free(cur);
+    }
+
+    /* a turn's key, as the plain order sorts it */
+#define TURN_OF(D, A, OUT)                                                              \
+    do {                                                                               \
+        int64_t ci_ = (A) * (int64_t)stride + ((D) - row_off[A]);                      \
+        int32_t i_ = active[A], j_ = ngb[ci_];                                         \
+        uint32_t xr_[4];                                                               \
+        pair_draw(seed, step, id[i_], id[j_], PURPOSE_PRIORITY, xr_);                   \
+        cand_ord_t e_ = {direction_word(xr_, id[i_] < id[j_]), id[i_], id[j_], ci_, (A)}; \
+        (OUT) = e_;                                                                    \
+    } while (0)
+
+    for (int64_t a = 0; a < n_active; ++a)
+        for (int64_t d = row_off[a]; d < row_off[a + 1]; ++d)
+            if (fl[d] & F_ACC0) {
+                cand_ord_t e;
+                TURN_OF(d, a, e);
+                fl[d] |= F_QUEUED;
+                if (heap_push(&hp, e)) { rc = OREF_E_NOMEM; goto done; }
+            }
+    while (hp.n > 0) {
+        cand_ord_t c = heap_pop(&hp);
+        int32_t i = active[c.a], j = ngb[c.c];
+        int64_t dc = row_off[c.a] + (c.c - c.a * (int64_t)stride);
+        double P = candidate_probability(x, y, z, vx, vy, vz, mass, m_scalar, state, periodic,
+                                         box, i, j, h, h_all, c.a, dt, xsec, s0, w0, model);
+        double u = oref_uniform_decision(seed, step, id[i], id[j]);
+        fl[dc] = (uint8_t)((fl[dc] & ~F_FLAGT) | (fabs(P - u) < band ? F_FLAGT : 0));
+        if (!(u < P)) continue;
+        do_kick(ph, i, j, mass, m_scalar, vx, vy, vz, state, id);
+        int32_t dd = 1 + (depth[i] > depth[j] ? depth[i] : depth[j]);
+        depth[i] = depth[j] = dd;
+        if (dd > st->n_passes) st->n_passes = dd;
+        st->n_events++;
+        if (cand_info) cand_info[c.c] |= OREF_CAND_SCATTER | ((uint32_t)dd << 8);
+        /* later turns touching i or j now see kicked velocities */
+        int32_t pp[2] = {i, j};
+        for (int q = 0; q < 2; ++q) {
+            int32_t p = pp[q];
+            int64_t ap = a_of[p];
+            int64_t lo = ap >= 0 ? row_off[ap] : 0, hi = ap >= 0 ? row_off[ap + 1] : 0;
+            for (int pass = 0; pass < 2; ++pass) {
+                int64_t b0 = pass == 0 ? lo : rstart[p], b1 = pass == 0 ? hi : rstart[p + 1];
+                for (int64_t t = b0; t < b1; ++t) {
+                    int64_t d = pass == 0 ? t : rlist[t];
+                    if (fl[d] & F_QUEUED) continue;
+                    int64_t ad = pass == 0 ? ap : row_of(row_off, n_active, d);
+                    cand_ord_t e;
+                    TURN_OF(d, ad, e);
+                    if (cand_ord_cmp(&e, &c) <= 0) continue;     /* its turn has passed */
+                    fl[d] |= F_QUEUED;
+                    if (heap_push(&hp, e)) { rc = OREF_E_NOMEM; goto done; }
+                }
+            }
+        }
+    }
+#undef TURN_OF
+    /* flagged at the turn: the visited turns' own evaluation, else the
+     * step-start one (which is what the turn would have computed) */
+    for (int64_t a = 0; a < n_active; ++a)
+        for (int64_t d = row_off[a]; d < row_off[a + 1]; ++d) {
+            int64_t ci = a * (int64_t)stride + (d - row_off[a]);
+            int f = (fl[d] & F_QUEUED) ? (fl[d] & F_FLAGT) != 0 : (fl[d] & F_FLAG0) != 0;
+            if (cand_info && (fl[d] & F_ACC0)) cand_info[ci] |= OREF_CAND_ACCEPT0;
+            if (f) {
+                st->n_flagged++;
+                if (cand_info) cand_info[ci] |= OREF_CAND_FLAGGED;
+            }
+        }
+done:
+    free(hp.e); free(depth); free(rlist); free(rstart); free(a_of); free(fl);
+    return rc;
+}
+
 static int scatter_core(int64_t n, const double *x, const double *y, const double *z,
                         double *vx, double *vy, double *vz, const double *mass, double m_scalar,
                         const uint32_t *id, uint8_t *state, int periodic, double box,
@@ -541,6 +744,14 @@ static int scatter_core(int64_t n, const double *x, const double *y, const doubl
     }
     const int64_t n_cand = row_off[n_active];
     st.n_cand = n_cand;
+    if (oref_turn_mode == 1) {
+        int rc = scatter_events(n, x, y, z, vx, vy, vz, mass, m_scalar, id, state, periodic, box,
+                                n_active, active, stride, ngb, h, h_all, dt, &ph, band, row_off,
+                                n_cand, cand_info, &st);
+        free(row_off);
+        if (stats) *stats = st;
+        return rc;
+    }
     cand_ord_t *ord = (cand_ord_t *)malloc((size_t)(n_cand > 0 ? n_cand : 1) * sizeof(cand_ord_t));
     int32_t *depth = (int32_t *)calloc((size_t)n, sizeof(int32_t));
     if (!ord || !depth) { free(ord); free(depth); free(row_off); return OREF_E_NOMEM; }

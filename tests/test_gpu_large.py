@@ -1,8 +1,9 @@
 """Parity at the full sizes of the large workloads, in the launch
 configuration the benchmark uses: the two-state Hernquist halo (N = 4e6,
-~1/8 active) against the whole oracle step, and the clustered 256^3 box
-(16.8M particles, all active) on sampled targets plus properties that hold at
-any size."""
+~1/8 active and all active) and the clustered 256^3 box (16.8M particles,
+all active) against the whole oracle step (its OpenMP build, visiting only
+the turns that can differ from the step-start evaluation), plus sampled
+targets and properties that hold at any size."""
 import numpy as np
 import pytest
 
@@ -44,6 +45,30 @@ def test_two_state_4e6_binned_full_parity():
     assert abs(e(g["vx"], g["vy"], g["vz"], g["state"]) - e0) <= 1e-12 * e0
 
 
+def _full_oracle(w):
+    """The oracle's whole step on all host cores (same results as the serial
+    build and the plain visit of every turn, which the CPU tests pin)."""
+    oracle.use_openmp(0)
+    oracle.set_turn_mode(1)
+    try:
+        return oracle.full_step(w)
+    finally:
+        oracle.set_turn_mode(0)
+        oracle.use_serial()
+
+
+@pytest.mark.timeout(900)
+def test_two_state_4e6_all_active_full_parity():
+    """All 4e6 particles of the two-state halo active (dt = 1e-3): every
+    output against the oracle."""
+    w = W.hernquist_halo(4_000_000, ic_seed=104, philox_seed=4, two_state=True)
+    w.dt = np.full(w.n, 1e-3)
+    _announce(f"two-state hernquist 4e6 all active, full oracle step")
+    g = gpu_step(w)
+    ref = _full_oracle(w)
+    assert_parity(w, g, ref)
+
+
 @pytest.fixture(scope="module")
 def clustered():
     w = W.clustered_box()
@@ -53,6 +78,18 @@ def clustered():
 def _sample(w, m, seed):
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.sort(rng.choice(w.n_active, size=m, replace=False))
+
+
+@pytest.mark.timeout(1200)
+def test_clustered_256cubed_full_parity(clustered):
+    """The 256^3 clustered box, all 16.8M particles active: every output
+    (neighbour lists, h, decisions, velocities, states, dt, statistics)
+    against the oracle's whole step."""
+    w = clustered
+    _announce(f"clustered 256^3 all active, full oracle step")
+    g = gpu_step(w)
+    ref = _full_oracle(w)
+    assert_parity(w, g, ref)
 
 
 def test_clustered_256cubed_sampled(clustered):

@@ -740,3 +740,50 @@ def test_openmp_build_gives_the_same_step():
     for f in ("ngb", "h", "vx", "vy", "vz", "state", "info", "dt_sidm"):
         assert np.array_equal(base[f], par[f]), f
     assert base["stats"] == par["stats"]
+
+
+@pytest.mark.parametrize("case", ["box_s3", "halo_two_state_partial", "yukawa_many", "beam",
+                                  "overlap"])
+def test_visiting_only_changeable_turns_gives_the_same_step(case):
+    """The oracle's second visit of the serial order (only the turns accepted
+    at the step start or touching a particle kicked earlier; the rest keep
+    their step-start evaluation) against the visit of every turn: the same
+    decisions, flags, depths, velocities and states bit for bit, serial and
+    OpenMP, on steps with long kick chains."""
+    if case == "box_s3":
+        w = W.uniform_box(5000, ic_seed=91, philox_seed=7, scatters_per_particle=3.0)
+    elif case == "halo_two_state_partial":
+        w = W.hernquist_halo(8000, ic_seed=92, philox_seed=8, two_state=True)
+        w.sigma0 *= 40.0
+        w = w.subset_active(5000)
+    elif case == "yukawa_many":
+        w = W.hernquist_halo(6000, ic_seed=93, philox_seed=9)
+        w.sigma0 *= 60.0
+    elif case == "beam":
+        w = W.beam_lattice(n_side=10, n_beam=1500, rate_dt=2.0)
+    else:
+        w = W.uniform_box(3000, ic_seed=94, philox_seed=10, scatters_per_particle=2.0)
+
+    def run():
+        if case == "overlap":
+            h = oracle.smoothing_lengths(w)
+            ngb, cnt = oracle.find_overlap(w, h, 512)
+            return oracle.scatter_overlap(w, h, ngb, cnt)
+        ngb, h = oracle.find_ngb(w, brute=False)
+        return oracle.scatter_step(w, ngb, h)
+
+    base = run()
+    out = []
+    try:
+        oracle.set_turn_mode(1)
+        out.append(run())
+        oracle.use_openmp(4)
+        out.append(run())
+    finally:
+        oracle.set_turn_mode(0)
+        oracle.use_serial()
+    assert base[5]["n_events"] > 100
+    for o in out:
+        for k in range(5):
+            assert np.array_equal(base[k], o[k]), k
+        assert base[5] == o[5]
