@@ -118,14 +118,15 @@ typedef struct {
                              SIDM_MODEL_BEAM (the fixed-target beam test of sec. 5.1:
                              state 1 = beam, 0 = target; only beam-target pairs scatter,
                              elastically, and the target does not recoil) */
-    int32_t precision;    /* SIDM_FP64, or SIDM_MIXED (FP32 search/probability with an
-                             FP64 recheck inside the bands below; kicks stay FP64)        */
+    int32_t precision;    /* SIDM_FP64, or SIDM_MIXED (FP32 probabilities with an FP64
+                             recheck inside band_p; the neighbour search is the exact
+                             FP64 one in both forms; kicks stay FP64)                     */
     double box;           /* periodic box side L                                          */
     double sigma0, w0;    /* cross-section parameters                                     */
     double eps, delta;    /* constant eps; two-state energy gap per unit mass             */
     double c_sidm;        /* timestep coefficient (paper: 0.1)                            */
     double flag_band;     /* evaluations with |P - u| < flag_band are flagged (1e-9)      */
-    double band_r2;       /* mixed form: relative r^2 band rechecked in FP64              */
+    double band_r2;       /* kept for layout; no effect (the search is FP64 in both forms)*/
     double band_p;        /* mixed form: relative |P - u| band rechecked in FP64          */
     /* SIDM_XSEC_TABLE (a tabulated sigma(w)/m of the pair's relative speed,
      * sec. 4.2, as the velocity-dependent models of sec. 6 are given):

@@ -2,34 +2,33 @@
 // and 4.5: h_i is set so that about N_ngb neighbours lie inside the kernel;
 // here exactly N_ngb, ties broken by particle ID, h_i = distance of the next).
 //
-// Two kernels per batch of targets, over the bucket tree (leaves of SIDM_LEAF
-// Morton-consecutive particles, SIDM_TREE_FAN-ary parents):
+// Three kernels per batch of targets, over the bucket tree (leaves of
+// SIDM_LEAF Morton-consecutive particles, each split into sub-buckets of
+// SIDM_SUB with their own boxes; SIDM_TREE_FAN-ary parents):
 //
-//  k_knn_list  sixteen lanes per target, four targets per wavefront.  A valid
-//              upper bound T on r^2 of the (N_ngb+1)-th neighbour comes from
-//              the target's Morton-order neighbours (64 on each side): their
-//              (N_ngb+1)-th smallest r^2, bracketed in FP32 rounded up, so the
-//              bound never falls below the exact value.  The wavefront then
-//              walks the tree level by level against the box enclosing all its
-//              targets' spheres (64 children tested per round, one coalesced
-//              load), and each target's lanes keep the leaves that meet its
-//              own sphere.
+//  k_knn_list   sixteen lanes per target, four targets per wavefront.  A valid
+//               upper bound T on r^2 of the (N_ngb+1)-th neighbour comes from
+//               the target's Morton-order neighbours (64 on each side): their
+//               (N_ngb+1)-th smallest r^2, bracketed in FP32 rounded up, so the
+//               bound never falls below the exact value.  The wavefront then
+//               walks the tree level by level against the box enclosing all its
+//               targets' spheres (64 children tested per round, one coalesced
+//               load), and each target's lanes keep the leaves that meet its
+//               own sphere.
 //
-//  k_knn_team  a team of 16 lanes per target, four targets per wavefront.  The
-//              team keys its leaf list by gap (FP32 rounded down, packed with
-//              the leaf index into one 64-bit word) and takes the leaves
-//              nearest first, two a step, until the nearest left lies beyond
-//              the current radius.  A step's 64 particles (four per lane) are
-//              requested together and tested when they arrive; those within
-//              the radius are appended to an LDS list of 16*E.  When the list
-//              might not hold the next step it is cut: the radius becomes the
-//              (N_ngb+1)-th smallest r^2 rounded up to FP32, found by
-//              bisection on team-wide counts, and the entries above it go.  At
-//              the end the teams of a wavefront sort their lists on r^2
-//              (register bitonic network, E keys per lane; runs of equal r^2
-//              are then placed by ID) and keep N_ngb+1.  A target whose list
-//              overflowed, or whose wavefront gave up its group walk, walks the
-//              tree from the root instead (same loop).
+//  k_knn_bucket one wavefront per target.  The sub-buckets of its leaves that
+//               meet the sphere, then their particles, four a lane a round; those
+//               within the radius go to an LDS list, cut to the (N_ngb+1)-th
+//               smallest when a round might not fit (bisection on ballot
+//               counts); at the end each survivor's exact r^2 and its rank in
+//               (r^2, ID, index) place it.
+//
+//  k_knn_team   the targets k_knn_bucket left (a leaf list that overflowed, a
+//               group walk given up, a list that many equal r^2 kept from being
+//               cut): a team of 16 lanes walks the tree from the root, nearest
+//               child first, tests a leaf's 32 particles at once, cuts its list
+//               by bisection on team-wide counts, and sorts it at the end
+//               (register bitonic network; runs of equal r^2 placed by ID).
 //
 // Pruning is exact-conservative: a box gap is computed with the same rounded
 // operations as a particle separation, and rounding is monotone, so no particle
@@ -60,8 +59,6 @@ struct KnnArgs {
     int64_t n, batch;
     int k;
     double box;
-    const float *xo, *yo, *zo;   // mixed form: FP32 offsets from the leaf's box centre
-    double band_r2;              // mixed form: relative widening of the FP32 radius test
 };
 
 constexpr int32_t kIdxMask = (1 << SIDM_LEVEL_SHIFT) - 1;
@@ -390,30 +387,6 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Nearest remaining leaf of the team's list: keys are (gap rounded down to
-// FP32, leaf) packed so that one 64-bit minimum orders them; the key taken is
-// retired.  Returns -1 once the nearest remaining gap exceeds T (then every
-// remaining gap does, since the rounded gaps never exceed the exact ones).
-template <int KP, int TS>
-__device__ __forceinline__ int32_t pick_nearest(uint64_t (&lk)[KP], double T)
-{
-    uint64_t m = lk[0];
-#pragma unroll
-    for (int q = 1; q < KP; ++q) m = lk[q] < m ? lk[q] : m;
-#pragma unroll
-    for (int off = 1; off < TS; off <<= 1) {
-        const uint64_t o = shfl_xor_u64(m, off);
-        m = o < m ? o : m;
-    }
-    if (m == ~0ull) return -1;
-#pragma unroll
-    for (int q = 0; q < KP; ++q)
-        if (lk[q] == m) lk[q] = ~0ull;
-    const float gf = __uint_as_float((uint32_t)(m >> 32));
-    if ((double)gf > T) return -1;
-    return (int32_t)(uint32_t)m;
-}
-
 // Next leaf of a root walk (targets whose list overflowed): pops the LDS
 // stack, pushing the children within T nearest on top; -1 when empty.
 template <bool PERIODIC, int TS>
@@ -459,12 +432,11 @@ __device__ __forceinline__ int32_t walk_next(const KnnArgs &A, int32_t *stk, int
 constexpr bool kPrefetchLeaf = false;
 
 // One target of kernel B (its team's lists and stack in LDS).
-template <bool PERIODIC, int E, bool MIXED, int TS, int LPI>
+template <bool PERIODIC, int E, int TS, int LPI>
 __device__ __forceinline__ void team_target(const KnnArgs &A, int64_t base, int64_t bb, double *L_r2,
                                             int32_t *L_j, int32_t *stk, int tl, int wteam)
 {
     constexpr int N = TS * E;                 // list capacity
-    constexpr int KP = (SIDM_KNN_LMAX + TS - 1) / TS;
     constexpr int PPL = SIDM_LEAF / TS;       // particles of a leaf per lane
     constexpr int PS = PPL * LPI;             // particles per lane per step (LPI leaves)
     constexpr uint64_t TMASK = (TS == 64) ? ~0ull : ((1ull << TS) - 1ull);
@@ -478,43 +450,10 @@ __device__ __forceinline__ void team_target(const KnnArgs &A, int64_t base, int6
     const int K1 = A.k + 1;
     const uint64_t below = (tl == 0) ? 0ull : ((1ull << tl) - 1ull);
 
-    // the leaf list of the first kernel, or a walk from the root if it overflowed
-    const int nl = A.nl[bb];
-    const int32_t *lst = A.list + bb * SIDM_KNN_LMAX;
-    const bool walk = nl < 0;
-    int sp = 0;
-    if (walk) {
-        if (tl == 0) stk[0] = (A.lv.nlev - 1) << SIDM_LEVEL_SHIFT;
-        sp = 1;
-    }
-    // the list's entries first, then their boxes, so that the requests of
-    // each stage go out together
-    int32_t lf[KP];
-#pragma unroll
-    for (int q = 0; q < KP; ++q) {
-        const int t = q * TS + tl;
-        lf[q] = (!walk && t < nl) ? lst[t] : -1;
-    }
-    // (an absent entry reads node 0 and is masked, so that no branch holds
-    // the requests back); the gap as node_gap2 computes it
-    double lbx[KP][6];
-#pragma unroll
-    for (int q = 0; q < KP; ++q) {
-        const double *nb = A.nodes + (int64_t)(lf[q] >= 0 ? lf[q] : 0) * 6;
-#pragma unroll
-        for (int d = 0; d < 6; ++d) lbx[q][d] = nb[d];
-    }
-    uint64_t lk[KP];
-#pragma unroll
-    for (int q = 0; q < KP; ++q) {
-        const double gx = axis_gap<PERIODIC>(lbx[q][0], lbx[q][3], px, box);
-        const double gy = axis_gap<PERIODIC>(lbx[q][1], lbx[q][4], py, box);
-        const double gz = axis_gap<PERIODIC>(lbx[q][2], lbx[q][5], pz, box);
-        const double g = lbx[q][0] <= lbx[q][3] ? (gx * gx + gy * gy) + gz * gz : INFINITY;
-        lk[q] = lf[q] >= 0
-                    ? ((uint64_t)__float_as_uint(__double2float_rd(g)) << 32) | (uint32_t)lf[q]
-                    : ~0ull;
-    }
+    // a walk from the root, nearest child first (the targets come here when
+    // their leaf list overflowed or kernel B' could not cut its list)
+    int sp = 1;
+    if (tl == 0) stk[0] = (A.lv.nlev - 1) << SIDM_LEVEL_SHIFT;
     double T = A.tb[bb];
     wave_sync();
 
@@ -522,22 +461,12 @@ __device__ __forceinline__ void team_target(const KnnArgs &A, int64_t base, int6
     // leaves, requests their positions and tests them (with kPrefetchLeaf the
     // next step's leaves are requested before the current ones are tested).
     // cur = -2 before the first leaf is picked, -1 once none is left.
-    // mixed form: the particles' FP32 offsets and their leaf's box; the test
-    // is in FP32 against a radius widened by band_r2, the list holds FP32
-    // r^2 until the final sort, which takes the exact FP64 r^2 of each entry
     int32_t cur[LPI];
     double cx[PS], cy[PS], cz[PS];
-    float fx[PS], fy[PS], fz[PS];
-    double cb[LPI][6];
 #pragma unroll
-    for (int u = 0; u < LPI; ++u) {
-        cur[u] = -2;
+    for (int u = 0; u < LPI; ++u) cur[u] = -2;
 #pragma unroll
-        for (int d = 0; d < 6; ++d) cb[u][d] = 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < PS; ++q) { cx[q] = cy[q] = cz[q] = 0.0; fx[q] = fy[q] = fz[q] = 0.0f; }
-    const float box32 = (float)box;
+    for (int q = 0; q < PS; ++q) cx[q] = cy[q] = cz[q] = 0.0;
     int count = 0;
     bool finished = false;
     double r[E];
@@ -545,35 +474,22 @@ __device__ __forceinline__ void team_target(const KnnArgs &A, int64_t base, int6
     while (true) {
         int32_t nxt[LPI];
         double nx[PS], ny[PS], nz[PS];
-        float gx[PS], gy[PS], gz[PS];
-        double nb6[LPI][6];
 #pragma unroll
-        for (int u = 0; u < LPI; ++u) {
-            nxt[u] = -1;
+        for (int u = 0; u < LPI; ++u) nxt[u] = -1;
 #pragma unroll
-            for (int d = 0; d < 6; ++d) nb6[u][d] = 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < PS; ++q) { nx[q] = ny[q] = nz[q] = 0.0; gx[q] = gy[q] = gz[q] = 0.0f; }
+        for (int q = 0; q < PS; ++q) nx[q] = ny[q] = nz[q] = 0.0;
         if (cur[0] != -1) {
 #pragma unroll
             for (int u = 0; u < LPI; ++u) {
                 if (u > 0 && nxt[u - 1] < 0) break;
-                nxt[u] = walk ? walk_next<PERIODIC, TS>(A, stk, sp, T, px, py, pz, tl, wteam)
-                              : pick_nearest<KP, TS>(lk, T);
+                nxt[u] = walk_next<PERIODIC, TS>(A, stk, sp, T, px, py, pz, tl, wteam);
                 if (nxt[u] >= 0) {
                     const int64_t s0 = (int64_t)nxt[u] * SIDM_LEAF;
 #pragma unroll
                     for (int q = 0; q < PPL; ++q) {
                         const int64_t j = s0 + q * TS + tl < n ? s0 + q * TS + tl : s0;
                         const int qq = u * PPL + q;
-                        if constexpr (MIXED) { gx[qq] = A.xo[j]; gy[qq] = A.yo[j]; gz[qq] = A.zo[j]; }
-                        else { nx[qq] = A.xs[j]; ny[qq] = A.ys[j]; nz[qq] = A.zs[j]; }
-                    }
-                    if constexpr (MIXED) {
-                        const double *nb = A.nodes + (int64_t)nxt[u] * 6;
-#pragma unroll
-                        for (int d = 0; d < 6; ++d) nb6[u][d] = nb[d];
+                        nx[qq] = A.xs[j]; ny[qq] = A.ys[j]; nz[qq] = A.zs[j];
                     }
                 }
             }
@@ -581,16 +497,9 @@ __device__ __forceinline__ void team_target(const KnnArgs &A, int64_t base, int6
         if constexpr (!kPrefetchLeaf) {
             // the picked leaves are tested in this step (their loads waited on)
 #pragma unroll
-            for (int u = 0; u < LPI; ++u) {
-                cur[u] = nxt[u];
+            for (int u = 0; u < LPI; ++u) cur[u] = nxt[u];
 #pragma unroll
-                for (int d = 0; d < 6; ++d) cb[u][d] = nb6[u][d];
-            }
-#pragma unroll
-            for (int q = 0; q < PS; ++q) {
-                cx[q] = nx[q]; cy[q] = ny[q]; cz[q] = nz[q];
-                fx[q] = gx[q]; fy[q] = gy[q]; fz[q] = gz[q];
-            }
+            for (int q = 0; q < PS; ++q) { cx[q] = nx[q]; cy[q] = ny[q]; cz[q] = nz[q]; }
         }
 #pragma unroll
         for (int u = 0; u < LPI; ++u) {
@@ -598,50 +507,12 @@ __device__ __forceinline__ void team_target(const KnnArgs &A, int64_t base, int6
             const int64_t s0 = (int64_t)cur[u] * SIDM_LEAF;
             double rq[PPL];
             bool pq[PPL];
-            if constexpr (MIXED) {
-                double dlx = box_centre(cb[u], 0) - px, dly = box_centre(cb[u], 1) - py,
-                       dlz = box_centre(cb[u], 2) - pz;
-                if (PERIODIC) {
-                    const double half = 0.5 * box;
-                    dlx = dlx >= half ? dlx - box : (dlx < -half ? dlx + box : dlx);
-                    dly = dly >= half ? dly - box : (dly < -half ? dly + box : dly);
-                    dlz = dlz >= half ? dlz - box : (dlz < -half ? dlz + box : dlz);
-                }
-                // Each FP32 component of the separation a = (centre - target)
-                // + f, f the particle's offset from the leaf centre, errs by
-                // at most 2^-23 (|a| + |f|).  While |a| + |f| stays below
-                // 16 sqrt(T) the error of r^2 stays below 7e-6 T, inside
-                // band_r2; a particle further from its leaf centre (32 Morton
-                // neighbours spread over a jump of the curve) is tested in
-                // FP64.  (|a| + |f|)^2 <= 2 (a^2 + f^2), so no square root.
-                const float ex = (float)dlx, ey = (float)dly, ez = (float)dlz;
-                const float T32 = __double2float_ru(T * (1.0 + A.band_r2));
-                const float Tfar = __double2float_rd(127.0 * T);
 #pragma unroll
-                for (int q = 0; q < PPL; ++q) {
-                    const int qq = u * PPL + q;
-                    float ax = ex + fx[qq], ay = ey + fy[qq], az = ez + fz[qq];
-                    if (PERIODIC) { ax = wrap32(ax, box32); ay = wrap32(ay, box32); az = wrap32(az, box32); }
-                    const int64_t j = s0 + q * TS + tl;
-                    const float v = (ax * ax + ay * ay) + az * az;
-                    const float f2 = (fx[qq] * fx[qq] + fy[qq] * fy[qq]) + fz[qq] * fz[qq];
-                    if (!(v + f2 <= Tfar)) {
-                        const int64_t jc = j < n ? j : s0;
-                        rq[q] = sep2_sel<PERIODIC>(px, py, pz, A.xs[jc], A.ys[jc], A.zs[jc], box);
-                        pq[q] = j < n && rq[q] <= T && j != i;
-                    } else {
-                        rq[q] = (double)v;
-                        pq[q] = j < n && v <= T32 && j != i;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < PPL; ++q) {
-                    const int qq = u * PPL + q;
-                    const int64_t j = s0 + q * TS + tl;
-                    rq[q] = sep2_sel<PERIODIC>(px, py, pz, cx[qq], cy[qq], cz[qq], box);
-                    pq[q] = j < n && rq[q] <= T && j != i;
-                }
+            for (int q = 0; q < PPL; ++q) {
+                const int qq = u * PPL + q;
+                const int64_t j = s0 + q * TS + tl;
+                rq[q] = sep2_sel<PERIODIC>(px, py, pz, cx[qq], cy[qq], cz[qq], box);
+                pq[q] = j < n && rq[q] <= T && j != i;
             }
 #pragma unroll
             for (int q = 0; q < PPL; ++q) {
@@ -675,15 +546,14 @@ __device__ __forceinline__ void team_target(const KnnArgs &A, int64_t base, int6
             }
             bool bad = false;
             if (need) {
-                // FP64: the exact r^2 rounded up.  Mixed: the FP32 r^2 widened
-                // by band_r2 both ways; the radius is the K1-th smallest upper
-                // bound and an entry goes only if its lower bound exceeds it
+                // the exact r^2 rounded up; the radius is the K1-th smallest
+                // and an entry goes if its value exceeds it
                 float f[E], fl[E];
                 uint32_t lo = 0xffffffffu, hi = 0u;
 #pragma unroll
                 for (int q = 0; q < E; ++q) {
-                    f[q] = MIXED ? __double2float_ru(r[q] * (1.0 + A.band_r2)) : __double2float_ru(r[q]);
-                    fl[q] = MIXED ? __double2float_rd(r[q] * (1.0 - A.band_r2)) : f[q];
+                    f[q] = __double2float_ru(r[q]);
+                    fl[q] = f[q];
                     if (tl * E + q < count) {
                         const uint32_t bv = __float_as_uint(f[q]);
                         lo = bv < lo ? bv : lo;
@@ -732,15 +602,6 @@ __device__ __forceinline__ void team_target(const KnnArgs &A, int64_t base, int6
             }
             const bool sort_now = all_done || (need && bad);
             if (sort_now) {
-                if constexpr (MIXED) {
-                    // the ranking is FP64: exact r^2 of every entry
-#pragma unroll
-                    for (int q = 0; q < E; ++q)
-                        if (jj[q] >= 0) {
-                            const int32_t j = jj[q];
-                            r[q] = sep2_sel<PERIODIC>(px, py, pz, A.xs[j], A.ys[j], A.zs[j], box);
-                        }
-                }
                 team_sort_r2<E, TS>(r, jj, tl);
                 // equal r^2 within the first K1 places: placed by ID below
                 const double nx0 = __shfl(r[0], (tl + 1) % TS, TS);
@@ -795,16 +656,9 @@ __device__ __forceinline__ void team_target(const KnnArgs &A, int64_t base, int6
             if (all_done) break;
         }
 #pragma unroll
-        for (int u = 0; u < LPI; ++u) {
-            cur[u] = nxt[u];
+        for (int u = 0; u < LPI; ++u) cur[u] = nxt[u];
 #pragma unroll
-            for (int d = 0; d < 6; ++d) cb[u][d] = nb6[u][d];
-        }
-#pragma unroll
-        for (int q = 0; q < PS; ++q) {
-            cx[q] = nx[q]; cy[q] = ny[q]; cz[q] = nz[q];
-            fx[q] = gx[q]; fy[q] = gy[q]; fz[q] = gz[q];
-        }
+        for (int q = 0; q < PS; ++q) { cx[q] = nx[q]; cy[q] = ny[q]; cz[q] = nz[q]; }
     }
 
     const int32_t a = A.slot[b];
@@ -822,11 +676,11 @@ __device__ __forceinline__ void team_target(const KnnArgs &A, int64_t base, int6
     }
 }
 
-// Kernel B over a batch (one team per target), or, as the fallback of kernel
-// B', over the targets it left (fb_list), the grid striding over them.
-template <bool PERIODIC, int E, bool MIXED, int TS, int LPI, bool FB>
+// Kernel B as the fallback of kernel B': a team per target of fb_list (the
+// targets B' left), the grid striding over them.
+template <bool PERIODIC, int E, int TS, int LPI>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
-void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
+void k_knn_team(KnnArgs A, int64_t base)
 {
     constexpr int N = TS * E;
     constexpr int NT = 256 / TS;              // teams per workgroup
@@ -835,20 +689,13 @@ void k_knn_team(KnnArgs A, int64_t base, int64_t nblk)
     __shared__ int32_t s_j[NT][N];
     const int team = threadIdx.x / TS, tl = threadIdx.x % TS;
     const int wteam = team % (64 / TS);       // team within the wavefront
-    if constexpr (FB) {
-        const int cnt = *A.fb_count;
-        const int64_t stride = (int64_t)gridDim.x * NT;
-        for (int64_t f0 = 0; f0 < cnt; f0 += stride) {
-            const int64_t idx = f0 + (int64_t)blockIdx.x * NT + team;
-            if (idx < cnt)
-                team_target<PERIODIC, E, MIXED, TS, LPI>(A, base, A.fb_list[idx], s_r2[team], s_j[team],
-                                                         s_stack[team], tl, wteam);
-        }
-    } else {
-        const int64_t blk = xcd_block(nblk);
-        if (blk < 0) return;                  // whole workgroup
-        team_target<PERIODIC, E, MIXED, TS, LPI>(A, base, blk * NT + team, s_r2[team], s_j[team],
-                                                 s_stack[team], tl, wteam);
+    const int cnt = *A.fb_count;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t f0 = 0; f0 < cnt; f0 += stride) {
+        const int64_t idx = f0 + (int64_t)blockIdx.x * NT + team;
+        if (idx < cnt)
+            team_target<PERIODIC, E, TS, LPI>(A, base, A.fb_list[idx], s_r2[team], s_j[team],
+                                              s_stack[team], tl, wteam);
     }
 }
 
@@ -1237,32 +1084,23 @@ constexpr int kFallbackGrid = 2048;       // workgroups of the fallback launch (
 constexpr int kLeavesPerStep = 2;          // leaves a team tests per step of its loop
 constexpr int kListLanes = 16;             // lanes per target in the leaf-list kernel (measured: 2, 4, 8, 32, 64 slower on the 10^6 halo)
 
-// teams of TS lanes; the list holds TS * E entries; LPI leaves per step
-template <bool P, int E, bool M, int TS, int LPI>
-void launch_batches_l(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipStream_t s)
-{
-    for (int64_t base = 0; base < n_active; base += nb_cap) {
-        KnnArgs A = A0;
-        A.batch = (n_active - base) < nb_cap ? (n_active - base) : nb_cap;
-        constexpr int G = 64 / kListLanes;
-        const int64_t gl = (A.batch + G - 1) / G, gt = (A.batch + 256 / TS - 1) / (256 / TS);
-        k_knn_list<P, kListLanes><<<xcd_grid(gl), 64, 0, s>>>(A, base, gl);
-        if constexpr (M) {
-            k_knn_team<P, E, M, TS, LPI, false><<<xcd_grid(gt), 256, 0, s>>>(A, base, gt);
-        } else {
-            const int64_t gw = (A.batch + 3) / 4;
-            k_knn_bucket<P><<<xcd_grid(gw), 256, 0, s>>>(A, base, gw);
-            k_knn_team<P, E, M, TS, LPI, true><<<kFallbackGrid, 256, 0, s>>>(A, base, 0);
-        }
-    }
-}
-
-template <bool P, int E, bool M, int TS>
+// per batch: leaf lists and bounds, the sub-bucket search, then the root
+// walk (teams of TS lanes, lists of TS * E entries, LPI leaves a step) of the
+// targets it left
+template <bool P, int E, int TS>
 void launch_batches(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipStream_t s)
 {
     // two leaves a step where the list leaves room for them after a cut
     constexpr int LPI = (TS * E >= 2 * SIDM_LEAF + 48) ? kLeavesPerStep : 1;
-    launch_batches_l<P, E, M, TS, LPI>(A0, n_active, nb_cap, s);
+    for (int64_t base = 0; base < n_active; base += nb_cap) {
+        KnnArgs A = A0;
+        A.batch = (n_active - base) < nb_cap ? (n_active - base) : nb_cap;
+        constexpr int G = 64 / kListLanes;
+        const int64_t gl = (A.batch + G - 1) / G, gw = (A.batch + 3) / 4;
+        k_knn_list<P, kListLanes><<<xcd_grid(gl), 64, 0, s>>>(A, base, gl);
+        k_knn_bucket<P><<<xcd_grid(gw), 256, 0, s>>>(A, base, gw);
+        k_knn_team<P, E, TS, LPI><<<kFallbackGrid, 256, 0, s>>>(A, base);
+    }
 }
 
 }  // namespace
@@ -1280,23 +1118,17 @@ hipError_t launch_knn(sidm_ctx *c, int64_t n_active, int32_t *ngb, double *h)
     A.fb_list = c->knn_fb; A.fb_count = c->knn_fbn;
     A.lv = c->lv;
     A.n = c->n; A.k = c->cfg.n_ngb; A.box = c->cfg.box; A.batch = 0;
-    A.xo = c->xo; A.yo = c->yo; A.zo = c->zo;
-    A.band_r2 = c->cfg.band_r2;
     const bool per = c->cfg.periodic != 0;
-    const bool mixed = c->cfg.precision == SIDM_MIXED;
     const bool small = A.k + 1 + 32 <= 64;       // list of 64 suffices for k <= 31
     phase_begin(c, PH_KNN);
-    const int sel = (per ? 4 : 0) | (small ? 2 : 0) | (mixed ? 1 : 0);
+    // both precision forms: the search is exact, so it is the FP64 one
+    const int sel = (per ? 2 : 0) | (small ? 1 : 0);
     constexpr int B = 128 / kTeam, S = 64 / kTeam;   // lists of 128 and 64 entries
     switch (sel) {
-    case 0: launch_batches<false, B, false, kTeam>(A, n_active, c->knn_batch, c->stream); break;
-    case 1: launch_batches<false, B, true, kTeam>(A, n_active, c->knn_batch, c->stream); break;
-    case 2: launch_batches<false, S, false, kTeam>(A, n_active, c->knn_batch, c->stream); break;
-    case 3: launch_batches<false, S, true, kTeam>(A, n_active, c->knn_batch, c->stream); break;
-    case 4: launch_batches<true, B, false, kTeam>(A, n_active, c->knn_batch, c->stream); break;
-    case 5: launch_batches<true, B, true, kTeam>(A, n_active, c->knn_batch, c->stream); break;
-    case 6: launch_batches<true, S, false, kTeam>(A, n_active, c->knn_batch, c->stream); break;
-    default: launch_batches<true, S, true, kTeam>(A, n_active, c->knn_batch, c->stream); break;
+    case 0: launch_batches<false, B, kTeam>(A, n_active, c->knn_batch, c->stream); break;
+    case 1: launch_batches<false, S, kTeam>(A, n_active, c->knn_batch, c->stream); break;
+    case 2: launch_batches<true, B, kTeam>(A, n_active, c->knn_batch, c->stream); break;
+    default: launch_batches<true, S, kTeam>(A, n_active, c->knn_batch, c->stream); break;
     }
     phase_end(c, PH_KNN);
     return hipGetLastError();

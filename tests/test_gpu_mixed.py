@@ -1,6 +1,6 @@
-"""The mixed-precision form (FP32 neighbour test and probabilities on
-leaf-relative offsets, FP64 recheck inside the bands, FP64 kicks) against the
-oracle and against the plain FP64 form on the GPU."""
+"""The mixed-precision form (FP32 probabilities on leaf-relative offsets,
+FP64 recheck inside the band, FP64 kicks; the neighbour search is the exact
+FP64 one) against the oracle and against the plain FP64 form on the GPU."""
 import numpy as np
 import pytest
 
@@ -107,3 +107,71 @@ def test_mixed_without_bands_error_is_small():
     assert r["ngb_mismatch_rate"] <= 1e-3
     assert r["decision_mismatch_rate"] <= 1e-4
     assert r["energy_drift_mixed"] < 1e-12 and r["momentum_drift_mixed"] < 1e-12
+
+
+_NEAR_TIE_FLAG = 1e-13
+
+
+def _near_tie_workload():
+    """A periodic box where one candidate (among the 8 nearest) of each of up
+    to 4000 targets has its P within 1e-9 to 4e-9 (relative, both signs) of
+    its own decision draw u (0.2 < u): the target's dt is set so (at most 100
+    times the box's dt).  FP64 decides these robustly (rounding is ~1e-16,
+    and the flag band of this test, 1e-13, lies far below |P - u|); the FP32
+    probability errs by up to a few 1e-8."""
+    w = W.uniform_box(20000, ic_seed=211, philox_seed=21, scatters_per_particle=0.1)
+    ngb, h = oracle.find_ngb(w, brute=False)
+    m = w.mass
+    dt = np.array(w.dt, dtype=np.float64)
+    rng = np.random.Generator(np.random.PCG64(5))
+    tuned = []
+    for a in range(4000):
+        i = int(w.active[a])
+        s = int(rng.integers(0, 8))                  # a near partner: W well inside the kernel
+        j = int(ngb[a, s])
+        r = np.sqrt(oracle.r2((w.x[i], w.y[i], w.z[i]), (w.x[j], w.y[j], w.z[j]), True, 1.0))
+        wr = float(np.sqrt((w.vx[i] - w.vx[j]) ** 2 + (w.vy[i] - w.vy[j]) ** 2 +
+                           (w.vz[i] - w.vz[j]) ** 2))
+        p1 = 0.5 * m * oracle.sigma(wr, w.xsec, w.sigma0, w.w0) * wr * oracle.kernel(r, h[a])
+        u = oracle.uniform_decision(w.seed, w.step, int(w.id[i]), int(w.id[j]))
+        if not (p1 > 0.0 and 0.2 < u < 0.999):
+            continue
+        delta = (1.0 + 3.0 * rng.random()) * 1e-9 * (1.0 if a % 2 == 0 else -1.0)
+        d = u * (1.0 + delta) / p1
+        if d > 100.0 * dt[i]:
+            continue
+        dt[i] = d
+        tuned.append((a, s))
+    w.dt = dt
+    return w, tuned
+
+
+def test_mixed_bands_are_needed_on_near_ties():
+    """Negative control of the band: on the near-tie box the FP32
+    probabilities left unchecked (band 0) decide some tuned candidates
+    otherwise than FP64 (measured: 15 scatters missed and 31 velocities
+    changed of 1121 tuned candidates).  A wrong FP32 acceptance is undone at the
+    candidate's turn (evaluated in FP64), but a wrong rejection of a candidate
+    whose particles no earlier kick touched stands: scatters are missed and
+    velocities differ from the oracle's.  With the default band every tuned
+    candidate is rechecked in FP64 and the whole step equals the oracle's."""
+    w, tuned = _near_tie_workload()
+    _announce(f"mixed near ties, {len(tuned)} tuned candidates")
+    ref = oracle.full_step(w, band=_NEAR_TIE_FLAG)
+    acc_ref = (ref["info"] & oracle.CAND_ACCEPT0) != 0
+    ta = np.array([t[0] for t in tuned]), np.array([t[1] for t in tuned])
+    assert len(tuned) > 1000
+    assert acc_ref[ta].sum() > len(tuned) // 4             # both sides of u are present
+    assert ref["stats"]["n_flagged"] == 0
+    bare = gpu_step(w, precision=MIXED, band_p=0.0, flag_band=_NEAR_TIE_FLAG)
+    sc_ref = (ref["info"] & oracle.CAND_SCATTER) != 0
+    sc_bare = (bare["info"] & oracle.CAND_SCATTER) != 0
+    missed = int((sc_ref[ta] & ~sc_bare[ta]).sum())
+    dv = np.abs(bare["vx"] - ref["vx"]) + np.abs(bare["vy"] - ref["vy"]) + np.abs(bare["vz"] - ref["vz"])
+    moved = int((dv > 1e-12 * np.abs(ref["vx"]).max()).sum())
+    print(f"[mixed near ties] band 0: {missed} tuned scatters missed, {moved} velocities differ, "
+          f"{bare['stats']['n_events']} vs {ref['stats']['n_events']} events", flush=True)
+    assert missed >= 5 and moved >= 10
+    banded = gpu_step(w, precision=MIXED, flag_band=_NEAR_TIE_FLAG)
+    assert banded["stats"]["n_recheck"] >= len(tuned)
+    assert_parity(w, banded, ref, mixed=True)
