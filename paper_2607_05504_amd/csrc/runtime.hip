@@ -41,6 +41,48 @@ int64_t acc_capacity(const sidm_config &cfg, int64_t cap_active)
     return e > floor_cap ? e : floor_cap;
 }
 
+// The phase buffer holds what only one call uses while it runs: the tree
+// build's sort keys and values, then (over them) its 64-byte particle
+// records; the neighbour search's leaf lists, counts, bounds and fallback
+// list.  Offsets of each part, 256-byte aligned.
+struct PhaseLayout {
+    size_t key1, val0, val1, nl, fb, tb, total;
+};
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+static PhaseLayout phase_layout(int64_t N, int64_t batch)
+{
+    PhaseLayout L;
+    L.key1 = al256((size_t)N * 8);
+    L.val0 = L.key1 + al256((size_t)N * 8);
+    L.val1 = L.val0 + al256((size_t)N * 4);
+    const size_t tree = L.val1 + al256((size_t)N * 4);
+    const size_t rec = al256((size_t)N * 64);
+    L.nl = al256((size_t)batch * SIDM_KNN_LMAX * 4);
+    L.fb = L.nl + al256((size_t)batch * 4);
+    L.tb = L.fb + al256((size_t)batch * 4);
+    const size_t knn = L.tb + al256((size_t)batch * 8);
+    L.total = tree > rec ? tree : rec;
+    L.total = L.total > knn ? L.total : knn;
+    return L;
+}
+static size_t phase_bytes(int64_t N, int64_t batch) { return phase_layout(N, batch).total; }
+
+// the aliases into the phase buffer
+static void carve_phase(sidm_ctx *c)
+{
+    const PhaseLayout L = phase_layout(c->cap_n, c->knn_batch);
+    char *b = c->phase;
+    c->key0 = (uint64_t *)b;
+    c->key1 = (uint64_t *)(b + L.key1);
+    c->val0 = (int32_t *)(b + L.val0);
+    c->val1 = (int32_t *)(b + L.val1);
+    c->rec = (double *)b;                  // written after the sort is done with the keys
+    c->knn_list = (int32_t *)b;
+    c->knn_nl = (int32_t *)(b + L.nl);
+    c->knn_fb = (int32_t *)(b + L.fb);
+    c->knn_tb = (double *)(b + L.tb);
+}
+
 void make_plan(sidm_ctx *c, Plan &P)
 {
     const int64_t N = c->cap_n, NA = c->cap_active;
@@ -50,10 +92,7 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(xs, N, double); ADD(ys, N, double); ADD(zs, N, double);
     ADD(vxs, N, double); ADD(vys, N, double); ADD(vzs, N, double); ADD(ms, N, double);
     ADD(ids, N, uint32_t); ADD(sts, N, uint8_t);
-    ADD(rec, N * 8, double);
     ADD(perm, N, int32_t); ADD(inv, N, int32_t);
-    ADD(key0, N, uint64_t); ADD(key1, N, uint64_t);
-    ADD(val0, N, int32_t); ADD(val1, N, int32_t);
     const int64_t nsb = (N + SIDM_SORT_TILE - 1) / SIDM_SORT_TILE;
     ADD(hist, 256 * nsb, uint32_t);
     ADD(dtot, 6 * 256, uint32_t);
@@ -63,13 +102,15 @@ void make_plan(sidm_ctx *c, Plan &P)
     if (c->cfg.precision == SIDM_MIXED) {
         ADD(xo, N, float); ADD(yo, N, float); ADD(zo, N, float);
     }
-    c->knn_batch = NA < SIDM_KNN_BATCH ? NA : SIDM_KNN_BATCH;
-    ADD(knn_list, c->knn_batch * SIDM_KNN_LMAX, int32_t);
+    // neighbour-search batches of at most an eighth of the particles (at
+    // least 65536 targets, at most SIDM_KNN_BATCH): their leaf lists share
+    // the phase buffer below
+    int64_t kb = N / 8 > ((int64_t)1 << 16) ? N / 8 : ((int64_t)1 << 16);
+    kb = kb < SIDM_KNN_BATCH ? kb : SIDM_KNN_BATCH;
+    c->knn_batch = NA < kb ? NA : kb;
+    ADD(phase, phase_bytes(N, c->knn_batch), char);
     ADD(jsort, NA * (int64_t)k, int32_t);
-    ADD(knn_nl, c->knn_batch, int32_t);
-    ADD(knn_fb, c->knn_batch, int32_t);
     ADD(knn_fbn, 1, int32_t);
-    ADD(knn_tb, c->knn_batch, double);
     ADD(flag, N, int32_t);
     ADD(tlist, NA, int32_t); ADD(slot, NA, int32_t);
     ADD(blk, (N + SIDM_SCAN_TILE - 1) / SIDM_SCAN_TILE + 1, int32_t);
@@ -278,6 +319,7 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
         *P.items[t].dst = base + off;
         off += P.items[t].bytes;
     }
+    carve_phase(c);
     c->jsort_ngb = nullptr;
     c->jsort_knn = 0;
     if (hipHostMalloc((void **)&c->hstats, sizeof(DevStats) + 64, hipHostMallocDefault) != hipSuccess) {

@@ -135,7 +135,8 @@ struct sidm_ctx {
 
     // neighbour search: per-target leaf lists, processed in batches of knn_batch
     int64_t knn_batch;
-    int32_t *knn_list;       // [knn_batch][SIDM_KNN_LMAX]
+    char *phase;             // buffer of the tree build's and the search's temporaries
+    int32_t *knn_list;       // [knn_batch][SIDM_KNN_LMAX]   (in phase)
     // the rows in the tree's order: jsort[b * n_ngb + s] = sorted index of
     // neighbour s of the b-th target in Morton order (-1 for an index out of
     // range).  sidm_find_ngb writes them beside ngb; sidm_scatter_step checks

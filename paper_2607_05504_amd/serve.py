@@ -14,7 +14,8 @@ One step of a request is the scattering step through the C ABI
 (sidm_build_tree, sidm_find_ngb, sidm_scatter_step, sidm_pair_timestep) and
 then sidm_advance_hernquist, the leapfrog step in the halo's potential that
 stands in for gravity and sets the next global step length from the
-per-pair bounds.  The step latency reported is the device time of the
+per-pair bounds; the first step's length comes from the bounds of the
+initial state, computed at admission.  The step latency reported is the device time of the
 scattering part, from events on the slot's stream; request latency is
 arrival to completion on the host clock.
 
@@ -89,10 +90,11 @@ class Server:
 
     # -- memory --------------------------------------------------------------
     def _config(self, w, cap):
-        # a request's first step runs at the largest step length before any
-        # per-pair bound exists: far outside the criterion, up to about one
-        # candidate per particle accepts, so the list is sized for that
-        return runner.config_for(w, precision=self.cfg.precision, max_accept=max(cap, 1))
+        # every step's length keeps all P(i|j) below C_SIDM (the first one's
+        # from the bound at admission), so a step lists far fewer candidates
+        # than there are particles; half of them is room to spare
+        return runner.config_for(w, precision=self.cfg.precision,
+                                 max_accept=max(cap // 2, 1 << 16))
 
     def _ctx_bytes(self, w, cap):
         return footprint(self._config(w, cap), cap, cap)
@@ -167,6 +169,7 @@ class Server:
                     ds = runner.upload(w, "cuda")
                     out = runner.alloc_out(ds, w.n_ngb)
                     ctx = self._take_ctx(w, cap, stream)
+                    self._first_step_length(ctx, ds, out)
                 mem = ctx._serve_bytes + state_bytes(w.n, w.n_ngb)
                 self.used += mem
                 slots[k] = _Active(req, w, ds, out, ctx, cap, mem, admitted=time.perf_counter() - t0)
@@ -216,6 +219,21 @@ class Server:
                     mean_admission_wait_s=float(np.mean(waits)) if waits else 0.0,
                     max_admission_wait_s=float(np.max(waits)) if waits else 0.0,
                     n_requests=len(results))
+
+    def _first_step_length(self, ctx, ds, out):
+        """The first step's length, as every later one's: the largest
+        dt_cap / 2^b not above the smallest per-pair bound (sec. 4.4) of the
+        request's initial state (one host round trip at admission)."""
+        ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state,
+                       m_scalar=ds.mass)
+        ctx.find_ngb(ds.active, out.ngb, out.h)
+        ctx.pair_timestep(ds.active, out.ngb, out.h, out.dt_sidm, reuse_active=True)
+        m = float(out.dt_sidm.min().item()) if out.dt_sidm.numel() else float("inf")
+        d, b = float(self.cfg.dt_cap), 0
+        while not d <= m and b < 62:
+            d *= 0.5
+            b += 1
+        ds.dt.fill_(d)
 
     def _issue(self, s: _Active, stream):
         torch = self.torch

@@ -93,8 +93,9 @@ def _reqs(ns, steps, gap=0.0, s0_scale=(1.0, 3.0, 0.3, 10.0, 0.1, 2.0)):
 
 
 def test_served_request_matches_oracle_steps():
-    """Two served steps of one halo (scatter step, pair timestep, advance with
-    the step length from the bounds) against the oracle doing the same."""
+    """Two served steps of one halo (the first step's length from the bounds
+    of the initial state; scatter step, pair timestep, advance with the step
+    length from the bounds) against the oracle doing the same."""
     from paper_2607_05504_amd.serve import Server, ServeConfig
     req = _reqs([3000], steps=2)[0]
     _announce("served request n=3000 steps=2 vs oracle")
@@ -103,6 +104,9 @@ def test_served_request_matches_oracle_steps():
     srv.close()
     g = rep["results"][0]
     w = W.request_workload(req)
+    # the first step's length: from the per-pair bounds of the initial state
+    ngb0, h0 = oracle.find_ngb(w)
+    w.dt = np.full(w.n, oracle.step_length(oracle.pair_timestep(w, ngb0, h0), 0.25))
     for t in range(2):
         w.step = t
         r = oracle.full_step(w)
