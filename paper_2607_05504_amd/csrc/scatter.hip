@@ -842,6 +842,7 @@ __device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk
         const int32_t j = partner(A, c, (int64_t)a * A.stride + s);
         check_candidate<PERIODIC, OVERLAP>(A, A.tlist[b], a, s, j);
     };
+    const int sh = (A.stride & (A.stride - 1)) == 0 ? __ffs(A.stride) - 1 : -1;
     if (tid == 0) qn = 0;
     __syncthreads();
     // chunks of nth * kScanU candidates; a thread takes kScanU of a chunk,
@@ -849,20 +850,40 @@ __device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk
     for (int64_t c0 = first_chunk; c0 < total; c0 += chunk_stride) {
         int64_t cc[kScanU];
         int32_t jj[kScanU], ii[kScanU];
+        if (!OVERLAP && A.jsort) {
+            // rows in the tree's order: the partner is jsort[c], the target
+            // tlist[c / k] (a shift for k a power of two)
 #pragma unroll
-        for (int u = 0; u < kScanU; ++u) {
-            const int64_t c = c0 + u * nth + tid;
-            cc[u] = c;
-            jj[u] = -1;
-            ii[u] = 0;
-            if (c < total) {
-                const int64_t b = total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)A.stride)
-                                                     : c / A.stride;
-                const int s = (int)(c - b * A.stride);
-                const int32_t a = A.slot[b];
-                if (!OVERLAP || s < A.cnt[a]) {
-                    jj[u] = partner(A, c, (int64_t)a * A.stride + s);
+            for (int u = 0; u < kScanU; ++u) {
+                const int64_t c = c0 + u * nth + tid;
+                cc[u] = c;
+                jj[u] = -1;
+                ii[u] = 0;
+                if (c < total) {
+                    const int64_t b = sh >= 0 ? (c >> sh)
+                                              : (total < 0x7fffffff
+                                                     ? (int64_t)((uint32_t)c / (uint32_t)A.stride)
+                                                     : c / A.stride);
+                    jj[u] = A.jsort[c];
                     ii[u] = A.tlist[b];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kScanU; ++u) {
+                const int64_t c = c0 + u * nth + tid;
+                cc[u] = c;
+                jj[u] = -1;
+                ii[u] = 0;
+                if (c < total) {
+                    const int64_t b = total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)A.stride)
+                                                         : c / A.stride;
+                    const int s = (int)(c - b * A.stride);
+                    const int32_t a = A.slot[b];
+                    if (!OVERLAP || s < A.cnt[a]) {
+                        jj[u] = partner(A, c, (int64_t)a * A.stride + s);
+                        ii[u] = A.tlist[b];
+                    }
                 }
             }
         }
