@@ -1086,20 +1086,44 @@ constexpr int kListLanes = 16;             // lanes per target in the leaf-list 
 
 // per batch: leaf lists and bounds, the sub-bucket search, then the root
 // walk (teams of TS lanes, lists of TS * E entries, LPI leaves a step) of the
-// targets it left
+// targets it left.  With several batches the root walk of a batch runs on the
+// context's second stream while the next batch is searched: the batches
+// alternate between two sets of counts, bounds and fallback lists (the leaf
+// lists, which the walk does not read, are shared), and a set is reused only
+// after the walk that read it has finished; the main stream waits for the
+// last walks before the call returns.
 template <bool P, int E, int TS>
-void launch_batches(const KnnArgs &A0, int64_t n_active, int64_t nb_cap, hipStream_t s)
+void launch_batches(sidm_ctx *c, const KnnArgs &A0, int64_t n_active)
 {
     // two leaves a step where the list leaves room for them after a cut
     constexpr int LPI = (TS * E >= 2 * SIDM_LEAF + 48) ? kLeavesPerStep : 1;
-    for (int64_t base = 0; base < n_active; base += nb_cap) {
+    const int64_t nb_cap = c->knn_batch;
+    const hipStream_t s = c->stream;
+    const bool fork = n_active > nb_cap;
+    int t = 0;
+    for (int64_t base = 0; base < n_active; base += nb_cap, ++t) {
+        const int q = t & 1;
         KnnArgs A = A0;
         A.batch = (n_active - base) < nb_cap ? (n_active - base) : nb_cap;
+        A.nl = c->knn_nl[q]; A.tb = c->knn_tb[q];
+        A.fb_list = c->knn_fb[q]; A.fb_count = c->knn_fbn[q];
+        if (fork && t >= 2) (void)hipStreamWaitEvent(s, c->knn_ev[q][1], 0);
         constexpr int G = 64 / kListLanes;
         const int64_t gl = (A.batch + G - 1) / G, gw = (A.batch + 3) / 4;
         k_knn_list<P, kListLanes><<<xcd_grid(gl), 64, 0, s>>>(A, base, gl);
         k_knn_bucket<P><<<xcd_grid(gw), 256, 0, s>>>(A, base, gw);
-        k_knn_team<P, E, TS, LPI><<<kFallbackGrid, 256, 0, s>>>(A, base);
+        if (fork) {
+            (void)hipEventRecord(c->knn_ev[q][0], s);
+            (void)hipStreamWaitEvent(c->knn_aux, c->knn_ev[q][0], 0);
+            k_knn_team<P, E, TS, LPI><<<kFallbackGrid, 256, 0, c->knn_aux>>>(A, base);
+            (void)hipEventRecord(c->knn_ev[q][1], c->knn_aux);
+        } else {
+            k_knn_team<P, E, TS, LPI><<<kFallbackGrid, 256, 0, s>>>(A, base);
+        }
+    }
+    if (fork) {
+        (void)hipStreamWaitEvent(s, c->knn_ev[0][1], 0);
+        if (t > 1) (void)hipStreamWaitEvent(s, c->knn_ev[1][1], 0);
     }
 }
 
@@ -1114,8 +1138,7 @@ hipError_t launch_knn(sidm_ctx *c, int64_t n_active, int32_t *ngb, double *h)
     A.tlist = c->tlist; A.slot = c->slot; A.nt_dev = c->nt_dev;
     A.ngb = ngb; A.h = h; A.derr = c->derr;
     A.jsort = c->jsort;
-    A.list = c->knn_list; A.nl = c->knn_nl; A.tb = c->knn_tb;
-    A.fb_list = c->knn_fb; A.fb_count = c->knn_fbn;
+    A.list = c->knn_list;
     A.lv = c->lv;
     A.n = c->n; A.k = c->cfg.n_ngb; A.box = c->cfg.box; A.batch = 0;
     const bool per = c->cfg.periodic != 0;
@@ -1125,10 +1148,10 @@ hipError_t launch_knn(sidm_ctx *c, int64_t n_active, int32_t *ngb, double *h)
     const int sel = (per ? 2 : 0) | (small ? 1 : 0);
     constexpr int B = 128 / kTeam, S = 64 / kTeam;   // lists of 128 and 64 entries
     switch (sel) {
-    case 0: launch_batches<false, B, kTeam>(A, n_active, c->knn_batch, c->stream); break;
-    case 1: launch_batches<false, S, kTeam>(A, n_active, c->knn_batch, c->stream); break;
-    case 2: launch_batches<true, B, kTeam>(A, n_active, c->knn_batch, c->stream); break;
-    default: launch_batches<true, S, kTeam>(A, n_active, c->knn_batch, c->stream); break;
+    case 0: launch_batches<false, B, kTeam>(c, A, n_active); break;
+    case 1: launch_batches<false, S, kTeam>(c, A, n_active); break;
+    case 2: launch_batches<true, B, kTeam>(c, A, n_active); break;
+    default: launch_batches<true, S, kTeam>(c, A, n_active); break;
     }
     phase_end(c, PH_KNN);
     return hipGetLastError();

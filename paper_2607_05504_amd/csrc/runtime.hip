@@ -46,7 +46,7 @@ int64_t acc_capacity(const sidm_config &cfg, int64_t cap_active)
 // records; the neighbour search's leaf lists, counts, bounds and fallback
 // list.  Offsets of each part, 256-byte aligned.
 struct PhaseLayout {
-    size_t key1, val0, val1, nl, fb, tb, total;
+    size_t key1, val0, val1, nl[2], fb[2], tb[2], total;
 };
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 static PhaseLayout phase_layout(int64_t N, int64_t batch)
@@ -57,10 +57,13 @@ static PhaseLayout phase_layout(int64_t N, int64_t batch)
     L.val1 = L.val0 + al256((size_t)N * 4);
     const size_t tree = L.val1 + al256((size_t)N * 4);
     const size_t rec = al256((size_t)N * 64);
-    L.nl = al256((size_t)batch * SIDM_KNN_LMAX * 4);
-    L.fb = L.nl + al256((size_t)batch * 4);
-    L.tb = L.fb + al256((size_t)batch * 4);
-    const size_t knn = L.tb + al256((size_t)batch * 8);
+    size_t o = al256((size_t)batch * SIDM_KNN_LMAX * 4);
+    for (int q = 0; q < 2; ++q) {
+        L.nl[q] = o; o += al256((size_t)batch * 4);
+        L.fb[q] = o; o += al256((size_t)batch * 4);
+        L.tb[q] = o; o += al256((size_t)batch * 8);
+    }
+    const size_t knn = o;
     L.total = tree > rec ? tree : rec;
     L.total = L.total > knn ? L.total : knn;
     return L;
@@ -78,9 +81,11 @@ static void carve_phase(sidm_ctx *c)
     c->val1 = (int32_t *)(b + L.val1);
     c->rec = (double *)b;                  // written after the sort is done with the keys
     c->knn_list = (int32_t *)b;
-    c->knn_nl = (int32_t *)(b + L.nl);
-    c->knn_fb = (int32_t *)(b + L.fb);
-    c->knn_tb = (double *)(b + L.tb);
+    for (int q = 0; q < 2; ++q) {
+        c->knn_nl[q] = (int32_t *)(b + L.nl[q]);
+        c->knn_fb[q] = (int32_t *)(b + L.fb[q]);
+        c->knn_tb[q] = (double *)(b + L.tb[q]);
+    }
 }
 
 void make_plan(sidm_ctx *c, Plan &P)
@@ -110,7 +115,7 @@ void make_plan(sidm_ctx *c, Plan &P)
     c->knn_batch = NA < kb ? NA : kb;
     ADD(phase, phase_bytes(N, c->knn_batch), char);
     ADD(jsort, NA * (int64_t)k, int32_t);
-    ADD(knn_fbn, 1, int32_t);
+    ADD(knn_fbn[0], 1, int32_t); ADD(knn_fbn[1], 1, int32_t);
     ADD(flag, N, int32_t);
     ADD(tlist, NA, int32_t); ADD(slot, NA, int32_t);
     ADD(blk, (N + SIDM_SCAN_TILE - 1) / SIDM_SCAN_TILE + 1, int32_t);
@@ -286,6 +291,22 @@ sidm_status sidm_footprint(const sidm_config *cfg, int64_t cap_n, int64_t cap_ac
     return SIDM_OK;
 }
 
+// the search's second stream and events (those that exist)
+static void release_aux(sidm_ctx *c)
+{
+    if (c->knn_aux) {
+        (void)hipStreamSynchronize(c->knn_aux);
+        (void)hipStreamDestroy(c->knn_aux);
+        c->knn_aux = nullptr;
+    }
+    for (int q = 0; q < 2; ++q)
+        for (int e = 0; e < 2; ++e)
+            if (c->knn_ev[q][e]) {
+                (void)hipEventDestroy(c->knn_ev[q][e]);
+                c->knn_ev[q][e] = nullptr;
+            }
+}
+
 sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_active, void *hip_stream,
                         sidm_ctx **out)
 {
@@ -328,6 +349,19 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
         return SIDM_E_NOMEM;
     }
     c->herr = (unsigned int *)((char *)c->hstats + sizeof(DevStats));
+    // the search's second stream and its fork/join events
+    bool ok = hipStreamCreateWithFlags(&c->knn_aux, hipStreamNonBlocking) == hipSuccess;
+    for (int q = 0; q < 2 && ok; ++q)
+        for (int e = 0; e < 2 && ok; ++e)
+            ok = hipEventCreateWithFlags(&c->knn_ev[q][e], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        release_aux(c);
+        (void)hipFree(base);
+        (void)hipHostFree(c->hstats);
+        free(c);
+        return SIDM_E_DEVICE;
+    }
     hipStream_t s = c->stream;
     // claims start cleared; error word and counters zero
     for (int b = 0; b < 2; ++b) {
@@ -410,6 +444,7 @@ sidm_status sidm_destroy(sidm_ctx *c)
 {
     if (!c) return SIDM_E_INVAL;
     (void)hipStreamSynchronize(c->stream);
+    release_aux(c);
     for (int p = 0; p < SIDM_PHASES; ++p)
         for (int r = 0; r < SIDM_TIMING_RING; ++r)
             for (int b = 0; b < 2; ++b)

@@ -145,10 +145,14 @@ struct sidm_ctx {
     int32_t *jsort;          // [cap_active * n_ngb]
     const int32_t *jsort_ngb;     // the ngb they match, NULL if none
     int jsort_knn;           // they are the last sidm_find_ngb's, for the current mapping
-    int32_t *knn_nl;         // [knn_batch]
-    int32_t *knn_fb;         // [knn_batch] targets of a batch left to the root walk
-    int32_t *knn_fbn;        // [1] their number
-    double *knn_tb;          // [knn_batch]
+    // per batch, in two sets that alternate between batches (a batch's root
+    // walk runs on knn_aux while the next batch is searched)
+    int32_t *knn_nl[2];      // [knn_batch]   (in phase)
+    int32_t *knn_fb[2];      // [knn_batch] targets of a batch left to the root walk (in phase)
+    int32_t *knn_fbn[2];     // [1] their number
+    hipStream_t knn_aux;     // default priority
+    hipEvent_t knn_ev[2][2]; // [set][0: sub-bucket kernel done, 1: root walk done]
+    double *knn_tb[2];       // [knn_batch]   (in phase)
 
     // active set in Morton order
     int32_t *flag;           // [cap_n] caller slot of an active particle, or -1
