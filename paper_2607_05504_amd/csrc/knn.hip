@@ -6,7 +6,7 @@
 // SIDM_LEAF Morton-consecutive particles, each split into sub-buckets of
 // SIDM_SUB with their own boxes; SIDM_TREE_FAN-ary parents):
 //
-//  k_knn_list   sixteen lanes per target, four targets per wavefront.  A valid
+//  k_knn_list   four lanes per target, sixteen targets per wavefront.  A valid
 //               upper bound T on r^2 of the (N_ngb+1)-th neighbour comes from
 //               the target's Morton-order neighbours (64 on each side): their
 //               (N_ngb+1)-th smallest r^2, bracketed in FP32 rounded up, so the
@@ -1082,7 +1082,7 @@ constexpr int kTeam = 16;                 // lanes per target in the team kernel
 
 constexpr int kFallbackGrid = 2048;       // workgroups of the fallback launch (they stride over its targets)
 constexpr int kLeavesPerStep = 2;          // leaves a team tests per step of its loop
-constexpr int kListLanes = 16;             // lanes per target in the leaf-list kernel (measured: 2, 4, 8, 32, 64 slower on the 10^6 halo)
+constexpr int kListLanes = 4;              // lanes per target in the leaf-list kernel (16 targets a wavefront share its walk; 16 and 8 lanes measured slower on the 256^3 box)
 
 // per batch: leaf lists and bounds, the sub-bucket search, then the root
 // walk (teams of TS lanes, lists of TS * E entries, LPI leaves a step) of the
