@@ -17,7 +17,7 @@
 //               own sphere.
 //
 //  k_knn_bucket one wavefront per target.  The sub-buckets of its leaves that
-//               meet the sphere, then their particles, four a lane a round; those
+//               meet the sphere, then their particles, two a lane a round; those
 //               within the radius go to an LDS list, cut to the (N_ngb+1)-th
 //               smallest when a round might not fit (bisection on ballot
 //               counts); at the end each survivor's exact r^2 and its rank in
@@ -716,7 +716,7 @@ void k_knn_team(KnnArgs A, int64_t base)
 // list cannot be cut (many equal r^2), are left to kernel B's root walk.
 constexpr int kSubPerLeaf = SIDM_LEAF / SIDM_SUB;
 constexpr int kKeepMax = 384;                 // kept sub-buckets per target (more: the root walk)
-constexpr int kRound = 4;                     // particles a lane tests per round
+constexpr int kRound = 2;                     // particles a lane tests per round (1, 3, 4 measured slower)
 constexpr int kHitCap = 64 * (kRound + 2);    // list entries per target
 constexpr int kHitQ = kHitCap / 64;           // list entries per lane
 // dword 3 of a raw buffer resource on gfx9-family parts (32-bit data format)
