@@ -6,7 +6,7 @@
 // SIDM_LEAF Morton-consecutive particles, each split into sub-buckets of
 // SIDM_SUB with their own boxes; SIDM_TREE_FAN-ary parents):
 //
-//  k_knn_list   four lanes per target, sixteen targets per wavefront.  A valid
+//  k_knn_list   four (large batches) or sixteen lanes per target.  A valid
 //               upper bound T on r^2 of the (N_ngb+1)-th neighbour comes from
 //               the target's Morton-order neighbours (64 on each side): their
 //               (N_ngb+1)-th smallest r^2, bracketed in FP32 rounded up, so the
@@ -1082,7 +1082,14 @@ constexpr int kTeam = 16;                 // lanes per target in the team kernel
 
 constexpr int kFallbackGrid = 2048;       // workgroups of the fallback launch (they stride over its targets)
 constexpr int kLeavesPerStep = 2;          // leaves a team tests per step of its loop
-constexpr int kListLanes = 4;              // lanes per target in the leaf-list kernel (16 targets a wavefront share its walk; 16 and 8 lanes measured slower on the 256^3 box)
+// lanes per target in the leaf-list kernel: four (sixteen targets share a
+// wavefront's group walk) for batches of at least kListWide targets, else
+// sixteen (four targets a wavefront, more wavefronts for small batches).
+// Measured: 256^3 box 78.5 -> 73.3 ms with four (8: 74.1); the 10^6 halo's
+// 95,360 targets 0.49 ms with sixteen against 0.72 with four
+constexpr int kListLanesWide = 4;
+constexpr int kListLanesNarrow = 16;
+constexpr int64_t kListWide = 1 << 18;
 
 // per batch: leaf lists and bounds, the sub-bucket search, then the root
 // walk (teams of TS lanes, lists of TS * E entries, LPI leaves a step) of the
@@ -1108,9 +1115,16 @@ void launch_batches(sidm_ctx *c, const KnnArgs &A0, int64_t n_active)
         A.nl = c->knn_nl[q]; A.tb = c->knn_tb[q];
         A.fb_list = c->knn_fb[q]; A.fb_count = c->knn_fbn[q];
         if (fork && t >= 2) (void)hipStreamWaitEvent(s, c->knn_ev[q][1], 0);
-        constexpr int G = 64 / kListLanes;
-        const int64_t gl = (A.batch + G - 1) / G, gw = (A.batch + 3) / 4;
-        k_knn_list<P, kListLanes><<<xcd_grid(gl), 64, 0, s>>>(A, base, gl);
+        const int64_t gw = (A.batch + 3) / 4;
+        if (A.batch >= kListWide) {
+            constexpr int G = 64 / kListLanesWide;
+            const int64_t gl = (A.batch + G - 1) / G;
+            k_knn_list<P, kListLanesWide><<<xcd_grid(gl), 64, 0, s>>>(A, base, gl);
+        } else {
+            constexpr int G = 64 / kListLanesNarrow;
+            const int64_t gl = (A.batch + G - 1) / G;
+            k_knn_list<P, kListLanesNarrow><<<xcd_grid(gl), 64, 0, s>>>(A, base, gl);
+        }
         k_knn_bucket<P><<<xcd_grid(gw), 256, 0, s>>>(A, base, gw);
         if (fork) {
             (void)hipEventRecord(c->knn_ev[q][0], s);
