@@ -123,6 +123,18 @@ __device__ __forceinline__ int32_t partner(const StepArgs &A, int64_t c, int64_t
     return (jc >= 0 && jc < A.n) ? A.inv[jc] : -1;
 }
 
+// Target of candidate c (rows of stride entries): a shift for a power-of-two
+// stride (sh >= 0), else a 32-bit division while the candidates fit 31 bits.
+__device__ __forceinline__ int64_t row_of_cand(int64_t c, int sh, int stride, int64_t total)
+{
+    if (sh >= 0) return c >> sh;
+    return total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)stride) : c / stride;
+}
+__device__ __forceinline__ int stride_shift(int stride)
+{
+    return (stride & (stride - 1)) == 0 ? __ffs(stride) - 1 : -1;
+}
+
 __device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
 
 // wave-aggregated counter increment; returns this lane's slot (valid lanes only)
@@ -328,6 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
     __shared__ unsigned long long s_red[4][6];
     const int64_t nt = *A.nt_dev;
     const int64_t total = nt * A.stride;
+    const int sh = stride_shift(A.stride);
     unsigned long long maxp = 0, n_fl = 0, n_ge1 = 0, n_acc = 0, n_rc = 0, n_cd = 0;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
@@ -339,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
         int s = 0;
         int32_t a = 0;
         if (live) {
-            b = total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)A.stride) : c / A.stride;
+            b = row_of_cand(c, sh, A.stride, total);
             s = (int)(c - b * A.stride);
             a = A.slot[b];
             if (OVERLAP) live = s < A.cnt[a];
@@ -842,7 +855,7 @@ __device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk
         const int32_t j = partner(A, c, (int64_t)a * A.stride + s);
         check_candidate<PERIODIC, OVERLAP>(A, A.tlist[b], a, s, j);
     };
-    const int sh = (A.stride & (A.stride - 1)) == 0 ? __ffs(A.stride) - 1 : -1;
+    const int sh = stride_shift(A.stride);
     if (tid == 0) qn = 0;
     __syncthreads();
     // chunks of nth * kScanU candidates; a thread takes kScanU of a chunk,
@@ -1184,28 +1197,56 @@ __device__ __forceinline__ double dt_from_rate(const StepArgs &A, int32_t i, dou
     return rmax > 0.0 ? (2.0 * c_sidm) / ((mass_of(A, i) * W0) * rmax) : INFINITY;
 }
 
+// A row of k (a power of two, at most 64) candidates per k lanes; the row's
+// maximum by shuffles.  CONST: sigma is constant, so w sigma rises with w^2
+// and, sqrt and the products rounding monotonically, the largest rate is
+// that of the largest w^2: the lanes carry w^2 and the row's first lane
+// takes one square root (the same value as the largest of the rates).
+template <bool CONST>
 __global__ __launch_bounds__(kBlock) void k_timestep_group(StepArgs A, double c_sidm, double *dt_out)
 {
     const int64_t nt = *A.nt_dev;
     const int64_t total = nt * A.k;
+    const int sh = __ffs(A.k) - 1;
     for (int64_t c0 = xcd_stride_block() * (int64_t)blockDim.x; c0 < total;
          c0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = c0 + threadIdx.x;
         const bool in = c < total;
-        const int64_t b = in ? c / A.k : 0;
-        const int s = (int)(c - b * A.k);
-        double rate = 0.0;
+        const int64_t b = in ? c >> sh : 0;
+        const int s = (int)(c - (b << sh));
+        double v = CONST ? -1.0 : 0.0;
         int32_t i = 0, a = 0;
         if (in) {
             i = A.tlist[b];
             a = A.slot[b];
-            rate = pair_rate(A, A.vxs[i], A.vys[i], A.vzs[i], partner(A, c, (int64_t)a * A.k + s));
+            const int32_t j = partner(A, c, (int64_t)a * A.k + s);
+            if constexpr (CONST) {
+                if (j < 0) {
+                    atomicOr(A.derr, DERR_INDEX);
+                } else {
+                    const double dx = A.vxs[i] - A.vxs[j], dy = A.vys[i] - A.vys[j],
+                                 dz = A.vzs[i] - A.vzs[j];
+                    v = (dx * dx + dy * dy) + dz * dz;
+                }
+            } else {
+                v = pair_rate(A, A.vxs[i], A.vys[i], A.vzs[i], j);
+            }
         }
         for (int off = 1; off < A.k; off <<= 1) {
-            const double o = __shfl_xor(rate, off);
-            rate = o > rate ? o : rate;
+            const double o = __shfl_xor(v, off);
+            v = o > v ? o : v;
         }
-        if (in && s == 0) dt_out[a] = dt_from_rate(A, i, A.h[a], rate, c_sidm);
+        if (in && s == 0) {
+            double rate = v;
+            if constexpr (CONST) {
+                rate = 0.0;
+                if (v >= 0.0) {
+                    const double w = A.vphys * sqrt(v);
+                    rate = w * sigma_of(A, w);
+                }
+            }
+            dt_out[a] = dt_from_rate(A, i, A.h[a], rate, c_sidm);
+        }
     }
 }
 
@@ -1313,9 +1354,10 @@ int grid_for(int64_t n, int cap = 8192)
 __global__ __launch_bounds__(kBlock) void k_rows(StepArgs A, int have)
 {
     const int64_t total = (int64_t)(*A.nt_dev) * A.stride;
+    const int sh = stride_shift(A.stride);
     for (int64_t c = xcd_stride_block() * (int64_t)kBlock + threadIdx.x; c < total;
          c += (int64_t)gridDim.x * kBlock) {
-        const int64_t b = total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)A.stride) : c / A.stride;
+        const int64_t b = row_of_cand(c, sh, A.stride, total);
         const int s = (int)(c - b * A.stride);
         const int32_t jc = A.ngb[(int64_t)A.slot[b] * A.stride + s];
         int32_t j = have ? A.jsort[c] : -1;
@@ -1399,9 +1441,14 @@ hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, co
     if (ngb && c->jsort_ngb == ngb) A.jsort = c->jsort;
     phase_begin(c, PH_TIMESTEP);
     const int k = A.k;
-    if (k <= 64 && (k & (k - 1)) == 0)
-        k_timestep_group<<<grid_for(n_active * k, 65536), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm,
-                                                                             dt_out);
+    if (k <= 64 && (k & (k - 1)) == 0) {
+        if (c->cfg.xsec == SIDM_XSEC_CONST)
+            k_timestep_group<true><<<grid_for(n_active * k, 65536), kBlock, 0, c->stream>>>(
+                A, c->cfg.c_sidm, dt_out);
+        else
+            k_timestep_group<false><<<grid_for(n_active * k, 65536), kBlock, 0, c->stream>>>(
+                A, c->cfg.c_sidm, dt_out);
+    }
     else
         k_timestep<<<grid_for(n_active), kBlock, 0, c->stream>>>(A, c->cfg.c_sidm, dt_out);
     phase_end(c, PH_TIMESTEP);
