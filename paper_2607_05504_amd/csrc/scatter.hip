@@ -1197,46 +1197,64 @@ __device__ __forceinline__ double dt_from_rate(const StepArgs &A, int32_t i, dou
     return rmax > 0.0 ? (2.0 * c_sidm) / ((mass_of(A, i) * W0) * rmax) : INFINITY;
 }
 
-// A row of k (a power of two, at most 64) candidates per k lanes; the row's
-// maximum by shuffles.  CONST: sigma is constant, so w sigma rises with w^2
-// and, sqrt and the products rounding monotonically, the largest rate is
-// that of the largest w^2: the lanes carry w^2 and the row's first lane
-// takes one square root (the same value as the largest of the rates).
+// A row of k (a power of two, at most 64) candidates per k / U lanes, U =
+// min(4, k) candidates a lane (lane l takes l, l + k/U, ...); the row's
+// maximum in registers, then by shuffles.  CONST: sigma is constant, so
+// w sigma rises with w^2 and, sqrt and the products rounding monotonically,
+// the largest rate is that of the largest w^2: the lanes carry w^2 and the
+// row's first lane takes one square root (the same value as the largest of
+// the rates).
 template <bool CONST>
 __global__ __launch_bounds__(kBlock) void k_timestep_group(StepArgs A, double c_sidm, double *dt_out)
 {
+    constexpr int UMAX = 4;
     const int64_t nt = *A.nt_dev;
-    const int64_t total = nt * A.k;
-    const int sh = __ffs(A.k) - 1;
-    for (int64_t c0 = xcd_stride_block() * (int64_t)blockDim.x; c0 < total;
-         c0 += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = c0 + threadIdx.x;
-        const bool in = c < total;
-        const int64_t b = in ? c >> sh : 0;
-        const int s = (int)(c - (b << sh));
+    const int k = A.k;
+    const int U = k < UMAX ? k : UMAX;
+    const int L = k / U;                      // lanes per row (a power of two)
+    const int lsh = __ffs(L) - 1;
+    const int64_t total = nt << lsh;          // lanes in all
+    for (int64_t t0 = xcd_stride_block() * (int64_t)blockDim.x; t0 < total;
+         t0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = t0 + threadIdx.x;
+        const bool in = t < total;
+        const int64_t b = in ? t >> lsh : 0;
+        const int l = (int)(t & (L - 1));
         double v = CONST ? -1.0 : 0.0;
         int32_t i = 0, a = 0;
         if (in) {
             i = A.tlist[b];
             a = A.slot[b];
-            const int32_t j = partner(A, c, (int64_t)a * A.k + s);
-            if constexpr (CONST) {
-                if (j < 0) {
-                    atomicOr(A.derr, DERR_INDEX);
+            const double vix = A.vxs[i], viy = A.vys[i], viz = A.vzs[i];
+            int32_t jj[UMAX];
+#pragma unroll
+            for (int u = 0; u < UMAX; ++u) {
+                const int s = l + u * L;
+                jj[u] = u < U ? partner(A, b * k + s, (int64_t)a * k + s) : -2;
+            }
+#pragma unroll
+            for (int u = 0; u < UMAX; ++u) {
+                const int32_t j = jj[u];
+                if (j == -2) continue;
+                if constexpr (CONST) {
+                    if (j < 0) {
+                        atomicOr(A.derr, DERR_INDEX);
+                    } else {
+                        const double dx = vix - A.vxs[j], dy = viy - A.vys[j], dz = viz - A.vzs[j];
+                        const double w2 = (dx * dx + dy * dy) + dz * dz;
+                        v = w2 > v ? w2 : v;
+                    }
                 } else {
-                    const double dx = A.vxs[i] - A.vxs[j], dy = A.vys[i] - A.vys[j],
-                                 dz = A.vzs[i] - A.vzs[j];
-                    v = (dx * dx + dy * dy) + dz * dz;
+                    const double r = pair_rate(A, vix, viy, viz, j);
+                    v = r > v ? r : v;
                 }
-            } else {
-                v = pair_rate(A, A.vxs[i], A.vys[i], A.vzs[i], j);
             }
         }
-        for (int off = 1; off < A.k; off <<= 1) {
+        for (int off = 1; off < L; off <<= 1) {
             const double o = __shfl_xor(v, off);
             v = o > v ? o : v;
         }
-        if (in && s == 0) {
+        if (in && l == 0) {
             double rate = v;
             if constexpr (CONST) {
                 rate = 0.0;
@@ -1442,11 +1460,12 @@ hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, co
     phase_begin(c, PH_TIMESTEP);
     const int k = A.k;
     if (k <= 64 && (k & (k - 1)) == 0) {
+        const int64_t lanes = n_active * (k < 4 ? 1 : k / 4);
         if (c->cfg.xsec == SIDM_XSEC_CONST)
-            k_timestep_group<true><<<grid_for(n_active * k, 65536), kBlock, 0, c->stream>>>(
+            k_timestep_group<true><<<grid_for(lanes, 65536), kBlock, 0, c->stream>>>(
                 A, c->cfg.c_sidm, dt_out);
         else
-            k_timestep_group<false><<<grid_for(n_active * k, 65536), kBlock, 0, c->stream>>>(
+            k_timestep_group<false><<<grid_for(lanes, 65536), kBlock, 0, c->stream>>>(
                 A, c->cfg.c_sidm, dt_out);
     }
     else
