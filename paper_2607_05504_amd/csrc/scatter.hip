@@ -840,6 +840,7 @@ __device__ void check_candidate(const StepArgs &A, int32_t i, int32_t a, int s, 
 // busy (in the first round about one candidate in a hundred hits on the
 // 256^3 box: evaluated where found, most lanes of a wavefront would wait).
 constexpr int kScanU = 8;          // candidates a thread scans per round of the loop
+static_assert(kScanU % 4 == 0, "the row-wise scan takes four candidates of a row a lane");
 
 template <bool PERIODIC, bool OVERLAP>
 __device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk_stride,
@@ -862,26 +863,35 @@ __device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk
     // nth apart, with their loads independent of each other
     for (int64_t c0 = first_chunk; c0 < total; c0 += chunk_stride) {
         int64_t cc[kScanU];
-        int32_t jj[kScanU], ii[kScanU];
-        if (!OVERLAP && A.jsort) {
-            // rows in the tree's order: the partner is jsort[c], the target
-            // tlist[c / k] (a shift for k a power of two)
+        bool hit[kScanU];
+        if (!OVERLAP && A.jsort && sh >= 2) {
+            // rows in the tree's order, k = 2^sh >= 4: a lane takes four
+            // candidates of a row (k / 4 lanes a row, kScanU / 4 rows a lane),
+            // the target tlist[b] and its D bit once, the partners jsort[c]
+            const int lsh = sh - 2;
+            const int L = 1 << lsh;
+            const int64_t b0 = c0 >> sh;
+            const int rows_pass = nth >> lsh;
+            int32_t jv[kScanU];
+            bool di[kScanU / 4];
 #pragma unroll
-            for (int u = 0; u < kScanU; ++u) {
-                const int64_t c = c0 + u * nth + tid;
-                cc[u] = c;
-                jj[u] = -1;
-                ii[u] = 0;
-                if (c < total) {
-                    const int64_t b = sh >= 0 ? (c >> sh)
-                                              : (total < 0x7fffffff
-                                                     ? (int64_t)((uint32_t)c / (uint32_t)A.stride)
-                                                     : c / A.stride);
-                    jj[u] = A.jsort[c];
-                    ii[u] = A.tlist[b];
+            for (int p = 0; p < kScanU / 4; ++p) {
+                const int64_t b = b0 + p * rows_pass + (tid >> lsh);
+                const int l = tid & (L - 1);
+                const bool ok = b < nt;
+                const int32_t i = ok ? A.tlist[b] : 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t c = (b << sh) + l + u * L;
+                    cc[p * 4 + u] = c;
+                    jv[p * 4 + u] = ok ? A.jsort[c] : -1;
                 }
+                di[p] = ok && dbit(A, i);
             }
+#pragma unroll
+            for (int e = 0; e < kScanU; ++e) hit[e] = jv[e] >= 0 && (di[e / 4] || dbit(A, jv[e]));
         } else {
+            int32_t jj[kScanU], ii[kScanU];
 #pragma unroll
             for (int u = 0; u < kScanU; ++u) {
                 const int64_t c = c0 + u * nth + tid;
@@ -889,20 +899,26 @@ __device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk
                 jj[u] = -1;
                 ii[u] = 0;
                 if (c < total) {
-                    const int64_t b = total < 0x7fffffff ? (int64_t)((uint32_t)c / (uint32_t)A.stride)
-                                                         : c / A.stride;
+                    const int64_t b = row_of_cand(c, sh, A.stride, total);
                     const int s = (int)(c - b * A.stride);
-                    const int32_t a = A.slot[b];
-                    if (!OVERLAP || s < A.cnt[a]) {
-                        jj[u] = partner(A, c, (int64_t)a * A.stride + s);
+                    if (!OVERLAP && A.jsort) {
+                        jj[u] = A.jsort[c];
                         ii[u] = A.tlist[b];
+                    } else {
+                        const int32_t a = A.slot[b];
+                        if (!OVERLAP || s < A.cnt[a]) {
+                            jj[u] = partner(A, c, (int64_t)a * A.stride + s);
+                            ii[u] = A.tlist[b];
+                        }
                     }
                 }
             }
+#pragma unroll
+            for (int u = 0; u < kScanU; ++u) hit[u] = jj[u] >= 0 && (dbit(A, jj[u]) || dbit(A, ii[u]));
         }
 #pragma unroll
         for (int u = 0; u < kScanU; ++u)
-            if (jj[u] >= 0 && (dbit(A, jj[u]) || dbit(A, ii[u]))) q[atomicAdd(&qn, 1)] = (int32_t)cc[u];
+            if (hit[u]) q[atomicAdd(&qn, 1)] = (int32_t)cc[u];
         __syncthreads();
         int n_q = qn;
         while (n_q >= nth) {
