@@ -25,6 +25,10 @@
  *     owns only the scratch it allocates in sidm_create; no call after
  *     sidm_create allocates device memory.
  *   - Every call is asynchronous and ordered on the context's HIP stream.
+ *     (sidm_find_ngb runs part of its work on a second stream the context
+ *     creates, of default priority, forked from and joined back to the
+ *     context's stream with events inside the call, so the ordering seen by
+ *     the caller is the same.)
  *     Errors found on the host (bad sizes, NULL pointers, capacity) are
  *     returned before anything is enqueued and leave every array untouched.
  *     Errors found by a kernel (an index out of range, a duplicate active
@@ -199,8 +203,11 @@ sidm_status sidm_footprint(const sidm_config *cfg, int64_t cap_n, int64_t cap_ac
 
 /* Create a context on the current HIP device with capacity for cap_n
  * particles and cap_active active particles; `hip_stream` (hipStream_t, may be
- * NULL for the default stream) orders all its work.  *out receives the
- * context, or NULL on error. */
+ * NULL for the default stream) orders all its work.  The context also creates
+ * one stream of its own (default priority) and four events for the neighbour
+ * search; sidm_destroy releases them.  *out receives the context, or NULL on
+ * error (SIDM_E_NOMEM, or SIDM_E_DEVICE if the stream or events cannot be
+ * created). */
 sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_active,
                         void *hip_stream, sidm_ctx **out);
 sidm_status sidm_destroy(sidm_ctx *ctx);
@@ -244,7 +251,11 @@ sidm_status sidm_tree_order(sidm_ctx *ctx, int32_t *order);
 
 /* For every active particle a (0 <= a < n_active, active[a] a particle
  * index, no duplicates): ngb[a*n_ngb + s] = its s-th nearest neighbour
- * (ascending (r^2, id)), h[a] = distance of the (n_ngb+1)-th. */
+ * (ascending (r^2, id)), h[a] = distance of the (n_ngb+1)-th (sec. 4.2:
+ * a fixed neighbour number sets h).  Exact in both precision forms.  The
+ * search runs in batches; with more than one batch the root walks of a
+ * batch's hard targets run on the context's second stream while the next
+ * batch is searched, and the call joins them back before it returns. */
 sidm_status sidm_find_ngb(sidm_ctx *ctx, const int32_t *active, int64_t n_active,
                           int32_t *ngb, double *h);
 
