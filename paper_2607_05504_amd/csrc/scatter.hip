@@ -1403,6 +1403,40 @@ __global__ __launch_bounds__(kBlock) void k_rows(StepArgs A, int have)
     }
 }
 
+// k_rows with four consecutive entries of a row per lane and 16-byte loads
+// and stores (rows of a multiple of 4 entries, ngb 16-byte aligned).
+__global__ __launch_bounds__(kBlock) void k_rows4(StepArgs A, int have)
+{
+    const int64_t total = (int64_t)(*A.nt_dev) * A.stride;
+    const int64_t nq = total >> 2;
+    const int sh = stride_shift(A.stride);
+    for (int64_t q = xcd_stride_block() * (int64_t)kBlock + threadIdx.x; q < nq;
+         q += (int64_t)gridDim.x * kBlock) {
+        const int64_t c = q << 2;
+        const int64_t b = row_of_cand(c, sh, A.stride, total);
+        const int s = (int)(c - b * A.stride);
+        const int4 g = *(const int4 *)(A.ngb + (int64_t)A.slot[b] * A.stride + s);
+        const int4 h = have ? *(const int4 *)(A.jsort + c) : make_int4(-1, -1, -1, -1);
+        const int32_t jc[4] = {g.x, g.y, g.z, g.w};
+        int32_t j[4] = {h.x, h.y, h.z, h.w};
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool in = j[u] >= 0 && j[u] < A.n;
+            ok[u] = in && A.perm[in ? j[u] : 0] == jc[u];
+        }
+        if (ok[0] && ok[1] && ok[2] && ok[3]) continue;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (ok[u]) continue;
+            j[u] = -1;
+            if (jc[u] >= 0 && jc[u] < A.n) j[u] = A.inv[jc[u]];
+            else atomicOr(A.derr, DERR_INDEX);
+        }
+        *(int4 *)(A.jsort + c) = make_int4(j[0], j[1], j[2], j[3]);
+    }
+}
+
 template <bool P, bool M, bool O = false>
 void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s)
 {
@@ -1453,7 +1487,10 @@ hipError_t launch_scatter(sidm_ctx *c, sidm_particles *p, int64_t n_active, cons
     StepArgs A = make_args(c, p, ngb, h, dt, seed, step, cand_info);
     A.jsort = c->jsort;
     const int have = c->jsort_knn || c->jsort_ngb == ngb;
-    k_rows<<<grid_for(n_active * A.stride, 8192), kBlock, 0, c->stream>>>(A, have);
+    if (A.stride % 4 == 0 && ((uintptr_t)ngb & 15) == 0)
+        k_rows4<<<grid_for(n_active * A.stride / 4, 8192), kBlock, 0, c->stream>>>(A, have);
+    else
+        k_rows<<<grid_for(n_active * A.stride, 8192), kBlock, 0, c->stream>>>(A, have);
     c->jsort_ngb = ngb;
     c->jsort_knn = 0;
     const bool mixed = c->cfg.precision == SIDM_MIXED;
