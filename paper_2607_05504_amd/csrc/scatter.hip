@@ -274,7 +274,15 @@ struct StagedAcc {
     double u[kStage], W[kStage];
 };
 
-__device__ void flush_staged(const StepArgs &A, StagedAcc &S, int n, int32_t &base_s)
+// the row-wise evaluation stages up to four candidates a thread a round
+constexpr int kStageRows = 5 * 256;
+struct StagedAccRows {
+    int32_t c[kStageRows];
+    double u[kStageRows], W[kStageRows];
+};
+
+template <class Stage>
+__device__ void flush_staged(const StepArgs &A, Stage &S, int n, int32_t &base_s)
 {
     if (threadIdx.x == 0) {
         base_s = atomicAdd(&A.ctl[CTL_MEM], n);
@@ -329,6 +337,152 @@ __device__ __forceinline__ float xsec_sigma32(float w, int xsec, float s0, float
         return s0 / (d * d);
     }
     return s0;
+}
+
+// workgroup reduction of the evaluation's statistics, one atomic each
+template <bool OVERLAP>
+__device__ void eval_stats(const StepArgs &A, unsigned long long (&s_red)[4][6], unsigned long long maxp,
+                           unsigned long long n_fl, unsigned long long n_ge1, unsigned long long n_acc,
+                           unsigned long long n_rc, unsigned long long n_cd)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = (unsigned long long)__shfl_xor((long long)maxp, off);
+        maxp = o > maxp ? o : maxp;
+        n_fl += (unsigned long long)__shfl_xor((long long)n_fl, off);
+        n_ge1 += (unsigned long long)__shfl_xor((long long)n_ge1, off);
+        n_acc += (unsigned long long)__shfl_xor((long long)n_acc, off);
+        n_rc += (unsigned long long)__shfl_xor((long long)n_rc, off);
+        n_cd += (unsigned long long)__shfl_xor((long long)n_cd, off);
+    }
+    const int w = threadIdx.x >> 6;
+    if (wave_lane() == 0) {
+        s_red[w][0] = maxp; s_red[w][1] = n_fl; s_red[w][2] = n_ge1; s_red[w][3] = n_acc; s_red[w][4] = n_rc;
+        s_red[w][5] = n_cd;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = 0, f = 0, g = 0, q = 0, rc = 0, cd = 0;
+        for (int v = 0; v < kBlock / 64; ++v) {
+            m = s_red[v][0] > m ? s_red[v][0] : m;
+            f += s_red[v][1]; g += s_red[v][2]; q += s_red[v][3]; rc += s_red[v][4];
+            cd += s_red[v][5];
+        }
+        if (OVERLAP && cd) atomicAdd(&A.st->n_cand, cd);
+        if (rc) atomicAdd(&A.st->n_recheck, rc);
+        if (m) atomicMax(&A.st->max_p_bits, m);
+        if (f) atomicAdd(&A.st->n_flagged, f);
+        if (g) atomicAdd(&A.st->n_p_ge_1, g);
+        if (q) atomicAdd(&A.st->n_accept0, q);
+    }
+}
+
+// W_CS(r, h) with the normalisation 8 / (pi h^3) given (computed as in
+// cubic_spline, so the value is the same bit for bit)
+__device__ __forceinline__ double spline_norm(double h)
+{
+    const double h3 = (h * h) * h;
+    return 8.0 / (SIDM_PI * h3);
+}
+__device__ __forceinline__ double cubic_spline_n(double r, double h, double norm)
+{
+    const double q = r / h;
+    if (q <= 0.5) {
+        const double q2 = q * q;
+        const double q3 = q2 * q;
+        return norm * ((1.0 - 6.0 * q2) + 6.0 * q3);
+    }
+    if (q <= 1.0) {
+        const double t = 1.0 - q;
+        return norm * (2.0 * ((t * t) * t));
+    }
+    return 0.0;
+}
+
+// k_eval of the FP64 one-sided form for rows of k = 2^sh >= 4 candidates: a
+// lane takes four candidates of a row (k / 4 lanes a row), so that the
+// target's data, its timestep and the kernel's normalisation are read and
+// computed once for four.  Same arithmetic per candidate as k_eval.
+template <bool PERIODIC>
+__global__ __launch_bounds__(kBlock) void k_eval_rows(StepArgs A)
+{
+    __shared__ StagedAccRows S;
+    __shared__ int s_n;
+    __shared__ int32_t s_base;
+    __shared__ unsigned long long s_red[4][6];
+    const int64_t nt = *A.nt_dev;
+    const int sh = stride_shift(A.stride);    // >= 2 (checked by the launch)
+    const int lsh = sh - 2;
+    const int L = 1 << lsh;
+    const int64_t lanes = nt << lsh;
+    unsigned long long maxp = 0, n_fl = 0, n_ge1 = 0, n_acc = 0, n_rc = 0, n_cd = 0;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    for (int64_t t0 = xcd_stride_block() * (int64_t)blockDim.x; t0 < lanes;
+         t0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = t0 + threadIdx.x;
+        if (t < lanes) {
+            const int64_t b = t >> lsh;
+            const int l = (int)(t & (L - 1));
+            const int32_t a = A.slot[b], i = A.tlist[b];
+            const double dta = A.dt[a];
+            const uint32_t idi = A.ids[i];
+            const double xi = A.xs[i], yi = A.ys[i], zi = A.zs[i];
+            const double vxi = A.vxs[i], vyi = A.vys[i], vzi = A.vzs[i];
+            const double hp = A.lphys * A.h[a];
+            const double norm = spline_norm(hp);
+            int32_t jj[4];
+#pragma unroll
+            for (int u4 = 0; u4 < 4; ++u4) {
+                const int sidx = l + u4 * L;
+                jj[u4] = partner(A, (b << sh) + sidx, (int64_t)a * A.stride + sidx);
+            }
+#pragma unroll
+            for (int u4 = 0; u4 < 4; ++u4) {
+                const int sidx = l + u4 * L;
+                const int64_t c = (b << sh) + sidx;
+                const int64_t ci = (int64_t)a * A.stride + sidx;
+                const int32_t j = jj[u4];
+                n_cd += 1;
+                if (j < 0) {
+                    if (!A.jsort) atomicOr(A.derr, DERR_INDEX);   // else latched by k_rows
+                    continue;
+                }
+                const uint32_t idj = A.ids[j];
+                const Philox4 x = pair_draw(A.seed, A.step, idi, idj, PURPOSE_DECIDE);
+                const double u = unit_from_word(direction_word(x, idi < idj));
+                const double r = A.lphys * sqrt(sep2<PERIODIC>(xi, yi, zi, A.xs[j], A.ys[j], A.zs[j], A.box));
+                const double W = cubic_spline_n(r, hp, norm);
+                const double w = A.vphys * rel_speed(vxi, vyi, vzi, A.vxs[j], A.vys[j], A.vzs[j]);
+                const double sig = sigma_of(A, w);
+                double P = pair_prob(mass_of(A, j), sig, w, W, dta);
+                if (!pair_allowed(A, i, j)) P = 0.0;
+                const bool acc = u < P;
+                const bool flagged = fabs(P - u) < A.band;
+                n_fl += flagged;
+                n_ge1 += P >= 1.0;
+                n_acc += acc;
+                const unsigned long long pb = (unsigned long long)__double_as_longlong(P);
+                maxp = pb > maxp ? pb : maxp;
+                if (A.cand_info)
+                    A.cand_info[ci] = (acc ? SIDM_CAND_ACCEPT0 : 0u) | (flagged ? SIDM_CAND_FLAGGED : 0u);
+                if (acc) {
+                    const int q = atomicAdd(&s_n, 1);      // LDS; kStageRows >= 5 * blockDim
+                    S.c[q] = (int32_t)c; S.u[q] = u; S.W[q] = W;
+                }
+            }
+        }
+        __syncthreads();
+        const int n_st = s_n;
+        // every wave has read s_n before any appends to it again
+        __syncthreads();
+        if (n_st > kStageRows - 4 * kBlock) {      // the next round might not fit
+            flush_staged(A, S, n_st, s_base);
+            if (threadIdx.x == 0) s_n = 0;
+            __syncthreads();
+        }
+    }
+    if (s_n > 0) flush_staged(A, S, s_n, s_base);
+    eval_stats<false>(A, s_red, maxp, n_fl, n_ge1, n_acc, n_rc, n_cd);
 }
 
 template <bool PERIODIC, bool MIXED, bool OVERLAP>
@@ -471,36 +625,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(StepArgs A)
         }
     }
     if (s_n > 0) flush_staged(A, S, s_n, s_base);
-    // workgroup reduction of the statistics, one atomic each
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = (unsigned long long)__shfl_xor((long long)maxp, off);
-        maxp = o > maxp ? o : maxp;
-        n_fl += (unsigned long long)__shfl_xor((long long)n_fl, off);
-        n_ge1 += (unsigned long long)__shfl_xor((long long)n_ge1, off);
-        n_acc += (unsigned long long)__shfl_xor((long long)n_acc, off);
-        n_rc += (unsigned long long)__shfl_xor((long long)n_rc, off);
-        n_cd += (unsigned long long)__shfl_xor((long long)n_cd, off);
-    }
-    const int w = threadIdx.x >> 6;
-    if (wave_lane() == 0) {
-        s_red[w][0] = maxp; s_red[w][1] = n_fl; s_red[w][2] = n_ge1; s_red[w][3] = n_acc; s_red[w][4] = n_rc;
-        s_red[w][5] = n_cd;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long m = 0, f = 0, g = 0, q = 0, rc = 0, cd = 0;
-        for (int v = 0; v < kBlock / 64; ++v) {
-            m = s_red[v][0] > m ? s_red[v][0] : m;
-            f += s_red[v][1]; g += s_red[v][2]; q += s_red[v][3]; rc += s_red[v][4];
-            cd += s_red[v][5];
-        }
-        if (OVERLAP && cd) atomicAdd(&A.st->n_cand, cd);
-        if (rc) atomicAdd(&A.st->n_recheck, rc);
-        if (m) atomicMax(&A.st->max_p_bits, m);
-        if (f) atomicAdd(&A.st->n_flagged, f);
-        if (g) atomicAdd(&A.st->n_p_ge_1, g);
-        if (q) atomicAdd(&A.st->n_accept0, q);
-    }
+    eval_stats<OVERLAP>(A, s_red, maxp, n_fl, n_ge1, n_acc, n_rc, n_cd);
 }
 
 // ----------------------------------------------------------------------------
@@ -1451,7 +1576,15 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
     int64_t ge = total / 2048;
     ge = ge > 8192 ? 8192 : ge;
     const int geval = ge > kEvalGrid ? grid8(ge) : grid_for(total, kEvalGrid);
-    k_eval<P, M, O><<<geval, kBlock, 0, s>>>(A);
+    if (!M && !O && A.jsort && A.stride >= 4 && (A.stride & (A.stride - 1)) == 0) {
+        // rows of four candidates a lane: a quarter of the threads
+        int64_t gr = total / 4 / 2048;
+        gr = gr > 8192 ? 8192 : gr;
+        const int gevr = gr > kEvalGrid ? grid8(gr) : grid_for(total / 4, kEvalGrid);
+        k_eval_rows<P><<<gevr, kBlock, 0, s>>>(A);
+    } else {
+        k_eval<P, M, O><<<geval, kBlock, 0, s>>>(A);
+    }
     phase_end(c, PH_EVAL);
     const int g = grid_for(A.cap_acc < total ? A.cap_acc : total, 2048);
     phase_begin(c, PH_RESOLVE);
