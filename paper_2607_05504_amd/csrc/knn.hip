@@ -1100,8 +1100,10 @@ constexpr int64_t kListWide = 1 << 18;
 // after the walk that read it has finished; the main stream waits for the
 // last walks before the call returns.
 template <bool P, int E, int TS>
-void launch_batches(sidm_ctx *c, const KnnArgs &A0, int64_t n_active)
+hipError_t launch_batches(sidm_ctx *c, const KnnArgs &A0, int64_t n_active)
 {
+    hipError_t err = hipSuccess;
+    auto keep = [&](hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; };
     // two leaves a step where the list leaves room for them after a cut
     constexpr int LPI = (TS * E >= 2 * SIDM_LEAF + 48) ? kLeavesPerStep : 1;
     const int64_t nb_cap = c->knn_batch;
@@ -1114,7 +1116,7 @@ void launch_batches(sidm_ctx *c, const KnnArgs &A0, int64_t n_active)
         A.batch = (n_active - base) < nb_cap ? (n_active - base) : nb_cap;
         A.nl = c->knn_nl[q]; A.tb = c->knn_tb[q];
         A.fb_list = c->knn_fb[q]; A.fb_count = c->knn_fbn[q];
-        if (fork && t >= 2) (void)hipStreamWaitEvent(s, c->knn_ev[q][1], 0);
+        if (fork && t >= 2) keep(hipStreamWaitEvent(s, c->knn_ev[q][1], 0));
         const int64_t gw = (A.batch + 3) / 4;
         if (A.batch >= kListWide) {
             constexpr int G = 64 / kListLanesWide;
@@ -1127,18 +1129,19 @@ void launch_batches(sidm_ctx *c, const KnnArgs &A0, int64_t n_active)
         }
         k_knn_bucket<P><<<xcd_grid(gw), 256, 0, s>>>(A, base, gw);
         if (fork) {
-            (void)hipEventRecord(c->knn_ev[q][0], s);
-            (void)hipStreamWaitEvent(c->knn_aux, c->knn_ev[q][0], 0);
+            keep(hipEventRecord(c->knn_ev[q][0], s));
+            keep(hipStreamWaitEvent(c->knn_aux, c->knn_ev[q][0], 0));
             k_knn_team<P, E, TS, LPI><<<kFallbackGrid, 256, 0, c->knn_aux>>>(A, base);
-            (void)hipEventRecord(c->knn_ev[q][1], c->knn_aux);
+            keep(hipEventRecord(c->knn_ev[q][1], c->knn_aux));
         } else {
             k_knn_team<P, E, TS, LPI><<<kFallbackGrid, 256, 0, s>>>(A, base);
         }
     }
     if (fork) {
-        (void)hipStreamWaitEvent(s, c->knn_ev[0][1], 0);
-        if (t > 1) (void)hipStreamWaitEvent(s, c->knn_ev[1][1], 0);
+        keep(hipStreamWaitEvent(s, c->knn_ev[0][1], 0));
+        if (t > 1) keep(hipStreamWaitEvent(s, c->knn_ev[1][1], 0));
     }
+    return err;
 }
 
 }  // namespace
@@ -1161,12 +1164,14 @@ hipError_t launch_knn(sidm_ctx *c, int64_t n_active, int32_t *ngb, double *h)
     // both precision forms: the search is exact, so it is the FP64 one
     const int sel = (per ? 2 : 0) | (small ? 1 : 0);
     constexpr int B = 128 / kTeam, S = 64 / kTeam;   // lists of 128 and 64 entries
+    hipError_t e;
     switch (sel) {
-    case 0: launch_batches<false, B, kTeam>(c, A, n_active); break;
-    case 1: launch_batches<false, S, kTeam>(c, A, n_active); break;
-    case 2: launch_batches<true, B, kTeam>(c, A, n_active); break;
-    default: launch_batches<true, S, kTeam>(c, A, n_active); break;
+    case 0: e = launch_batches<false, B, kTeam>(c, A, n_active); break;
+    case 1: e = launch_batches<false, S, kTeam>(c, A, n_active); break;
+    case 2: e = launch_batches<true, B, kTeam>(c, A, n_active); break;
+    default: e = launch_batches<true, S, kTeam>(c, A, n_active); break;
     }
     phase_end(c, PH_KNN);
-    return hipGetLastError();
+    const hipError_t l = hipGetLastError();
+    return e != hipSuccess ? e : l;
 }
