@@ -140,6 +140,9 @@ void make_plan(sidm_ctx *c, Plan &P)
     ADD(head, N, int32_t);
     ADD(tmin, N, unsigned long long);
     ADD(dbits, (N + 31) / 32, uint32_t);
+    ADD(bbits, bucket_words(N), uint32_t);
+    if (k >= 4 && k <= SIDM_SUM_U && (k & (k - 1)) == 0)
+        ADD(csum, (NA * (int64_t)k + SIDM_SUM_U - 1) / SIDM_SUM_U * SIDM_SUM_WORDS, int32_t);
     ADD(flist, 2 * SIDM_FLAG_CAP, int32_t);
     for (int b = 0; b < 2; ++b) {
         ADD(claim1[b], N, unsigned long long); ADD(claim2[b], N, unsigned long long);
@@ -375,6 +378,7 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
     launch_fill_u64(c->tmin, ~0ull, cap_n, s);
     launch_fill_i32(c->mmark, 0, c->cap_acc, s);
     launch_fill_i32((int32_t *)c->dbits, 0, (cap_n + 31) / 32, s);
+    launch_fill_i32((int32_t *)c->bbits, 0, bucket_words(cap_n), s);
     c->dev_rounds = test_device_rounds();
     launch_fill_i32((int32_t *)c->dstats, 0, (int64_t)(sizeof(DevStats) / 4), s);
     hipError_t e = copy_table(c);

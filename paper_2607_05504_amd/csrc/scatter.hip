@@ -47,9 +47,11 @@ constexpr int kFinisherMax = 256;      // shorter lists go to the one-workgroup 
 // flag, [4] listed candidates, [5] turn-record pairs ever used (x2), [6]
 // first candidate listed since the last replay, [7] done (no candidate newly
 // listed), [8] free record pairs, [9] re-rounds run, [10] particles of D
-// (in plist), [11] flagged candidates listed for the final count
+// (in plist), [11] flagged candidates listed for the final count, [12] index
+// buckets holding a particle of D
 enum { CTL_COUNT0 = 0, CTL_COUNT1 = 1, CTL_PASS = 2, CTL_HANDOFF = 3, CTL_MEM = 4, CTL_REC = 5,
-       CTL_NEWLO = 6, CTL_DONE = 7, CTL_FREE = 8, CTL_ROUNDS = 9, CTL_PL = 10, CTL_FLAG = 11 };
+       CTL_NEWLO = 6, CTL_DONE = 7, CTL_FREE = 8, CTL_ROUNDS = 9, CTL_PL = 10, CTL_FLAG = 11,
+       CTL_DBK = 12 };
 
 struct StepArgs {
     // Morton-ordered snapshot
@@ -72,6 +74,9 @@ struct StepArgs {
     TurnRecords R;
     unsigned long long *tmin;
     uint32_t *dbits;
+    uint32_t *bbits;         // bit per index bucket holding a particle of D
+    int64_t nbw;             // its words for n particles
+    int32_t *csum;           // row block summaries of the step's rows, or NULL
     int32_t *flist;
     int32_t *jsort;          // the step's rows in Morton order (sorted indices), or NULL
     int32_t *ctl;
@@ -967,9 +972,102 @@ __device__ void check_candidate(const StepArgs &A, int32_t i, int32_t a, int s, 
 constexpr int kScanU = 8;          // candidates a thread scans per round of the loop
 static_assert(kScanU % 4 == 0, "the row-wise scan takes four candidates of a row a lane");
 
-template <bool PERIODIC, bool OVERLAP>
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_or_u32(unsigned int);
+
+// Summaries of the row blocks a round of the row-wise scan covers (kBlock
+// threads, kScanU / 4 rows a lane: kScanU / 4 blocks of SIDM_SUM_U).  Each
+// wavefront lists the buckets outside a block's window that it saw, each
+// once; the block's writer merges the wavefronts' lists.
+constexpr int kSumPer = kScanU / 4;
+constexpr int kSumWaves = kBlock / 64;
+static_assert(kBlock * 4 == SIDM_SUM_U, "a row of the row-wise scan's lanes covers one block");
+static_assert(kSumWaves * SIDM_SUM_OUT <= 64 && kSumPer <= kSumWaves, "a wavefront merges a block's lists");
+struct SumLds {
+    uint32_t m[kSumPer][2];
+    int cnt[kSumPer][kSumWaves];                      // > SIDM_SUM_OUT: too many
+    int32_t out[kSumPer][kSumWaves][SIDM_SUM_OUT];
+};
+
+__device__ __forceinline__ void sum_reset(SumLds *S, int tid)
+{
+    if (tid < kSumPer) { S->m[tid][0] = 0u; S->m[tid][1] = 0u; }
+}
+
+// The distinct values of the lanes' pending entries v[e] (bit e of pend), at
+// most SIDM_SUM_OUT + 1 of them, one a round: lane r gets the r-th in found;
+// returns their number.
+template <int E>
+__device__ __forceinline__ int wave_distinct(const int32_t (&v)[E], uint32_t pend, int32_t &found)
+{
+    const int lane = threadIdx.x & 63;
+    int nf = 0;
+    for (; nf <= SIDM_SUM_OUT; ++nf) {
+        const uint64_t any = __ballot(pend != 0u);
+        if (any == 0ull) break;
+        int32_t mine = -1;
+#pragma unroll
+        for (int e = E - 1; e >= 0; --e)
+            if ((pend >> e) & 1u) mine = v[e];
+        const int32_t bk = __builtin_amdgcn_readlane(mine, __ffsll((long long)any) - 1);
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (((pend >> e) & 1u) && v[e] == bk) pend &= ~(1u << e);
+        if (lane == nf) found = bk;
+    }
+    return nf;
+}
+
+// A lane's buckets v (-1: none) into block p's summary: those within 32 of
+// base into the mask, the others into this wavefront's list.
+__device__ __forceinline__ void sum_add(SumLds *S, int p, int32_t base, const int32_t (&v)[5])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t mlo = 0u, mhi = 0u, pend = 0u;
+#pragma unroll
+    for (int e = 0; e < 5; ++e) {
+        if (v[e] < 0) continue;
+        const int32_t rel = v[e] - base + 32;
+        if (rel >= 0 && rel < 32) mlo |= 1u << rel;
+        else if (rel >= 32 && rel < 64) mhi |= 1u << (rel - 32);
+        else pend |= 1u << e;
+    }
+    mlo = __ockl_wfred_or_u32(mlo);
+    mhi = __ockl_wfred_or_u32(mhi);
+    if (lane == 0) {
+        if (mlo) atomicOr(&S->m[p][0], mlo);
+        if (mhi) atomicOr(&S->m[p][1], mhi);
+    }
+    int32_t found = -1;
+    const int nf = wave_distinct<5>(v, pend, found);
+    if (lane < nf && lane < SIDM_SUM_OUT) S->out[p][w][lane] = found;
+    if (lane == 0) S->cnt[p][w] = nf;
+}
+
+// Wavefront p of the workgroup merges block p's lists and writes the
+// summary of block blk.
+__device__ __forceinline__ void sum_write(const StepArgs &A, const SumLds *S, int p, int64_t blk, int sh)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = lane / SIDM_SUM_OUT, r = lane % SIDM_SUM_OUT;
+    bool over = false;
+#pragma unroll
+    for (int q = 0; q < kSumWaves; ++q) over = over || S->cnt[p][q] > SIDM_SUM_OUT;
+    int32_t v[1] = {-1};
+    if (w < kSumWaves && r < S->cnt[p][w]) v[0] = S->out[p][w][r];
+    int32_t found = -1;
+    const int nf = wave_distinct<1>(v, v[0] >= 0 ? 1u : 0u, found);
+    over = over || nf > SIDM_SUM_OUT;
+    int32_t *o = A.csum + blk * SIDM_SUM_WORDS;
+    if (!over && lane < nf) o[4 + lane] = found;
+    if (lane == 32) o[0] = (int32_t)S->m[p][0];
+    if (lane == 33) o[1] = (int32_t)S->m[p][1];
+    if (lane == 34) o[2] = A.tlist[(blk * SIDM_SUM_U) >> sh] >> SIDM_DBUCKET_SHIFT;
+    if (lane == 35) o[3] = over ? -1 : nf;
+}
+
+template <bool PERIODIC, bool OVERLAP, bool BUILD = false>
 __device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk_stride,
-                           int32_t *q, int &qn)
+                           int32_t *q, int &qn, SumLds *S = nullptr)
 {
     const int nth = blockDim.x, tid = threadIdx.x;
     const int64_t nt = *A.nt_dev;
@@ -983,6 +1081,7 @@ __device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk
     };
     const int sh = stride_shift(A.stride);
     if (tid == 0) qn = 0;
+    if (BUILD) sum_reset(S, tid);
     __syncthreads();
     // chunks of nth * kScanU candidates; a thread takes kScanU of a chunk,
     // nth apart, with their loads independent of each other
@@ -1015,6 +1114,21 @@ __device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk
             }
 #pragma unroll
             for (int e = 0; e < kScanU; ++e) hit[e] = jv[e] >= 0 && (di[e / 4] || dbit(A, jv[e]));
+            if constexpr (BUILD) {
+                // the summaries of this chunk's blocks (rows of the block's
+                // lanes: p, the first target's bucket its base)
+#pragma unroll
+                for (int p = 0; p < kSumPer; ++p) {
+                    const int64_t bf = b0 + p * rows_pass;
+                    const int64_t b = bf + (tid >> lsh);
+                    const int32_t base = A.tlist[bf < nt ? bf : 0] >> SIDM_DBUCKET_SHIFT;
+                    int32_t v[5];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = jv[p * 4 + u] >= 0 ? jv[p * 4 + u] >> SIDM_DBUCKET_SHIFT : -1;
+                    v[4] = b < nt ? A.tlist[b] >> SIDM_DBUCKET_SHIFT : -1;
+                    sum_add(S, p, base, v);
+                }
+            }
         } else {
             int32_t jj[kScanU], ii[kScanU];
 #pragma unroll
@@ -1045,6 +1159,11 @@ __device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk
         for (int u = 0; u < kScanU; ++u)
             if (hit[u]) q[atomicAdd(&qn, 1)] = (int32_t)cc[u];
         __syncthreads();
+        if constexpr (BUILD) {
+            const int p = tid >> 6;
+            const int64_t blk = c0 / SIDM_SUM_U + p;
+            if (p < kSumPer && blk * SIDM_SUM_U < total) sum_write(A, S, p, blk, sh);
+        }
         int n_q = qn;
         while (n_q >= nth) {
             evaluate(q[n_q - nth + tid]);
@@ -1052,6 +1171,7 @@ __device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk
         }
         __syncthreads();
         if (tid == 0) qn = n_q;
+        if (BUILD) sum_reset(S, tid);
         __syncthreads();
     }
     const int n_q = qn;
@@ -1059,14 +1179,190 @@ __device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk
     __syncthreads();
 }
 
-template <bool PERIODIC, bool OVERLAP>
+// Does the block whose summary is s hold a candidate touching D?  False only
+// if none of its buckets holds a particle of D.
+__device__ __forceinline__ bool block_meets_d(const StepArgs &A, const int32_t *s)
+{
+    const int4 h = *(const int4 *)s;
+    const int nout = h.w;
+    if (nout < 0) return true;
+    const uint64_t mask = (uint64_t)(uint32_t)h.x | ((uint64_t)(uint32_t)h.y << 32);
+    if (mask) {
+        const int64_t b0 = (int64_t)h.z - 32;          // the bucket of mask bit 0
+        const int64_t w0 = b0 >= 0 ? (b0 >> 5) : -((31 - b0) >> 5);
+        const int o = (int)(b0 - w0 * 32);
+        uint64_t wd[3];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const int64_t w = w0 + e;
+            wd[e] = (w >= 0 && w < A.nbw) ? A.bbits[w] : 0u;
+        }
+        const uint64_t lo = wd[0] | (wd[1] << 32);
+        const uint64_t win = o == 0 ? lo : (lo >> o) | (wd[2] << (64 - o));
+        if (win & mask) return true;
+    }
+    for (int e = 0; e < nout; ++e) {
+        const int32_t bk = s[4 + e];
+        if ((A.bbits[bk >> 5] >> (bk & 31)) & 1u) return true;
+    }
+    return false;
+}
+
+// The check's scan with block summaries (rows in the tree's order of a
+// power of two entries, k <= SIDM_SUM_U): the blocks are tested against the
+// bucket bits of D, nth at a time, and only the blocks that may hold a
+// candidate touching D are scanned, nth / 256 at once, 256 threads of four
+// candidates of a row each; hits queue and are evaluated as in check_scan.
+template <bool PERIODIC>
+__device__ void check_blocks(const StepArgs &A, int64_t g0, int64_t g_stride, int gsz, int32_t *q,
+                             int &qn, int32_t *sb, int &sbn)
+{
+    const int nth = blockDim.x, tid = threadIdx.x;
+    const int64_t nt = *A.nt_dev;
+    const int64_t total = nt * A.stride;
+    const int64_t nblocks = (total + SIDM_SUM_U - 1) / SIDM_SUM_U;
+    const int sh = stride_shift(A.stride);
+    const int lsh = sh - 2;
+    const int L = 1 << lsh;
+    const int G = nth >> 8;
+    constexpr int PB = 2;
+    static_assert(4 * PB <= kScanU, "a round queues at most kScanU hits a thread");
+    auto evaluate = [&](int64_t c) {
+        const int64_t b = c >> sh;
+        const int s = (int)(c - (b << sh));
+        const int32_t a = A.slot[b];
+        const int32_t j = partner(A, c, (int64_t)a * A.stride + s);
+        check_candidate<PERIODIC, false>(A, A.tlist[b], a, s, j);
+    };
+    if (tid == 0) qn = 0;
+    __syncthreads();
+    for (int64_t g = g0; g * gsz < nblocks; g += g_stride) {
+        if (tid == 0) sbn = 0;
+        __syncthreads();
+        const int64_t u = g * gsz + tid;
+        if (tid < gsz && u < nblocks && block_meets_d(A, A.csum + u * SIDM_SUM_WORDS)) sb[atomicAdd(&sbn, 1)] = (int32_t)u;
+        __syncthreads();
+        const int nb = sbn;
+        // PB blocks a round for a workgroup of 256 threads (G * PB for more)
+        for (int h0 = 0; h0 < nb; h0 += G * PB) {
+            const int t = tid & 255;
+            int64_t cc[4 * PB];
+            bool hit[4 * PB];
+#pragma unroll
+            for (int p = 0; p < PB; ++p) {
+                const int h = h0 + p * G + (tid >> 8);
+                int32_t jv[4];
+                bool di = false;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) { cc[p * 4 + e] = 0; jv[e] = -1; }
+                if (h < nb) {
+                    const int64_t b = (((int64_t)sb[h] * SIDM_SUM_U) >> sh) + (t >> lsh);
+                    if (b < nt) {
+                        const int l = t & (L - 1);
+                        di = dbit(A, A.tlist[b]);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            cc[p * 4 + e] = (b << sh) + l + e * L;
+                            jv[e] = A.jsort[cc[p * 4 + e]];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) hit[p * 4 + e] = jv[e] >= 0 && (di || dbit(A, jv[e]));
+            }
+#pragma unroll
+            for (int e = 0; e < 4 * PB; ++e)
+                if (hit[e]) q[atomicAdd(&qn, 1)] = (int32_t)cc[e];
+            __syncthreads();
+            int n_q = qn;
+            while (n_q >= nth) {
+                evaluate(q[n_q - nth + tid]);
+                n_q -= nth;
+            }
+            __syncthreads();
+            if (tid == 0) qn = n_q;
+            __syncthreads();
+        }
+    }
+    const int n_q = qn;
+    if (tid < n_q) evaluate(q[tid]);
+    __syncthreads();
+}
+
+// blocks a workgroup of the grid check tests at once: few, so that the
+// groups of a large step outnumber the workgroups and spread over every XCD
+// (consecutive workgroups go to different XCDs)
+constexpr int kCheckGroup = 64;
+
+// The block summaries are tested only while few buckets hold a particle of
+// D (at most a quarter of them): with more, most blocks would be scanned
+// anyway and the plain scan is faster.
+__device__ __forceinline__ bool use_blocks(const StepArgs &A, int32_t dbk)
+{
+    return A.csum && (int64_t)dbk * 4 <= A.nbw * 32;
+}
+
+// The index buckets holding a particle of D, from its bits: one thread per
+// bucket (SIDM_DBUCKET particles, 2^SIDM_DBUCKET_SHIFT / 32 words of bits),
+// a bucket word per half wavefront; the count of such buckets into CTL_DBK
+// (zeroed by the round that set D).
+__device__ __forceinline__ int dbucket_word(const StepArgs &A, int64_t bk)
+{
+    constexpr int W = (1 << SIDM_DBUCKET_SHIFT) / 32;
+    const int64_t ndw = (A.n + 31) / 32;
+    const int64_t w0 = bk * W;
+    uint32_t any = 0u;
+    if (w0 + W <= ndw) {
+#pragma unroll
+        for (int e = 0; e < W; e += 4) {
+            const uint4 d = *(const uint4 *)(A.dbits + w0 + e);
+            any |= d.x | d.y | d.z | d.w;
+        }
+    } else {
+        for (int64_t w = w0; w < ndw; ++w) any |= A.dbits[w];
+    }
+    return any != 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_dbuckets(StepArgs A)
+{
+    if (load_i32(&A.ctl[CTL_DONE])) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t nb = A.nbw * 32;
+    for (int64_t b0 = xcd_stride_block() * (int64_t)kBlock + (threadIdx.x & ~63); b0 < nb;
+         b0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t bk = b0 + lane;
+        const uint64_t m = __ballot(bk < nb && dbucket_word(A, bk));
+        if (lane == 0) {
+            A.bbits[b0 >> 5] = (uint32_t)m;
+            if (m) atomicAdd(&A.ctl[CTL_DBK], __popcll(m));
+        } else if (lane == 32 && (b0 >> 5) + 1 < A.nbw) {
+            A.bbits[(b0 >> 5) + 1] = (uint32_t)(m >> 32);
+        }
+    }
+}
+
+// The first check (BUILD) scans every candidate and writes the block
+// summaries on the way; later checks scan the blocks that may hold a
+// candidate touching D while few buckets do.
+template <bool PERIODIC, bool OVERLAP, bool BUILD>
 __global__ __launch_bounds__(kBlock) void k_check(StepArgs A)
 {
     __shared__ int32_t q[(kScanU + 1) * kBlock];
-    __shared__ int qn;
+    __shared__ int32_t sb[kBlock];
+    __shared__ int qn, sbn;
+    __shared__ SumLds S;
     if (A.ctl[CTL_DONE]) return;
-    check_scan<PERIODIC, OVERLAP>(A, xcd_stride_block() * (int64_t)kBlock * kScanU,
-                                  (int64_t)gridDim.x * kBlock * kScanU, q, qn);
+    if constexpr (BUILD && !OVERLAP) {
+        check_scan<PERIODIC, false, true>(A, xcd_stride_block() * (int64_t)kBlock * kScanU,
+                                          (int64_t)gridDim.x * kBlock * kScanU, q, qn, &S);
+    } else {
+        if (!OVERLAP && use_blocks(A, A.ctl[CTL_DBK]))
+            check_blocks<PERIODIC>(A, blockIdx.x, gridDim.x, kCheckGroup, q, qn, sb, sbn);
+        else
+            check_scan<PERIODIC, OVERLAP>(A, xcd_stride_block() * (int64_t)kBlock * kScanU,
+                                          (int64_t)gridDim.x * kBlock * kScanU, q, qn);
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -1196,6 +1492,7 @@ __device__ void reround_body(const StepArgs &A, RoundShared &S)
     if (tid == 0) {
         A.ctl[CTL_NEWLO] = S.hi;
         A.ctl[CTL_PL] = S.pl;
+        A.ctl[CTL_DBK] = 0;
         A.ctl[CTL_ROUNDS] += 1;
         // pops that found the free stack empty left the count below zero
         if (A.ctl[CTL_FREE] < 0) A.ctl[CTL_FREE] = 0;
@@ -1220,7 +1517,8 @@ __global__ __launch_bounds__(1024) void k_tail(StepArgs A)
     __shared__ RoundShared S;
     __shared__ int s_done;
     __shared__ int32_t tq[(kScanU + 1) * 1024];
-    __shared__ int tqn;
+    __shared__ int32_t tsb[1024];
+    __shared__ int tqn, tsbn;
     for (int round = 0;; ++round) {
         if (threadIdx.x == 0) {
             s_done = load_i32(&A.ctl[CTL_DONE]);
@@ -1231,7 +1529,29 @@ __global__ __launch_bounds__(1024) void k_tail(StepArgs A)
         }
         __syncthreads();
         if (s_done) break;
-        check_scan<PERIODIC, OVERLAP>(A, 0, (int64_t)blockDim.x * kScanU, tq, tqn);
+        if (!OVERLAP && A.csum) {
+            // the bucket bits of this round's D
+            if (threadIdx.x == 0) tsbn = 0;
+            __syncthreads();
+            const int lane = threadIdx.x & 63;
+            const int64_t nb = A.nbw * 32;
+            for (int64_t b0 = threadIdx.x & ~63; b0 < nb; b0 += blockDim.x) {
+                const uint64_t m = __ballot(b0 + lane < nb && dbucket_word(A, b0 + lane));
+                if (lane == 0) {
+                    A.bbits[b0 >> 5] = (uint32_t)m;
+                    if (m) atomicAdd(&tsbn, __popcll(m));
+                } else if (lane == 32 && (b0 >> 5) + 1 < A.nbw) {
+                    A.bbits[(b0 >> 5) + 1] = (uint32_t)(m >> 32);
+                }
+            }
+            __syncthreads();
+            const int dbk = tsbn;
+            __syncthreads();
+            if (use_blocks(A, dbk)) check_blocks<PERIODIC>(A, 0, 1, 1024, tq, tqn, tsb, tsbn);
+            else check_scan<PERIODIC, OVERLAP>(A, 0, (int64_t)blockDim.x * kScanU, tq, tqn);
+        } else {
+            check_scan<PERIODIC, OVERLAP>(A, 0, (int64_t)blockDim.x * kScanU, tq, tqn);
+        }
         wg_sync();
         reround_body(A, S);
         wg_sync();
@@ -1479,6 +1799,7 @@ StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const dou
     A.wl0 = c->wl[0]; A.wl1 = c->wl[1]; A.mmark = c->mmark; A.plist = c->plist; A.head = c->head;
     A.R = c->trec; A.tmin = c->tmin; A.cap_rec = c->cap_rec;
     A.rfree = c->rfree; A.dbits = c->dbits; A.flist = c->flist; A.jsort = nullptr;
+    A.bbits = c->bbits; A.nbw = bucket_words(c->n); A.csum = nullptr;
     A.ctl = c->acc_count;
     A.c1a = c->claim1[0]; A.c1b = c->claim1[1]; A.c2a = c->claim2[0]; A.c2b = c->claim2[1];
     A.st = c->dstats; A.derr = c->derr;
@@ -1601,7 +1922,12 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
     dmax = dmax < A.n ? dmax : A.n;
     const int gcheck = grid_for((total + kScanU - 1) / kScanU, 8192);
     for (int r = 0; r < c->dev_rounds; ++r) {
-        k_check<P, O><<<gcheck, kBlock, 0, s>>>(A);
+        if (r == 0 && A.csum) {
+            k_check<P, O, true><<<gcheck, kBlock, 0, s>>>(A);
+        } else {
+            if (A.csum) k_dbuckets<<<grid_for(A.nbw * 32, 1024), kBlock, 0, s>>>(A);
+            k_check<P, O, false><<<gcheck, kBlock, 0, s>>>(A);
+        }
         k_reround<<<1, 1024, 0, s>>>(A);
     }
     k_tail<P, O><<<1, 1024, 0, s>>>(A);
@@ -1626,6 +1952,11 @@ hipError_t launch_scatter(sidm_ctx *c, sidm_particles *p, int64_t n_active, cons
         k_rows<<<grid_for(n_active * A.stride, 8192), kBlock, 0, c->stream>>>(A, have);
     c->jsort_ngb = ngb;
     c->jsort_knn = 0;
+    // row block summaries for the checks: rows of a power of two entries,
+    // written by the first grid check
+    const int st = A.stride;
+    if (c->csum && c->dev_rounds > 0 && st >= 4 && st <= SIDM_SUM_U && (st & (st - 1)) == 0)
+        A.csum = c->csum;
     const bool mixed = c->cfg.precision == SIDM_MIXED;
     if (c->cfg.periodic) {
         mixed ? run_scatter<true, true>(c, A, n_active, c->stream)

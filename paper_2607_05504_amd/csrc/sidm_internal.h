@@ -96,6 +96,20 @@ struct TurnRecords {
 
 #define SIDM_FLAG_CAP 4096    // candidates whose flagged status a step re-counts at its end
 
+// Block summaries of the candidate rows, for the checks of a small D: the
+// rows in the tree's order are cut into blocks of SIDM_SUM_U candidates, and
+// each block records the index buckets (SIDM_DBUCKET particles of the sorted
+// order each) of its targets and partners.  Sixteen int32 a block: [0..1] a
+// 64-bit mask of the buckets base - 32 .. base + 31, [2] base (the first
+// target's bucket), [3] the number of other buckets (-1: too many to list,
+// the block is always scanned), [4..15] those buckets.
+#define SIDM_SUM_U 1024
+#define SIDM_SUM_WORDS 16
+#define SIDM_SUM_OUT 12
+#define SIDM_DBUCKET_SHIFT 8
+// words of the bucket bitmap for n particles
+inline int64_t bucket_words(int64_t n) { return ((n >> SIDM_DBUCKET_SHIFT) + 1 + 31) / 32; }
+
 struct sidm_ctx {
     sidm_config cfg;
     int64_t cap_n, cap_active, cap_acc, cap_rec;
@@ -173,6 +187,8 @@ struct sidm_ctx {
     int32_t *head;           // [cap_n] latest turn record of each particle, -1 if none
     unsigned long long *tmin;     // [cap_n] smallest priority a re-round replays, ~0 if none
     uint32_t *dbits;         // [cap_n / 32] bit per sorted index: the particle is in D
+    uint32_t *bbits;         // [cap_n / 2^(5 + SIDM_DBUCKET_SHIFT)] bit per index bucket: holds a particle of D
+    int32_t *csum;           // [cap_active * n_ngb / SIDM_SUM_U][SIDM_SUM_WORDS] row block summaries, or NULL
     int32_t *flist;          // [2 SIDM_FLAG_CAP] (target, candidate slot) once flagged
     int32_t *acc_count;      // [16] control words (list counts, passes, rounds)
     unsigned long long *claim1[2], *claim2[2];   // [cap_n] per-particle claims

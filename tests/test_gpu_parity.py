@@ -87,6 +87,20 @@ def test_rounds_in_one_workgroup(monkeypatch):
     assert (hit & ~acc0).any() and (acc0 & ~hit).any()
 
 
+def test_tail_rounds_with_block_summaries(monkeypatch):
+    """One grid round (the full scan that writes the row block summaries),
+    every later round in the one-workgroup tail: few particles per index
+    bucket change after the first round, so the tail's checks scan only the
+    row blocks that may touch them.  The same serial order."""
+    monkeypatch.setenv("SIDM_TEST_DEVICE_ROUNDS", "1")
+    w = W.uniform_box(262144, ic_seed=46, scatters_per_particle=0.05)
+    _announce("tail rounds with block summaries")
+    ref = oracle.full_step(w)
+    g = gpu_step(w)
+    assert g["stats"]["n_rounds"] >= 2
+    assert_parity(w, g, ref)
+
+
 @pytest.mark.parametrize("k", [1, 8, 16, 31, 48, 63])
 def test_neighbour_counts(k):
     """n_ngb from 1 to the largest accepted (63): the short-list and long-list
