@@ -79,6 +79,8 @@ struct StepArgs {
     int32_t *csum;           // row block summaries of the step's rows, or NULL
     int32_t *flist;
     int32_t *jsort;          // the step's rows in Morton order (sorted indices), or NULL
+    const double4 *vaos;     // velocities as (vx, vy, vz, 0) records for the timestep's gathers, or NULL
+    const double2 *erec;     // per particle (x, y), (z, vx), (vy, vz), (id bits, mass): the evaluation's gathers
     int32_t *ctl;
     unsigned long long *c1a, *c1b, *c2a, *c2b;
     DevStats *st;
@@ -403,6 +405,29 @@ __device__ __forceinline__ double cubic_spline_n(double r, double h, double norm
     return 0.0;
 }
 
+// The evaluation's per-particle records (in the phase buffer, which the step
+// does not otherwise use): a partner's data in one 64-byte line.
+__global__ __launch_bounds__(kBlock) void k_eval_recs(StepArgs A, double2 *out)
+{
+    // a lane a 16-byte quarter of a record: consecutive lanes write
+    // consecutive bytes
+    const int64_t total = 4 * A.n;
+    for (int64_t t = xcd_stride_block() * (int64_t)kBlock + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * kBlock) {
+        const int64_t q = t >> 2;
+        const int part = (int)(t & 3);
+        double2 v;
+        if (part < 3) {
+            const double *pa = part == 0 ? A.xs : part == 1 ? A.zs : A.vys;
+            const double *pb = part == 0 ? A.ys : part == 1 ? A.vxs : A.vzs;
+            v = make_double2(pa[q], pb[q]);
+        } else {
+            v = make_double2(__longlong_as_double((long long)A.ids[q]), mass_of(A, (int32_t)q));
+        }
+        out[t] = v;
+    }
+}
+
 // k_eval of the FP64 one-sided form for rows of k = 2^sh >= 4 candidates: a
 // lane takes four candidates of a row (k / 4 lanes a row), so that the
 // target's data, its timestep and the kernel's normalisation are read and
@@ -452,14 +477,17 @@ __global__ __launch_bounds__(kBlock) void k_eval_rows(StepArgs A)
                     if (!A.jsort) atomicOr(A.derr, DERR_INDEX);   // else latched by k_rows
                     continue;
                 }
-                const uint32_t idj = A.ids[j];
+                // the partner's record: four 16-byte loads instead of eight gathers
+                const double2 *R = A.erec + 4 * (int64_t)j;
+                const double2 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3];
+                const uint32_t idj = (uint32_t)__double_as_longlong(r3.x);
                 const Philox4 x = pair_draw(A.seed, A.step, idi, idj, PURPOSE_DECIDE);
                 const double u = unit_from_word(direction_word(x, idi < idj));
-                const double r = A.lphys * sqrt(sep2<PERIODIC>(xi, yi, zi, A.xs[j], A.ys[j], A.zs[j], A.box));
+                const double r = A.lphys * sqrt(sep2<PERIODIC>(xi, yi, zi, r0.x, r0.y, r1.x, A.box));
                 const double W = cubic_spline_n(r, hp, norm);
-                const double w = A.vphys * rel_speed(vxi, vyi, vzi, A.vxs[j], A.vys[j], A.vzs[j]);
+                const double w = A.vphys * rel_speed(vxi, vyi, vzi, r1.y, r2.x, r2.y);
                 const double sig = sigma_of(A, w);
-                double P = pair_prob(mass_of(A, j), sig, w, W, dta);
+                double P = pair_prob(r3.y, sig, w, W, dta);
                 if (!pair_allowed(A, i, j)) P = 0.0;
                 const bool acc = u < P;
                 const bool flagged = fabs(P - u) < A.band;
@@ -1658,13 +1686,28 @@ __device__ __forceinline__ double dt_from_rate(const StepArgs &A, int32_t i, dou
     return rmax > 0.0 ? (2.0 * c_sidm) / ((mass_of(A, i) * W0) * rmax) : INFINITY;
 }
 
+// The velocities as (vx, vy, vz, 0) records of 32 bytes (in the phase
+// buffer, which the timestep does not otherwise use), for the timestep's
+// gathers of partners: two 16-byte loads of one line instead of three
+// gathers of three lines.
+__global__ __launch_bounds__(kBlock) void k_vel_aos(int64_t n, const double *vx, const double *vy,
+                                                   const double *vz, double2 *out)
+{
+    // a lane a half record: (vx, vy) or (vz, 0)
+    for (int64_t t = xcd_stride_block() * (int64_t)kBlock + threadIdx.x; t < 2 * n;
+         t += (int64_t)gridDim.x * kBlock) {
+        const int64_t q = t >> 1;
+        out[t] = (t & 1) ? make_double2(vz[q], 0.0) : make_double2(vx[q], vy[q]);
+    }
+}
+
 // A row of k (a power of two, at most 64) candidates per k / U lanes, U =
 // min(4, k) candidates a lane (lane l takes l, l + k/U, ...); the row's
 // maximum in registers, then by shuffles.  CONST: sigma is constant, so
 // w sigma rises with w^2 and, sqrt and the products rounding monotonically,
 // the largest rate is that of the largest w^2: the lanes carry w^2 and the
 // row's first lane takes one square root (the same value as the largest of
-// the rates).
+// the rates).  CONST reads the partners' velocities from those records.
 template <bool CONST>
 __global__ __launch_bounds__(kBlock) void k_timestep_group(StepArgs A, double c_sidm, double *dt_out)
 {
@@ -1701,7 +1744,8 @@ __global__ __launch_bounds__(kBlock) void k_timestep_group(StepArgs A, double c_
                     if (j < 0) {
                         atomicOr(A.derr, DERR_INDEX);
                     } else {
-                        const double dx = vix - A.vxs[j], dy = viy - A.vys[j], dz = viz - A.vzs[j];
+                        const double4 vj = A.vaos[j];
+                        const double dx = vix - vj.x, dy = viy - vj.y, dz = viz - vj.z;
                         const double w2 = (dx * dx + dy * dy) + dz * dz;
                         v = w2 > v ? w2 : v;
                     }
@@ -1799,7 +1843,8 @@ StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const dou
     A.wl0 = c->wl[0]; A.wl1 = c->wl[1]; A.mmark = c->mmark; A.plist = c->plist; A.head = c->head;
     A.R = c->trec; A.tmin = c->tmin; A.cap_rec = c->cap_rec;
     A.rfree = c->rfree; A.dbits = c->dbits; A.flist = c->flist; A.jsort = nullptr;
-    A.bbits = c->bbits; A.nbw = bucket_words(c->n); A.csum = nullptr;
+    A.bbits = c->bbits; A.nbw = bucket_words(c->n); A.csum = nullptr; A.vaos = nullptr;
+    A.erec = nullptr;
     A.ctl = c->acc_count;
     A.c1a = c->claim1[0]; A.c1b = c->claim1[1]; A.c2a = c->claim2[0]; A.c2b = c->claim2[1];
     A.st = c->dstats; A.derr = c->derr;
@@ -1902,7 +1947,10 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
         int64_t gr = total / 4 / 2048;
         gr = gr > 8192 ? 8192 : gr;
         const int gevr = gr > kEvalGrid ? grid8(gr) : grid_for(total / 4, kEvalGrid);
-        k_eval_rows<P><<<gevr, kBlock, 0, s>>>(A);
+        StepArgs E = A;
+        E.erec = (const double2 *)c->phase;
+        k_eval_recs<<<grid_for(4 * A.n, 8192), kBlock, 0, s>>>(A, (double2 *)c->phase);
+        k_eval_rows<P><<<gevr, kBlock, 0, s>>>(E);
     } else {
         k_eval<P, M, O><<<geval, kBlock, 0, s>>>(A);
     }
@@ -1978,9 +2026,13 @@ hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, co
     const int k = A.k;
     if (k <= 64 && (k & (k - 1)) == 0) {
         const int64_t lanes = n_active * (k < 4 ? 1 : k / 4);
-        if (c->cfg.xsec == SIDM_XSEC_CONST)
+        if (c->cfg.xsec == SIDM_XSEC_CONST) {
+            A.vaos = (const double4 *)c->phase;
+            k_vel_aos<<<grid_for(2 * c->n, 8192), kBlock, 0, c->stream>>>(c->n, c->vxs, c->vys, c->vzs,
+                                                                           (double2 *)c->phase);
             k_timestep_group<true><<<grid_for(lanes, 65536), kBlock, 0, c->stream>>>(
                 A, c->cfg.c_sidm, dt_out);
+        }
         else
             k_timestep_group<false><<<grid_for(lanes, 65536), kBlock, 0, c->stream>>>(
                 A, c->cfg.c_sidm, dt_out);
