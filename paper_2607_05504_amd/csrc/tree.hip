@@ -316,14 +316,22 @@ __global__ __launch_bounds__(256) void k_pack(int64_t n, const double *__restric
                                               const uint32_t *__restrict__ id,
                                               const uint8_t *__restrict__ st, double2 *rec)
 {
-    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n;
-         o += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t w = (uint64_t)id[o] | ((uint64_t)(st ? st[o] : 0) << 32);
-        double2 *r = rec + o * 4;
-        r[0] = make_double2(x[o], y[o]);
-        r[1] = make_double2(z[o], vx[o]);
-        r[2] = make_double2(vy[o], vz[o]);
-        r[3] = make_double2(mass ? mass[o] : 0.0, __longlong_as_double((long long)w));
+    // a lane a 16-byte quarter of a record: consecutive lanes write
+    // consecutive bytes
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 4 * n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = t >> 2;
+        const int q = (int)(t & 3);
+        double2 v;
+        if (q < 3) {
+            const double *pa = q == 0 ? x : q == 1 ? z : vy;
+            const double *pb = q == 0 ? y : q == 1 ? vx : vz;
+            v = make_double2(pa[o], pb[o]);
+        } else {
+            const uint64_t w = (uint64_t)id[o] | ((uint64_t)(st ? st[o] : 0) << 32);
+            v = make_double2(mass ? mass[o] : 0.0, __longlong_as_double((long long)w));
+        }
+        rec[t] = v;
     }
 }
 
@@ -604,7 +612,7 @@ hipError_t launch_refit_tree(sidm_ctx *c, const sidm_particles *p)
     hipStream_t s = c->stream;
     const int64_t n = p->n;
     const sidm_config &cfg = c->cfg;
-    k_pack<<<grid_for(n), kBlock, 0, s>>>(n, p->x, p->y, p->z, p->vx, p->vy, p->vz, p->mass, p->id,
+    k_pack<<<grid_for(4 * n), kBlock, 0, s>>>(n, p->x, p->y, p->z, p->vx, p->vy, p->vz, p->mass, p->id,
                                          p->state, (double2 *)c->rec);
     k_gather_rec<<<grid_for(4 * n), kBlock, 0, s>>>(n, c->perm, (const double2 *)c->rec,
                                                     p->mass != nullptr, c->xs, c->ys, c->zs,
