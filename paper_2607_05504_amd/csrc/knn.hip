@@ -811,19 +811,28 @@ __device__ __forceinline__ uint32_t wave_select(const uint32_t (&f)[E], int coun
 // Keeps the entries whose pattern is at most Tf, in order, at the front of
 // the list; returns their number.
 template <int E>
-__device__ __forceinline__ int wave_compact(uint64_t *L, const uint32_t (&f)[E], uint32_t Tf, int count)
+__device__ __forceinline__ int wave_compact(uint64_t *L, double *R2, const uint32_t (&f)[E], uint32_t Tf,
+                                            int count)
 {
     const int lane = threadIdx.x & 63;
     uint64_t v[E];
+    double r[E];
 #pragma unroll
-    for (int q = 0; q < E; ++q) v[q] = q * 64 + lane < count ? L[q * 64 + lane] : 0ull;
+    for (int q = 0; q < E; ++q) {
+        const bool in = q * 64 + lane < count;
+        v[q] = in ? L[q * 64 + lane] : 0ull;
+        r[q] = in ? R2[q * 64 + lane] : 0.0;
+    }
     wave_sync();
     int total = 0;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
         const bool keep = q * 64 + lane < count && f[q] <= Tf;
         const uint64_t m = __ballot(keep);
-        if (keep) L[total + lanes_below(m)] = v[q];
+        if (keep) {
+            L[total + lanes_below(m)] = v[q];
+            R2[total + lanes_below(m)] = r[q];
+        }
         total += __popcll(m);
     }
     wave_sync();
@@ -842,7 +851,7 @@ __device__ __forceinline__ uint64_t hit_word(double r2, int32_t j)
 template <bool PER, bool BUF>
 __device__ __forceinline__ bool wave_scan(const KnnArgs &A, const PosRsrc &pr, int32_t i, double px,
                                           double py, double pz, const int32_t *lst, int nl, uint32_t *K,
-                                          uint64_t *L, double &T, int &count)
+                                          uint64_t *L, double *R2, double &T, int &count)
 {
     const int lane = threadIdx.x & 63;
     const double box = A.box;
@@ -908,7 +917,7 @@ __device__ __forceinline__ bool wave_scan(const KnnArgs &A, const PosRsrc &pr, i
             int c_hi;
             const uint32_t Tf = wave_select<kHitQ>(f, count, K1, K1 + 8, c_hi);
             if (c_hi > kHitCap - 64 * kRound) return false;   // too many equal values
-            count = wave_compact<kHitQ>(L, f, Tf, count);
+            count = wave_compact<kHitQ>(L, R2, f, Tf, count);
             T = fmin(T, (double)__uint_as_float(Tf));
 #pragma unroll
             for (int u = 0; u < kRound; ++u) hit[u] = ok[u] && r2[u] <= T;
@@ -916,7 +925,10 @@ __device__ __forceinline__ bool wave_scan(const KnnArgs &A, const PosRsrc &pr, i
 #pragma unroll
         for (int u = 0; u < kRound; ++u) {
             const uint64_t m = __ballot(hit[u]);
-            if (hit[u]) L[count + lanes_below(m)] = hit_word(r2[u], jv[u]);
+            if (hit[u]) {
+                L[count + lanes_below(m)] = hit_word(r2[u], jv[u]);
+                R2[count + lanes_below(m)] = r2[u];
+            }
             count += __popcll(m);
         }
     }
@@ -924,27 +936,25 @@ __device__ __forceinline__ bool wave_scan(const KnnArgs &A, const PosRsrc &pr, i
 }
 
 // Each lane's entries (RQ each, entry q * 64 + lane < count) placed by rank in
-// (exact r^2, ID, index): rank < k to row place rank, rank k gives h.
-template <bool PER, bool BUF, int RQ>
-__device__ __forceinline__ void wave_rank_out(const KnnArgs &A, const PosRsrc &pr, double px, double py,
-                                              double pz, const uint64_t *L, double *R2, uint32_t *S,
-                                              int count, int32_t *out, int32_t *srt, int32_t a)
+// (exact r^2, ID, index): rank < k to row place rank, rank k gives h.  The
+// exact r^2 are those the scan stored beside the list.
+template <int RQ>
+__device__ __forceinline__ void wave_rank_out(const KnnArgs &A, const uint64_t *L, const double *R2,
+                                              uint32_t *S, int count, int32_t *out, int32_t *srt,
+                                              int32_t a)
 {
     const int lane = threadIdx.x & 63;
     double re[RQ];
     int32_t je[RQ];
     int rank[RQ];
+    wave_sync();
 #pragma unroll
     for (int q = 0; q < RQ; ++q) {
         const int e = q * 64 + lane;
         je[q] = e < count ? (int32_t)(uint32_t)L[e] : -1;
-        double x = 0.0, y = 0.0, z = 0.0;
-        if (je[q] >= 0) load_pos<BUF>(A, pr, je[q], x, y, z);
-        re[q] = je[q] >= 0 ? sep2_sel<PER>(px, py, pz, x, y, z, A.box) : INFINITY;
-        if (e < count) R2[e] = re[q];
+        re[q] = e < count ? R2[e] : INFINITY;
         rank[q] = 0;
     }
-    wave_sync();
     for (int f2 = 0; f2 < count; ++f2) {
         const double rf = R2[f2];
 #pragma unroll
@@ -1023,8 +1033,8 @@ __device__ __forceinline__ void wave_target(const KnnArgs &A, int64_t base, int6
     const bool inside = px - R > 0.0 && px + R < box && py - R > 0.0 && py + R < box && pz - R > 0.0 &&
                         pz + R < box;
     const bool per = PERIODIC && !inside;
-    const bool done = per ? wave_scan<PERIODIC, BUF>(A, pr, i, px, py, pz, lst, nl, K, L, T, count)
-                          : wave_scan<false, BUF>(A, pr, i, px, py, pz, lst, nl, K, L, T, count);
+    const bool done = per ? wave_scan<PERIODIC, BUF>(A, pr, i, px, py, pz, lst, nl, K, L, R2, T, count)
+                          : wave_scan<false, BUF>(A, pr, i, px, py, pz, lst, nl, K, L, R2, T, count);
     if (!done) {
         if (lane == 0) {
             A.nl[bb] = -1;
@@ -1046,18 +1056,13 @@ __device__ __forceinline__ void wave_target(const KnnArgs &A, int64_t base, int6
             f[q] = q * 64 + lane < count ? (uint32_t)(L[q * 64 + lane] >> 32) : 0xffffffffu;
         int c_hi;
         const uint32_t Tf = wave_select<kHitQ>(f, count, K1, 64, c_hi);
-        count = wave_compact<kHitQ>(L, f, Tf, count);
+        count = wave_compact<kHitQ>(L, R2, f, Tf, count);
     }
     int32_t *out = A.ngb + (int64_t)a * A.k;
     int32_t *srt = A.jsort + b * A.k;
     uint32_t *S = K;                           // the kept list is done with
-    if (count <= 64) {
-        if (per) wave_rank_out<PERIODIC, BUF, 1>(A, pr, px, py, pz, L, R2, S, count, out, srt, a);
-        else wave_rank_out<false, BUF, 1>(A, pr, px, py, pz, L, R2, S, count, out, srt, a);
-    } else {
-        if (per) wave_rank_out<PERIODIC, BUF, kHitQ>(A, pr, px, py, pz, L, R2, S, count, out, srt, a);
-        else wave_rank_out<false, BUF, kHitQ>(A, pr, px, py, pz, L, R2, S, count, out, srt, a);
-    }
+    if (count <= 64) wave_rank_out<1>(A, L, R2, S, count, out, srt, a);
+    else wave_rank_out<kHitQ>(A, L, R2, S, count, out, srt, a);
 }
 
 template <bool PERIODIC>
