@@ -459,15 +459,22 @@ __global__ void k_level_boxes(double *nodes, int64_t off_child, int64_t cnt_chil
 }
 
 // --- active set -> Morton order --------------------------------------------------------
+// Plain stores mark the sorted slots (a duplicate entry overwrites its twin);
+// the entries out of range are counted in *bad, so that the scan finds a
+// duplicate as fewer marked slots than valid entries.
 __global__ void k_mark_active(const int32_t *__restrict__ active, int64_t n_active, int64_t n,
-                              const int32_t *__restrict__ inv, int32_t *flag, unsigned int *derr)
+                              const int32_t *__restrict__ inv, int32_t *flag, int32_t *bad,
+                              unsigned int *derr)
 {
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n_active;
          a += (int64_t)gridDim.x * blockDim.x) {
         int32_t i = active[a];
-        if (i < 0 || i >= n) { atomicOr(derr, DERR_INDEX); continue; }
-        int32_t old = atomicExch(&flag[inv[i]], (int32_t)a);
-        if (old != -1) atomicOr(derr, DERR_DUPLICATE);
+        if (i < 0 || i >= n) {
+            atomicOr(derr, DERR_INDEX);
+            atomicAdd(bad, 1);
+            continue;
+        }
+        flag[inv[i]] = (int32_t)a;
     }
 }
 
@@ -487,8 +494,11 @@ __global__ __launch_bounds__(256) void k_count_active(const int32_t *__restrict_
     if (threadIdx.x == 0) blk[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
 
-// single workgroup: exclusive scan of the per-block counts, total -> *nt
-__global__ __launch_bounds__(1024) void k_scan_blocks(int32_t *blk, int nblk, int32_t *nt)
+// single workgroup: exclusive scan of the per-block counts, total -> *nt;
+// blk[nblk] holds the active entries out of range: fewer marked slots than
+// the other entries means a duplicate
+__global__ __launch_bounds__(1024) void k_scan_blocks(int32_t *blk, int nblk, int32_t *nt, int64_t n_active,
+                                                      unsigned int *derr)
 {
     __shared__ int32_t part[1024];
     const int per = (nblk + 1023) / 1024;
@@ -512,7 +522,10 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int32_t *blk, int nblk, in
             run += c;
         }
     }
-    if (threadIdx.x == 1023) *nt = part[1023];
+    if (threadIdx.x == 1023) {
+        *nt = part[1023];
+        if ((int64_t)part[1023] + blk[nblk] < n_active) atomicOr(derr, DERR_DUPLICATE);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_compact_active(const int32_t *__restrict__ flag, int64_t n,
@@ -640,12 +653,13 @@ hipError_t launch_map_active(sidm_ctx *c, const int32_t *active, int64_t n_activ
     hipStream_t s = c->stream;
     const int64_t n = c->n;
     phase_begin(c, PH_MAP);
-    launch_fill_i32(c->flag, -1, n, s);
-    k_mark_active<<<grid_for(n_active), kBlock, 0, s>>>(active, n_active, n, c->inv, c->flag,
-                                                        c->derr);
     const int nblk = (int)((n + SIDM_SCAN_TILE - 1) / SIDM_SCAN_TILE);
+    launch_fill_i32(c->flag, -1, n, s);
+    launch_fill_i32(c->blk + nblk, 0, 1, s);
+    k_mark_active<<<grid_for(n_active), kBlock, 0, s>>>(active, n_active, n, c->inv, c->flag,
+                                                        c->blk + nblk, c->derr);
     k_count_active<<<nblk, 256, 0, s>>>(c->flag, n, c->blk);
-    k_scan_blocks<<<1, 1024, 0, s>>>(c->blk, nblk, c->nt_dev);
+    k_scan_blocks<<<1, 1024, 0, s>>>(c->blk, nblk, c->nt_dev, n_active, c->derr);
     k_compact_active<<<nblk, 256, 0, s>>>(c->flag, n, c->blk, c->tlist, c->slot);
     phase_end(c, PH_MAP);
     return hipGetLastError();
