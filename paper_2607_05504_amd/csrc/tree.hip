@@ -638,7 +638,7 @@ hipError_t launch_refit_tree(sidm_ctx *c, const sidm_particles *p)
     k_leaf_boxes<<<(unsigned)((nleaf * 32 + 255) / 256), 256, 0, s>>>(
         n, nleaf, c->xs, c->ys, c->zs, c->nodes, c->sbox, lv.off[1], lv.cnt[1]);
     int l = 2;
-    for (; l < lv.nlev && lv.cnt[l] > 8192; ++l)
+    for (; l < lv.nlev && lv.cnt[l] > 1024; ++l)
         k_level_boxes<<<(unsigned)((lv.cnt[l] + 255) / 256), 256, 0, s>>>(
             c->nodes, lv.off[l - 1], lv.cnt[l - 1], lv.off[l], lv.cnt[l]);
     if (l < lv.nlev) k_top_levels<<<1, 1024, 0, s>>>(c->nodes, lv, l);
