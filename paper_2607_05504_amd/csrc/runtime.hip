@@ -241,6 +241,14 @@ int test_device_rounds()
     return 6;
 }
 
+// tests only: the row block summaries and the partner records also for the
+// small steps they do not pay off on
+int test_force_rows()
+{
+    const char *e = getenv("SIDM_TEST_FORCE_ROWS");
+    return e && e[0] == '1';
+}
+
 }  // namespace
 
 extern "C" {
@@ -380,6 +388,7 @@ sidm_status sidm_create(const sidm_config *cfg, int64_t cap_n, int64_t cap_activ
     launch_fill_i32((int32_t *)c->dbits, 0, (cap_n + 31) / 32, s);
     launch_fill_i32((int32_t *)c->bbits, 0, bucket_words(cap_n), s);
     c->dev_rounds = test_device_rounds();
+    c->force_rows = test_force_rows();
     launch_fill_i32((int32_t *)c->dstats, 0, (int64_t)(sizeof(DevStats) / 4), s);
     hipError_t e = copy_table(c);
     if (e == hipSuccess && c->cfg.estimator == SIDM_EST_OVERLAP) e = launch_overlap_table(c);

@@ -432,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_recs(StepArgs A, double2 *out)
 // lane takes four candidates of a row (k / 4 lanes a row), so that the
 // target's data, its timestep and the kernel's normalisation are read and
 // computed once for four.  Same arithmetic per candidate as k_eval.
-template <bool PERIODIC>
+template <bool PERIODIC, bool REC>
 __global__ __launch_bounds__(kBlock) void k_eval_rows(StepArgs A)
 {
     __shared__ StagedAccRows S;
@@ -477,9 +477,18 @@ __global__ __launch_bounds__(kBlock) void k_eval_rows(StepArgs A)
                     if (!A.jsort) atomicOr(A.derr, DERR_INDEX);   // else latched by k_rows
                     continue;
                 }
-                // the partner's record: four 16-byte loads instead of eight gathers
-                const double2 *R = A.erec + 4 * (int64_t)j;
-                const double2 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3];
+                // the partner's record (four 16-byte loads instead of eight
+                // gathers), else its entries in the snapshot
+                double2 r0, r1, r2, r3;
+                if constexpr (REC) {
+                    const double2 *R = A.erec + 4 * (int64_t)j;
+                    r0 = R[0]; r1 = R[1]; r2 = R[2]; r3 = R[3];
+                } else {
+                    r0 = make_double2(A.xs[j], A.ys[j]);
+                    r1 = make_double2(A.zs[j], A.vxs[j]);
+                    r2 = make_double2(A.vys[j], A.vzs[j]);
+                    r3 = make_double2(__longlong_as_double((long long)A.ids[j]), mass_of(A, j));
+                }
                 const uint32_t idj = (uint32_t)__double_as_longlong(r3.x);
                 const Philox4 x = pair_draw(A.seed, A.step, idi, idj, PURPOSE_DECIDE);
                 const double u = unit_from_word(direction_word(x, idi < idj));
@@ -1708,7 +1717,7 @@ __global__ __launch_bounds__(kBlock) void k_vel_aos(int64_t n, const double *vx,
 // the largest rate is that of the largest w^2: the lanes carry w^2 and the
 // row's first lane takes one square root (the same value as the largest of
 // the rates).  CONST reads the partners' velocities from those records.
-template <bool CONST>
+template <bool CONST, bool REC>
 __global__ __launch_bounds__(kBlock) void k_timestep_group(StepArgs A, double c_sidm, double *dt_out)
 {
     constexpr int UMAX = 4;
@@ -1744,8 +1753,14 @@ __global__ __launch_bounds__(kBlock) void k_timestep_group(StepArgs A, double c_
                     if (j < 0) {
                         atomicOr(A.derr, DERR_INDEX);
                     } else {
-                        const double4 vj = A.vaos[j];
-                        const double dx = vix - vj.x, dy = viy - vj.y, dz = viz - vj.z;
+                        double vjx, vjy, vjz;
+                        if constexpr (REC) {
+                            const double4 vj = A.vaos[j];
+                            vjx = vj.x; vjy = vj.y; vjz = vj.z;
+                        } else {
+                            vjx = A.vxs[j]; vjy = A.vys[j]; vjz = A.vzs[j];
+                        }
+                        const double dx = vix - vjx, dy = viy - vjy, dz = viz - vjz;
                         const double w2 = (dx * dx + dy * dy) + dz * dz;
                         v = w2 > v ? w2 : v;
                     }
@@ -1947,10 +1962,16 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
         int64_t gr = total / 4 / 2048;
         gr = gr > 8192 ? 8192 : gr;
         const int gevr = gr > kEvalGrid ? grid8(gr) : grid_for(total / 4, kEvalGrid);
-        StepArgs E = A;
-        E.erec = (const double2 *)c->phase;
-        k_eval_recs<<<grid_for(4 * A.n, 8192), kBlock, 0, s>>>(A, (double2 *)c->phase);
-        k_eval_rows<P><<<gevr, kBlock, 0, s>>>(E);
+        // partner records when the gathers they save outweigh writing one
+        // for every particle (at least 8 candidates a particle)
+        if (c->force_rows || total >= 8 * A.n) {
+            StepArgs E = A;
+            E.erec = (const double2 *)c->phase;
+            k_eval_recs<<<grid_for(4 * A.n, 8192), kBlock, 0, s>>>(A, (double2 *)c->phase);
+            k_eval_rows<P, true><<<gevr, kBlock, 0, s>>>(E);
+        } else {
+            k_eval_rows<P, false><<<gevr, kBlock, 0, s>>>(A);
+        }
     } else {
         k_eval<P, M, O><<<geval, kBlock, 0, s>>>(A);
     }
@@ -2001,9 +2022,13 @@ hipError_t launch_scatter(sidm_ctx *c, sidm_particles *p, int64_t n_active, cons
     c->jsort_ngb = ngb;
     c->jsort_knn = 0;
     // row block summaries for the checks: rows of a power of two entries,
-    // written by the first grid check
+    // written by the first grid check; they pay off on long steps (the
+    // first check's extra work against the later checks' savings: 2^26
+    // candidates, and at least 8 a particle)
     const int st = A.stride;
-    if (c->csum && c->dev_rounds > 0 && st >= 4 && st <= SIDM_SUM_U && (st & (st - 1)) == 0)
+    const int64_t cands = n_active * st;
+    if (c->csum && c->dev_rounds > 0 && st >= 4 && st <= SIDM_SUM_U && (st & (st - 1)) == 0 &&
+        (c->force_rows || (cands >= ((int64_t)1 << 26) && cands >= 8 * c->n)))
         A.csum = c->csum;
     const bool mixed = c->cfg.precision == SIDM_MIXED;
     if (c->cfg.periodic) {
@@ -2027,14 +2052,21 @@ hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, co
     if (k <= 64 && (k & (k - 1)) == 0) {
         const int64_t lanes = n_active * (k < 4 ? 1 : k / 4);
         if (c->cfg.xsec == SIDM_XSEC_CONST) {
-            A.vaos = (const double4 *)c->phase;
-            k_vel_aos<<<grid_for(2 * c->n, 8192), kBlock, 0, c->stream>>>(c->n, c->vxs, c->vys, c->vzs,
-                                                                           (double2 *)c->phase);
-            k_timestep_group<true><<<grid_for(lanes, 65536), kBlock, 0, c->stream>>>(
-                A, c->cfg.c_sidm, dt_out);
+            // velocity records when the gathers they save outweigh writing
+            // one for every particle (at least 8 candidates a particle)
+            if (c->force_rows || n_active * k >= 8 * c->n) {
+                A.vaos = (const double4 *)c->phase;
+                k_vel_aos<<<grid_for(2 * c->n, 8192), kBlock, 0, c->stream>>>(c->n, c->vxs, c->vys,
+                                                                               c->vzs, (double2 *)c->phase);
+                k_timestep_group<true, true><<<grid_for(lanes, 65536), kBlock, 0, c->stream>>>(
+                    A, c->cfg.c_sidm, dt_out);
+            } else {
+                k_timestep_group<true, false><<<grid_for(lanes, 65536), kBlock, 0, c->stream>>>(
+                    A, c->cfg.c_sidm, dt_out);
+            }
         }
         else
-            k_timestep_group<false><<<grid_for(lanes, 65536), kBlock, 0, c->stream>>>(
+            k_timestep_group<false, false><<<grid_for(lanes, 65536), kBlock, 0, c->stream>>>(
                 A, c->cfg.c_sidm, dt_out);
     }
     else

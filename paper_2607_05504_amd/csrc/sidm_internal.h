@@ -193,6 +193,7 @@ struct sidm_ctx {
     int32_t *acc_count;      // [16] control words (list counts, passes, rounds)
     unsigned long long *claim1[2], *claim2[2];   // [cap_n] per-particle claims
     int dev_rounds;          // rounds run as grid launches before the one-workgroup tail
+    int force_rows;          // row block summaries and partner records whatever the sizes (tests)
 
     DevStats *dstats;
     unsigned int *derr;

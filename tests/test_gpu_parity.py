@@ -87,14 +87,18 @@ def test_rounds_in_one_workgroup(monkeypatch):
     assert (hit & ~acc0).any() and (acc0 & ~hit).any()
 
 
-def test_tail_rounds_with_block_summaries(monkeypatch):
-    """One grid round (the full scan that writes the row block summaries),
-    every later round in the one-workgroup tail: few particles per index
-    bucket change after the first round, so the tail's checks scan only the
-    row blocks that may touch them.  The same serial order."""
-    monkeypatch.setenv("SIDM_TEST_DEVICE_ROUNDS", "1")
+@pytest.mark.parametrize("grid_rounds", [6, 1])
+def test_rounds_with_block_summaries(monkeypatch, grid_rounds):
+    """Row block summaries and partner records forced on (the library keeps
+    them for steps of 2^26 candidates and more): the first check's full scan
+    writes the summaries; few particles per index bucket change after the
+    first round, so the later checks scan only the row blocks that may touch
+    them -- on the grid, or (one grid round) in the one-workgroup tail.  The
+    same serial order."""
+    monkeypatch.setenv("SIDM_TEST_FORCE_ROWS", "1")
+    monkeypatch.setenv("SIDM_TEST_DEVICE_ROUNDS", str(grid_rounds))
     w = W.uniform_box(262144, ic_seed=46, scatters_per_particle=0.05)
-    _announce("tail rounds with block summaries")
+    _announce(f"rounds with block summaries, {grid_rounds} on the grid")
     ref = oracle.full_step(w)
     g = gpu_step(w)
     assert g["stats"]["n_rounds"] >= 2
