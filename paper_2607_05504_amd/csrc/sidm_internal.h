@@ -292,7 +292,7 @@ __device__ __forceinline__ double node_gap2(const double *__restrict__ nodes, in
 // nothing.
 #define SIDM_XCDS 8
 #ifndef SIDM_XCD_RUN
-#define SIDM_XCD_RUN 16
+#define SIDM_XCD_RUN 256
 #endif
 inline unsigned xcd_grid(int64_t g)
 {

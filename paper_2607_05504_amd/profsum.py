@@ -49,14 +49,19 @@ def copy_factor(d: str, mib: int) -> float:
     return (mib * 1024.0) / (sum(big) / len(big))
 
 
-KNN_KERNELS = ("k_knn_list", "k_knn_team", "k_knn")
-KNN_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "knn.hip")
+KNN_KERNELS = ("k_knn_list", "k_knn_bucket", "k_knn_team")
+KNN_SOURCES = tuple(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f)
+                    for f in ("knn.hip", "sidm_internal.h"))
 
 
-def source_hash(path: str = KNN_SOURCE) -> str:
-    """Identifies the kernel source the counters were taken on; a traffic
-    figure taken on another source is stale."""
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def source_hash(paths=KNN_SOURCES) -> str:
+    """Identifies the kernel sources the counters were taken on (the search
+    and the shared header with its launch mapping); a traffic figure taken on
+    other sources is stale."""
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic(fd, wd, cfd, cwd, mib, workload, out_json=None) -> str:
