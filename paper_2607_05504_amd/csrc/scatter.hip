@@ -1963,8 +1963,9 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
         gr = gr > 8192 ? 8192 : gr;
         const int gevr = gr > kEvalGrid ? grid8(gr) : grid_for(total / 4, kEvalGrid);
         // partner records when the gathers they save outweigh writing one
-        // for every particle (at least 8 candidates a particle)
-        if (c->force_rows || total >= 8 * A.n) {
+        // for every particle (at least 8 candidates a particle) and the
+        // launch (2^20 candidates)
+        if (c->force_rows || (total >= 8 * A.n && total >= ((int64_t)1 << 20))) {
             StepArgs E = A;
             E.erec = (const double2 *)c->phase;
             k_eval_recs<<<grid_for(4 * A.n, 8192), kBlock, 0, s>>>(A, (double2 *)c->phase);
@@ -2053,8 +2054,10 @@ hipError_t launch_timestep(sidm_ctx *c, int64_t n_active, const int32_t *ngb, co
         const int64_t lanes = n_active * (k < 4 ? 1 : k / 4);
         if (c->cfg.xsec == SIDM_XSEC_CONST) {
             // velocity records when the gathers they save outweigh writing
-            // one for every particle (at least 8 candidates a particle)
-            if (c->force_rows || n_active * k >= 8 * c->n) {
+            // one for every particle (at least 8 candidates a particle) and
+            // the launch (2^20 candidates)
+            const int64_t cands = n_active * k;
+            if (c->force_rows || (cands >= 8 * c->n && cands >= ((int64_t)1 << 20))) {
                 A.vaos = (const double4 *)c->phase;
                 k_vel_aos<<<grid_for(2 * c->n, 8192), kBlock, 0, c->stream>>>(c->n, c->vxs, c->vys,
                                                                                c->vzs, (double2 *)c->phase);

@@ -286,25 +286,29 @@ __device__ __forceinline__ double node_gap2(const double *__restrict__ nodes, in
 // XCD-aware block order.  The 8 XCDs of an MI355X each have their own L2, and
 // a launch deals its workgroups to them round-robin (workgroup b to XCD
 // b % 8).  Launched with xcd_grid(g) workgroups, xcd_block maps them so that
-// each XCD runs runs of SIDM_XCD_RUN consecutive logical blocks (spatially
+// each XCD runs runs of xcd_run(g) consecutive logical blocks (spatially
 // close targets share an L2), the runs dealt round-robin so that the XCDs'
-// loads stay balanced.  Returns -1 for the padding workgroups, which must do
+// loads stay balanced: runs of g / 64 blocks (at least eight a XCD), from 16
+// to SIDM_XCD_RUN.  Returns -1 for the padding workgroups, which must do
 // nothing.
 #define SIDM_XCDS 8
-#ifndef SIDM_XCD_RUN
 #define SIDM_XCD_RUN 256
-#endif
+__host__ __device__ inline int64_t xcd_run(int64_t g)
+{
+    const int64_t r = g / (8 * SIDM_XCDS);
+    return r < 16 ? 16 : r > SIDM_XCD_RUN ? SIDM_XCD_RUN : r;
+}
 inline unsigned xcd_grid(int64_t g)
 {
-    const int64_t span = (int64_t)SIDM_XCDS * SIDM_XCD_RUN;
+    const int64_t span = (int64_t)SIDM_XCDS * xcd_run(g);
     return (unsigned)((g + span - 1) / span * span);
 }
 __device__ __forceinline__ int64_t xcd_block(int64_t g)
 {
+    const int64_t run = xcd_run(g);
     const int64_t b = blockIdx.x;
     const int64_t x = b % SIDM_XCDS, k = b / SIDM_XCDS;     // k-th workgroup on XCD x
-    const int64_t logical = (k / SIDM_XCD_RUN) * (SIDM_XCDS * SIDM_XCD_RUN) + x * SIDM_XCD_RUN +
-                            k % SIDM_XCD_RUN;
+    const int64_t logical = (k / run) * (SIDM_XCDS * run) + x * run + k % run;
     return logical < g ? logical : -1;
 }
 
