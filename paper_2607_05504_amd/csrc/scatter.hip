@@ -25,7 +25,11 @@
 //              accepts there would have changed the step: it is listed.
 //              If no candidate is, the replayed turns are the serial order
 //              (every unlisted candidate rejects at its turn, so it changes
-//              nothing), and the check's counts are the step's.
+//              nothing), and the check's counts are the step's.  On long
+//              steps the first check also writes a summary of each block of
+//              1024 candidates (the index buckets its particles lie in), and
+//              a later check scans only the blocks with a bucket holding a
+//              particle of D.
 //  k_reround   one workgroup: the turns that a newly listed candidate can
 //              affect (later turns of its particles, closed under sharing a
 //              particle) are rewound -- those particles' velocities restored
