@@ -105,6 +105,20 @@ def test_rounds_with_block_summaries(monkeypatch, grid_rounds):
     assert_parity(w, g, ref)
 
 
+@pytest.mark.parametrize("k", [4, 16])
+def test_block_summaries_other_row_lengths(monkeypatch, k):
+    """Row block summaries and partner records forced on for rows of 4 and 16
+    candidates (a block of 1024 candidates is 256 or 64 rows; a lane of the
+    checks and of the evaluation takes four candidates of a row)."""
+    monkeypatch.setenv("SIDM_TEST_FORCE_ROWS", "1")
+    w = W.uniform_box(131072, ic_seed=47 + k, scatters_per_particle=0.1, n_ngb=k)
+    _announce(f"block summaries, n_ngb={k}")
+    ref = oracle.full_step(w)
+    g = gpu_step(w)
+    assert g["stats"]["n_rounds"] >= 2
+    assert_parity(w, g, ref)
+
+
 @pytest.mark.parametrize("k", [1, 8, 16, 31, 48, 63])
 def test_neighbour_counts(k):
     """n_ngb from 1 to the largest accepted (63): the short-list and long-list
