@@ -85,6 +85,7 @@ struct StepArgs {
     int32_t *jsort;          // the step's rows in Morton order (sorted indices), or NULL
     const double4 *vaos;     // velocities as (vx, vy, vz, 0) records for the timestep's gathers, or NULL
     const double2 *erec;     // per particle (x, y), (z, vx), (vy, vz), (id bits, mass): the evaluation's gathers
+    int recs, verify_rows;   // the row-wise evaluation uses erec; and checks the rows against ngb
     int32_t *ctl;
     unsigned long long *c1a, *c1b, *c2a, *c2b;
     DevStats *st;
@@ -410,7 +411,8 @@ __device__ __forceinline__ double cubic_spline_n(double r, double h, double norm
 }
 
 // The evaluation's per-particle records (in the phase buffer, which the step
-// does not otherwise use): a partner's data in one 64-byte line.
+// does not otherwise use): a partner's data in one 64-byte line, the ID in
+// the low and the caller index in the high half of the third word.
 __global__ __launch_bounds__(kBlock) void k_eval_recs(StepArgs A, double2 *out)
 {
     // a lane a 16-byte quarter of a record: consecutive lanes write
@@ -426,7 +428,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_recs(StepArgs A, double2 *out)
             const double *pb = part == 0 ? A.ys : part == 1 ? A.vxs : A.vzs;
             v = make_double2(pa[q], pb[q]);
         } else {
-            v = make_double2(__longlong_as_double((long long)A.ids[q]), mass_of(A, (int32_t)q));
+            const uint64_t w = ((uint64_t)(uint32_t)A.perm[q] << 32) | A.ids[q];
+            v = make_double2(__longlong_as_double((long long)w), mass_of(A, (int32_t)q));
         }
         out[t] = v;
     }
@@ -436,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_recs(StepArgs A, double2 *out)
 // lane takes four candidates of a row (k / 4 lanes a row), so that the
 // target's data, its timestep and the kernel's normalisation are read and
 // computed once for four.  Same arithmetic per candidate as k_eval.
-template <bool PERIODIC, bool REC>
+template <bool PERIODIC, bool REC, bool VERIFY>
 __global__ __launch_bounds__(kBlock) void k_eval_rows(StepArgs A)
 {
     __shared__ StagedAccRows S;
@@ -464,30 +467,61 @@ __global__ __launch_bounds__(kBlock) void k_eval_rows(StepArgs A)
             const double vxi = A.vxs[i], vyi = A.vys[i], vzi = A.vzs[i];
             const double hp = A.lphys * A.h[a];
             const double norm = spline_norm(hp);
-            int32_t jj[4];
+            // with records a lane takes four consecutive entries of the row
+            // (one 16-byte load of the rows, and of ngb to check them), else
+            // every L-th (the row's lanes read consecutive words)
+            int32_t jj[4], jc[4];
+            if constexpr (REC) {
+                const int4 q = *(const int4 *)(A.jsort + (b << sh) + 4 * l);
+                jj[0] = q.x; jj[1] = q.y; jj[2] = q.z; jj[3] = q.w;
+                if constexpr (VERIFY) {
+                    const int4 g = *(const int4 *)(A.ngb + (int64_t)a * A.stride + 4 * l);
+                    jc[0] = g.x; jc[1] = g.y; jc[2] = g.z; jc[3] = g.w;
+                }
+            } else {
 #pragma unroll
-            for (int u4 = 0; u4 < 4; ++u4) {
-                const int sidx = l + u4 * L;
-                jj[u4] = partner(A, (b << sh) + sidx, (int64_t)a * A.stride + sidx);
+                for (int u4 = 0; u4 < 4; ++u4) {
+                    const int sidx = l + u4 * L;
+                    jj[u4] = partner(A, (b << sh) + sidx, (int64_t)a * A.stride + sidx);
+                }
             }
 #pragma unroll
             for (int u4 = 0; u4 < 4; ++u4) {
-                const int sidx = l + u4 * L;
+                const int sidx = REC ? 4 * l + u4 : l + u4 * L;
                 const int64_t c = (b << sh) + sidx;
                 const int64_t ci = (int64_t)a * A.stride + sidx;
-                const int32_t j = jj[u4];
+                int32_t j = jj[u4];
                 n_cd += 1;
-                if (j < 0) {
-                    if (!A.jsort) atomicOr(A.derr, DERR_INDEX);   // else latched by k_rows
-                    continue;
-                }
                 // the partner's record (four 16-byte loads instead of eight
                 // gathers), else its entries in the snapshot
                 double2 r0, r1, r2, r3;
-                if constexpr (REC) {
+                if constexpr (VERIFY) {
+                    // k_rows' check here: the row entry stands if the caller
+                    // index in its record is the caller's ngb entry, else it
+                    // is translated (and written back for the later kernels)
+                    bool ok = j >= 0 && j < A.n;
+                    if (ok) {
+                        const double2 *R = A.erec + 4 * (int64_t)j;
+                        r0 = R[0]; r1 = R[1]; r2 = R[2]; r3 = R[3];
+                        ok = (int32_t)((uint64_t)__double_as_longlong(r3.x) >> 32) == jc[u4];
+                    }
+                    if (!ok) {
+                        j = (jc[u4] >= 0 && jc[u4] < A.n) ? A.inv[jc[u4]] : -1;
+                        if (j < 0) atomicOr(A.derr, DERR_INDEX);
+                        A.jsort[c] = j;
+                        if (j < 0) continue;
+                        const double2 *R = A.erec + 4 * (int64_t)j;
+                        r0 = R[0]; r1 = R[1]; r2 = R[2]; r3 = R[3];
+                    }
+                } else if constexpr (REC) {
+                    if (j < 0) continue;                        // latched by k_rows
                     const double2 *R = A.erec + 4 * (int64_t)j;
                     r0 = R[0]; r1 = R[1]; r2 = R[2]; r3 = R[3];
                 } else {
+                    if (j < 0) {
+                        if (!A.jsort) atomicOr(A.derr, DERR_INDEX);   // else latched by k_rows
+                        continue;
+                    }
                     r0 = make_double2(A.xs[j], A.ys[j]);
                     r1 = make_double2(A.zs[j], A.vxs[j]);
                     r2 = make_double2(A.vys[j], A.vzs[j]);
@@ -1863,7 +1897,7 @@ StepArgs make_args(sidm_ctx *c, sidm_particles *p, const int32_t *ngb, const dou
     A.R = c->trec; A.tmin = c->tmin; A.cap_rec = c->cap_rec;
     A.rfree = c->rfree; A.dbits = c->dbits; A.flist = c->flist; A.jsort = nullptr;
     A.bbits = c->bbits; A.nbw = bucket_words(c->n); A.csum = nullptr; A.vaos = nullptr;
-    A.erec = nullptr;
+    A.erec = nullptr; A.recs = 0; A.verify_rows = 0;
     A.ctl = c->acc_count;
     A.c1a = c->claim1[0]; A.c1b = c->claim1[1]; A.c2a = c->claim2[0]; A.c2b = c->claim2[1];
     A.st = c->dstats; A.derr = c->derr;
@@ -1969,15 +2003,18 @@ void run_scatter(sidm_ctx *c, const StepArgs &A, int64_t n_active, hipStream_t s
         // partner records when the gathers they save outweigh writing one
         // for every particle (at least 8 candidates a particle) and the
         // launch (2^20 candidates)
-        if (c->force_rows || (total >= 8 * A.n && total >= ((int64_t)1 << 20))) {
+        if (A.recs) {
             StepArgs E = A;
             E.erec = (const double2 *)c->phase;
             k_eval_recs<<<grid_for(4 * A.n, 8192), kBlock, 0, s>>>(A, (double2 *)c->phase);
-            k_eval_rows<P, true><<<gevr, kBlock, 0, s>>>(E);
+            if (A.verify_rows) k_eval_rows<P, true, true><<<gevr, kBlock, 0, s>>>(E);
+            else k_eval_rows<P, true, false><<<gevr, kBlock, 0, s>>>(E);
         } else {
-            k_eval_rows<P, false><<<gevr, kBlock, 0, s>>>(A);
+            k_eval_rows<P, false, false><<<gevr, kBlock, 0, s>>>(A);
         }
     } else {
+        if (A.verify_rows)       // not reached (the rows form is taken whenever records are)
+            k_rows<<<grid_for(total, 8192), kBlock, 0, s>>>(A, 1);
         k_eval<P, M, O><<<geval, kBlock, 0, s>>>(A);
     }
     phase_end(c, PH_EVAL);
@@ -2020,22 +2057,33 @@ hipError_t launch_scatter(sidm_ctx *c, sidm_particles *p, int64_t n_active, cons
     StepArgs A = make_args(c, p, ngb, h, dt, seed, step, cand_info);
     A.jsort = c->jsort;
     const int have = c->jsort_knn || c->jsort_ngb == ngb;
-    if (A.stride % 4 == 0 && ((uintptr_t)ngb & 15) == 0)
+    const bool mixed = c->cfg.precision == SIDM_MIXED;
+    const int st = A.stride;
+    const int64_t cands = n_active * st;
+    // the row-wise evaluation (rows of a power of two entries) gathers from
+    // partner records when they outweigh writing one for every particle (at
+    // least 8 candidates a particle) and the launch (2^20 candidates); with
+    // records and rows from a search it also checks the rows against ngb,
+    // which k_rows does otherwise
+    const bool rows = !mixed && st >= 4 && (st & (st - 1)) == 0;
+    A.recs = rows && (c->force_rows || (cands >= 8 * c->n && cands >= ((int64_t)1 << 20)));
+    A.verify_rows = A.recs && have && ((uintptr_t)ngb & 15) == 0;
+    if (A.verify_rows) {
+        // the evaluation checks the rows
+    } else if (A.stride % 4 == 0 && ((uintptr_t)ngb & 15) == 0) {
         k_rows4<<<grid_for(n_active * A.stride / 4, 8192), kBlock, 0, c->stream>>>(A, have);
-    else
+    } else {
         k_rows<<<grid_for(n_active * A.stride, 8192), kBlock, 0, c->stream>>>(A, have);
+    }
     c->jsort_ngb = ngb;
     c->jsort_knn = 0;
     // row block summaries for the checks: rows of a power of two entries,
     // written by the first grid check; they pay off on long steps (the
     // first check's extra work against the later checks' savings: 2^26
     // candidates, and at least 8 a particle)
-    const int st = A.stride;
-    const int64_t cands = n_active * st;
     if (c->csum && c->dev_rounds > 0 && st >= 4 && st <= SIDM_SUM_U && (st & (st - 1)) == 0 &&
         (c->force_rows || (cands >= ((int64_t)1 << 26) && cands >= 8 * c->n)))
         A.csum = c->csum;
-    const bool mixed = c->cfg.precision == SIDM_MIXED;
     if (c->cfg.periodic) {
         mixed ? run_scatter<true, true>(c, A, n_active, c->stream)
               : run_scatter<true, false>(c, A, n_active, c->stream);

@@ -72,8 +72,13 @@ def test_active_index_out_of_range_is_reported():
     ctx.close()
 
 
-def test_bad_neighbour_index_is_reported():
-    _announce("neighbour index out of range in scatter_step and pair_timestep")
+@pytest.mark.parametrize("force_rows", ["0", "1"])
+def test_bad_neighbour_index_is_reported(monkeypatch, force_rows):
+    """Out-of-range entries of a caller's ngb are latched whether the rows
+    are checked by their own kernel or (partner records forced on) by the
+    evaluation."""
+    monkeypatch.setenv("SIDM_TEST_FORCE_ROWS", force_rows)
+    _announce(f"neighbour index out of range in scatter_step and pair_timestep, force_rows={force_rows}")
     w, ds, ctx, out = _setup()
     ctx.find_ngb(ds.active, out.ngb, out.h)
     ctx.sync()

@@ -119,6 +119,50 @@ def test_block_summaries_other_row_lengths(monkeypatch, k):
     assert_parity(w, g, ref)
 
 
+@pytest.mark.parametrize("force_rows", ["0", "1"])
+def test_caller_reordered_rows(monkeypatch, force_rows):
+    """The step takes the caller's ngb, not the search's rows: with two entries
+    of some rows swapped (the same candidates in another order), the rows
+    the step uses are translated from ngb -- by their own kernel, or (partner
+    records forced on) by the evaluation -- and the step is the same, its
+    per-candidate information following the swap."""
+    import torch
+    from paper_2607_05504_amd import Context, runner
+    monkeypatch.setenv("SIDM_TEST_FORCE_ROWS", force_rows)
+    w = W.uniform_box(20000, ic_seed=48, scatters_per_particle=0.5)
+    _announce(f"caller-reordered rows, force_rows={force_rows}")
+    res = []
+    for swap in (False, True):
+        ds = runner.upload(w, "cuda")
+        ctx = Context(runner.config_for(w), w.n, w.n_active)
+        out = runner.alloc_out(ds, w.n_ngb, with_info=True)
+        ctx.build_tree(ds.x, ds.y, ds.z, ds.vx, ds.vy, ds.vz, ds.ids, state=ds.state,
+                       m_scalar=ds.mass)
+        ctx.find_ngb(ds.active, out.ngb, out.h)
+        ngb = out.ngb
+        if swap:
+            ngb = out.ngb.clone()
+            rows = torch.arange(0, w.n_active, 7, device=ngb.device)
+            a, b = ngb[rows, 3].clone(), ngb[rows, 20].clone()
+            ngb[rows, 3], ngb[rows, 20] = b, a
+        ctx.scatter_step(ds.active, ngb, out.h, ds.dt, w.seed, w.step, cand_info=out.cand_info,
+                         reuse_active=True)
+        ctx.pair_timestep(ds.active, ngb, out.h, out.dt_sidm, reuse_active=True)
+        stats = ctx.sync()
+        info = out.cand_info.cpu().numpy().view(np.uint32).reshape(w.n_active, w.n_ngb).copy()
+        if swap:
+            r = np.arange(0, w.n_active, 7)
+            info[r, 3], info[r, 20] = info[r, 20].copy(), info[r, 3].copy()
+        res.append(dict(v=np.stack([ds.vx.cpu().numpy(), ds.vy.cpu().numpy(), ds.vz.cpu().numpy()]),
+                        dt=out.dt_sidm.cpu().numpy(), info=info, events=stats["n_events"]))
+        ctx.close()
+    assert res[0]["events"] > 100
+    assert res[0]["events"] == res[1]["events"]
+    assert np.array_equal(res[0]["v"], res[1]["v"])
+    assert np.array_equal(res[0]["dt"], res[1]["dt"])
+    assert np.array_equal(res[0]["info"], res[1]["info"])
+
+
 @pytest.mark.parametrize("k", [1, 8, 16, 31, 48, 63])
 def test_neighbour_counts(k):
     """n_ngb from 1 to the largest accepted (63): the short-list and long-list
