@@ -1179,12 +1179,12 @@ __device__ void check_scan(const StepArgs &A, int64_t first_chunk, int64_t chunk
                 const int l = tid & (L - 1);
                 const bool ok = b < nt;
                 const int32_t i = ok ? A.tlist[b] : 0;
+                // four consecutive entries of the row, one 16-byte load
+                const int64_t c4 = (b << sh) + 4 * l;
+                const int4 q = ok ? *(const int4 *)(A.jsort + c4) : make_int4(-1, -1, -1, -1);
+                jv[p * 4 + 0] = q.x; jv[p * 4 + 1] = q.y; jv[p * 4 + 2] = q.z; jv[p * 4 + 3] = q.w;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int64_t c = (b << sh) + l + u * L;
-                    cc[p * 4 + u] = c;
-                    jv[p * 4 + u] = ok ? A.jsort[c] : -1;
-                }
+                for (int u = 0; u < 4; ++u) cc[p * 4 + u] = c4 + u;
                 di[p] = ok && dbit(A, i);
             }
 #pragma unroll
@@ -1335,11 +1335,11 @@ __device__ void check_blocks(const StepArgs &A, int64_t g0, int64_t g_stride, in
                     if (b < nt) {
                         const int l = t & (L - 1);
                         di = dbit(A, A.tlist[b]);
+                        const int64_t c4 = (b << sh) + 4 * l;
+                        const int4 q = *(const int4 *)(A.jsort + c4);
+                        jv[0] = q.x; jv[1] = q.y; jv[2] = q.z; jv[3] = q.w;
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            cc[p * 4 + e] = (b << sh) + l + e * L;
-                            jv[e] = A.jsort[cc[p * 4 + e]];
-                        }
+                        for (int e = 0; e < 4; ++e) cc[p * 4 + e] = c4 + e;
                     }
                 }
 #pragma unroll
