@@ -1366,8 +1366,9 @@ __device__ void check_blocks(const StepArgs &A, int64_t g0, int64_t g_stride, in
 
 // blocks a workgroup of the grid check tests at once: few, so that the
 // groups of a large step outnumber the workgroups and spread over every XCD
-// (consecutive workgroups go to different XCDs)
-constexpr int kCheckGroup = 64;
+// (consecutive workgroups go to different XCDs), and the blocks that meet D,
+// which cluster, spread over many workgroups (64, 32, 16, 8 measured: 16)
+constexpr int kCheckGroup = 16;
 
 // The block summaries are tested only while few buckets hold a particle of
 // D (at most a quarter of them): with more, most blocks would be scanned
